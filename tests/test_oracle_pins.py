@@ -1,0 +1,320 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself:
+closed forms, textbook identities, independent library routines, brute force on
+tiny inputs and the numbers the paper prints.  CPU only."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from workloads import laplace2d, fv3d, fd2d_variable, gaussian_C, uniform_C
+from oracle import dense as D
+from oracle import krylov as K
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ generators
+def test_laplace2d_structure_and_spectrum():
+    op = laplace2d(32)
+    rp, ci, va = op.to_csr()
+    assert rp[-1] == 5 * op.n - 4 * 32 == 4992          # 5-point nnz
+    A = op.to_scipy().toarray()
+    assert np.array_equal(A, A.T)
+    h = 1 / 33
+    assert A[0, 0] == -4 / h ** 2 and A[0, 1] == 1 / h ** 2
+    ev = np.linalg.eigvalsh(A)
+    an = np.sort(D.laplace2d_eigs(32))
+    assert np.max(np.abs(ev - an)) / np.max(np.abs(an)) < 1e-13
+    assert abs(an.min() / an.max() - 440.7) < 0.1             # condition number
+
+
+def test_fv3d_structure():
+    N = 6
+    op = fv3d(N, 1.0, 3)
+    rp, ci, va = op.to_csr()
+    assert rp[-1] == 7 * op.n - 6 * N * N               # 7-point nnz
+    A = op.to_scipy().toarray()
+    assert np.array_equal(A, A.T)
+    assert np.all(np.linalg.eigvalsh(A) < 0)
+    # conservation: A 1 = -(boundary face transmissibilities)
+    k = op.meta["k"].reshape(N, N, N)
+    bnd = np.zeros((N, N, N))
+    inv = N * N
+    for ax in range(3):
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[ax] = 0
+        hi[ax] = -1
+        bnd[tuple(lo)] += 2 * k[tuple(lo)] * inv
+        bnd[tuple(hi)] += 2 * k[tuple(hi)] * inv
+    assert np.allclose(A @ np.ones(op.n), -bnd.ravel(), rtol=1e-12, atol=1e-9)
+    # harmonic face value between cells 0 and 1
+    assert np.isclose(A[0, 1], 2 * k[0, 0, 0] * k[0, 0, 1] / (k[0, 0, 0] + k[0, 0, 1]) * inv)
+
+
+def test_gaussian_C_prefix_property():
+    C1 = gaussian_C(100, 1, 7)
+    C4 = gaussian_C(100, 4, 7)
+    assert np.array_equal(C1[:, 0], C4[:, 0])
+    assert C4.flags["F_CONTIGUOUS"]
+
+
+# ------------------------------------------------------------------ dense references
+def test_dense_references_agree():
+    op = laplace2d(5)
+    A = op.to_scipy().toarray()
+    C = gaussian_C(op.n, 2, 3)
+    Xk = D.lyap_kron(A, C)
+    Xe = D.lyap_eig(A, C)
+    Xd = D.lyap_laplace2d_dense(5, C)
+    nrm = np.linalg.norm(Xk)
+    assert np.linalg.norm(Xk - Xe) / nrm < 1e-12
+    assert np.linalg.norm(Xk - Xd) / nrm < 1e-12
+    assert np.linalg.norm(A @ Xk + Xk @ A + C @ C.T) / np.linalg.norm(C @ C.T) < 1e-12
+
+
+def test_diag_closed_form_matches_kron():
+    rng = np.random.default_rng(0)
+    a = -rng.uniform(1, 10, 20)
+    C = rng.standard_normal((20, 3))
+    assert np.allclose(D.lyap_diag(a, C), D.lyap_kron(np.diag(a), C), rtol=1e-12, atol=1e-14)
+
+
+def test_exp_sum_lowrank_matches_dense():
+    N = 20
+    C = gaussian_C(N * N, 2, 5)
+    X = D.lyap_laplace2d_dense(N, C)
+    Z = D.lyap_laplace2d_lowrank(N, C)
+    assert np.linalg.norm(Z @ Z.T - X) / np.linalg.norm(X) < 1e-11
+
+
+def test_sylvester_eig_residual():
+    A = laplace2d(4).to_scipy().toarray()
+    B = fv3d(2, 0.5, 1).to_scipy().toarray()
+    rng = np.random.default_rng(1)
+    C1 = rng.standard_normal((16, 2))
+    C2 = rng.standard_normal((8, 2))
+    X = D.sylv_eig(A, B, C1, C2)
+    Xs = sla.solve_sylvester(A, B, -C1 @ C2.T)
+    assert np.linalg.norm(X - Xs) / np.linalg.norm(Xs) < 1e-12
+
+
+# ------------------------------------------------------------------ Lanczos invariants
+def _run_basis(op, s, m, seed=2):
+    A = op.to_scipy()
+    C = gaussian_C(op.n, s, seed)
+    _, gamma = K.qr_pos(C)
+    V = [K.right_solve_upper(C, gamma)]
+    Vprev = np.zeros_like(V[0])
+    recs = []
+    for j in range(m):
+        Vn, rec, _, _, _ = K.block_lanczos_step(A, Vprev, V[-1])
+        recs.append(rec)
+        Vprev = V[-1]
+        V.append(Vn)
+    return A, C, gamma, np.concatenate(V, axis=1), recs
+
+
+@pytest.mark.parametrize("s", [1, 3])
+def test_lanczos_relation_and_orthogonality(s):
+    op = laplace2d(12)
+    m = 15
+    A, C, gamma, V, recs = _run_basis(op, s, m)
+    Vm = V[:, :s * m]
+    assert np.linalg.norm(Vm.T @ Vm - np.eye(s * m)) < 1e-10
+    T = K.assemble_T(recs, m)
+    # A V_m = V_m T_m + V_{m+1} tau_{m+1,m} E_m^T
+    Em = np.zeros((s * m, s))
+    Em[-s:, :] = np.eye(s)
+    lhs = A @ Vm
+    rhs = Vm @ T + V[:, s * m:] @ recs[m - 1].R @ Em.T
+    assert np.linalg.norm(lhs - rhs) / np.linalg.norm(lhs) < 1e-10
+    # T_m = V_m^T A V_m, block tridiagonal with upper triangular sub-diagonal blocks
+    assert np.linalg.norm(T - Vm.T @ (A @ Vm)) / np.linalg.norm(T) < 1e-10
+    for j in range(m):
+        for i in range(m):
+            if abs(i - j) > 1:
+                assert np.all(T[i * s:(i + 1) * s, j * s:(j + 1) * s] == 0)
+        R = recs[j].R
+        assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) > 0)
+    # C = V_1 gamma
+    assert np.allclose(V[:, :s] @ gamma, C, atol=1e-12 * np.abs(C).max())
+
+
+def test_range_is_block_krylov_space():
+    op = laplace2d(8)
+    s, m = 2, 5
+    A, C, gamma, V, recs = _run_basis(op, s, m)
+    Kry = [C]
+    for _ in range(m - 1):
+        Kry.append(A @ Kry[-1])
+    Kq, _ = np.linalg.qr(np.concatenate(Kry, axis=1))
+    Vm = V[:, :s * m]
+    # projector difference
+    assert np.linalg.norm(Kq @ Kq.T - Vm @ Vm.T) < 1e-8
+
+
+# ------------------------------------------------------------------ residual formulas
+def _explicit_dense_residual(A, V, Y, C):
+    X = V @ Y @ V.T
+    return np.linalg.norm(A @ X + X @ A + C @ C.T)
+
+
+@pytest.mark.parametrize("s,m", [(1, 10), (2, 15), (4, 6)])
+def test_prop1_equals_reduced_equals_explicit(s, m):
+    op = laplace2d(12)
+    A, C, gamma, V, recs = _run_basis(op, s, m, seed=0)
+    T = K.assemble_T(recs, m)
+    tau = recs[m - 1].R
+    r3 = K.residual_alg3(T, gamma, tau).res
+    rr = K.residual_reduced(T, gamma, tau)
+    Y = K.reduced_solution(T, gamma)
+    re = _explicit_dense_residual(A.toarray(), V[:, :s * m], Y, C)
+    assert abs(r3 - rr) / rr < 1e-10
+    assert abs(r3 - re) / re < 1e-8
+
+
+def test_prop1_on_random_spd_tridiagonal_brute_force():
+    """Brute force on a tiny random block tridiagonal T: the Alg. 3 sum equals
+    sqrt(2)||Y E_m tau^T|| with Y from the Kronecker solve."""
+    rng = np.random.default_rng(4)
+    ell, m = 2, 4
+    k = ell * m
+    B = rng.standard_normal((k, k))
+    T = -(B @ B.T + k * np.eye(k))
+    for i in range(m):
+        for j in range(m):
+            if abs(i - j) > 1:
+                T[i * ell:(i + 1) * ell, j * ell:(j + 1) * ell] = 0
+    T = 0.5 * (T + T.T)
+    T -= 3 * k * np.eye(k)
+    gamma = np.triu(rng.standard_normal((ell, ell)))
+    tau = np.triu(rng.standard_normal((ell, ell)))
+    E1g = np.zeros((k, ell))
+    E1g[:ell] = gamma
+    Y = D.lyap_kron(T, E1g)
+    brute = np.sqrt(2) * np.linalg.norm(Y[:, -ell:] @ tau.T)
+    assert abs(K.residual_alg3(T, gamma, tau).res - brute) / brute < 1e-12
+
+
+# planted mistakes: each variant must be caught by the pin above
+def _alg3_variant(T, gamma, tau, mistake):
+    ell = gamma.shape[0]
+    lam, Q = sla.eigh(T)
+    g = Q[:ell, :].T @ gamma
+    if mistake == "E1_vs_Em":
+        g = Q[-ell:, :].T @ gamma
+    S = g @ g.T
+    Wm = Q[-ell:, :].T @ (tau if mistake == "tau_not_transposed" else tau.T)
+    acc = 0.0
+    for i in range(lam.shape[0]):
+        Di = lam[i] - lam if mistake == "sign" else lam[i] + lam
+        if mistake == "sign":
+            Di = np.where(Di == 0, 1.0, Di)
+        row = (S[i, :] / Di) @ Wm
+        acc += row @ row
+    f = 1.0 if mistake == "no_sqrt2" else np.sqrt(2.0)
+    return f * np.sqrt(acc)
+
+
+@pytest.mark.parametrize("mistake", ["E1_vs_Em", "tau_not_transposed", "sign", "no_sqrt2"])
+def test_pins_catch_planted_mistakes(mistake):
+    op = laplace2d(10)
+    A, C, gamma, V, recs = _run_basis(op, 3, 6, seed=0)
+    T = K.assemble_T(recs, 6)
+    tau = recs[5].R
+    rr = K.residual_reduced(T, gamma, tau)
+    assert abs(_alg3_variant(T, gamma, tau, "none") - rr) / rr < 1e-10
+    assert abs(_alg3_variant(T, gamma, tau, mistake) - rr) / rr > 1e-3
+
+
+# ------------------------------------------------------------------ truncation and Z
+def test_truncation_error_bound():
+    op = laplace2d(16)
+    A, C, gamma, V, recs = _run_basis(op, 2, 30, seed=1)
+    T = K.assemble_T(recs, 30)
+    a3 = K.residual_alg3(T, gamma, recs[29].R)
+    Y = a3.Q @ (-(a3.g @ a3.g.T) / (a3.lam[:, None] + a3.lam[None, :])) @ a3.Q.T
+    Yr = K.reduced_solution(T, gamma)
+    assert np.linalg.norm(Y - Yr) / np.linalg.norm(Yr) < 1e-10    # eq. (lyap2sol)
+    for eps in (1e-6, 1e-9, 1e-12):
+        M, _ = K.truncated_factor(a3.lam, a3.Q, a3.g, eps * np.linalg.norm(Y))
+        assert np.linalg.norm(Y - M @ M.T) <= 1.01 * eps * np.linalg.norm(Y) + 1e-15 * np.linalg.norm(Y)
+
+
+@pytest.mark.parametrize("s", [1, 4])
+def test_c1_end_to_end_against_exact_solution(s):
+    """Config: 32x32 Laplacian (n=1024), Gaussian C, tol 1e-8, check every step."""
+    op = laplace2d(32)
+    A = op.to_scipy()
+    C = gaussian_C(op.n, s, 1)
+    r = K.lyap_std(A, C, tol=1e-8, check_every=1, compute_dense_residual=True)
+    assert r.converged
+    last = r.hist[-1]
+    assert last["res"] <= 1e-8
+    assert abs(last["res"] - last["res_reduced"]) / last["res"] < 1e-6
+    expl = K.explicit_residual(A, r.Z, C) / r.beta ** 2
+    assert expl <= 1.1e-8
+    X = D.lyap_laplace2d_dense(32, C)
+    assert K.lowrank_vs_dense_error(r.Z, X) <= 1e-7
+    # two-pass equals the stored-basis factor
+    r2 = K.lyap_std(A, C, tol=1e-8, check_every=1, two_pass=False)
+    assert r2.m == r.m and np.abs(r2.Z - r.Z).max() <= 1e-12 * np.abs(r.Z).max()
+
+
+def test_diagonal_operator_closed_form():
+    rng = np.random.default_rng(9)
+    n = 300
+    a = -np.sort(rng.uniform(1.0, 50.0, n))
+    import scipy.sparse as sp
+    A = sp.diags(a).tocsr()
+    C = rng.standard_normal((n, 2))
+    r = K.lyap_std(A, C, tol=1e-10, check_every=1)
+    X = D.lyap_diag(a, C)
+    assert K.lowrank_vs_dense_error(r.Z, X) < 1e-8
+
+
+def test_factor_error_and_explicit_residual_identities():
+    rng = np.random.default_rng(3)
+    n = 60
+    Za = rng.standard_normal((n, 5))
+    Zb = rng.standard_normal((n, 7))
+    ref = np.linalg.norm(Za @ Za.T - Zb @ Zb.T) / np.linalg.norm(Zb @ Zb.T)
+    assert abs(K.factor_error(Za, Zb) - ref) / ref < 1e-12
+    A = laplace2d(int(np.sqrt(64))).to_scipy()
+    Z = rng.standard_normal((64, 4))
+    C = rng.standard_normal((64, 2))
+    Ad = A.toarray()
+    ref = np.linalg.norm(Ad @ Z @ Z.T + Z @ Z.T @ Ad + C @ C.T)
+    assert abs(K.explicit_residual(A, Z, C) - ref) / ref < 1e-12
+
+
+# ------------------------------------------------------------------ the paper's printed numbers
+def test_paper_example1_iteration_count():
+    """Table 1, s=1: 444 iterations at tol 1e-6 with the residual checked at
+    every step.  The paper's random C is not reproducible, so allow 2%."""
+    g = json.load(open(os.path.join(GOLD, "paper_example1.json")))
+    op = fd2d_variable(148, lambda x, y: np.exp(-x * y), lambda x, y: np.exp(x * y), "e1")
+    A = op.to_scipy()
+    C = uniform_C(op.n, 1, 0)
+    r = K.lyap_std(A, C, tol=g["tol"], check=lambda m: m >= 420, max_iter=480)
+    ref = g["iterations"]["1"]
+    assert r.converged and abs(r.m - ref) <= 0.02 * ref
+    # memory columns of Table 2: whole basis s*m vs 3s vectors in the two-pass scheme
+    for s in ("1", "4", "8"):
+        assert g["memory_whole_basis_s_times_m"][s] == int(s) * g["iterations"][s]
+        assert g["memory_two_pass_3s"][s] == 3 * int(s)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("s", [4, 8])
+def test_paper_example1_iteration_count_blocks(s):
+    g = json.load(open(os.path.join(GOLD, "paper_example1.json")))
+    op = fd2d_variable(148, lambda x, y: np.exp(-x * y), lambda x, y: np.exp(x * y), "e1")
+    A = op.to_scipy()
+    C = uniform_C(op.n, s, 0)
+    ref = g["iterations"][str(s)]
+    r = K.lyap_std(A, C, tol=g["tol"], check=lambda m: m >= int(0.95 * ref), max_iter=int(1.1 * ref))
+    assert r.converged and abs(r.m - ref) <= 0.03 * ref
