@@ -1,0 +1,258 @@
+/*
+ * lyap.h — C ABI of the MI355X (gfx950) projection solver for
+ *
+ *     A X + X A + C C^T = 0           (Lyapunov)
+ *     A X + X B + C1 C2^T = 0         (Sylvester, symmetric A and B)
+ *
+ * with A, B large, sparse, symmetric negative definite and C tall (n x s,
+ * s << n), following Palitta & Simoncini, "Computationally enhanced
+ * projection methods for symmetric Sylvester and Lyapunov matrix equations":
+ * Galerkin projection onto block Krylov spaces (Section 2, Algorithm 1),
+ * block Lanczos with twice-applied block modified Gram-Schmidt
+ * (Algorithm 2), the residual norm of Proposition 1 / Algorithm 3 computed
+ * from the eigendecomposition of the block tridiagonal T_m without solving
+ * the reduced equation, the two-pass reconstruction of the low-rank factor
+ * Z (Section 3.3, eq. (twopasseq)), the extended Krylov variant (Section 4)
+ * and the two-sided Sylvester variant (Section 5.1, Algorithm 4).
+ *
+ * Conventions
+ *  - All pointers named "device" are HIP device pointers on the current
+ *    device; the library never dereferences them on the host.
+ *  - Dense n x s inputs are column-major FP64 with leading dimension ld >= n.
+ *  - Every entry point returns a lyap_status and never aborts; on error
+ *    lyap_last_error() gives a thread-local, human-readable message.
+ *  - Inputs are borrowed for the duration of a call.  The library keeps no
+ *    state between calls.
+ *  - Work is enqueued on opts->stream (a hipStream_t; NULL = the null
+ *    stream); solver entry points synchronise that stream before returning.
+ */
+#ifndef LYAP_H
+#define LYAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+typedef enum lyap_status {
+  LYAP_OK = 0,               /* converged: ||R||_F / beta^2 <= tol            */
+  LYAP_NOT_CONVERGED = 1,    /* max_iter reached; Z is from the last check     */
+  LYAP_E_ARG = -1,           /* invalid argument (message says which)          */
+  LYAP_E_BREAKDOWN = -2,     /* rank-deficient block (C or W) with the residual
+                                still above tol; deflation is not implemented */
+  LYAP_E_INDEFINITE = -3,    /* a Ritz value >= 0: A is not negative definite  */
+  LYAP_E_NUMERIC = -4,       /* NaN/Inf met (input or arithmetic)              */
+  LYAP_E_INNER = -5,         /* an inner solve (extended Krylov) failed        */
+  LYAP_E_NOMEM = -6,         /* device allocation failed                       */
+  LYAP_E_DEVICE = -7,        /* a HIP runtime call failed                      */
+  LYAP_E_UNSUPPORTED = -8    /* combination of options not built               */
+} lyap_status;
+
+/* ------------------------------------------------------------------ operator */
+enum {
+  LYAP_OP_CSR = 0,       /* general sparse symmetric matrix in CSR          */
+  LYAP_OP_STENCIL5 = 1,  /* constant 5-point operator on an nx x ny grid    */
+  LYAP_OP_STENCIL7 = 2   /* variable 7-point operator on nx x ny x nz cells */
+};
+
+/*
+ * A sparse symmetric negative definite operator.  Grid rows are ordered
+ * lexicographically with x fastest: row = i + nx*(j + ny*l).
+ *
+ * STENCIL5: (A v)_r = cc v_r + co (v_{r-1} + v_{r+1} + v_{r-nx} + v_{r+nx}),
+ *           neighbours outside the grid omitted (zero Dirichlet boundary).
+ *           n = nx*ny.
+ * STENCIL7: per-cell device arrays diag, tx, ty, tz (length n, FP64):
+ *           (A v)_r = diag_r v_r + tx_r v_{r+1} + tx_{r-1} v_{r-1}
+ *                   + ty_r v_{r+nx} + ty_{r-nx} v_{r-nx}
+ *                   + tz_r v_{r+nx*ny} + tz_{r-nx*ny} v_{r-nx*ny};
+ *           the coupling arrays are zero on the last cell of a line.
+ *           n = nx*ny*nz (nz = 1 for a 2-D grid).
+ * CSR:      device rowptr (int64, n+1), colind (int32, nnz, ascending within
+ *           a row), val (FP64, nnz).  The matrix must be symmetric.
+ * shift:    added to the diagonal of every kind (A + shift I).
+ */
+typedef struct lyap_op {
+  int32_t kind;
+  int32_t nx, ny, nz;
+  int64_t n;
+  double cc, co;
+  const double* diag;
+  const double* tx;
+  const double* ty;
+  const double* tz;
+  const int64_t* rowptr;
+  const int32_t* colind;
+  const double* val;
+  int64_t nnz;
+  double shift;
+} lyap_op;
+
+/* ------------------------------------------------------------------ options */
+enum { LYAP_STORE_F64 = 0, LYAP_STORE_F32 = 1 };
+enum { LYAP_METHOD_STD = 0, LYAP_METHOD_EXT = 1 };
+enum { LYAP_PC_NONE = 0, LYAP_PC_JACOBI = 1, LYAP_PC_IC0 = 2, LYAP_PC_LEARNED = 3 };
+
+typedef void* (*lyap_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*lyap_free_fn)(void* ptr, void* ctx);
+
+typedef struct lyap_opts {
+  double tol;           /* stop when ||R_m||_F / ||C||_F^2 <= tol (Alg. 1 step 6.3) */
+  int32_t max_iter;     /* maximum number of basis blocks m                          */
+  int32_t method;       /* LYAP_METHOD_STD (block Lanczos) or LYAP_METHOD_EXT          */
+  int32_t check_every;  /* d > 0: check every d steps (the paper's d); 0: adaptive      */
+  int32_t storage;      /* LYAP_STORE_F64 or LYAP_STORE_F32 (basis and SpMM storage;
+                           coefficients, T_m, eigen and residual are always FP64)      */
+  int32_t two_pass;     /* 1: regenerate the basis in a second pass (Section 3.3);
+                           0: store the whole basis (memory s*m vectors)               */
+  double trunc_eps;     /* < 0: default truncation threshold (see lyap_solve);
+                           >= 0: absolute threshold on ||Sigma_2||_F               */
+  int32_t inner_pc;     /* extended Krylov inner solver preconditioner (LYAP_PC_*)  */
+  double inner_tol;     /* inner solves accepted when true ||b-Ax||/||b|| <= this  */
+  int32_t inner_max_iter;
+  int32_t flush_blocks; /* second pass: blocks buffered per Z update (0 = default)  */
+  void* stream;         /* hipStream_t                                              */
+  lyap_alloc_fn alloc;  /* device allocator for returned buffers (NULL: hipMalloc)  */
+  lyap_free_fn release; /* matching release (NULL: hipFree)                         */
+  void* alloc_ctx;
+  int32_t want_T;       /* 1: return T_m band and gamma/tau on the host            */
+  int32_t verbose;
+} lyap_opts;
+
+/* Fills *o with: tol 1e-8, max_iter 5000, STD, adaptive checks, F64 storage,
+ * two_pass 1, default truncation, inner PC IC0, inner_tol 1e-12,
+ * inner_max_iter 5000, hipMalloc allocation, null stream. */
+void lyap_opts_default(lyap_opts* o);
+
+/* ------------------------------------------------------------------ result */
+enum {
+  LYAP_T_PASS1 = 0,    /* basis generation (first pass), ms               */
+  LYAP_T_CHECKS = 1,   /* residual checks (eigen + Prop. 1 sum), ms        */
+  LYAP_T_FINAL = 2,    /* truncation and Q Y-check, ms                      */
+  LYAP_T_PASS2 = 3,    /* second pass and Z accumulation, ms               */
+  LYAP_T_INNER = 4,    /* inner solves (extended Krylov), ms               */
+  LYAP_T_TRAIN = 5,    /* preconditioner training, ms                      */
+  LYAP_T_TOTAL = 6,    /* whole call, ms                                   */
+  LYAP_T_TO_TOL = 7    /* entry to the first passing check, ms            */
+};
+
+typedef struct lyap_result {
+  int32_t status;
+  int32_t s;           /* block width of C                                 */
+  int32_t ell;         /* block size of T_m: s (standard) or 2s (extended) */
+  int32_t m;           /* number of basis blocks (dim = ell*m)             */
+  int32_t t;           /* columns of Z                                     */
+  int64_t n;
+  double* Z;           /* device, n x t column-major FP64, owned by caller
+                          (allocated with opts->alloc, else hipMalloc)     */
+  int32_t n_hist;
+  int32_t* hist_m;     /* host: m at each check                            */
+  double* hist_res;    /* host: ||R_m||_F / beta^2 at each check            */
+  double beta;         /* ||C||_F                                          */
+  double res;          /* last checked ||R_m||_F / beta^2                  */
+  double trunc_eps;    /* truncation threshold used                        */
+  double times_ms[8];
+  int64_t inner_iters; /* total inner iterations (extended Krylov)         */
+  int32_t n_inner;     /* number of inner solves                           */
+  int32_t n_checks;
+  double* T_band;      /* host, (ell+1) x (ell*m) lower band of T_m (want_T) */
+  double* gamma;       /* host, ell x ell, column-major (want_T)            */
+  double* tau;         /* host, ell x ell tau_{m+1,m}, column-major (want_T) */
+  int64_t bytes_pass1; /* algorithmic HBM bytes of the first pass          */
+  int64_t bytes_spmm;  /* algorithmic HBM bytes of the SpMM calls           */
+  double ms_spmm;      /* measured device time of SpMM calls, ms (0 if off) */
+  int32_t owns_Z;      /* 1: Z came from hipMalloc and lyap_result_free frees it */
+} lyap_result;
+
+/*
+ * lyap_solve — AX + XA + CC^T = 0 by Algorithm 1.
+ *
+ *  A     operator (device arrays), symmetric negative definite.
+ *  C     device, n x s column-major FP64, leading dimension ldc >= n.
+ *  s     1 <= s <= 8 (standard) or 1 <= s <= 8 (extended, ell = 2s).
+ *  opts  may be NULL (defaults).
+ *  out   filled on return (also on error, with status and history so far).
+ *
+ * The residual is checked after m blocks when the schedule asks for it
+ * (every d steps, or adaptively: spaced checks that tighten near the
+ * predicted crossing) by Proposition 1 with T_m's eigendecomposition on the
+ * GPU in FP64.  At the first passing check, Y~ of eq. (lyap2sol) is truncated
+ * (eigenvalues with ||Sigma_2||_F <= eps are dropped; default
+ * eps = min(1e-12, 0.05 tol / nu) ||C||_F^2 with nu = max|lambda(T_m)| +
+ * ||tau_{m+1,m}||_F, so truncation moves the residual by at most 0.1 tol), and
+ * Z = V_m (Q_m Y-check) is formed in a second Lanczos pass (two_pass = 1) or
+ * from the stored basis.  Z Z^T approximates X.
+ */
+lyap_status lyap_solve(const lyap_op* A, const double* C, int32_t s, int64_t ldc,
+                       const lyap_opts* opts, lyap_result* out);
+
+typedef struct sylv_result {
+  int32_t status;
+  int32_t m, t;
+  int64_t n1, n2;
+  double* Z1;          /* device, n1 x t column-major */
+  double* Z2;          /* device, n2 x t column-major */
+  int32_t n_hist;
+  int32_t* hist_m;
+  double* hist_res;    /* ||R_m||_F / (||C1||_F ||C2||_F) */
+  double res;
+  double times_ms[8];
+  int32_t n_checks;
+} sylv_result;
+
+/*
+ * sylv_solve — AX + XB + C1 C2^T = 0 with two standard block Krylov spaces
+ * K_m(A, C1), K_m(B, C2) of equal dimension (Section 5.1).  The residual uses
+ * eq. (resSylv) evaluated without Y_m (Algorithm 4, with the shifts of the
+ * two diagonal matrices D'_i, D''_i taken as lambda_i I + Upsilon and
+ * upsilon_j I + Lambda so that it agrees with eq. (resSylv)).  Z1 Z2^T
+ * approximates X.  C1 is n1 x s, C2 is n2 x s (device, column-major FP64).
+ */
+lyap_status sylv_solve(const lyap_op* A, const lyap_op* B, const double* C1, int64_t ldc1,
+                       const double* C2, int64_t ldc2, int32_t s, const lyap_opts* opts,
+                       sylv_result* out);
+
+/* Releases host arrays of a result and, when the library allocated Z with
+ * hipMalloc (opts->alloc == NULL), Z itself.  Safe on a zeroed struct. */
+void lyap_result_free(lyap_result* r);
+void sylv_result_free(sylv_result* r);
+
+/* Thread-local message describing the last error (empty if none). */
+const char* lyap_last_error(void);
+
+/* ------------------------------------------------------------------ components
+ * Single steps of the path, used by the tests and the benchmark.  Blocks are
+ * n x s row-interleaved (row r holds its s entries contiguously) in the
+ * storage type (double for LYAP_STORE_F64, float for LYAP_STORE_F32).
+ */
+
+/* W = A V for an n x s block (the sparse product of Algorithm 2's input
+ * W = A V_{m-1}).  V and W are device pointers, not aliased. */
+lyap_status lyap_op_apply(const lyap_op* A, int32_t storage, const void* V, void* W,
+                          int32_t s, void* stream);
+
+/* Same as lyap_op_apply repeated `reps` times back to back, returning the
+ * average device time per call in *ms (HIP events on `stream`). */
+lyap_status lyap_op_apply_timed(const lyap_op* A, int32_t storage, const void* V, void* W,
+                                int32_t s, int32_t reps, void* stream, double* ms);
+
+/*
+ * Residual of Proposition 1 (Algorithm 3) for a given block tridiagonal T.
+ *  T_band  host, (ell+1) x k lower band, column-major: T_band[c*(ell+1)+d] = T(c+d, c).
+ *  gamma   host, ell x ell column-major.
+ *  tau     host, ell x ell column-major (tau_{m+1,m}).
+ *  res     output ||R||_F.
+ *  lam     optional host output, k eigenvalues of T ascending (may be NULL).
+ * Everything runs on the GPU in FP64.
+ */
+lyap_status lyap_ctri(const double* T_band, int32_t ell, int32_t k, const double* gamma,
+                      const double* tau, double* res, double* lam, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LYAP_H */

@@ -1,0 +1,307 @@
+"""ctypes binding of liblyap.so (the C ABI in include/lyap.h).
+
+Argument marshalling only: device memory comes from PyTorch tensors and every
+step of the solver runs in the library's HIP kernels.  There is no fallback —
+if the library is missing the import fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblyap.so")
+
+# status codes (lyap_status)
+OK, NOT_CONVERGED = 0, 1
+E_ARG, E_BREAKDOWN, E_INDEFINITE, E_NUMERIC, E_INNER, E_NOMEM, E_DEVICE, E_UNSUPPORTED = range(-1, -9, -1)
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "E_ARG", -2: "E_BREAKDOWN", -3: "E_INDEFINITE",
+                -4: "E_NUMERIC", -5: "E_INNER", -6: "E_NOMEM", -7: "E_DEVICE", -8: "E_UNSUPPORTED"}
+
+OP_CSR, OP_STENCIL5, OP_STENCIL7 = 0, 1, 2
+STORE_F64, STORE_F32 = 0, 1
+METHOD_STD, METHOD_EXT = 0, 1
+PC_NONE, PC_JACOBI, PC_IC0, PC_LEARNED = 0, 1, 2, 3
+
+ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_size_t, ct.c_void_p)
+FREE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p)
+
+
+class LyapOp(ct.Structure):
+    _fields_ = [("kind", ct.c_int32), ("nx", ct.c_int32), ("ny", ct.c_int32), ("nz", ct.c_int32),
+                ("n", ct.c_int64), ("cc", ct.c_double), ("co", ct.c_double),
+                ("diag", ct.c_void_p), ("tx", ct.c_void_p), ("ty", ct.c_void_p), ("tz", ct.c_void_p),
+                ("rowptr", ct.c_void_p), ("colind", ct.c_void_p), ("val", ct.c_void_p),
+                ("nnz", ct.c_int64), ("shift", ct.c_double)]
+
+
+class LyapOpts(ct.Structure):
+    _fields_ = [("tol", ct.c_double), ("max_iter", ct.c_int32), ("method", ct.c_int32),
+                ("check_every", ct.c_int32), ("storage", ct.c_int32), ("two_pass", ct.c_int32),
+                ("trunc_eps", ct.c_double), ("inner_pc", ct.c_int32), ("inner_tol", ct.c_double),
+                ("inner_max_iter", ct.c_int32), ("flush_blocks", ct.c_int32), ("stream", ct.c_void_p),
+                ("alloc", ALLOC_FN), ("release", FREE_FN), ("alloc_ctx", ct.c_void_p),
+                ("want_T", ct.c_int32), ("verbose", ct.c_int32)]
+
+
+class LyapResult(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("s", ct.c_int32), ("ell", ct.c_int32), ("m", ct.c_int32),
+                ("t", ct.c_int32), ("n", ct.c_int64), ("Z", ct.c_void_p), ("n_hist", ct.c_int32),
+                ("hist_m", ct.POINTER(ct.c_int32)), ("hist_res", ct.POINTER(ct.c_double)),
+                ("beta", ct.c_double), ("res", ct.c_double), ("trunc_eps", ct.c_double),
+                ("times_ms", ct.c_double * 8), ("inner_iters", ct.c_int64), ("n_inner", ct.c_int32),
+                ("n_checks", ct.c_int32), ("T_band", ct.POINTER(ct.c_double)),
+                ("gamma", ct.POINTER(ct.c_double)), ("tau", ct.POINTER(ct.c_double)),
+                ("bytes_pass1", ct.c_int64), ("bytes_spmm", ct.c_int64), ("ms_spmm", ct.c_double),
+                ("owns_Z", ct.c_int32)]
+
+
+class SylvResult(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("m", ct.c_int32), ("t", ct.c_int32), ("n1", ct.c_int64),
+                ("n2", ct.c_int64), ("Z1", ct.c_void_p), ("Z2", ct.c_void_p), ("n_hist", ct.c_int32),
+                ("hist_m", ct.POINTER(ct.c_int32)), ("hist_res", ct.POINTER(ct.c_double)),
+                ("res", ct.c_double), ("times_ms", ct.c_double * 8), ("n_checks", ct.c_int32)]
+
+
+# exported symbols declared in include/lyap.h
+EXPORTS = ["lyap_opts_default", "lyap_solve", "sylv_solve", "lyap_result_free", "sylv_result_free",
+           "lyap_last_error", "lyap_op_apply", "lyap_op_apply_timed", "lyap_ctri"]
+
+
+class LyapError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_LIB = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblyap.so (built by ``paper_1602_05033_amd.build``)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1602_05033_amd.build`")
+    lib = ct.CDLL(path)
+    lib.lyap_opts_default.argtypes = [ct.POINTER(LyapOpts)]
+    lib.lyap_opts_default.restype = None
+    lib.lyap_solve.argtypes = [ct.POINTER(LyapOp), ct.c_void_p, ct.c_int32, ct.c_int64, ct.POINTER(LyapOpts),
+                               ct.POINTER(LyapResult)]
+    lib.lyap_solve.restype = ct.c_int
+    lib.sylv_solve.argtypes = [ct.POINTER(LyapOp), ct.POINTER(LyapOp), ct.c_void_p, ct.c_int64, ct.c_void_p,
+                               ct.c_int64, ct.c_int32, ct.POINTER(LyapOpts), ct.POINTER(SylvResult)]
+    lib.sylv_solve.restype = ct.c_int
+    lib.lyap_result_free.argtypes = [ct.POINTER(LyapResult)]
+    lib.lyap_result_free.restype = None
+    lib.sylv_result_free.argtypes = [ct.POINTER(SylvResult)]
+    lib.sylv_result_free.restype = None
+    lib.lyap_last_error.argtypes = []
+    lib.lyap_last_error.restype = ct.c_char_p
+    lib.lyap_op_apply.argtypes = [ct.POINTER(LyapOp), ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p]
+    lib.lyap_op_apply.restype = ct.c_int
+    lib.lyap_op_apply_timed.argtypes = [ct.POINTER(LyapOp), ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_int32,
+                                        ct.c_int32, ct.c_void_p, ct.POINTER(ct.c_double)]
+    lib.lyap_op_apply_timed.restype = ct.c_int
+    lib.lyap_ctri.argtypes = [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p,
+                              ct.POINTER(ct.c_double), ct.c_void_p, ct.c_void_p]
+    lib.lyap_ctri.restype = ct.c_int
+    _LIB = lib
+    return lib
+
+
+def _check(status: int, allow=(OK,)):
+    if status not in allow:
+        raise LyapError(status, load().lyap_last_error().decode())
+    return status
+
+
+# --------------------------------------------------------------------- operators
+@dataclass
+class DeviceOp:
+    """A ``lyap_op`` whose arrays live in torch tensors kept alive here."""
+    c: LyapOp
+    keep: list = field(default_factory=list)
+    n: int = 0
+
+
+def device_op(op, device="cuda", as_csr: bool = False, shift: float = 0.0) -> DeviceOp:
+    """Marshal a ``workloads.Operator`` into a ``lyap_op`` (device arrays)."""
+    import torch
+    c = LyapOp()
+    c.n = op.n
+    c.nx, c.ny, c.nz = op.nx, op.ny, op.nz
+    c.shift = shift
+    keep = []
+    if as_csr:
+        rp, ci, va = op.to_csr()
+        trp = torch.from_numpy(rp).to(device)
+        tci = torch.from_numpy(ci).to(device)
+        tva = torch.from_numpy(va).to(device)
+        keep += [trp, tci, tva]
+        c.kind = OP_CSR
+        c.rowptr, c.colind, c.val = trp.data_ptr(), tci.data_ptr(), tva.data_ptr()
+        c.nnz = int(va.shape[0])
+    elif op.kind == "stencil5":
+        c.kind = OP_STENCIL5
+        c.cc, c.co = op.cc, op.co
+    elif op.kind == "stencil7":
+        c.kind = OP_STENCIL7
+        arrs = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+                for a in (op.diag, op.tx, op.ty, op.tz)]
+        keep += arrs
+        c.diag, c.tx, c.ty, c.tz = (a.data_ptr() for a in arrs)
+    else:
+        raise ValueError(op.kind)
+    return DeviceOp(c, keep, op.n)
+
+
+# --------------------------------------------------------------------- allocator
+class _TorchAllocator:
+    """Device allocations requested by the library are torch tensors."""
+
+    def __init__(self, device):
+        self.device = device
+        self.live = {}
+
+        def _alloc(nbytes, ctx):
+            import torch
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            self.live[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def _free(ptr, ctx):
+            self.live.pop(ptr, None)
+
+        self.alloc_cb = ALLOC_FN(_alloc)
+        self.free_cb = FREE_FN(_free)
+
+    def take(self, ptr):
+        return self.live.pop(ptr, None)
+
+
+@dataclass
+class LyapSolution:
+    status: int
+    Z: object            # torch tensor (n, t) on the device, column-major storage
+    m: int
+    t: int
+    beta: float
+    res: float
+    hist_m: list
+    hist_res: list
+    times_ms: dict
+    n_checks: int
+    trunc_eps: float
+    T_band: Optional[np.ndarray] = None
+    gamma: Optional[np.ndarray] = None
+    tau: Optional[np.ndarray] = None
+    bytes_pass1: int = 0
+    bytes_spmm: int = 0
+    inner_iters: int = 0
+    n_inner: int = 0
+    ell: int = 0
+
+
+TIME_KEYS = ["pass1", "checks", "final", "pass2", "inner", "train", "total", "to_tol"]
+
+
+def make_opts(tol=1e-8, max_iter=5000, method=METHOD_STD, check_every=0, storage=STORE_F64, two_pass=True,
+              trunc_eps=-1.0, inner_pc=PC_IC0, inner_tol=1e-12, inner_max_iter=5000, want_T=False,
+              verbose=False, stream=None):
+    o = LyapOpts()
+    load().lyap_opts_default(ct.byref(o))
+    o.tol, o.max_iter, o.method, o.check_every = tol, max_iter, method, check_every
+    o.storage, o.two_pass, o.trunc_eps = storage, int(bool(two_pass)), trunc_eps
+    o.inner_pc, o.inner_tol, o.inner_max_iter = inner_pc, inner_tol, inner_max_iter
+    o.want_T, o.verbose = int(bool(want_T)), int(bool(verbose))
+    if stream is not None:
+        o.stream = stream
+    return o
+
+
+def lyap_solve(dop: DeviceOp, C, raise_on_error: bool = True, **kw) -> LyapSolution:
+    """Solve A X + X A + C C^T = 0.  ``C`` is an (n, s) float64 torch tensor on
+    the device; returns Z (n, t) with Z Z^T ~ X."""
+    import torch
+    lib = load()
+    n, s = C.shape
+    assert n == dop.n and C.dtype == torch.float64 and C.is_cuda
+    Ccm = C.t().contiguous()                   # column-major n x s, ld = n
+    alloc = _TorchAllocator(C.device)
+    o = make_opts(stream=torch.cuda.current_stream(C.device).cuda_stream, **kw)
+    o.alloc, o.release = alloc.alloc_cb, alloc.free_cb
+    r = LyapResult()
+    st = lib.lyap_solve(ct.byref(dop.c), ct.c_void_p(Ccm.data_ptr()), s, n, ct.byref(o), ct.byref(r))
+    msg = lib.lyap_last_error().decode()
+    try:
+        if raise_on_error and st not in (OK, NOT_CONVERGED):
+            raise LyapError(st, msg)
+        Z = None
+        if r.Z:
+            buf = alloc.take(r.Z)
+            if r.t > 0:
+                Z = buf[: 8 * n * r.t].view(torch.float64).view(r.t, n).t()
+            else:
+                Z = torch.zeros((n, 0), dtype=torch.float64, device=C.device)
+        ell = r.ell
+        k = ell * r.m
+        sol = LyapSolution(
+            status=st, Z=Z, m=r.m, t=r.t, beta=r.beta, res=r.res,
+            hist_m=[r.hist_m[i] for i in range(r.n_hist)], hist_res=[r.hist_res[i] for i in range(r.n_hist)],
+            times_ms={k_: r.times_ms[i] for i, k_ in enumerate(TIME_KEYS)}, n_checks=r.n_checks,
+            trunc_eps=r.trunc_eps, bytes_pass1=r.bytes_pass1, bytes_spmm=r.bytes_spmm,
+            inner_iters=r.inner_iters, n_inner=r.n_inner, ell=ell)
+        if r.T_band:
+            sol.T_band = np.ctypeslib.as_array(r.T_band, shape=(k * (ell + 1),)).copy().reshape(k, ell + 1)
+            sol.gamma = np.ctypeslib.as_array(r.gamma, shape=(ell * ell,)).copy().reshape(ell, ell, order="F")
+            nt = ell if r.s == ell else r.s
+            sol.tau = np.ctypeslib.as_array(r.tau, shape=(nt * ell,)).copy().reshape(nt, ell, order="F")
+        sol.error = msg
+        return sol
+    finally:
+        lib.lyap_result_free(ct.byref(r))
+
+
+def op_apply(dop: DeviceOp, V, storage: int):
+    """W = A V for a row-interleaved (n, s) block (float64 or float32 tensor)."""
+    import torch
+    lib = load()
+    W = torch.empty_like(V)
+    st = lib.lyap_op_apply(ct.byref(dop.c), storage, ct.c_void_p(V.data_ptr()), ct.c_void_p(W.data_ptr()),
+                           V.shape[1], ct.c_void_p(torch.cuda.current_stream(V.device).cuda_stream))
+    _check(st)
+    return W
+
+
+def op_apply_timed(dop: DeviceOp, V, storage: int, reps: int):
+    import torch
+    lib = load()
+    W = torch.empty_like(V)
+    ms = ct.c_double(0)
+    st = lib.lyap_op_apply_timed(ct.byref(dop.c), storage, ct.c_void_p(V.data_ptr()), ct.c_void_p(W.data_ptr()),
+                                 V.shape[1], reps, ct.c_void_p(torch.cuda.current_stream(V.device).cuda_stream),
+                                 ct.byref(ms))
+    _check(st)
+    return W, ms.value
+
+
+def ctri(T_band: np.ndarray, gamma: np.ndarray, tau: np.ndarray):
+    """Residual norm of Proposition 1 for a host band (k, ell+1); returns (res, lam)."""
+    lib = load()
+    k, l1 = T_band.shape
+    ell = l1 - 1
+    tb = np.ascontiguousarray(T_band, dtype=np.float64)
+    g = np.asfortranarray(gamma, dtype=np.float64)
+    t = np.asfortranarray(tau, dtype=np.float64)
+    lam = np.zeros(k)
+    res = ct.c_double(0)
+    st = lib.lyap_ctri(tb.ctypes.data_as(ct.c_void_p), ell, k, g.ctypes.data_as(ct.c_void_p),
+                       t.ctypes.data_as(ct.c_void_p), ct.byref(res), lam.ctypes.data_as(ct.c_void_p), None)
+    _check(st)
+    return res.value, lam

@@ -1,0 +1,573 @@
+// Divide and conquer for the symmetric band matrix T_m (half-bandwidth ell),
+// returning every eigenvalue and only the first and last ell rows of the
+// eigenvector matrix Q — the data Proposition 1 needs (Section 3.2 computes
+// exactly these rows, E_1^T Q and E_m^T Q, from a band-to-tridiagonal
+// reduction; here the band is split directly instead).
+//
+// Tree: leaves are diagonal blocks of T (size b = a multiple of ell, <= 64),
+// solved by Jacobi.  Two adjacent nodes L, R are coupled only by the ell x ell
+// block B = T[first rows of R, last rows of L]; with B = U diag(sigma) V^T,
+//     T = diag(T_L, T_R) + sum_i sigma_i (w+ w+^T - w- w-^T),
+//     w+- = (E_a v_i +- E_b u_i)/sqrt(2),
+// i.e. 2*ell symmetric rank-one updates of signs +-sigma_i, and the children
+// are never modified (their decompositions stay valid as T grows).  Each
+// update of D + rho z z^T (in the current eigenbasis) is done as in Cuppen's
+// method with the deflation of Dongarra-Sorensen, a safeguarded rational
+// secular-equation iteration, and the Gu-Eisenstat recomputation of z so the
+// eigenvectors are numerically orthogonal.  Only 4*ell rows of the eigenvector
+// matrix are carried through a merge: the first/last ell rows of each child
+// (to form z and to keep the merged node's first/last rows).
+#include <algorithm>
+#include <cmath>
+
+#include "dc.hpp"
+
+namespace lyap {
+
+constexpr int kMaxL = 16;              // ell <= 16
+constexpr int kRows = 4 * kMaxL;       // tracked rows per merge (4*ell)
+constexpr double kEps = 2.220446049250313e-16;
+
+struct DcMerge {
+  int a;    // first row of the merged node
+  int K1;   // size of the left child
+  int K;    // size of the merged node
+  int pad;
+};
+
+struct DcScal {
+  int Kn, Kd, sg, skip;
+  double r;          // |rho| * ||z||^2 (normalised problem)
+  double sigma[kMaxL];
+  double U[kMaxL * kMaxL];  // column i = u_i (R side)
+  double V[kMaxL * kMaxL];  // column i = v_i (L side)
+};
+
+// ------------------------------------------------------------------ leaves
+__global__ void k_leaf_extract(const double* band, int ldb, int ell, int k, int b, int nl, double* A) {
+  const int leaf = blockIdx.y;
+  const int a0 = leaf * b;
+  const int n = min(b, k - a0);
+  double* M = A + (size_t)leaf * b * b;
+  for (int e = threadIdx.x + blockIdx.x * blockDim.x; e < n * n; e += blockDim.x * gridDim.x) {
+    const int i = e / n, j = e % n;
+    const int d = i > j ? i - j : j - i;
+    const int c = (i > j ? j : i) + a0;
+    M[e] = d <= ell ? band[(size_t)c * ldb + d] : 0.0;
+  }
+}
+
+__global__ void k_leaf_store(const double* Q, const double* lam, int b, int ell, int k, double* D, double* F,
+                             double* L) {
+  const int leaf = blockIdx.y;
+  const int a0 = leaf * b;
+  const int n = min(b, k - a0);
+  const double* Ql = Q + (size_t)leaf * b * b;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    D[a0 + i] = lam[(size_t)leaf * b + i];
+    for (int a = 0; a < ell; ++a) {
+      F[(size_t)a * k + a0 + i] = Ql[a * n + i];
+      L[(size_t)a * k + a0 + i] = Ql[(n - ell + a) * n + i];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ small SVD (one-sided Jacobi)
+__device__ void svd_small(const double* B, int ell, double* U, double* sig, double* V) {
+  double W[kMaxL * kMaxL];
+  for (int i = 0; i < ell * ell; ++i) W[i] = B[i];  // W[r*ell + c], columns are vectors
+  for (int i = 0; i < ell; ++i)
+    for (int j = 0; j < ell; ++j) V[i * ell + j] = i == j ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < ell; ++p)
+      for (int q = p + 1; q < ell; ++q) {
+        double al = 0, be = 0, ga = 0;
+        for (int r = 0; r < ell; ++r) {
+          al += W[r * ell + p] * W[r * ell + p];
+          be += W[r * ell + q] * W[r * ell + q];
+          ga += W[r * ell + p] * W[r * ell + q];
+        }
+        if (fabs(ga) <= 1e-300 || fabs(ga) <= kEps * sqrt(al * be)) continue;
+        off = fmax(off, fabs(ga) / sqrt(al * be));
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        for (int r = 0; r < ell; ++r) {
+          const double wp = W[r * ell + p], wq = W[r * ell + q];
+          W[r * ell + p] = c * wp - s * wq;
+          W[r * ell + q] = s * wp + c * wq;
+          const double vp = V[r * ell + p], vq = V[r * ell + q];
+          V[r * ell + p] = c * vp - s * vq;
+          V[r * ell + q] = s * vp + c * vq;
+        }
+      }
+    if (off <= 2 * kEps) break;
+  }
+  for (int c = 0; c < ell; ++c) {
+    double nn = 0;
+    for (int r = 0; r < ell; ++r) nn += W[r * ell + c] * W[r * ell + c];
+    nn = sqrt(nn);
+    sig[c] = nn;
+    for (int r = 0; r < ell; ++r) U[r * ell + c] = nn > 0 ? W[r * ell + c] / nn : (r == c ? 1.0 : 0.0);
+  }
+}
+
+// ------------------------------------------------------------------ merge setup
+// Builds the sorted eigenvalues of diag(T_L, T_R) and the 4*ell tracked rows
+// [F_L 0; L_L 0; 0 F_R; 0 L_R] in that order; thread 0 of x-block 0 computes
+// the SVD of the coupling block.
+__global__ void k_merge_setup(const DcMerge* md, DcScal* ms, const double* band, int ldb, int ell, int k,
+                              const double* Dm, const double* Fm, const double* Lm, double* Dw, double* Rw) {
+  const DcMerge g = md[blockIdx.y];
+  const int a = g.a, K1 = g.K1, K2 = g.K - g.K1;
+  const double* lamL = Dm + a;
+  const double* lamR = Dm + a + K1;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < g.K; e += gridDim.x * blockDim.x) {
+    int pos;
+    const bool left = e < K1;
+    const int i = left ? e : e - K1;
+    const double v = left ? lamL[i] : lamR[i];
+    if (left) {  // + number of right values < v
+      int lo = 0, hi = K2;
+      while (lo < hi) { int mid = (lo + hi) >> 1; if (lamR[mid] < v) lo = mid + 1; else hi = mid; }
+      pos = i + lo;
+    } else {     // + number of left values <= v
+      int lo = 0, hi = K1;
+      while (lo < hi) { int mid = (lo + hi) >> 1; if (lamL[mid] <= v) lo = mid + 1; else hi = mid; }
+      pos = i + lo;
+    }
+    Dw[a + pos] = v;
+    const int col = a + e;
+    for (int r = 0; r < ell; ++r) {
+      Rw[(size_t)r * k + a + pos] = left ? Fm[(size_t)r * k + col] : 0.0;
+      Rw[(size_t)(ell + r) * k + a + pos] = left ? Lm[(size_t)r * k + col] : 0.0;
+      Rw[(size_t)(2 * ell + r) * k + a + pos] = left ? 0.0 : Fm[(size_t)r * k + col];
+      Rw[(size_t)(3 * ell + r) * k + a + pos] = left ? 0.0 : Lm[(size_t)r * k + col];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double B[kMaxL * kMaxL];
+    // B[r][c] = T(a + K1 + r, a + K1 - ell + c)
+    for (int r = 0; r < ell; ++r)
+      for (int c = 0; c < ell; ++c) {
+        const int row = a + K1 + r, colT = a + K1 - ell + c;
+        const int d = row - colT;
+        B[r * ell + c] = (d >= 0 && d <= ell) ? band[(size_t)colT * ldb + d] : 0.0;
+      }
+    DcScal& s = ms[blockIdx.y];
+    svd_small(B, ell, s.U, s.sigma, s.V);
+  }
+}
+
+// z = (R_a^T v_i + sg R_b^T u_i) / sqrt(2) for update u = 2i + (sg < 0)
+__global__ void k_zform(const DcMerge* md, const DcScal* ms, int ell, int k, int upd, const double* Rw, double* z) {
+  const DcMerge g = md[blockIdx.y];
+  const DcScal& s = ms[blockIdx.y];
+  const int i = upd >> 1;
+  const double sg = (upd & 1) ? -1.0 : 1.0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < g.K; e += gridDim.x * blockDim.x) {
+    const int col = g.a + e;
+    double zx = 0.0, zy = 0.0;
+    for (int r = 0; r < ell; ++r) {
+      zx = fma(Rw[(size_t)(ell + r) * k + col], s.V[r * ell + i], zx);
+      zy = fma(Rw[(size_t)(2 * ell + r) * k + col], s.U[r * ell + i], zy);
+    }
+    z[col] = (zx + sg * zy) * 0.70710678118654752440;
+  }
+}
+
+// Deflation (one thread per merge).  Working index w runs over the columns in
+// ascending order of sg*D (sg = sign(rho)): column c(w) = w (sg > 0) or K-1-w.
+__global__ void k_deflate(const DcMerge* md, DcScal* ms, int ell, int k, int upd, double* Dw, double* Rw,
+                          const double* z, double* Dn, double* zn, int* nd, int* defl, double* defv) {
+  if (threadIdx.x != 0) return;
+  const DcMerge g = md[blockIdx.x];
+  DcScal& s = ms[blockIdx.x];
+  const int a = g.a, K = g.K;
+  const int i = upd >> 1;
+  const int sg = (upd & 1) ? -1 : 1;
+  double r = s.sigma[i];
+  double nz2 = 0.0, dmax = 0.0;
+  for (int c = 0; c < K; ++c) {
+    nz2 += z[a + c] * z[a + c];
+    dmax = fmax(dmax, fabs(Dw[a + c]));
+  }
+  s.sg = sg;
+  const int nr = 4 * ell;
+  if (!(r > 0.0) || !(nz2 > 0.0)) {
+    s.skip = 1;
+    s.Kn = 0;
+    s.Kd = K;
+    for (int w = 0; w < K; ++w) {
+      const int c = sg > 0 ? w : K - 1 - w;
+      defl[a + w] = w;
+      defv[a + w] = sg * Dw[a + c];
+    }
+    s.r = 0.0;
+    return;
+  }
+  s.skip = 0;
+  r *= nz2;
+  const double inv = 1.0 / sqrt(nz2);
+  const double tol = 8.0 * kEps * fmax(dmax, r);
+  int p = -1, Kn = 0, Kd = 0;
+  double pz = 0.0, pd = 0.0;
+  for (int w = 0; w < K; ++w) {
+    const int c = sg > 0 ? w : K - 1 - w;
+    const double zw = z[a + c] * inv;
+    const double dw = sg * Dw[a + c];
+    if (r * fabs(zw) <= tol) {
+      defl[a + Kd] = w;
+      defv[a + Kd] = dw;
+      ++Kd;
+      continue;
+    }
+    if (p < 0) { p = w; pz = zw; pd = dw; continue; }
+    const double tt = hypot(zw, pz);
+    const double cc = zw / tt, ss = pz / tt;
+    if (fabs((dw - pd) * cc * ss) <= tol) {
+      // rotate columns c(p), c(w): q_p' = cc q_p - ss q_w, q_w' = ss q_p + cc q_w
+      const int cp = sg > 0 ? p : K - 1 - p;
+      for (int row = 0; row < nr; ++row) {
+        double* R = Rw + (size_t)row * k + a;
+        const double qp = R[cp], qw = R[c];
+        R[cp] = cc * qp - ss * qw;
+        R[c] = ss * qp + cc * qw;
+      }
+      const double dpn = pd * cc * cc + dw * ss * ss;
+      const double dwn = pd * ss * ss + dw * cc * cc;
+      defl[a + Kd] = p;
+      defv[a + Kd] = dpn;
+      ++Kd;
+      p = w; pz = tt; pd = dwn;
+    } else {
+      nd[a + Kn] = p; Dn[a + Kn] = pd; zn[a + Kn] = pz; ++Kn;
+      p = w; pz = zw; pd = dw;
+    }
+  }
+  if (p >= 0) { nd[a + Kn] = p; Dn[a + Kn] = pd; zn[a + Kn] = pz; ++Kn; }
+  // deflated values nearly sorted (rotations move values slightly): insertion sort
+  for (int x = 1; x < Kd; ++x) {
+    const double v = defv[a + x];
+    const int iw = defl[a + x];
+    int y = x - 1;
+    while (y >= 0 && defv[a + y] > v) { defv[a + y + 1] = defv[a + y]; defl[a + y + 1] = defl[a + y]; --y; }
+    defv[a + y + 1] = v;
+    defl[a + y + 1] = iw;
+  }
+  s.Kn = Kn;
+  s.Kd = Kd;
+  s.r = r;
+}
+
+// Secular equation 1/r + sum_i z_i^2/(d_i - lambda) = 0: one wave per root.
+// Root j lies in (d_j, d_{j+1}) (last: (d_{K-1}, d_{K-1} + r||z||^2)); it is
+// stored as the nearer pole index o_j and the offset tau_j = lambda_j - d_{o_j}
+// so that every difference d_i - lambda_j is formed accurately.
+__global__ __launch_bounds__(256) void k_secular(const DcMerge* md, const DcScal* ms, const double* Dn,
+                                                 const double* zn, int* orig, double* tau, double* lamn) {
+  const DcMerge g = md[blockIdx.y];
+  const DcScal& s = ms[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int Kn = s.Kn;
+  if (j >= Kn) return;
+  const double* d = Dn + g.a;
+  const double* zz = zn + g.a;
+  const double r = s.r;
+  const double ir = 1.0 / r;
+  const bool last = (j == Kn - 1);
+  int o;
+  double lo, hi;
+  if (!last) {
+    const double delta = d[j + 1] - d[j];
+    const double mid = d[j] + 0.5 * delta;
+    double f = 0.0;
+    for (int i = lane; i < Kn; i += 64) f += zz[i] * zz[i] / (d[i] - mid);
+    f = wave_sum(f) + ir;
+    if (f >= 0.0) { o = j; lo = 0.0; hi = 0.5 * delta; }
+    else { o = j + 1; lo = -0.5 * delta; hi = 0.0; }
+  } else {
+    double z2 = 0.0;
+    for (int i = lane; i < Kn; i += 64) z2 += zz[i] * zz[i];
+    z2 = wave_sum(z2);
+    o = j; lo = 0.0; hi = r * z2;
+  }
+  const double dO = d[o];
+  double t = 0.5 * (lo + hi);
+  const double Dj = d[j] - dO;
+  const double Dj1 = last ? 0.0 : d[j + 1] - dO;
+  for (int it = 0; it < 120; ++it) {
+    double psi = 0, phi = 0, dpsi = 0, dphi = 0;
+    for (int i = lane; i < Kn; i += 64) {
+      const double dl = (d[i] - dO) - t;
+      const double z2 = zz[i] * zz[i];
+      const double q = z2 / dl;
+      if (i <= j) { psi += q; dpsi += q / dl; }
+      else { phi += q; dphi += q / dl; }
+    }
+    psi = wave_sum(psi); phi = wave_sum(phi); dpsi = wave_sum(dpsi); dphi = wave_sum(dphi);
+    const double f = ir + psi + phi;
+    if (f < 0.0) lo = fmax(lo, t); else hi = fmin(hi, t);
+    const double err = 8.0 * kEps * (ir + fabs(psi) + fabs(phi) + fabs(t) * (dpsi + dphi));
+    if (fabs(f) <= err || (hi - lo) <= 4.0 * kEps * fmax(fabs(lo), fabs(hi))) break;
+    const double dlj = Dj - t;
+    const double b1 = dpsi * dlj * dlj;
+    const double a1 = psi - b1 / dlj;
+    double tn;
+    if (!last) {
+      const double dlj1 = Dj1 - t;
+      const double b2 = dphi * dlj1 * dlj1;
+      const double a2 = phi - b2 / dlj1;
+      const double c = ir + a1 + a2;
+      const double dd = Dj1 - Dj;
+      const double Bq = c * dd + b1 + b2, Cq = b1 * dd;
+      double p;
+      if (c == 0.0) {
+        p = -Cq / Bq;
+      } else {
+        const double sq = sqrt(fmax(Bq * Bq - 4.0 * c * Cq, 0.0));
+        double p1, p2;
+        if (Bq > 0) { p1 = (-Bq - sq) / (2.0 * c); p2 = 2.0 * Cq / (-Bq - sq); }
+        else { const double den = -Bq + sq; p1 = den != 0.0 ? 2.0 * Cq / den : -INFINITY; p2 = den / (2.0 * c); }
+        p = (p1 > -dd && p1 < 0.0) ? p1 : p2;
+      }
+      tn = Dj - p;
+    } else {
+      const double c = ir + a1;
+      tn = c != 0.0 ? Dj + b1 / c : 0.5 * (lo + hi);
+    }
+    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    if (tn == t) break;
+    t = tn;
+  }
+  if (lane == 0) {
+    orig[g.a + j] = o;
+    tau[g.a + j] = t;
+    lamn[g.a + j] = dO + t;
+  }
+}
+
+// Gu-Eisenstat: r zhat_i^2 = prod_j (lambda_j - d_i) / prod_{j != i} (d_j - d_i); one wave per i.
+__global__ __launch_bounds__(256) void k_zhat(const DcMerge* md, const DcScal* ms, const double* Dn,
+                                              const double* zn, const int* orig, const double* tau, double* zh) {
+  const DcMerge g = md[blockIdx.y];
+  const DcScal& s = ms[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int Kn = s.Kn;
+  if (i >= Kn) return;
+  const double* d = Dn + g.a;
+  const int* og = orig + g.a;
+  const double* tt = tau + g.a;
+  const double di = d[i];
+  double prod = 1.0;
+  for (int j = lane; j < Kn; j += 64) {
+    const double num = (d[og[j]] - di) + tt[j];  // lambda_j - d_i
+    prod *= (j == i) ? num : num / (d[j] - di);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) prod *= __shfl_xor(prod, off, 64);
+  if (lane == 0) {
+    const double v = sqrt(fmax(prod, 0.0) / s.r);
+    zh[g.a + i] = zn[g.a + i] >= 0.0 ? v : -v;
+  }
+}
+
+// Eigenvector j of D + r z z^T is zhat ./ (d - lambda_j), normalised; the
+// tracked rows become Rows(:, nd) * u_j.  One wave per j.
+__global__ __launch_bounds__(256) void k_vec(const DcMerge* md, const DcScal* ms, int ell, int k, const double* Rw,
+                                             const double* Dn, const int* nd, const int* orig, const double* tau,
+                                             const double* zh, double* NR) {
+  const DcMerge g = md[blockIdx.y];
+  const DcScal& s = ms[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int Kn = s.Kn;
+  if (j >= Kn) return;
+  const int nr = 4 * ell;
+  const double* d = Dn + g.a;
+  const double dO = d[orig[g.a + j]];
+  const double tj = tau[g.a + j];
+  double acc[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) acc[r] = 0.0;
+  double nn = 0.0;
+  for (int i = lane; i < Kn; i += 64) {
+    const double u = zh[g.a + i] / ((d[i] - dO) - tj);
+    nn = fma(u, u, nn);
+    const int w = nd[g.a + i];
+    const int c = s.sg > 0 ? w : g.K - 1 - w;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r)
+      if (r < nr) acc[r] = fma(Rw[(size_t)r * k + g.a + c], u, acc[r]);
+  }
+  nn = wave_sum(nn);
+  const double inv = 1.0 / sqrt(nn);
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    if (r < nr) {
+      const double v = wave_sum(acc[r]);
+      if (lane == 0) NR[(size_t)r * k + g.a + j] = v * inv;
+    }
+  }
+}
+
+// New spectrum = deflated values U new roots, merged in ascending order (ties:
+// deflated first), mapped back to the original orientation.
+__global__ void k_assemble(const DcMerge* md, const DcScal* ms, int ell, int k, const double* Rin, const double* NR,
+                           const int* defl, const double* defv, const double* lamn, double* Dout, double* Rout) {
+  const DcMerge g = md[blockIdx.y];
+  const DcScal& s = ms[blockIdx.y];
+  const int a = g.a, K = g.K, Kn = s.Kn, Kd = s.Kd, sg = s.sg;
+  const int nr = 4 * ell;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < K; e += gridDim.x * blockDim.x) {
+    int pos;
+    double v;
+    if (e < Kd) {
+      v = defv[a + e];
+      int lo = 0, hi = Kn;
+      while (lo < hi) { int mid = (lo + hi) >> 1; if (lamn[a + mid] < v) lo = mid + 1; else hi = mid; }
+      pos = e + lo;
+    } else {
+      const int j = e - Kd;
+      v = lamn[a + j];
+      int lo = 0, hi = Kd;
+      while (lo < hi) { int mid = (lo + hi) >> 1; if (defv[a + mid] <= v) lo = mid + 1; else hi = mid; }
+      pos = j + lo;
+    }
+    const int P = sg > 0 ? pos : K - 1 - pos;
+    Dout[a + P] = sg > 0 ? v : -v;
+    if (e < Kd) {
+      const int w = defl[a + e];
+      const int c = sg > 0 ? w : K - 1 - w;
+      for (int r = 0; r < nr; ++r) Rout[(size_t)r * k + a + P] = Rin[(size_t)r * k + a + c];
+    } else {
+      const int j = e - Kd;
+      for (int r = 0; r < nr; ++r) Rout[(size_t)r * k + a + P] = NR[(size_t)r * k + a + j];
+    }
+  }
+}
+
+__global__ void k_merge_finish(const DcMerge* md, int ell, int k, const double* Dw, const double* Rw, double* Dm,
+                               double* Fm, double* Lm) {
+  const DcMerge g = md[blockIdx.y];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < g.K; e += gridDim.x * blockDim.x) {
+    const int col = g.a + e;
+    Dm[col] = Dw[col];
+    for (int r = 0; r < ell; ++r) {
+      Fm[(size_t)r * k + col] = Rw[(size_t)r * k + col];
+      Lm[(size_t)r * k + col] = Rw[(size_t)(3 * ell + r) * k + col];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ driver
+struct DcWork::Impl {
+  int ell;
+  hipStream_t st;
+  int cap = 0;
+  int leaf = 32;
+  DevBuf Da, Db, Ra, Rb, z, Dn, zn, nd, defl, defv, orig, tau, lamn, zh, NR;
+  DevBuf leafA, leafQ, leafL, leafN;
+  DevBuf md, ms;
+  int md_cap = 0;
+
+  void ensure(int k) {
+    if (k <= cap) return;
+    int c = std::max(k, cap * 3 / 2);
+    c = (c + 255) / 256 * 256;
+    const size_t d = (size_t)c * sizeof(double), ii = (size_t)c * sizeof(int);
+    Da.alloc(d); Db.alloc(d);
+    Ra.alloc(d * 4 * ell); Rb.alloc(d * 4 * ell); NR.alloc(d * 4 * ell);
+    z.alloc(d); Dn.alloc(d); zn.alloc(d); defv.alloc(d); tau.alloc(d); lamn.alloc(d); zh.alloc(d);
+    nd.alloc(ii); defl.alloc(ii); orig.alloc(ii);
+    const int nl = (c + leaf - 1) / leaf;
+    leafA.alloc((size_t)nl * leaf * leaf * sizeof(double));
+    leafQ.alloc((size_t)nl * leaf * leaf * sizeof(double));
+    leafL.alloc((size_t)nl * leaf * sizeof(double));
+    leafN.alloc((size_t)nl * sizeof(int));
+    cap = c;
+  }
+};
+
+DcWork::DcWork(int ell, hipStream_t st) : impl_(new Impl) {
+  LYAP_REQUIRE(ell >= 1 && ell <= kMaxL, LYAP_E_UNSUPPORTED, "band eigensolver: ell=%d > %d", ell, kMaxL);
+  impl_->ell = ell;
+  impl_->st = st;
+  int b = ell * std::max(1, 32 / ell);
+  impl_->leaf = b;
+}
+DcWork::~DcWork() { delete impl_; }
+
+void DcWork::run(const double* band, int ldb, int k, double* lam, double* F, double* L) {
+  Impl& w = *impl_;
+  const int ell = w.ell;
+  const int b = w.leaf;
+  hipStream_t st = w.st;
+  w.ensure(k);
+  // leaves
+  const int nl = (k + b - 1) / b;
+  std::vector<int> nlist(nl);
+  for (int i = 0; i < nl; ++i) nlist[i] = std::min(b, k - i * b);
+  LYAP_HIP(hipMemcpyAsync(w.leafN.p, nlist.data(), nl * sizeof(int), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_leaf_extract, dim3(4, nl), dim3(256), 0, st, band, ldb, ell, k, b, nl, w.leafA.as<double>());
+  launch_jacobi(w.leafA.as<double>(), (int64_t)b * b, w.leafQ.as<double>(), (int64_t)b * b, w.leafL.as<double>(), b,
+                w.leafN.as<int>(), b, nl, st);
+  hipLaunchKernelGGL(k_leaf_store, dim3(1, nl), dim3(64), 0, st, w.leafQ.as<double>(), w.leafL.as<double>(), b, ell,
+                     k, lam, F, L);
+  LYAP_LAUNCHED("dc leaves");
+  // nodes: (offset, size)
+  std::vector<std::pair<int, int>> nodes;
+  for (int i = 0; i < nl; ++i) nodes.emplace_back(i * b, nlist[i]);
+  while (nodes.size() > 1) {
+    std::vector<DcMerge> hm;
+    std::vector<std::pair<int, int>> next;
+    int Kmax = 0;
+    for (size_t i = 0; i + 1 < nodes.size(); i += 2) {
+      DcMerge g{nodes[i].first, nodes[i].second, nodes[i].second + nodes[i + 1].second, 0};
+      hm.push_back(g);
+      next.emplace_back(g.a, g.K);
+      Kmax = std::max(Kmax, g.K);
+    }
+    if (nodes.size() % 2) next.push_back(nodes.back());
+    const int nm = (int)hm.size();
+    if (nm > w.md_cap) {
+      w.md.alloc((size_t)nm * sizeof(DcMerge));
+      w.ms.alloc((size_t)nm * sizeof(DcScal));
+      w.md_cap = nm;
+    }
+    LYAP_HIP(hipMemcpyAsync(w.md.p, hm.data(), nm * sizeof(DcMerge), hipMemcpyHostToDevice, st));
+    const DcMerge* md = w.md.as<DcMerge>();
+    DcScal* ms = w.ms.as<DcScal>();
+    const int gx = std::min((Kmax + 255) / 256, 64);
+    const int gw = (Kmax + 3) / 4;  // one wave per element, 4 waves per block
+    double* Dcur = w.Da.as<double>();
+    double* Dnx = w.Db.as<double>();
+    double* Rcur = w.Ra.as<double>();
+    double* Rnx = w.Rb.as<double>();
+    hipLaunchKernelGGL(k_merge_setup, dim3(gx, nm), dim3(256), 0, st, md, ms, band, ldb, ell, k, lam, F, L, Dcur,
+                       Rcur);
+    for (int u = 0; u < 2 * ell; ++u) {
+      hipLaunchKernelGGL(k_zform, dim3(gx, nm), dim3(256), 0, st, md, ms, ell, k, u, Rcur, w.z.as<double>());
+      hipLaunchKernelGGL(k_deflate, dim3(nm), dim3(64), 0, st, md, ms, ell, k, u, Dcur, Rcur, w.z.as<double>(),
+                         w.Dn.as<double>(), w.zn.as<double>(), w.nd.as<int>(), w.defl.as<int>(), w.defv.as<double>());
+      hipLaunchKernelGGL(k_secular, dim3(gw, nm), dim3(256), 0, st, md, ms, w.Dn.as<double>(), w.zn.as<double>(),
+                         w.orig.as<int>(), w.tau.as<double>(), w.lamn.as<double>());
+      hipLaunchKernelGGL(k_zhat, dim3(gw, nm), dim3(256), 0, st, md, ms, w.Dn.as<double>(), w.zn.as<double>(),
+                         w.orig.as<int>(), w.tau.as<double>(), w.zh.as<double>());
+      hipLaunchKernelGGL(k_vec, dim3(gw, nm), dim3(256), 0, st, md, ms, ell, k, Rcur, w.Dn.as<double>(),
+                         w.nd.as<int>(), w.orig.as<int>(), w.tau.as<double>(), w.zh.as<double>(), w.NR.as<double>());
+      hipLaunchKernelGGL(k_assemble, dim3(gx, nm), dim3(256), 0, st, md, ms, ell, k, Rcur, w.NR.as<double>(),
+                         w.defl.as<int>(), w.defv.as<double>(), w.lamn.as<double>(), Dnx, Rnx);
+      std::swap(Dcur, Dnx);
+      std::swap(Rcur, Rnx);
+    }
+    hipLaunchKernelGGL(k_merge_finish, dim3(gx, nm), dim3(256), 0, st, md, ell, k, Dcur, Rcur, lam, F, L);
+    LYAP_LAUNCHED("dc merge level");
+    nodes.swap(next);
+  }
+}
+
+}  // namespace lyap

@@ -1,0 +1,62 @@
+// Launch interface of the block Lanczos kernels (see lanczos.hip).
+#pragma once
+
+#include "op.hpp"
+
+namespace lyap {
+
+// Per-step coefficient log: 11 slots of S x S FP64 (row-major [a][b]) followed
+// by 4 scalars (log_stride(S) doubles per step).
+enum LogSlot {
+  L_A1 = 0,  // alpha applied against V_{j-1}, first sweep
+  L_A2 = 1,  // alpha against V_j, first sweep
+  L_A3 = 2,  // alpha against V_{j-1}, second sweep
+  L_A4 = 3,  // alpha against V_j, second sweep
+  L_G1 = 4,  // W^T W before the QR
+  L_R1 = 5,  // chol(G1)
+  L_R1I = 6, // R1^{-1}
+  L_G2 = 7,  // (W R1^{-1})^T (W R1^{-1})
+  L_R2 = 8,  // chol(G2)
+  L_R = 9,   // tau_{j+1,j} = R2 R1
+  L_RI = 10, // R1^{-1} R2^{-1}
+  L_FLAG = 11,  // scalars at 11*S*S: [0] smallest pivot ratio of chol(G1), [1] trace(G1)
+  L_NSLOT = 12
+};
+constexpr size_t log_stride(int S) { return (size_t)11 * S * S + 4; }
+
+template <typename T>
+struct StepArgs {
+  OpDev<T> op;
+  int n;
+  const T* Vprev;
+  const T* Vcur;
+  T* W;
+  T* Vnext;
+  double* log;       // this step's log
+  double* band;      // T_m lower band, ld = S+1
+  int j;             // step index (0-based)
+  double* part;      // grid partials
+  unsigned* counter; // arrival counter (zero between launches)
+  int* flags;        // [0] first breakdown step+1, [1] first non-finite step+1
+};
+
+template <typename T> void launch_step(const StepArgs<T>& a, int S, int grid, hipStream_t st);
+template <typename T>
+void launch_replay(const OpDev<T>& op, int S, const T* Vprev, const T* Vcur, T* Vnext, const double* log, int grid,
+                   hipStream_t st);
+template <typename T>
+void launch_init(const double* C, int64_t ldc, int n, int S, double* glog, double* part, unsigned* counter, int* flags,
+                 T* V1, int grid, hipStream_t st);
+template <typename T>
+void launch_init_store(const double* C, int64_t ldc, int n, int S, const double* glog, T* V1, int grid, hipStream_t st);
+// Up to 64 block pointers per flush launch (64/S blocks are used at a time).
+struct BlockList {
+  const void* p[64];
+};
+template <typename T>
+void launch_zflush(const void* const* blocks, int nb, int n, int S, const double* Mrows, int t, double* Z,
+                   int64_t ldz, int grid, hipStream_t st);
+template <typename T> void launch_apply(const OpDev<T>& op, int S, const T* V, T* W, int grid, hipStream_t st);
+int zflush_max_blocks(int S);
+
+}  // namespace lyap

@@ -1,0 +1,114 @@
+// Sparse operator application for row-interleaved n x S blocks: row r of a
+// block holds its S entries contiguously, so one row of V is one (or two)
+// vector loads and a stencil reads each neighbour row once.
+//
+// The per-row arithmetic (op_row) is the single definition used by the first
+// Lanczos pass, by the second pass that replays it and by lyap_op_apply, so
+// that all three produce the same bits for the same input.
+#pragma once
+
+#include "common.hpp"
+
+namespace lyap {
+
+// Device-side description of the operator; coefficient arrays are stored in the
+// basis storage type T (converted once per solve).
+template <typename T>
+struct OpDev {
+  int kind;            // LYAP_OP_*
+  int nx, ny, nz;
+  int n;
+  T cc, co;            // stencil5 centre (shift included) / neighbour
+  T shift;             // csr diagonal shift
+  const T* diag;       // stencil7 (shift included)
+  const T* tx;
+  const T* ty;
+  const T* tz;
+  const int64_t* rowptr;
+  const int32_t* col;
+  const T* val;
+};
+
+template <typename T, int S>
+__device__ __forceinline__ void load_row(const T* __restrict__ p, T (&v)[S]) {
+#pragma unroll
+  for (int c = 0; c < S; ++c) v[c] = p[c];
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void store_row(T* __restrict__ p, const T (&v)[S]) {
+#pragma unroll
+  for (int c = 0; c < S; ++c) p[c] = v[c];
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void axpy_row(T a, const T* __restrict__ p, T (&acc)[S]) {
+  T v[S];
+  load_row<T, S>(p, v);
+#pragma unroll
+  for (int c = 0; c < S; ++c) acc[c] = fma(a, v[c], acc[c]);
+}
+
+// w = (A V)_r, accumulated in T with a fixed order of terms.
+template <typename T, int S>
+__device__ __forceinline__ void op_row(const OpDev<T>& op, const T* __restrict__ V, int r,
+                                       T (&w)[S]) {
+  if (op.kind == LYAP_OP_STENCIL5) {
+    const int nx = op.nx;
+    const int j = r / nx;
+    const int i = r - j * nx;
+    T v[S];
+    load_row<T, S>(V + (size_t)r * S, v);
+#pragma unroll
+    for (int c = 0; c < S; ++c) w[c] = op.cc * v[c];
+    if (j > 0) axpy_row<T, S>(op.co, V + (size_t)(r - nx) * S, w);
+    if (i > 0) axpy_row<T, S>(op.co, V + (size_t)(r - 1) * S, w);
+    if (i < nx - 1) axpy_row<T, S>(op.co, V + (size_t)(r + 1) * S, w);
+    if (j < op.ny - 1) axpy_row<T, S>(op.co, V + (size_t)(r + nx) * S, w);
+  } else if (op.kind == LYAP_OP_STENCIL7) {
+    const int nx = op.nx, ny = op.ny;
+    const int nxy = nx * ny;
+    const int l = r / nxy;
+    const int rem = r - l * nxy;
+    const int j = rem / nx;
+    const int i = rem - j * nx;
+    T v[S];
+    load_row<T, S>(V + (size_t)r * S, v);
+    const T d = op.diag[r];
+#pragma unroll
+    for (int c = 0; c < S; ++c) w[c] = d * v[c];
+    if (l > 0) axpy_row<T, S>(op.tz[r - nxy], V + (size_t)(r - nxy) * S, w);
+    if (j > 0) axpy_row<T, S>(op.ty[r - nx], V + (size_t)(r - nx) * S, w);
+    if (i > 0) axpy_row<T, S>(op.tx[r - 1], V + (size_t)(r - 1) * S, w);
+    if (i < nx - 1) axpy_row<T, S>(op.tx[r], V + (size_t)(r + 1) * S, w);
+    if (j < ny - 1) axpy_row<T, S>(op.ty[r], V + (size_t)(r + nx) * S, w);
+    if (l < op.nz - 1) axpy_row<T, S>(op.tz[r], V + (size_t)(r + nxy) * S, w);
+  } else {  // CSR
+    const int64_t b = op.rowptr[r];
+    const int64_t e = op.rowptr[r + 1];
+#pragma unroll
+    for (int c = 0; c < S; ++c) w[c] = T(0);
+    for (int64_t k = b; k < e; ++k) axpy_row<T, S>(op.val[k], V + (size_t)op.col[k] * S, w);
+    if (op.shift != T(0)) axpy_row<T, S>(op.shift, V + (size_t)r * S, w);
+  }
+}
+
+// Host side: an operator converted to storage type T on the device.
+template <typename T>
+struct OpHolder {
+  OpDev<T> dev{};
+  DevBuf diag, tx, ty, tz, val;
+  int64_t nnz = 0;
+  // Algorithmic bytes read per row for the coefficients (0 for stencil5).
+  double coef_bytes_per_row() const {
+    if (dev.kind == LYAP_OP_STENCIL7) return 4.0 * sizeof(T);
+    if (dev.kind == LYAP_OP_CSR) return (double)nnz / dev.n * (sizeof(T) + 4) + 8;
+    return 0.0;
+  }
+};
+
+void make_op_f64(const lyap_op* A, OpHolder<double>& h, hipStream_t st);
+void make_op_f32(const lyap_op* A, OpHolder<float>& h, hipStream_t st);
+void validate_op(const lyap_op* A);
+
+}  // namespace lyap

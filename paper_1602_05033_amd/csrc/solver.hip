@@ -1,0 +1,429 @@
+// lyap_solve for the standard block Krylov space: Algorithm 1 driving the
+// block Lanczos kernels, the GPU residual check of Proposition 1 on the
+// schedule chosen below, the truncated factor of Y~ and the second Lanczos
+// pass of Section 3.3 (or the stored basis).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <type_traits>
+
+#include "check.hpp"
+#include "lanczos.hpp"
+#include "solver.hpp"
+
+using namespace lyap;
+
+extern "C" void lyap_opts_default(lyap_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-8;
+  o->max_iter = 5000;
+  o->method = LYAP_METHOD_STD;
+  o->check_every = 0;
+  o->storage = LYAP_STORE_F64;
+  o->two_pass = 1;
+  o->trunc_eps = -1.0;
+  o->inner_pc = LYAP_PC_IC0;
+  o->inner_tol = 1e-12;
+  o->inner_max_iter = 5000;
+  o->flush_blocks = 0;
+}
+
+extern "C" void lyap_result_free(lyap_result* r) {
+  if (!r) return;
+  std::free(r->hist_m);
+  std::free(r->hist_res);
+  std::free(r->T_band);
+  std::free(r->gamma);
+  std::free(r->tau);
+  if (r->Z && r->owns_Z) (void)hipFree(r->Z);
+  std::memset(r, 0, sizeof(*r));
+}
+
+namespace lyap {
+
+double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+// -------------------------------------------------------------- check schedule
+int CheckSchedule::first() const {
+  if (d > 0) return std::min(d, max_iter);
+  return std::min(10, max_iter);
+}
+
+int CheckSchedule::next(int m, double res, double tol) {
+  hist.emplace_back(m, std::log10(std::max(res, 1e-300)));
+  if (d > 0) return std::min(m + d, max_iter);
+  const int grow = std::max(5, m / 2);
+  int nxt = m + grow;
+  if (hist.size() >= 2) {
+    const auto& a = hist[hist.size() - 2];
+    const auto& b = hist[hist.size() - 1];
+    const double slope = (b.second - a.second) / double(b.first - a.first);
+    if (slope < 0) {
+      const double gap = (std::log10(tol) - b.second) / slope;  // steps to the predicted crossing
+      const int step = (int)std::ceil(gap);
+      nxt = m + std::max(1, std::min(step, grow));
+    }
+  }
+  return std::min(nxt, max_iter);
+}
+
+// -------------------------------------------------------------- result helpers
+void store_history(lyap_result* out, const std::vector<int>& hm, const std::vector<double>& hr) {
+  out->n_hist = (int)hm.size();
+  out->hist_m = (int32_t*)std::malloc(std::max<size_t>(1, hm.size()) * sizeof(int32_t));
+  out->hist_res = (double*)std::malloc(std::max<size_t>(1, hr.size()) * sizeof(double));
+  for (size_t i = 0; i < hm.size(); ++i) {
+    out->hist_m[i] = hm[i];
+    out->hist_res[i] = hr[i];
+  }
+}
+
+double* alloc_output(const lyap_opts& o, size_t bytes, bool* owned) {
+  void* p = nullptr;
+  if (o.alloc) {
+    p = o.alloc(bytes ? bytes : 8, o.alloc_ctx);
+    LYAP_REQUIRE(p != nullptr, LYAP_E_NOMEM, "allocator callback returned NULL for %zu bytes", bytes);
+    *owned = false;
+  } else {
+    hipError_t e = hipMalloc(&p, bytes ? bytes : 8);
+    LYAP_REQUIRE(e == hipSuccess, LYAP_E_NOMEM, "hipMalloc(%zu) for Z failed", bytes);
+    *owned = true;
+  }
+  return (double*)p;
+}
+
+static void rowmajor_to_colmajor(const double* rm, int rows, int cols, double* cm) {
+  for (int i = 0; i < rows; ++i)
+    for (int j = 0; j < cols; ++j) cm[i + (size_t)j * rows] = rm[(size_t)i * cols + j];
+}
+
+// -------------------------------------------------------------- standard Krylov
+template <typename T>
+lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, const lyap_opts& o, lyap_result* out) {
+  const auto t_entry = Clock::now();
+  hipStream_t st = (hipStream_t)o.stream;
+  const int n = (int)A->n;
+  out->n = n;
+  out->s = S;
+  out->ell = S;
+  OpHolder<T> op;
+  if constexpr (std::is_same_v<T, double>) make_op_f64(A, op, st);
+  else make_op_f32(A, op, st);
+
+  const int maxit = o.max_iter;
+  const size_t blk = (size_t)n * S * sizeof(T);
+  const size_t LS = log_stride(S);  // log doubles per step
+  const int grid = grid_for(n, 2, 2048);
+
+  DevBuf Vb0(blk), Vb1(blk), Wb(blk), zero(blk);
+  DevBuf logb(((size_t)maxit + 1) * LS * sizeof(double));
+  DevBuf glog(LS * sizeof(double));
+  DevBuf band((size_t)(S + 1) * S * (maxit + 2) * sizeof(double));
+  DevBuf part((size_t)2048 * S * S * sizeof(double));
+  DevBuf counter(256);
+  DevBuf flags(64);
+  DevBuf chk(sizeof(CheckOut));
+  HostBuf hchk(sizeof(CheckOut));
+  HostBuf hflags(64);
+  LYAP_HIP(hipMemsetAsync(counter.p, 0, 256, st));
+  LYAP_HIP(hipMemsetAsync(flags.p, 0, 64, st));
+  LYAP_HIP(hipMemsetAsync(zero.p, 0, blk, st));
+  LYAP_HIP(hipMemsetAsync(Vb0.p, 0, blk, st));
+  LYAP_HIP(hipMemsetAsync(band.p, 0, band.bytes, st));
+
+  // stored-basis mode keeps every block
+  std::vector<DevBuf> stored;
+  const bool two_pass = o.two_pass != 0;
+
+  // V_1 gamma = C  (CholQR2 of C)
+  T* V1p = two_pass ? Vb1.as<T>() : nullptr;
+  if (!two_pass) {
+    stored.emplace_back(blk);
+    V1p = stored.back().as<T>();
+  }
+  launch_init<T>(C, ldc, n, S, glog.as<double>(), part.as<double>(), counter.as<unsigned>(), flags.as<int>(), V1p,
+                 grid, st);
+  std::vector<double> hglog(LS);
+  LYAP_HIP(hipMemcpyAsync(hglog.data(), glog.p, LS * sizeof(double), hipMemcpyDeviceToHost, st));
+  LYAP_HIP(hipMemcpyAsync(hflags.p, flags.p, 64, hipMemcpyDeviceToHost, st));
+  LYAP_HIP(hipStreamSynchronize(st));
+  {
+    const int* f = hflags.as<int>();
+    const double trC = hglog[L_FLAG * S * S + 1];
+    LYAP_REQUIRE(f[1] == 0 && std::isfinite(trC), LYAP_E_NUMERIC, "C contains NaN or Inf");
+    LYAP_REQUIRE(trC > 0.0, LYAP_E_ARG, "C is zero");
+    LYAP_REQUIRE(f[0] == 0, LYAP_E_BREAKDOWN, "C is numerically rank deficient (deflation not implemented)");
+    out->beta = std::sqrt(trC);
+  }
+  const double beta2 = out->beta * out->beta;
+  const double* gamma_dev = glog.as<double>() + L_R * S * S;
+
+  Checker ck(S, S, st);
+  CheckSchedule sched{o.check_every, maxit};
+  std::vector<int> hm;
+  std::vector<double> hr;
+  double check_ms = 0.0;
+  int next_check = sched.first();
+  int m = 0;
+  lyap_status status = LYAP_NOT_CONVERGED;
+  double last_res = INFINITY;
+  double lam_absmax = 0.0;
+  int checked_m = 0;
+  double t_to_tol = 0.0;
+
+  T* Vprev = two_pass ? Vb0.as<T>() : zero.as<T>();
+  T* Vcur = V1p;
+
+  StepArgs<T> sa{};
+  sa.op = op.dev;
+  sa.n = n;
+  sa.W = Wb.as<T>();
+  sa.band = band.as<double>();
+  sa.part = part.as<double>();
+  sa.counter = counter.as<unsigned>();
+  sa.flags = flags.as<int>();
+
+  auto run_check = [&](int mm) {
+    const auto t0 = Clock::now();
+    const double* tau_dev = logb.as<double>() + (size_t)(mm - 1) * LS + L_R * S * S;
+    ck.run(band.as<double>(), mm * S, gamma_dev, tau_dev, chk.as<CheckOut>());
+    LYAP_HIP(hipMemcpyAsync(hchk.p, chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipStreamSynchronize(st));
+    check_ms += ms_since(t0);
+    const CheckOut& c = *hchk.as<CheckOut>();
+    checked_m = mm;
+    lam_absmax = std::max(std::fabs(c.lam_min), std::fabs(c.lam_max));
+    out->n_checks++;
+    return c;
+  };
+
+  const auto t_pass1 = Clock::now();
+  while (m < maxit) {
+    T* Vnext;
+    if (two_pass) {
+      Vnext = Vprev;  // V_{j+1} overwrites V_{j-1}
+    } else {
+      stored.emplace_back(blk);
+      Vnext = stored.back().as<T>();
+    }
+    sa.Vprev = Vprev;
+    sa.Vcur = Vcur;
+    sa.Vnext = Vnext;
+    sa.log = logb.as<double>() + (size_t)m * LS;
+    sa.j = m;
+    launch_step<T>(sa, S, grid, st);
+    ++m;
+    Vprev = Vcur;
+    Vcur = Vnext;
+    if (m == next_check || m == maxit) {
+      LYAP_HIP(hipMemcpyAsync(hflags.p, flags.p, 64, hipMemcpyDeviceToHost, st));
+      LYAP_HIP(hipStreamSynchronize(st));
+      const int* f = hflags.as<int>();
+      int mm = m;
+      bool broke = false;
+      if (f[0] > 0 && f[0] <= m) {
+        mm = f[0];  // the QR of step f[0]-1 found a rank-deficient block
+        broke = true;
+      } else if (f[1] > 0) {
+        LYAP_REQUIRE(false, LYAP_E_NUMERIC, "non-finite values in the Lanczos recurrence at step %d", f[1]);
+      }
+      CheckOut c = run_check(mm);
+      LYAP_REQUIRE(std::isfinite(c.res), LYAP_E_NUMERIC, "residual is not finite at m=%d", mm);
+      const double rel = c.res / beta2;
+      hm.push_back(mm);
+      hr.push_back(rel);
+      last_res = rel;
+      if (o.verbose) std::fprintf(stderr, "[lyap] m=%d k=%d res=%.3e\n", mm, mm * S, rel);
+      LYAP_REQUIRE(c.lam_max < 0.0, LYAP_E_INDEFINITE,
+                   "Ritz value %.3e >= 0 at m=%d: the operator is not negative definite", c.lam_max, mm);
+      if (rel <= o.tol) {
+        status = LYAP_OK;
+        m = mm;
+        t_to_tol = ms_since(t_entry);
+        break;
+      }
+      if (broke) {
+        m = mm;
+        status = LYAP_E_BREAKDOWN;
+        set_error("block Lanczos breakdown at m=%d with residual %.3e above tol", mm, rel);
+        break;
+      }
+      next_check = sched.next(m, rel, o.tol);
+    }
+  }
+  if (checked_m != m) {  // the last basis was not checked (max_iter without a due check)
+    CheckOut c = run_check(m);
+    hm.push_back(m);
+    hr.push_back(c.res / beta2);
+    last_res = c.res / beta2;
+  }
+  const double pass1_ms = ms_since(t_pass1) - check_ms;
+  out->m = m;
+  out->res = last_res;
+  store_history(out, hm, hr);
+
+  // ------------------------------------------------------------ finalisation
+  const auto t_fin = Clock::now();
+  std::vector<double> tau_h(S * S);
+  LYAP_HIP(hipMemcpyAsync(tau_h.data(), logb.as<double>() + (size_t)(m - 1) * LS + L_R * S * S,
+                          S * S * sizeof(double), hipMemcpyDeviceToHost, st));
+  LYAP_HIP(hipStreamSynchronize(st));
+  double tau_f = 0.0;
+  for (double v : tau_h) tau_f += v * v;
+  tau_f = std::sqrt(tau_f);
+  double eps = o.trunc_eps;
+  if (!(eps >= 0.0)) eps = std::min(1e-12, 0.05 * o.tol / (lam_absmax + tau_f)) * beta2;
+  out->trunc_eps = eps;
+  DevBuf M;
+  const int t = finalise_factor(ck, band.as<double>(), gamma_dev, eps, M, st);
+  out->t = t;
+  const double fin_ms = ms_since(t_fin);
+
+  // ------------------------------------------------------------ Z
+  const auto t_p2 = Clock::now();
+  bool owned = false;
+  out->Z = alloc_output(o, (size_t)n * std::max(t, 1) * sizeof(double), &owned);
+  out->owns_Z = owned ? 1 : 0;
+  if (t > 0) {
+    LYAP_HIP(hipMemsetAsync(out->Z, 0, (size_t)n * t * sizeof(double), st));
+    const int QB = zflush_max_blocks(S);
+    if (two_pass) {
+      const int R = QB + 2;
+      std::vector<DevBuf> ring;
+      for (int i = 0; i < R; ++i) ring.emplace_back(blk);
+      launch_init_store<T>(C, ldc, n, S, glog.as<double>(), ring[0].as<T>(), grid, st);
+      std::vector<const void*> pend;
+      int first = 0;
+      for (int i = 0; i < m; ++i) {
+        if (i + 1 < m) {
+          const T* vp = i > 0 ? ring[(i - 1) % R].as<T>() : zero.as<T>();
+          launch_replay<T>(op.dev, S, vp, ring[i % R].as<T>(), ring[(i + 1) % R].as<T>(),
+                           logb.as<double>() + (size_t)i * LS, grid, st);
+        }
+        if (pend.empty()) first = i;
+        pend.push_back(ring[i % R].p);
+        if ((int)pend.size() == QB || i == m - 1) {
+          launch_zflush<T>(pend.data(), (int)pend.size(), n, S, M.as<double>() + (size_t)first * S * t, t, out->Z,
+                           n, grid, st);
+          pend.clear();
+        }
+      }
+    } else {
+      std::vector<const void*> ptrs;
+      for (int i = 0; i < m; ++i) ptrs.push_back(stored[i].p);
+      launch_zflush<T>(ptrs.data(), m, n, S, M.as<double>(), t, out->Z, n, grid, st);
+    }
+  }
+  LYAP_HIP(hipStreamSynchronize(st));
+  const double p2_ms = ms_since(t_p2);
+
+  if (o.want_T) {
+    const int k = m * S;
+    out->T_band = (double*)std::malloc((size_t)(S + 1) * k * sizeof(double));
+    LYAP_HIP(hipMemcpy(out->T_band, band.p, (size_t)(S + 1) * k * sizeof(double), hipMemcpyDeviceToHost));
+    // entries below row k belong to tau_{m+1,m}; clear them
+    for (int c = 0; c < k; ++c)
+      for (int d = 0; d <= S; ++d)
+        if (c + d >= k) out->T_band[(size_t)c * (S + 1) + d] = 0.0;
+    out->gamma = (double*)std::malloc(S * S * sizeof(double));
+    out->tau = (double*)std::malloc(S * S * sizeof(double));
+    rowmajor_to_colmajor(hglog.data() + L_R * S * S, S, S, out->gamma);
+    rowmajor_to_colmajor(tau_h.data(), S, S, out->tau);
+  }
+  out->times_ms[LYAP_T_PASS1] = pass1_ms;
+  out->times_ms[LYAP_T_CHECKS] = check_ms;
+  out->times_ms[LYAP_T_FINAL] = fin_ms;
+  out->times_ms[LYAP_T_PASS2] = p2_ms;
+  out->times_ms[LYAP_T_TOTAL] = ms_since(t_entry);
+  out->times_ms[LYAP_T_TO_TOL] = t_to_tol;
+  const double b = sizeof(T);
+  const double coef = op.coef_bytes_per_row();
+  out->bytes_pass1 = (int64_t)((double)m * n * (21.0 * S * b + coef));
+  out->bytes_spmm = (int64_t)((double)m * n * (2.0 * S * b + coef));
+  out->status = status;
+  return status;
+}
+
+template lyap_status solve_std<float>(const lyap_op*, const double*, int, int64_t, const lyap_opts&, lyap_result*);
+template lyap_status solve_std<double>(const lyap_op*, const double*, int, int64_t, const lyap_opts&, lyap_result*);
+
+}  // namespace lyap
+
+extern "C" lyap_status lyap_solve(const lyap_op* A, const double* C, int32_t s, int64_t ldc, const lyap_opts* opts,
+                                  lyap_result* out) {
+  clear_error();
+  if (!out) {
+    set_error("out is NULL");
+    return LYAP_E_ARG;
+  }
+  std::memset(out, 0, sizeof(*out));
+  lyap_opts o;
+  if (opts) o = *opts;
+  else lyap_opts_default(&o);
+  try {
+    validate_op(A);
+    LYAP_REQUIRE(C != nullptr, LYAP_E_ARG, "C is NULL");
+    LYAP_REQUIRE(s >= 1 && s <= 8, LYAP_E_ARG, "s=%d out of range 1..8", s);
+    LYAP_REQUIRE(ldc >= A->n, LYAP_E_ARG, "ldc=%lld < n=%lld", (long long)ldc, (long long)A->n);
+    LYAP_REQUIRE(s <= A->n, LYAP_E_ARG, "s > n");
+    LYAP_REQUIRE(o.tol > 0.0 && o.tol < 1.0, LYAP_E_ARG, "tol=%g must be in (0,1)", o.tol);
+    LYAP_REQUIRE(o.max_iter >= 1 && (int64_t)o.max_iter * s <= (int64_t)1 << 20, LYAP_E_ARG,
+                 "max_iter=%d out of range", o.max_iter);
+    LYAP_REQUIRE(o.check_every >= 0, LYAP_E_ARG, "check_every must be >= 0");
+    LYAP_REQUIRE(o.storage == LYAP_STORE_F64 || o.storage == LYAP_STORE_F32, LYAP_E_ARG, "unknown storage %d",
+                 o.storage);
+    if (o.method == LYAP_METHOD_STD) {
+      lyap_status st = o.storage == LYAP_STORE_F64 ? solve_std<double>(A, C, s, ldc, o, out)
+                                                   : solve_std<float>(A, C, s, ldc, o, out);
+      out->status = st;
+      return st;
+    }
+    if (o.method == LYAP_METHOD_EXT) {
+      lyap_status st = o.storage == LYAP_STORE_F64 ? solve_ext<double>(A, C, s, ldc, o, out)
+                                                   : solve_ext<float>(A, C, s, ldc, o, out);
+      out->status = st;
+      return st;
+    }
+    LYAP_REQUIRE(false, LYAP_E_ARG, "unknown method %d", o.method);
+  } catch (const Error& e) {
+    out->status = e.st;
+    return e.st;
+  }
+  return LYAP_E_ARG;
+}
+
+extern "C" lyap_status lyap_ctri(const double* T_band, int32_t ell, int32_t k, const double* gamma,
+                                 const double* tau, double* res, double* lam, void* stream) {
+  clear_error();
+  try {
+    LYAP_REQUIRE(T_band && gamma && tau && res, LYAP_E_ARG, "NULL argument");
+    LYAP_REQUIRE(ell >= 1 && ell <= 16 && k >= ell && k % ell == 0, LYAP_E_ARG, "bad ell=%d / k=%d", ell, k);
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf band((size_t)(ell + 1) * k * sizeof(double));
+    DevBuf g(ell * ell * sizeof(double)), t(ell * ell * sizeof(double));
+    std::vector<double> grm(ell * ell), trm(ell * ell);
+    for (int i = 0; i < ell; ++i)
+      for (int j = 0; j < ell; ++j) {
+        grm[i * ell + j] = gamma[i + j * ell];
+        trm[i * ell + j] = tau[i + j * ell];
+      }
+    LYAP_HIP(hipMemcpyAsync(band.p, T_band, band.bytes, hipMemcpyHostToDevice, st));
+    LYAP_HIP(hipMemcpyAsync(g.p, grm.data(), ell * ell * sizeof(double), hipMemcpyHostToDevice, st));
+    LYAP_HIP(hipMemcpyAsync(t.p, trm.data(), ell * ell * sizeof(double), hipMemcpyHostToDevice, st));
+    DevBuf chk(sizeof(CheckOut));
+    Checker ck(ell, ell, st);
+    ck.run(band.as<double>(), k, g.as<double>(), t.as<double>(), chk.as<CheckOut>());
+    CheckOut h;
+    LYAP_HIP(hipMemcpyAsync(&h, chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, st));
+    if (lam) LYAP_HIP(hipMemcpyAsync(lam, ck.lam(), (size_t)k * sizeof(double), hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipStreamSynchronize(st));
+    *res = h.res;
+    return LYAP_OK;
+  } catch (const Error& e) {
+    return e.st;
+  }
+}

@@ -1,0 +1,274 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle on
+the same seeded inputs.  Needs an MI355X and the built library."""
+import numpy as np
+import pytest
+
+from workloads import laplace2d, fv3d, fd2d_variable, gaussian_C
+from oracle import krylov as K
+from oracle import dense as D
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _b():
+    from paper_1602_05033_amd import binding
+    return binding
+
+
+def _dev_C(C):
+    return torch.from_numpy(np.ascontiguousarray(C)).cuda()
+
+
+# ------------------------------------------------------------------ SpMM
+def _ops():
+    return {
+        "stencil5": (laplace2d(37, shift=0.5), False),
+        "stencil7_3d": (fv3d(11, 1.0, 3), False),
+        "stencil7_2d": (fd2d_variable(29, lambda x, y: np.exp(-x * y), lambda x, y: np.exp(x * y)), False),
+        "csr": (fv3d(9, 0.5, 4), True),
+    }
+
+
+@pytest.mark.parametrize("kind", ["stencil5", "stencil7_3d", "stencil7_2d", "csr"])
+@pytest.mark.parametrize("storage", [0, 1])
+@pytest.mark.parametrize("s", [1, 3, 4, 8])
+def test_spmm_parity(lib, kind, storage, s):
+    b = _b()
+    op, as_csr = _ops()[kind]
+    shift = 0.5 if kind == "stencil5" else 0.0
+    dop = b.device_op(op, as_csr=as_csr, shift=0.0)
+    rng = np.random.default_rng([11, s, storage])
+    V = rng.standard_normal((op.n, s))
+    dt = np.float64 if storage == 0 else np.float32
+    Vs = V.astype(dt)
+    W = b.op_apply(dop, torch.from_numpy(Vs).cuda(), storage).cpu().numpy().astype(np.float64)
+    A = op.to_scipy()
+    ref = A @ Vs.astype(np.float64)
+    scale = abs(A) @ np.abs(Vs.astype(np.float64)) + 1e-300
+    err = np.max(np.abs(W - ref) / scale)
+    tol = 4e-16 if storage == 0 else 8e-7
+    assert err <= tol * 8, (kind, storage, s, err)
+    del shift
+
+
+def test_spmm_full_size_sampled(lib):
+    """The 1000 x 1000 Laplacian at s=4, FP32 storage: sampled rows against the
+    definition, rows spanning tile edges and the grid boundary."""
+    b = _b()
+    op = laplace2d(1000)
+    dop = b.device_op(op)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    V = torch.randn(op.n, 4, device="cuda", generator=g, dtype=torch.float32)
+    W = b.op_apply(dop, V, 1)
+    rows = np.unique(np.concatenate([np.arange(0, 1100), np.arange(op.n - 1100, op.n),
+                                     np.random.default_rng(1).integers(0, op.n, 4000)]))
+    Vh = V.cpu().numpy().astype(np.float64)
+    A = op.to_scipy()[rows]
+    ref = A @ Vh
+    scale = abs(A) @ np.abs(Vh)
+    err = np.max(np.abs(W.cpu().numpy()[rows] - ref) / scale)
+    assert err < 8 * 8e-7
+
+
+# ------------------------------------------------------------------ residual formula
+def _lanczos_T(N, s, m, seed=1):
+    op = laplace2d(N)
+    A = op.to_scipy()
+    C = gaussian_C(op.n, s, seed)
+    _, gamma = K.qr_pos(C)
+    V = K.right_solve_upper(C, gamma)
+    Vp = np.zeros_like(V)
+    recs = []
+    for _ in range(m):
+        Vn, rec, _, _, _ = K.block_lanczos_step(A, Vp, V)
+        recs.append(rec)
+        Vp, V = V, Vn
+    T = K.assemble_T(recs, m)
+    k = s * m
+    band = np.zeros((k, s + 1))
+    for c in range(k):
+        for d in range(s + 1):
+            if c + d < k:
+                band[c, d] = T[c + d, c]
+    return T, band, gamma, recs[-1].R, float(np.linalg.norm(C) ** 2)
+
+
+@pytest.mark.parametrize("N,s,m", [(32, 1, 40), (32, 2, 30), (32, 4, 25), (32, 4, 60), (60, 1, 300),
+                                   (60, 2, 200), (100, 4, 175), (100, 3, 111)])
+def test_ctri_parity(lib, N, s, m):
+    """Eigenvalues (Jacobi for k <= 64, divide and conquer above) and the
+    Proposition 1 residual against LAPACK-based Algorithm 3 in the oracle."""
+    b = _b()
+    T, band, gamma, tau, beta2 = _lanczos_T(N, s, m)
+    ref = K.residual_alg3(T, gamma, tau)
+    res, lam = b.ctri(band, gamma, tau)
+    assert np.max(np.abs(lam - ref.lam)) < 1e-12 * np.max(np.abs(ref.lam))
+    # relative agreement where the residual is above the FP64 floor of the formula
+    assert abs(res - ref.res) / ref.res < 1e-7 or abs(res - ref.res) / beta2 < 1e-14
+
+
+def test_band_eigen_with_ghost_clusters(lib):
+    """Lanczos run far past convergence: T has ghost copies of converged Ritz
+    values (relative gaps ~1e-13); all eigenvalues must still be found."""
+    b = _b()
+    T, band, gamma, tau, beta2 = _lanczos_T(32, 1, 400)
+    ref = K.residual_alg3(T, gamma, tau)
+    res, lam = b.ctri(band, gamma, tau)
+    assert np.min(np.diff(ref.lam)) / np.max(np.abs(ref.lam)) < 1e-12
+    assert np.max(np.abs(lam - ref.lam)) < 1e-12 * np.max(np.abs(ref.lam))
+    assert res / beta2 < 1e-14
+
+
+# ------------------------------------------------------------------ whole solver, C1
+def _c1(s):
+    op = laplace2d(32)
+    return op, gaussian_C(op.n, s, 1)
+
+
+@pytest.fixture(scope="module")
+def oracle_c1():
+    out = {}
+    for s in (1, 4):
+        op, C = _c1(s)
+        out[s] = K.lyap_std(op.to_scipy(), C, tol=1e-8, check_every=1)
+    return out
+
+
+@pytest.mark.parametrize("s", [1, 4])
+@pytest.mark.parametrize("two_pass", [True, False])
+def test_c1_solve_fp64(lib, oracle_c1, s, two_pass):
+    b = _b()
+    op, C = _c1(s)
+    orc = oracle_c1[s]
+    sol = b.lyap_solve(b.device_op(op), _dev_C(C), tol=1e-8, check_every=1, two_pass=two_pass, want_T=True)
+    assert sol.status == b.OK
+    assert sol.m == orc.m
+    gh = np.array(sol.hist_res)
+    oh = np.array([h["res"] for h in orc.hist])
+    assert len(gh) == len(oh)
+    assert np.max(np.abs(gh - oh) / oh) < 1e-6
+    Z = sol.Z.cpu().numpy()
+    A = op.to_scipy()
+    expl = K.explicit_residual(A, Z, C) / sol.beta ** 2
+    assert expl <= 1.2e-8
+    X = D.lyap_laplace2d_dense(32, C)
+    assert K.lowrank_vs_dense_error(Z, X) <= 1e-7
+    assert K.factor_error(Z, orc.Z) <= 1e-7
+    # T_m: early blocks agree entrywise with the oracle's
+    k = s * sol.m
+    Tg = np.zeros((k, k))
+    for c in range(k):
+        for d in range(s + 1):
+            if c + d < k:
+                Tg[c + d, c] = Tg[c, c + d] = sol.T_band[c, d]
+    kk = 10 * s
+    assert np.max(np.abs(Tg[:kk, :kk] - orc.T[:kk, :kk])) <= 1e-10 * np.max(np.abs(orc.T))
+
+
+@pytest.mark.parametrize("s", [1, 4])
+def test_two_pass_replays_the_basis_bitwise(lib, s):
+    """The second pass regenerates every block exactly: Z from the replay equals
+    Z from the stored basis bit for bit (same flush grouping)."""
+    b = _b()
+    op, C = _c1(s)
+    dop = b.device_op(op)
+    z1 = b.lyap_solve(dop, _dev_C(C), check_every=1, two_pass=True).Z
+    z2 = b.lyap_solve(dop, _dev_C(C), check_every=1, two_pass=False).Z
+    assert torch.equal(z1, z2)
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_run_twice_bitwise(lib, storage):
+    b = _b()
+    op, C = _c1(4)
+    dop = b.device_op(op)
+    a = b.lyap_solve(dop, _dev_C(C), storage=storage)
+    c = b.lyap_solve(dop, _dev_C(C), storage=storage)
+    assert a.hist_res == c.hist_res and a.m == c.m
+    assert torch.equal(a.Z, c.Z)
+
+
+@pytest.mark.parametrize("s", [1, 4])
+def test_c1_fp32_storage_error_is_stated(lib, oracle_c1, s):
+    """FP32 basis/SpMM with FP64 reductions: the cheap residual meets tol; the
+    explicit residual and the distance to the FP64 oracle sit at the FP32
+    floor (a few 1e-8 and ~1e-7)."""
+    b = _b()
+    op, C = _c1(s)
+    sol = b.lyap_solve(b.device_op(op), _dev_C(C), tol=1e-8, storage=1)
+    assert sol.status == b.OK and sol.res <= 1e-8
+    Z = sol.Z.cpu().numpy()
+    expl = K.explicit_residual(op.to_scipy(), Z, C) / sol.beta ** 2
+    ferr = K.factor_error(Z, oracle_c1[s].Z)
+    print(f"fp32 s={s}: explicit residual {expl:.2e}, factor error vs oracle {ferr:.2e}")
+    assert expl < 3e-7
+    assert ferr < 2e-6
+
+
+def test_adaptive_schedule_matches(lib, oracle_c1):
+    b = _b()
+    op, C = _c1(1)
+    sol = b.lyap_solve(b.device_op(op), _dev_C(C), tol=1e-8, check_every=0)
+    assert sol.status == b.OK and sol.res <= 1e-8
+    assert sol.n_checks < oracle_c1[1].m
+    assert sol.m >= oracle_c1[1].m
+    Z = sol.Z.cpu().numpy()
+    assert K.explicit_residual(op.to_scipy(), Z, C) / sol.beta ** 2 <= 1.2e-8
+
+
+def test_variable_coefficient_3d_matches_oracle(lib):
+    b = _b()
+    op = fv3d(12, 1.0, 3)
+    C = gaussian_C(op.n, 2, 3)
+    orc = K.lyap_std(op.to_scipy(), C, tol=1e-8, check_every=5)
+    sol = b.lyap_solve(b.device_op(op), _dev_C(C), tol=1e-8, check_every=5)
+    assert sol.status == b.OK and sol.m == orc.m
+    assert K.factor_error(sol.Z.cpu().numpy(), orc.Z) < 1e-7
+
+
+def test_csr_matches_stencil(lib):
+    b = _b()
+    op = fv3d(10, 0.5, 4)
+    C = gaussian_C(op.n, 1, 4)
+    z1 = b.lyap_solve(b.device_op(op), _dev_C(C), check_every=2)
+    z2 = b.lyap_solve(b.device_op(op, as_csr=True), _dev_C(C), check_every=2)
+    assert z1.m == z2.m
+    assert K.factor_error(z1.Z.cpu().numpy(), z2.Z.cpu().numpy()) < 1e-10
+
+
+# ------------------------------------------------------------------ failure handling
+def test_rank_deficient_C_is_breakdown(lib):
+    b = _b()
+    op = laplace2d(16)
+    C = gaussian_C(op.n, 2, 1)
+    C[:, 1] = C[:, 0]
+    sol = b.lyap_solve(b.device_op(op), _dev_C(C), raise_on_error=False)
+    assert sol.status == b.E_BREAKDOWN
+
+
+def test_positive_definite_operator_is_rejected(lib):
+    b = _b()
+    op = laplace2d(16)
+    op.cc, op.co = -op.cc, -op.co          # now symmetric positive definite
+    C = gaussian_C(op.n, 1, 1)
+    sol = b.lyap_solve(b.device_op(op), _dev_C(C), raise_on_error=False)
+    assert sol.status == b.E_INDEFINITE
+
+
+def test_nan_in_C_is_numeric_error(lib):
+    b = _b()
+    op = laplace2d(16)
+    C = gaussian_C(op.n, 1, 1)
+    C[5, 0] = np.nan
+    sol = b.lyap_solve(b.device_op(op), _dev_C(C), raise_on_error=False)
+    assert sol.status == b.E_NUMERIC
+
+
+def test_max_iter_gives_not_converged_with_partial_Z(lib):
+    b = _b()
+    op, C = _c1(1)
+    sol = b.lyap_solve(b.device_op(op), _dev_C(C), max_iter=20, check_every=5)
+    assert sol.status == b.NOT_CONVERGED and sol.m == 20 and sol.res > 1e-8
+    assert sol.Z is not None and sol.Z.shape[0] == op.n
