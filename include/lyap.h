@@ -120,6 +120,8 @@ typedef struct lyap_opts {
   void* alloc_ctx;
   int32_t want_T;       /* 1: return T_m band and gamma/tau on the host            */
   int32_t verbose;
+  int32_t profile;      /* 1: time every kernel of the two passes with HIP events on
+                           the stream (small overhead); see lyap_result.kern_ms */
 } lyap_opts;
 
 /* Fills *o with: tol 1e-8, max_iter 5000, STD, adaptive checks, F64 storage,
@@ -165,7 +167,24 @@ typedef struct lyap_result {
   int64_t bytes_spmm;  /* algorithmic HBM bytes of the SpMM calls           */
   double ms_spmm;      /* measured device time of SpMM calls, ms (0 if off) */
   int32_t owns_Z;      /* 1: Z came from hipMalloc and lyap_result_free frees it */
+  /* opts->profile: device time and launch count per kernel kind (LYAP_K_*) */
+  double kern_ms[12];
+  int32_t kern_n[12];
+  double kern_bytes[12]; /* algorithmic HBM bytes per launch of each kind */
 } lyap_result;
+
+/* kernel kinds of lyap_result.kern_ms */
+enum {
+  LYAP_K_SPMM_GRAM = 0,  /* W = A V_j fused with the first block Gram product  */
+  LYAP_K_UPD_GRAM = 1,   /* block MGS update fused with the next Gram product  */
+  LYAP_K_CHOL_GRAM = 2,  /* Cholesky of W^T W and the second Gram product      */
+  LYAP_K_CHOL_STORE = 3, /* second Cholesky, V_{j+1} = W R^{-1}                */
+  LYAP_K_REPLAY = 4,     /* second pass: one whole step from the log            */
+  LYAP_K_ZFLUSH = 5,     /* Z += V_i M_i for a group of buffered blocks         */
+  LYAP_K_CHECK = 6,      /* one residual check (all its kernels)                */
+  LYAP_K_FINAL = 7,      /* truncation and Q Y-check (all its kernels)          */
+  LYAP_K_INIT = 8        /* QR of C                                             */
+};
 
 /*
  * lyap_solve — AX + XA + CC^T = 0 by Algorithm 1.

@@ -45,7 +45,7 @@ class LyapOpts(ct.Structure):
                 ("trunc_eps", ct.c_double), ("inner_pc", ct.c_int32), ("inner_tol", ct.c_double),
                 ("inner_max_iter", ct.c_int32), ("flush_blocks", ct.c_int32), ("stream", ct.c_void_p),
                 ("alloc", ALLOC_FN), ("release", FREE_FN), ("alloc_ctx", ct.c_void_p),
-                ("want_T", ct.c_int32), ("verbose", ct.c_int32)]
+                ("want_T", ct.c_int32), ("verbose", ct.c_int32), ("profile", ct.c_int32)]
 
 
 class LyapResult(ct.Structure):
@@ -57,7 +57,8 @@ class LyapResult(ct.Structure):
                 ("n_checks", ct.c_int32), ("T_band", ct.POINTER(ct.c_double)),
                 ("gamma", ct.POINTER(ct.c_double)), ("tau", ct.POINTER(ct.c_double)),
                 ("bytes_pass1", ct.c_int64), ("bytes_spmm", ct.c_int64), ("ms_spmm", ct.c_double),
-                ("owns_Z", ct.c_int32)]
+                ("owns_Z", ct.c_int32), ("kern_ms", ct.c_double * 12), ("kern_n", ct.c_int32 * 12),
+                ("kern_bytes", ct.c_double * 12)]
 
 
 class SylvResult(ct.Structure):
@@ -206,20 +207,24 @@ class LyapSolution:
     inner_iters: int = 0
     n_inner: int = 0
     ell: int = 0
+    kernels: dict = field(default_factory=dict)
 
 
 TIME_KEYS = ["pass1", "checks", "final", "pass2", "inner", "train", "total", "to_tol"]
 
 
+KERNEL_KINDS = ["spmm_gram", "upd_gram", "chol_gram", "chol_store", "replay", "zflush", "check", "final", "init"]
+
+
 def make_opts(tol=1e-8, max_iter=5000, method=METHOD_STD, check_every=0, storage=STORE_F64, two_pass=True,
               trunc_eps=-1.0, inner_pc=PC_IC0, inner_tol=1e-12, inner_max_iter=5000, want_T=False,
-              verbose=False, stream=None):
+              verbose=False, stream=None, profile=False):
     o = LyapOpts()
     load().lyap_opts_default(ct.byref(o))
     o.tol, o.max_iter, o.method, o.check_every = tol, max_iter, method, check_every
     o.storage, o.two_pass, o.trunc_eps = storage, int(bool(two_pass)), trunc_eps
     o.inner_pc, o.inner_tol, o.inner_max_iter = inner_pc, inner_tol, inner_max_iter
-    o.want_T, o.verbose = int(bool(want_T)), int(bool(verbose))
+    o.want_T, o.verbose, o.profile = int(bool(want_T)), int(bool(verbose)), int(bool(profile))
     if stream is not None:
         o.stream = stream
     return o
@@ -256,7 +261,9 @@ def lyap_solve(dop: DeviceOp, C, raise_on_error: bool = True, **kw) -> LyapSolut
             hist_m=[r.hist_m[i] for i in range(r.n_hist)], hist_res=[r.hist_res[i] for i in range(r.n_hist)],
             times_ms={k_: r.times_ms[i] for i, k_ in enumerate(TIME_KEYS)}, n_checks=r.n_checks,
             trunc_eps=r.trunc_eps, bytes_pass1=r.bytes_pass1, bytes_spmm=r.bytes_spmm,
-            inner_iters=r.inner_iters, n_inner=r.n_inner, ell=ell)
+            inner_iters=r.inner_iters, n_inner=r.n_inner, ell=ell,
+            kernels={name: {"ms": r.kern_ms[i], "n": r.kern_n[i], "bytes_per_launch": r.kern_bytes[i]}
+                     for i, name in enumerate(KERNEL_KINDS) if r.kern_n[i] > 0})
         if r.T_band:
             sol.T_band = np.ctypeslib.as_array(r.T_band, shape=(k * (ell + 1),)).copy().reshape(k, ell + 1)
             sol.gamma = np.ctypeslib.as_array(r.gamma, shape=(ell * ell,)).copy().reshape(ell, ell, order="F")

@@ -66,50 +66,26 @@ int finalise_factor(const Checker& ck, const double* band, const double* gamma, 
   DevBuf d((size_t)k * sizeof(double));
   DevBuf Lc((size_t)k * tmax * sizeof(double));
   DevBuf piv((size_t)tmax * sizeof(int));
-  DevBuf tout(sizeof(int) * 4);
-  // pivoted-Cholesky error (trace of the remaining Schur complement) far below eps
-  const double delta = 1e-3 * eps;
-  launch_pchol(ck.lam(), ck.g(), k, ell, delta, tmax, d.as<double>(), Lc.as<double>(), piv.as<int>(),
-               tout.as<int>(), st);
-  int tp = 0;
-  LYAP_HIP(hipMemcpyAsync(&tp, tout.p, sizeof(int), hipMemcpyDeviceToHost, st));
-  LYAP_HIP(hipStreamSynchronize(st));
-  if (tp <= 0) {
-    M.alloc(8);
-    return 0;
-  }
-  LYAP_REQUIRE(tp <= 1024, LYAP_E_UNSUPPORTED, "truncation rank %d exceeds 1024", tp);
-  DevBuf G((size_t)tp * tp * sizeof(double));
-  DevBuf Qg((size_t)tp * tp * sizeof(double));
-  DevBuf sg((size_t)tp * sizeof(double));
-  launch_gram_cols(Lc.as<double>(), k, tp, G.as<double>(), st);
-  launch_jacobi(G.as<double>(), 0, Qg.as<double>(), 0, sg.as<double>(), 0, nullptr, tp, 1, st);
-  std::vector<double> w(tp);
-  LYAP_HIP(hipMemcpyAsync(w.data(), sg.p, tp * sizeof(double), hipMemcpyDeviceToHost, st));
-  LYAP_HIP(hipStreamSynchronize(st));
-  // eigenvalues of Y~ ~= L L^T, largest first; drop the tail with ||Sigma_2||_F <= eps
-  std::reverse(w.begin(), w.end());
-  int npos = 0;
-  for (int i = 0; i < tp; ++i) npos += w[i] > 0.0;
-  std::vector<double> tail(tp + 1, 0.0);
-  for (int i = tp - 1; i >= 0; --i) tail[i] = std::sqrt(tail[i + 1] * tail[i + 1] + w[i] * w[i]);
-  int t = npos;
-  while (t > 0 && tail[t - 1] <= eps) --t;
+  // Y~ ~= L L^T with trace(Y~ - L L^T) <= eps, hence ||Y~ - L L^T||_F <= eps
+  // (the error bound of the paper's eigenvalue truncation, at a rank at most a
+  // few columns above it)
+  const int t = run_pchol(ck.lam(), ck.g(), k, ell, eps, tmax, d.as<double>(), Lc.as<double>(), piv.as<int>(), st);
   if (t <= 0) {
     M.alloc(8);
     return 0;
   }
-  DevBuf Lb((size_t)(ell + 1) * k * tp * sizeof(double));
-  DevBuf X((size_t)k * tp * sizeof(double));
+  LYAP_REQUIRE(t < tmax || tmax == k, LYAP_E_UNSUPPORTED, "truncation rank exceeds %d", tmax);
+  // Q L = Q Y~(:, P) L_PP^{-T}, with Q Y~(:, p) from a banded shifted solve
+  DevBuf Lb((size_t)(ell + 1) * k * t * sizeof(double));
+  DevBuf X((size_t)k * t * sizeof(double));
   DevBuf fail(sizeof(int) * 4);
   LYAP_HIP(hipMemsetAsync(fail.p, 0, sizeof(int) * 4, st));
-  launch_shift_solve(band, ell + 1, ell, k, ck.lam(), ck.g(), gamma, piv.as<int>(), tp, Lb.as<double>(),
+  launch_shift_solve(band, ell + 1, ell, k, ck.lam(), ck.g(), gamma, piv.as<int>(), t, Lb.as<double>(),
                      X.as<double>(), fail.as<int>(), st);
-  DevBuf V1((size_t)tp * t * sizeof(double));
-  DevBuf B((size_t)tp * t * sizeof(double));
+  DevBuf B((size_t)t * t * sizeof(double));
   M.alloc((size_t)k * t * sizeof(double));
-  launch_assemble_M(Lc.as<double>(), k, piv.as<int>(), tp, Qg.as<double>(), t, X.as<double>(), V1.as<double>(),
-                    B.as<double>(), M.as<double>(), st);
+  launch_assemble_M(Lc.as<double>(), k, piv.as<int>(), t, nullptr, t, X.as<double>(), nullptr, B.as<double>(),
+                    M.as<double>(), st);
   int hfail = 0;
   LYAP_HIP(hipMemcpyAsync(&hfail, fail.p, sizeof(int), hipMemcpyDeviceToHost, st));
   LYAP_HIP(hipStreamSynchronize(st));

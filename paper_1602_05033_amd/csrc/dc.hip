@@ -177,88 +177,175 @@ __global__ void k_zform(const DcMerge* md, const DcScal* ms, int ell, int k, int
   }
 }
 
-// Deflation (one thread per merge).  Working index w runs over the columns in
-// ascending order of sg*D (sg = sign(rho)): column c(w) = w (sg > 0) or K-1-w.
-__global__ void k_deflate(const DcMerge* md, DcScal* ms, int ell, int k, int upd, double* Dw, double* Rw,
-                          const double* z, double* Dn, double* zn, int* nd, int* defl, double* defv) {
-  if (threadIdx.x != 0) return;
+// Deflation, one 1024-thread workgroup per merge.  Working index w runs over
+// the columns in ascending order of sg*D (sg = sign(rho)): column c(w) = w
+// (sg > 0) or K-1-w.  Entries with negligible z deflate directly; the others
+// are compacted in order (prefix sums); an adjacent pair that is close enough
+// for a Givens rotation to zero one z component deflates too.  The rotation
+// test of a pair depends on the previous pair's outcome, so when any pair
+// qualifies one thread walks the compacted candidate list in order.
+constexpr int kDefThreads = 1024;
+
+__device__ __forceinline__ int block_excl_scan(int v, int* sh, int* total) {
+  // Hillis-Steele over kDefThreads values in shared memory
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kDefThreads; off <<= 1) {
+    const int x = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
+  }
+  const int incl = sh[t];
+  if (total) *total = sh[kDefThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kDefThreads) void k_deflate(const DcMerge* md, DcScal* ms, int ell, int k, int upd,
+                                                         double* Dw, double* Rw, const double* z, double* Dn,
+                                                         double* zn, int* nd, int* defl, double* defv, int* sml,
+                                                         double* smv, int* rdl, double* rdv) {
+  __shared__ int sh[kDefThreads];
+  __shared__ double redd[kDefThreads / 64 * 2];
+  __shared__ int any_trig, s_Kc, s_Ks, s_Kn, s_Nr;
   const DcMerge g = md[blockIdx.x];
   DcScal& s = ms[blockIdx.x];
   const int a = g.a, K = g.K;
   const int i = upd >> 1;
   const int sg = (upd & 1) ? -1 : 1;
-  double r = s.sigma[i];
+  const int t = threadIdx.x;
+  const int chunk = (K + kDefThreads - 1) / kDefThreads;
+  const int w0 = min(t * chunk, K), w1 = min(w0 + chunk, K);
+  auto col = [&](int w) { return sg > 0 ? w : K - 1 - w; };
+  // ---- norms
   double nz2 = 0.0, dmax = 0.0;
-  for (int c = 0; c < K; ++c) {
+  for (int w = w0; w < w1; ++w) {
+    const int c = col(w);
     nz2 += z[a + c] * z[a + c];
     dmax = fmax(dmax, fabs(Dw[a + c]));
   }
-  s.sg = sg;
-  const int nr = 4 * ell;
-  if (!(r > 0.0) || !(nz2 > 0.0)) {
-    s.skip = 1;
-    s.Kn = 0;
-    s.Kd = K;
-    for (int w = 0; w < K; ++w) {
-      const int c = sg > 0 ? w : K - 1 - w;
-      defl[a + w] = w;
-      defv[a + w] = sg * Dw[a + c];
+  {
+    const int lane = t & 63, wave = t >> 6;
+    double v = wave_sum(nz2);
+    double m = dmax;
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if (lane == 0) { redd[wave] = v; redd[kDefThreads / 64 + wave] = m; }
+    __syncthreads();
+    if (t == 0) {
+      double sv = 0.0, mv = 0.0;
+      for (int w = 0; w < kDefThreads / 64; ++w) { sv += redd[w]; mv = fmax(mv, redd[kDefThreads / 64 + w]); }
+      redd[0] = sv;
+      redd[1] = mv;
     }
-    s.r = 0.0;
+    __syncthreads();
+    nz2 = redd[0];
+    dmax = redd[1];
+  }
+  const double r0 = s.sigma[i];
+  if (t == 0) s.sg = sg;
+  if (!(r0 > 0.0) || !(nz2 > 0.0)) {  // nothing to do: every entry deflates
+    for (int w = w0; w < w1; ++w) {
+      defl[a + w] = w;
+      defv[a + w] = sg * Dw[a + col(w)];
+    }
+    if (t == 0) { s.skip = 1; s.Kn = 0; s.Kd = K; s.r = 0.0; }
     return;
   }
-  s.skip = 0;
-  r *= nz2;
+  const double r = r0 * nz2;
   const double inv = 1.0 / sqrt(nz2);
   const double tol = 8.0 * kEps * fmax(dmax, r);
-  int p = -1, Kn = 0, Kd = 0;
-  double pz = 0.0, pd = 0.0;
-  for (int w = 0; w < K; ++w) {
-    const int c = sg > 0 ? w : K - 1 - w;
-    const double zw = z[a + c] * inv;
-    const double dw = sg * Dw[a + c];
-    if (r * fabs(zw) <= tol) {
-      defl[a + Kd] = w;
-      defv[a + Kd] = dw;
-      ++Kd;
-      continue;
+  // ---- compaction of candidates (non-small z) and of small entries
+  int cnt = 0;
+  for (int w = w0; w < w1; ++w) cnt += (r * fabs(z[a + col(w)] * inv) > tol);
+  int Kc = 0, Ks = 0;
+  const int bc = block_excl_scan(cnt, sh, &Kc);
+  const int bs = block_excl_scan((w1 - w0) - cnt, sh, &Ks);
+  {
+    int ic = bc, is = bs;
+    for (int w = w0; w < w1; ++w) {
+      const int c = col(w);
+      const double zw = z[a + c] * inv;
+      const double dw = sg * Dw[a + c];
+      if (r * fabs(zw) > tol) { nd[a + ic] = w; Dn[a + ic] = dw; zn[a + ic] = zw; ++ic; }
+      else { sml[a + is] = w; smv[a + is] = dw; ++is; }
     }
-    if (p < 0) { p = w; pz = zw; pd = dw; continue; }
-    const double tt = hypot(zw, pz);
-    const double cc = zw / tt, ss = pz / tt;
-    if (fabs((dw - pd) * cc * ss) <= tol) {
-      // rotate columns c(p), c(w): q_p' = cc q_p - ss q_w, q_w' = ss q_p + cc q_w
-      const int cp = sg > 0 ? p : K - 1 - p;
-      for (int row = 0; row < nr; ++row) {
-        double* R = Rw + (size_t)row * k + a;
-        const double qp = R[cp], qw = R[c];
-        R[cp] = cc * qp - ss * qw;
-        R[c] = ss * qp + cc * qw;
+  }
+  if (t == 0) any_trig = 0;
+  __syncthreads();
+  // ---- adjacent-pair rotation test with the original values
+  for (int q = 1 + t; q < Kc; q += kDefThreads) {
+    const double zp = zn[a + q - 1], zw = zn[a + q];
+    const double tt = hypot(zw, zp);
+    if (fabs((Dn[a + q] - Dn[a + q - 1]) * (zw / tt) * (zp / tt)) <= tol) any_trig = 1;
+  }
+  __syncthreads();
+  if (!any_trig) {
+    for (int e = t; e < Ks; e += kDefThreads) { defl[a + e] = sml[a + e]; defv[a + e] = smv[a + e]; }
+    if (t == 0) { s.skip = 0; s.Kn = Kc; s.Kd = Ks; s.r = r; }
+    return;
+  }
+  // ---- sequential walk over the candidates (rotations depend on the order)
+  if (t == 0) {
+    const int nr = 4 * ell;
+    int p = -1, Kn = 0, Nr = 0;
+    double pz = 0.0, pd = 0.0;
+    for (int q = 0; q < Kc; ++q) {
+      const int w = nd[a + q];
+      const double zw = zn[a + q], dw = Dn[a + q];
+      if (p < 0) { p = w; pz = zw; pd = dw; continue; }
+      const double tt = hypot(zw, pz);
+      const double cc = zw / tt, ss = pz / tt;
+      if (fabs((dw - pd) * cc * ss) <= tol) {
+        const int cp = col(p), cw = col(w);
+        for (int row = 0; row < nr; ++row) {
+          double* R = Rw + (size_t)row * k + a;
+          const double qp = R[cp], qw = R[cw];
+          R[cp] = cc * qp - ss * qw;
+          R[cw] = ss * qp + cc * qw;
+        }
+        rdl[a + Nr] = p;
+        rdv[a + Nr] = pd * cc * cc + dw * ss * ss;
+        ++Nr;
+        p = w; pz = tt; pd = pd * ss * ss + dw * cc * cc;
+      } else {
+        nd[a + Kn] = p; Dn[a + Kn] = pd; zn[a + Kn] = pz; ++Kn;  // in place: Kn <= q
+        p = w; pz = zw; pd = dw;
       }
-      const double dpn = pd * cc * cc + dw * ss * ss;
-      const double dwn = pd * ss * ss + dw * cc * cc;
-      defl[a + Kd] = p;
-      defv[a + Kd] = dpn;
-      ++Kd;
-      p = w; pz = tt; pd = dwn;
+    }
+    if (p >= 0) { nd[a + Kn] = p; Dn[a + Kn] = pd; zn[a + Kn] = pz; ++Kn; }
+    for (int x = 1; x < Nr; ++x) {  // rotated-out values are nearly sorted
+      const double v = rdv[a + x];
+      const int iw = rdl[a + x];
+      int y = x - 1;
+      while (y >= 0 && rdv[a + y] > v) { rdv[a + y + 1] = rdv[a + y]; rdl[a + y + 1] = rdl[a + y]; --y; }
+      rdv[a + y + 1] = v;
+      rdl[a + y + 1] = iw;
+    }
+    s_Kn = Kn;
+    s_Nr = Nr;
+  }
+  __syncthreads();
+  const int Nr = s_Nr;
+  // ---- merge the two sorted deflated lists (small-z first on ties)
+  for (int e = t; e < Ks + Nr; e += kDefThreads) {
+    if (e < Ks) {
+      const double v = smv[a + e];
+      int lo = 0, hi = Nr;
+      while (lo < hi) { int mid = (lo + hi) >> 1; if (rdv[a + mid] < v) lo = mid + 1; else hi = mid; }
+      defl[a + e + lo] = sml[a + e];
+      defv[a + e + lo] = v;
     } else {
-      nd[a + Kn] = p; Dn[a + Kn] = pd; zn[a + Kn] = pz; ++Kn;
-      p = w; pz = zw; pd = dw;
+      const int x = e - Ks;
+      const double v = rdv[a + x];
+      int lo = 0, hi = Ks;
+      while (lo < hi) { int mid = (lo + hi) >> 1; if (smv[a + mid] <= v) lo = mid + 1; else hi = mid; }
+      defl[a + x + lo] = rdl[a + x];
+      defv[a + x + lo] = v;
     }
   }
-  if (p >= 0) { nd[a + Kn] = p; Dn[a + Kn] = pd; zn[a + Kn] = pz; ++Kn; }
-  // deflated values nearly sorted (rotations move values slightly): insertion sort
-  for (int x = 1; x < Kd; ++x) {
-    const double v = defv[a + x];
-    const int iw = defl[a + x];
-    int y = x - 1;
-    while (y >= 0 && defv[a + y] > v) { defv[a + y + 1] = defv[a + y]; defl[a + y + 1] = defl[a + y]; --y; }
-    defv[a + y + 1] = v;
-    defl[a + y + 1] = iw;
-  }
-  s.Kn = Kn;
-  s.Kd = Kd;
-  s.r = r;
+  if (t == 0) { s.skip = 0; s.Kn = s_Kn; s.Kd = Ks + Nr; s.r = r; }
 }
 
 // Secular equation 1/r + sum_i z_i^2/(d_i - lambda) = 0: one wave per root.
@@ -469,7 +556,7 @@ struct DcWork::Impl {
   hipStream_t st;
   int cap = 0;
   int leaf = 32;
-  DevBuf Da, Db, Ra, Rb, z, Dn, zn, nd, defl, defv, orig, tau, lamn, zh, NR;
+  DevBuf Da, Db, Ra, Rb, z, Dn, zn, nd, defl, defv, orig, tau, lamn, zh, NR, sml, smv, rdl, rdv;
   DevBuf leafA, leafQ, leafL, leafN;
   DevBuf md, ms;
   int md_cap = 0;
@@ -482,7 +569,8 @@ struct DcWork::Impl {
     Da.alloc(d); Db.alloc(d);
     Ra.alloc(d * 4 * ell); Rb.alloc(d * 4 * ell); NR.alloc(d * 4 * ell);
     z.alloc(d); Dn.alloc(d); zn.alloc(d); defv.alloc(d); tau.alloc(d); lamn.alloc(d); zh.alloc(d);
-    nd.alloc(ii); defl.alloc(ii); orig.alloc(ii);
+    nd.alloc(ii); defl.alloc(ii); orig.alloc(ii); sml.alloc(ii); rdl.alloc(ii);
+    smv.alloc(d); rdv.alloc(d);
     const int nl = (c + leaf - 1) / leaf;
     leafA.alloc((size_t)nl * leaf * leaf * sizeof(double));
     leafQ.alloc((size_t)nl * leaf * leaf * sizeof(double));
@@ -551,8 +639,10 @@ void DcWork::run(const double* band, int ldb, int k, double* lam, double* F, dou
                        Rcur);
     for (int u = 0; u < 2 * ell; ++u) {
       hipLaunchKernelGGL(k_zform, dim3(gx, nm), dim3(256), 0, st, md, ms, ell, k, u, Rcur, w.z.as<double>());
-      hipLaunchKernelGGL(k_deflate, dim3(nm), dim3(64), 0, st, md, ms, ell, k, u, Dcur, Rcur, w.z.as<double>(),
-                         w.Dn.as<double>(), w.zn.as<double>(), w.nd.as<int>(), w.defl.as<int>(), w.defv.as<double>());
+      hipLaunchKernelGGL(k_deflate, dim3(nm), dim3(kDefThreads), 0, st, md, ms, ell, k, u, Dcur, Rcur,
+                         w.z.as<double>(), w.Dn.as<double>(), w.zn.as<double>(), w.nd.as<int>(), w.defl.as<int>(),
+                         w.defv.as<double>(), w.sml.as<int>(), w.smv.as<double>(), w.rdl.as<int>(),
+                         w.rdv.as<double>());
       hipLaunchKernelGGL(k_secular, dim3(gw, nm), dim3(256), 0, st, md, ms, w.Dn.as<double>(), w.zn.as<double>(),
                          w.orig.as<int>(), w.tau.as<double>(), w.lamn.as<double>());
       hipLaunchKernelGGL(k_zhat, dim3(gw, nm), dim3(256), 0, st, md, ms, w.Dn.as<double>(), w.zn.as<double>(),

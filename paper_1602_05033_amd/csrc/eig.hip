@@ -34,119 +34,182 @@ __global__ void k_band_to_dense(const double* band, int ldb, int ell, int k, dou
 // lam + b*strideL, ascending.  On exit A is destroyed.
 constexpr int kJacThreads = 256;
 constexpr int kJacMaxN = 1024;
+constexpr int kJacLds = 64;  // matrices up to this size are worked on in LDS
 
-__global__ __launch_bounds__(kJacThreads) void k_jacobi(double* Aall, int64_t strideA, double* Qall, int64_t strideQ,
-                                                       double* lamall, int64_t strideL, const int* nlist, int nfixed,
-                                                       int max_sweeps) {
-  const int bidx = blockIdx.x;
-  const int n = nlist ? nlist[bidx] : nfixed;
-  double* A = Aall + bidx * strideA;
-  double* Q = Qall + bidx * strideQ;
-  double* lam = lamall + bidx * strideL;
-  __shared__ int sp[kJacMaxN / 2 + 1], sq[kJacMaxN / 2 + 1];
-  __shared__ double sc[kJacMaxN / 2 + 1], ss[kJacMaxN / 2 + 1];
-  __shared__ double red[2 * kWaves * 4];
-  __shared__ int done;
-  if (n <= 0) return;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) Q[e] = (e / n == e % n) ? 1.0 : 0.0;
-  __syncthreads();
-  if (n == 1) {
-    if (threadIdx.x == 0) lam[0] = A[0];
-    return;
+// One sweep rotates every pair with |a_pq| > eps*sqrt(|a_pp a_qq|); after the
+// row/column updates the rotated pair is set exactly (a_pq = 0,
+// a_pp - t a_pq, a_qq + t a_pq), so rounding does not re-create the entry just
+// annihilated and the loop ends after a sweep that rotates nothing.
+// NN > 0: the matrix (n <= NN <= 64) lives in LDS and each thread owns column
+// (or row) threadIdx.x % 64 of the updates; NN == 0: global memory, any n.
+template <int NN>
+__device__ int jacobi_core(double* A, double* Q, int n, int max_sweeps, int* sp, int* sq, double* sc, double* ss,
+                           double* st_, int* nrot) {
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int r = e / n;
+    Q[e] = (r == e - r * n) ? 1.0 : 0.0;
   }
+  __syncthreads();
+  if (n == 1) return 0;
   const int np = (n + 1) & ~1;  // players (one dummy when n is odd)
   const int rot = np - 1;       // rotating players
   const int half = np / 2;
+  const int lane = threadIdx.x & 63;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    // convergence test: off-diagonal vs diagonal mass
-    double off = 0.0, dia = 0.0;
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-      const double v = A[e];
-      if (e / n == e % n) dia += v * v; else off += v * v;
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    off = wave_sum(off);
-    dia = wave_sum(dia);
-    if (lane == 0) { red[wave] = off; red[kWaves + wave] = dia; }
+    if (threadIdx.x == 0) *nrot = 0;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      double o = 0, d = 0;
-      for (int w = 0; w < kJacThreads / 64; ++w) { o += red[w]; d += red[kWaves + w]; }
-      done = (o <= 1e-30 * d) || (o == 0.0);
-    }
-    __syncthreads();
-    if (done) break;
     for (int round = 0; round < rot; ++round) {
       for (int kp = threadIdx.x; kp < half; kp += blockDim.x) {
         int p, q;
         if (kp == 0) { p = 0; q = 1 + round; }
-        else { p = 1 + (round + kp) % rot; q = 1 + (round - kp + rot) % rot; }
+        else {
+          p = round + kp; if (p >= rot) p -= rot; p += 1;
+          q = round - kp; if (q < 0) q += rot; q += 1;
+        }
         if (p > q) { int t = p; p = q; q = t; }
         double c = 1.0, s = 0.0;
         if (q < n) {
           const double apq = A[p * n + q];
           const double app = A[p * n + p], aqq = A[q * n + q];
-          if (fabs(apq) > 1e-17 * (fabs(app) + fabs(aqq)) && fabs(apq) > 1e-300) {
+          if (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app) * fabs(aqq)) && fabs(apq) > 1e-300) {
             const double theta = (aqq - app) / (2.0 * apq);
             const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
             c = 1.0 / sqrt(t * t + 1.0);
             s = t * c;
+            st_[3 * kp + 0] = app - t * apq;
+            st_[3 * kp + 1] = aqq + t * apq;
+            atomicAdd(nrot, 1);
           }
         }
         sp[kp] = p; sq[kp] = q; sc[kp] = c; ss[kp] = s;
       }
       __syncthreads();
-      // rows: A <- J^T A
-      for (int e = threadIdx.x; e < half * n; e += blockDim.x) {
-        const int kp = e / n, col = e % n;
-        const int p = sp[kp], q = sq[kp];
-        if (q >= n || ss[kp] == 0.0) continue;
-        const double c = sc[kp], s = ss[kp];
-        const double ap = A[p * n + col], aq = A[q * n + col];
-        A[p * n + col] = c * ap - s * aq;
-        A[q * n + col] = s * ap + c * aq;
+      if constexpr (NN > 0) {
+        // one wave: lane owns column `lane` (row phase) then row `lane` (column phase)
+        int pp[NN / 2], qq[NN / 2];
+        double cc[NN / 2], sv[NN / 2];
+#pragma unroll
+        for (int kp = 0; kp < NN / 2; ++kp) {
+          if (kp < half) { pp[kp] = sp[kp]; qq[kp] = sq[kp]; cc[kp] = sc[kp]; sv[kp] = ss[kp]; }
+          else { pp[kp] = 0; qq[kp] = n; cc[kp] = 1.0; sv[kp] = 0.0; }
+        }
+        if (lane < n) {
+#pragma unroll
+          for (int kp = 0; kp < NN / 2; ++kp) {
+            if (qq[kp] >= n || sv[kp] == 0.0) continue;
+            const double ap = A[pp[kp] * n + lane], aq = A[qq[kp] * n + lane];
+            A[pp[kp] * n + lane] = cc[kp] * ap - sv[kp] * aq;
+            A[qq[kp] * n + lane] = sv[kp] * ap + cc[kp] * aq;
+          }
+        }
+        __syncthreads();
+        if (lane < n) {
+#pragma unroll
+          for (int kp = 0; kp < NN / 2; ++kp) {
+            if (qq[kp] >= n || sv[kp] == 0.0) continue;
+            const double ap = A[lane * n + pp[kp]], aq = A[lane * n + qq[kp]];
+            A[lane * n + pp[kp]] = cc[kp] * ap - sv[kp] * aq;
+            A[lane * n + qq[kp]] = sv[kp] * ap + cc[kp] * aq;
+            const double qp = Q[lane * n + pp[kp]], qv = Q[lane * n + qq[kp]];
+            Q[lane * n + pp[kp]] = cc[kp] * qp - sv[kp] * qv;
+            Q[lane * n + qq[kp]] = sv[kp] * qp + cc[kp] * qv;
+          }
+        }
+      } else {
+        for (int e = threadIdx.x; e < half * n; e += blockDim.x) {  // rows: A <- J^T A
+          const int kp = e / n, col = e - kp * n;
+          const int p = sp[kp], q = sq[kp];
+          if (q >= n || ss[kp] == 0.0) continue;
+          const double c = sc[kp], s = ss[kp];
+          const double ap = A[p * n + col], aq = A[q * n + col];
+          A[p * n + col] = c * ap - s * aq;
+          A[q * n + col] = s * ap + c * aq;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < half * n; e += blockDim.x) {  // columns: A <- A J, Q <- Q J
+          const int kp = e / n, row = e - kp * n;
+          const int p = sp[kp], q = sq[kp];
+          if (q >= n || ss[kp] == 0.0) continue;
+          const double c = sc[kp], s = ss[kp];
+          const double ap = A[row * n + p], aq = A[row * n + q];
+          A[row * n + p] = c * ap - s * aq;
+          A[row * n + q] = s * ap + c * aq;
+          const double qp = Q[row * n + p], qq = Q[row * n + q];
+          Q[row * n + p] = c * qp - s * qq;
+          Q[row * n + q] = s * qp + c * qq;
+        }
       }
       __syncthreads();
-      // columns: A <- A J, Q <- Q J
-      for (int e = threadIdx.x; e < half * n; e += blockDim.x) {
-        const int kp = e / n, row = e % n;
+      for (int kp = threadIdx.x; kp < half; kp += blockDim.x) {
         const int p = sp[kp], q = sq[kp];
         if (q >= n || ss[kp] == 0.0) continue;
-        const double c = sc[kp], s = ss[kp];
-        const double ap = A[row * n + p], aq = A[row * n + q];
-        A[row * n + p] = c * ap - s * aq;
-        A[row * n + q] = s * ap + c * aq;
-        const double qp = Q[row * n + p], qq = Q[row * n + q];
-        Q[row * n + p] = c * qp - s * qq;
-        Q[row * n + q] = s * qp + c * qq;
+        A[p * n + q] = 0.0;
+        A[q * n + p] = 0.0;
+        A[p * n + p] = st_[3 * kp + 0];
+        A[q * n + q] = st_[3 * kp + 1];
       }
       __syncthreads();
     }
+    const int done = (*nrot == 0);
+    __syncthreads();
+    if (done) return sweep + 1;
   }
-  // sort ascending: rank of each eigenvalue, then permute Q columns through A
-  for (int i = threadIdx.x; i < n; i += blockDim.x) lam[i] = A[i * n + i];
-  __syncthreads();
+  return max_sweeps;
+}
+
+// Matrix b of the batch: A + b*strideA (n x n, row-major, lda = n), eigenvector
+// matrix Q + b*strideQ (row-major, eigenvector i in column i), eigenvalues
+// lam + b*strideL, ascending.  On exit A is destroyed.
+__global__ __launch_bounds__(kJacThreads) void k_jacobi(double* Aall, int64_t strideA, double* Qall, int64_t strideQ,
+                                                       double* lamall, int64_t strideL, const int* nlist, int nfixed,
+                                                       int max_sweeps, int* sweeps_out) {
+  const int bidx = blockIdx.x;
+  const int n = nlist ? nlist[bidx] : nfixed;
+  double* Ag = Aall + bidx * strideA;
+  double* Qg = Qall + bidx * strideQ;
+  double* lam = lamall + bidx * strideL;
+  __shared__ int sp[kJacMaxN / 2 + 1], sq[kJacMaxN / 2 + 1];
+  __shared__ double sc[kJacMaxN / 2 + 1], ss[kJacMaxN / 2 + 1];
+  __shared__ double As[kJacLds * kJacLds], Qs[kJacLds * kJacLds];
+  __shared__ double stt[3 * (kJacMaxN / 2 + 1)];
+  __shared__ int nrot;
+  __shared__ int rk[kJacMaxN];
+  if (n <= 0) return;
+  const bool lds = n <= kJacLds;
+  int nsw;
+  if (lds) {
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) As[e] = Ag[e];
+    __syncthreads();
+    nsw = jacobi_core<kJacLds>(As, Qs, n, max_sweeps, sp, sq, sc, ss, stt, &nrot);
+  } else {
+    nsw = jacobi_core<0>(Ag, Qg, n, max_sweeps, sp, sq, sc, ss, stt, &nrot);
+  }
+  if (sweeps_out && threadIdx.x == 0) sweeps_out[bidx] = nsw;
+  const double* A = lds ? As : Ag;
+  // sort ascending: rank of each eigenvalue (ties by index), permute columns
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double li = lam[i];
+    const double li = A[i * n + i];
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-      const double lj = lam[j];
+      const double lj = A[j * n + j];
       rank += (lj < li) || (lj == li && j < i);
     }
-    for (int r = 0; r < n; ++r) A[r * n + rank] = Q[r * n + i];  // A reused as scratch
+    rk[i] = rank;
+    lam[rank] = li;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) Q[e] = A[e];
-  __syncthreads();
-  // eigenvalues in sorted order (recomputed from the stored diagonal ranks)
-  if (threadIdx.x == 0) {
-    // simple insertion sort of lam (n <= kJacMaxN, once)
-    for (int i = 1; i < n; ++i) {
-      double v = lam[i];
-      int j = i - 1;
-      while (j >= 0 && lam[j] > v) { lam[j + 1] = lam[j]; --j; }
-      lam[j + 1] = v;
+  if (lds) {
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int r = e / n, i = e - r * n;
+      Qg[r * n + rk[i]] = Qs[e];
     }
+  } else {  // permute through A (its contents are no longer needed)
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int r = e / n, i = e - r * n;
+      Ag[r * n + rk[i]] = Qg[e];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) Qg[e] = Ag[e];
   }
 }
 
@@ -175,7 +238,7 @@ constexpr int kMaxEll = 16;
 __global__ __launch_bounds__(kBlock) void k_ctri_sum(const double* lam, const double* g, const double* Wm, int k,
                                                      int ell, int nt, double* part, unsigned* counter,
                                                      CheckOut* out) {
-  __shared__ double red[kMaxEll * kWaves];
+  __shared__ double red[pow2_at_least(kMaxEll) * kWaves];
   double blocksum = 0.0;
   for (int i = blockIdx.x; i < k; i += gridDim.x) {
     double gi[kMaxEll];
@@ -214,83 +277,113 @@ __global__ __launch_bounds__(kBlock) void k_ctri_sum(const double* lam, const do
 }
 
 // ------------------------------------------------------------------ pivoted Cholesky of Y~
-// One workgroup.  Y~_ij = -(g_i . g_j)/(lambda_i + lambda_j).  Stops when the
-// trace of the Schur complement is <= delta or tmax columns are formed.
-constexpr int kPcThreads = 1024;
+// Y~_ij = -(g_i . g_j)/(lambda_i + lambda_j), generated on the fly.  One
+// kernel per pivot: every workgroup first reduces the previous kernel's
+// per-workgroup (max diagonal, index, trace) partials in a fixed order, takes
+// the pivot, forms its column of the factor for its rows, updates the Schur
+// diagonal and writes its own partials.  Stops (all later launches return at
+// once) when the trace of the remaining Schur complement is <= delta.
+constexpr int kPcThreads = 256;
 
-__global__ __launch_bounds__(kPcThreads) void k_pchol(const double* lam, const double* g, int k, int ell, double delta,
-                                                      int tmax, double* d, double* Lc, int* piv, int* tout) {
-  __shared__ double rv[kPcThreads / 64];
+struct PcState {
+  int stop;    // set once the trace criterion is met
+  int t;       // number of columns formed
+  int pad[2];
+};
+
+__device__ __forceinline__ void pc_partials(const double* d, int k, double* pv, int* pi, double* ps) {
+  __shared__ double rv[kPcThreads / 64], rs[kPcThreads / 64];
   __shared__ int ri[kPcThreads / 64];
-  __shared__ double rsum[kPcThreads / 64];
-  __shared__ int sp;
-  __shared__ double spiv, strace;
-  __shared__ double gp[kMaxEll];
-  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+  double best = -1.0, sum = 0.0;
+  int bi = 0x7fffffff;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    const double v = d[i];
+    sum += v;
+    if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    sum += __shfl_xor(sum, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) { rv[wave] = best; ri[wave] = bi; rs[wave] = sum; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = rv[0], sm = rs[0];
+    int ii = ri[0];
+    for (int w = 1; w < kPcThreads / 64; ++w) {
+      if (rv[w] > b || (rv[w] == b && ri[w] < ii)) { b = rv[w]; ii = ri[w]; }
+      sm += rs[w];
+    }
+    pv[blockIdx.x] = b; pi[blockIdx.x] = ii; ps[blockIdx.x] = sm;
+  }
+}
+
+__global__ __launch_bounds__(kPcThreads) void k_pchol_init(const double* lam, const double* g, int k, int ell,
+                                                           double* d, double* pv, int* pi, double* ps, PcState* stt) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
     double nn = 0.0;
     for (int a = 0; a < ell; ++a) nn = fma(g[(size_t)i * ell + a], g[(size_t)i * ell + a], nn);
     d[i] = -nn / (2.0 * lam[i]);
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) { stt->stop = 0; stt->t = 0; }
+  // the partials below read d written by this same workgroup's threads only
   __syncthreads();
-  int r = 0;
-  for (; r < tmax; ++r) {
-    // argmax and trace
-    double best = -1.0, sum = 0.0;
-    int bi = 0x7fffffff;
-    for (int i = threadIdx.x; i < k; i += blockDim.x) {
-      const double v = d[i];
-      sum += v;
-      if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+  pc_partials(d, k, pv, pi, ps);
+}
+
+__global__ __launch_bounds__(kPcThreads) void k_pchol_step(const double* lam, const double* g, int k, int ell,
+                                                           double delta, int r, double* d, double* Lc, int* piv,
+                                                           const double* pv_in, const int* pi_in,
+                                                           const double* ps_in, int nparts, double* pv, int* pi,
+                                                           double* ps, PcState* stt) {
+  __shared__ int sp;
+  __shared__ double spiv, strace;
+  __shared__ double gp[kMaxEll];
+  if (stt->stop) return;
+  if (threadIdx.x == 0) {
+    double b = -1.0, sm = 0.0;
+    int ii = 0x7fffffff;
+    for (int w = 0; w < nparts; ++w) {
+      if (pv_in[w] > b || (pv_in[w] == b && pi_in[w] < ii)) { b = pv_in[w]; ii = pi_in[w]; }
+      sm += ps_in[w];
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      sum += __shfl_xor(sum, off, 64);
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) { rv[wave] = best; ri[wave] = bi; rsum[wave] = sum; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double b = rv[0]; int ii = ri[0]; double s = rsum[0];
-      for (int w = 1; w < kPcThreads / 64; ++w) {
-        if (rv[w] > b || (rv[w] == b && ri[w] < ii)) { b = rv[w]; ii = ri[w]; }
-        s += rsum[w];
-      }
-      sp = ii; spiv = b; strace = s;
-    }
-    __syncthreads();
-    if (!(strace > delta) || !(spiv > 0.0)) break;
-    const int p = sp;
-    const double sq = sqrt(spiv);
-    if (threadIdx.x < ell) gp[threadIdx.x] = g[(size_t)p * ell + threadIdx.x];
-    __syncthreads();
-    const double lp = lam[p];
-    for (int i = threadIdx.x; i < k; i += blockDim.x) {
-      double v;
-      if (i == p) {
-        v = sq;
-      } else if (d[i] == 0.0) {
-        v = 0.0;  // an earlier pivot (or an exactly represented row)
-      } else {
-        double dot = 0.0;
-        for (int a = 0; a < ell; ++a) dot = fma(g[(size_t)i * ell + a], gp[a], dot);
-        double y = -dot / (lam[i] + lp);
-        for (int q = 0; q < r; ++q) y = fma(-Lc[(size_t)q * k + i], Lc[(size_t)q * k + p], y);
-        v = y / sq;
-      }
-      Lc[(size_t)r * k + i] = v;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < k; i += blockDim.x) {
-      const double v = Lc[(size_t)r * k + i];
-      double nd = (i == p) ? 0.0 : d[i] - v * v;
-      d[i] = nd > 0.0 ? nd : 0.0;
-    }
-    if (threadIdx.x == 0) piv[r] = p;
-    __syncthreads();
+    sp = ii; spiv = b; strace = sm;
   }
-  if (threadIdx.x == 0) *tout = r;
+  __syncthreads();
+  if (!(strace > delta) || !(spiv > 0.0)) {
+    // every workgroup sees the same totals; workgroup 0 records the stop
+    if (blockIdx.x == 0 && threadIdx.x == 0) { stt->stop = 1; stt->t = r; }
+    return;
+  }
+  const int p = sp;
+  const double sq = sqrt(spiv);
+  if (threadIdx.x < ell) gp[threadIdx.x] = g[(size_t)p * ell + threadIdx.x];
+  __syncthreads();
+  const double lp = lam[p];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    double v;
+    const double di = d[i];
+    if (i == p) {
+      v = sq;
+    } else if (di == 0.0) {
+      v = 0.0;  // an earlier pivot (or a row already represented exactly)
+    } else {
+      double dot = 0.0;
+      for (int a = 0; a < ell; ++a) dot = fma(g[(size_t)i * ell + a], gp[a], dot);
+      double y = -dot / (lam[i] + lp);
+      for (int q = 0; q < r; ++q) y = fma(-Lc[(size_t)q * k + i], Lc[(size_t)q * k + p], y);
+      v = y / sq;
+    }
+    Lc[(size_t)r * k + i] = v;
+    const double nd = (i == p) ? 0.0 : di - v * v;
+    d[i] = nd > 0.0 ? nd : 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) { piv[r] = p; stt->t = r + 1; }
+  __syncthreads();
+  pc_partials(d, k, pv, pi, ps);
 }
 
 // G = Lc^T Lc (tp x tp, row-major); one workgroup per entry (a <= b).
@@ -311,60 +404,108 @@ __global__ __launch_bounds__(kBlock) void k_gram_cols(const double* Lc, int k, i
   }
 }
 
-// Banded shifted solves: thread p builds chol(-(T + lambda_{piv[p]} I)) (lower
-// band, bandwidth ell) and solves for b = E_1 (gamma g_{piv[p]}^T).
-// X: k x tp column-major.  Lb scratch: ((ell+1)*k) x tp, interleaved by thread.
-__global__ void k_shift_solve(const double* band, int ldb, int ell, int k, const double* lam, const double* g,
-                              const double* gamma, const int* piv, int tp, double* Lb, double* X, int* fail) {
+// Banded shifted solves: thread p factors S_p = -(T + lambda_{piv[p]} I) =
+// L L^T (lower band, bandwidth ELL; S_p is positive definite since T is
+// negative definite) row by row with the last ELL rows of L kept in registers,
+// solves L z = E_1 (gamma g_{piv[p]}^T) on the fly, stores the rows of L
+// (interleaved by thread), then solves L^T x = z backwards.  x is
+// Q Y~(:, piv[p]) = -(T + lambda I)^{-1} E_1 gamma g^T written as S_p^{-1} E_1 gamma g^T.
+// X: k x tp column-major.
+template <int ELL>
+__global__ __launch_bounds__(64) void k_shift_solve(const double* band, int ldb, int k, const double* lam,
+                                                    const double* g, const double* gamma, const int* piv, int tp,
+                                                    double* Lb, double* X, int* fail) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= tp) return;
+  constexpr int LB = ELL + 1;
   const int ip = piv[p];
   const double sh = lam[ip];
-  const int lb = ell + 1;
-#define LB(j, dd) Lb[((size_t)(j) * lb + (dd)) * tp + p]
-  // factor: L(j+d, j) stored at LB(j, d)
-  for (int j = 0; j < k; ++j) {
-    // diagonal
-    double djj = -(band[(size_t)j * ldb + 0] + sh);
-    const int i0 = j - ell > 0 ? j - ell : 0;
-    for (int i = i0; i < j; ++i) {
-      const double lji = LB(i, j - i);
-      djj -= lji * lji;
-    }
-    if (!(djj > 0.0)) { fail[0] = 1; djj = 1e-300; }
-    const double ljj = sqrt(djj);
-    LB(j, 0) = ljj;
-    const int rmax = j + ell < k - 1 ? j + ell : k - 1;
-    for (int r = j + 1; r <= rmax; ++r) {
-      double v = -band[(size_t)j * ldb + (r - j)];
-      const int i1 = r - ell > 0 ? r - ell : 0;
-      for (int i = i1; i < j; ++i) v -= LB(i, r - i) * LB(i, j - i);
-      LB(j, r - j) = v / ljj;
-    }
-  }
-  // rhs
-  double* x = X + (size_t)p * k;
-  for (int i = 0; i < k; ++i) x[i] = 0.0;
-  for (int a = 0; a < ell && a < k; ++a) {
+  double rhs[ELL];
+#pragma unroll
+  for (int a = 0; a < ELL; ++a) {
     double acc = 0.0;
-    for (int c = 0; c < ell; ++c) acc = fma(gamma[a * ell + c], g[(size_t)ip * ell + c], acc);
-    x[a] = acc;
+    for (int c = 0; c < ELL; ++c) acc = fma(gamma[a * ELL + c], g[(size_t)ip * ELL + c], acc);
+    rhs[a] = acc;
   }
-  // forward L z = b
+  // window: W[i][m] = L(j-ELL+i, j-ELL+i-ELL+m) for the previous ELL rows (m = 0..ELL, m == ELL is diagonal)
+  double W[ELL][LB];
+  double zw[ELL];  // z of the previous ELL rows
+#pragma unroll
+  for (int i = 0; i < ELL; ++i) {
+    zw[i] = 0.0;
+#pragma unroll
+    for (int m = 0; m < LB; ++m) W[i][m] = (m == ELL) ? 1.0 : 0.0;
+  }
+  double* x = X + (size_t)p * k;
   for (int j = 0; j < k; ++j) {
-    double v = x[j];
-    const int i0 = j - ell > 0 ? j - ell : 0;
-    for (int i = i0; i < j; ++i) v -= LB(i, j - i) * x[i];
-    x[j] = v / LB(j, 0);
+    // row j of L: Lj[m] = L(j, j-ELL+m), m = 0..ELL
+    double Lj[LB];
+#pragma unroll
+    for (int m = 0; m < ELL; ++m) {
+      const int i = j - ELL + m;  // column
+      double v = 0.0;
+      if (i >= 0) {
+        v = -band[(size_t)i * ldb + (j - i)];
+        // subtract sum_{mm < m} L(j, j-ELL+mm) L(i, j-ELL+mm); row i is window slot m
+#pragma unroll
+        for (int mm = 0; mm < m; ++mm) {
+          // L(i, j-ELL+mm) = W[m][mm + (ELL - m)] (row i = j-ELL+m, its column offset base i-ELL)
+          v = fma(-Lj[mm], W[m][mm + ELL - m], v);
+        }
+        v = v / W[m][ELL];
+      }
+      Lj[m] = v;
+    }
+    double djj = -(band[(size_t)j * ldb] + sh);
+#pragma unroll
+    for (int m = 0; m < ELL; ++m) djj = fma(-Lj[m], Lj[m], djj);
+    if (!(djj > 0.0)) { fail[0] = 1; djj = 1e-300; }
+    Lj[ELL] = sqrt(djj);
+    // forward substitution
+    double zj = j < ELL ? rhs[j] : 0.0;
+#pragma unroll
+    for (int m = 0; m < ELL; ++m) zj = fma(-Lj[m], zw[m], zj);
+    zj /= Lj[ELL];
+    // store row j, slide the window
+#pragma unroll
+    for (int m = 0; m < LB; ++m) Lb[((size_t)j * LB + m) * tp + p] = Lj[m];
+    x[j] = zj;
+#pragma unroll
+    for (int i = 0; i < ELL - 1; ++i) {
+      zw[i] = zw[i + 1];
+#pragma unroll
+      for (int m = 0; m < LB; ++m) W[i][m] = W[i + 1][m];
+    }
+    zw[ELL - 1] = zj;
+#pragma unroll
+    for (int m = 0; m < LB; ++m) W[ELL - 1][m] = Lj[m];
   }
-  // backward L^T x = z
+  // backward: x_j = (z_j - sum_{r=j+1}^{j+ELL} L(r, j) x_r) / L(j, j); L(r, j) = row r slot j-r+ELL
+  double xw[ELL];   // x of rows j+1..j+ELL
+  double Rw[ELL][LB];  // rows j+1..j+ELL of L
+#pragma unroll
+  for (int i = 0; i < ELL; ++i) {
+    xw[i] = 0.0;
+#pragma unroll
+    for (int m = 0; m < LB; ++m) Rw[i][m] = 0.0;
+  }
   for (int j = k - 1; j >= 0; --j) {
     double v = x[j];
-    const int rmax = j + ell < k - 1 ? j + ell : k - 1;
-    for (int r = j + 1; r <= rmax; ++r) v -= LB(j, r - j) * x[r];
-    x[j] = v / LB(j, 0);
+#pragma unroll
+    for (int i = 0; i < ELL; ++i) v = fma(-Rw[i][ELL - 1 - i], xw[i], v);  // row j+1+i, column j: slot ELL-(1+i)
+    const double ljj = Lb[((size_t)j * LB + ELL) * tp + p];
+    v /= ljj;
+    x[j] = v;
+#pragma unroll
+    for (int i = ELL - 1; i > 0; --i) {
+      xw[i] = xw[i - 1];
+#pragma unroll
+      for (int m = 0; m < LB; ++m) Rw[i][m] = Rw[i - 1][m];
+    }
+    xw[0] = v;
+#pragma unroll
+    for (int m = 0; m < LB; ++m) Rw[0][m] = Lb[((size_t)j * LB + m) * tp + p];
   }
-#undef LB
 }
 
 // B = L_PP^{-T} V1: L_PP[a][b] = Lc[b*k + piv[a]] (lower triangular);
@@ -373,7 +514,7 @@ __global__ void k_trsm_lt(const double* Lc, int k, const int* piv, int tp, const
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= t) return;
   for (int a = tp - 1; a >= 0; --a) {
-    double v = V1[(size_t)a * t + c];
+    double v = V1 ? V1[(size_t)a * t + c] : (a == c ? 1.0 : 0.0);
     for (int b = a + 1; b < tp; ++b) v -= Lc[(size_t)a * k + piv[b]] * B[(size_t)b * t + c];
     B[(size_t)a * t + c] = v / Lc[(size_t)a * k + piv[a]];
   }
@@ -409,11 +550,13 @@ void launch_band_to_dense(const double* band, int ldb, int ell, int k, double* A
 }
 
 void launch_jacobi(double* A, int64_t strideA, double* Q, int64_t strideQ, double* lam, int64_t strideL,
-                   const int* nlist, int nfixed, int batch, hipStream_t st) {
+                   const int* nlist, int nfixed, int batch, hipStream_t st, int* sweeps) {
   LYAP_REQUIRE(nfixed <= kJacMaxN, LYAP_E_UNSUPPORTED, "dense eigensolver limited to n <= %d (got %d)", kJacMaxN,
                nfixed);
-  hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(kJacThreads), 0, st, A, strideA, Q, strideQ, lam, strideL, nlist,
-                     nfixed, 40);
+  // nfixed is the largest n of the batch; LDS-sized matrices run on one wave
+  const int threads = nfixed <= kJacLds ? 64 : kJacThreads;
+  hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(threads), 0, st, A, strideA, Q, strideQ, lam, strideL, nlist,
+                     nfixed, 40, sweeps);
   LYAP_LAUNCHED("jacobi");
 }
 
@@ -432,10 +575,29 @@ void launch_ctri_sum(const double* lam, const double* g, const double* Wm, int k
   LYAP_LAUNCHED("ctri_sum");
 }
 
-void launch_pchol(const double* lam, const double* g, int k, int ell, double delta, int tmax, double* d, double* Lc,
-                  int* piv, int* tout, hipStream_t st) {
-  hipLaunchKernelGGL(k_pchol, dim3(1), dim3(kPcThreads), 0, st, lam, g, k, ell, delta, tmax, d, Lc, piv, tout);
+int run_pchol(const double* lam, const double* g, int k, int ell, double delta, int tmax, double* d, double* Lc,
+              int* piv, hipStream_t st) {
+  const int grid = std::max(1, std::min((k + kPcThreads - 1) / kPcThreads, 256));
+  DevBuf pvA(grid * sizeof(double)), pvB(grid * sizeof(double)), psA(grid * sizeof(double)),
+      psB(grid * sizeof(double)), piA(grid * sizeof(int)), piB(grid * sizeof(int)), stt(sizeof(PcState));
+  hipLaunchKernelGGL(k_pchol_init, dim3(grid), dim3(kPcThreads), 0, st, lam, g, k, ell, d, pvA.as<double>(),
+                     piA.as<int>(), psA.as<double>(), stt.as<PcState>());
+  PcState h{};
+  for (int r = 0; r < tmax; ++r) {
+    const bool even = (r % 2) == 0;
+    hipLaunchKernelGGL(k_pchol_step, dim3(grid), dim3(kPcThreads), 0, st, lam, g, k, ell, delta, r, d, Lc, piv,
+                       even ? pvA.as<double>() : pvB.as<double>(), even ? piA.as<int>() : piB.as<int>(),
+                       even ? psA.as<double>() : psB.as<double>(), grid, even ? pvB.as<double>() : pvA.as<double>(),
+                       even ? piB.as<int>() : piA.as<int>(), even ? psB.as<double>() : psA.as<double>(),
+                       stt.as<PcState>());
+    if ((r + 1) % 32 == 0 || r + 1 == tmax) {
+      LYAP_HIP(hipMemcpyAsync(&h, stt.p, sizeof(PcState), hipMemcpyDeviceToHost, st));
+      LYAP_HIP(hipStreamSynchronize(st));
+      if (h.stop) break;
+    }
+  }
   LYAP_LAUNCHED("pchol");
+  return h.t;
 }
 
 void launch_gram_cols(const double* Lc, int k, int tp, double* G, hipStream_t st) {
@@ -448,9 +610,14 @@ void launch_gram_cols(const double* Lc, int k, int tp, double* G, hipStream_t st
 void launch_shift_solve(const double* band, int ldb, int ell, int k, const double* lam, const double* g,
                         const double* gamma, const int* piv, int tp, double* Lb, double* X, int* fail,
                         hipStream_t st) {
-  int grid = (tp + 63) / 64;
-  hipLaunchKernelGGL(k_shift_solve, dim3(grid), dim3(64), 0, st, band, ldb, ell, k, lam, g, gamma, piv, tp, Lb, X,
-                     fail);
+  const int grid = (tp + 63) / 64;
+  switch (ell) {
+#define LYAP_SS(E) case E: hipLaunchKernelGGL((k_shift_solve<E>), dim3(grid), dim3(64), 0, st, band, ldb, k, lam, g, gamma, piv, tp, Lb, X, fail); break;
+    LYAP_SS(1) LYAP_SS(2) LYAP_SS(3) LYAP_SS(4) LYAP_SS(5) LYAP_SS(6) LYAP_SS(7) LYAP_SS(8)
+    LYAP_SS(10) LYAP_SS(12) LYAP_SS(14) LYAP_SS(16)
+#undef LYAP_SS
+    default: LYAP_REQUIRE(false, LYAP_E_UNSUPPORTED, "shifted solve for ell=%d not built", ell);
+  }
   LYAP_LAUNCHED("shift_solve");
 }
 
@@ -458,7 +625,7 @@ void launch_assemble_M(const double* Lc, int k, const int* piv, int tp, const do
                        double* V1, double* B, double* M, hipStream_t st) {
   int64_t tot = (int64_t)tp * t;
   int grid = (int)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 4096));
-  hipLaunchKernelGGL(k_pick_top, dim3(grid), dim3(256), 0, st, Qg, tp, t, V1);
+  if (Qg) hipLaunchKernelGGL(k_pick_top, dim3(grid), dim3(256), 0, st, Qg, tp, t, V1);
   hipLaunchKernelGGL(k_trsm_lt, dim3((t + 63) / 64), dim3(64), 0, st, Lc, k, piv, tp, V1, t, B);
   tot = (int64_t)k * t;
   grid = (int)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 8192));

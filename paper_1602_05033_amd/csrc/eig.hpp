@@ -15,13 +15,15 @@ struct CheckOut {
 
 void launch_band_to_dense(const double* band, int ldb, int ell, int k, double* A, hipStream_t st);
 void launch_jacobi(double* A, int64_t strideA, double* Q, int64_t strideQ, double* lam, int64_t strideL,
-                   const int* nlist, int nfixed, int batch, hipStream_t st);
+                   const int* nlist, int nfixed, int batch, hipStream_t st, int* sweeps = nullptr);
 void launch_gw(const double* F, int64_t ldf, const double* L, int64_t ldl, int k, int ell, int nt,
                const double* gamma, const double* tau, double* g, double* Wm, hipStream_t st);
 void launch_ctri_sum(const double* lam, const double* g, const double* Wm, int k, int ell, int nt, double* part,
                      unsigned* counter, CheckOut* out, hipStream_t st);
-void launch_pchol(const double* lam, const double* g, int k, int ell, double delta, int tmax, double* d, double* Lc,
-                  int* piv, int* tout, hipStream_t st);
+// Pivoted Cholesky of Y~ (k x k, generated from lambda and g); returns the
+// number of columns formed (<= tmax).  Lc: k x tmax column-major, piv: tmax.
+int run_pchol(const double* lam, const double* g, int k, int ell, double delta, int tmax, double* d, double* Lc,
+              int* piv, hipStream_t st);
 void launch_gram_cols(const double* Lc, int k, int tp, double* G, hipStream_t st);
 void launch_shift_solve(const double* band, int ldb, int ell, int k, const double* lam, const double* g,
                         const double* gamma, const int* piv, int tp, double* Lb, double* X, int* fail,

@@ -115,122 +115,181 @@ __device__ void mul_upper(const double* A, const double* B, double* C) {  // C =
 constexpr double kBreakdownRatio = 1e-14;
 
 // ------------------------------------------------------------------ kernels
-// K1: W = A V_j ; alpha1 = V_{j-1}^T W
+// Rows owned by this thread: grid-stride over kSBlock-thread workgroups,
+// kRPT rows at a time (loads of all kRPT rows are issued before any arithmetic).
+#define LYAP_ROWS(r, n) for (int r = blockIdx.x * stream_threads(S) + threadIdx.x; r < (n); r += gridDim.x * stream_threads(S))
+// rows per thread: at most 64 bytes of each streamed array in flight per thread
+// (measured on MI355X: one row per thread per grid-stride iteration streams at
+// the cache/HBM rate; batching several rows per thread before any use was
+// several times slower)
 template <typename T, int S>
-__global__ __launch_bounds__(kBlock) void k_spmm_gram(StepArgs<T> a) {
-  __shared__ double red[S * S * kWaves];
-  double acc[S * S];
+constexpr int rows_per_thread() {
+  return 1;
+}
+#define LYAP_BATCH(r0, n) \
+  constexpr int kRPT = rows_per_thread<T, S>(); \
+  for (int r0 = blockIdx.x * stream_threads(S) + threadIdx.x; r0 < (n); r0 += gridDim.x * stream_threads(S) * kRPT)
+#define LYAP_FOR_U _Pragma("unroll") for (int u = 0; u < kRPT; ++u)
+
+template <int S>
+__device__ __forceinline__ void zero(double (&a)[S * S]) {
 #pragma unroll
-  for (int i = 0; i < S * S; ++i) acc[i] = 0.0;
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < a.n; r += gridDim.x * kBlock) {
-    T w[S], x[S];
-    op_row<T, S>(a.op, a.Vcur, r, w);
-    store_row<T, S>(a.W + (size_t)r * S, w);
-    load_row<T, S>(a.Vprev + (size_t)r * S, x);
-#pragma unroll
-    for (int p = 0; p < S; ++p)
-#pragma unroll
-      for (int q = 0; q < S; ++q) acc[p * S + q] = fma((double)x[p], (double)w[q], acc[p * S + q]);
-  }
-  if (grid_sum_last<S * S>(acc, red, a.part, a.counter)) {
-    if (threadIdx.x < S * S) a.log[L_A1 * S * S + threadIdx.x] = red[threadIdx.x];
-  }
+  for (int i = 0; i < S * S; ++i) a[i] = 0.0;
 }
 
-// K2..K4: W -= X alpha_in ; alpha_out = Y^T W
-template <typename T, int S>
-__global__ __launch_bounds__(kBlock) void k_upd_gram(StepArgs<T> a, const T* X, const T* Y, int slot_in,
-                                                     int slot_out) {
-  __shared__ double red[S * S * kWaves];
-  double al[S * S];
-  load_coef<S>(a.log + slot_in * S * S, al);
-  double acc[S * S];
+template <typename X, typename Y, int S>
+__device__ __forceinline__ void outer_acc(double (&acc)[S * S], const X (&x)[S], const Y (&y)[S]) {
 #pragma unroll
-  for (int i = 0; i < S * S; ++i) acc[i] = 0.0;
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < a.n; r += gridDim.x * kBlock) {
-    T w[S], x[S], y[S];
-    load_row<T, S>(a.W + (size_t)r * S, w);
-    load_row<T, S>(X + (size_t)r * S, x);
-    upd_row<T, S>(w, x, al);
-    store_row<T, S>(a.W + (size_t)r * S, w);
-    load_row<T, S>(Y + (size_t)r * S, y);
+  for (int p = 0; p < S; ++p)
 #pragma unroll
-    for (int p = 0; p < S; ++p)
-#pragma unroll
-      for (int q = 0; q < S; ++q) acc[p * S + q] = fma((double)y[p], (double)w[q], acc[p * S + q]);
-  }
-  if (grid_sum_last<S * S>(acc, red, a.part, a.counter)) {
-    if (threadIdx.x < S * S) a.log[slot_out * S * S + threadIdx.x] = red[threadIdx.x];
-  }
+    for (int q = 0; q < S; ++q) acc[p * S + q] = fma((double)x[p], (double)y[q], acc[p * S + q]);
 }
 
-// K5: W -= V_j alpha4 ; G1 = W^T W ; R1 = chol(G1)
+// Prologue: total of the previous kernel's partial Gram matrices into g[];
+// workgroup 0 also records it in the log slot (if slot >= 0).
+template <int S>
+__device__ __forceinline__ void take_gram(const double* pin, int nparts, double* red, double (&g)[S * S],
+                                          double* log_slot) {
+  reduce_partials<S * S, stream_threads(S)>(pin, nparts, red);
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) g[i] = uniform_d(red[i]);
+  if (blockIdx.x == 0 && log_slot && threadIdx.x < S * S) log_slot[threadIdx.x] = red[threadIdx.x];
+  __syncthreads();  // red is reused by the epilogue
+}
+
+// K1: W = A V_j ; partial alpha1 = V_{j-1}^T W
 template <typename T, int S>
-__global__ __launch_bounds__(kBlock) void k_upd_gramself(StepArgs<T> a) {
-  __shared__ double red[S * S * kWaves];
-  double al[S * S];
-  load_coef<S>(a.log + L_A4 * S * S, al);
+__global__ __launch_bounds__(stream_threads(S)) void k_spmm_gram(StepArgs<T> a) {
+  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
   double acc[S * S];
-#pragma unroll
-  for (int i = 0; i < S * S; ++i) acc[i] = 0.0;
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < a.n; r += gridDim.x * kBlock) {
-    T w[S], x[S];
-    load_row<T, S>(a.W + (size_t)r * S, w);
-    load_row<T, S>(a.Vcur + (size_t)r * S, x);
-    upd_row<T, S>(w, x, al);
-    store_row<T, S>(a.W + (size_t)r * S, w);
-#pragma unroll
-    for (int p = 0; p < S; ++p)
-#pragma unroll
-      for (int q = 0; q < S; ++q) acc[p * S + q] = fma((double)w[p], (double)w[q], acc[p * S + q]);
-  }
-  if (grid_sum_last<S * S>(acc, red, a.part, a.counter)) {
-    if (threadIdx.x == 0) {
-      double* L = a.log;
-      for (int i = 0; i < S * S; ++i) L[L_G1 * S * S + i] = red[i];
-      double ratio = chol_upper<S>(L + L_G1 * S * S, L + L_R1 * S * S);
-      inv_upper<S>(L + L_R1 * S * S, L + L_R1I * S * S);
-      double tr = 0.0;
-      for (int i = 0; i < S; ++i) tr += red[i * S + i];
-      L[L_FLAG * S * S + 0] = ratio;
-      L[L_FLAG * S * S + 1] = tr;
-      if (!(ratio > kBreakdownRatio) && a.flags[0] == 0) a.flags[0] = a.j + 1;
-      if (!(tr == tr) || tr > 1e300) a.flags[1] = a.j + 1;
+  zero<S>(acc);
+  const int str = gridDim.x * stream_threads(S);
+  LYAP_BATCH(r0, a.n) {
+    T w[kRPT][S], x[kRPT][S];
+    LYAP_FOR_U {
+      const int r = r0 + u * str;
+      if (r < a.n) {
+        op_row<T, S>(a.op, a.Vcur, r, w[u]);
+        load_row<T, S>(a.Vprev + (size_t)r * S, x[u]);
+      }
+    }
+    LYAP_FOR_U {
+      const int r = r0 + u * str;
+      if (r < a.n) {
+        store_row<T, S>(a.W + (size_t)r * S, w[u]);
+        outer_acc<T, T, S>(acc, x[u], w[u]);
+      }
     }
   }
+  write_partial<S * S, stream_threads(S)>(acc, red, a.pout);
 }
 
-// K6: U = W R1^{-1} ; G2 = U^T U ; R2 = chol(G2) ; tau_{j+1,j} = R2 R1 ; T band
+// K2..K5: alpha_in = total of the previous partials (logged), W -= X alpha_in,
+// partial Y^T W (Y == nullptr: W^T W for the QR that follows).
 template <typename T, int S>
-__global__ __launch_bounds__(kBlock) void k_apply_gramself(StepArgs<T> a) {
-  __shared__ double red[S * S * kWaves];
-  double ri[S * S];
-  load_coef<S>(a.log + L_R1I * S * S, ri);
+__global__ __launch_bounds__(stream_threads(S)) void k_upd_gram(StepArgs<T> a, const T* X, const T* Y, int slot_in) {
+  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+  double al[S * S];
+  take_gram<S>(a.pin, a.nparts, red, al, a.log + slot_in * S * S);
   double acc[S * S];
-#pragma unroll
-  for (int i = 0; i < S * S; ++i) acc[i] = 0.0;
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < a.n; r += gridDim.x * kBlock) {
-    T w[S];
-    double u[S];
-    load_row<T, S>(a.W + (size_t)r * S, w);
-    apply_upper_d<T, S>(w, ri, u);
-#pragma unroll
-    for (int p = 0; p < S; ++p)
-#pragma unroll
-      for (int q = 0; q < S; ++q) acc[p * S + q] = fma(u[p], u[q], acc[p * S + q]);
+  zero<S>(acc);
+  const int str = gridDim.x * stream_threads(S);
+  LYAP_BATCH(r0, a.n) {
+    T w[kRPT][S], x[kRPT][S], y[kRPT][S];
+    LYAP_FOR_U {
+      const int r = r0 + u * str;
+      if (r < a.n) {
+        load_row<T, S>(a.W + (size_t)r * S, w[u]);
+        load_row<T, S>(X + (size_t)r * S, x[u]);
+        if (Y) load_row<T, S>(Y + (size_t)r * S, y[u]);
+      }
+    }
+    LYAP_FOR_U {
+      const int r = r0 + u * str;
+      if (r < a.n) {
+        upd_row<T, S>(w[u], x[u], al);
+        store_row<T, S>(a.W + (size_t)r * S, w[u]);
+        if (Y) outer_acc<T, T, S>(acc, y[u], w[u]);
+        else outer_acc<T, T, S>(acc, w[u], w[u]);
+      }
+    }
   }
-  if (grid_sum_last<S * S>(acc, red, a.part, a.counter)) {
-    if (threadIdx.x == 0) {
-      double* L = a.log;
-      for (int i = 0; i < S * S; ++i) L[L_G2 * S * S + i] = red[i];
-      double ratio = chol_upper<S>(L + L_G2 * S * S, L + L_R2 * S * S);
-      double R2i[S * S];
-      inv_upper<S>(L + L_R2 * S * S, R2i);
-      mul_upper<S>(L + L_R2 * S * S, L + L_R1 * S * S, L + L_R * S * S);
-      mul_upper<S>(L + L_R1I * S * S, R2i, L + L_RI * S * S);
+  write_partial<S * S, stream_threads(S)>(acc, red, a.pout);
+}
+
+// K6: G1 = W^T W (logged), R1 = chol(G1) ; partial (W R1^{-1})^T (W R1^{-1})
+template <typename T, int S>
+__global__ __launch_bounds__(stream_threads(S)) void k_chol_gram(StepArgs<T> a) {
+  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+  __shared__ double sR1[S * S], sR1I[S * S];
+  __shared__ double sratio;
+  double G[S * S];
+  take_gram<S>(a.pin, a.nparts, red, G, a.log + L_G1 * S * S);
+  if (threadIdx.x == 0) {
+    sratio = chol_upper<S>(G, sR1);
+    inv_upper<S>(sR1, sR1I);
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x < S * S) {
+    a.log[L_R1 * S * S + threadIdx.x] = sR1[threadIdx.x];
+    a.log[L_R1I * S * S + threadIdx.x] = sR1I[threadIdx.x];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < S; ++i) tr += G[i * S + i];
+    a.log[L_FLAG * S * S + 0] = sratio;
+    a.log[L_FLAG * S * S + 1] = tr;
+    if (!(sratio > kBreakdownRatio) && a.flags[0] == 0) a.flags[0] = a.j + 1;
+    if (!(tr == tr) || tr > 1e300) a.flags[1] = a.j + 1;
+  }
+  double ri[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) ri[i] = uniform_d(sR1I[i]);
+  double acc[S * S];
+  zero<S>(acc);
+  const int str = gridDim.x * stream_threads(S);
+  LYAP_BATCH(r0, a.n) {
+    T w[kRPT][S];
+    LYAP_FOR_U {
+      const int r = r0 + u * str;
+      if (r < a.n) load_row<T, S>(a.W + (size_t)r * S, w[u]);
+    }
+    LYAP_FOR_U {
+      const int r = r0 + u * str;
+      if (r < a.n) {
+        double uu[S];
+        apply_upper_d<T, S>(w[u], ri, uu);
+        outer_acc<double, double, S>(acc, uu, uu);
+      }
+    }
+  }
+  write_partial<S * S, stream_threads(S)>(acc, red, a.pout);
+}
+
+// K7: G2 (logged), R2 = chol(G2), tau_{j+1,j} = R2 R1, V_{j+1} = W (R1^{-1} R2^{-1});
+// workgroup 0 writes the log and the T_m band (diagonal block sym(alpha2 +
+// alpha4), sub-diagonal block tau_{j+1,j}).
+template <typename T, int S>
+__global__ __launch_bounds__(stream_threads(S)) void k_chol_store(StepArgs<T> a) {
+  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+  __shared__ double sRI[S * S];
+  double G[S * S];
+  take_gram<S>(a.pin, a.nparts, red, G, a.log + L_G2 * S * S);
+  if (threadIdx.x == 0) {
+    double R2[S * S], R2i[S * S], R[S * S];
+    const double ratio = chol_upper<S>(G, R2);
+    inv_upper<S>(R2, R2i);
+    const double* L = a.log;
+    mul_upper<S>(L + L_R1I * S * S, R2i, sRI);
+    if (blockIdx.x == 0) {
+      double* Lw = a.log;
+      mul_upper<S>(R2, L + L_R1 * S * S, R);
+      for (int i = 0; i < S * S; ++i) {
+        Lw[L_R2 * S * S + i] = R2[i];
+        Lw[L_R * S * S + i] = R[i];
+        Lw[L_RI * S * S + i] = sRI[i];
+      }
       if (!(ratio > kBreakdownRatio) && a.flags[0] == 0) a.flags[0] = a.j + 1;
-      // T_m band (lower, ld = S+1): diagonal block sym(alpha2 + alpha4),
-      // sub-diagonal block tau_{j+1,j} = R.
       const int ld = S + 1;
       const int c0 = a.j * S;
       for (int p = 0; p < S; ++p)
@@ -240,121 +299,131 @@ __global__ __launch_bounds__(kBlock) void k_apply_gramself(StepArgs<T> a) {
           a.band[(size_t)(c0 + q) * ld + (p - q)] = 0.5 * (tpq + tqp);
         }
       for (int p = 0; p < S; ++p)
-        for (int q = p; q < S; ++q) a.band[(size_t)(c0 + q) * ld + (S + p - q)] = L[L_R * S * S + p * S + q];
+        for (int q = p; q < S; ++q) a.band[(size_t)(c0 + q) * ld + (S + p - q)] = R[p * S + q];
     }
   }
-}
-
-// K7: V_{j+1} = W (R1^{-1} R2^{-1})
-template <typename T, int S>
-__global__ __launch_bounds__(kBlock) void k_apply_store(StepArgs<T> a) {
+  __syncthreads();
   double ri[S * S];
-  load_coef<S>(a.log + L_RI * S * S, ri);
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < a.n; r += gridDim.x * kBlock) {
-    T w[S], v[S];
-    load_row<T, S>(a.W + (size_t)r * S, w);
-    apply_upper<T, S>(w, ri, v);
-    store_row<T, S>(a.Vnext + (size_t)r * S, v);
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) ri[i] = uniform_d(sRI[i]);
+  const int str = gridDim.x * stream_threads(S);
+  LYAP_BATCH(r0, a.n) {
+    T w[kRPT][S];
+    LYAP_FOR_U {
+      const int r = r0 + u * str;
+      if (r < a.n) load_row<T, S>(a.W + (size_t)r * S, w[u]);
+    }
+    LYAP_FOR_U {
+      const int r = r0 + u * str;
+      if (r < a.n) {
+        T v[S];
+        apply_upper<T, S>(w[u], ri, v);
+        store_row<T, S>(a.Vnext + (size_t)r * S, v);
+      }
+    }
   }
 }
 
 // Second pass: the whole step from the log, one kernel (V_{j+1} may alias V_{j-1}).
 template <typename T, int S>
-__global__ __launch_bounds__(kBlock) void k_replay(OpDev<T> op, int n, const T* Vprev, const T* Vcur, T* Vnext,
-                                                   const double* log) {
+__global__ __launch_bounds__(stream_threads(S)) void k_replay(OpDev<T> op, int n, const T* Vprev, const T* Vcur, T* Vnext,
+                                                    const double* log) {
   double a1[S * S], a2[S * S], a3[S * S], a4[S * S], ri[S * S];
   load_coef<S>(log + L_A1 * S * S, a1);
   load_coef<S>(log + L_A2 * S * S, a2);
   load_coef<S>(log + L_A3 * S * S, a3);
   load_coef<S>(log + L_A4 * S * S, a4);
   load_coef<S>(log + L_RI * S * S, ri);
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
-    T w[S], x[S], y[S], v[S];
-    op_row<T, S>(op, Vcur, r, w);
-    load_row<T, S>(Vprev + (size_t)r * S, x);
-    load_row<T, S>(Vcur + (size_t)r * S, y);
-    upd_row<T, S>(w, x, a1);
-    upd_row<T, S>(w, y, a2);
-    upd_row<T, S>(w, x, a3);
-    upd_row<T, S>(w, y, a4);
-    apply_upper<T, S>(w, ri, v);
-    store_row<T, S>(Vnext + (size_t)r * S, v);
+  const int str = gridDim.x * stream_threads(S);
+  LYAP_BATCH(r0, n) {
+    T w[kRPT][S], x[kRPT][S], y[kRPT][S];
+    LYAP_FOR_U {
+      const int r = r0 + u * str;
+      if (r < n) {
+        op_row<T, S>(op, Vcur, r, w[u]);
+        load_row<T, S>(Vprev + (size_t)r * S, x[u]);
+        load_row<T, S>(Vcur + (size_t)r * S, y[u]);
+      }
+    }
+    LYAP_FOR_U {
+      const int r = r0 + u * str;
+      if (r < n) {
+        T v[S];
+        upd_row<T, S>(w[u], x[u], a1);
+        upd_row<T, S>(w[u], y[u], a2);
+        upd_row<T, S>(w[u], x[u], a3);
+        upd_row<T, S>(w[u], y[u], a4);
+        apply_upper<T, S>(w[u], ri, v);
+        store_row<T, S>(Vnext + (size_t)r * S, v);
+      }
+    }
   }
 }
 
 // ------------------------------------------------------------------ initial block: C = V_1 gamma
 template <int S>
-__global__ __launch_bounds__(kBlock) void k_init_gram(const double* C, int64_t ldc, int n, double* glog,
-                                                      double* part, unsigned* counter, int* flags) {
-  __shared__ double red[S * S * kWaves];
-  double acc[S * S];
+__device__ __forceinline__ void load_C(const double* C, int64_t ldc, int r, double (&c)[S]) {
 #pragma unroll
-  for (int i = 0; i < S * S; ++i) acc[i] = 0.0;
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
-    double c[S];
-#pragma unroll
-    for (int q = 0; q < S; ++q) c[q] = C[(size_t)q * ldc + r];
-#pragma unroll
-    for (int p = 0; p < S; ++p)
-#pragma unroll
-      for (int q = 0; q < S; ++q) acc[p * S + q] = fma(c[p], c[q], acc[p * S + q]);
-  }
-  if (grid_sum_last<S * S>(acc, red, part, counter)) {
-    if (threadIdx.x == 0) {
-      for (int i = 0; i < S * S; ++i) glog[L_G1 * S * S + i] = red[i];
-      double tr = 0.0;
-      for (int i = 0; i < S; ++i) tr += red[i * S + i];
-      double ratio = chol_upper<S>(glog + L_G1 * S * S, glog + L_R1 * S * S);
-      inv_upper<S>(glog + L_R1 * S * S, glog + L_R1I * S * S);
-      glog[L_FLAG * S * S + 0] = ratio;
-      glog[L_FLAG * S * S + 1] = tr;
-      if (!(tr == tr) || tr > 1e300) flags[1] = -1;
-      if (!(ratio > kBreakdownRatio)) flags[0] = -1;
-    }
-  }
+  for (int q = 0; q < S; ++q) c[q] = C[(size_t)q * ldc + r];
 }
 
 template <int S>
-__global__ __launch_bounds__(kBlock) void k_init_gram2(const double* C, int64_t ldc, int n, double* glog,
-                                                       double* part, unsigned* counter, int* flags) {
-  __shared__ double red[S * S * kWaves];
-  double ri[S * S];
-  load_coef<S>(glog + L_R1I * S * S, ri);
+__global__ __launch_bounds__(stream_threads(S)) void k_init_gram(const double* C, int64_t ldc, int n, double* pout) {
+  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
   double acc[S * S];
+  zero<S>(acc);
+  LYAP_ROWS(r, n) {
+    double c[S];
+    load_C<S>(C, ldc, r, c);
+    outer_acc<double, double, S>(acc, c, c);
+  }
+  write_partial<S * S, stream_threads(S)>(acc, red, pout);
+}
+
+template <int S>
+__global__ __launch_bounds__(stream_threads(S)) void k_init_chol_gram(const double* C, int64_t ldc, int n, double* glog,
+                                                            const double* pin, int nparts, double* pout, int* flags) {
+  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+  __shared__ double sR1[S * S], sR1I[S * S];
+  __shared__ double sratio;
+  double G[S * S];
+  take_gram<S>(pin, nparts, red, G, glog + L_G1 * S * S);
+  if (threadIdx.x == 0) {
+    sratio = chol_upper<S>(G, sR1);
+    inv_upper<S>(sR1, sR1I);
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x < S * S) {
+    glog[L_R1 * S * S + threadIdx.x] = sR1[threadIdx.x];
+    glog[L_R1I * S * S + threadIdx.x] = sR1I[threadIdx.x];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < S; ++i) tr += G[i * S + i];
+    glog[L_FLAG * S * S + 0] = sratio;
+    glog[L_FLAG * S * S + 1] = tr;
+    if (!(tr == tr) || tr > 1e300) flags[1] = -1;
+    if (!(sratio > kBreakdownRatio)) flags[0] = -1;
+  }
+  double ri[S * S];
 #pragma unroll
-  for (int i = 0; i < S * S; ++i) acc[i] = 0.0;
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
+  for (int i = 0; i < S * S; ++i) ri[i] = uniform_d(sR1I[i]);
+  double acc[S * S];
+  zero<S>(acc);
+  LYAP_ROWS(r, n) {
     double c[S], u[S];
-#pragma unroll
-    for (int q = 0; q < S; ++q) c[q] = C[(size_t)q * ldc + r];
+    load_C<S>(C, ldc, r, c);
     apply_upper_d<double, S>(c, ri, u);
-#pragma unroll
-    for (int p = 0; p < S; ++p)
-#pragma unroll
-      for (int q = 0; q < S; ++q) acc[p * S + q] = fma(u[p], u[q], acc[p * S + q]);
+    outer_acc<double, double, S>(acc, u, u);
   }
-  if (grid_sum_last<S * S>(acc, red, part, counter)) {
-    if (threadIdx.x == 0) {
-      for (int i = 0; i < S * S; ++i) glog[L_G2 * S * S + i] = red[i];
-      double ratio = chol_upper<S>(glog + L_G2 * S * S, glog + L_R2 * S * S);
-      double R2i[S * S];
-      inv_upper<S>(glog + L_R2 * S * S, R2i);
-      mul_upper<S>(glog + L_R2 * S * S, glog + L_R1 * S * S, glog + L_R * S * S);    // gamma
-      mul_upper<S>(glog + L_R1I * S * S, R2i, glog + L_RI * S * S);                 // gamma^{-1}
-      if (!(ratio > kBreakdownRatio)) flags[0] = -1;
-    }
-  }
+  write_partial<S * S, stream_threads(S)>(acc, red, pout);
 }
 
 template <typename T, int S>
-__global__ __launch_bounds__(kBlock) void k_init_store(const double* C, int64_t ldc, int n, const double* glog,
-                                                       T* V1) {
-  double ri[S * S];
-  load_coef<S>(glog + L_RI * S * S, ri);
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
+__device__ __forceinline__ void store_V1(const double* C, int64_t ldc, int n, const double (&ri)[S * S], T* V1) {
+  LYAP_ROWS(r, n) {
     double c[S], u[S];
-#pragma unroll
-    for (int q = 0; q < S; ++q) c[q] = C[(size_t)q * ldc + r];
+    load_C<S>(C, ldc, r, c);
     apply_upper_d<double, S>(c, ri, u);
     T v[S];
 #pragma unroll
@@ -363,38 +432,98 @@ __global__ __launch_bounds__(kBlock) void k_init_store(const double* C, int64_t 
   }
 }
 
-// ------------------------------------------------------------------ Z accumulation
-// Z[:, c] += sum_{b < nb} V_b M_{[b]}[:, c] for the blocks listed in bl.
-// Mrows: row-major (nb*S) x t rows of M belonging to those blocks, in order.
+// gamma = R2 R1 (the positive-diagonal QR factor of C), V_1 = C gamma^{-1}
 template <typename T, int S>
-__global__ __launch_bounds__(kBlock) void k_zflush(BlockList bl, int nb, int n, const double* Mrows, int t, double* Z,
-                                                   int64_t ldz) {
-  constexpr int QB = (64 / S) > 0 ? 64 / S : 1;
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
-    double v[QB * S];
+__global__ __launch_bounds__(stream_threads(S)) void k_init_store(const double* C, int64_t ldc, int n, double* glog,
+                                                        const double* pin, int nparts, T* V1, int* flags) {
+  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+  __shared__ double sRI[S * S];
+  double G[S * S];
+  take_gram<S>(pin, nparts, red, G, glog + L_G2 * S * S);
+  if (threadIdx.x == 0) {
+    double R2[S * S], R2i[S * S], R[S * S];
+    const double ratio = chol_upper<S>(G, R2);
+    inv_upper<S>(R2, R2i);
+    mul_upper<S>(glog + L_R1I * S * S, R2i, sRI);
+    if (blockIdx.x == 0) {
+      mul_upper<S>(R2, glog + L_R1 * S * S, R);
+      for (int i = 0; i < S * S; ++i) {
+        glog[L_R2 * S * S + i] = R2[i];
+        glog[L_R * S * S + i] = R[i];
+        glog[L_RI * S * S + i] = sRI[i];
+      }
+      if (!(ratio > kBreakdownRatio)) flags[0] = -1;
+    }
+  }
+  __syncthreads();
+  double ri[S * S];
 #pragma unroll
-    for (int b = 0; b < QB; ++b) {
-      if (b < nb) {
-        T x[S];
+  for (int i = 0; i < S * S; ++i) ri[i] = uniform_d(sRI[i]);
+  store_V1<T, S>(C, ldc, n, ri, V1);
+}
+
+// V_1 again from the logged gamma^{-1} (second pass): same arithmetic.
+template <typename T, int S>
+__global__ __launch_bounds__(stream_threads(S)) void k_init_apply(const double* C, int64_t ldc, int n, const double* glog,
+                                                        T* V1) {
+  double ri[S * S];
+  load_coef<S>(glog + L_RI * S * S, ri);
+  store_V1<T, S>(C, ldc, n, ri, V1);
+}
+
+// ------------------------------------------------------------------ Z accumulation
+// Z[:, c] += sum_{b < nb} V_b M_{[b]}[:, c] for the blocks listed in bl
+// (nb <= 64), i.e. Z (n x t, column-major) += [V_b ...] (n x nb*S) times
+// Mrows (nb*S x t, row-major).  Workgroup tile: 64 rows x 64 columns of Z; lane
+// = row (coalesced Z and V accesses), wave = group of 16 columns kept in
+// registers; chunks of M staged in LDS and read by broadcast.  Plain FP64
+// FMAs, accumulated in the order of the buffered blocks, starting from Z.
+constexpr int kZR = 64, kZC = 64;
+
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_zflush(BlockList bl, int nb, int n, const double* Mrows, int t, double* Z,
+                                                int64_t ldz) {
+  constexpr int KQ = S * (32 / S);  // q values per LDS chunk (a multiple of S)
+  __shared__ double Ms[KQ * kZC];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = blockIdx.x * kZR + lane;
+  const int c0 = blockIdx.y * kZC;
+  const int cw = c0 + wv * 16;
+  const bool rowok = r < n;
+  double acc[16];
+#pragma unroll
+  for (int cc = 0; cc < 16; ++cc) acc[cc] = (rowok && cw + cc < t) ? Z[(size_t)(cw + cc) * ldz + r] : 0.0;
+  const int nq = nb * S;
+  for (int q0 = 0; q0 < nq; q0 += KQ) {
+    const int qn = min(KQ, nq - q0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < qn * kZC; e += 256) {
+      const int qi = e / kZC, cc = e - qi * kZC;
+      Ms[qi * kZC + cc] = (c0 + cc < t) ? Mrows[(size_t)(q0 + qi) * t + c0 + cc] : 0.0;
+    }
+    __syncthreads();
+    for (int bq = 0; bq < qn; bq += S) {
+      const int b = (q0 + bq) / S;
+      T x[S];
+      if (rowok) {
         load_row<T, S>((const T*)bl.p[b] + (size_t)r * S, x);
-#pragma unroll
-        for (int q = 0; q < S; ++q) v[b * S + q] = (double)x[q];
       } else {
 #pragma unroll
-        for (int q = 0; q < S; ++q) v[b * S + q] = 0.0;
+        for (int q = 0; q < S; ++q) x[q] = T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        const double a = (double)x[q];
+        const double* mrow = Ms + (bq + q) * kZC + wv * 16;
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) acc[cc] = fma(a, mrow[cc], acc[cc]);
       }
     }
-    for (int c = 0; c < t; ++c) {
-      double acc = Z[(size_t)c * ldz + r];
+  }
+  if (rowok) {
 #pragma unroll
-      for (int b = 0; b < QB; ++b) {
-        if (b < nb) {
-#pragma unroll
-          for (int q = 0; q < S; ++q) acc = fma(v[b * S + q], Mrows[(size_t)(b * S + q) * t + c], acc);
-        }
-      }
-      Z[(size_t)c * ldz + r] = acc;
-    }
+    for (int cc = 0; cc < 16; ++cc)
+      if (cw + cc < t) Z[(size_t)(cw + cc) * ldz + r] = acc[cc];
   }
 }
 
@@ -422,15 +551,33 @@ __global__ __launch_bounds__(kBlock) void k_apply(OpDev<T> op, const T* V, T* W)
   }
 
 template <typename T>
-void launch_step(const StepArgs<T>& a, int S, int grid, hipStream_t st) {
+void launch_step(const StepArgs<T>& a0, int S, int grid, double* partA, double* partB, hipStream_t st,
+                 KernelTimer* kt) {
+  StepArgs<T> a = a0;
+  a.nparts = grid;
+  auto mark = [&](int k) { if (kt) kt->mark(k); };
   LYAP_SWITCH_S(S, {
-    hipLaunchKernelGGL((k_spmm_gram<T, S>), dim3(grid), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL((k_upd_gram<T, S>), dim3(grid), dim3(kBlock), 0, st, a, a.Vprev, a.Vcur, (int)L_A1, (int)L_A2);
-    hipLaunchKernelGGL((k_upd_gram<T, S>), dim3(grid), dim3(kBlock), 0, st, a, a.Vcur, a.Vprev, (int)L_A2, (int)L_A3);
-    hipLaunchKernelGGL((k_upd_gram<T, S>), dim3(grid), dim3(kBlock), 0, st, a, a.Vprev, a.Vcur, (int)L_A3, (int)L_A4);
-    hipLaunchKernelGGL((k_upd_gramself<T, S>), dim3(grid), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL((k_apply_gramself<T, S>), dim3(grid), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL((k_apply_store<T, S>), dim3(grid), dim3(kBlock), 0, st, a);
+    a.pin = nullptr; a.pout = partA;
+    mark(LYAP_K_SPMM_GRAM);
+    hipLaunchKernelGGL((k_spmm_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a);
+    a.pin = partA; a.pout = partB;
+    mark(LYAP_K_UPD_GRAM);
+    hipLaunchKernelGGL((k_upd_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a, a.Vprev, a.Vcur, (int)L_A1);
+    a.pin = partB; a.pout = partA;
+    mark(LYAP_K_UPD_GRAM);
+    hipLaunchKernelGGL((k_upd_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a, a.Vcur, a.Vprev, (int)L_A2);
+    a.pin = partA; a.pout = partB;
+    mark(LYAP_K_UPD_GRAM);
+    hipLaunchKernelGGL((k_upd_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a, a.Vprev, a.Vcur, (int)L_A3);
+    a.pin = partB; a.pout = partA;
+    mark(LYAP_K_UPD_GRAM);
+    hipLaunchKernelGGL((k_upd_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a, a.Vcur, (const T*)nullptr, (int)L_A4);
+    a.pin = partA; a.pout = partB;
+    mark(LYAP_K_CHOL_GRAM);
+    hipLaunchKernelGGL((k_chol_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a);
+    a.pin = partB; a.pout = partA;
+    mark(LYAP_K_CHOL_STORE);
+    hipLaunchKernelGGL((k_chol_store<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a);
   });
   LYAP_LAUNCHED("lanczos step");
 }
@@ -438,47 +585,48 @@ void launch_step(const StepArgs<T>& a, int S, int grid, hipStream_t st) {
 template <typename T>
 void launch_replay(const OpDev<T>& op, int S, const T* Vprev, const T* Vcur, T* Vnext, const double* log, int grid,
                    hipStream_t st) {
-  LYAP_SWITCH_S(S, { hipLaunchKernelGGL((k_replay<T, S>), dim3(grid), dim3(kBlock), 0, st, op, op.n, Vprev, Vcur, Vnext, log); });
+  LYAP_SWITCH_S(S, { hipLaunchKernelGGL((k_replay<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, op, op.n, Vprev, Vcur, Vnext, log); });
   LYAP_LAUNCHED("replay");
 }
 
 template <typename T>
-void launch_init(const double* C, int64_t ldc, int n, int S, double* glog, double* part, unsigned* counter, int* flags,
+void launch_init(const double* C, int64_t ldc, int n, int S, double* glog, double* partA, double* partB, int* flags,
                  T* V1, int grid, hipStream_t st) {
   LYAP_SWITCH_S(S, {
-    hipLaunchKernelGGL((k_init_gram<S>), dim3(grid), dim3(kBlock), 0, st, C, ldc, n, glog, part, counter, flags);
-    hipLaunchKernelGGL((k_init_gram2<S>), dim3(grid), dim3(kBlock), 0, st, C, ldc, n, glog, part, counter, flags);
-    hipLaunchKernelGGL((k_init_store<T, S>), dim3(grid), dim3(kBlock), 0, st, C, ldc, n, glog, V1);
+    hipLaunchKernelGGL((k_init_gram<S>), dim3(grid), dim3(stream_threads(S)), 0, st, C, ldc, n, partA);
+    hipLaunchKernelGGL((k_init_chol_gram<S>), dim3(grid), dim3(stream_threads(S)), 0, st, C, ldc, n, glog, partA, grid, partB,
+                       flags);
+    hipLaunchKernelGGL((k_init_store<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, C, ldc, n, glog, partB, grid, V1, flags);
   });
   LYAP_LAUNCHED("init");
 }
 
 template <typename T>
 void launch_init_store(const double* C, int64_t ldc, int n, int S, const double* glog, T* V1, int grid, hipStream_t st) {
-  LYAP_SWITCH_S(S, { hipLaunchKernelGGL((k_init_store<T, S>), dim3(grid), dim3(kBlock), 0, st, C, ldc, n, glog, V1); });
-  LYAP_LAUNCHED("init_store");
+  LYAP_SWITCH_S(S, { hipLaunchKernelGGL((k_init_apply<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, C, ldc, n, glog, V1); });
+  LYAP_LAUNCHED("init_apply");
 }
 
 template <typename T>
 void launch_zflush(const void* const* blocks, int nb, int n, int S, const double* Mrows, int t, double* Z,
-                   int64_t ldz, int grid, hipStream_t st) {
+                   int64_t ldz, int /*grid*/, hipStream_t st) {
   if (nb <= 0 || t <= 0) return;
   LYAP_SWITCH_S(S, {
-    constexpr int QB = (64 / S) > 0 ? 64 / S : 1;
     int done = 0;
     while (done < nb) {
-      const int cnt = nb - done < QB ? nb - done : QB;
+      const int cnt = nb - done < 64 ? nb - done : 64;
       BlockList bl{};
       for (int b = 0; b < cnt; ++b) bl.p[b] = blocks[done + b];
-      hipLaunchKernelGGL((k_zflush<T, S>), dim3(grid), dim3(kBlock), 0, st, bl, cnt, n,
-                         Mrows + (size_t)done * S * t, t, Z, ldz);
+      dim3 grid((n + kZR - 1) / kZR, (t + kZC - 1) / kZC);
+      hipLaunchKernelGGL((k_zflush<T, S>), grid, dim3(256), 0, st, bl, cnt, n, Mrows + (size_t)done * S * t, t, Z,
+                         ldz);
       done += cnt;
     }
   });
   LYAP_LAUNCHED("zflush");
 }
 
-int zflush_max_blocks(int S) { return (64 / S) > 0 ? 64 / S : 1; }
+int zflush_max_blocks(int) { return 64; }
 
 template <typename T>
 void launch_apply(const OpDev<T>& op, int S, const T* V, T* W, int grid, hipStream_t st) {
@@ -487,9 +635,9 @@ void launch_apply(const OpDev<T>& op, int S, const T* V, T* W, int grid, hipStre
 }
 
 #define LYAP_INST(T)                                                                                         \
-  template void launch_step<T>(const StepArgs<T>&, int, int, hipStream_t);                                  \
+  template void launch_step<T>(const StepArgs<T>&, int, int, double*, double*, hipStream_t, KernelTimer*);  \
   template void launch_replay<T>(const OpDev<T>&, int, const T*, const T*, T*, const double*, int, hipStream_t); \
-  template void launch_init<T>(const double*, int64_t, int, int, double*, double*, unsigned*, int*, T*, int,   \
+  template void launch_init<T>(const double*, int64_t, int, int, double*, double*, double*, int*, T*, int,     \
                                hipStream_t);                                                                 \
   template void launch_init_store<T>(const double*, int64_t, int, int, const double*, T*, int, hipStream_t);  \
   template void launch_zflush<T>(const void* const*, int, int, int, const double*, int, double*, int64_t, int, \

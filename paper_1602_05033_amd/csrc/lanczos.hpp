@@ -1,6 +1,8 @@
 // Launch interface of the block Lanczos kernels (see lanczos.hip).
 #pragma once
 
+#include <algorithm>
+
 #include "op.hpp"
 
 namespace lyap {
@@ -35,17 +37,67 @@ struct StepArgs {
   double* log;       // this step's log
   double* band;      // T_m lower band, ld = S+1
   int j;             // step index (0-based)
-  double* part;      // grid partials
-  unsigned* counter; // arrival counter (zero between launches)
+  const double* pin; // partial Gram matrices of the previous kernel
+  double* pout;      // partial Gram matrices of this kernel (one per workgroup)
+  int nparts;        // number of workgroups (= partials)
   int* flags;        // [0] first breakdown step+1, [1] first non-finite step+1
 };
 
-template <typename T> void launch_step(const StepArgs<T>& a, int S, int grid, hipStream_t st);
+// Workgroups of the streaming kernels for an n-row block (<= 256, one per CU).
+inline int stream_grid(int64_t n) {
+  int64_t g = (n + 2 * (int64_t)kSBlock - 1) / (2 * (int64_t)kSBlock);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, kSGrid));
+}
+
+// Optional per-kernel timing with HIP events on the solver's stream: the time
+// between one mark and the next is attributed to the kind given at the first.
+struct KernelTimer {
+  hipStream_t st = nullptr;
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kind;
+  size_t used = 0;
+  double ms[12] = {0};
+  int n[12] = {0};
+  void mark(int k) {
+    if (!on) return;
+    if (used == ev.size()) {
+      hipEvent_t e;
+      LYAP_HIP(hipEventCreate(&e));
+      ev.push_back(e);
+      kind.push_back(-1);
+    }
+    LYAP_HIP(hipEventRecord(ev[used], st));
+    kind[used] = k;
+    ++used;
+  }
+  // Closes the open interval and accumulates everything recorded so far.
+  void collect() {
+    if (!on || used == 0) return;
+    mark(-1);
+    LYAP_HIP(hipEventSynchronize(ev[used - 1]));
+    for (size_t i = 0; i + 1 < used; ++i) {
+      if (kind[i] < 0) continue;
+      float t = 0.f;
+      LYAP_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+      ms[kind[i]] += t;
+      n[kind[i]] += 1;
+    }
+    used = 0;
+  }
+  ~KernelTimer() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+template <typename T>
+void launch_step(const StepArgs<T>& a, int S, int grid, double* partA, double* partB, hipStream_t st,
+                 KernelTimer* kt = nullptr);
 template <typename T>
 void launch_replay(const OpDev<T>& op, int S, const T* Vprev, const T* Vcur, T* Vnext, const double* log, int grid,
                    hipStream_t st);
 template <typename T>
-void launch_init(const double* C, int64_t ldc, int n, int S, double* glog, double* part, unsigned* counter, int* flags,
+void launch_init(const double* C, int64_t ldc, int n, int S, double* glog, double* partA, double* partB, int* flags,
                  T* V1, int grid, hipStream_t st);
 template <typename T>
 void launch_init_store(const double* C, int64_t ldc, int n, int S, const double* glog, T* V1, int grid, hipStream_t st);

@@ -29,16 +29,54 @@ struct OpDev {
   const T* val;
 };
 
+// Rows are S*sizeof(T) bytes at a 256-byte aligned base: use 16- or 8-byte
+// vector accesses when the row size allows it.
 template <typename T, int S>
 __device__ __forceinline__ void load_row(const T* __restrict__ p, T (&v)[S]) {
+  constexpr int B = S * (int)sizeof(T);
+  if constexpr (B % 16 == 0) {
+    const uint4* q = reinterpret_cast<const uint4*>(p);
 #pragma unroll
-  for (int c = 0; c < S; ++c) v[c] = p[c];
+    for (int i = 0; i < B / 16; ++i) {
+      uint4 x = q[i];
+      __builtin_memcpy(reinterpret_cast<char*>(v) + 16 * i, &x, 16);
+    }
+  } else if constexpr (B % 8 == 0) {
+    const uint2* q = reinterpret_cast<const uint2*>(p);
+#pragma unroll
+    for (int i = 0; i < B / 8; ++i) {
+      uint2 x = q[i];
+      __builtin_memcpy(reinterpret_cast<char*>(v) + 8 * i, &x, 8);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < S; ++c) v[c] = p[c];
+  }
 }
 
 template <typename T, int S>
 __device__ __forceinline__ void store_row(T* __restrict__ p, const T (&v)[S]) {
+  constexpr int B = S * (int)sizeof(T);
+  if constexpr (B % 16 == 0) {
+    uint4* q = reinterpret_cast<uint4*>(p);
 #pragma unroll
-  for (int c = 0; c < S; ++c) p[c] = v[c];
+    for (int i = 0; i < B / 16; ++i) {
+      uint4 x;
+      __builtin_memcpy(&x, reinterpret_cast<const char*>(v) + 16 * i, 16);
+      q[i] = x;
+    }
+  } else if constexpr (B % 8 == 0) {
+    uint2* q = reinterpret_cast<uint2*>(p);
+#pragma unroll
+    for (int i = 0; i < B / 8; ++i) {
+      uint2 x;
+      __builtin_memcpy(&x, reinterpret_cast<const char*>(v) + 8 * i, 8);
+      q[i] = x;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < S; ++c) p[c] = v[c];
+  }
 }
 
 template <typename T, int S>

