@@ -98,11 +98,78 @@ struct HostBuf {
 constexpr int kBlock = 256;          // threads per workgroup of the small kernels
 constexpr int kWaves = kBlock / 64;  // wave64
 
-// Sum of v over the 64 lanes of a wave (butterfly, fixed order; every lane
-// ends with the total).
+// ------------------------------------------------------------------ cross-lane exchange
+// Value held by lane (l ^ M) of the same wave, without going through the LDS
+// crossbar (ds_bpermute costs tens of cycles of LDS time per instruction and
+// dominated every reduction epilogue): DPP row permutations inside each
+// 16-lane row -- quad_perm [1,0,3,2] (M = 1), [2,3,0,1] (M = 2), the half-row
+// mirror (lane i <-> 7 - i, M = 7) and the row mirror (i <-> 15 - i, M = 15)
+// -- and the gfx950 permlane swaps across rows (M = 16, 32), which return the
+// even-row / low-half copy first.  All are plain VALU instructions.
+template <int M>
+__device__ __forceinline__ unsigned lane_xor_u(unsigned x) {
+  static_assert(M == 1 || M == 2 || M == 7 || M == 15 || M == 16 || M == 32, "unsupported lane mask");
+  if constexpr (M == 1) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);
+  } else if constexpr (M == 2) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);
+  } else if constexpr (M == 7) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false);
+  } else if constexpr (M == 15) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false);
+  } else if constexpr (M == 16) {
+    const auto s = __builtin_amdgcn_permlane16_swap(x, x, false, false);  // {even rows, odd rows}
+    return (__lane_id() & 16) ? s[0] : s[1];
+  } else {
+    const auto s = __builtin_amdgcn_permlane32_swap(x, x, false, false);  // {low half, high half}
+    return (__lane_id() & 32) ? s[0] : s[1];
+  }
+}
+
+template <int M>
+__device__ __forceinline__ double lane_xor(double v) {
+  const unsigned long long x = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = lane_xor_u<M>((unsigned)(x & 0xffffffffull));
+  const unsigned hi = lane_xor_u<M>((unsigned)(x >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int M>
+__device__ __forceinline__ int lane_xor(int v) {
+  return (int)lane_xor_u<M>((unsigned)v);
+}
+
+// Butterfly over the 64 lanes (masks 1, 2, 7, 15, 16, 32 span all six lane
+// bits).  Each lane combines its value with its partner's; the combination is
+// commutative, so both lanes of a pair hold the same bits and every lane ends
+// with the identical total.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  v += lane_xor<1>(v);
+  v += lane_xor<2>(v);
+  v += lane_xor<7>(v);
+  v += lane_xor<15>(v);
+  v += lane_xor<16>(v);
+  v += lane_xor<32>(v);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, lane_xor<1>(v));
+  v = fmax(v, lane_xor<2>(v));
+  v = fmax(v, lane_xor<7>(v));
+  v = fmax(v, lane_xor<15>(v));
+  v = fmax(v, lane_xor<16>(v));
+  v = fmax(v, lane_xor<32>(v));
+  return v;
+}
+
+__device__ __forceinline__ double wave_prod(double v) {
+  v *= lane_xor<1>(v);
+  v *= lane_xor<2>(v);
+  v *= lane_xor<7>(v);
+  v *= lane_xor<15>(v);
+  v *= lane_xor<16>(v);
+  v *= lane_xor<32>(v);
   return v;
 }
 
@@ -112,36 +179,52 @@ constexpr int pow2_at_least(int k) {
   return p;
 }
 
-// Sums of K per-lane values over a wave with a "transpose" butterfly: at each
-// step a lane keeps half of its values and receives the partner's copy of
-// that half, so K values need K-1 (+ the remaining log steps) shuffles instead
-// of K*6.  Returns the wave total of value index key(lane) in every lane; the
-// lanes whose low bits (below 64/P) are zero hold distinct keys 0..P-1.
-template <int K>
-__device__ __forceinline__ double wave_transpose_sum(const double (&v)[K], int lane, int* key) {
-  constexpr int P = pow2_at_least(K);
-  double w[P];
+constexpr int log2_exact(int p) {
+  int l = 0;
+  while ((1 << l) < p) ++l;
+  return l;
+}
+
+// One step of the transpose butterfly on lane bit B (partner mask M flips B
+// and only lower bits): the lane keeps the half of its CNT values selected by
+// bit B, adds the partner's copy of that half, and records the key offset.
+template <int M, int B, int CNT>
+__device__ __forceinline__ void transpose_step(double* w, int lane, int& key) {
+  constexpr int H = CNT / 2;
+  const bool up = ((lane >> B) & 1) != 0;
 #pragma unroll
-  for (int i = 0; i < P; ++i) w[i] = i < K ? v[i] : 0.0;
-  int k = 0;
-  int off = 32;
-#pragma unroll
-  for (int cnt = P; cnt > 1; cnt >>= 1) {
-    const int half = cnt >> 1;
-    const bool up = (lane & off) != 0;
-#pragma unroll
-    for (int i = 0; i < half; ++i) {
-      const double send = up ? w[i] : w[i + half];
-      const double keep = up ? w[i + half] : w[i];
-      w[i] = keep + __shfl_xor(send, off, 64);
-    }
-    if (up) k += half;
-    off >>= 1;
+  for (int i = 0; i < H; ++i) {
+    const double send = up ? w[i] : w[i + H];
+    const double keep = up ? w[i + H] : w[i];
+    w[i] = keep + lane_xor<M>(send);
   }
-  double r = w[0];
-  for (; off > 0; off >>= 1) r += __shfl_xor(r, off, 64);
-  *key = k;
-  return r;
+  if (up) key += H;
+}
+
+// Sum of v over the 64 lanes of a wave for P = pow2(K) values per lane.  Within
+// each 16-lane row a transpose butterfly on lane bits 3, 2, 1, 0 halves the
+// values held per lane at each step (P - 1 exchanges for P values instead of
+// 6 P); the remaining bits are plain sums, then the four rows are combined.
+// On return lane l holds the wave totals of keys key .. key + C - 1 in w[0..C),
+// C = max(P / 16, 1); in row 0 the lanes with (l & (16 / P - 1)) == 0 hold
+// each key exactly once.
+template <int P>
+__device__ __forceinline__ void wave_transpose_sum(double* w, int lane, int& key) {
+  key = 0;
+  if constexpr (P >= 2) transpose_step<15, 3, P>(w, lane, key);
+  else w[0] += lane_xor<15>(w[0]);
+  if constexpr (P >= 4) transpose_step<7, 2, P / 2>(w, lane, key);
+  else w[0] += lane_xor<7>(w[0]);
+  if constexpr (P >= 8) transpose_step<2, 1, P / 4>(w, lane, key);
+  else w[0] += lane_xor<2>(w[0]);
+  if constexpr (P >= 16) transpose_step<1, 0, P / 8>(w, lane, key);
+  else w[0] += lane_xor<1>(w[0]);
+  constexpr int C = P >= 16 ? P / 16 : 1;
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    w[i] += lane_xor<16>(w[i]);
+    w[i] += lane_xor<32>(w[i]);
+  }
 }
 
 // Reduce K per-thread values over an NT-thread workgroup.  The result is in
@@ -150,16 +233,25 @@ template <int K, int NT = kBlock>
 __device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
   constexpr int W = NT / 64;
   constexpr int P = pow2_at_least(K);
+  constexpr int C = P >= 16 ? P / 16 : 1;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  double w[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) w[i] = i < K ? v[i] : 0.0;
   int key;
-  const double s = wave_transpose_sum<K>(v, lane, &key);
-  if ((lane & ((64 / P) - 1)) == 0 && key < K) red[wave * P + key] = s;
+  wave_transpose_sum<P>(w, lane, key);
+  constexpr int lowmask = P >= 16 ? 0 : 16 / P - 1;
+  if (lane < 16 && (lane & lowmask) == 0) {
+#pragma unroll
+    for (int i = 0; i < C; ++i)
+      if (key + i < K) red[wave * P + key + i] = w[i];
+  }
   __syncthreads();
   if (threadIdx.x < K) {
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < W; ++w) t += red[w * P + threadIdx.x];
+    for (int q = 0; q < W; ++q) t += red[q * P + threadIdx.x];
     red[threadIdx.x] = t;  // slot k is only rewritten by thread k after reading it
   }
   __syncthreads();
@@ -219,21 +311,27 @@ constexpr int stream_threads(int S) { return S <= 4 ? kSBlock : 256; }
 
 template <int K, int NT>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nparts, double* red) {
-  // thread -> (value k, group of partials); the groups of one k are then summed
-  // across lanes and waves, always in the same order
+  // lane -> (value k in the high lane bits, slot in the low bits); the slots of
+  // one k are summed over the low lane bits and then across waves, always in
+  // the same order
   constexpr int P = pow2_at_least(K);
   static_assert(P <= 64, "K too large");
-  constexpr int G = NT / P;  // partial groups
-  const int k = threadIdx.x & (P - 1);
-  const int grp = threadIdx.x / P;
+  constexpr int LB = 6 - log2_exact(P);  // low lane bits = slots per wave
+  constexpr int G = NT / P;              // slots in the workgroup
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int k = lane >> LB;
+  const int g = wave * (1 << LB) + (lane & ((1 << LB) - 1));
   double acc = 0.0;
   if (k < K)
-    for (int b = grp; b < nparts; b += G) acc += part[(size_t)b * K + k];
-  // lanes with the same k within a wave: offsets P..32
-  for (int off = 32; off >= P; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    for (int b = g; b < nparts; b += G) acc += part[(size_t)b * K + k];
+  if constexpr (LB >= 1) acc += lane_xor<1>(acc);
+  if constexpr (LB >= 2) acc += lane_xor<2>(acc);
+  if constexpr (LB >= 3) acc += lane_xor<7>(acc);
+  if constexpr (LB >= 4) acc += lane_xor<15>(acc);
+  if constexpr (LB >= 5) acc += lane_xor<16>(acc);
+  if constexpr (LB >= 6) acc += lane_xor<32>(acc);
   constexpr int W = NT / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane < P && k < K) red[wave * P + k] = acc;
+  if ((lane & ((1 << LB) - 1)) == 0 && k < K) red[wave * P + k] = acc;
   __syncthreads();
   if (threadIdx.x < K) {
     double t = 0.0;

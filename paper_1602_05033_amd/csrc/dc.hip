@@ -229,8 +229,7 @@ __global__ __launch_bounds__(kDefThreads) void k_deflate(const DcMerge* md, DcSc
   {
     const int lane = t & 63, wave = t >> 6;
     double v = wave_sum(nz2);
-    double m = dmax;
-    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    const double m = wave_max(dmax);
     if (lane == 0) { redd[wave] = v; redd[kDefThreads / 64 + wave] = m; }
     __syncthreads();
     if (t == 0) {
@@ -454,8 +453,7 @@ __global__ __launch_bounds__(256) void k_zhat(const DcMerge* md, const DcScal* m
     const double num = (d[og[j]] - di) + tt[j];  // lambda_j - d_i
     prod *= (j == i) ? num : num / (d[j] - di);
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) prod *= __shfl_xor(prod, off, 64);
+  prod = wave_prod(prod);
   if (lane == 0) {
     const double v = sqrt(fmax(prod, 0.0) / s.r);
     zh[g.a + i] = zn[g.a + i] >= 0.0 ? v : -v;

@@ -301,12 +301,17 @@ __device__ __forceinline__ void pc_partials(const double* d, int k, double* pv, 
     sum += v;
     if (v > best || (v == best && i < bi)) { best = v; bi = i; }
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ob = __shfl_xor(best, off, 64);
-    const int oi = __shfl_xor(bi, off, 64);
+  // butterfly over the wave: both lanes of a pair keep the same (value, index)
+  auto merge = [&](double ob, int oi) {
     if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    sum += __shfl_xor(sum, off, 64);
-  }
+  };
+  merge(lane_xor<1>(best), lane_xor<1>(bi));
+  merge(lane_xor<2>(best), lane_xor<2>(bi));
+  merge(lane_xor<7>(best), lane_xor<7>(bi));
+  merge(lane_xor<15>(best), lane_xor<15>(bi));
+  merge(lane_xor<16>(best), lane_xor<16>(bi));
+  merge(lane_xor<32>(best), lane_xor<32>(bi));
+  sum = wave_sum(sum);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) { rv[wave] = best; ri[wave] = bi; rs[wave] = sum; }
   __syncthreads();
