@@ -114,7 +114,7 @@ def reduced_solution(T: np.ndarray, gamma: np.ndarray) -> np.ndarray:
     """Y_m of eq. (reducesLyap) by Bartels-Stewart (SciPy)."""
     ell = gamma.shape[0]
     k = T.shape[0]
-    E1g = np.zeros((k, ell))
+    E1g = np.zeros((k, gamma.shape[1]))   # E_1 gamma, k x s (gamma is ell x s)
     E1g[:ell, :] = gamma
     return sla.solve_continuous_lyapunov(T, -(E1g @ E1g.T))
 

@@ -1,0 +1,142 @@
+"""Preconditioned conjugate gradients for the inner solves of the extended
+Krylov method (Section 4 needs A^{-1} applied to a block at every step).
+
+Oracle -- test infrastructure only.  Plain float64 NumPy/SciPy.
+
+The paper solves with A exactly (sparse LU).  At large n this oracle instead
+solves (-A) x = -b (A is symmetric negative definite, so -A is SPD) with
+textbook PCG, column by column, and accepts a solve only when the *true*
+relative residual ||b - A x|| / ||b|| is at most eta; if the recursively
+updated residual reached eta but the true one did not, CG is restarted from
+the current iterate with the true residual (at most ``restarts`` times).
+
+Preconditioners:
+* ``"none"``;
+* ``"jacobi"``: M = diag(-A);
+* ``"ic0"``: zero fill-in incomplete Cholesky of -A in the natural (given)
+  ordering, M = L L^T, applied by two sparse triangular solves.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+
+@dataclass
+class PcgResult:
+    x: np.ndarray
+    iters: int            # CG iterations summed over restarts
+    relres_true: float    # ||b - A x|| / ||b|| at exit
+    converged: bool
+    restarts: int
+    history: list         # recursive ||r_k|| / ||b|| per iteration (first run)
+
+
+def ic0(Apos: sp.csr_matrix) -> sp.csr_matrix:
+    """Lower triangular L with the sparsity of tril(Apos) and
+    (L L^T)_ij = Apos_ij on that pattern (IC(0), natural ordering).
+    Row-by-row (left-looking) form: for each entry (i, j), j <= i, of the
+    pattern, L_ij = (a_ij - sum_{k<j} L_ik L_jk) / L_jj, L_ii = sqrt(a_ii - sum L_ik^2)."""
+    A = sp.tril(Apos, format="csr")
+    A.sort_indices()
+    n = A.shape[0]
+    rows = [dict() for _ in range(n)]
+    for i in range(n):
+        for p in range(A.indptr[i], A.indptr[i + 1]):
+            j = A.indices[p]
+            v = A.data[p]
+            if j < i:
+                s = v
+                Li, Lj = rows[i], rows[j]
+                for k, lik in Li.items():
+                    if k < j and k in Lj:
+                        s -= lik * Lj[k]
+                Li[j] = s / Lj[j]
+            elif j == i:
+                s = v - sum(l * l for k, l in rows[i].items() if k < i)
+                if not s > 0.0:
+                    raise np.linalg.LinAlgError("IC(0) pivot is not positive")
+                rows[i][i] = np.sqrt(s)
+    ri, ci, vv = [], [], []
+    for i in range(n):
+        for j, v in rows[i].items():
+            ri.append(i)
+            ci.append(j)
+            vv.append(v)
+    return sp.csr_matrix((vv, (ri, ci)), shape=(n, n))
+
+
+def make_preconditioner(A, kind: str):
+    """Returns z = M^{-1} r for the SPD matrix -A."""
+    Apos = -sp.csr_matrix(A)
+    if kind == "none":
+        return lambda r: r.copy()
+    if kind == "jacobi":
+        d = Apos.diagonal()
+        return lambda r: r / d
+    if kind == "ic0":
+        L = ic0(Apos)
+        Lt = L.T.tocsr()
+        def apply(r):
+            y = spla.spsolve_triangular(L, r, lower=True)
+            return spla.spsolve_triangular(Lt, y, lower=False)
+        return apply
+    raise ValueError(kind)
+
+
+def pcg(A, b: np.ndarray, eta: float = 1e-12, max_iter: int = 10000, pc: str = "jacobi",
+        restarts: int = 3, precond=None, x0: Optional[np.ndarray] = None) -> PcgResult:
+    """Solve A x = b (A symmetric negative definite) by PCG on (-A) x = -b."""
+    Apos = -sp.csr_matrix(A)
+    if precond is None:
+        precond = make_preconditioner(A, pc)
+    rhs = -b
+    bn = float(np.linalg.norm(b))
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    if bn == 0.0:
+        return PcgResult(x * 0.0, 0, 0.0, True, 0, [])
+    total = 0
+    hist = []
+    nrest = 0
+    while True:
+        r = rhs - Apos @ x
+        z = precond(r)
+        p = z.copy()
+        rho = float(r @ z)
+        for _ in range(max_iter - total):
+            if float(np.linalg.norm(r)) <= eta * bn:
+                break
+            q = Apos @ p
+            sigma = float(p @ q)
+            alpha = rho / sigma
+            x = x + alpha * p
+            r = r - alpha * q
+            total += 1
+            if nrest == 0:
+                hist.append(float(np.linalg.norm(r)) / bn)
+            z = precond(r)
+            rho_new = float(r @ z)
+            beta = rho_new / rho
+            rho = rho_new
+            p = z + beta * p
+        true = float(np.linalg.norm(b - A @ x)) / bn
+        if true <= eta:
+            return PcgResult(x, total, true, True, nrest, hist)
+        if nrest >= restarts or total >= max_iter:
+            return PcgResult(x, total, true, False, nrest, hist)
+        nrest += 1
+
+
+def pcg_block(A, B: np.ndarray, **kw):
+    """Column-by-column PCG for an n x s block; returns (X, [PcgResult])."""
+    X = np.zeros_like(B)
+    res = []
+    for c in range(B.shape[1]):
+        r = pcg(A, B[:, c], **kw)
+        X[:, c] = r.x
+        res.append(r)
+    return X, res
