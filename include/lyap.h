@@ -110,7 +110,8 @@ typedef struct lyap_opts {
                            0: store the whole basis (memory s*m vectors)               */
   double trunc_eps;     /* < 0: default truncation threshold (see lyap_solve);
                            >= 0: absolute threshold on ||Sigma_2||_F               */
-  int32_t inner_pc;     /* extended Krylov inner solver preconditioner (LYAP_PC_*)  */
+  int32_t inner_pc;     /* extended Krylov inner CG preconditioner: LYAP_PC_NONE or
+                           LYAP_PC_JACOBI (others: LYAP_E_UNSUPPORTED)            */
   double inner_tol;     /* inner solves accepted when true ||b-Ax||/||b|| <= this  */
   int32_t inner_max_iter;
   int32_t flush_blocks; /* second pass: blocks buffered per Z update (0 = default)  */
@@ -125,7 +126,7 @@ typedef struct lyap_opts {
 } lyap_opts;
 
 /* Fills *o with: tol 1e-8, max_iter 5000, STD, adaptive checks, F64 storage,
- * two_pass 1, default truncation, inner PC IC0, inner_tol 1e-12,
+ * two_pass 1, default truncation, inner PC Jacobi, inner_tol 1e-12,
  * inner_max_iter 5000, hipMalloc allocation, null stream. */
 void lyap_opts_default(lyap_opts* o);
 
@@ -183,7 +184,10 @@ enum {
   LYAP_K_ZFLUSH = 5,     /* Z += V_i M_i for a group of buffered blocks         */
   LYAP_K_CHECK = 6,      /* one residual check (all its kernels)                */
   LYAP_K_FINAL = 7,      /* truncation and Q Y-check (all its kernels)          */
-  LYAP_K_INIT = 8        /* QR of C                                             */
+  LYAP_K_INIT = 8,       /* QR of C                                             */
+  LYAP_K_CG_DIR = 9,     /* inner CG: new direction fused with q = -A p         */
+  LYAP_K_CG_UPD = 10,    /* inner CG: x, r update and the next dot products     */
+  LYAP_K_EXT_ORTH = 11   /* extended Krylov: full reorthogonalisation + QR + T  */
 };
 
 /*
@@ -269,6 +273,26 @@ lyap_status lyap_op_apply_timed(const lyap_op* A, int32_t storage, const void* V
  */
 lyap_status lyap_ctri(const double* T_band, int32_t ell, int32_t k, const double* gamma,
                       const double* tau, double* res, double* lam, void* stream);
+
+/*
+ * Inner solve of the extended Krylov method (Section 4 applies A^{-1} to a
+ * block at every step): X = A^{-1} B by preconditioned conjugate gradients on
+ * -A (symmetric positive definite), FP64, the s columns advanced together
+ * with their own scalars.
+ *  A        operator (device arrays), symmetric negative definite.
+ *  B, X     device, n x s column-major FP64, leading dimensions ldb, ldx >= n;
+ *           X is overwritten (B is not modified).
+ *  s        1, 2 or 4.
+ *  opts     inner_pc (LYAP_PC_NONE or LYAP_PC_JACOBI), inner_tol (bound on
+ *           the true ||b - A x|| / ||b|| of every column), inner_max_iter and
+ *           stream are used; NULL means defaults.
+ *  iters    optional output: CG iterations, restarts included.
+ *  relres   optional output: largest true relative residual over the columns.
+ * Returns LYAP_E_INNER when a column does not reach inner_tol (X then holds
+ * the last iterate), LYAP_E_INDEFINITE when a diagonal entry of A is >= 0.
+ */
+lyap_status lyap_inner_solve(const lyap_op* A, const double* B, int64_t ldb, double* X, int64_t ldx, int32_t s,
+                             const lyap_opts* opts, int64_t* iters, double* relres);
 
 #ifdef __cplusplus
 }

@@ -70,7 +70,7 @@ class SylvResult(ct.Structure):
 
 # exported symbols declared in include/lyap.h
 EXPORTS = ["lyap_opts_default", "lyap_solve", "sylv_solve", "lyap_result_free", "sylv_result_free",
-           "lyap_last_error", "lyap_op_apply", "lyap_op_apply_timed", "lyap_ctri"]
+           "lyap_last_error", "lyap_op_apply", "lyap_op_apply_timed", "lyap_ctri", "lyap_inner_solve"]
 
 
 class LyapError(RuntimeError):
@@ -112,6 +112,9 @@ def load(path: str = LIB_PATH):
     lib.lyap_ctri.argtypes = [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p,
                               ct.POINTER(ct.c_double), ct.c_void_p, ct.c_void_p]
     lib.lyap_ctri.restype = ct.c_int
+    lib.lyap_inner_solve.argtypes = [ct.POINTER(LyapOp), ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int64, ct.c_int32,
+                                     ct.POINTER(LyapOpts), ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
+    lib.lyap_inner_solve.restype = ct.c_int
     _LIB = lib
     return lib
 
@@ -213,11 +216,12 @@ class LyapSolution:
 TIME_KEYS = ["pass1", "checks", "final", "pass2", "inner", "train", "total", "to_tol"]
 
 
-KERNEL_KINDS = ["spmm_gram", "upd_gram", "chol_gram", "chol_store", "replay", "zflush", "check", "final", "init"]
+KERNEL_KINDS = ["spmm_gram", "upd_gram", "chol_gram", "chol_store", "replay", "zflush", "check", "final", "init",
+                "cg_dir", "cg_upd", "ext_orth"]
 
 
 def make_opts(tol=1e-8, max_iter=5000, method=METHOD_STD, check_every=0, storage=STORE_F64, two_pass=True,
-              trunc_eps=-1.0, inner_pc=PC_IC0, inner_tol=1e-12, inner_max_iter=5000, want_T=False,
+              trunc_eps=-1.0, inner_pc=PC_JACOBI, inner_tol=1e-12, inner_max_iter=5000, want_T=False,
               verbose=False, stream=None, profile=False):
     o = LyapOpts()
     load().lyap_opts_default(ct.byref(o))
@@ -267,8 +271,7 @@ def lyap_solve(dop: DeviceOp, C, raise_on_error: bool = True, **kw) -> LyapSolut
         if r.T_band:
             sol.T_band = np.ctypeslib.as_array(r.T_band, shape=(k * (ell + 1),)).copy().reshape(k, ell + 1)
             sol.gamma = np.ctypeslib.as_array(r.gamma, shape=(ell * ell,)).copy().reshape(ell, ell, order="F")
-            nt = ell if r.s == ell else r.s
-            sol.tau = np.ctypeslib.as_array(r.tau, shape=(nt * ell,)).copy().reshape(nt, ell, order="F")
+            sol.tau = np.ctypeslib.as_array(r.tau, shape=(ell * ell,)).copy().reshape(ell, ell, order="F")
         sol.error = msg
         return sol
     finally:
@@ -312,3 +315,23 @@ def ctri(T_band: np.ndarray, gamma: np.ndarray, tau: np.ndarray):
                        t.ctypes.data_as(ct.c_void_p), ct.byref(res), lam.ctypes.data_as(ct.c_void_p), None)
     _check(st)
     return res.value, lam
+
+
+def inner_solve(dop: DeviceOp, B, raise_on_error: bool = True, **kw):
+    """X = A^{-1} B by the library's inner PCG.  ``B`` is an (n, s) float64
+    torch tensor on the device; returns (X, iterations, worst true relative
+    residual, status)."""
+    import torch
+    lib = load()
+    n, s = B.shape
+    assert n == dop.n and B.dtype == torch.float64 and B.is_cuda
+    Bcm = B.t().contiguous()
+    Xcm = torch.empty_like(Bcm)
+    o = make_opts(stream=torch.cuda.current_stream(B.device).cuda_stream, **kw)
+    iters = ct.c_int64(0)
+    rel = ct.c_double(0.0)
+    st = lib.lyap_inner_solve(ct.byref(dop.c), ct.c_void_p(Bcm.data_ptr()), n, ct.c_void_p(Xcm.data_ptr()), n, s,
+                              ct.byref(o), ct.byref(iters), ct.byref(rel))
+    if raise_on_error and st != OK:
+        raise LyapError(st, lib.lyap_last_error().decode())
+    return Xcm.t(), iters.value, rel.value, st

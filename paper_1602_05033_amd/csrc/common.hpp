@@ -84,7 +84,10 @@ struct HostBuf {
   void* p = nullptr;
   size_t bytes = 0;
   HostBuf() = default;
-  explicit HostBuf(size_t b) {
+  explicit HostBuf(size_t b) { alloc(b); }
+  void alloc(size_t b) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
     LYAP_HIP(hipHostMalloc(&p, b ? b : 64, hipHostMallocDefault));
     bytes = b;
   }

@@ -87,22 +87,29 @@ __device__ __forceinline__ void axpy_row(T a, const T* __restrict__ p, T (&acc)[
   for (int c = 0; c < S; ++c) acc[c] = fma(a, v[c], acc[c]);
 }
 
-// w = (A V)_r, accumulated in T with a fixed order of terms.
-template <typename T, int S>
-__device__ __forceinline__ void op_row(const OpDev<T>& op, const T* __restrict__ V, int r,
-                                       T (&w)[S]) {
+// w = (A v)_r, accumulated in T with a fixed order of terms; row i of the
+// operand v is produced by ld(i, out) (a plain load for a stored block, or a
+// value computed on the fly, e.g. a CG search direction).
+template <typename T, int S, typename Load>
+__device__ __forceinline__ void op_row_fn(const OpDev<T>& op, int r, Load&& ld, T (&w)[S]) {
+  auto axpy = [&](T a, int i) {
+    T v[S];
+    ld(i, v);
+#pragma unroll
+    for (int c = 0; c < S; ++c) w[c] = fma(a, v[c], w[c]);
+  };
   if (op.kind == LYAP_OP_STENCIL5) {
     const int nx = op.nx;
     const int j = r / nx;
     const int i = r - j * nx;
     T v[S];
-    load_row<T, S>(V + (size_t)r * S, v);
+    ld(r, v);
 #pragma unroll
     for (int c = 0; c < S; ++c) w[c] = op.cc * v[c];
-    if (j > 0) axpy_row<T, S>(op.co, V + (size_t)(r - nx) * S, w);
-    if (i > 0) axpy_row<T, S>(op.co, V + (size_t)(r - 1) * S, w);
-    if (i < nx - 1) axpy_row<T, S>(op.co, V + (size_t)(r + 1) * S, w);
-    if (j < op.ny - 1) axpy_row<T, S>(op.co, V + (size_t)(r + nx) * S, w);
+    if (j > 0) axpy(op.co, r - nx);
+    if (i > 0) axpy(op.co, r - 1);
+    if (i < nx - 1) axpy(op.co, r + 1);
+    if (j < op.ny - 1) axpy(op.co, r + nx);
   } else if (op.kind == LYAP_OP_STENCIL7) {
     const int nx = op.nx, ny = op.ny;
     const int nxy = nx * ny;
@@ -111,24 +118,41 @@ __device__ __forceinline__ void op_row(const OpDev<T>& op, const T* __restrict__
     const int j = rem / nx;
     const int i = rem - j * nx;
     T v[S];
-    load_row<T, S>(V + (size_t)r * S, v);
+    ld(r, v);
     const T d = op.diag[r];
 #pragma unroll
     for (int c = 0; c < S; ++c) w[c] = d * v[c];
-    if (l > 0) axpy_row<T, S>(op.tz[r - nxy], V + (size_t)(r - nxy) * S, w);
-    if (j > 0) axpy_row<T, S>(op.ty[r - nx], V + (size_t)(r - nx) * S, w);
-    if (i > 0) axpy_row<T, S>(op.tx[r - 1], V + (size_t)(r - 1) * S, w);
-    if (i < nx - 1) axpy_row<T, S>(op.tx[r], V + (size_t)(r + 1) * S, w);
-    if (j < ny - 1) axpy_row<T, S>(op.ty[r], V + (size_t)(r + nx) * S, w);
-    if (l < op.nz - 1) axpy_row<T, S>(op.tz[r], V + (size_t)(r + nxy) * S, w);
+    if (l > 0) axpy(op.tz[r - nxy], r - nxy);
+    if (j > 0) axpy(op.ty[r - nx], r - nx);
+    if (i > 0) axpy(op.tx[r - 1], r - 1);
+    if (i < nx - 1) axpy(op.tx[r], r + 1);
+    if (j < ny - 1) axpy(op.ty[r], r + nx);
+    if (l < op.nz - 1) axpy(op.tz[r], r + nxy);
   } else {  // CSR
     const int64_t b = op.rowptr[r];
     const int64_t e = op.rowptr[r + 1];
 #pragma unroll
     for (int c = 0; c < S; ++c) w[c] = T(0);
-    for (int64_t k = b; k < e; ++k) axpy_row<T, S>(op.val[k], V + (size_t)op.col[k] * S, w);
-    if (op.shift != T(0)) axpy_row<T, S>(op.shift, V + (size_t)r * S, w);
+    for (int64_t k = b; k < e; ++k) axpy(op.val[k], op.col[k]);
+    if (op.shift != T(0)) axpy(op.shift, r);
   }
+}
+
+// w = (A V)_r for a stored row-interleaved block V.
+template <typename T, int S>
+__device__ __forceinline__ void op_row(const OpDev<T>& op, const T* __restrict__ V, int r, T (&w)[S]) {
+  op_row_fn<T, S>(op, r, [&](int i, T (&v)[S]) { load_row<T, S>(V + (size_t)i * S, v); }, w);
+}
+
+// Diagonal entry A_rr (shift included).
+template <typename T>
+__device__ __forceinline__ T op_diag(const OpDev<T>& op, int r) {
+  if (op.kind == LYAP_OP_STENCIL5) return op.cc;
+  if (op.kind == LYAP_OP_STENCIL7) return op.diag[r];
+  T d = op.shift;
+  for (int64_t k = op.rowptr[r]; k < op.rowptr[r + 1]; ++k)
+    if (op.col[k] == r) d += op.val[k];
+  return d;
 }
 
 // Host side: an operator converted to storage type T on the device.

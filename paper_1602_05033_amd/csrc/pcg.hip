@@ -1,0 +1,448 @@
+// Preconditioned CG on -A for the inner solves of the extended Krylov method.
+//
+// One iteration is two streaming kernels with consumer-side reductions (the
+// same scheme as the Lanczos step: each kernel writes one partial per
+// workgroup, the next kernel sums all partials in a fixed order):
+//
+//   D  beta = rho_k / rho_{k-1};  p = z + beta p_old  (z = M^{-1} r);
+//      q = (-A) p, where the rows of p that the stencil needs are recomputed
+//      from r, M^{-1} and p_old on the fly; partial p^T q
+//   U  alpha = rho_k / p^T q;  x += alpha p;  r -= alpha q;  z = M^{-1} r;
+//      partials r^T z and r^T r
+//
+// The host launches iterations in chunks and reads the logged r^T r of each
+// chunk once; a column whose recursive residual is below the threshold is
+// frozen (alpha = 0, p = 0), so iterations after convergence change nothing.
+// Every solve is then certified by the true residual ||b - A x|| / ||b||; a
+// solve that fails it restarts from the current iterate (at most three times).
+#include <cmath>
+
+#include "pcg.hpp"
+
+namespace lyap {
+
+constexpr int kCgChunk = 32;
+constexpr int kCgRestarts = 3;
+
+// Row i of the search direction: active columns z_i + beta p_old_i, others 0.
+template <int S>
+__device__ __forceinline__ void dir_row(const double* __restrict__ r, const double* __restrict__ dinv,
+                                        const double* __restrict__ pold, const double (&beta)[S],
+                                        const double (&mask)[S], int i, double (&p)[S]) {
+  double rv[S];
+  load_row<double, S>(r + (size_t)i * S, rv);
+  const double di = dinv[i];
+  if (pold) {
+    double pv[S];
+    load_row<double, S>(pold + (size_t)i * S, pv);
+#pragma unroll
+    for (int c = 0; c < S; ++c) p[c] = mask[c] * fma(beta[c], pv[c], rv[c] * di);
+  } else {
+#pragma unroll
+    for (int c = 0; c < S; ++c) p[c] = mask[c] * (rv[c] * di);
+  }
+}
+
+#define CG_ROWS(r, n) for (int r = blockIdx.x * NT + threadIdx.x; r < (n); r += gridDim.x * NT)
+
+__global__ void k_cg_diag(OpDev<double> op, int n, int pc, double* dinv, int* flag) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const double d = -op_diag<double>(op, r);
+    if (!(d > 0.0)) flag[0] = 1;
+    dinv[r] = pc == LYAP_PC_JACOBI ? 1.0 / d : 1.0;
+  }
+}
+
+// mode 0: x = 0, r = -B (so that (-A) x = -B, i.e. A x = B); mode 1: r already
+// holds the true residual of the current x.  Partials r^T z, r^T r.
+template <int S, int NT>
+__global__ __launch_bounds__(NT) void k_cg_init(const double* __restrict__ B, double* __restrict__ x,
+                                                double* __restrict__ r, const double* __restrict__ dinv, int n,
+                                                int mode, double* pout) {
+  __shared__ double red[pow2_at_least(2 * S) * (NT / 64)];
+  double acc[2 * S];
+#pragma unroll
+  for (int c = 0; c < 2 * S; ++c) acc[c] = 0.0;
+  CG_ROWS(i, n) {
+    double rv[S];
+    if (mode == 0) {
+      double bv[S], xv[S];
+      load_row<double, S>(B + (size_t)i * S, bv);
+#pragma unroll
+      for (int c = 0; c < S; ++c) {
+        rv[c] = -bv[c];
+        xv[c] = 0.0;
+      }
+      store_row<double, S>(r + (size_t)i * S, rv);
+      store_row<double, S>(x + (size_t)i * S, xv);
+    } else {
+      load_row<double, S>(r + (size_t)i * S, rv);
+    }
+    const double di = dinv[i];
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+      acc[c] = fma(rv[c], rv[c] * di, acc[c]);
+      acc[S + c] = fma(rv[c], rv[c], acc[S + c]);
+    }
+  }
+  write_partial<2 * S, NT>(acc, red, pout);
+}
+
+template <int S, int NT>
+__global__ __launch_bounds__(NT) void k_cg_dir(OpDev<double> op, const double* __restrict__ r,
+                                               const double* __restrict__ dinv, const double* __restrict__ pold,
+                                               double* __restrict__ pnew, double* __restrict__ q, CgIter* log, int it,
+                                               int first, double* state, double eta2, const double* pin, int nparts,
+                                               double* pout, int n) {
+  __shared__ double red[pow2_at_least(2 * S) * (NT / 64)];
+  reduce_partials<2 * S, NT>(pin, nparts, red);
+  double rho[S], rr[S], beta[S], mask[S];
+#pragma unroll
+  for (int c = 0; c < S; ++c) {
+    rho[c] = uniform_d(red[c]);
+    rr[c] = uniform_d(red[S + c]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < S; ++c) {
+    const double thr = (first && it == 0) ? eta2 * rr[c] : uniform_d(state[c]);
+    const bool active = rr[c] > thr;
+    mask[c] = active ? 1.0 : 0.0;
+    beta[c] = (active && it > 0) ? rho[c] / uniform_d(log[it - 1].rho[c]) : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (first && it == 0) state[c] = thr;
+      log[it].rho[c] = rho[c];
+      log[it].rr[c] = rr[c];
+    }
+  }
+  const double* po = it > 0 ? pold : nullptr;
+  double acc[S];
+#pragma unroll
+  for (int c = 0; c < S; ++c) acc[c] = 0.0;
+  CG_ROWS(i, n) {
+    double p[S], w[S];
+    dir_row<S>(r, dinv, po, beta, mask, i, p);
+    store_row<double, S>(pnew + (size_t)i * S, p);
+    op_row_fn<double, S>(op, i, [&](int j, double (&v)[S]) { dir_row<S>(r, dinv, po, beta, mask, j, v); }, w);
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+      w[c] = -w[c];
+      acc[c] = fma(p[c], w[c], acc[c]);
+    }
+    store_row<double, S>(q + (size_t)i * S, w);
+  }
+  write_partial<S, NT>(acc, red, pout);
+}
+
+template <int S, int NT>
+__global__ __launch_bounds__(NT) void k_cg_upd(double* __restrict__ x, double* __restrict__ r,
+                                               const double* __restrict__ p, const double* __restrict__ q,
+                                               const double* __restrict__ dinv, CgIter* log, int it,
+                                               const double* state, const double* pin, int nparts, double* pout,
+                                               int* flag, int n) {
+  __shared__ double red[pow2_at_least(2 * S) * (NT / 64)];
+  reduce_partials<S, NT>(pin, nparts, red);
+  double alpha[S];
+#pragma unroll
+  for (int c = 0; c < S; ++c) {
+    const double sigma = uniform_d(red[c]);
+    const double rho = uniform_d(log[it].rho[c]);
+    const bool active = uniform_d(log[it].rr[c]) > uniform_d(state[c]);
+    alpha[c] = (active && sigma > 0.0) ? rho / sigma : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      log[it].sigma[c] = sigma;
+      log[it].alpha[c] = alpha[c];
+      if (active && !(sigma > 0.0)) flag[1] = it + 1;
+    }
+  }
+  __syncthreads();
+  double acc[2 * S];
+#pragma unroll
+  for (int c = 0; c < 2 * S; ++c) acc[c] = 0.0;
+  CG_ROWS(i, n) {
+    double xv[S], rv[S], pv[S], qv[S];
+    load_row<double, S>(x + (size_t)i * S, xv);
+    load_row<double, S>(r + (size_t)i * S, rv);
+    load_row<double, S>(p + (size_t)i * S, pv);
+    load_row<double, S>(q + (size_t)i * S, qv);
+    const double di = dinv[i];
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+      xv[c] = fma(alpha[c], pv[c], xv[c]);
+      rv[c] = fma(-alpha[c], qv[c], rv[c]);
+      acc[c] = fma(rv[c], rv[c] * di, acc[c]);
+      acc[S + c] = fma(rv[c], rv[c], acc[S + c]);
+    }
+    store_row<double, S>(x + (size_t)i * S, xv);
+    store_row<double, S>(r + (size_t)i * S, rv);
+  }
+  write_partial<2 * S, NT>(acc, red, pout);
+}
+
+// r = A x - B (the residual of (-A) x = -B); partials r^T r and B^T B.
+template <int S, int NT>
+__global__ __launch_bounds__(NT) void k_cg_true(OpDev<double> op, const double* __restrict__ B,
+                                                const double* __restrict__ x, double* __restrict__ r, int n,
+                                                double* pout) {
+  __shared__ double red[pow2_at_least(2 * S) * (NT / 64)];
+  double acc[2 * S];
+#pragma unroll
+  for (int c = 0; c < 2 * S; ++c) acc[c] = 0.0;
+  CG_ROWS(i, n) {
+    double w[S], bv[S];
+    op_row<double, S>(op, x, i, w);
+    load_row<double, S>(B + (size_t)i * S, bv);
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+      w[c] = w[c] - bv[c];
+      acc[c] = fma(w[c], w[c], acc[c]);
+      acc[S + c] = fma(bv[c], bv[c], acc[S + c]);
+    }
+    store_row<double, S>(r + (size_t)i * S, w);
+  }
+  write_partial<2 * S, NT>(acc, red, pout);
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_sum_partials(const double* pin, int nparts, double* out) {
+  __shared__ double red[pow2_at_least(K) * 4];
+  reduce_partials<K, 256>(pin, nparts, red);
+  if (threadIdx.x < K) out[threadIdx.x] = red[threadIdx.x];
+}
+
+// ------------------------------------------------------------------ host
+InnerCG::InnerCG(const OpDev<double>& op, int n, int S, int pc, double eta, int max_iter, hipStream_t st)
+    : op_(op), n_(n), S_(S), pc_(pc), max_iter_(max_iter), eta_(eta), st_(st) {
+  LYAP_REQUIRE(S == 1 || S == 2 || S == 4, LYAP_E_UNSUPPORTED, "inner CG supports 1, 2 or 4 right-hand sides");
+  LYAP_REQUIRE(pc == LYAP_PC_NONE || pc == LYAP_PC_JACOBI, LYAP_E_UNSUPPORTED,
+               "inner preconditioner %d is not available in this build", pc);
+  LYAP_REQUIRE(eta > 0.0 && eta < 1.0, LYAP_E_ARG, "inner_tol=%g must be in (0,1)", eta);
+  LYAP_REQUIRE(max_iter >= 1, LYAP_E_ARG, "inner_max_iter must be >= 1");
+  grid_ = stream_grid(n);
+  const size_t blk = (size_t)n * S * sizeof(double);
+  dinv_.alloc((size_t)n * sizeof(double));
+  r_.alloc(blk);
+  p0_.alloc(blk);
+  p1_.alloc(blk);
+  q_.alloc(blk);
+  partA_.alloc((size_t)kSGrid * 2 * S * sizeof(double));
+  partB_.alloc((size_t)kSGrid * 2 * S * sizeof(double));
+  log_.alloc((size_t)(max_iter + kCgChunk) * sizeof(CgIter));
+  state_.alloc(64 * sizeof(double));
+  tot_.alloc(64 * sizeof(double));
+  flag_.alloc(64);
+  hlog_.alloc((size_t)kCgChunk * sizeof(CgIter));
+  htot_.alloc(64 * sizeof(double) + 64);
+  LYAP_HIP(hipMemsetAsync(flag_.p, 0, 64, st_));
+  hipLaunchKernelGGL(k_cg_diag, dim3(grid_for(n, 1, 1024)), dim3(kBlock), 0, st_, op_, n_, pc_,
+                     dinv_.as<double>(), flag_.as<int>());
+  LYAP_LAUNCHED("k_cg_diag");
+  int hf[2] = {0, 0};
+  LYAP_HIP(hipMemcpyAsync(hf, flag_.p, sizeof(hf), hipMemcpyDeviceToHost, st_));
+  LYAP_HIP(hipStreamSynchronize(st_));
+  LYAP_REQUIRE(hf[0] == 0, LYAP_E_INDEFINITE, "A has a diagonal entry >= 0: not negative definite");
+}
+
+template <int S>
+static void cg_launch_init(const double* B, double* x, double* r, const double* dinv, int n, int mode, double* pout,
+                           int grid, hipStream_t st) {
+  constexpr int NT = stream_threads(S);
+  hipLaunchKernelGGL((k_cg_init<S, NT>), dim3(grid), dim3(NT), 0, st, B, x, r, dinv, n, mode, pout);
+  LYAP_LAUNCHED("k_cg_init");
+}
+
+template <int S>
+static void cg_launch_iter(const OpDev<double>& op, double* x, double* r, const double* dinv, const double* pold,
+                           double* pnew, double* q, CgIter* log, int it, int first, double* state, double eta2,
+                           double* partA, double* partB, int* flag, int n, int grid, hipStream_t st,
+                           KernelTimer* kt) {
+  constexpr int NT = stream_threads(S);
+  if (kt) kt->mark(LYAP_K_CG_DIR);
+  hipLaunchKernelGGL((k_cg_dir<S, NT>), dim3(grid), dim3(NT), 0, st, op, r, dinv, pold, pnew, q, log, it, first,
+                     state, eta2, partA, grid, partB, n);
+  LYAP_LAUNCHED("k_cg_dir");
+  if (kt) kt->mark(LYAP_K_CG_UPD);
+  hipLaunchKernelGGL((k_cg_upd<S, NT>), dim3(grid), dim3(NT), 0, st, x, r, pnew, q, dinv, log, it, state, partB,
+                     grid, partA, flag, n);
+  LYAP_LAUNCHED("k_cg_upd");
+}
+
+template <int S>
+static void cg_launch_true(const OpDev<double>& op, const double* B, const double* x, double* r, int n, double* part,
+                           double* tot, int grid, hipStream_t st) {
+  constexpr int NT = stream_threads(S);
+  hipLaunchKernelGGL((k_cg_true<S, NT>), dim3(grid), dim3(NT), 0, st, op, B, x, r, n, part);
+  LYAP_LAUNCHED("k_cg_true");
+  hipLaunchKernelGGL((k_sum_partials<2 * S>), dim3(1), dim3(256), 0, st, part, grid, tot);
+  LYAP_LAUNCHED("k_sum_partials");
+}
+
+void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
+  const auto t0 = Clock::now();
+  const int S = S_;
+  const double eta_rec = 0.5 * eta_;  // recursive target, so that the true residual passes
+  const double eta2 = eta_rec * eta_rec;
+  auto init = [&](int mode) {
+    switch (S) {
+      case 1: cg_launch_init<1>(B, X, r_.as<double>(), dinv_.as<double>(), n_, mode, partA_.as<double>(), grid_, st_); break;
+      case 2: cg_launch_init<2>(B, X, r_.as<double>(), dinv_.as<double>(), n_, mode, partA_.as<double>(), grid_, st_); break;
+      default: cg_launch_init<4>(B, X, r_.as<double>(), dinv_.as<double>(), n_, mode, partA_.as<double>(), grid_, st_); break;
+    }
+  };
+  auto iter = [&](int it, int first) {
+    double* pn = (it % 2 == 0) ? p0_.as<double>() : p1_.as<double>();
+    const double* po = (it % 2 == 0) ? p1_.as<double>() : p0_.as<double>();
+    CgIter* lg = log_.as<CgIter>();
+    switch (S) {
+      case 1: cg_launch_iter<1>(op_, X, r_.as<double>(), dinv_.as<double>(), po, pn, q_.as<double>(), lg, it, first,
+                                state_.as<double>(), eta2, partA_.as<double>(), partB_.as<double>(), flag_.as<int>(),
+                                n_, grid_, st_, kt); break;
+      case 2: cg_launch_iter<2>(op_, X, r_.as<double>(), dinv_.as<double>(), po, pn, q_.as<double>(), lg, it, first,
+                                state_.as<double>(), eta2, partA_.as<double>(), partB_.as<double>(), flag_.as<int>(),
+                                n_, grid_, st_, kt); break;
+      default: cg_launch_iter<4>(op_, X, r_.as<double>(), dinv_.as<double>(), po, pn, q_.as<double>(), lg, it, first,
+                                 state_.as<double>(), eta2, partA_.as<double>(), partB_.as<double>(), flag_.as<int>(),
+                                 n_, grid_, st_, kt); break;
+    }
+  };
+  auto true_res = [&]() {
+    switch (S) {
+      case 1: cg_launch_true<1>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), grid_, st_); break;
+      case 2: cg_launch_true<2>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), grid_, st_); break;
+      default: cg_launch_true<4>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), grid_, st_); break;
+    }
+  };
+
+  int total = 0;
+  double worst = 0.0;
+  for (int start = 0; start <= kCgRestarts; ++start) {
+    init(start == 0 ? 0 : 1);
+    int it = 0;
+    bool done = false;
+    while (!done && total + it < max_iter_) {
+      const int it0 = it;
+      const int cnt = std::min(kCgChunk, max_iter_ - total - it);
+      for (int c = 0; c < cnt; ++c) iter(it++, start == 0 ? 1 : 0);
+      kt ? kt->collect() : (void)0;
+      LYAP_HIP(hipMemcpyAsync(hlog_.p, log_.as<CgIter>() + it0, (size_t)cnt * sizeof(CgIter), hipMemcpyDeviceToHost,
+                              st_));
+      LYAP_HIP(hipMemcpyAsync(htot_.as<char>() + 64 * sizeof(double), flag_.p, 8, hipMemcpyDeviceToHost, st_));
+      LYAP_HIP(hipMemcpyAsync(htot_.p, state_.p, S * sizeof(double), hipMemcpyDeviceToHost, st_));
+      LYAP_HIP(hipStreamSynchronize(st_));
+      const int* hf = reinterpret_cast<const int*>(htot_.as<char>() + 64 * sizeof(double));
+      LYAP_REQUIRE(hf[1] == 0, LYAP_E_INNER, "inner CG breakdown (p^T A p <= 0) at iteration %d", hf[1]);
+      const double* thr = htot_.as<double>();
+      const CgIter* lg = hlog_.as<CgIter>();
+      for (int c = 0; c < cnt && !done; ++c) {
+        bool all = true;
+        for (int k = 0; k < S; ++k) {
+          LYAP_REQUIRE(std::isfinite(lg[c].rr[k]), LYAP_E_NUMERIC, "inner CG produced a non-finite residual");
+          if (lg[c].rr[k] > thr[k]) all = false;
+        }
+        if (all) {
+          done = true;
+          it = it0 + c;  // iterations that changed x
+        }
+      }
+    }
+    total += it;
+    true_res();
+    LYAP_HIP(hipMemcpyAsync(htot_.p, tot_.p, 2 * S * sizeof(double), hipMemcpyDeviceToHost, st_));
+    LYAP_HIP(hipStreamSynchronize(st_));
+    const double* h = htot_.as<double>();
+    worst = 0.0;
+    for (int k = 0; k < S; ++k) {
+      const double rel = h[S + k] > 0.0 ? std::sqrt(h[k] / h[S + k]) : 0.0;
+      LYAP_REQUIRE(std::isfinite(rel), LYAP_E_NUMERIC, "inner solve produced non-finite values");
+      worst = std::max(worst, rel);
+    }
+    if (worst <= eta_) {
+      stats_.iters += total;
+      stats_.solves += 1;
+      stats_.restarts += start;
+      stats_.worst_relres = std::max(stats_.worst_relres, worst);
+      stats_.ms += ms_since(t0);
+      return;
+    }
+    if (total >= max_iter_) break;
+  }
+  stats_.iters += total;
+  stats_.worst_relres = std::max(stats_.worst_relres, worst);
+  LYAP_REQUIRE(false, LYAP_E_INNER, "inner CG did not reach the true relative residual %.1e in %d iterations", eta_,
+               total);
+}
+
+template <int S>
+__global__ void k_pack_cols(const double* __restrict__ B, int64_t ldb, int n, double* __restrict__ out) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    double v[S];
+#pragma unroll
+    for (int c = 0; c < S; ++c) v[c] = B[(size_t)c * ldb + r];
+    store_row<double, S>(out + (size_t)r * S, v);
+  }
+}
+
+template <int S>
+__global__ void k_unpack_cols(const double* __restrict__ in, int n, double* __restrict__ X, int64_t ldx) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    double v[S];
+    load_row<double, S>(in + (size_t)r * S, v);
+#pragma unroll
+    for (int c = 0; c < S; ++c) X[(size_t)c * ldx + r] = v[c];
+  }
+}
+
+}  // namespace lyap
+
+extern "C" lyap_status lyap_inner_solve(const lyap_op* A, const double* B, int64_t ldb, double* X, int64_t ldx,
+                                        int32_t s, const lyap_opts* opts, int64_t* iters, double* relres) {
+  using namespace lyap;
+  clear_error();
+  lyap_opts o;
+  if (opts) o = *opts;
+  else lyap_opts_default(&o);
+  try {
+    validate_op(A);
+    LYAP_REQUIRE(B != nullptr && X != nullptr, LYAP_E_ARG, "B or X is NULL");
+    LYAP_REQUIRE(s == 1 || s == 2 || s == 4, LYAP_E_UNSUPPORTED, "s=%d: the inner solver takes 1, 2 or 4 columns", s);
+    LYAP_REQUIRE(ldb >= A->n && ldx >= A->n, LYAP_E_ARG, "leading dimension below n");
+    hipStream_t st = (hipStream_t)o.stream;
+    const int n = (int)A->n;
+    OpHolder<double> op;
+    make_op_f64(A, op, st);
+    InnerCG cg(op.dev, n, s, o.inner_pc, o.inner_tol, o.inner_max_iter, st);
+    DevBuf Bi((size_t)n * s * sizeof(double)), Xi((size_t)n * s * sizeof(double));
+    const int g = grid_for(n, 1, 1024);
+    auto pack = [&]() {
+      switch (s) {
+        case 1: hipLaunchKernelGGL((k_pack_cols<1>), dim3(g), dim3(kBlock), 0, st, B, ldb, n, Bi.as<double>()); break;
+        case 2: hipLaunchKernelGGL((k_pack_cols<2>), dim3(g), dim3(kBlock), 0, st, B, ldb, n, Bi.as<double>()); break;
+        default: hipLaunchKernelGGL((k_pack_cols<4>), dim3(g), dim3(kBlock), 0, st, B, ldb, n, Bi.as<double>()); break;
+      }
+      LYAP_LAUNCHED("k_pack_cols");
+    };
+    auto unpack = [&]() {
+      switch (s) {
+        case 1: hipLaunchKernelGGL((k_unpack_cols<1>), dim3(g), dim3(kBlock), 0, st, Xi.as<double>(), n, X, ldx); break;
+        case 2: hipLaunchKernelGGL((k_unpack_cols<2>), dim3(g), dim3(kBlock), 0, st, Xi.as<double>(), n, X, ldx); break;
+        default: hipLaunchKernelGGL((k_unpack_cols<4>), dim3(g), dim3(kBlock), 0, st, Xi.as<double>(), n, X, ldx); break;
+      }
+      LYAP_LAUNCHED("k_unpack_cols");
+    };
+    pack();
+    lyap_status status = LYAP_OK;
+    try {
+      cg.solve(Bi.as<double>(), Xi.as<double>());
+    } catch (const Error& e) {
+      if (e.st != LYAP_E_INNER) throw;
+      status = LYAP_E_INNER;
+    }
+    unpack();
+    LYAP_HIP(hipStreamSynchronize(st));
+    if (iters) *iters = cg.stats().iters;
+    if (relres) *relres = cg.stats().worst_relres;
+    return status;
+  } catch (const Error& e) {
+    return e.st;
+  }
+}

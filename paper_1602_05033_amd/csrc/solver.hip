@@ -24,7 +24,7 @@ extern "C" void lyap_opts_default(lyap_opts* o) {
   o->storage = LYAP_STORE_F64;
   o->two_pass = 1;
   o->trunc_eps = -1.0;
-  o->inner_pc = LYAP_PC_IC0;
+  o->inner_pc = LYAP_PC_JACOBI;
   o->inner_tol = 1e-12;
   o->inner_max_iter = 5000;
   o->flush_blocks = 0;
