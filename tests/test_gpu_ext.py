@@ -190,3 +190,47 @@ def test_ek_lucky_breakdown_eigenvector(lib):
     dop = b.device_op(op)
     sol = b.lyap_solve(dop, _dev(v), method=b.METHOD_EXT, raise_on_error=False)
     assert sol.status == b.E_BREAKDOWN
+
+
+def _explicit_residual_gpu(b, dop, Z, C):
+    """||A Z Z^T + Z Z^T A + C C^T||_F from a QR of [AZ, Z, C] (FP64, torch on the device)."""
+    n, t = Z.shape
+    AZ = torch.empty_like(Z)
+    for c0 in range(0, t, 8):
+        AZ[:, c0:c0 + 8] = b.op_apply(dop, Z[:, c0:c0 + 8].contiguous(), b.STORE_F64)
+    P = torch.cat([AZ, Z, C], dim=1)
+    R = torch.linalg.qr(P, mode="r")[1]
+    s = C.shape[1]
+    Phi = torch.zeros(2 * t + s, 2 * t + s, dtype=torch.float64, device=Z.device)
+    Phi[:t, t:2 * t] = torch.eye(t, dtype=torch.float64, device=Z.device)
+    Phi[t:2 * t, :t] = torch.eye(t, dtype=torch.float64, device=Z.device)
+    Phi[2 * t:, 2 * t:] = torch.eye(s, dtype=torch.float64, device=Z.device)
+    return float(torch.linalg.norm(R @ Phi @ R.T))
+
+
+def test_ek_full_size_100cubed(lib):
+    """The full-size extended Krylov configuration: 100^3 cells, lognormal k
+    (sigma 1), s = 1, n = 1e6, the launch configuration bench.py times.  The
+    oracle cannot run here, so: convergence by Proposition 1, the explicit
+    FP64 residual of the returned Z agrees with it, T_m is banded symmetric
+    negative definite (Ritz values < 0) and every inner solve was certified."""
+    b = _b()
+    op = fv3d(100, 1.0, 3)
+    C = gaussian_C(op.n, 1, 3)
+    dop = b.device_op(op)
+    Cd = _dev(C)
+    sol = b.lyap_solve(dop, Cd, method=b.METHOD_EXT, tol=1e-8, check_every=0, inner_pc=b.PC_JACOBI,
+                       inner_tol=1e-12, want_T=True)
+    assert sol.status == b.OK and sol.res <= 1e-8
+    assert 30 <= sol.m <= 70 and sol.n_inner == sol.m + 1
+    ex = _explicit_residual_gpu(b, dop, sol.Z, Cd) / sol.beta ** 2
+    assert ex <= 2e-8, ex
+    # T_m symmetric negative definite: dense from the band
+    k = sol.T_band.shape[0]
+    ell = sol.T_band.shape[1] - 1
+    T = np.zeros((k, k))
+    for c in range(k):
+        for d in range(ell + 1):
+            if c + d < k:
+                T[c + d, c] = T[c, c + d] = sol.T_band[c, d]
+    assert np.linalg.eigvalsh(T).max() < 0.0
