@@ -214,7 +214,9 @@ lyap_status lyap_solve(const lyap_op* A, const double* C, int32_t s, int64_t ldc
 
 typedef struct sylv_result {
   int32_t status;
-  int32_t m, t;
+  int32_t m, t;        /* blocks per space, rank of Z1 Z2^T                */
+  int32_t s, ell;
+  int32_t owns_Z;      /* 1: Z1/Z2 from hipMalloc, freed by sylv_result_free */
   int64_t n1, n2;
   double* Z1;          /* device, n1 x t column-major */
   double* Z2;          /* device, n2 x t column-major */
@@ -222,8 +224,20 @@ typedef struct sylv_result {
   int32_t* hist_m;
   double* hist_res;    /* ||R_m||_F / (||C1||_F ||C2||_F) */
   double res;
+  double beta1, beta2; /* ||C1||_F, ||C2||_F */
+  double trunc_eps;    /* absolute threshold used for ||Y~ - Y1 Y2^T||_F */
   double times_ms[8];
   int32_t n_checks;
+  /* opts->want_T: host copies (band layout and column-major as in lyap_result) */
+  double* T_band;      /* (ell+1) x k, T_m = V_m^T A V_m */
+  double* J_band;      /* (ell+1) x k, J_m = U_m^T B U_m */
+  double* gamma1;      /* ell x ell */
+  double* gamma2;
+  double* tau;         /* tau_{m+1,m} */
+  double* iota;        /* iota_{m+1,m} */
+  double kern_ms[12];
+  int32_t kern_n[12];
+  double kern_bytes[12];
 } sylv_result;
 
 /*

@@ -62,10 +62,16 @@ class LyapResult(ct.Structure):
 
 
 class SylvResult(ct.Structure):
-    _fields_ = [("status", ct.c_int32), ("m", ct.c_int32), ("t", ct.c_int32), ("n1", ct.c_int64),
+    _fields_ = [("status", ct.c_int32), ("m", ct.c_int32), ("t", ct.c_int32), ("s", ct.c_int32),
+                ("ell", ct.c_int32), ("owns_Z", ct.c_int32), ("n1", ct.c_int64),
                 ("n2", ct.c_int64), ("Z1", ct.c_void_p), ("Z2", ct.c_void_p), ("n_hist", ct.c_int32),
                 ("hist_m", ct.POINTER(ct.c_int32)), ("hist_res", ct.POINTER(ct.c_double)),
-                ("res", ct.c_double), ("times_ms", ct.c_double * 8), ("n_checks", ct.c_int32)]
+                ("res", ct.c_double), ("beta1", ct.c_double), ("beta2", ct.c_double), ("trunc_eps", ct.c_double),
+                ("times_ms", ct.c_double * 8), ("n_checks", ct.c_int32),
+                ("T_band", ct.POINTER(ct.c_double)), ("J_band", ct.POINTER(ct.c_double)),
+                ("gamma1", ct.POINTER(ct.c_double)), ("gamma2", ct.POINTER(ct.c_double)),
+                ("tau", ct.POINTER(ct.c_double)), ("iota", ct.POINTER(ct.c_double)),
+                ("kern_ms", ct.c_double * 12), ("kern_n", ct.c_int32 * 12), ("kern_bytes", ct.c_double * 12)]
 
 
 # exported symbols declared in include/lyap.h
@@ -335,3 +341,80 @@ def inner_solve(dop: DeviceOp, B, raise_on_error: bool = True, **kw):
     if raise_on_error and st != OK:
         raise LyapError(st, lib.lyap_last_error().decode())
     return Xcm.t(), iters.value, rel.value, st
+
+
+@dataclass
+class SylvSolution:
+    status: int
+    Z1: object
+    Z2: object
+    m: int
+    t: int
+    beta1: float
+    beta2: float
+    res: float
+    hist_m: list
+    hist_res: list
+    times_ms: dict
+    n_checks: int
+    trunc_eps: float
+    T_band: Optional[np.ndarray] = None
+    J_band: Optional[np.ndarray] = None
+    gamma1: Optional[np.ndarray] = None
+    gamma2: Optional[np.ndarray] = None
+    tau: Optional[np.ndarray] = None
+    iota: Optional[np.ndarray] = None
+    kernels: dict = field(default_factory=dict)
+    error: str = ""
+
+
+def sylv_solve(dopA: DeviceOp, dopB: DeviceOp, C1, C2, raise_on_error: bool = True, **kw) -> SylvSolution:
+    """Solve A X + X B + C1 C2^T = 0; C1 (n1, s), C2 (n2, s) float64 torch
+    tensors on the device.  Returns Z1 (n1, t), Z2 (n2, t) with Z1 Z2^T ~ X."""
+    import torch
+    lib = load()
+    n1, s = C1.shape
+    n2, s2 = C2.shape
+    assert s == s2 and n1 == dopA.n and n2 == dopB.n
+    assert C1.dtype == torch.float64 and C2.dtype == torch.float64 and C1.is_cuda and C2.is_cuda
+    C1cm = C1.t().contiguous()
+    C2cm = C2.t().contiguous()
+    alloc = _TorchAllocator(C1.device)
+    o = make_opts(stream=torch.cuda.current_stream(C1.device).cuda_stream, **kw)
+    o.alloc, o.release = alloc.alloc_cb, alloc.free_cb
+    r = SylvResult()
+    st = lib.sylv_solve(ct.byref(dopA.c), ct.byref(dopB.c), ct.c_void_p(C1cm.data_ptr()), n1,
+                        ct.c_void_p(C2cm.data_ptr()), n2, s, ct.byref(o), ct.byref(r))
+    msg = lib.lyap_last_error().decode()
+    try:
+        if raise_on_error and st not in (OK, NOT_CONVERGED):
+            raise LyapError(st, msg)
+        Z1 = Z2 = None
+        if r.Z1 and r.Z2:
+            b1 = alloc.take(r.Z1)
+            b2 = alloc.take(r.Z2)
+            if r.t > 0:
+                Z1 = b1[: 8 * n1 * r.t].view(torch.float64).view(r.t, n1).t()
+                Z2 = b2[: 8 * n2 * r.t].view(torch.float64).view(r.t, n2).t()
+            else:
+                Z1 = torch.zeros((n1, 0), dtype=torch.float64, device=C1.device)
+                Z2 = torch.zeros((n2, 0), dtype=torch.float64, device=C1.device)
+        ell = r.ell
+        k = ell * r.m
+        sol = SylvSolution(
+            status=st, Z1=Z1, Z2=Z2, m=r.m, t=r.t, beta1=r.beta1, beta2=r.beta2, res=r.res,
+            hist_m=[r.hist_m[i] for i in range(r.n_hist)], hist_res=[r.hist_res[i] for i in range(r.n_hist)],
+            times_ms={k_: r.times_ms[i] for i, k_ in enumerate(TIME_KEYS)}, n_checks=r.n_checks,
+            trunc_eps=r.trunc_eps,
+            kernels={name: {"ms": r.kern_ms[i], "n": r.kern_n[i], "bytes_per_launch": r.kern_bytes[i]}
+                     for i, name in enumerate(KERNEL_KINDS) if r.kern_n[i] > 0})
+        if r.T_band:
+            sol.T_band = np.ctypeslib.as_array(r.T_band, shape=(k * (ell + 1),)).copy().reshape(k, ell + 1)
+            sol.J_band = np.ctypeslib.as_array(r.J_band, shape=(k * (ell + 1),)).copy().reshape(k, ell + 1)
+            for name in ("gamma1", "gamma2", "tau", "iota"):
+                setattr(sol, name, np.ctypeslib.as_array(getattr(r, name), shape=(ell * ell,)).copy()
+                        .reshape(ell, ell, order="F"))
+        sol.error = msg
+        return sol
+    finally:
+        lib.sylv_result_free(ct.byref(r))

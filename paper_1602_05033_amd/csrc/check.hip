@@ -48,12 +48,16 @@ void Checker::eig_dc(const double* band, int k) {
   static_cast<DcWork*>(dc_)->run(band, ell_ + 1, k, lam_.as<double>(), F_.as<double>(), L_.as<double>());
 }
 
-void Checker::run(const double* band, int k, const double* gamma, const double* tau, CheckOut* dev_out) {
+void Checker::prepare(const double* band, int k, const double* gamma, const double* tau) {
   ensure(k);
   k_ = k;
   if (k <= kDenseMax) eig_jacobi(band, k);
   else eig_dc(band, k);
   launch_gw(F_.as<double>(), k, L_.as<double>(), k, k, ell_, nt_, gamma, tau, g_.as<double>(), Wm_.as<double>(), st_);
+}
+
+void Checker::run(const double* band, int k, const double* gamma, const double* tau, CheckOut* dev_out) {
+  prepare(band, k, gamma, tau);
   launch_ctri_sum(lam_.as<double>(), g_.as<double>(), Wm_.as<double>(), k, ell_, nt_, part_.as<double>(),
                   counter_.as<unsigned>(), dev_out, st_);
 }

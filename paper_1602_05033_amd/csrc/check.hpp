@@ -13,6 +13,11 @@ class Checker {
   // band: device, (ell+1) x k lower band (ld = ell+1), gamma: device ell x ell
   // row-major, tau: device nt x ell row-major.  Result lands in *dev_out.
   void run(const double* band, int k, const double* gamma, const double* tau, CheckOut* dev_out);
+  // Eigenvalues, g = (E_1^T Q)^T gamma and W_m = (E_m^T Q)^T tau^T only (the
+  // inputs of the Sylvester residual, which couples two such spaces).
+  void prepare(const double* band, int k, const double* gamma, const double* tau);
+  const double* Wm() const { return Wm_.as<double>(); }
+  int nt() const { return nt_; }
   const double* lam() const { return lam_.as<double>(); }
   const double* g() const { return g_.as<double>(); }
   int k() const { return k_; }

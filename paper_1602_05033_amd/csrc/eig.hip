@@ -626,6 +626,13 @@ void launch_shift_solve(const double* band, int ldb, int ell, int k, const doubl
   LYAP_LAUNCHED("shift_solve");
 }
 
+void launch_gemm_xb(const double* X, int k, int tp, const double* B, int t, double* M, hipStream_t st) {
+  const int64_t tot = (int64_t)k * t;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 8192));
+  hipLaunchKernelGGL(k_gemm_xb, dim3(grid), dim3(256), 0, st, X, k, tp, B, t, M);
+  LYAP_LAUNCHED("gemm_xb");
+}
+
 void launch_assemble_M(const double* Lc, int k, const int* piv, int tp, const double* Qg, int t, const double* X,
                        double* V1, double* B, double* M, hipStream_t st) {
   int64_t tot = (int64_t)tp * t;

@@ -28,6 +28,8 @@ void launch_gram_cols(const double* Lc, int k, int tp, double* G, hipStream_t st
 void launch_shift_solve(const double* band, int ldb, int ell, int k, const double* lam, const double* g,
                         const double* gamma, const int* piv, int tp, double* Lb, double* X, int* fail,
                         hipStream_t st);
+// M (k x t, row-major) = X (k x tp, column-major) B (tp x t, row-major).
+void launch_gemm_xb(const double* X, int k, int tp, const double* B, int t, double* M, hipStream_t st);
 void launch_assemble_M(const double* Lc, int k, const int* piv, int tp, const double* Qg, int t, const double* X,
                        double* V1, double* B, double* M, hipStream_t st);
 

@@ -10,6 +10,7 @@
 
 #include "check.hpp"
 #include "lanczos.hpp"
+#include "side.hpp"
 #include "solver.hpp"
 
 using namespace lyap;
@@ -96,10 +97,155 @@ double* alloc_output(const lyap_opts& o, size_t bytes, bool* owned) {
   return (double*)p;
 }
 
-static void rowmajor_to_colmajor(const double* rm, int rows, int cols, double* cm) {
+void rowmajor_to_colmajor(const double* rm, int rows, int cols, double* cm) {
   for (int i = 0; i < rows; ++i)
     for (int j = 0; j < cols; ++j) cm[i + (size_t)j * rows] = rm[(size_t)i * cols + j];
 }
+
+// Algorithmic HBM bytes per launch of the streaming kernels (per-row model).
+template <typename T>
+void fill_kernel_bytes(int n, int S, double coef, const KernelTimer& kt, double zflush_bytes, double* kb) {
+  const double nsb = (double)n * S * sizeof(T);
+  kb[LYAP_K_SPMM_GRAM] = 3.0 * nsb + coef * n;
+  kb[LYAP_K_UPD_GRAM] = 3.75 * nsb;
+  kb[LYAP_K_CHOL_GRAM] = 1.0 * nsb;
+  kb[LYAP_K_CHOL_STORE] = 2.0 * nsb;
+  kb[LYAP_K_REPLAY] = 3.0 * nsb + coef * n;
+  kb[LYAP_K_ZFLUSH] = kt.n[LYAP_K_ZFLUSH] > 0 ? zflush_bytes / kt.n[LYAP_K_ZFLUSH] : 0.0;
+}
+template void fill_kernel_bytes<float>(int, int, double, const KernelTimer&, double, double*);
+template void fill_kernel_bytes<double>(int, int, double, const KernelTimer&, double, double*);
+
+// -------------------------------------------------------------- one Krylov space
+template <typename T>
+LanczosSide<T>::LanczosSide(const lyap_op* A, const double* C, int S, int64_t ldc, int max_iter, bool two_pass,
+                            hipStream_t st, KernelTimer* kt)
+    : C_(C), ldc_(ldc), n_((int)A->n), S_(S), maxit_(max_iter), two_pass_(two_pass), st_(st), kt_(kt) {
+  if constexpr (std::is_same_v<T, double>) make_op_f64(A, op_, st);
+  else make_op_f32(A, op_, st);
+  blk_ = (size_t)n_ * S * sizeof(T);
+  LS_ = log_stride(S);
+  grid_ = stream_grid(n_);
+  Vb0_.alloc(blk_);
+  Vb1_.alloc(blk_);
+  Wb_.alloc(blk_);
+  zero_.alloc(blk_);
+  logb_.alloc(((size_t)maxit_ + 1) * LS_ * sizeof(double));
+  glog_.alloc(LS_ * sizeof(double));
+  band_.alloc((size_t)(S + 1) * S * (maxit_ + 2) * sizeof(double));
+  partA_.alloc((size_t)kSGrid * S * S * sizeof(double));
+  partB_.alloc((size_t)kSGrid * S * S * sizeof(double));
+  flags_.alloc(64);
+  hflags_.alloc(64);
+  LYAP_HIP(hipMemsetAsync(flags_.p, 0, 64, st_));
+  LYAP_HIP(hipMemsetAsync(zero_.p, 0, blk_, st_));
+  LYAP_HIP(hipMemsetAsync(Vb0_.p, 0, blk_, st_));
+  LYAP_HIP(hipMemsetAsync(band_.p, 0, band_.bytes, st_));
+}
+
+template <typename T>
+void LanczosSide<T>::init() {
+  T* V1p = two_pass_ ? Vb1_.as<T>() : nullptr;
+  if (!two_pass_) {
+    stored_.emplace_back(blk_);
+    V1p = stored_.back().as<T>();
+  }
+  if (kt_) kt_->mark(LYAP_K_INIT);
+  launch_init<T>(C_, ldc_, n_, S_, glog_.as<double>(), partA_.as<double>(), partB_.as<double>(), flags_.as<int>(),
+                 V1p, grid_, st_);
+  hglog_.assign(LS_, 0.0);
+  LYAP_HIP(hipMemcpyAsync(hglog_.data(), glog_.p, LS_ * sizeof(double), hipMemcpyDeviceToHost, st_));
+  LYAP_HIP(hipMemcpyAsync(hflags_.p, flags_.p, 64, hipMemcpyDeviceToHost, st_));
+  LYAP_HIP(hipStreamSynchronize(st_));
+  const int* f = hflags_.as<int>();
+  const double trC = hglog_[L_FLAG * S_ * S_ + 1];
+  LYAP_REQUIRE(f[1] == 0 && std::isfinite(trC), LYAP_E_NUMERIC, "C contains NaN or Inf");
+  LYAP_REQUIRE(trC > 0.0, LYAP_E_ARG, "C is zero");
+  LYAP_REQUIRE(f[0] == 0, LYAP_E_BREAKDOWN, "C is numerically rank deficient (deflation not implemented)");
+  beta_ = std::sqrt(trC);
+  Vprev_ = two_pass_ ? Vb0_.as<T>() : zero_.as<T>();
+  Vcur_ = V1p;
+}
+
+template <typename T>
+void LanczosSide<T>::step() {
+  T* Vnext;
+  if (two_pass_) {
+    Vnext = Vprev_;  // V_{j+1} overwrites V_{j-1}
+  } else {
+    stored_.emplace_back(blk_);
+    Vnext = stored_.back().as<T>();
+  }
+  StepArgs<T> sa{};
+  sa.op = op_.dev;
+  sa.n = n_;
+  sa.W = Wb_.as<T>();
+  sa.band = band_.as<double>();
+  sa.flags = flags_.as<int>();
+  sa.Vprev = Vprev_;
+  sa.Vcur = Vcur_;
+  sa.Vnext = Vnext;
+  sa.log = logb_.as<double>() + (size_t)m_ * LS_;
+  sa.j = m_;
+  launch_step<T>(sa, S_, grid_, partA_.as<double>(), partB_.as<double>(), st_, kt_);
+  ++m_;
+  Vprev_ = Vcur_;
+  Vcur_ = Vnext;
+}
+
+template <typename T>
+void LanczosSide<T>::read_flags(int* breakdown, int* nonfinite) {
+  LYAP_HIP(hipMemcpyAsync(hflags_.p, flags_.p, 64, hipMemcpyDeviceToHost, st_));
+  LYAP_HIP(hipStreamSynchronize(st_));
+  *breakdown = hflags_.as<int>()[0];
+  *nonfinite = hflags_.as<int>()[1];
+}
+
+template <typename T>
+void LanczosSide<T>::accumulate_Z(int m, const double* Mrows, int t, double* Z, int64_t ldz, double* bytes_out) {
+  const int S = S_;
+  const int n = n_;
+  double zbytes = 0.0;
+  if (t > 0) {
+    LYAP_HIP(hipMemsetAsync(Z, 0, (size_t)ldz * t * sizeof(double), st_));
+    const int QB = zflush_max_blocks(S);
+    if (two_pass_) {
+      const int R = QB + 2;
+      std::vector<DevBuf> ring;
+      for (int i = 0; i < R; ++i) ring.emplace_back(blk_);
+      launch_init_store<T>(C_, ldc_, n, S, glog_.as<double>(), ring[0].as<T>(), grid_, st_);
+      std::vector<const void*> pend;
+      int first = 0;
+      for (int i = 0; i < m; ++i) {
+        if (i + 1 < m) {
+          const T* vp = i > 0 ? ring[(i - 1) % R].as<T>() : zero_.as<T>();
+          if (kt_) kt_->mark(LYAP_K_REPLAY);
+          launch_replay<T>(op_.dev, S, vp, ring[i % R].as<T>(), ring[(i + 1) % R].as<T>(),
+                           logb_.as<double>() + (size_t)i * LS_, grid_, st_);
+        }
+        if (pend.empty()) first = i;
+        pend.push_back(ring[i % R].p);
+        if ((int)pend.size() == QB || i == m - 1) {
+          if (kt_) kt_->mark(LYAP_K_ZFLUSH);
+          zbytes += (double)pend.size() * blk_ + 2.0 * n * t * sizeof(double);
+          launch_zflush<T>(pend.data(), (int)pend.size(), n, S, Mrows + (size_t)first * S * t, t, Z, ldz, 0, st_);
+          pend.clear();
+        }
+      }
+      LYAP_HIP(hipStreamSynchronize(st_));  // the ring is released on return
+    } else {
+      std::vector<const void*> ptrs;
+      for (int i = 0; i < m; ++i) ptrs.push_back(stored_[i].p);
+      if (kt_) kt_->mark(LYAP_K_ZFLUSH);
+      zbytes += (double)m * blk_ + 2.0 * n * t * sizeof(double) * ((m + QB - 1) / QB);
+      launch_zflush<T>(ptrs.data(), m, n, S, Mrows, t, Z, ldz, 0, st_);
+    }
+  }
+  if (bytes_out) *bytes_out += zbytes;
+}
+
+template class LanczosSide<float>;
+template class LanczosSide<double>;
 
 // -------------------------------------------------------------- standard Krylov
 template <typename T>
@@ -110,60 +256,18 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   out->n = n;
   out->s = S;
   out->ell = S;
-  OpHolder<T> op;
-  if constexpr (std::is_same_v<T, double>) make_op_f64(A, op, st);
-  else make_op_f32(A, op, st);
-
   const int maxit = o.max_iter;
-  const size_t blk = (size_t)n * S * sizeof(T);
-  const size_t LS = log_stride(S);  // log doubles per step
-  const int grid = stream_grid(n);
-  const int zgrid = grid_for(n, 1, 1024);
-
-  DevBuf Vb0(blk), Vb1(blk), Wb(blk), zero(blk);
-  DevBuf logb(((size_t)maxit + 1) * LS * sizeof(double));
-  DevBuf glog(LS * sizeof(double));
-  DevBuf band((size_t)(S + 1) * S * (maxit + 2) * sizeof(double));
-  DevBuf partA((size_t)kSGrid * S * S * sizeof(double)), partB((size_t)kSGrid * S * S * sizeof(double));
-  DevBuf flags(64);
-  DevBuf chk(sizeof(CheckOut));
-  HostBuf hchk(sizeof(CheckOut));
-  HostBuf hflags(64);
-  LYAP_HIP(hipMemsetAsync(flags.p, 0, 64, st));
-  LYAP_HIP(hipMemsetAsync(zero.p, 0, blk, st));
-  LYAP_HIP(hipMemsetAsync(Vb0.p, 0, blk, st));
-  LYAP_HIP(hipMemsetAsync(band.p, 0, band.bytes, st));
-
-  // stored-basis mode keeps every block
-  std::vector<DevBuf> stored;
-  const bool two_pass = o.two_pass != 0;
-
-  // V_1 gamma = C  (CholQR2 of C)
-  T* V1p = two_pass ? Vb1.as<T>() : nullptr;
-  if (!two_pass) {
-    stored.emplace_back(blk);
-    V1p = stored.back().as<T>();
-  }
-  launch_init<T>(C, ldc, n, S, glog.as<double>(), partA.as<double>(), partB.as<double>(), flags.as<int>(), V1p,
-                 grid, st);
-  std::vector<double> hglog(LS);
-  LYAP_HIP(hipMemcpyAsync(hglog.data(), glog.p, LS * sizeof(double), hipMemcpyDeviceToHost, st));
-  LYAP_HIP(hipMemcpyAsync(hflags.p, flags.p, 64, hipMemcpyDeviceToHost, st));
-  LYAP_HIP(hipStreamSynchronize(st));
-  {
-    const int* f = hflags.as<int>();
-    const double trC = hglog[L_FLAG * S * S + 1];
-    LYAP_REQUIRE(f[1] == 0 && std::isfinite(trC), LYAP_E_NUMERIC, "C contains NaN or Inf");
-    LYAP_REQUIRE(trC > 0.0, LYAP_E_ARG, "C is zero");
-    LYAP_REQUIRE(f[0] == 0, LYAP_E_BREAKDOWN, "C is numerically rank deficient (deflation not implemented)");
-    out->beta = std::sqrt(trC);
-  }
-  const double beta2 = out->beta * out->beta;
-  const double* gamma_dev = glog.as<double>() + L_R * S * S;
-
   KernelTimer kt;
   kt.st = st;
   kt.on = o.profile != 0;
+  LanczosSide<T> side(A, C, S, ldc, maxit, o.two_pass != 0, st, &kt);
+  DevBuf chk(sizeof(CheckOut));
+  HostBuf hchk(sizeof(CheckOut));
+
+  side.init();
+  out->beta = side.beta();
+  const double beta2 = out->beta * out->beta;
+
   Checker ck(S, S, st);
   CheckSchedule sched{o.check_every, maxit};
   std::vector<int> hm;
@@ -177,21 +281,10 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   int checked_m = 0;
   double t_to_tol = 0.0;
 
-  T* Vprev = two_pass ? Vb0.as<T>() : zero.as<T>();
-  T* Vcur = V1p;
-
-  StepArgs<T> sa{};
-  sa.op = op.dev;
-  sa.n = n;
-  sa.W = Wb.as<T>();
-  sa.band = band.as<double>();
-  sa.flags = flags.as<int>();
-
   auto run_check = [&](int mm) {
     const auto t0 = Clock::now();
-    const double* tau_dev = logb.as<double>() + (size_t)(mm - 1) * LS + L_R * S * S;
     kt.mark(LYAP_K_CHECK);
-    ck.run(band.as<double>(), mm * S, gamma_dev, tau_dev, chk.as<CheckOut>());
+    ck.run(side.band(), mm * S, side.gamma_dev(), side.tau_dev(mm), chk.as<CheckOut>());
     kt.collect();
     LYAP_HIP(hipMemcpyAsync(hchk.p, chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, st));
     LYAP_HIP(hipStreamSynchronize(st));
@@ -205,33 +298,18 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
 
   const auto t_pass1 = Clock::now();
   while (m < maxit) {
-    T* Vnext;
-    if (two_pass) {
-      Vnext = Vprev;  // V_{j+1} overwrites V_{j-1}
-    } else {
-      stored.emplace_back(blk);
-      Vnext = stored.back().as<T>();
-    }
-    sa.Vprev = Vprev;
-    sa.Vcur = Vcur;
-    sa.Vnext = Vnext;
-    sa.log = logb.as<double>() + (size_t)m * LS;
-    sa.j = m;
-    launch_step<T>(sa, S, grid, partA.as<double>(), partB.as<double>(), st, &kt);
-    ++m;
-    Vprev = Vcur;
-    Vcur = Vnext;
+    side.step();
+    m = side.m();
     if (m == next_check || m == maxit) {
-      LYAP_HIP(hipMemcpyAsync(hflags.p, flags.p, 64, hipMemcpyDeviceToHost, st));
-      LYAP_HIP(hipStreamSynchronize(st));
-      const int* f = hflags.as<int>();
+      int fb = 0, fn = 0;
+      side.read_flags(&fb, &fn);
       int mm = m;
       bool broke = false;
-      if (f[0] > 0 && f[0] <= m) {
-        mm = f[0];  // the QR of step f[0]-1 found a rank-deficient block
+      if (fb > 0 && fb <= m) {
+        mm = fb;  // the QR of step fb-1 found a rank-deficient block
         broke = true;
-      } else if (f[1] > 0) {
-        LYAP_REQUIRE(false, LYAP_E_NUMERIC, "non-finite values in the Lanczos recurrence at step %d", f[1]);
+      } else if (fn > 0) {
+        LYAP_REQUIRE(false, LYAP_E_NUMERIC, "non-finite values in the Lanczos recurrence at step %d", fn);
       }
       CheckOut c = run_check(mm);
       LYAP_REQUIRE(std::isfinite(c.res), LYAP_E_NUMERIC, "residual is not finite at m=%d", mm);
@@ -271,8 +349,7 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   // ------------------------------------------------------------ finalisation
   const auto t_fin = Clock::now();
   std::vector<double> tau_h(S * S);
-  LYAP_HIP(hipMemcpyAsync(tau_h.data(), logb.as<double>() + (size_t)(m - 1) * LS + L_R * S * S,
-                          S * S * sizeof(double), hipMemcpyDeviceToHost, st));
+  LYAP_HIP(hipMemcpyAsync(tau_h.data(), side.tau_dev(m), S * S * sizeof(double), hipMemcpyDeviceToHost, st));
   LYAP_HIP(hipStreamSynchronize(st));
   double tau_f = 0.0;
   for (double v : tau_h) tau_f += v * v;
@@ -282,52 +359,19 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   out->trunc_eps = eps;
   DevBuf M;
   kt.mark(LYAP_K_FINAL);
-  const int t = finalise_factor(ck, band.as<double>(), gamma_dev, eps, M, st);
+  const int t = finalise_factor(ck, side.band(), side.gamma_dev(), eps, M, st);
   kt.collect();
   out->t = t;
   const double fin_ms = ms_since(t_fin);
 
-  // ------------------------------------------------------------ Z
+  // ------------------------------------------------------------ Z (the side keeps
+  // the steps it took; a breakdown check at mm < m uses the first mm blocks)
   const auto t_p2 = Clock::now();
   double zflush_bytes = 0.0;
   bool owned = false;
   out->Z = alloc_output(o, (size_t)n * std::max(t, 1) * sizeof(double), &owned);
   out->owns_Z = owned ? 1 : 0;
-  if (t > 0) {
-    LYAP_HIP(hipMemsetAsync(out->Z, 0, (size_t)n * t * sizeof(double), st));
-    const int QB = zflush_max_blocks(S);
-    if (two_pass) {
-      const int R = QB + 2;
-      std::vector<DevBuf> ring;
-      for (int i = 0; i < R; ++i) ring.emplace_back(blk);
-      launch_init_store<T>(C, ldc, n, S, glog.as<double>(), ring[0].as<T>(), grid, st);
-      std::vector<const void*> pend;
-      int first = 0;
-      for (int i = 0; i < m; ++i) {
-        if (i + 1 < m) {
-          const T* vp = i > 0 ? ring[(i - 1) % R].as<T>() : zero.as<T>();
-          kt.mark(LYAP_K_REPLAY);
-          launch_replay<T>(op.dev, S, vp, ring[i % R].as<T>(), ring[(i + 1) % R].as<T>(),
-                           logb.as<double>() + (size_t)i * LS, grid, st);
-        }
-        if (pend.empty()) first = i;
-        pend.push_back(ring[i % R].p);
-        if ((int)pend.size() == QB || i == m - 1) {
-          kt.mark(LYAP_K_ZFLUSH);
-          zflush_bytes += (double)pend.size() * blk + 2.0 * n * t * sizeof(double);
-          launch_zflush<T>(pend.data(), (int)pend.size(), n, S, M.as<double>() + (size_t)first * S * t, t, out->Z,
-                           n, zgrid, st);
-          pend.clear();
-        }
-      }
-    } else {
-      std::vector<const void*> ptrs;
-      for (int i = 0; i < m; ++i) ptrs.push_back(stored[i].p);
-      kt.mark(LYAP_K_ZFLUSH);
-      zflush_bytes += (double)m * blk + 2.0 * n * t * sizeof(double) * ((m + QB - 1) / QB);
-      launch_zflush<T>(ptrs.data(), m, n, S, M.as<double>(), t, out->Z, n, zgrid, st);
-    }
-  }
+  side.accumulate_Z(m, M.as<double>(), t, out->Z, n, &zflush_bytes);
   LYAP_HIP(hipStreamSynchronize(st));
   kt.collect();
   const double p2_ms = ms_since(t_p2);
@@ -335,14 +379,14 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   if (o.want_T) {
     const int k = m * S;
     out->T_band = (double*)std::malloc((size_t)(S + 1) * k * sizeof(double));
-    LYAP_HIP(hipMemcpy(out->T_band, band.p, (size_t)(S + 1) * k * sizeof(double), hipMemcpyDeviceToHost));
+    LYAP_HIP(hipMemcpy(out->T_band, side.band(), (size_t)(S + 1) * k * sizeof(double), hipMemcpyDeviceToHost));
     // entries below row k belong to tau_{m+1,m}; clear them
     for (int c = 0; c < k; ++c)
       for (int d = 0; d <= S; ++d)
         if (c + d >= k) out->T_band[(size_t)c * (S + 1) + d] = 0.0;
     out->gamma = (double*)std::malloc(S * S * sizeof(double));
     out->tau = (double*)std::malloc(S * S * sizeof(double));
-    rowmajor_to_colmajor(hglog.data() + L_R * S * S, S, S, out->gamma);
+    rowmajor_to_colmajor(side.gamma_host(), S, S, out->gamma);
     rowmajor_to_colmajor(tau_h.data(), S, S, out->tau);
   }
   out->times_ms[LYAP_T_PASS1] = pass1_ms;
@@ -352,22 +396,14 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   out->times_ms[LYAP_T_TOTAL] = ms_since(t_entry);
   out->times_ms[LYAP_T_TO_TOL] = t_to_tol;
   const double b = sizeof(T);
-  const double coef = op.coef_bytes_per_row();
+  const double coef = side.op().coef_bytes_per_row();
   out->bytes_pass1 = (int64_t)((double)m * n * (21.0 * S * b + coef));
   out->bytes_spmm = (int64_t)((double)m * n * (2.0 * S * b + coef));
   for (int i = 0; i < 12; ++i) {
     out->kern_ms[i] = kt.ms[i];
     out->kern_n[i] = kt.n[i];
   }
-  {
-    const double nsb = (double)n * S * b;
-    out->kern_bytes[LYAP_K_SPMM_GRAM] = 3.0 * nsb + coef * n;
-    out->kern_bytes[LYAP_K_UPD_GRAM] = 3.75 * nsb;
-    out->kern_bytes[LYAP_K_CHOL_GRAM] = 1.0 * nsb;
-    out->kern_bytes[LYAP_K_CHOL_STORE] = 2.0 * nsb;
-    out->kern_bytes[LYAP_K_REPLAY] = 3.0 * nsb + coef * n;
-    out->kern_bytes[LYAP_K_ZFLUSH] = kt.n[LYAP_K_ZFLUSH] > 0 ? zflush_bytes / kt.n[LYAP_K_ZFLUSH] : 0.0;
-  }
+  fill_kernel_bytes<T>(n, S, coef, kt, zflush_bytes, out->kern_bytes);
   out->status = status;
   return status;
 }

@@ -27,6 +27,10 @@ struct CheckSchedule {
 
 void store_history(lyap_result* out, const std::vector<int>& hm, const std::vector<double>& hr);
 double* alloc_output(const lyap_opts& o, size_t bytes, bool* owned);
+void rowmajor_to_colmajor(const double* rm, int rows, int cols, double* cm);
+struct KernelTimer;
+template <typename T>
+void fill_kernel_bytes(int n, int S, double coef, const KernelTimer& kt, double zflush_bytes, double* kb);
 
 template <typename T>
 lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, const lyap_opts& o, lyap_result* out);

@@ -1,0 +1,106 @@
+"""GPU parity of sylv_solve (two lockstep block Lanczos spaces, the corrected
+Algorithm 4 residual, cross-approximation truncation, two passes) against the
+CPU FP64 oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+from workloads import laplace2d, fv3d, gaussian_C
+from oracle import sylvester as Y
+from oracle import dense as D
+from oracle import krylov as K
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _b():
+    from paper_1602_05033_amd import binding
+    return binding
+
+
+def _dev(C):
+    return torch.from_numpy(np.ascontiguousarray(C)).cuda()
+
+
+def _case(opA, opB, s, tol, storage=0, two_pass=True, check_every=1, csr=False):
+    b = _b()
+    A = opA.to_scipy()
+    B = opB.to_scipy()
+    C1 = gaussian_C(opA.n, s, 4)
+    C2 = gaussian_C(opB.n, s, 5)
+    sol = b.sylv_solve(b.device_op(opA, as_csr=csr), b.device_op(opB, as_csr=csr), _dev(C1), _dev(C2), tol=tol,
+                       storage=storage, two_pass=two_pass, check_every=check_every, want_T=True)
+    return A, B, C1, C2, sol
+
+
+@pytest.mark.parametrize("s", [1, 2, 4])
+@pytest.mark.parametrize("two_pass", [True, False])
+def test_sylv_parity_fp64(lib, s, two_pass):
+    opA, opB = laplace2d(14), fv3d(6, 0.5, 4)
+    A, B, C1, C2, sol = _case(opA, opB, s, 1e-9, two_pass=two_pass)
+    ref = Y.sylv_std(A, B, C1, C2, tol=1e-9)
+    assert sol.status == 0 and ref.converged
+    assert sol.m == ref.m, (sol.m, ref.m)
+    assert sol.hist_m == [h["m"] for h in ref.hist]
+    for g, r in zip(sol.hist_res, ref.hist):
+        assert abs(g - r["res"]) <= 1e-6 * r["res"] + 1e-14
+    Z1, Z2 = sol.Z1.cpu().numpy(), sol.Z2.cpu().numpy()
+    X = D.sylv_eig(A.toarray(), B.toarray(), C1, C2)
+    assert Y.lowrank_error(Z1, Z2, X) <= 1e-8
+    assert np.linalg.norm(Z1 @ Z2.T - ref.Z1 @ ref.Z2.T) <= 1e-8 * np.linalg.norm(X)
+    ex = Y.explicit_residual(A, B, Z1, Z2, C1, C2) / (sol.beta1 * sol.beta2)
+    assert ex <= 1.2e-9
+    # T_m, J_m early blocks entrywise, tau / iota of the last step, gammas
+    k = s * sol.m
+    for band, Tref in ((sol.T_band, ref.T), (sol.J_band, ref.J)):
+        for c in range(min(k, 4 * s)):
+            for d in range(s + 1):
+                if c + d < k:
+                    assert abs(band[c, d] - Tref[c + d, c]) <= 1e-10 * np.abs(Tref).max()
+    assert np.allclose(sol.gamma1, ref.gamma1, atol=1e-12 * np.abs(ref.gamma1).max(), rtol=0)
+    assert np.allclose(sol.gamma2, ref.gamma2, atol=1e-12 * np.abs(ref.gamma2).max(), rtol=0)
+
+
+def test_sylv_lyapunov_special_case(lib):
+    """B = A, C2 = C1: same iteration and residual as lyap_solve."""
+    b = _b()
+    op = laplace2d(20)
+    C = gaussian_C(op.n, 2, 1)
+    dop = b.device_op(op)
+    sl = b.lyap_solve(dop, _dev(C), tol=1e-8, check_every=1)
+    sy = b.sylv_solve(dop, dop, _dev(C), _dev(C), tol=1e-8, check_every=1)
+    assert sy.m == sl.m
+    for a, c in zip(sy.hist_res, sl.hist_res):
+        assert abs(a - c) <= 1e-9 * c
+    Zs = sl.Z.cpu().numpy()
+    assert np.linalg.norm(sy.Z1.cpu().numpy() @ sy.Z2.cpu().numpy().T - Zs @ Zs.T) <= 1e-7 * np.linalg.norm(Zs.T @ Zs)
+
+
+def test_sylv_fp32_and_csr(lib):
+    """FP32 storage (the stated FP32 floor) and the CSR operator path."""
+    opA, opB = laplace2d(16), fv3d(7, 0.5, 4)
+    A, B, C1, C2, sol = _case(opA, opB, 2, 1e-8, storage=1, check_every=0, csr=True)
+    assert sol.status == 0
+    X = D.sylv_eig(A.toarray(), B.toarray(), C1, C2)
+    Z1, Z2 = sol.Z1.cpu().numpy(), sol.Z2.cpu().numpy()
+    assert Y.lowrank_error(Z1, Z2, X) <= 5e-6
+    ex = Y.explicit_residual(A, B, Z1, Z2, C1, C2) / (sol.beta1 * sol.beta2)
+    assert ex <= 2e-7
+
+
+def test_sylv_different_sizes_and_errors(lib):
+    b = _b()
+    opA, opB = laplace2d(9), fv3d(5, 0.5, 4)     # n1 = 81, n2 = 125
+    C1 = _dev(gaussian_C(opA.n, 1, 4))
+    C2 = _dev(gaussian_C(opB.n, 1, 5))
+    dA, dB = b.device_op(opA), b.device_op(opB)
+    sol = b.sylv_solve(dA, dB, C1, C2, tol=1e-10)
+    assert sol.status == 0 and sol.Z1.shape[0] == 81 and sol.Z2.shape[0] == 125
+    with pytest.raises(b.LyapError):
+        b.sylv_solve(dA, dB, C1, C2, method=b.METHOD_EXT)
+    Cz = torch.zeros_like(C2)
+    with pytest.raises(b.LyapError):
+        b.sylv_solve(dA, dB, C1, Cz)
+    s2 = b.sylv_solve(dA, dB, C1, C2, tol=1e-14, max_iter=4, raise_on_error=False)
+    assert s2.status == b.NOT_CONVERGED and s2.m == 4
