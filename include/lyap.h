@@ -308,6 +308,30 @@ lyap_status lyap_ctri(const double* T_band, int32_t ell, int32_t k, const double
 lyap_status lyap_inner_solve(const lyap_op* A, const double* B, int64_t ldb, double* X, int64_t ldx, int32_t s,
                              const lyap_opts* opts, int64_t* iters, double* relres);
 
+/*
+ * lyap_solve_batched -- `count` independent equations A_i X + X A_i + C_i C_i^T = 0
+ * advanced together: the block Lanczos steps of all unconverged problems of
+ * one block width run in the same grouped launches (a work map assigns each
+ * workgroup to a problem and a row range), each problem keeps its own check
+ * schedule (Algorithm 1 step 6) and leaves the group when it converges, and
+ * the second pass (Section 3.3) is grouped the same way.
+ *  A      host array of `count` operators (device arrays inside).
+ *  C      host array of `count` device pointers, n_i x s_i column-major FP64.
+ *  s      host array, 1 <= s_i <= 8;  ldc: host array, ldc_i >= n_i.
+ *  opts   shared by all problems (tol, max_iter, check_every, storage,
+ *         allocator, stream, profile); method must be STD and two_pass 1.
+ *  tune   0: fixed workgroups per problem (reproducible bits); 1: autotuned
+ *         per (block width, size bucket) once per process by timing one
+ *         grouped step on scratch data for each candidate.
+ *  out    array of `count` results, filled like lyap_solve's; phase times are
+ *         those of the whole batch (times_ms[LYAP_T_TO_TOL] is per problem);
+ *         kern_ms / kern_n of out[0] cover the whole batch.
+ * Returns LYAP_OK when every problem converged, else the first error status
+ * (or LYAP_NOT_CONVERGED); each out[i].status has the problem's own status.
+ */
+lyap_status lyap_solve_batched(int32_t count, const lyap_op* A, const double* const* C, const int32_t* s,
+                               const int64_t* ldc, const lyap_opts* opts, int32_t tune, lyap_result* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,7 +76,8 @@ class SylvResult(ct.Structure):
 
 # exported symbols declared in include/lyap.h
 EXPORTS = ["lyap_opts_default", "lyap_solve", "sylv_solve", "lyap_result_free", "sylv_result_free",
-           "lyap_last_error", "lyap_op_apply", "lyap_op_apply_timed", "lyap_ctri", "lyap_inner_solve"]
+           "lyap_last_error", "lyap_op_apply", "lyap_op_apply_timed", "lyap_ctri", "lyap_inner_solve",
+           "lyap_solve_batched"]
 
 
 class LyapError(RuntimeError):
@@ -121,6 +122,10 @@ def load(path: str = LIB_PATH):
     lib.lyap_inner_solve.argtypes = [ct.POINTER(LyapOp), ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int64, ct.c_int32,
                                      ct.POINTER(LyapOpts), ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
     lib.lyap_inner_solve.restype = ct.c_int
+    lib.lyap_solve_batched.argtypes = [ct.c_int32, ct.POINTER(LyapOp), ct.POINTER(ct.c_void_p),
+                                       ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int64), ct.POINTER(LyapOpts),
+                                       ct.c_int32, ct.POINTER(LyapResult)]
+    lib.lyap_solve_batched.restype = ct.c_int
     _LIB = lib
     return lib
 
@@ -257,31 +262,65 @@ def lyap_solve(dop: DeviceOp, C, raise_on_error: bool = True, **kw) -> LyapSolut
     try:
         if raise_on_error and st not in (OK, NOT_CONVERGED):
             raise LyapError(st, msg)
-        Z = None
-        if r.Z:
-            buf = alloc.take(r.Z)
-            if r.t > 0:
-                Z = buf[: 8 * n * r.t].view(torch.float64).view(r.t, n).t()
-            else:
-                Z = torch.zeros((n, 0), dtype=torch.float64, device=C.device)
-        ell = r.ell
-        k = ell * r.m
-        sol = LyapSolution(
-            status=st, Z=Z, m=r.m, t=r.t, beta=r.beta, res=r.res,
-            hist_m=[r.hist_m[i] for i in range(r.n_hist)], hist_res=[r.hist_res[i] for i in range(r.n_hist)],
-            times_ms={k_: r.times_ms[i] for i, k_ in enumerate(TIME_KEYS)}, n_checks=r.n_checks,
-            trunc_eps=r.trunc_eps, bytes_pass1=r.bytes_pass1, bytes_spmm=r.bytes_spmm,
-            inner_iters=r.inner_iters, n_inner=r.n_inner, ell=ell,
-            kernels={name: {"ms": r.kern_ms[i], "n": r.kern_n[i], "bytes_per_launch": r.kern_bytes[i]}
-                     for i, name in enumerate(KERNEL_KINDS) if r.kern_n[i] > 0})
-        if r.T_band:
-            sol.T_band = np.ctypeslib.as_array(r.T_band, shape=(k * (ell + 1),)).copy().reshape(k, ell + 1)
-            sol.gamma = np.ctypeslib.as_array(r.gamma, shape=(ell * ell,)).copy().reshape(ell, ell, order="F")
-            sol.tau = np.ctypeslib.as_array(r.tau, shape=(ell * ell,)).copy().reshape(ell, ell, order="F")
-        sol.error = msg
-        return sol
+        return _solution(r, st, alloc, n, C.device, msg)
     finally:
         lib.lyap_result_free(ct.byref(r))
+
+
+def _solution(r, st, alloc, n, device, msg) -> LyapSolution:
+    import torch
+    Z = None
+    if r.Z:
+        buf = alloc.take(r.Z)
+        if r.t > 0:
+            Z = buf[: 8 * n * r.t].view(torch.float64).view(r.t, n).t()
+        else:
+            Z = torch.zeros((n, 0), dtype=torch.float64, device=device)
+    ell = r.ell
+    k = ell * r.m
+    sol = LyapSolution(
+        status=st, Z=Z, m=r.m, t=r.t, beta=r.beta, res=r.res,
+        hist_m=[r.hist_m[i] for i in range(r.n_hist)], hist_res=[r.hist_res[i] for i in range(r.n_hist)],
+        times_ms={k_: r.times_ms[i] for i, k_ in enumerate(TIME_KEYS)}, n_checks=r.n_checks,
+        trunc_eps=r.trunc_eps, bytes_pass1=r.bytes_pass1, bytes_spmm=r.bytes_spmm,
+        inner_iters=r.inner_iters, n_inner=r.n_inner, ell=ell,
+        kernels={name: {"ms": r.kern_ms[i], "n": r.kern_n[i], "bytes_per_launch": r.kern_bytes[i]}
+                 for i, name in enumerate(KERNEL_KINDS) if r.kern_n[i] > 0})
+    if r.T_band:
+        sol.T_band = np.ctypeslib.as_array(r.T_band, shape=(k * (ell + 1),)).copy().reshape(k, ell + 1)
+        sol.gamma = np.ctypeslib.as_array(r.gamma, shape=(ell * ell,)).copy().reshape(ell, ell, order="F")
+        sol.tau = np.ctypeslib.as_array(r.tau, shape=(ell * ell,)).copy().reshape(ell, ell, order="F")
+    sol.error = msg
+    return sol
+
+
+def lyap_solve_batched(dops, Cs, tune: bool = False, raise_on_error: bool = True, **kw):
+    """Solve a batch of Lyapunov equations in grouped launches.  ``dops``:
+    list of DeviceOp; ``Cs``: list of (n_i, s_i) float64 device tensors.
+    Returns (status, [LyapSolution])."""
+    import torch
+    lib = load()
+    count = len(dops)
+    assert count == len(Cs) and count > 0
+    ops = (LyapOp * count)(*[d.c for d in dops])
+    Ccm = [C.t().contiguous() for C in Cs]
+    ptrs = (ct.c_void_p * count)(*[c.data_ptr() for c in Ccm])
+    ss = (ct.c_int32 * count)(*[C.shape[1] for C in Cs])
+    lds = (ct.c_int64 * count)(*[C.shape[0] for C in Cs])
+    alloc = _TorchAllocator(Cs[0].device)
+    o = make_opts(stream=torch.cuda.current_stream(Cs[0].device).cuda_stream, **kw)
+    o.alloc, o.release = alloc.alloc_cb, alloc.free_cb
+    res = (LyapResult * count)()
+    st = lib.lyap_solve_batched(count, ops, ptrs, ss, lds, ct.byref(o), int(bool(tune)), res)
+    msg = lib.lyap_last_error().decode()
+    try:
+        if raise_on_error and st not in (OK, NOT_CONVERGED):
+            raise LyapError(st, msg)
+        sols = [_solution(res[i], res[i].status, alloc, Cs[i].shape[0], Cs[i].device, msg) for i in range(count)]
+        return st, sols
+    finally:
+        for i in range(count):
+            lib.lyap_result_free(ct.byref(res[i]))
 
 
 def op_apply(dop: DeviceOp, V, storage: int):

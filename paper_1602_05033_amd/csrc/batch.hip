@@ -1,0 +1,501 @@
+// lyap_solve_batched: many independent Lyapunov equations (different n, s and
+// iteration counts) advanced together by grouped launches.  Every active
+// problem of one block width takes its next block Lanczos step in the same
+// seven kernels -- each workgroup looks up its (problem, workgroup-in-problem)
+// pair in a work map -- so a batch of small problems fills the GPU and costs
+// seven launches per step instead of seven per problem.  Residual checks run
+// on each problem's own schedule; converged problems leave the work map.  The
+// second pass is grouped the same way (one replay launch per step for all
+// problems still replaying), with per-problem Z accumulation.
+//
+// Workgroups per problem ("nparts") are chosen per (block width, size
+// bucket): a fixed rule, or an autotuner that times one grouped step on
+// scratch problems for each candidate and keeps the fastest for the process.
+// The choice sets the order of the partial sums, so autotuned runs are
+// reproducible within a process (and across processes when the timings pick
+// the same candidates); the fixed rule is reproducible always.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <memory>
+#include <tuple>
+#include <mutex>
+#include <type_traits>
+
+#include "check.hpp"
+#include "lanczos.hpp"
+#include "solver.hpp"
+
+namespace lyap {
+
+namespace {
+
+constexpr int kChunkCandidates[] = {2048, 4096, 8192, 16384};
+
+int nparts_for(int64_t n, int chunk) {
+  const int64_t p = (n + chunk - 1) / chunk;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(p, kSGrid));
+}
+
+int size_bucket(int64_t n) {
+  int b = 0;
+  while ((int64_t(1) << (b + 1)) <= n) ++b;
+  return b;
+}
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tune;  // (storage, S, bucket) -> rows per workgroup
+
+template <typename T>
+struct Problem {
+  int id;
+  int n, S;
+  const double* C;
+  int64_t ldc;
+  OpHolder<T> op;
+  DevBuf Vb0, Vb1, W, zero, log, glog, band, partA, partB, ring;
+  std::vector<double> hglog;
+  double beta = 0.0;
+  int m = 0;           // steps taken
+  int m_final = 0;     // blocks of the accepted basis
+  bool active = true;
+  lyap_status status = LYAP_NOT_CONVERGED;
+  std::unique_ptr<Checker> ck;
+  CheckSchedule sched{0, 0};
+  int next_check = 0;
+  int checked_m = 0;
+  double lam_absmax = 0.0;
+  double last_res = INFINITY;
+  double t_to_tol = 0.0;
+  std::vector<int> hm;
+  std::vector<double> hr;
+  int nparts = 1;
+  DevBuf M;
+  int t = 0;
+};
+
+// Times one grouped step on a scratch problem (random block, the 5-point
+// operator of the bucket's size) for each candidate; returns the fastest.
+template <typename T>
+int autotune_chunk(int S, int64_t n, hipStream_t st) {
+  const int storage = std::is_same_v<T, double> ? LYAP_STORE_F64 : LYAP_STORE_F32;
+  const auto key = std::make_tuple(storage, S, size_bucket(n));
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  const int N = (int)std::max<int64_t>(8, (int64_t)std::sqrt((double)n));
+  const int nn = N * N;
+  const size_t blk = (size_t)nn * S * sizeof(T);
+  DevBuf Vb0(blk), Vb1(blk), W(blk), zero(blk), log(4 * log_stride(S) * sizeof(double)),
+      band((size_t)(S + 1) * S * 8 * sizeof(double)), pA((size_t)kSGrid * S * S * sizeof(double)),
+      pB((size_t)kSGrid * S * S * sizeof(double)), flags(64), dd(sizeof(BatchDesc<T>));
+  LYAP_HIP(hipMemsetAsync(Vb0.p, 0, blk, st));
+  LYAP_HIP(hipMemsetAsync(W.p, 0, blk, st));
+  LYAP_HIP(hipMemsetAsync(flags.p, 0, 64, st));
+  {
+    std::vector<T> h((size_t)nn * S);
+    for (size_t i = 0; i < h.size(); ++i) h[i] = (T)(((i * 2654435761u) % 1000) * 1e-3 - 0.5);
+    LYAP_HIP(hipMemcpy(Vb1.p, h.data(), blk, hipMemcpyHostToDevice));
+  }
+  BatchDesc<T> d{};
+  d.op.kind = LYAP_OP_STENCIL5;
+  d.op.nx = N;
+  d.op.ny = N;
+  d.op.nz = 1;
+  d.op.n = nn;
+  d.op.cc = (T)-4;
+  d.op.co = (T)1;
+  d.n = nn;
+  d.Vb0 = Vb0.template as<T>();
+  d.Vb1 = Vb1.template as<T>();
+  d.W = W.template as<T>();
+  d.log = log.template as<double>();
+  d.band = band.template as<double>();
+  d.partA = pA.template as<double>();
+  d.partB = pB.template as<double>();
+  d.flags = flags.template as<int>();
+  hipEvent_t e0, e1;
+  LYAP_HIP(hipEventCreate(&e0));
+  LYAP_HIP(hipEventCreate(&e1));
+  int best = kChunkCandidates[0];
+  float best_ms = 1e30f;
+  for (int chunk : kChunkCandidates) {
+    d.nparts = nparts_for(nn, chunk);
+    std::vector<int2> map(d.nparts);
+    for (int w = 0; w < d.nparts; ++w) map[w] = make_int2(0, w);
+    DevBuf dm(map.size() * sizeof(int2));
+    LYAP_HIP(hipMemcpy(dd.p, &d, sizeof(d), hipMemcpyHostToDevice));
+    LYAP_HIP(hipMemcpy(dm.p, map.data(), map.size() * sizeof(int2), hipMemcpyHostToDevice));
+    // step 0 twice (the same inputs every time), then timed
+    for (int r = 0; r < 2; ++r)
+      launch_batch_step<T>(dd.template as<BatchDesc<T>>(), dm.template as<int2>(), d.nparts, S, 0, st);
+    LYAP_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < 5; ++r)
+      launch_batch_step<T>(dd.template as<BatchDesc<T>>(), dm.template as<int2>(), d.nparts, S, 0, st);
+    LYAP_HIP(hipEventRecord(e1, st));
+    LYAP_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    LYAP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = chunk;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[key] = best;
+  return best;
+}
+
+template <typename T>
+lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, const int32_t* s, const int64_t* ldc,
+                         const lyap_opts& o, int tune, lyap_result* out) {
+  const auto t_entry = Clock::now();
+  hipStream_t st = (hipStream_t)o.stream;
+  const int maxit = o.max_iter;
+  KernelTimer kt;
+  kt.st = st;
+  kt.on = o.profile != 0;
+
+  std::vector<std::unique_ptr<Problem<T>>> P;
+  DevBuf flags_all((size_t)count * 16 * sizeof(int));
+  LYAP_HIP(hipMemsetAsync(flags_all.p, 0, flags_all.bytes, st));
+  HostBuf hflags((size_t)count * 16 * sizeof(int));
+  for (int i = 0; i < count; ++i) {
+    auto p = std::make_unique<Problem<T>>();
+    p->id = i;
+    p->n = (int)A[i].n;
+    p->S = s[i];
+    p->C = C[i];
+    p->ldc = ldc[i];
+    if constexpr (std::is_same_v<T, double>) make_op_f64(&A[i], p->op, st);
+    else make_op_f32(&A[i], p->op, st);
+    const size_t blk = (size_t)p->n * p->S * sizeof(T);
+    const size_t LS = log_stride(p->S);
+    p->Vb0.alloc(blk);
+    p->Vb1.alloc(blk);
+    p->W.alloc(blk);
+    p->zero.alloc(blk);
+    p->log.alloc(((size_t)maxit + 1) * LS * sizeof(double));
+    p->glog.alloc(LS * sizeof(double));
+    p->band.alloc((size_t)(p->S + 1) * p->S * (maxit + 2) * sizeof(double));
+    p->partA.alloc((size_t)kSGrid * p->S * p->S * sizeof(double));
+    p->partB.alloc((size_t)kSGrid * p->S * p->S * sizeof(double));
+    LYAP_HIP(hipMemsetAsync(p->zero.p, 0, blk, st));
+    LYAP_HIP(hipMemsetAsync(p->Vb0.p, 0, blk, st));
+    LYAP_HIP(hipMemsetAsync(p->band.p, 0, p->band.bytes, st));
+    const int chunk = tune ? autotune_chunk<T>(p->S, p->n, st) : 2048;
+    p->nparts = nparts_for(p->n, chunk);
+    p->ck = std::make_unique<Checker>(p->S, p->S, st);
+    p->sched = CheckSchedule{o.check_every, maxit};
+    p->next_check = p->sched.first();
+    out[i].n = p->n;
+    out[i].s = p->S;
+    out[i].ell = p->S;
+    P.push_back(std::move(p));
+  }
+  // QR of every C
+  kt.mark(LYAP_K_INIT);
+  for (auto& p : P) {
+    launch_init<T>(p->C, p->ldc, p->n, p->S, p->glog.template as<double>(), p->partA.template as<double>(), p->partB.template as<double>(),
+                   flags_all.template as<int>() + 16 * p->id, p->Vb1.template as<T>(), stream_grid(p->n), st);
+    p->hglog.assign(log_stride(p->S), 0.0);
+    LYAP_HIP(hipMemcpyAsync(p->hglog.data(), p->glog.p, p->hglog.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            st));
+  }
+  LYAP_HIP(hipMemcpyAsync(hflags.p, flags_all.p, flags_all.bytes, hipMemcpyDeviceToHost, st));
+  LYAP_HIP(hipStreamSynchronize(st));
+  kt.collect();
+  for (auto& p : P) {
+    const int* f = hflags.template as<int>() + 16 * p->id;
+    const double trC = p->hglog[L_FLAG * p->S * p->S + 1];
+    LYAP_REQUIRE(f[1] == 0 && std::isfinite(trC), LYAP_E_NUMERIC, "problem %d: C contains NaN or Inf", p->id);
+    LYAP_REQUIRE(trC > 0.0, LYAP_E_ARG, "problem %d: C is zero", p->id);
+    LYAP_REQUIRE(f[0] == 0, LYAP_E_BREAKDOWN, "problem %d: C is numerically rank deficient", p->id);
+    p->beta = std::sqrt(trC);
+    out[p->id].beta = p->beta;
+  }
+
+  // block widths present, descriptors and work maps per width
+  std::vector<int> widths;
+  for (auto& p : P)
+    if (std::find(widths.begin(), widths.end(), p->S) == widths.end()) widths.push_back(p->S);
+  std::sort(widths.begin(), widths.end());
+  struct Group {
+    int S;
+    std::vector<Problem<T>*> probs;
+    DevBuf desc, map;
+    int nwg = 0;
+  };
+  std::vector<Group> groups(widths.size());
+  for (size_t g = 0; g < widths.size(); ++g) {
+    groups[g].S = widths[g];
+    for (auto& p : P)
+      if (p->S == widths[g]) groups[g].probs.push_back(p.get());
+  }
+  auto upload = [&](Group& g, bool replay, int step) {
+    std::vector<BatchDesc<T>> d(g.probs.size());
+    std::vector<int2> map;
+    for (size_t q = 0; q < g.probs.size(); ++q) {
+      Problem<T>* p = g.probs[q];
+      BatchDesc<T>& b = d[q];
+      b.op = p->op.dev;
+      b.n = p->n;
+      b.nparts = p->nparts;
+      b.Vb0 = p->Vb0.template as<T>();
+      b.Vb1 = p->Vb1.template as<T>();
+      b.W = p->W.template as<T>();
+      b.log = p->log.template as<double>();
+      b.band = p->band.template as<double>();
+      b.partA = p->partA.template as<double>();
+      b.partB = p->partB.template as<double>();
+      b.flags = flags_all.template as<int>() + 16 * p->id;
+      b.ring = p->ring.p ? p->ring.template as<T>() : nullptr;
+      b.R = zflush_max_blocks(p->S) + 2;
+      b.zero = p->zero.template as<T>();
+      const bool take = replay ? (step + 1 < p->m_final) : p->active;
+      if (take)
+        for (int w = 0; w < p->nparts; ++w) map.push_back(make_int2((int)q, w));
+    }
+    LYAP_HIP(hipStreamSynchronize(st));  // the previous descriptors / map may still be read
+    if (g.desc.bytes < d.size() * sizeof(BatchDesc<T>)) g.desc.alloc(d.size() * sizeof(BatchDesc<T>));
+    if (g.map.bytes < std::max<size_t>(1, map.size()) * sizeof(int2))
+      g.map.alloc(std::max<size_t>(1, map.size()) * sizeof(int2));
+    LYAP_HIP(hipMemcpy(g.desc.p, d.data(), d.size() * sizeof(BatchDesc<T>), hipMemcpyHostToDevice));
+    if (!map.empty()) LYAP_HIP(hipMemcpy(g.map.p, map.data(), map.size() * sizeof(int2), hipMemcpyHostToDevice));
+    g.nwg = (int)map.size();
+  };
+  for (auto& g : groups) upload(g, false, 0);
+
+  DevBuf chk((size_t)count * sizeof(CheckOut));
+  HostBuf hchk((size_t)count * sizeof(CheckOut));
+  double check_ms = 0.0;
+  const auto t_pass1 = Clock::now();
+  int j = 0;
+  int n_active = count;
+  while (n_active > 0 && j < maxit) {
+    for (auto& g : groups) launch_batch_step<T>(g.desc.template as<BatchDesc<T>>(), g.map.template as<int2>(), g.nwg, g.S, j, st, &kt);
+    ++j;
+    std::vector<Problem<T>*> due;
+    for (auto& p : P)
+      if (p->active) {
+        p->m = j;
+        if (j == p->next_check || j == maxit) due.push_back(p.get());
+      }
+    if (due.empty()) continue;
+    const auto t0 = Clock::now();
+    LYAP_HIP(hipMemcpyAsync(hflags.p, flags_all.p, flags_all.bytes, hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipStreamSynchronize(st));
+    kt.collect();
+    std::vector<int> mm(due.size());
+    std::vector<bool> broke(due.size(), false);
+    kt.mark(LYAP_K_CHECK);
+    for (size_t q = 0; q < due.size(); ++q) {
+      Problem<T>* p = due[q];
+      const int* f = hflags.template as<int>() + 16 * p->id;
+      LYAP_REQUIRE(f[1] == 0, LYAP_E_NUMERIC, "problem %d: non-finite values at step %d", p->id, f[1]);
+      mm[q] = j;
+      if (f[0] > 0 && f[0] <= j) {
+        mm[q] = f[0];
+        broke[q] = true;
+      }
+      const size_t LS = log_stride(p->S);
+      p->ck->run(p->band.template as<double>(), mm[q] * p->S, p->glog.template as<double>() + L_R * p->S * p->S,
+                 p->log.template as<double>() + (size_t)(mm[q] - 1) * LS + L_R * p->S * p->S, chk.template as<CheckOut>() + p->id);
+    }
+    LYAP_HIP(hipMemcpyAsync(hchk.p, chk.p, chk.bytes, hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipStreamSynchronize(st));
+    kt.collect();
+    bool changed = false;
+    for (size_t q = 0; q < due.size(); ++q) {
+      Problem<T>* p = due[q];
+      const CheckOut& c = hchk.template as<CheckOut>()[p->id];
+      LYAP_REQUIRE(std::isfinite(c.res), LYAP_E_NUMERIC, "problem %d: residual not finite", p->id);
+      LYAP_REQUIRE(c.lam_max < 0.0, LYAP_E_INDEFINITE, "problem %d: Ritz value %.3e >= 0", p->id, c.lam_max);
+      const double rel = c.res / (p->beta * p->beta);
+      p->hm.push_back(mm[q]);
+      p->hr.push_back(rel);
+      p->last_res = rel;
+      p->checked_m = mm[q];
+      p->lam_absmax = std::max(std::fabs(c.lam_min), std::fabs(c.lam_max));
+      out[p->id].n_checks++;
+      if (o.verbose) std::fprintf(stderr, "[batch] problem %d m=%d res=%.3e\n", p->id, mm[q], rel);
+      if (rel <= o.tol) {
+        p->status = LYAP_OK;
+        p->m_final = mm[q];
+        p->active = false;
+        p->t_to_tol = ms_since(t_entry);
+      } else if (broke[q]) {
+        p->status = LYAP_E_BREAKDOWN;
+        p->m_final = mm[q];
+        p->active = false;
+      } else if (j >= maxit) {
+        p->m_final = j;
+        p->active = false;
+      } else {
+        p->next_check = p->sched.next(j, rel, o.tol);
+      }
+      if (!p->active) {
+        changed = true;
+        --n_active;
+      }
+    }
+    check_ms += ms_since(t0);
+    if (changed)
+      for (auto& g : groups) upload(g, false, 0);
+  }
+  for (auto& p : P)
+    if (p->m_final == 0) p->m_final = p->m;
+  const double pass1_ms = ms_since(t_pass1) - check_ms;
+
+  // ---- finalisation per problem
+  const auto t_fin = Clock::now();
+  kt.mark(LYAP_K_FINAL);
+  for (auto& p : P) {
+    const int S = p->S;
+    const size_t LS = log_stride(S);
+    if (p->checked_m != p->m_final) {  // (only when max_iter ended without a due check)
+      p->ck->run(p->band.template as<double>(), p->m_final * S, p->glog.template as<double>() + L_R * S * S,
+                 p->log.template as<double>() + (size_t)(p->m_final - 1) * LS + L_R * S * S, chk.template as<CheckOut>() + p->id);
+      LYAP_HIP(hipMemcpyAsync(hchk.template as<CheckOut>() + p->id, chk.template as<CheckOut>() + p->id, sizeof(CheckOut),
+                              hipMemcpyDeviceToHost, st));
+      LYAP_HIP(hipStreamSynchronize(st));
+      const CheckOut& c = hchk.template as<CheckOut>()[p->id];
+      p->last_res = c.res / (p->beta * p->beta);
+      p->hm.push_back(p->m_final);
+      p->hr.push_back(p->last_res);
+      p->lam_absmax = std::max(std::fabs(c.lam_min), std::fabs(c.lam_max));
+    }
+    std::vector<double> tau(S * S);
+    LYAP_HIP(hipMemcpy(tau.data(), p->log.template as<double>() + (size_t)(p->m_final - 1) * LS + L_R * S * S,
+                       S * S * sizeof(double), hipMemcpyDeviceToHost));
+    double tf = 0.0;
+    for (double v : tau) tf += v * v;
+    tf = std::sqrt(tf);
+    const double b2 = p->beta * p->beta;
+    double eps = o.trunc_eps;
+    if (!(eps >= 0.0)) eps = std::min(1e-12, 0.05 * o.tol / (p->lam_absmax + tf)) * b2;
+    out[p->id].trunc_eps = eps;
+    p->t = finalise_factor(*p->ck, p->band.template as<double>(), p->glog.template as<double>() + L_R * S * S, eps, p->M, st);
+  }
+  kt.collect();
+  const double fin_ms = ms_since(t_fin);
+
+  // ---- second pass, grouped
+  const auto t_p2 = Clock::now();
+  int mmax = 0;
+  for (auto& p : P) {
+    bool owned = false;
+    out[p->id].Z = alloc_output(o, (size_t)p->n * std::max(p->t, 1) * sizeof(double), &owned);
+    out[p->id].owns_Z = owned ? 1 : 0;
+    const int R = zflush_max_blocks(p->S) + 2;
+    p->ring.alloc((size_t)R * p->n * p->S * sizeof(T));
+    if (p->t > 0) {
+      LYAP_HIP(hipMemsetAsync(out[p->id].Z, 0, (size_t)p->n * p->t * sizeof(double), st));
+      launch_init_store<T>(p->C, p->ldc, p->n, p->S, p->glog.template as<double>(), p->ring.template as<T>(), stream_grid(p->n), st);
+      mmax = std::max(mmax, p->m_final);
+    }
+  }
+  // problems with t == 0 take no part in the replay
+  for (auto& p : P)
+    if (p->t <= 0) p->m_final = 0;
+  for (auto& g : groups) upload(g, true, 0);
+  std::vector<int> first(count, 0);
+  std::vector<std::vector<const void*>> pend(count);
+  for (int i = 0; i < mmax; ++i) {
+    bool map_changes = false;
+    for (auto& g : groups) {
+      if (g.nwg > 0) {
+        kt.mark(LYAP_K_REPLAY);
+        launch_batch_replay<T>(g.desc.template as<BatchDesc<T>>(), g.map.template as<int2>(), g.nwg, g.S, i, st);
+      }
+      for (Problem<T>* p : g.probs)
+        if (i + 2 == p->m_final) map_changes = true;  // leaves the replay map after this step
+    }
+    for (auto& p : P) {
+      if (i >= p->m_final) continue;
+      const int S = p->S;
+      const int R = zflush_max_blocks(S) + 2;
+      if (pend[p->id].empty()) first[p->id] = i;
+      pend[p->id].push_back(p->ring.template as<T>() + (size_t)(i % R) * p->n * S);
+      if ((int)pend[p->id].size() == zflush_max_blocks(S) || i == p->m_final - 1) {
+        kt.mark(LYAP_K_ZFLUSH);
+        launch_zflush<T>(pend[p->id].data(), (int)pend[p->id].size(), p->n, S,
+                         p->M.template as<double>() + (size_t)first[p->id] * S * p->t, p->t, out[p->id].Z, p->n, 0, st);
+        pend[p->id].clear();
+      }
+    }
+    if (map_changes)
+      for (auto& g : groups) upload(g, true, i + 1);
+  }
+  LYAP_HIP(hipStreamSynchronize(st));
+  kt.collect();
+  const double p2_ms = ms_since(t_p2);
+
+  lyap_status worst = LYAP_OK;
+  for (auto& p : P) {
+    lyap_result& r = out[p->id];
+    r.m = p->m_final;
+    r.t = p->t;
+    r.res = p->last_res;
+    r.status = p->status;
+    store_history(&r, p->hm, p->hr);
+    r.times_ms[LYAP_T_PASS1] = pass1_ms;
+    r.times_ms[LYAP_T_CHECKS] = check_ms;
+    r.times_ms[LYAP_T_FINAL] = fin_ms;
+    r.times_ms[LYAP_T_PASS2] = p2_ms;
+    r.times_ms[LYAP_T_TOTAL] = ms_since(t_entry);
+    r.times_ms[LYAP_T_TO_TOL] = p->t_to_tol;
+    if (p->status != LYAP_OK && (worst == LYAP_OK || p->status < 0)) worst = p->status;
+  }
+  // batch-level kernel times in the first result
+  for (int i = 0; i < 12; ++i) {
+    out[0].kern_ms[i] = kt.ms[i];
+    out[0].kern_n[i] = kt.n[i];
+  }
+  return worst;
+}
+
+}  // namespace
+}  // namespace lyap
+
+extern "C" lyap_status lyap_solve_batched(int32_t count, const lyap_op* A, const double* const* C, const int32_t* s,
+                                          const int64_t* ldc, const lyap_opts* opts, int32_t tune,
+                                          lyap_result* out) {
+  using namespace lyap;
+  clear_error();
+  if (!out || count <= 0 || !A || !C || !s || !ldc) {
+    set_error("bad arguments (count <= 0 or NULL array)");
+    return LYAP_E_ARG;
+  }
+  for (int i = 0; i < count; ++i) std::memset(&out[i], 0, sizeof(lyap_result));
+  lyap_opts o;
+  if (opts) o = *opts;
+  else lyap_opts_default(&o);
+  try {
+    for (int i = 0; i < count; ++i) {
+      validate_op(&A[i]);
+      LYAP_REQUIRE(C[i] != nullptr, LYAP_E_ARG, "problem %d: C is NULL", i);
+      LYAP_REQUIRE(s[i] >= 1 && s[i] <= 8, LYAP_E_ARG, "problem %d: s=%d out of range 1..8", i, s[i]);
+      LYAP_REQUIRE(ldc[i] >= A[i].n && s[i] <= A[i].n, LYAP_E_ARG, "problem %d: bad ldc or s > n", i);
+    }
+    LYAP_REQUIRE(o.tol > 0.0 && o.tol < 1.0, LYAP_E_ARG, "tol=%g must be in (0,1)", o.tol);
+    LYAP_REQUIRE(o.max_iter >= 1 && (int64_t)o.max_iter * 8 <= (int64_t)1 << 20, LYAP_E_ARG,
+                 "max_iter=%d out of range", o.max_iter);
+    LYAP_REQUIRE(o.check_every >= 0, LYAP_E_ARG, "check_every must be >= 0");
+    LYAP_REQUIRE(o.method == LYAP_METHOD_STD, LYAP_E_UNSUPPORTED, "the batched solver builds standard Krylov spaces");
+    LYAP_REQUIRE(o.two_pass != 0, LYAP_E_UNSUPPORTED, "the batched solver uses the two-pass strategy");
+    LYAP_REQUIRE(o.storage == LYAP_STORE_F64 || o.storage == LYAP_STORE_F32, LYAP_E_ARG, "unknown storage %d",
+                 o.storage);
+    return o.storage == LYAP_STORE_F64 ? batched_impl<double>(count, A, C, s, ldc, o, tune, out)
+                                       : batched_impl<float>(count, A, C, s, ldc, o, tune, out);
+  } catch (const Error& e) {
+    for (int i = 0; i < count; ++i)
+      if (out[i].status == 0) out[i].status = e.st;
+    return e.st;
+  }
+}

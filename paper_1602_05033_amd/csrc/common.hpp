@@ -346,9 +346,14 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
 }
 
 template <int K, int NT>
-__device__ __forceinline__ void write_partial(double (&v)[K], double* red, double* part) {
+__device__ __forceinline__ void write_partial_at(double (&v)[K], double* red, double* part, int idx) {
   block_sum<K, NT>(v, red);
-  if (threadIdx.x < K) part[(size_t)blockIdx.x * K + threadIdx.x] = red[threadIdx.x];
+  if (threadIdx.x < K) part[(size_t)idx * K + threadIdx.x] = red[threadIdx.x];
+}
+
+template <int K, int NT>
+__device__ __forceinline__ void write_partial(double (&v)[K], double* red, double* part) {
+  write_partial_at<K, NT>(v, red, part, blockIdx.x);
 }
 
 inline int grid_for(int64_t rows, int rows_per_thread_min = 1, int max_blocks = 2048) {

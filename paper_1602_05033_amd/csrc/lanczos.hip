@@ -73,9 +73,12 @@ template <typename T, int S>
 constexpr int rows_per_thread() {
   return 1;
 }
+// (wg_id, wg_cnt): this workgroup's index among the wg_cnt that share the
+// problem -- blockIdx.x / gridDim.x for a single problem, the work-map entry
+// in a grouped launch over several problems.
 #define LYAP_BATCH(r0, n) \
   constexpr int kRPT = rows_per_thread<T, S>(); \
-  for (int r0 = blockIdx.x * stream_threads(S) + threadIdx.x; r0 < (n); r0 += gridDim.x * stream_threads(S) * kRPT)
+  for (int r0 = wg_id * stream_threads(S) + threadIdx.x; r0 < (n); r0 += wg_cnt * stream_threads(S) * kRPT)
 #define LYAP_FOR_U _Pragma("unroll") for (int u = 0; u < kRPT; ++u)
 
 template <int S>
@@ -96,21 +99,20 @@ __device__ __forceinline__ void outer_acc(double (&acc)[S * S], const X (&x)[S],
 // workgroup 0 also records it in the log slot (if slot >= 0).
 template <int S>
 __device__ __forceinline__ void take_gram(const double* pin, int nparts, double* red, double (&g)[S * S],
-                                          double* log_slot) {
+                                          double* log_slot, bool lead) {
   reduce_partials<S * S, stream_threads(S)>(pin, nparts, red);
 #pragma unroll
   for (int i = 0; i < S * S; ++i) g[i] = uniform_d(red[i]);
-  if (blockIdx.x == 0 && log_slot && threadIdx.x < S * S) log_slot[threadIdx.x] = red[threadIdx.x];
+  if (lead && log_slot && threadIdx.x < S * S) log_slot[threadIdx.x] = red[threadIdx.x];
   __syncthreads();  // red is reused by the epilogue
 }
 
 // K1: W = A V_j ; partial alpha1 = V_{j-1}^T W
 template <typename T, int S>
-__global__ __launch_bounds__(stream_threads(S)) void k_spmm_gram(StepArgs<T> a) {
-  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+__device__ __forceinline__ void spmm_gram_body(const StepArgs<T>& a, int wg_id, int wg_cnt, double* red) {
   double acc[S * S];
   zero<S>(acc);
-  const int str = gridDim.x * stream_threads(S);
+  const int str = wg_cnt * stream_threads(S);
   LYAP_BATCH(r0, a.n) {
     T w[kRPT][S], x[kRPT][S];
     LYAP_FOR_U {
@@ -128,19 +130,19 @@ __global__ __launch_bounds__(stream_threads(S)) void k_spmm_gram(StepArgs<T> a) 
       }
     }
   }
-  write_partial<S * S, stream_threads(S)>(acc, red, a.pout);
+  write_partial_at<S * S, stream_threads(S)>(acc, red, a.pout, wg_id);
 }
 
 // K2..K5: alpha_in = total of the previous partials (logged), W -= X alpha_in,
 // partial Y^T W (Y == nullptr: W^T W for the QR that follows).
 template <typename T, int S>
-__global__ __launch_bounds__(stream_threads(S)) void k_upd_gram(StepArgs<T> a, const T* X, const T* Y, int slot_in) {
-  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+__device__ __forceinline__ void upd_gram_body(const StepArgs<T>& a, const T* X, const T* Y, int slot_in, int wg_id,
+                                              int wg_cnt, double* red) {
   double al[S * S];
-  take_gram<S>(a.pin, a.nparts, red, al, a.log + slot_in * S * S);
+  take_gram<S>(a.pin, a.nparts, red, al, a.log + slot_in * S * S, wg_id == 0);
   double acc[S * S];
   zero<S>(acc);
-  const int str = gridDim.x * stream_threads(S);
+  const int str = wg_cnt * stream_threads(S);
   LYAP_BATCH(r0, a.n) {
     T w[kRPT][S], x[kRPT][S], y[kRPT][S];
     LYAP_FOR_U {
@@ -161,27 +163,26 @@ __global__ __launch_bounds__(stream_threads(S)) void k_upd_gram(StepArgs<T> a, c
       }
     }
   }
-  write_partial<S * S, stream_threads(S)>(acc, red, a.pout);
+  write_partial_at<S * S, stream_threads(S)>(acc, red, a.pout, wg_id);
 }
 
 // K6: G1 = W^T W (logged), R1 = chol(G1) ; partial (W R1^{-1})^T (W R1^{-1})
 template <typename T, int S>
-__global__ __launch_bounds__(stream_threads(S)) void k_chol_gram(StepArgs<T> a) {
-  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+__device__ __forceinline__ void chol_gram_body(const StepArgs<T>& a, int wg_id, int wg_cnt, double* red) {
   __shared__ double sR1[S * S], sR1I[S * S];
   __shared__ double sratio;
   double G[S * S];
-  take_gram<S>(a.pin, a.nparts, red, G, a.log + L_G1 * S * S);
+  take_gram<S>(a.pin, a.nparts, red, G, a.log + L_G1 * S * S, wg_id == 0);
   if (threadIdx.x == 0) {
     sratio = chol_upper<S>(G, sR1);
     inv_upper<S>(sR1, sR1I);
   }
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x < S * S) {
+  if (wg_id == 0 && threadIdx.x < S * S) {
     a.log[L_R1 * S * S + threadIdx.x] = sR1[threadIdx.x];
     a.log[L_R1I * S * S + threadIdx.x] = sR1I[threadIdx.x];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (wg_id == 0 && threadIdx.x == 0) {
     double tr = 0.0;
     for (int i = 0; i < S; ++i) tr += G[i * S + i];
     a.log[L_FLAG * S * S + 0] = sratio;
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(stream_threads(S)) void k_chol_gram(StepArgs<T> a) 
   for (int i = 0; i < S * S; ++i) ri[i] = uniform_d(sR1I[i]);
   double acc[S * S];
   zero<S>(acc);
-  const int str = gridDim.x * stream_threads(S);
+  const int str = wg_cnt * stream_threads(S);
   LYAP_BATCH(r0, a.n) {
     T w[kRPT][S];
     LYAP_FOR_U {
@@ -210,25 +211,24 @@ __global__ __launch_bounds__(stream_threads(S)) void k_chol_gram(StepArgs<T> a) 
       }
     }
   }
-  write_partial<S * S, stream_threads(S)>(acc, red, a.pout);
+  write_partial_at<S * S, stream_threads(S)>(acc, red, a.pout, wg_id);
 }
 
 // K7: G2 (logged), R2 = chol(G2), tau_{j+1,j} = R2 R1, V_{j+1} = W (R1^{-1} R2^{-1});
 // workgroup 0 writes the log and the T_m band (diagonal block sym(alpha2 +
 // alpha4), sub-diagonal block tau_{j+1,j}).
 template <typename T, int S>
-__global__ __launch_bounds__(stream_threads(S)) void k_chol_store(StepArgs<T> a) {
-  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+__device__ __forceinline__ void chol_store_body(const StepArgs<T>& a, int wg_id, int wg_cnt, double* red) {
   __shared__ double sRI[S * S];
   double G[S * S];
-  take_gram<S>(a.pin, a.nparts, red, G, a.log + L_G2 * S * S);
+  take_gram<S>(a.pin, a.nparts, red, G, a.log + L_G2 * S * S, wg_id == 0);
   if (threadIdx.x == 0) {
     double R2[S * S], R2i[S * S], R[S * S];
     const double ratio = chol_upper<S>(G, R2);
     inv_upper<S>(R2, R2i);
     const double* L = a.log;
     mul_upper<S>(L + L_R1I * S * S, R2i, sRI);
-    if (blockIdx.x == 0) {
+    if (wg_id == 0) {
       double* Lw = a.log;
       mul_upper<S>(R2, L + L_R1 * S * S, R);
       for (int i = 0; i < S * S; ++i) {
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(stream_threads(S)) void k_chol_store(StepArgs<T> a)
   double ri[S * S];
 #pragma unroll
   for (int i = 0; i < S * S; ++i) ri[i] = uniform_d(sRI[i]);
-  const int str = gridDim.x * stream_threads(S);
+  const int str = wg_cnt * stream_threads(S);
   LYAP_BATCH(r0, a.n) {
     T w[kRPT][S];
     LYAP_FOR_U {
@@ -273,15 +273,15 @@ __global__ __launch_bounds__(stream_threads(S)) void k_chol_store(StepArgs<T> a)
 
 // Second pass: the whole step from the log, one kernel (V_{j+1} may alias V_{j-1}).
 template <typename T, int S>
-__global__ __launch_bounds__(stream_threads(S)) void k_replay(OpDev<T> op, int n, const T* Vprev, const T* Vcur, T* Vnext,
-                                                    const double* log) {
+__device__ __forceinline__ void replay_body(const OpDev<T>& op, int n, const T* Vprev, const T* Vcur, T* Vnext,
+                                            const double* log, int wg_id, int wg_cnt) {
   double a1[S * S], a2[S * S], a3[S * S], a4[S * S], ri[S * S];
   load_coef<S>(log + L_A1 * S * S, a1);
   load_coef<S>(log + L_A2 * S * S, a2);
   load_coef<S>(log + L_A3 * S * S, a3);
   load_coef<S>(log + L_A4 * S * S, a4);
   load_coef<S>(log + L_RI * S * S, ri);
-  const int str = gridDim.x * stream_threads(S);
+  const int str = wg_cnt * stream_threads(S);
   LYAP_BATCH(r0, n) {
     T w[kRPT][S], x[kRPT][S], y[kRPT][S];
     LYAP_FOR_U {
@@ -305,6 +305,37 @@ __global__ __launch_bounds__(stream_threads(S)) void k_replay(OpDev<T> op, int n
       }
     }
   }
+}
+
+// ------------------------------------------------------------------ single-problem kernels
+template <typename T, int S>
+__global__ __launch_bounds__(stream_threads(S)) void k_spmm_gram(StepArgs<T> a) {
+  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+  spmm_gram_body<T, S>(a, blockIdx.x, gridDim.x, red);
+}
+
+template <typename T, int S>
+__global__ __launch_bounds__(stream_threads(S)) void k_upd_gram(StepArgs<T> a, const T* X, const T* Y, int slot_in) {
+  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+  upd_gram_body<T, S>(a, X, Y, slot_in, blockIdx.x, gridDim.x, red);
+}
+
+template <typename T, int S>
+__global__ __launch_bounds__(stream_threads(S)) void k_chol_gram(StepArgs<T> a) {
+  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+  chol_gram_body<T, S>(a, blockIdx.x, gridDim.x, red);
+}
+
+template <typename T, int S>
+__global__ __launch_bounds__(stream_threads(S)) void k_chol_store(StepArgs<T> a) {
+  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+  chol_store_body<T, S>(a, blockIdx.x, gridDim.x, red);
+}
+
+template <typename T, int S>
+__global__ __launch_bounds__(stream_threads(S)) void k_replay(OpDev<T> op, int n, const T* Vprev, const T* Vcur,
+                                                              T* Vnext, const double* log) {
+  replay_body<T, S>(op, n, Vprev, Vcur, Vnext, log, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------ initial block: C = V_1 gamma
@@ -334,7 +365,7 @@ __global__ __launch_bounds__(stream_threads(S)) void k_init_chol_gram(const doub
   __shared__ double sR1[S * S], sR1I[S * S];
   __shared__ double sratio;
   double G[S * S];
-  take_gram<S>(pin, nparts, red, G, glog + L_G1 * S * S);
+  take_gram<S>(pin, nparts, red, G, glog + L_G1 * S * S, blockIdx.x == 0);
   if (threadIdx.x == 0) {
     sratio = chol_upper<S>(G, sR1);
     inv_upper<S>(sR1, sR1I);
@@ -386,7 +417,7 @@ __global__ __launch_bounds__(stream_threads(S)) void k_init_store(const double* 
   __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
   __shared__ double sRI[S * S];
   double G[S * S];
-  take_gram<S>(pin, nparts, red, G, glog + L_G2 * S * S);
+  take_gram<S>(pin, nparts, red, G, glog + L_G2 * S * S, blockIdx.x == 0);
   if (threadIdx.x == 0) {
     double R2[S * S], R2i[S * S], R[S * S];
     const double ratio = chol_upper<S>(G, R2);
@@ -483,6 +514,77 @@ __global__ __launch_bounds__(kBlock) void k_apply(OpDev<T> op, const T* V, T* W)
   }
 }
 
+// ------------------------------------------------------------------ grouped kernels
+template <typename T, int S>
+__device__ __forceinline__ StepArgs<T> batch_args(const BatchDesc<T>& d, int j, bool flip) {
+  StepArgs<T> a{};
+  a.op = d.op;
+  a.n = d.n;
+  const bool even = (j % 2) == 0;
+  a.Vcur = even ? d.Vb1 : d.Vb0;
+  T* other = even ? d.Vb0 : d.Vb1;
+  a.Vprev = other;
+  a.Vnext = other;
+  a.W = d.W;
+  a.log = d.log + (size_t)j * log_stride(S);
+  a.band = d.band;
+  a.j = j;
+  a.pin = flip ? d.partA : d.partB;
+  a.pout = flip ? d.partB : d.partA;
+  a.nparts = d.nparts;
+  a.flags = d.flags;
+  return a;
+}
+
+template <typename T, int S>
+__global__ __launch_bounds__(stream_threads(S)) void kb_spmm_gram(const BatchDesc<T>* d, const int2* map, int j) {
+  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+  const int2 pm = map[blockIdx.x];
+  const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, false);
+  spmm_gram_body<T, S>(a, pm.y, a.nparts, red);
+}
+
+// mode 0: X = V_{j-1}, Y = V_j; 1: X = V_j, Y = V_{j-1}; 2: as 0; 3: X = V_j, Y = none
+template <typename T, int S>
+__global__ __launch_bounds__(stream_threads(S)) void kb_upd_gram(const BatchDesc<T>* d, const int2* map, int j,
+                                                                 int mode, int slot, int flip) {
+  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+  const int2 pm = map[blockIdx.x];
+  const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, flip != 0);
+  const T* X = (mode == 0 || mode == 2) ? a.Vprev : a.Vcur;
+  const T* Y = mode == 3 ? nullptr : ((mode == 1) ? a.Vprev : a.Vcur);
+  upd_gram_body<T, S>(a, X, Y, slot, pm.y, a.nparts, red);
+}
+
+template <typename T, int S>
+__global__ __launch_bounds__(stream_threads(S)) void kb_chol_gram(const BatchDesc<T>* d, const int2* map, int j) {
+  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+  const int2 pm = map[blockIdx.x];
+  const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, true);
+  chol_gram_body<T, S>(a, pm.y, a.nparts, red);
+}
+
+template <typename T, int S>
+__global__ __launch_bounds__(stream_threads(S)) void kb_chol_store(const BatchDesc<T>* d, const int2* map, int j) {
+  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+  const int2 pm = map[blockIdx.x];
+  const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, false);
+  chol_store_body<T, S>(a, pm.y, a.nparts, red);
+}
+
+// Second pass step i of every problem in the map: V_{i+1} from V_i, V_{i-1}
+// and log entry i, in the problem's ring of R blocks.
+template <typename T, int S>
+__global__ __launch_bounds__(stream_threads(S)) void kb_replay(const BatchDesc<T>* d, const int2* map, int i) {
+  const int2 pm = map[blockIdx.x];
+  const BatchDesc<T>& b = d[pm.x];
+  const size_t nS = (size_t)b.n * S;
+  const T* Vprev = i > 0 ? b.ring + (size_t)((i - 1) % b.R) * nS : b.zero;
+  const T* Vcur = b.ring + (size_t)(i % b.R) * nS;
+  T* Vnext = b.ring + (size_t)((i + 1) % b.R) * nS;
+  replay_body<T, S>(b.op, b.n, Vprev, Vcur, Vnext, b.log + (size_t)i * log_stride(S), pm.y, b.nparts);
+}
+
 // ------------------------------------------------------------------ host launchers
 #define LYAP_SWITCH_S(Sv, ...)                                  \
   switch (Sv) {                                                 \
@@ -576,6 +678,38 @@ void launch_zflush(const void* const* blocks, int nb, int n, int S, const double
 int zflush_max_blocks(int) { return 64; }
 
 template <typename T>
+void launch_batch_step(const BatchDesc<T>* d, const int2* map, int nwg, int S, int j, hipStream_t st,
+                       KernelTimer* kt) {
+  if (nwg <= 0) return;
+  auto mark = [&](int k) { if (kt) kt->mark(k); };
+  LYAP_SWITCH_S(S, {
+    constexpr int NT = stream_threads(S);
+    mark(LYAP_K_SPMM_GRAM);
+    hipLaunchKernelGGL((kb_spmm_gram<T, S>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+    mark(LYAP_K_UPD_GRAM);
+    hipLaunchKernelGGL((kb_upd_gram<T, S>), dim3(nwg), dim3(NT), 0, st, d, map, j, 0, (int)L_A1, 1);
+    mark(LYAP_K_UPD_GRAM);
+    hipLaunchKernelGGL((kb_upd_gram<T, S>), dim3(nwg), dim3(NT), 0, st, d, map, j, 1, (int)L_A2, 0);
+    mark(LYAP_K_UPD_GRAM);
+    hipLaunchKernelGGL((kb_upd_gram<T, S>), dim3(nwg), dim3(NT), 0, st, d, map, j, 2, (int)L_A3, 1);
+    mark(LYAP_K_UPD_GRAM);
+    hipLaunchKernelGGL((kb_upd_gram<T, S>), dim3(nwg), dim3(NT), 0, st, d, map, j, 3, (int)L_A4, 0);
+    mark(LYAP_K_CHOL_GRAM);
+    hipLaunchKernelGGL((kb_chol_gram<T, S>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+    mark(LYAP_K_CHOL_STORE);
+    hipLaunchKernelGGL((kb_chol_store<T, S>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+  });
+  LYAP_LAUNCHED("batched lanczos step");
+}
+
+template <typename T>
+void launch_batch_replay(const BatchDesc<T>* d, const int2* map, int nwg, int S, int i, hipStream_t st) {
+  if (nwg <= 0) return;
+  LYAP_SWITCH_S(S, { hipLaunchKernelGGL((kb_replay<T, S>), dim3(nwg), dim3(stream_threads(S)), 0, st, d, map, i); });
+  LYAP_LAUNCHED("batched replay");
+}
+
+template <typename T>
 void launch_apply(const OpDev<T>& op, int S, const T* V, T* W, int grid, hipStream_t st) {
   LYAP_SWITCH_S(S, { hipLaunchKernelGGL((k_apply<T, S>), dim3(grid), dim3(kBlock), 0, st, op, V, W); });
   LYAP_LAUNCHED("apply");
@@ -589,7 +723,9 @@ void launch_apply(const OpDev<T>& op, int S, const T* V, T* W, int grid, hipStre
   template void launch_init_store<T>(const double*, int64_t, int, int, const double*, T*, int, hipStream_t);  \
   template void launch_zflush<T>(const void* const*, int, int, int, const double*, int, double*, int64_t, int, \
                                  hipStream_t);                                                               \
-  template void launch_apply<T>(const OpDev<T>&, int, const T*, T*, int, hipStream_t);
+  template void launch_apply<T>(const OpDev<T>&, int, const T*, T*, int, hipStream_t);                     \
+  template void launch_batch_step<T>(const BatchDesc<T>*, const int2*, int, int, int, hipStream_t, KernelTimer*); \
+  template void launch_batch_replay<T>(const BatchDesc<T>*, const int2*, int, int, int, hipStream_t);
 
 LYAP_INST(float)
 LYAP_INST(double)

@@ -111,4 +111,34 @@ void launch_zflush(const void* const* blocks, int nb, int n, int S, const double
 template <typename T> void launch_apply(const OpDev<T>& op, int S, const T* V, T* W, int grid, hipStream_t st);
 int zflush_max_blocks(int S);
 
+// ------------------------------------------------------------------ grouped launches
+// Per-problem state of a grouped (batched) launch: every problem advances by
+// the same step j, so the step's blocks and log entry follow from j (V_{j+1}
+// overwrites V_{j-1}; V_j is Vb1 for even j, Vb0 for odd j).
+template <typename T>
+struct BatchDesc {
+  OpDev<T> op;
+  int n;
+  int nparts;        // workgroups of this problem in every grouped launch
+  T* Vb0;
+  T* Vb1;
+  T* W;
+  double* log;       // step 0 of the coefficient log
+  double* band;
+  double* partA;
+  double* partB;
+  int* flags;
+  T* ring;           // second pass: R blocks of n x S
+  int R;
+  const T* zero;     // an n x S block of zeros
+};
+
+// map[w] = (problem, workgroup index within the problem) for every workgroup
+// of a grouped launch over the problems of one block width S.
+template <typename T>
+void launch_batch_step(const BatchDesc<T>* d, const int2* map, int nwg, int S, int j, hipStream_t st,
+                       KernelTimer* kt = nullptr);
+template <typename T>
+void launch_batch_replay(const BatchDesc<T>* d, const int2* map, int nwg, int S, int i, hipStream_t st);
+
 }  // namespace lyap

@@ -1,0 +1,120 @@
+"""GPU parity of lyap_solve_batched (grouped launches over many problems)
+against the CPU FP64 oracle, against the single-problem path, and on the
+full 64-problem batched workload by properties that hold at any size."""
+import numpy as np
+import pytest
+
+from workloads import laplace2d, fv3d, gaussian_C, batch_c5
+from oracle import krylov as K
+from oracle import dense as D
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _b():
+    from paper_1602_05033_amd import binding
+    return binding
+
+
+def _dev(C):
+    return torch.from_numpy(np.ascontiguousarray(C)).cuda()
+
+
+def _small_batch():
+    specs = [(20, 0.0, 1), (37, 3.0, 2), (31, 1.5, 4), (23, 0.0, 2), (41, 7.0, 1), (26, 2.0, 4)]
+    return [(laplace2d(N, shift=c), gaussian_C(N * N, s, 100 + i)) for i, (N, c, s) in enumerate(specs)]
+
+
+def _explicit_residual_gpu(b, dop, Z, C, storage):
+    n, t = Z.shape
+    AZ = torch.empty_like(Z)
+    for c0 in range(0, t, 8):
+        AZ[:, c0:c0 + 8] = b.op_apply(dop, Z[:, c0:c0 + 8].contiguous(), b.STORE_F64)
+    R = torch.linalg.qr(torch.cat([AZ, Z, C], dim=1), mode="r")[1]
+    s = C.shape[1]
+    Phi = torch.zeros(2 * t + s, 2 * t + s, dtype=torch.float64, device=Z.device)
+    Phi[:t, t:2 * t] = torch.eye(t, dtype=torch.float64, device=Z.device)
+    Phi[t:2 * t, :t] = torch.eye(t, dtype=torch.float64, device=Z.device)
+    Phi[2 * t:, 2 * t:] = torch.eye(s, dtype=torch.float64, device=Z.device)
+    return float(torch.linalg.norm(R @ Phi @ R.T))
+
+
+@pytest.mark.parametrize("tune", [False, True])
+def test_batched_parity_fp64(lib, tune):
+    b = _b()
+    probs = _small_batch()
+    dops = [b.device_op(op) for op, _ in probs]
+    Cs = [_dev(C) for _, C in probs]
+    st, sols = b.lyap_solve_batched(dops, Cs, tune=tune, tol=1e-8, check_every=1)
+    assert st == b.OK
+    for (op, C), sol in zip(probs, sols):
+        A = op.to_scipy()
+        ref = K.lyap_std(A, C, tol=1e-8, check_every=1)
+        assert sol.status == b.OK and sol.m == ref.m, (op.n, sol.m, ref.m)
+        assert sol.hist_m == [h["m"] for h in ref.hist]
+        for g, r in zip(sol.hist_res, ref.hist):
+            assert abs(g - r["res"]) <= 1e-6 * r["res"] + 1e-14
+        Z = sol.Z.cpu().numpy()
+        X = D.lyap_eig(A.toarray(), C)
+        assert K.lowrank_vs_dense_error(Z, X) <= 1e-7
+        assert K.factor_error(Z, ref.Z) <= 1e-7
+
+
+def test_batched_matches_single_problem_path(lib):
+    b = _b()
+    probs = _small_batch()[:4]
+    dops = [b.device_op(op) for op, _ in probs]
+    Cs = [_dev(C) for _, C in probs]
+    st, sols = b.lyap_solve_batched(dops, Cs, tol=1e-8, check_every=0, storage=b.STORE_F32)
+    assert st == b.OK
+    for dop, C, sol in zip(dops, Cs, sols):
+        one = b.lyap_solve(dop, C, tol=1e-8, check_every=0, storage=b.STORE_F32)
+        assert sol.m == one.m and sol.hist_m == one.hist_m
+        for a, c in zip(sol.hist_res, one.hist_res):
+            assert abs(a - c) <= 1e-4 * c
+        Za, Zb = sol.Z.cpu().numpy(), one.Z.cpu().numpy()
+        assert K.factor_error(Za, Zb) <= 1e-6
+
+
+def test_batched_mixed_operators_and_errors(lib):
+    """A 3D variable-coefficient operator and a CSR operator in one batch;
+    argument errors are reported without device work."""
+    b = _b()
+    ops = [fv3d(9, 1.0, 3), laplace2d(19)]
+    dops = [b.device_op(ops[0]), b.device_op(ops[1], as_csr=True)]
+    Cs = [_dev(gaussian_C(ops[0].n, 2, 7)), _dev(gaussian_C(ops[1].n, 1, 8))]
+    st, sols = b.lyap_solve_batched(dops, Cs, tol=1e-9)
+    assert st == b.OK
+    for op, C, sol in zip(ops, Cs, sols):
+        A = op.to_scipy()
+        X = D.lyap_eig(A.toarray(), C.cpu().numpy())
+        assert K.lowrank_vs_dense_error(sol.Z.cpu().numpy(), X) <= 1e-7
+    with pytest.raises(b.LyapError):
+        b.lyap_solve_batched(dops, Cs, two_pass=False)
+    with pytest.raises(b.LyapError):
+        b.lyap_solve_batched(dops, [Cs[0], torch.zeros_like(Cs[1])])
+    st, sols = b.lyap_solve_batched(dops, Cs, tol=1e-14, max_iter=5, raise_on_error=False)
+    assert st == b.NOT_CONVERGED and all(s.m == 5 and s.status == b.NOT_CONVERGED for s in sols)
+
+
+def test_batched_full_workload(lib):
+    """The full batched workload: 64 equations, N_i in 64..512, shifts in
+    [0, 10), s_i in {1, 2, 4}, FP32 storage, tol 1e-8 each.  Every problem
+    converges by Proposition 1, its explicit FP64 residual (QR of [AZ, Z, C] on
+    the device) agrees up to the FP32 floor, and a sample of problems matches
+    the single-problem path."""
+    b = _b()
+    probs = batch_c5(64, 6)
+    dops = [b.device_op(op) for op, _ in probs]
+    Cs = [_dev(C) for _, C in probs]
+    st, sols = b.lyap_solve_batched(dops, Cs, tune=True, tol=1e-8, storage=b.STORE_F32, check_every=0)
+    assert st == b.OK
+    for dop, C, sol in zip(dops, Cs, sols):
+        assert sol.status == b.OK and sol.res <= 1e-8
+        ex = _explicit_residual_gpu(b, dop, sol.Z, C, b.STORE_F32) / sol.beta ** 2
+        assert ex <= 2e-7, ex
+    for i in (0, 17, 40, 63):
+        one = b.lyap_solve(dops[i], Cs[i], tol=1e-8, storage=b.STORE_F32, check_every=0)
+        assert abs(one.m - sols[i].m) <= max(5, 0.05 * one.m)
