@@ -58,7 +58,10 @@ def test_batched_parity_fp64(lib, tune):
             assert abs(g - r["res"]) <= 1e-6 * r["res"] + 1e-14
         Z = sol.Z.cpu().numpy()
         X = D.lyap_eig(A.toarray(), C)
-        assert K.lowrank_vs_dense_error(Z, X) <= 1e-7
+        # the factor error is bounded by ||R|| / (2 |lambda_min(A)|), not by tol:
+        # hold the GPU to the oracle's own error at the same m
+        err_ref = K.lowrank_vs_dense_error(ref.Z, X)
+        assert K.lowrank_vs_dense_error(Z, X) <= max(1e-7, 1.05 * err_ref)
         assert K.factor_error(Z, ref.Z) <= 1e-7
 
 
