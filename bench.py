@@ -40,10 +40,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--explicit-residual", action="store_true", help="also report the explicit FP64 residual")
-    ap.add_argument("--workload", choices=["std", "ext", "sylv"], default="std",
+    ap.add_argument("--workload", choices=["std", "ext", "sylv", "batch"], default="std",
                     help="std: standard Krylov + two-pass on the 2D Laplacian (the headline); "
                          "ext: extended Krylov + inner PCG on the 100^3 lognormal finite-volume operator; "
-                         "sylv: Sylvester, 700^2 Laplacian and 80^3 lognormal FV, s=2")
+                         "sylv: Sylvester, 700^2 Laplacian and 80^3 lognormal FV, s=2; "
+                         "batch: 64 shifted Laplacians N_i in 64..512, s_i in {1,2,4}, grouped launches")
     return ap.parse_args()
 
 
@@ -272,6 +273,63 @@ def main_sylv(args):
     print(json.dumps(out), flush=True)
 
 
+def main_batch(args):
+    import numpy as np
+    import torch
+    from paper_1602_05033_amd import binding as b
+    from workloads import batch_c5
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    b.load()
+    dev = torch.device("cuda:0")
+    probs = batch_c5(64, 6)
+    dops = [b.device_op(op, device=dev) for op, _ in probs]
+    Cs = [torch.from_numpy(C).to(dev) for _, C in probs]
+    storage = b.STORE_F32 if args.storage == "f32" else b.STORE_F64
+    kw = dict(tol=1e-8, storage=storage, check_every=0, tune=True)
+    for _ in range(args.warmup):
+        b.lyap_solve_batched(dops, Cs, **kw)
+    torch.cuda.synchronize()
+    runs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        runs.append(b.lyap_solve_batched(dops, Cs, profile=True, **kw))
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1000.0 / args.steps
+    st, sols = runs[-1]
+    assert st == b.OK, st
+    agg = aggregate([r[1][0] for r in runs])
+    # algorithmic bytes of one grouped step over all problems (per-row model of the single-problem kernels)
+    nsb_tot = sum(op.n * C.shape[1] * (4 if storage == b.STORE_F32 else 8) for op, C in probs)
+    per_kind = {"spmm_gram": 3.0, "upd_gram": 3.75, "chol_gram": 1.0, "chol_store": 2.0, "replay": 3.0}
+    steps_all = sum(s.m for s in sols)
+    for k, f in per_kind.items():
+        if k in agg:
+            # launches cover a shrinking set of problems; use the step-weighted mean bytes per launch
+            n_launch = agg[k]["n"]
+            per_step_launches = {"upd_gram": 4}.get(k, 1)
+            tot_bytes = f * sum(op.n * C.shape[1] * (4 if storage == b.STORE_F32 else 8) * s.m
+                                for (op, C), s in zip(probs, sols)) * per_step_launches * len(runs)
+            agg[k]["bytes_per_launch"] = tot_bytes / n_launch
+    n_tot = sum(op.n for op, _ in probs)
+    out = {
+        "metric": "time to rel. residual 1e-8 for all 64 equations of the batch (grouped launches, two-pass Z)",
+        "value": round(ms_per_step / 1000.0, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 storage / f64 reductions" if storage == b.STORE_F32 else "f64", "data": "synthetic",
+        "config": {"workload": f"64 Lyapunov equations A_i = -(5-point Laplacian N_i^2 + c_i I), N_i ~ U{{64..512}}, "
+                               f"c_i ~ U[0,10), s_i ~ U{{1,2,4}}, master seed 6, sum n_i = {n_tot}, tol 1e-8",
+                   "count": 64, "sum_n": n_tot, "storage": args.storage, "tune": True},
+        "result": {"m": [s.m for s in sols], "t": [s.t for s in sols], "total_steps": steps_all,
+                   "phases_ms": {k: round(v, 2) for k, v in sols[0].times_ms.items()}},
+        "kernels": kernel_table(agg),
+        "roofline": roofline(agg, ("spmm_gram", "upd_gram", "chol_gram", "chol_store", "replay")),
+        "block_bytes_sum": nsb_tot,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -282,6 +340,8 @@ def main():
         return main_ext(args)
     if args.workload == "sylv":
         return main_sylv(args)
+    if args.workload == "batch":
+        return main_batch(args)
     import numpy as np
     import torch
     from paper_1602_05033_amd import binding as b
