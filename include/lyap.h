@@ -110,8 +110,9 @@ typedef struct lyap_opts {
                            0: store the whole basis (memory s*m vectors)               */
   double trunc_eps;     /* < 0: default truncation threshold (see lyap_solve);
                            >= 0: absolute threshold on ||Sigma_2||_F               */
-  int32_t inner_pc;     /* extended Krylov inner CG preconditioner: LYAP_PC_NONE or
-                           LYAP_PC_JACOBI (others: LYAP_E_UNSUPPORTED)            */
+  int32_t inner_pc;     /* extended Krylov inner CG preconditioner: LYAP_PC_NONE,
+                           LYAP_PC_JACOBI or LYAP_PC_LEARNED (see below);
+                           LYAP_PC_IC0: LYAP_E_UNSUPPORTED                        */
   double inner_tol;     /* inner solves accepted when true ||b-Ax||/||b|| <= this  */
   int32_t inner_max_iter;
   int32_t flush_blocks; /* second pass: blocks buffered per Z update (0 = default)  */
@@ -331,6 +332,35 @@ lyap_status lyap_inner_solve(const lyap_op* A, const double* B, int64_t ldb, dou
  */
 lyap_status lyap_solve_batched(int32_t count, const lyap_op* A, const double* const* C, const int32_t* s,
                                const int64_t* ldc, const lyap_opts* opts, int32_t tune, lyap_result* out);
+
+/* ------------------------------------------------------------------ learned preconditioner
+ * Inner solves of the extended Krylov method with opts->inner_pc =
+ * LYAP_PC_LEARNED (stencil operators, s = 1): the first inner solve runs
+ * Jacobi-PCG and keeps its residual / iterate every 32 iterations (at most 16);
+ * the network below is then trained for 200 Adam steps (learning rate 2e-3) on
+ * those pairs, and later solves run flexible CG with z = M(r):
+ *   M r = D^{-1} r + s (K^T K)(s r),  s = sqrt(D^{-1}),  D = diag(-A),
+ *   K(u) = conv2(conv1([u, f u])),  f = log(-diag A) - mean,
+ * two 3x3x3 convolutions (2 -> C -> C channels, C = 4, zero padding, no bias)
+ * on the operator's grid, FP32 weights (SplitMix64 seed 0x5eed, uniform in
+ * [-0.05, 0.05)).  M is symmetric positive definite for any weights.  The loss
+ * of a pair (r, e), (-A) e = r, is (M r - e)^T (-A) (M r - e) / e^T (-A) e.
+ * The entry points below expose the pieces for testing; W holds C*2*27 + C*C*27
+ * floats, W1[o][i][t] then W2[o][i][t], t = 9 (dz+1) + 3 (dy+1) + (dx+1).
+ * Vectors are device FP64, length n.
+ */
+void lyap_pcnet_init(int32_t C, uint64_t seed, double scale, float* W);
+lyap_status lyap_pcnet_apply(const lyap_op* A, int32_t C, const float* W, const double* r, double* z, void* stream);
+/* loss of (r, e) and its gradient (host, FP64, same layout as W) */
+lyap_status lyap_pcnet_grad(const lyap_op* A, int32_t C, const float* W, const double* r, const double* e,
+                            double* loss, double* grad, void* stream);
+/* `steps` Adam steps over the pairs in order (pair t mod npairs at step t);
+ * W (host) in/out; losses (host, optional) gets the loss before each step. */
+lyap_status lyap_pcnet_train(const lyap_op* A, int32_t C, float* W, int32_t npairs, const double* const* r,
+                             const double* const* e, int32_t steps, double lr, double* losses, void* stream);
+/* X = A^{-1} B (one column) by flexible CG with M; certified like lyap_inner_solve. */
+lyap_status lyap_pcnet_fcg(const lyap_op* A, int32_t C, const float* W, const double* B, double* X, double eta,
+                           int32_t max_iter, int64_t* iters, double* relres, void* stream);
 
 #ifdef __cplusplus
 }

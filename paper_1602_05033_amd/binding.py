@@ -77,7 +77,8 @@ class SylvResult(ct.Structure):
 # exported symbols declared in include/lyap.h
 EXPORTS = ["lyap_opts_default", "lyap_solve", "sylv_solve", "lyap_result_free", "sylv_result_free",
            "lyap_last_error", "lyap_op_apply", "lyap_op_apply_timed", "lyap_ctri", "lyap_inner_solve",
-           "lyap_solve_batched"]
+           "lyap_solve_batched", "lyap_pcnet_init", "lyap_pcnet_apply", "lyap_pcnet_grad", "lyap_pcnet_train",
+           "lyap_pcnet_fcg"]
 
 
 class LyapError(RuntimeError):
@@ -126,6 +127,21 @@ def load(path: str = LIB_PATH):
                                        ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int64), ct.POINTER(LyapOpts),
                                        ct.c_int32, ct.POINTER(LyapResult)]
     lib.lyap_solve_batched.restype = ct.c_int
+    lib.lyap_pcnet_init.argtypes = [ct.c_int32, ct.c_uint64, ct.c_double, ct.c_void_p]
+    lib.lyap_pcnet_init.restype = None
+    lib.lyap_pcnet_apply.argtypes = [ct.POINTER(LyapOp), ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                     ct.c_void_p]
+    lib.lyap_pcnet_apply.restype = ct.c_int
+    lib.lyap_pcnet_grad.argtypes = [ct.POINTER(LyapOp), ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                    ct.POINTER(ct.c_double), ct.c_void_p, ct.c_void_p]
+    lib.lyap_pcnet_grad.restype = ct.c_int
+    lib.lyap_pcnet_train.argtypes = [ct.POINTER(LyapOp), ct.c_int32, ct.c_void_p, ct.c_int32,
+                                     ct.POINTER(ct.c_void_p), ct.POINTER(ct.c_void_p), ct.c_int32, ct.c_double,
+                                     ct.c_void_p, ct.c_void_p]
+    lib.lyap_pcnet_train.restype = ct.c_int
+    lib.lyap_pcnet_fcg.argtypes = [ct.POINTER(LyapOp), ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_double,
+                                   ct.c_int32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double), ct.c_void_p]
+    lib.lyap_pcnet_fcg.restype = ct.c_int
     _LIB = lib
     return lib
 
@@ -457,3 +473,64 @@ def sylv_solve(dopA: DeviceOp, dopB: DeviceOp, C1, C2, raise_on_error: bool = Tr
         return sol
     finally:
         lib.sylv_result_free(ct.byref(r))
+
+
+# ------------------------------------------------------------------ learned preconditioner components
+def pcnet_init(C: int, seed: int, scale: float) -> np.ndarray:
+    """SplitMix64 initial weights (host function of the library)."""
+    lib = load()
+    n = C * 2 * 27 + C * C * 27
+    W = np.zeros(n, dtype=np.float32)
+    lib.lyap_pcnet_init(C, seed, scale, W.ctypes.data_as(ct.c_void_p))
+    return W
+
+
+def _stream(dev):
+    import torch
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def pcnet_apply(dop: DeviceOp, C: int, W: np.ndarray, r):
+    import torch
+    lib = load()
+    Wf = np.ascontiguousarray(W, dtype=np.float32)
+    z = torch.empty_like(r)
+    _check(lib.lyap_pcnet_apply(ct.byref(dop.c), C, Wf.ctypes.data_as(ct.c_void_p), ct.c_void_p(r.data_ptr()),
+                                ct.c_void_p(z.data_ptr()), ct.c_void_p(_stream(r.device))))
+    return z
+
+
+def pcnet_grad(dop: DeviceOp, C: int, W: np.ndarray, r, e):
+    lib = load()
+    Wf = np.ascontiguousarray(W, dtype=np.float32)
+    g = np.zeros(Wf.shape[0])
+    L = ct.c_double(0.0)
+    _check(lib.lyap_pcnet_grad(ct.byref(dop.c), C, Wf.ctypes.data_as(ct.c_void_p), ct.c_void_p(r.data_ptr()),
+                               ct.c_void_p(e.data_ptr()), ct.byref(L), g.ctypes.data_as(ct.c_void_p),
+                               ct.c_void_p(_stream(r.device))))
+    return L.value, g
+
+
+def pcnet_train(dop: DeviceOp, C: int, W: np.ndarray, rs, es, steps: int, lr: float):
+    lib = load()
+    Wf = np.array(W, dtype=np.float32)
+    P = len(rs)
+    rp = (ct.c_void_p * P)(*[r.data_ptr() for r in rs])
+    ep = (ct.c_void_p * P)(*[e.data_ptr() for e in es])
+    losses = np.zeros(max(steps, 1))
+    _check(lib.lyap_pcnet_train(ct.byref(dop.c), C, Wf.ctypes.data_as(ct.c_void_p), P, rp, ep, steps, lr,
+                                losses.ctypes.data_as(ct.c_void_p), ct.c_void_p(_stream(rs[0].device))))
+    return Wf, losses[:steps]
+
+
+def pcnet_fcg(dop: DeviceOp, C: int, W: np.ndarray, B, eta: float = 1e-12, max_iter: int = 5000):
+    import torch
+    lib = load()
+    Wf = np.ascontiguousarray(W, dtype=np.float32)
+    X = torch.empty_like(B)
+    it = ct.c_int64(0)
+    rel = ct.c_double(0.0)
+    st = lib.lyap_pcnet_fcg(ct.byref(dop.c), C, Wf.ctypes.data_as(ct.c_void_p), ct.c_void_p(B.data_ptr()),
+                            ct.c_void_p(X.data_ptr()), eta, max_iter, ct.byref(it), ct.byref(rel),
+                            ct.c_void_p(_stream(B.device)))
+    return X, it.value, rel.value, st

@@ -16,17 +16,27 @@
 // V_m (Q_m Y-check) from the stored basis.
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <type_traits>
 
 #include "check.hpp"
 #include "lanczos.hpp"
 #include "pcg.hpp"
+#include "pcnet.hpp"
 #include "small.hpp"
 #include "solver.hpp"
 
 namespace lyap {
 
 constexpr int kExtThreads = 256;
+
+// Learned inner preconditioner: width, SplitMix64 seed and scale of the
+// initial weights, harvest cadence and count, Adam steps and learning rate.
+constexpr int kPcC = 4;
+constexpr uint64_t kPcSeed = 0x5eedULL;
+constexpr double kPcScale = 0.05;
+constexpr int kPcEvery = 32, kPcKeep = 16, kPcSteps = 200;
+constexpr double kPcLr = 2e-3;
 
 // C (n x S column-major, leading dimension ldc) -> row-interleaved n x S.
 template <int S>
@@ -302,7 +312,38 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
   // ---- start: [C, A^{-1} C] = V_1 R, gamma = R[:, :s]
   const auto t_pass1 = Clock::now();
   hipLaunchKernelGGL((k_ext_pack<S>), dim3(eg), dim3(kBlock), 0, st, C, ldc, n, Bs.as<double>());
+  std::unique_ptr<PcNetGpu> net;
+  double train_ms = 0.0;
+  if (o.inner_pc == LYAP_PC_LEARNED) {
+    net = std::make_unique<PcNetGpu>(op.dev, kPcC, st);
+    std::vector<float> W(pcnet_param_count(kPcC));
+    pcnet_init_weights(kPcC, kPcSeed, kPcScale, W.data());
+    net->set_weights(W.data());
+    cg.harvest(kPcEvery, kPcKeep);
+  }
   cg.solve(Bs.as<double>(), Xs.as<double>(), &kt);
+  if (net) {
+    // train on the start solve's own iterates, then switch to flexible CG
+    const auto t_tr = Clock::now();
+    std::vector<int> use;
+    std::vector<double> eAe;
+    for (int i = 0; i < cg.pairs(); ++i) {
+      const double v = net->energy(cg.pair_e(i));
+      if (v > 0.0) {
+        use.push_back(i);
+        eAe.push_back(v);
+      }
+    }
+    LYAP_REQUIRE(!use.empty(), LYAP_E_INNER, "no training pairs from the first inner solve");
+    for (int t = 0; t < kPcSteps; ++t) {
+      const int q = t % (int)use.size();
+      net->grad(cg.pair_r(use[q]), cg.pair_e(use[q]), eAe[q], false);
+      net->adam(kPcLr);
+    }
+    LYAP_HIP(hipStreamSynchronize(st));
+    train_ms = ms_since(t_tr);
+    cg.set_net(net.get());
+  }
   hipLaunchKernelGGL((k_ext_merge<S>), dim3(eg), dim3(kBlock), 0, st, Bs.as<double>(), S, Xs.as<double>(), n,
                      W.as<double>());
   LYAP_LAUNCHED("ext start");
@@ -476,6 +517,7 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
   out->n_inner = cs.solves;
   out->times_ms[LYAP_T_PASS1] = pass1_ms;
   out->times_ms[LYAP_T_INNER] = cs.ms;
+  out->times_ms[LYAP_T_TRAIN] = train_ms;
   out->times_ms[LYAP_T_CHECKS] = check_ms;
   out->times_ms[LYAP_T_FINAL] = fin_ms;
   out->times_ms[LYAP_T_PASS2] = z_ms;

@@ -18,6 +18,7 @@
 #include <cmath>
 
 #include "pcg.hpp"
+#include "pcnet.hpp"
 
 namespace lyap {
 
@@ -49,7 +50,7 @@ __global__ void k_cg_diag(OpDev<double> op, int n, int pc, double* dinv, int* fl
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
     const double d = -op_diag<double>(op, r);
     if (!(d > 0.0)) flag[0] = 1;
-    dinv[r] = pc == LYAP_PC_JACOBI ? 1.0 / d : 1.0;
+    dinv[r] = pc == LYAP_PC_NONE ? 1.0 : 1.0 / d;
   }
 }
 
@@ -210,12 +211,97 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* pin, int npa
   if (threadIdx.x < K) out[threadIdx.x] = red[threadIdx.x];
 }
 
+// ------------------------------------------------------------------ flexible CG (one column)
+// D: beta = -(z.q_old) / (p_old.q_old) (0 at it = 0); p = z + beta p_old;
+//    q = (-A) p (rows of p recomputed from z, p_old); partials p.q, p.r
+template <int NT>
+__global__ __launch_bounds__(NT) void k_fcg_dir(OpDev<double> op, const double* __restrict__ z,
+                                                const double* __restrict__ pold, double* __restrict__ pnew,
+                                                double* __restrict__ q, const double* __restrict__ r, CgIter* log,
+                                                int it, int first, double* state, double eta2, const double* partR,
+                                                const double* partZ, int nparts, double* pout, int n) {
+  __shared__ double red[pow2_at_least(2) * (NT / 64)];
+  reduce_partials<2, NT>(partR, nparts, red);
+  const double rr = uniform_d(red[1]);
+  __syncthreads();
+  double zq = 0.0;
+  if (it > 0) {
+    reduce_partials<1, NT>(partZ, nparts, red);
+    zq = uniform_d(red[0]);
+    __syncthreads();
+  }
+  const double thr = (first && it == 0) ? eta2 * rr : uniform_d(state[0]);
+  const bool active = rr > thr;
+  const double pq_old = it > 0 ? uniform_d(log[it - 1].sigma[0]) : 1.0;
+  const double beta = (active && it > 0 && pq_old > 0.0) ? -zq / pq_old : 0.0;
+  const double mask = active ? 1.0 : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (first && it == 0) state[0] = thr;
+    log[it].rr[0] = rr;
+  }
+  const double* po = it > 0 ? pold : nullptr;
+  auto prow = [&](int i) -> double {
+    const double zi = z[i];
+    return mask * (po ? fma(beta, po[i], zi) : zi);
+  };
+  double acc[2] = {0.0, 0.0};
+  for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+    const double pi = prow(i);
+    pnew[i] = pi;
+    double w[1];
+    op_row_fn<double, 1>(op, i, [&](int j, double (&v)[1]) { v[0] = prow(j); }, w);
+    const double qi = -w[0];
+    q[i] = qi;
+    acc[0] = fma(pi, qi, acc[0]);
+    acc[1] = fma(pi, r[i], acc[1]);
+  }
+  write_partial<2, NT>(acc, red, pout);
+}
+
+// U: alpha = p.r / p.q; x += alpha p; r -= alpha q; partials (r.r, r.r)
+template <int NT>
+__global__ __launch_bounds__(NT) void k_fcg_upd(double* __restrict__ x, double* __restrict__ r,
+                                                const double* __restrict__ p, const double* __restrict__ q, CgIter* log,
+                                                int it, const double* state, const double* pin, int nparts,
+                                                double* pout, int* flag, int n) {
+  __shared__ double red[pow2_at_least(2) * (NT / 64)];
+  reduce_partials<2, NT>(pin, nparts, red);
+  const double pq = uniform_d(red[0]), pr = uniform_d(red[1]);
+  __syncthreads();
+  const bool active = uniform_d(log[it].rr[0]) > uniform_d(state[0]);
+  const double alpha = (active && pq > 0.0) ? pr / pq : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    log[it].sigma[0] = pq;
+    log[it].rho[0] = pr;
+    log[it].alpha[0] = alpha;
+    if (active && !(pq > 0.0)) flag[1] = it + 1;
+  }
+  double acc[2] = {0.0, 0.0};
+  for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+    const double xi = fma(alpha, p[i], x[i]);
+    const double ri = fma(-alpha, q[i], r[i]);
+    x[i] = xi;
+    r[i] = ri;
+    acc[0] = fma(ri, ri, acc[0]);
+  }
+  acc[1] = acc[0];
+  write_partial<2, NT>(acc, red, pout);
+}
+
+// e_i = x* - x_i in place
+__global__ void k_cg_errors(const double* __restrict__ xs, double* __restrict__ xi, int n) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) xi[p] = xs[p] - xi[p];
+}
+
 // ------------------------------------------------------------------ host
 InnerCG::InnerCG(const OpDev<double>& op, int n, int S, int pc, double eta, int max_iter, hipStream_t st)
     : op_(op), n_(n), S_(S), pc_(pc), max_iter_(max_iter), eta_(eta), st_(st) {
   LYAP_REQUIRE(S == 1 || S == 2 || S == 4, LYAP_E_UNSUPPORTED, "inner CG supports 1, 2 or 4 right-hand sides");
-  LYAP_REQUIRE(pc == LYAP_PC_NONE || pc == LYAP_PC_JACOBI, LYAP_E_UNSUPPORTED,
+  LYAP_REQUIRE(pc == LYAP_PC_NONE || pc == LYAP_PC_JACOBI || pc == LYAP_PC_LEARNED, LYAP_E_UNSUPPORTED,
                "inner preconditioner %d is not available in this build", pc);
+  LYAP_REQUIRE(pc != LYAP_PC_LEARNED || S == 1, LYAP_E_UNSUPPORTED,
+               "the learned preconditioner handles one right-hand side per solve");
   LYAP_REQUIRE(eta > 0.0 && eta < 1.0, LYAP_E_ARG, "inner_tol=%g must be in (0,1)", eta);
   LYAP_REQUIRE(max_iter >= 1, LYAP_E_ARG, "inner_max_iter must be >= 1");
   grid_ = stream_grid(n);
@@ -277,7 +363,85 @@ static void cg_launch_true(const OpDev<double>& op, const double* B, const doubl
   LYAP_LAUNCHED("k_sum_partials");
 }
 
+void InnerCG::solve_fcg(const double* B, double* X, KernelTimer* kt) {
+  const auto t0 = Clock::now();
+  constexpr int NT = stream_threads(1);
+  constexpr int kChunk = 16;
+  const double eta_rec = 0.5 * eta_;
+  const double eta2 = eta_rec * eta_rec;
+  if (!z_.p) {
+    z_.alloc((size_t)n_ * sizeof(double));
+    partZ_.alloc((size_t)kSGrid * sizeof(double));
+  }
+  int total = 0;
+  double worst = 0.0;
+  for (int start = 0; start <= kCgRestarts; ++start) {
+    cg_launch_init<1>(B, X, r_.as<double>(), dinv_.as<double>(), n_, start == 0 ? 0 : 1, partA_.as<double>(), grid_,
+                      st_);
+    net_->apply(r_.as<double>(), z_.as<double>(), nullptr, nullptr);
+    int it = 0;
+    bool done = false;
+    while (!done && total + it < max_iter_) {
+      const int it0 = it;
+      const int cnt = std::min(kChunk, max_iter_ - total - it);
+      for (int c = 0; c < cnt; ++c, ++it) {
+        double* pn = (it % 2 == 0) ? p0_.as<double>() : p1_.as<double>();
+        const double* po = (it % 2 == 0) ? p1_.as<double>() : p0_.as<double>();
+        if (kt) kt->mark(LYAP_K_CG_DIR);
+        hipLaunchKernelGGL((k_fcg_dir<NT>), dim3(grid_), dim3(NT), 0, st_, op_, z_.as<double>(), po, pn,
+                           q_.as<double>(), r_.as<double>(), log_.as<CgIter>(), it, start == 0 ? 1 : 0,
+                           state_.as<double>(), eta2, partA_.as<double>(), partZ_.as<double>(), grid_,
+                           partB_.as<double>(), n_);
+        if (kt) kt->mark(LYAP_K_CG_UPD);
+        hipLaunchKernelGGL((k_fcg_upd<NT>), dim3(grid_), dim3(NT), 0, st_, X, r_.as<double>(), pn, q_.as<double>(),
+                           log_.as<CgIter>(), it, state_.as<double>(), partB_.as<double>(), grid_,
+                           partA_.as<double>(), flag_.as<int>(), n_);
+        LYAP_LAUNCHED("fcg iteration");
+        net_->apply(r_.as<double>(), z_.as<double>(), q_.as<double>(), partZ_.as<double>());
+      }
+      if (kt) kt->collect();
+      LYAP_HIP(hipMemcpyAsync(hlog_.p, log_.as<CgIter>() + it0, (size_t)cnt * sizeof(CgIter), hipMemcpyDeviceToHost,
+                              st_));
+      LYAP_HIP(hipMemcpyAsync(htot_.as<char>() + 64 * sizeof(double), flag_.p, 8, hipMemcpyDeviceToHost, st_));
+      LYAP_HIP(hipMemcpyAsync(htot_.p, state_.p, sizeof(double), hipMemcpyDeviceToHost, st_));
+      LYAP_HIP(hipStreamSynchronize(st_));
+      const int* hf = reinterpret_cast<const int*>(htot_.as<char>() + 64 * sizeof(double));
+      LYAP_REQUIRE(hf[1] == 0, LYAP_E_INNER, "flexible CG breakdown (p^T A p <= 0) at iteration %d", hf[1]);
+      const double thr = htot_.as<double>()[0];
+      const CgIter* lg = hlog_.as<CgIter>();
+      for (int c = 0; c < cnt && !done; ++c) {
+        LYAP_REQUIRE(std::isfinite(lg[c].rr[0]), LYAP_E_NUMERIC, "flexible CG produced a non-finite residual");
+        if (!(lg[c].rr[0] > thr)) {
+          done = true;
+          it = it0 + c;
+        }
+      }
+    }
+    total += it;
+    cg_launch_true<1>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), grid_, st_);
+    LYAP_HIP(hipMemcpyAsync(htot_.p, tot_.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st_));
+    LYAP_HIP(hipStreamSynchronize(st_));
+    const double* h = htot_.as<double>();
+    worst = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : 0.0;
+    LYAP_REQUIRE(std::isfinite(worst), LYAP_E_NUMERIC, "inner solve produced non-finite values");
+    if (worst <= eta_) {
+      stats_.iters += total;
+      stats_.solves += 1;
+      stats_.restarts += start;
+      stats_.worst_relres = std::max(stats_.worst_relres, worst);
+      stats_.ms += ms_since(t0);
+      return;
+    }
+    if (total >= max_iter_) break;
+  }
+  stats_.iters += total;
+  stats_.worst_relres = std::max(stats_.worst_relres, worst);
+  LYAP_REQUIRE(false, LYAP_E_INNER, "flexible CG did not reach the true relative residual %.1e in %d iterations",
+               eta_, total);
+}
+
 void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
+  if (net_) return solve_fcg(B, X, kt);
   const auto t0 = Clock::now();
   const int S = S_;
   const double eta_rec = 0.5 * eta_;  // recursive target, so that the true residual passes
@@ -319,10 +483,20 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
     init(start == 0 ? 0 : 1);
     int it = 0;
     bool done = false;
+    const bool harvesting = harvest_every_ > 0 && start == 0;
+    auto snapshot = [&]() {
+      if (!harvesting || (int)hr_.size() >= harvest_keep_) return;
+      hr_.emplace_back((size_t)n_ * S * sizeof(double));
+      hx_.emplace_back((size_t)n_ * S * sizeof(double));
+      LYAP_HIP(hipMemcpyAsync(hr_.back().p, r_.p, (size_t)n_ * S * sizeof(double), hipMemcpyDeviceToDevice, st_));
+      LYAP_HIP(hipMemcpyAsync(hx_.back().p, X, (size_t)n_ * S * sizeof(double), hipMemcpyDeviceToDevice, st_));
+    };
+    snapshot();
     while (!done && total + it < max_iter_) {
       const int it0 = it;
       const int cnt = std::min(kCgChunk, max_iter_ - total - it);
       for (int c = 0; c < cnt; ++c) iter(it++, start == 0 ? 1 : 0);
+      if (harvesting && it % std::max(1, harvest_every_) == 0) snapshot();
       kt ? kt->collect() : (void)0;
       LYAP_HIP(hipMemcpyAsync(hlog_.p, log_.as<CgIter>() + it0, (size_t)cnt * sizeof(CgIter), hipMemcpyDeviceToHost,
                               st_));
@@ -357,6 +531,12 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
       worst = std::max(worst, rel);
     }
     if (worst <= eta_) {
+      if (harvest_every_ > 0) {  // e_i = x* - x_i for the kept iterates
+        for (auto& x : hx_)
+          hipLaunchKernelGGL(k_cg_errors, dim3((n_ * S + 255) / 256), dim3(256), 0, st_, X, x.as<double>(), n_ * S);
+        LYAP_LAUNCHED("k_cg_errors");
+        harvest_every_ = 0;
+      }
       stats_.iters += total;
       stats_.solves += 1;
       stats_.restarts += start;
@@ -406,6 +586,8 @@ extern "C" lyap_status lyap_inner_solve(const lyap_op* A, const double* B, int64
     LYAP_REQUIRE(B != nullptr && X != nullptr, LYAP_E_ARG, "B or X is NULL");
     LYAP_REQUIRE(s == 1 || s == 2 || s == 4, LYAP_E_UNSUPPORTED, "s=%d: the inner solver takes 1, 2 or 4 columns", s);
     LYAP_REQUIRE(ldb >= A->n && ldx >= A->n, LYAP_E_ARG, "leading dimension below n");
+    LYAP_REQUIRE(o.inner_pc != LYAP_PC_LEARNED, LYAP_E_UNSUPPORTED,
+                 "the learned preconditioner is trained inside an extended Krylov solve (lyap_solve)");
     hipStream_t st = (hipStream_t)o.stream;
     const int n = (int)A->n;
     OpHolder<double> op;

@@ -1,0 +1,68 @@
+// Learned preconditioner for the inner solves of the extended Krylov method:
+//   M r = D^{-1} r + s * K^T(K(s * r)),  s = sqrt(D^{-1}),
+//   K(u) = conv2(conv1([u, f u])),  f = log(-diag A) - mean,
+// two 3x3x3 convolutions (2 -> C -> C channels, zero padding, no bias) on the
+// operator's grid.  M is symmetric positive definite for any weights (zero
+// weights give Jacobi).  Network tensors are FP32, channel-major [c][n]; the
+// CG vectors stay FP64.  Trained with the energy-norm loss
+// (M r - e)^T (-A) (M r - e) / e^T (-A) e on pairs harvested from the run's
+// own Jacobi-PCG solve, by Adam, with this file's own forward, backward and
+// optimizer kernels.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "lanczos.hpp"
+#include "solver.hpp"
+
+namespace lyap {
+
+constexpr int kPcMaxC = 8;
+inline int pcnet_param_count(int C) { return C * 2 * 27 + C * C * 27; }
+
+// SplitMix64 initial weights, uniform in [-scale, scale): u = (top 53 bits) / 2^53.
+void pcnet_init_weights(int C, uint64_t seed, double scale, float* W);
+
+class PcNetGpu {
+ public:
+  // op: FP64 stencil operator (5- or 7-point; its grid is the network's grid).
+  PcNetGpu(const OpDev<double>& op, int C, hipStream_t st);
+  int C() const { return C_; }
+  int n() const { return n_; }
+  void set_weights(const float* host);
+  void get_weights(float* host) const;
+  // z = M r (device FP64 n-vectors).  With q != nullptr, also one partial
+  // z.q per workgroup of a stream_grid(n) launch into part.
+  void apply(const double* r, double* z, const double* q, double* part);
+  // Loss of the pair (r, e) (eAe = e^T (-A) e) and its gradient into the
+  // device FP64 buffer grad (param_count values); the loss is left on the
+  // device (loss_dev) and returned when want_loss (host sync).
+  double grad(const double* r, const double* e, double eAe, bool want_loss);
+  // One Adam step with the gradient of the last grad() call.
+  void adam(double lr);
+  // e^T (-A) e on the device, returned to the host.
+  double energy(const double* e);
+  const double* dinv() const { return dinv_.as<double>(); }
+  const double* grad_dev() const { return grad_.as<double>(); }
+
+ private:
+  template <int CI, int CO>
+  void conv(const float* in, const float* W, float* out);
+  template <int CO, int CI>
+  void convT(const float* in, const float* W, float* out);
+  template <int CI, int CO>
+  void wgrad(const float* x, const float* g, double* gradW, bool accumulate);
+  void forward(const double* r);
+
+  OpDev<double> op_;
+  int nx_, ny_, nz_, n_, C_, P_;
+  hipStream_t st_;
+  int adam_t_ = 0;
+  DevBuf W_, m_, v_, grad_, dinv_, s_, f_;
+  DevBuf x0_, a1_, k_, t1_, d_, x0g_, a1g_, kg_, t2_, z_, gw_;
+  DevBuf part_, wpart_, loss_;
+  size_t wpart_cap_ = 0;
+};
+
+}  // namespace lyap

@@ -98,3 +98,15 @@ def test_argument_errors_without_device_work(lib):
     res = ct.c_double()
     assert lib.lyap_ctri(None, 1, 4, None, None, ct.byref(res), None, None) == b.E_ARG
     lib.lyap_result_free(ct.byref(r))       # safe on an error result
+
+
+def test_pcnet_init_matches_oracle():
+    """Host-side SplitMix64 weight initialisation of the library = the oracle's
+    (the same published generator implemented twice), rounded to FP32."""
+    import numpy as np
+    from paper_1602_05033_amd import binding as b
+    from oracle import cnn as N
+    for C, seed, scale in ((4, 0x5eed, 0.05), (2, 7, 0.3), (8, 12345, 1.0)):
+        W = b.pcnet_init(C, seed, scale)
+        ref = N.init_net(C, seed, scale).flat().astype(np.float32)
+        assert np.array_equal(W, ref)

@@ -1,0 +1,133 @@
+"""GPU parity of the learned preconditioner (forward, gradient, Adam training,
+flexible CG) and of extended Krylov with it, against the CPU FP64 oracle."""
+import numpy as np
+import pytest
+
+from workloads import fv3d, laplace2d, gaussian_C
+from oracle import cnn as N
+from oracle import extended as E
+from oracle import krylov as K
+from oracle import dense as D
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _b():
+    from paper_1602_05033_amd import binding
+    return binding
+
+
+def _dev(v):
+    return torch.from_numpy(np.ascontiguousarray(v)).cuda()
+
+
+def _net_from(W32, C):
+    return N.PcNet.from_flat(np.asarray(W32, dtype=np.float64), C)
+
+
+@pytest.mark.parametrize("shape,C", [((7, 6, 5), 4), ((9, 9, 9), 2), ((11, 10, 1), 8)])
+def test_pcnet_apply_parity(lib, shape, C):
+    b = _b()
+    nx, ny, nz = shape
+    op = fv3d(nx, 1.0, 3, Ny=ny, Nz=nz) if nz > 1 else laplace2d(nx, shift=1.0)
+    if nz == 1:
+        nx, ny = op.nx, op.ny
+    A = op.to_scipy()
+    g = N.grid_of(A, op.nx, op.ny, op.nz if op.kind == "stencil7" else 1)
+    W = b.pcnet_init(C, 77, 0.3)
+    net = _net_from(W, C)
+    r = np.random.default_rng(3).standard_normal(op.n)
+    z = b.pcnet_apply(b.device_op(op), C, W, _dev(r)).cpu().numpy()
+    ref = N.apply(net, g, r)
+    corr = ref - g.dinv * r
+    assert np.linalg.norm(z - ref) <= 2e-6 * np.linalg.norm(corr) + 1e-14 * np.linalg.norm(ref)
+
+
+def test_pcnet_grad_parity(lib):
+    b = _b()
+    op = fv3d(8, 1.0, 3)
+    A = op.to_scipy()
+    g = N.grid_of(A, op.nx, op.ny, op.nz)
+    C = 4
+    W = b.pcnet_init(C, 5, 0.2)
+    net = _net_from(W, C)
+    e = np.random.default_rng(4).standard_normal(op.n)
+    r = -(A @ e)
+    L, grad = b.pcnet_grad(b.device_op(op), C, W, _dev(r), _dev(e))
+    Lr, dW1, dW2 = N.loss_and_grad(net, g, A, r, e)
+    gref = np.concatenate([dW1.ravel(), dW2.ravel()])
+    assert abs(L - Lr) <= 1e-5 * Lr
+    assert np.linalg.norm(grad - gref) <= 1e-4 * np.linalg.norm(gref)
+
+
+def test_pcnet_train_parity(lib):
+    """Ten Adam steps on harvested pairs from the same initial weights."""
+    b = _b()
+    op = fv3d(9, 1.0, 3)
+    A = op.to_scipy()
+    g = N.grid_of(A, op.nx, op.ny, op.nz)
+    bvec = gaussian_C(op.n, 1, 3)[:, 0]
+    pairs, _, _ = N.harvest_pairs(A, bvec, every=4, keep=6)
+    C = 4
+    W = b.pcnet_init(C, 9, 0.05)
+    net = _net_from(W, C)
+    losses_ref = N.train(net, g, A, pairs, steps=10, lr=2e-3)
+    W2, losses = b.pcnet_train(b.device_op(op), C, W, [_dev(r) for r, _ in pairs], [_dev(e) for _, e in pairs],
+                               10, 2e-3)
+    assert np.allclose(losses, losses_ref, rtol=1e-4)
+    assert np.linalg.norm(W2 - net.flat()) <= 1e-3 * np.linalg.norm(net.flat())
+
+
+def test_pcnet_fcg_parity(lib):
+    """Flexible CG with weights trained by the oracle: certified solution,
+    iteration count within a few of the oracle's, fewer than Jacobi."""
+    b = _b()
+    op = fv3d(12, 1.0, 3)
+    A = op.to_scipy()
+    g = N.grid_of(A, op.nx, op.ny, op.nz)
+    bvec = gaussian_C(op.n, 1, 3)[:, 0]
+    pairs, _, _ = N.harvest_pairs(A, bvec, every=4, keep=16)
+    C = 4
+    net = _net_from(b.pcnet_init(C, 7, 0.05), C)
+    N.train(net, g, A, pairs, steps=120, lr=2e-3)
+    W = net.flat().astype(np.float32)
+    b2 = gaussian_C(op.n, 1, 11)[:, 0]
+    X, it, rel, st = b.pcnet_fcg(b.device_op(op), C, W, _dev(b2))
+    assert st == b.OK and rel <= 1e-12
+    Xh = X.cpu().numpy()
+    assert np.linalg.norm(A @ Xh - b2) <= 1e-12 * np.linalg.norm(b2)
+    _, it_ref, _ = N.fcg(A, b2, lambda r: N.apply(_net_from(W, C), g, r), eta=1e-12)
+    _, it_jac, _ = N.fcg(A, b2, lambda r: r * g.dinv, eta=1e-12)
+    assert abs(it - it_ref) <= max(3, 0.1 * it_ref), (it, it_ref)
+    assert it < it_jac
+
+
+def test_ek_with_learned_preconditioner(lib):
+    """Extended Krylov with inner_pc = LEARNED: harvest, train, flexible CG;
+    same blocks and factor as the oracle with exact solves."""
+    b = _b()
+    op = fv3d(14, 1.0, 3)
+    A = op.to_scipy()
+    C = gaussian_C(op.n, 1, 3)
+    sol = b.lyap_solve(b.device_op(op), _dev(C), method=b.METHOD_EXT, tol=1e-8, check_every=1,
+                       inner_pc=b.PC_LEARNED)
+    ref = E.lyap_ext(A, C, tol=1e-8)
+    assert sol.status == b.OK and sol.m == ref.m
+    Z = sol.Z.cpu().numpy()
+    assert K.lowrank_vs_dense_error(Z, D.lyap_eig(A.toarray(), C)) <= 1e-7
+    assert sol.times_ms["train"] > 0.0 and sol.n_inner == sol.m + 1
+
+
+def test_learned_pc_errors(lib):
+    b = _b()
+    op = laplace2d(10)
+    B = _dev(gaussian_C(op.n, 2, 1))
+    with pytest.raises(b.LyapError):    # two columns
+        b.lyap_solve(b.device_op(op), B, method=b.METHOD_EXT, inner_pc=b.PC_LEARNED)
+    with pytest.raises(b.LyapError):    # CSR: no grid
+        b.lyap_solve(b.device_op(op, as_csr=True), B[:, :1].contiguous(), method=b.METHOD_EXT,
+                     inner_pc=b.PC_LEARNED)
+    with pytest.raises(b.LyapError):
+        b.inner_solve(b.device_op(op), B[:, :1].contiguous(), inner_pc=b.PC_LEARNED)
