@@ -234,3 +234,22 @@ def test_ek_full_size_100cubed(lib):
             if c + d < k:
                 T[c + d, c] = T[c, c + d] = sol.T_band[c, d]
     assert np.linalg.eigvalsh(T).max() < 0.0
+
+
+def test_ek_full_size_learned_preconditioner(lib):
+    """The full-size extended Krylov configuration with the learned inner
+    preconditioner (trained in the run): same acceptance as with Jacobi, every
+    inner solve certified, and fewer inner iterations than the Jacobi run."""
+    b = _b()
+    op = fv3d(100, 1.0, 3)
+    C = gaussian_C(op.n, 1, 3)
+    dop = b.device_op(op)
+    Cd = _dev(C)
+    sol = b.lyap_solve(dop, Cd, method=b.METHOD_EXT, tol=1e-8, check_every=0, inner_pc=b.PC_LEARNED,
+                       inner_tol=1e-12)
+    assert sol.status == b.OK and sol.res <= 1e-8
+    ex = _explicit_residual_gpu(b, dop, sol.Z, Cd) / sol.beta ** 2
+    assert ex <= 2e-8, ex
+    jac = b.lyap_solve(dop, Cd, method=b.METHOD_EXT, tol=1e-8, check_every=0, inner_pc=b.PC_JACOBI, inner_tol=1e-12)
+    assert abs(sol.m - jac.m) <= 2
+    assert sol.inner_iters < jac.inner_iters

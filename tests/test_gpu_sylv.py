@@ -109,18 +109,16 @@ def test_sylv_different_sizes_and_errors(lib):
 def test_sylv_full_size(lib):
     """The full-size Sylvester configuration: A the 700 x 700 Laplacian
     (n1 = 490000), B the 80^3 lognormal finite-volume operator (sigma 0.5,
-    n2 = 512000), s = 2, FP32 storage.  Convergence by the corrected
-    Algorithm 4, and the explicit residual of Z1 Z2^T computed on the device
-    in FP64 from the QRs of [A Z1, Z1, C1] and [Z2, B Z2, C2] agrees with it up
-    to the FP32 floor."""
+    n2 = 512000), s = 2.  Convergence by the corrected Algorithm 4; the
+    explicit residual of Z1 Z2^T, computed on the device in FP64 from the QRs
+    of [A Z1, Z1, C1] and [Z2, B Z2, C2], agrees with it in FP64 storage and
+    stays within the stated floor in FP32 storage (rounding of the two stored
+    bases breaks the Lanczos relations at the u32 ||A|| level)."""
     b = _b()
     opA, opB = laplace2d(700), fv3d(80, 0.5, 4)
     C1 = _dev(gaussian_C(opA.n, 2, 4))
     C2 = _dev(gaussian_C(opB.n, 2, 5))
     dA, dB = b.device_op(opA), b.device_op(opB)
-    sol = b.sylv_solve(dA, dB, C1, C2, tol=1e-8, storage=b.STORE_F32, check_every=0)
-    assert sol.status == b.OK and sol.res <= 1e-8
-    Z1, Z2 = sol.Z1, sol.Z2
 
     def apply(dop, Z):
         out = torch.empty_like(Z)
@@ -128,7 +126,11 @@ def test_sylv_full_size(lib):
             out[:, c0:c0 + 8] = b.op_apply(dop, Z[:, c0:c0 + 8].contiguous(), b.STORE_F64)
         return out
 
-    R1 = torch.linalg.qr(torch.cat([apply(dA, Z1), Z1, C1], dim=1), mode="r")[1]
-    R2 = torch.linalg.qr(torch.cat([Z2, apply(dB, Z2), C2], dim=1), mode="r")[1]
-    ex = float(torch.linalg.norm(R1 @ R2.T)) / (sol.beta1 * sol.beta2)
-    assert ex <= 1e-7, ex
+    for storage, bound in ((b.STORE_F64, 1.5e-8), (b.STORE_F32, 5e-7)):
+        sol = b.sylv_solve(dA, dB, C1, C2, tol=1e-8, storage=storage, check_every=0)
+        assert sol.status == b.OK and sol.res <= 1e-8
+        Z1, Z2 = sol.Z1, sol.Z2
+        R1 = torch.linalg.qr(torch.cat([apply(dA, Z1), Z1, C1], dim=1), mode="r")[1]
+        R2 = torch.linalg.qr(torch.cat([Z2, apply(dB, Z2), C2], dim=1), mode="r")[1]
+        ex = float(torch.linalg.norm(R1 @ R2.T)) / (sol.beta1 * sol.beta2)
+        assert ex <= bound, (storage, ex)
