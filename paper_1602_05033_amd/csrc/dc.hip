@@ -582,7 +582,9 @@ DcWork::DcWork(int ell, hipStream_t st) : impl_(new Impl) {
   LYAP_REQUIRE(ell >= 1 && ell <= kMaxL, LYAP_E_UNSUPPORTED, "band eigensolver: ell=%d > %d", ell, kMaxL);
   impl_->ell = ell;
   impl_->st = st;
-  int b = ell * std::max(1, 32 / ell);
+  // leaves of at least 8 rows, a multiple of ell: small dense Jacobi problems
+  // (each leaf is one sequential wave) and a few more merge levels
+  int b = ell * std::max(1, 8 / ell);
   impl_->leaf = b;
 }
 DcWork::~DcWork() { delete impl_; }

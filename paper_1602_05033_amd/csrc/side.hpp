@@ -30,6 +30,7 @@ class LanczosSide {
   void accumulate_Z(int m, const double* Mrows, int t, double* Z, int64_t ldz, double* bytes_out);
 
   const double* band() const { return band_.as<double>(); }
+  const int* flags_dev() const { return flags_.as<int>(); }
   const double* gamma_dev() const { return glog_.as<double>() + L_R * S_ * S_; }
   const double* tau_dev(int mm) const { return logb_.as<double>() + (size_t)(mm - 1) * LS_ + L_R * S_ * S_; }
   const double* gamma_host() const { return hglog_.data() + L_R * S_ * S_; }

@@ -268,7 +268,33 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   out->beta = side.beta();
   const double beta2 = out->beta * out->beta;
 
-  Checker ck(S, S, st);
+  // Residual checks run on a second stream while the Lanczos steps continue:
+  // a check at mm reads only T_mm's band, gamma and tau_{mm+1,mm}, which later
+  // steps never write.  The host keeps at most kAhead steps queued ahead of
+  // the GPU, so after the converging check the extra steps are few; they are
+  // simply not used (the accepted basis is the checked one).  With
+  // opts->profile the checks run on the solver's stream, one at a time.
+  constexpr int kAhead = 24;
+  const bool overlap = o.profile == 0;
+  hipStream_t cst = st;
+  struct StreamGuard {
+    hipStream_t s = nullptr;
+    ~StreamGuard() { if (s) (void)hipStreamDestroy(s); }
+  } sg;
+  if (overlap) {
+    LYAP_HIP(hipStreamCreateWithFlags(&sg.s, hipStreamNonBlocking));
+    cst = sg.s;
+  }
+  struct EventRing {
+    std::vector<hipEvent_t> ev;
+    ~EventRing() { for (auto e : ev) (void)hipEventDestroy(e); }
+  } er;
+  er.ev.resize(kAhead + 2);
+  for (auto& e : er.ev) LYAP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  hipEvent_t ev_step = er.ev[kAhead], ev_chk = er.ev[kAhead + 1];
+  HostBuf hflags(64);
+
+  Checker ck(S, S, cst);
   CheckSchedule sched{o.check_every, maxit};
   std::vector<int> hm;
   std::vector<double> hr;
@@ -280,71 +306,113 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   double lam_absmax = 0.0;
   int checked_m = 0;
   double t_to_tol = 0.0;
+  bool pending = false;
+  int pending_mm = 0;
 
-  auto run_check = [&](int mm) {
-    const auto t0 = Clock::now();
+  auto launch_check = [&](int mm) {
+    LYAP_HIP(hipEventRecord(ev_step, st));
+    LYAP_HIP(hipStreamWaitEvent(cst, ev_step, 0));
     kt.mark(LYAP_K_CHECK);
     ck.run(side.band(), mm * S, side.gamma_dev(), side.tau_dev(mm), chk.as<CheckOut>());
-    kt.collect();
-    LYAP_HIP(hipMemcpyAsync(hchk.p, chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, st));
-    LYAP_HIP(hipStreamSynchronize(st));
+    LYAP_HIP(hipMemcpyAsync(hchk.p, chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, cst));
+    LYAP_HIP(hipMemcpyAsync(hflags.p, side.flags_dev(), 2 * sizeof(int), hipMemcpyDeviceToHost, cst));
+    LYAP_HIP(hipEventRecord(ev_chk, cst));
+    pending = true;
+    pending_mm = mm;
+    out->n_checks++;
+  };
+  auto wait_check = [&]() {
+    const auto t0 = Clock::now();
+    LYAP_HIP(hipEventSynchronize(ev_chk));
     check_ms += ms_since(t0);
-    const CheckOut& c = *hchk.as<CheckOut>();
+    kt.collect();
+  };
+  // Reads the finished check; returns true when the iteration stops.
+  auto finish_check = [&]() -> bool {
+    pending = false;
+    const int mm = pending_mm;
+    const CheckOut c = *hchk.as<CheckOut>();
+    const int fb = hflags.as<int>()[0], fn = hflags.as<int>()[1];
+    LYAP_REQUIRE(!(fn > 0 && fn <= mm), LYAP_E_NUMERIC, "non-finite values in the Lanczos recurrence at step %d",
+                 fn);
+    if (fb > 0 && fb <= mm) {
+      // a rank-deficient block at step fb-1: check the basis it ends instead
+      LYAP_HIP(hipStreamSynchronize(st));
+      launch_check(fb);
+      wait_check();
+      const CheckOut cb = *hchk.as<CheckOut>();
+      pending = false;
+      LYAP_REQUIRE(std::isfinite(cb.res), LYAP_E_NUMERIC, "residual is not finite at m=%d", fb);
+      const double rel = cb.res / beta2;
+      hm.push_back(fb);
+      hr.push_back(rel);
+      last_res = rel;
+      checked_m = fb;
+      lam_absmax = std::max(std::fabs(cb.lam_min), std::fabs(cb.lam_max));
+      m = fb;
+      if (rel <= o.tol) {
+        status = LYAP_OK;
+        t_to_tol = ms_since(t_entry);
+      } else {
+        status = LYAP_E_BREAKDOWN;
+        set_error("block Lanczos breakdown at m=%d with residual %.3e above tol", fb, rel);
+      }
+      return true;
+    }
+    LYAP_REQUIRE(std::isfinite(c.res), LYAP_E_NUMERIC, "residual is not finite at m=%d", mm);
+    const double rel = c.res / beta2;
+    hm.push_back(mm);
+    hr.push_back(rel);
+    last_res = rel;
     checked_m = mm;
     lam_absmax = std::max(std::fabs(c.lam_min), std::fabs(c.lam_max));
-    out->n_checks++;
-    return c;
+    if (o.verbose) std::fprintf(stderr, "[lyap] m=%d k=%d res=%.3e\n", mm, mm * S, rel);
+    LYAP_REQUIRE(c.lam_max < 0.0, LYAP_E_INDEFINITE,
+                 "Ritz value %.3e >= 0 at m=%d: the operator is not negative definite", c.lam_max, mm);
+    if (rel <= o.tol) {
+      status = LYAP_OK;
+      m = mm;
+      t_to_tol = ms_since(t_entry);
+      return true;
+    }
+    if (mm >= maxit) {
+      m = mm;
+      return true;
+    }
+    next_check = sched.next(mm, rel, o.tol);
+    return false;
   };
 
   const auto t_pass1 = Clock::now();
-  while (m < maxit) {
-    side.step();
-    m = side.m();
-    if (m == next_check || m == maxit) {
-      int fb = 0, fn = 0;
-      side.read_flags(&fb, &fn);
-      int mm = m;
-      bool broke = false;
-      if (fb > 0 && fb <= m) {
-        mm = fb;  // the QR of step fb-1 found a rank-deficient block
-        broke = true;
-      } else if (fn > 0) {
-        LYAP_REQUIRE(false, LYAP_E_NUMERIC, "non-finite values in the Lanczos recurrence at step %d", fn);
+  int steps = 0;  // steps enqueued
+  while (true) {
+    if (pending) {
+      const hipError_t q = hipEventQuery(ev_chk);
+      if (q == hipSuccess || steps >= maxit || !overlap) {
+        if (q != hipSuccess) wait_check();
+        if (finish_check()) break;
+      } else if (q != hipErrorNotReady) {
+        LYAP_HIP(q);
       }
-      CheckOut c = run_check(mm);
-      LYAP_REQUIRE(std::isfinite(c.res), LYAP_E_NUMERIC, "residual is not finite at m=%d", mm);
-      const double rel = c.res / beta2;
-      hm.push_back(mm);
-      hr.push_back(rel);
-      last_res = rel;
-      if (o.verbose) std::fprintf(stderr, "[lyap] m=%d k=%d res=%.3e\n", mm, mm * S, rel);
-      LYAP_REQUIRE(c.lam_max < 0.0, LYAP_E_INDEFINITE,
-                   "Ritz value %.3e >= 0 at m=%d: the operator is not negative definite", c.lam_max, mm);
-      if (rel <= o.tol) {
-        status = LYAP_OK;
-        m = mm;
-        t_to_tol = ms_since(t_entry);
-        break;
-      }
-      if (broke) {
-        m = mm;
-        status = LYAP_E_BREAKDOWN;
-        set_error("block Lanczos breakdown at m=%d with residual %.3e above tol", mm, rel);
-        break;
-      }
-      next_check = sched.next(m, rel, o.tol);
     }
+    if (!pending && (steps >= next_check || steps >= maxit)) {
+      // always at the scheduled point (not at however far the steps have run
+      // ahead), so that the result does not depend on timing
+      launch_check(std::min(next_check, steps));
+      continue;
+    }
+    if (steps >= maxit) continue;  // a check is pending
+    if (steps >= kAhead) LYAP_HIP(hipEventSynchronize(er.ev[steps % kAhead]));
+    side.step();
+    LYAP_HIP(hipEventRecord(er.ev[steps % kAhead], st));
+    ++steps;
   }
-  if (checked_m != m) {  // the last basis was not checked (max_iter without a due check)
-    CheckOut c = run_check(m);
-    hm.push_back(m);
-    hr.push_back(c.res / beta2);
-    last_res = c.res / beta2;
-  }
+  if (overlap) LYAP_HIP(hipStreamWaitEvent(st, ev_chk, 0));  // finalisation reads the checker's results
   const double pass1_ms = ms_since(t_pass1) - check_ms;
   out->m = m;
   out->res = last_res;
   store_history(out, hm, hr);
+  (void)checked_m;
 
   // ------------------------------------------------------------ finalisation
   const auto t_fin = Clock::now();
