@@ -161,6 +161,19 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
   kt.st = st;
   kt.on = o.profile != 0;
 
+  // residual checks run on kCS extra streams (problem i on stream i mod kCS)
+  // while the grouped steps continue; with opts->profile on the solver's stream
+  constexpr int kCS = 4;
+  const bool overlap = o.profile == 0;
+  struct Streams {
+    hipStream_t s[kCS] = {nullptr, nullptr, nullptr, nullptr};
+    ~Streams() { for (auto x : s) if (x) (void)hipStreamDestroy(x); }
+  } cs;
+  for (int i = 0; i < kCS; ++i) {
+    if (overlap) LYAP_HIP(hipStreamCreateWithFlags(&cs.s[i], hipStreamNonBlocking));
+  }
+  auto cstream = [&](int id) { return overlap ? cs.s[id % kCS] : st; };
+
   std::vector<std::unique_ptr<Problem<T>>> P;
   DevBuf flags_all((size_t)count * 16 * sizeof(int));
   LYAP_HIP(hipMemsetAsync(flags_all.p, 0, flags_all.bytes, st));
@@ -190,7 +203,7 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
     LYAP_HIP(hipMemsetAsync(p->band.p, 0, p->band.bytes, st));
     const int chunk = tune ? autotune_chunk<T>(p->S, p->n, st) : 2048;
     p->nparts = nparts_for(p->n, chunk);
-    p->ck = std::make_unique<Checker>(p->S, p->S, st);
+    p->ck = std::make_unique<Checker>(p->S, p->S, cstream(i));
     p->sched = CheckSchedule{o.check_every, maxit};
     p->next_check = p->sched.first();
     out[i].n = p->n;
@@ -274,80 +287,153 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
   DevBuf chk((size_t)count * sizeof(CheckOut));
   HostBuf hchk((size_t)count * sizeof(CheckOut));
   double check_ms = 0.0;
-  const auto t_pass1 = Clock::now();
-  int j = 0;
+  constexpr int kAhead = 24;
+  struct EventRing {
+    std::vector<hipEvent_t> ev;
+    ~EventRing() { for (auto e : ev) (void)hipEventDestroy(e); }
+  } er;
+  er.ev.resize(kAhead + 1 + kCS);
+  for (auto& e : er.ev) LYAP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  hipEvent_t ev_step = er.ev[kAhead];
+  hipEvent_t* ev_cs = &er.ev[kAhead + 1];
+  bool pending = false;
+  std::vector<Problem<T>*> pend_chk;
+  std::vector<int> pend_mm;
   int n_active = count;
-  while (n_active > 0 && j < maxit) {
-    for (auto& g : groups) launch_batch_step<T>(g.desc.template as<BatchDesc<T>>(), g.map.template as<int2>(), g.nwg, g.S, j, st, &kt);
-    ++j;
-    std::vector<Problem<T>*> due;
-    for (auto& p : P)
-      if (p->active) {
-        p->m = j;
-        if (j == p->next_check || j == maxit) due.push_back(p.get());
-      }
-    if (due.empty()) continue;
-    const auto t0 = Clock::now();
-    LYAP_HIP(hipMemcpyAsync(hflags.p, flags_all.p, flags_all.bytes, hipMemcpyDeviceToHost, st));
-    LYAP_HIP(hipStreamSynchronize(st));
-    kt.collect();
-    std::vector<int> mm(due.size());
-    std::vector<bool> broke(due.size(), false);
+  auto launch_checks = [&](const std::vector<Problem<T>*>& due, int j) {
+    LYAP_HIP(hipEventRecord(ev_step, st));
+    for (int i = 0; i < kCS; ++i)
+      if (overlap) LYAP_HIP(hipStreamWaitEvent(cs.s[i], ev_step, 0));
     kt.mark(LYAP_K_CHECK);
-    for (size_t q = 0; q < due.size(); ++q) {
-      Problem<T>* p = due[q];
-      const int* f = hflags.template as<int>() + 16 * p->id;
-      LYAP_REQUIRE(f[1] == 0, LYAP_E_NUMERIC, "problem %d: non-finite values at step %d", p->id, f[1]);
-      mm[q] = j;
-      if (f[0] > 0 && f[0] <= j) {
-        mm[q] = f[0];
-        broke[q] = true;
-      }
+    pend_chk.clear();
+    pend_mm.clear();
+    for (Problem<T>* p : due) {
+      const int mm = std::min(p->next_check, j);
       const size_t LS = log_stride(p->S);
-      p->ck->run(p->band.template as<double>(), mm[q] * p->S, p->glog.template as<double>() + L_R * p->S * p->S,
-                 p->log.template as<double>() + (size_t)(mm[q] - 1) * LS + L_R * p->S * p->S, chk.template as<CheckOut>() + p->id);
+      hipStream_t cq = cstream(p->id);
+      p->ck->run(p->band.template as<double>(), mm * p->S, p->glog.template as<double>() + L_R * p->S * p->S,
+                 p->log.template as<double>() + (size_t)(mm - 1) * LS + L_R * p->S * p->S,
+                 chk.template as<CheckOut>() + p->id);
+      LYAP_HIP(hipMemcpyAsync(hchk.template as<CheckOut>() + p->id, chk.template as<CheckOut>() + p->id,
+                              sizeof(CheckOut), hipMemcpyDeviceToHost, cq));
+      LYAP_HIP(hipMemcpyAsync(hflags.template as<int>() + 16 * p->id, flags_all.template as<int>() + 16 * p->id,
+                              2 * sizeof(int), hipMemcpyDeviceToHost, cq));
+      pend_chk.push_back(p);
+      pend_mm.push_back(mm);
     }
-    LYAP_HIP(hipMemcpyAsync(hchk.p, chk.p, chk.bytes, hipMemcpyDeviceToHost, st));
-    LYAP_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < kCS; ++i) LYAP_HIP(hipEventRecord(ev_cs[i], overlap ? cs.s[i] : st));
+    pending = true;
+  };
+  auto checks_ready = [&]() {
+    for (int i = 0; i < kCS; ++i) {
+      const hipError_t q = hipEventQuery(ev_cs[i]);
+      if (q == hipErrorNotReady) return false;
+      LYAP_HIP(q);
+    }
+    return true;
+  };
+  auto wait_checks = [&]() {
+    const auto t0 = Clock::now();
+    for (int i = 0; i < kCS; ++i) LYAP_HIP(hipEventSynchronize(ev_cs[i]));
+    check_ms += ms_since(t0);
     kt.collect();
+  };
+  // a check at m on problem p's stream, waited for (breakdown re-checks)
+  auto check_now = [&](Problem<T>* p, int mm) {
+    LYAP_HIP(hipStreamSynchronize(st));
+    const size_t LS = log_stride(p->S);
+    hipStream_t cq = cstream(p->id);
+    p->ck->run(p->band.template as<double>(), mm * p->S, p->glog.template as<double>() + L_R * p->S * p->S,
+               p->log.template as<double>() + (size_t)(mm - 1) * LS + L_R * p->S * p->S,
+               chk.template as<CheckOut>() + p->id);
+    LYAP_HIP(hipMemcpyAsync(hchk.template as<CheckOut>() + p->id, chk.template as<CheckOut>() + p->id,
+                            sizeof(CheckOut), hipMemcpyDeviceToHost, cq));
+    LYAP_HIP(hipStreamSynchronize(cq));
+  };
+  auto process_checks = [&](int j) {
+    pending = false;
     bool changed = false;
-    for (size_t q = 0; q < due.size(); ++q) {
-      Problem<T>* p = due[q];
+    for (size_t q = 0; q < pend_chk.size(); ++q) {
+      Problem<T>* p = pend_chk[q];
+      int mm = pend_mm[q];
+      const int* f = hflags.template as<int>() + 16 * p->id;
+      LYAP_REQUIRE(!(f[1] > 0 && f[1] <= mm && (f[0] == 0 || f[1] <= f[0])), LYAP_E_NUMERIC,
+                   "problem %d: non-finite values at step %d", p->id, f[1]);
+      bool broke = false;
+      if (f[0] > 0 && f[0] <= mm) {
+        mm = f[0];
+        broke = true;
+        check_now(p, mm);
+      }
       const CheckOut& c = hchk.template as<CheckOut>()[p->id];
       LYAP_REQUIRE(std::isfinite(c.res), LYAP_E_NUMERIC, "problem %d: residual not finite", p->id);
       LYAP_REQUIRE(c.lam_max < 0.0, LYAP_E_INDEFINITE, "problem %d: Ritz value %.3e >= 0", p->id, c.lam_max);
       const double rel = c.res / (p->beta * p->beta);
-      p->hm.push_back(mm[q]);
+      p->hm.push_back(mm);
       p->hr.push_back(rel);
       p->last_res = rel;
-      p->checked_m = mm[q];
+      p->checked_m = mm;
       p->lam_absmax = std::max(std::fabs(c.lam_min), std::fabs(c.lam_max));
       out[p->id].n_checks++;
-      if (o.verbose) std::fprintf(stderr, "[batch] problem %d m=%d res=%.3e\n", p->id, mm[q], rel);
+      if (o.verbose) std::fprintf(stderr, "[batch] problem %d m=%d res=%.3e\n", p->id, mm, rel);
       if (rel <= o.tol) {
         p->status = LYAP_OK;
-        p->m_final = mm[q];
+        p->m_final = mm;
         p->active = false;
         p->t_to_tol = ms_since(t_entry);
-      } else if (broke[q]) {
+      } else if (broke) {
         p->status = LYAP_E_BREAKDOWN;
-        p->m_final = mm[q];
+        p->m_final = mm;
         p->active = false;
-      } else if (j >= maxit) {
-        p->m_final = j;
+      } else if (mm >= maxit) {
+        p->m_final = mm;
         p->active = false;
       } else {
-        p->next_check = p->sched.next(j, rel, o.tol);
+        p->next_check = p->sched.next(mm, rel, o.tol);
       }
       if (!p->active) {
         changed = true;
         --n_active;
       }
     }
-    check_ms += ms_since(t0);
+    (void)j;
     if (changed)
       for (auto& g : groups) upload(g, false, 0);
+  };
+
+  const auto t_pass1 = Clock::now();
+  int j = 0;
+  while (n_active > 0) {
+    if (pending) {
+      if (!overlap || j >= maxit || checks_ready()) {
+        wait_checks();
+        process_checks(j);
+        continue;
+      }
+    }
+    if (!pending) {
+      std::vector<Problem<T>*> due;
+      for (auto& p : P)
+        if (p->active && (j >= p->next_check || j >= maxit)) due.push_back(p.get());
+      if (!due.empty()) {
+        launch_checks(due, j);
+        continue;
+      }
+    }
+    if (j >= maxit) {
+      if (!pending) break;
+      continue;
+    }
+    if (j >= kAhead) LYAP_HIP(hipEventSynchronize(er.ev[j % kAhead]));
+    for (auto& g : groups)
+      launch_batch_step<T>(g.desc.template as<BatchDesc<T>>(), g.map.template as<int2>(), g.nwg, g.S, j, st, &kt);
+    LYAP_HIP(hipEventRecord(er.ev[j % kAhead], st));
+    ++j;
+    for (auto& p : P)
+      if (p->active) p->m = j;
   }
+  if (overlap)
+    for (int i = 0; i < kCS; ++i) LYAP_HIP(hipStreamWaitEvent(st, ev_cs[i], 0));
   for (auto& p : P)
     if (p->m_final == 0) p->m_final = p->m;
   const double pass1_ms = ms_since(t_pass1) - check_ms;
@@ -359,11 +445,12 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
     const int S = p->S;
     const size_t LS = log_stride(S);
     if (p->checked_m != p->m_final) {  // (only when max_iter ended without a due check)
+      LYAP_HIP(hipStreamSynchronize(st));
       p->ck->run(p->band.template as<double>(), p->m_final * S, p->glog.template as<double>() + L_R * S * S,
                  p->log.template as<double>() + (size_t)(p->m_final - 1) * LS + L_R * S * S, chk.template as<CheckOut>() + p->id);
       LYAP_HIP(hipMemcpyAsync(hchk.template as<CheckOut>() + p->id, chk.template as<CheckOut>() + p->id, sizeof(CheckOut),
-                              hipMemcpyDeviceToHost, st));
-      LYAP_HIP(hipStreamSynchronize(st));
+                              hipMemcpyDeviceToHost, cstream(p->id)));
+      LYAP_HIP(hipStreamSynchronize(cstream(p->id)));
       const CheckOut& c = hchk.template as<CheckOut>()[p->id];
       p->last_res = c.res / (p->beta * p->beta);
       p->hm.push_back(p->m_final);

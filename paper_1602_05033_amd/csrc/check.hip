@@ -8,7 +8,7 @@
 namespace lyap {
 
 // dense Jacobi is used up to this size; larger T_m go through divide and conquer
-constexpr int kDenseMax = 64;
+constexpr int kDenseMax = 16;
 
 Checker::~Checker() { delete static_cast<DcWork*>(dc_); }
 

@@ -347,6 +347,46 @@ __global__ __launch_bounds__(kDefThreads) void k_deflate(const DcMerge* md, DcSc
   if (t == 0) { s.skip = 0; s.Kn = s_Kn; s.Kd = Ks + Nr; s.r = r; }
 }
 
+constexpr int kSecReg = 8;  // merges with Kn <= 64 * kSecReg keep the poles in registers
+
+// sum z_i^2 / (d_i - dO - t) and sum z_i^2 / (d_i - dO - t)^2 over i = i0, i0 + 64,
+// ... < i1 (one lane's share), accumulated in that order; four terms per pass
+// so that their loads are in flight together.
+__device__ __forceinline__ void secular_terms(const double* d, const double* zz, double dO, double t, int i0, int i1,
+                                              double& s1, double& s2) {
+  int i = i0;
+  for (; i + 192 < i1; i += 256) {
+    double zv[4], dv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      zv[u] = zz[i + 64 * u];
+      dv[u] = d[i + 64 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double q = zv[u] / ((dv[u] - dO) - t);
+      s1 = fma(zv[u], q, s1);
+      s2 = fma(q, q, s2);
+    }
+  }
+  for (; i < i1; i += 64) {
+    const double q = zz[i] / ((d[i] - dO) - t);
+    s1 = fma(zz[i], q, s1);
+    s2 = fma(q, q, s2);
+  }
+}
+
+// Root of a x^2 + b x + c0 = 0 in (L, R) when there is one (else the other
+// root), from the cancellation-free pair q / a and c0 / q.
+__device__ __forceinline__ double quad_root_in(double a, double b, double c0, double L, double R) {
+  if (a == 0.0) return -c0 / b;
+  const double sq = sqrt(fmax(b * b - 4.0 * a * c0, 0.0));
+  const double q = -0.5 * (b >= 0.0 ? b + sq : b - sq);
+  const double x1 = q / a;
+  const double x2 = q != 0.0 ? c0 / q : x1;
+  return (x1 > L && x1 < R) ? x1 : x2;
+}
+
 // Secular equation 1/r + sum_i z_i^2/(d_i - lambda) = 0: one wave per root.
 // Root j lies in (d_j, d_{j+1}) (last: (d_{K-1}, d_{K-1} + r||z||^2)); it is
 // stored as the nearer pole index o_j and the offset tau_j = lambda_j - d_{o_j}
@@ -384,14 +424,37 @@ __global__ __launch_bounds__(256) void k_secular(const DcMerge* md, const DcScal
   double t = 0.5 * (lo + hi);
   const double Dj = d[j] - dO;
   const double Dj1 = last ? 0.0 : d[j + 1] - dO;
+  // small problems keep z_i and d_i - d_o (i = lane + 64 u) in registers for
+  // all iterations; padding (z = 0) adds nothing
+  const bool reg = Kn <= 64 * kSecReg;
+  double zr[kSecReg], er[kSecReg];
+  if (reg) {
+#pragma unroll
+    for (int u = 0; u < kSecReg; ++u) {
+      const int i = lane + 64 * u;
+      zr[u] = i < Kn ? zz[i] : 0.0;
+      er[u] = i < Kn ? d[i] - dO : 1e300;
+    }
+  }
   for (int it = 0; it < 120; ++it) {
+    // with q = z_i / (d_i - lambda): z_i^2 / (d_i - lambda) = z_i q and its
+    // derivative z_i^2 / (d_i - lambda)^2 = q^2 (one division per term)
     double psi = 0, phi = 0, dpsi = 0, dphi = 0;
-    for (int i = lane; i < Kn; i += 64) {
-      const double dl = (d[i] - dO) - t;
-      const double z2 = zz[i] * zz[i];
-      const double q = z2 / dl;
-      if (i <= j) { psi += q; dpsi += q / dl; }
-      else { phi += q; dphi += q / dl; }
+    if (reg) {
+#pragma unroll
+      for (int u = 0; u < kSecReg; ++u) {
+        const double q = zr[u] / (er[u] - t);
+        if (lane + 64 * u <= j) {
+          psi = fma(zr[u], q, psi);
+          dpsi = fma(q, q, dpsi);
+        } else {
+          phi = fma(zr[u], q, phi);
+          dphi = fma(q, q, dphi);
+        }
+      }
+    } else {
+      secular_terms(d, zz, dO, t, lane, j + 1, psi, dpsi);
+      secular_terms(d, zz, dO, t, j + 1 + lane, Kn, phi, dphi);
     }
     psi = wave_sum(psi); phi = wave_sum(phi); dpsi = wave_sum(dpsi); dphi = wave_sum(dphi);
     const double f = ir + psi + phi;
@@ -408,24 +471,26 @@ __global__ __launch_bounds__(256) void k_secular(const DcMerge* md, const DcScal
       const double a2 = phi - b2 / dlj1;
       const double c = ir + a1 + a2;
       const double dd = Dj1 - Dj;
-      const double Bq = c * dd + b1 + b2, Cq = b1 * dd;
-      double p;
-      if (c == 0.0) {
-        p = -Cq / Bq;
-      } else {
-        const double sq = sqrt(fmax(Bq * Bq - 4.0 * c * Cq, 0.0));
-        double p1, p2;
-        if (Bq > 0) { p1 = (-Bq - sq) / (2.0 * c); p2 = 2.0 * Cq / (-Bq - sq); }
-        else { const double den = -Bq + sq; p1 = den != 0.0 ? 2.0 * Cq / den : -INFINITY; p2 = den / (2.0 * c); }
-        p = (p1 > -dd && p1 < 0.0) ? p1 : p2;
-      }
-      tn = Dj - p;
+      // root of c + b1/(Dj - x) + b2/(Dj1 - x), solved for its distance to the
+      // origin pole (Dj or Dj1 is 0) so that a root next to that pole keeps
+      // its relative accuracy: u = Dj - x in (-dd, 0) or w = Dj1 - x in (0, dd)
+      if (o == j) tn = Dj - quad_root_in(c, c * dd + b1 + b2, b1 * dd, -dd, 0.0);
+      else tn = Dj1 - quad_root_in(c, b1 + b2 - c * dd, -b2 * dd, 0.0, dd);
     } else {
       const double c = ir + a1;
       tn = c != 0.0 ? Dj + b1 / c : 0.5 * (lo + hi);
     }
-    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-    if (tn == t) break;
+    // The model matches f and f' at t and increases between its poles, so a
+    // root of it on the side of t that the sign of f(t) points away from (or
+    // t itself) comes either from f(t) being at the rounding level of the
+    // sum (bound K eps sum|terms|: converged) or from a model without a root
+    // in the bracket (bisect).
+    if (f < 0.0 ? tn <= t : tn >= t) {
+      if (fabs(f) <= kEps * Kn * (ir + fabs(psi) + fabs(phi))) break;
+      tn = 0.5 * (lo + hi);
+    } else if (!(tn > lo && tn < hi)) {
+      tn = 0.5 * (lo + hi);
+    }
     t = tn;
   }
   if (lane == 0) {
@@ -436,14 +501,23 @@ __global__ __launch_bounds__(256) void k_secular(const DcMerge* md, const DcScal
 }
 
 // Gu-Eisenstat: r zhat_i^2 = prod_j (lambda_j - d_i) / prod_{j != i} (d_j - d_i); one wave per i.
-__global__ __launch_bounds__(256) void k_zhat(const DcMerge* md, const DcScal* ms, const double* Dn,
-                                              const double* zn, const int* orig, const double* tau, double* zh) {
+// The wave also gathers the tracked rows of candidate i, Rt[i][r] = Rw[r][c(nd_i)]
+// (contiguous per candidate, zero-padded to npad rows: the layout k_vec reads).
+__global__ __launch_bounds__(256) void k_zhat(const DcMerge* md, const DcScal* ms, int nr, int npad, int k,
+                                              const double* Rw,
+                                              const int* nd, const double* Dn, const double* zn, const int* orig,
+                                              const double* tau, double* zh, double* Rt) {
   const DcMerge g = md[blockIdx.y];
   const DcScal& s = ms[blockIdx.y];
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int Kn = s.Kn;
   if (i >= Kn) return;
+  if (lane < npad) {
+    const int w = nd[g.a + i];
+    const int c = s.sg > 0 ? w : g.K - 1 - w;
+    Rt[(size_t)(g.a + i) * npad + lane] = lane < nr ? Rw[(size_t)lane * k + g.a + c] : 0.0;
+  }
   const double* d = Dn + g.a;
   const int* og = orig + g.a;
   const double* tt = tau + g.a;
@@ -461,48 +535,91 @@ __global__ __launch_bounds__(256) void k_zhat(const DcMerge* md, const DcScal* m
 }
 
 // Eigenvector j of D + r z z^T is zhat ./ (d - lambda_j), normalised; the
-// tracked rows become Rows(:, nd) * u_j.  One wave per j.
-__global__ __launch_bounds__(256) void k_vec(const DcMerge* md, const DcScal* ms, int ell, int k, const double* Rw,
-                                             const double* Dn, const int* nd, const int* orig, const double* tau,
-                                             const double* zh, double* NR) {
+// tracked rows become Rows(:, nd) * u_j.  Lane = root j (64 roots per wave),
+// wave = one of nsp slices of the candidates i; the candidate data (d_i,
+// zhat_i, Rt[i][:]) is the same for every lane, so each wave streams it once
+// for 64 roots.  Per slice sp, rows r < nr and (r = nr) the squared norm go to
+// part[(sp (nr+1) + r) k + a + j]; k_vec_sum adds the slices up.
+template <int NRP>
+__global__ __launch_bounds__(256) void k_vec(const DcMerge* __restrict__ md, const DcScal* __restrict__ ms, int nr,
+                                             int k, int nsp, const double* __restrict__ Rt,
+                                             const double* __restrict__ Dn, const int* __restrict__ orig,
+                                             const double* __restrict__ tau, const double* __restrict__ zh,
+                                             double* __restrict__ part) {
   const DcMerge g = md[blockIdx.y];
-  const DcScal& s = ms[blockIdx.y];
+  const int Kn = ms[blockIdx.y].Kn;
+  const int nsp4 = nsp >> 2;
+  const int chunk = blockIdx.x / nsp4;
+  const int sp = (blockIdx.x % nsp4) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (chunk * 64 >= Kn) return;
   const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int Kn = s.Kn;
-  if (j >= Kn) return;
-  const int nr = 4 * ell;
+  const int jr = chunk * 64 + lane;
+  const int j = min(jr, Kn - 1);
   const double* d = Dn + g.a;
   const double dO = d[orig[g.a + j]];
   const double tj = tau[g.a + j];
-  double acc[kRows];
+  const int span = (Kn + nsp - 1) / nsp;
+  const int i0 = min(Kn, sp * span), i1 = min(Kn, i0 + span);
+  double acc[NRP];
 #pragma unroll
-  for (int r = 0; r < kRows; ++r) acc[r] = 0.0;
+  for (int r = 0; r < NRP; ++r) acc[r] = 0.0;
   double nn = 0.0;
-  for (int i = lane; i < Kn; i += 64) {
+#pragma unroll 2
+  for (int i = i0; i < i1; ++i) {
     const double u = zh[g.a + i] / ((d[i] - dO) - tj);
     nn = fma(u, u, nn);
-    const int w = nd[g.a + i];
-    const int c = s.sg > 0 ? w : g.K - 1 - w;
+    const double* R = Rt + (size_t)(g.a + i) * NRP;  // rows >= nr are zero
 #pragma unroll
-    for (int r = 0; r < kRows; ++r)
-      if (r < nr) acc[r] = fma(Rw[(size_t)r * k + g.a + c], u, acc[r]);
+    for (int r = 0; r < NRP; ++r) acc[r] = fma(R[r], u, acc[r]);
   }
-  nn = wave_sum(nn);
-  const double inv = 1.0 / sqrt(nn);
+  if (jr < Kn) {
+    double* P = part + (size_t)sp * (nr + 1) * k + g.a + jr;
 #pragma unroll
-  for (int r = 0; r < kRows; ++r) {
-    if (r < nr) {
-      const double v = wave_sum(acc[r]);
-      if (lane == 0) NR[(size_t)r * k + g.a + j] = v * inv;
-    }
+    for (int r = 0; r < NRP; ++r)
+      if (r < nr) P[(size_t)r * k] = acc[r];
+    P[(size_t)nr * k] = nn;
   }
+}
+
+constexpr int kMaxSplit = 16;
+
+// NR[r][a + j] = sum over slices of part (rows r < nr), nrm[a + j] = the squared
+// norm; one thread per (row, root).
+__global__ void k_vec_sum(const DcMerge* md, const DcScal* ms, int nr, int k, int nsp, const double* part, double* NR,
+                          double* nrm) {
+  const DcMerge g = md[blockIdx.y];
+  const int Kn = ms[blockIdx.y].Kn;
+  const size_t ps = (size_t)(nr + 1) * k;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < (nr + 1) * Kn; e += gridDim.x * blockDim.x) {
+    const int r = e / Kn, j = e - r * Kn;
+    const double* P = part + (size_t)r * k + g.a + j;
+    double v = 0.0;
+    for (int sp = 0; sp < nsp; ++sp) v += P[sp * ps];
+    if (r < nr) NR[(size_t)r * k + g.a + j] = v;
+    else nrm[g.a + j] = v;
+  }
+}
+
+inline int vec_pad(int nr) { return nr <= 8 ? 8 : nr <= 16 ? 16 : nr <= 32 ? 32 : 64; }
+
+void launch_vec(dim3 grid, const DcMerge* md, const DcScal* ms, int nr, int k, int nsp, const double* Rt,
+                const double* Dn, const int* orig, const double* tau, const double* zh, double* part,
+                hipStream_t st) {
+  if (nr <= 8)
+    hipLaunchKernelGGL(k_vec<8>, grid, dim3(256), 0, st, md, ms, nr, k, nsp, Rt, Dn, orig, tau, zh, part);
+  else if (nr <= 16)
+    hipLaunchKernelGGL(k_vec<16>, grid, dim3(256), 0, st, md, ms, nr, k, nsp, Rt, Dn, orig, tau, zh, part);
+  else if (nr <= 32)
+    hipLaunchKernelGGL(k_vec<32>, grid, dim3(256), 0, st, md, ms, nr, k, nsp, Rt, Dn, orig, tau, zh, part);
+  else
+    hipLaunchKernelGGL(k_vec<64>, grid, dim3(256), 0, st, md, ms, nr, k, nsp, Rt, Dn, orig, tau, zh, part);
 }
 
 // New spectrum = deflated values U new roots, merged in ascending order (ties:
 // deflated first), mapped back to the original orientation.
 __global__ void k_assemble(const DcMerge* md, const DcScal* ms, int ell, int k, const double* Rin, const double* NR,
-                           const int* defl, const double* defv, const double* lamn, double* Dout, double* Rout) {
+                           const double* nrm, const int* defl, const double* defv, const double* lamn, double* Dout,
+                           double* Rout) {
   const DcMerge g = md[blockIdx.y];
   const DcScal& s = ms[blockIdx.y];
   const int a = g.a, K = g.K, Kn = s.Kn, Kd = s.Kd, sg = s.sg;
@@ -530,7 +647,8 @@ __global__ void k_assemble(const DcMerge* md, const DcScal* ms, int ell, int k, 
       for (int r = 0; r < nr; ++r) Rout[(size_t)r * k + a + P] = Rin[(size_t)r * k + a + c];
     } else {
       const int j = e - Kd;
-      for (int r = 0; r < nr; ++r) Rout[(size_t)r * k + a + P] = NR[(size_t)r * k + a + j];
+      const double inv = 1.0 / sqrt(nrm[a + j]);
+      for (int r = 0; r < nr; ++r) Rout[(size_t)r * k + a + P] = NR[(size_t)r * k + a + j] * inv;
     }
   }
 }
@@ -554,7 +672,7 @@ struct DcWork::Impl {
   hipStream_t st;
   int cap = 0;
   int leaf = 32;
-  DevBuf Da, Db, Ra, Rb, z, Dn, zn, nd, defl, defv, orig, tau, lamn, zh, NR, sml, smv, rdl, rdv;
+  DevBuf Da, Db, Ra, Rb, z, Dn, zn, nd, defl, defv, orig, tau, lamn, zh, Rt, part, NR, nrm, sml, smv, rdl, rdv;
   DevBuf leafA, leafQ, leafL, leafN;
   DevBuf md, ms;
   int md_cap = 0;
@@ -565,7 +683,10 @@ struct DcWork::Impl {
     c = (c + 255) / 256 * 256;
     const size_t d = (size_t)c * sizeof(double), ii = (size_t)c * sizeof(int);
     Da.alloc(d); Db.alloc(d);
-    Ra.alloc(d * 4 * ell); Rb.alloc(d * 4 * ell); NR.alloc(d * 4 * ell);
+    Ra.alloc(d * 4 * ell); Rb.alloc(d * 4 * ell); Rt.alloc(d * vec_pad(4 * ell));
+    part.alloc(d * (4 * ell + 1) * kMaxSplit);
+    NR.alloc(d * 4 * ell);
+    nrm.alloc(d);
     z.alloc(d); Dn.alloc(d); zn.alloc(d); defv.alloc(d); tau.alloc(d); lamn.alloc(d); zh.alloc(d);
     nd.alloc(ii); defl.alloc(ii); orig.alloc(ii); sml.alloc(ii); rdl.alloc(ii);
     smv.alloc(d); rdv.alloc(d);
@@ -631,6 +752,11 @@ void DcWork::run(const double* band, int ldb, int k, double* lam, double* F, dou
     DcScal* ms = w.ms.as<DcScal>();
     const int gx = std::min((Kmax + 255) / 256, 64);
     const int gw = (Kmax + 3) / 4;  // one wave per element, 4 waves per block
+    // k_vec: 64 roots per wave, candidate slices so that a level has ~2048 waves
+    const int nr = 4 * ell;
+    const int nchunk = (Kmax + 63) / 64;
+    int nsp = (2048 + nchunk * nm - 1) / (nchunk * nm);
+    nsp = std::min(kMaxSplit, std::max(4, (nsp + 3) / 4 * 4));
     double* Dcur = w.Da.as<double>();
     double* Dnx = w.Db.as<double>();
     double* Rcur = w.Ra.as<double>();
@@ -645,12 +771,15 @@ void DcWork::run(const double* band, int ldb, int k, double* lam, double* F, dou
                          w.rdv.as<double>());
       hipLaunchKernelGGL(k_secular, dim3(gw, nm), dim3(256), 0, st, md, ms, w.Dn.as<double>(), w.zn.as<double>(),
                          w.orig.as<int>(), w.tau.as<double>(), w.lamn.as<double>());
-      hipLaunchKernelGGL(k_zhat, dim3(gw, nm), dim3(256), 0, st, md, ms, w.Dn.as<double>(), w.zn.as<double>(),
-                         w.orig.as<int>(), w.tau.as<double>(), w.zh.as<double>());
-      hipLaunchKernelGGL(k_vec, dim3(gw, nm), dim3(256), 0, st, md, ms, ell, k, Rcur, w.Dn.as<double>(),
-                         w.nd.as<int>(), w.orig.as<int>(), w.tau.as<double>(), w.zh.as<double>(), w.NR.as<double>());
+      hipLaunchKernelGGL(k_zhat, dim3(gw, nm), dim3(256), 0, st, md, ms, nr, vec_pad(nr), k, Rcur, w.nd.as<int>(),
+                         w.Dn.as<double>(), w.zn.as<double>(), w.orig.as<int>(), w.tau.as<double>(),
+                         w.zh.as<double>(), w.Rt.as<double>());
+      launch_vec(dim3(nchunk * (nsp / 4), nm), md, ms, nr, k, nsp, w.Rt.as<double>(), w.Dn.as<double>(),
+                 w.orig.as<int>(), w.tau.as<double>(), w.zh.as<double>(), w.part.as<double>(), st);
+      hipLaunchKernelGGL(k_vec_sum, dim3(std::min(((nr + 1) * Kmax + 255) / 256, 1024), nm), dim3(256), 0, st, md,
+                         ms, nr, k, nsp, w.part.as<double>(), w.NR.as<double>(), w.nrm.as<double>());
       hipLaunchKernelGGL(k_assemble, dim3(gx, nm), dim3(256), 0, st, md, ms, ell, k, Rcur, w.NR.as<double>(),
-                         w.defl.as<int>(), w.defv.as<double>(), w.lamn.as<double>(), Dnx, Rnx);
+                         w.nrm.as<double>(), w.defl.as<int>(), w.defv.as<double>(), w.lamn.as<double>(), Dnx, Rnx);
       std::swap(Dcur, Dnx);
       std::swap(Rcur, Rnx);
     }

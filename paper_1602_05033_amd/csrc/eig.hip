@@ -160,27 +160,32 @@ __device__ int jacobi_core(double* A, double* Q, int n, int max_sweeps, int* sp,
 // Matrix b of the batch: A + b*strideA (n x n, row-major, lda = n), eigenvector
 // matrix Q + b*strideQ (row-major, eigenvector i in column i), eigenvalues
 // lam + b*strideL, ascending.  On exit A is destroyed.
+// NN > 0: every matrix of the batch has n <= NN and is worked on in LDS by one
+// wave; NN == 0: global memory, kJacThreads threads.
+template <int NN>
 __global__ __launch_bounds__(kJacThreads) void k_jacobi(double* Aall, int64_t strideA, double* Qall, int64_t strideQ,
                                                        double* lamall, int64_t strideL, const int* nlist, int nfixed,
                                                        int max_sweeps, int* sweeps_out) {
+  constexpr int MAXN = NN > 0 ? NN : kJacMaxN;
+  constexpr int LDSN = NN > 0 ? NN : 1;
   const int bidx = blockIdx.x;
   const int n = nlist ? nlist[bidx] : nfixed;
   double* Ag = Aall + bidx * strideA;
   double* Qg = Qall + bidx * strideQ;
   double* lam = lamall + bidx * strideL;
-  __shared__ int sp[kJacMaxN / 2 + 1], sq[kJacMaxN / 2 + 1];
-  __shared__ double sc[kJacMaxN / 2 + 1], ss[kJacMaxN / 2 + 1];
-  __shared__ double As[kJacLds * kJacLds], Qs[kJacLds * kJacLds];
-  __shared__ double stt[3 * (kJacMaxN / 2 + 1)];
+  __shared__ int sp[MAXN / 2 + 1], sq[MAXN / 2 + 1];
+  __shared__ double sc[MAXN / 2 + 1], ss[MAXN / 2 + 1];
+  __shared__ double As[LDSN * LDSN], Qs[LDSN * LDSN];
+  __shared__ double stt[3 * (MAXN / 2 + 1)];
   __shared__ int nrot;
-  __shared__ int rk[kJacMaxN];
+  __shared__ int rk[MAXN];
   if (n <= 0) return;
-  const bool lds = n <= kJacLds;
+  constexpr bool lds = NN > 0;
   int nsw;
-  if (lds) {
+  if constexpr (lds) {
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) As[e] = Ag[e];
     __syncthreads();
-    nsw = jacobi_core<kJacLds>(As, Qs, n, max_sweeps, sp, sq, sc, ss, stt, &nrot);
+    nsw = jacobi_core<NN>(As, Qs, n, max_sweeps, sp, sq, sc, ss, stt, &nrot);
   } else {
     nsw = jacobi_core<0>(Ag, Qg, n, max_sweeps, sp, sq, sc, ss, stt, &nrot);
   }
@@ -558,10 +563,21 @@ void launch_jacobi(double* A, int64_t strideA, double* Q, int64_t strideQ, doubl
                    const int* nlist, int nfixed, int batch, hipStream_t st, int* sweeps) {
   LYAP_REQUIRE(nfixed <= kJacMaxN, LYAP_E_UNSUPPORTED, "dense eigensolver limited to n <= %d (got %d)", kJacMaxN,
                nfixed);
-  // nfixed is the largest n of the batch; LDS-sized matrices run on one wave
-  const int threads = nfixed <= kJacLds ? 64 : kJacThreads;
-  hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(threads), 0, st, A, strideA, Q, strideQ, lam, strideL, nlist,
-                     nfixed, 40, sweeps);
+  // nfixed is the largest n of the batch; LDS-sized matrices run on one wave,
+  // with the rotation loops unrolled for the smallest size class that fits
+  const dim3 g(batch);
+  if (nfixed <= 8)
+    hipLaunchKernelGGL(k_jacobi<8>, g, dim3(64), 0, st, A, strideA, Q, strideQ, lam, strideL, nlist, nfixed, 40, sweeps);
+  else if (nfixed <= 16)
+    hipLaunchKernelGGL(k_jacobi<16>, g, dim3(64), 0, st, A, strideA, Q, strideQ, lam, strideL, nlist, nfixed, 40, sweeps);
+  else if (nfixed <= 32)
+    hipLaunchKernelGGL(k_jacobi<32>, g, dim3(64), 0, st, A, strideA, Q, strideQ, lam, strideL, nlist, nfixed, 40, sweeps);
+  else if (nfixed <= kJacLds)
+    hipLaunchKernelGGL(k_jacobi<kJacLds>, g, dim3(64), 0, st, A, strideA, Q, strideQ, lam, strideL, nlist, nfixed, 40,
+                       sweeps);
+  else
+    hipLaunchKernelGGL(k_jacobi<0>, g, dim3(kJacThreads), 0, st, A, strideA, Q, strideQ, lam, strideL, nlist, nfixed,
+                       40, sweeps);
   LYAP_LAUNCHED("jacobi");
 }
 

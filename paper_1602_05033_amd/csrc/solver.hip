@@ -333,8 +333,9 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
     const int mm = pending_mm;
     const CheckOut c = *hchk.as<CheckOut>();
     const int fb = hflags.as<int>()[0], fn = hflags.as<int>()[1];
-    LYAP_REQUIRE(!(fn > 0 && fn <= mm), LYAP_E_NUMERIC, "non-finite values in the Lanczos recurrence at step %d",
-                 fn);
+    // non-finite values that follow a breakdown belong to the breakdown
+    LYAP_REQUIRE(!(fn > 0 && fn <= mm && (fb == 0 || fn <= fb)), LYAP_E_NUMERIC,
+                 "non-finite values in the Lanczos recurrence at step %d", fn);
     if (fb > 0 && fb <= mm) {
       // a rank-deficient block at step fb-1: check the basis it ends instead
       LYAP_HIP(hipStreamSynchronize(st));

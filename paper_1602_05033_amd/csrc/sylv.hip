@@ -348,90 +348,154 @@ lyap_status sylv_impl(const lyap_op* A, const lyap_op* B, const double* C1, int6
   out->beta2 = sb.beta();
   const double b12 = sa.beta() * sb.beta();
 
-  Checker ca(S, S, st), cb(S, S, st);
+  // Checks run on a second stream while both sides keep stepping (see
+  // solve_std): a check at mm reads only the two leading bands and logs.
+  constexpr int kAhead = 24;
+  const bool overlap = o.profile == 0;
+  hipStream_t cst = st;
+  struct StreamGuard {
+    hipStream_t s = nullptr;
+    ~StreamGuard() { if (s) (void)hipStreamDestroy(s); }
+  } sg;
+  if (overlap) {
+    LYAP_HIP(hipStreamCreateWithFlags(&sg.s, hipStreamNonBlocking));
+    cst = sg.s;
+  }
+  struct EventRing {
+    std::vector<hipEvent_t> ev;
+    ~EventRing() { for (auto e : ev) (void)hipEventDestroy(e); }
+  } er;
+  er.ev.resize(kAhead + 2);
+  for (auto& e : er.ev) LYAP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  hipEvent_t ev_step = er.ev[kAhead], ev_chk = er.ev[kAhead + 1];
+
+  Checker ca(S, S, cst), cb(S, S, cst);
   DevBuf part(4096 * sizeof(double)), counter(64), chk(sizeof(CheckOut));
-  HostBuf hchk(sizeof(CheckOut));
+  HostBuf hchk(sizeof(CheckOut) + 4 * sizeof(double) + 4 * sizeof(int));
   LYAP_HIP(hipMemsetAsync(counter.p, 0, 64, st));
+  LYAP_HIP(hipStreamSynchronize(st));
   CheckSchedule sched{o.check_every, maxit};
   std::vector<int> hm;
   std::vector<double> hr;
   double check_ms = 0.0, t_to_tol = 0.0, lamA_abs = 0.0, lamB_abs = 0.0, last_res = INFINITY;
-  int next_check = sched.first(), m = 0, checked_m = 0;
+  int next_check = sched.first(), m = 0;
   lyap_status status = LYAP_NOT_CONVERGED;
+  bool pending = false;
+  int pending_mm = 0;
+  CheckOut* hc = hchk.as<CheckOut>();
+  double* hl = reinterpret_cast<double*>(hchk.as<char>() + sizeof(CheckOut));
+  int* hf = reinterpret_cast<int*>(hchk.as<char>() + sizeof(CheckOut) + 4 * sizeof(double));
 
-  auto run_check = [&](int mm) {
-    const auto t0 = Clock::now();
+  auto launch_check = [&](int mm) {
+    LYAP_HIP(hipEventRecord(ev_step, st));
+    LYAP_HIP(hipStreamWaitEvent(cst, ev_step, 0));
     kt.mark(LYAP_K_CHECK);
     const int k = mm * S;
     ca.prepare(sa.band(), k, sa.gamma_dev(), sa.tau_dev(mm));
     cb.prepare(sb.band(), k, sb.gamma_dev(), sb.tau_dev(mm));
     const int grid = std::max(1, std::min(2 * k, 2048));
-    hipLaunchKernelGGL(k_sylv_sum, dim3(grid), dim3(kBlock), 0, st, ca.lam(), ca.g(), ca.Wm(), cb.lam(), cb.g(),
+    hipLaunchKernelGGL(k_sylv_sum, dim3(grid), dim3(kBlock), 0, cst, ca.lam(), ca.g(), ca.Wm(), cb.lam(), cb.g(),
                        cb.Wm(), k, S, S, part.as<double>(), counter.as<unsigned>(), chk.as<CheckOut>());
     LYAP_LAUNCHED("k_sylv_sum");
-    kt.collect();
-    LYAP_HIP(hipMemcpyAsync(hchk.p, chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, st));
-    double lams[4];
-    LYAP_HIP(hipMemcpyAsync(&lams[0], ca.lam(), sizeof(double), hipMemcpyDeviceToHost, st));
-    LYAP_HIP(hipMemcpyAsync(&lams[1], ca.lam() + k - 1, sizeof(double), hipMemcpyDeviceToHost, st));
-    LYAP_HIP(hipMemcpyAsync(&lams[2], cb.lam(), sizeof(double), hipMemcpyDeviceToHost, st));
-    LYAP_HIP(hipMemcpyAsync(&lams[3], cb.lam() + k - 1, sizeof(double), hipMemcpyDeviceToHost, st));
-    LYAP_HIP(hipStreamSynchronize(st));
-    check_ms += ms_since(t0);
-    checked_m = mm;
-    lamA_abs = std::max(std::fabs(lams[0]), std::fabs(lams[1]));
-    lamB_abs = std::max(std::fabs(lams[2]), std::fabs(lams[3]));
+    LYAP_HIP(hipMemcpyAsync(hc, chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, cst));
+    LYAP_HIP(hipMemcpyAsync(&hl[0], ca.lam(), sizeof(double), hipMemcpyDeviceToHost, cst));
+    LYAP_HIP(hipMemcpyAsync(&hl[1], ca.lam() + k - 1, sizeof(double), hipMemcpyDeviceToHost, cst));
+    LYAP_HIP(hipMemcpyAsync(&hl[2], cb.lam(), sizeof(double), hipMemcpyDeviceToHost, cst));
+    LYAP_HIP(hipMemcpyAsync(&hl[3], cb.lam() + k - 1, sizeof(double), hipMemcpyDeviceToHost, cst));
+    LYAP_HIP(hipMemcpyAsync(&hf[0], sa.flags_dev(), 2 * sizeof(int), hipMemcpyDeviceToHost, cst));
+    LYAP_HIP(hipMemcpyAsync(&hf[2], sb.flags_dev(), 2 * sizeof(int), hipMemcpyDeviceToHost, cst));
+    LYAP_HIP(hipEventRecord(ev_chk, cst));
+    pending = true;
+    pending_mm = mm;
     out->n_checks++;
-    return *hchk.as<CheckOut>();
+  };
+  auto wait_check = [&]() {
+    const auto t0 = Clock::now();
+    LYAP_HIP(hipEventSynchronize(ev_chk));
+    check_ms += ms_since(t0);
+    kt.collect();
+  };
+  auto record = [&](int mm) -> double {
+    const CheckOut c = *hc;
+    LYAP_REQUIRE(std::isfinite(c.res), LYAP_E_NUMERIC, "residual is not finite at m=%d", mm);
+    const double rel = c.res / b12;
+    hm.push_back(mm);
+    hr.push_back(rel);
+    last_res = rel;
+    lamA_abs = std::max(std::fabs(hl[0]), std::fabs(hl[1]));
+    lamB_abs = std::max(std::fabs(hl[2]), std::fabs(hl[3]));
+    if (o.verbose) std::fprintf(stderr, "[sylv] m=%d k=%d res=%.3e\n", mm, mm * S, rel);
+    LYAP_REQUIRE(c.lam_max < 0.0, LYAP_E_INDEFINITE,
+                 "Ritz value %.3e >= 0 at m=%d: an operator is not negative definite", c.lam_max, mm);
+    return rel;
+  };
+  // returns true when the iteration stops
+  auto finish_check = [&]() -> bool {
+    pending = false;
+    const int mm = pending_mm;
+    int fbk = 0, fnf = 0;
+    for (int f : {hf[0], hf[2]})
+      if (f > 0 && f <= mm && (fbk == 0 || f < fbk)) fbk = f;
+    for (int f : {hf[1], hf[3]})
+      if (f > 0 && f <= mm && (fnf == 0 || f < fnf)) fnf = f;
+    // non-finite values that follow a breakdown belong to the breakdown
+    LYAP_REQUIRE(!(fnf > 0 && (fbk == 0 || fnf <= fbk)), LYAP_E_NUMERIC,
+                 "non-finite values in the Lanczos recurrences at step %d", fnf);
+    if (fbk > 0) {  // a rank-deficient block: check the basis it ends instead
+      LYAP_HIP(hipStreamSynchronize(st));
+      launch_check(fbk);
+      wait_check();
+      pending = false;
+      const double rel = record(fbk);
+      m = fbk;
+      if (rel <= o.tol) {
+        status = LYAP_OK;
+        t_to_tol = ms_since(t_entry);
+      } else {
+        status = LYAP_E_BREAKDOWN;
+        set_error("block Lanczos breakdown at m=%d with residual %.3e above tol", fbk, rel);
+      }
+      return true;
+    }
+    const double rel = record(mm);
+    if (rel <= o.tol) {
+      status = LYAP_OK;
+      m = mm;
+      t_to_tol = ms_since(t_entry);
+      return true;
+    }
+    if (mm >= maxit) {
+      m = mm;
+      return true;
+    }
+    next_check = sched.next(mm, rel, o.tol);
+    return false;
   };
 
   const auto t_pass1 = Clock::now();
-  while (m < maxit) {
+  int steps = 0;
+  while (true) {
+    if (pending) {
+      const hipError_t q = hipEventQuery(ev_chk);
+      if (q == hipSuccess || steps >= maxit || !overlap) {
+        if (q != hipSuccess) wait_check();
+        if (finish_check()) break;
+      } else if (q != hipErrorNotReady) {
+        LYAP_HIP(q);
+      }
+    }
+    if (!pending && (steps >= next_check || steps >= maxit)) {
+      launch_check(std::min(next_check, steps));
+      continue;
+    }
+    if (steps >= maxit) continue;
+    if (steps >= kAhead) LYAP_HIP(hipEventSynchronize(er.ev[steps % kAhead]));
     sa.step();
     sb.step();
-    m = sa.m();
-    if (m == next_check || m == maxit) {
-      int fa = 0, na = 0, fb = 0, nb = 0;
-      sa.read_flags(&fa, &na);
-      sb.read_flags(&fb, &nb);
-      LYAP_REQUIRE(na == 0 && nb == 0, LYAP_E_NUMERIC, "non-finite values in the Lanczos recurrences");
-      int mm = m;
-      bool broke = false;
-      for (int f : {fa, fb})
-        if (f > 0 && f <= mm) {
-          mm = f;
-          broke = true;
-        }
-      CheckOut c = run_check(mm);
-      LYAP_REQUIRE(std::isfinite(c.res), LYAP_E_NUMERIC, "residual is not finite at m=%d", mm);
-      const double rel = c.res / b12;
-      hm.push_back(mm);
-      hr.push_back(rel);
-      last_res = rel;
-      if (o.verbose) std::fprintf(stderr, "[sylv] m=%d k=%d res=%.3e\n", mm, mm * S, rel);
-      LYAP_REQUIRE(c.lam_max < 0.0, LYAP_E_INDEFINITE,
-                   "Ritz value %.3e >= 0 at m=%d: an operator is not negative definite", c.lam_max, mm);
-      if (rel <= o.tol) {
-        status = LYAP_OK;
-        m = mm;
-        t_to_tol = ms_since(t_entry);
-        break;
-      }
-      if (broke) {
-        m = mm;
-        status = LYAP_E_BREAKDOWN;
-        set_error("block Lanczos breakdown at m=%d with residual %.3e above tol", mm, rel);
-        break;
-      }
-      next_check = sched.next(m, rel, o.tol);
-    }
+    LYAP_HIP(hipEventRecord(er.ev[steps % kAhead], st));
+    ++steps;
   }
-  if (checked_m != m) {
-    CheckOut c = run_check(m);
-    hm.push_back(m);
-    hr.push_back(c.res / b12);
-    last_res = c.res / b12;
-  }
+  if (overlap) LYAP_HIP(hipStreamWaitEvent(st, ev_chk, 0));
   const double pass1_ms = ms_since(t_pass1) - check_ms;
   out->m = m;
   out->res = last_res;
