@@ -452,56 +452,93 @@ __global__ __launch_bounds__(stream_threads(S)) void k_init_apply(const double* 
 // ------------------------------------------------------------------ Z accumulation
 // Z[:, c] += sum_{b < nb} V_b M_{[b]}[:, c] for the blocks listed in bl
 // (nb <= 64), i.e. Z (n x t, column-major) += [V_b ...] (n x nb*S) times
-// Mrows (nb*S x t, row-major).  Workgroup tile: 64 rows x 64 columns of Z; lane
-// = row (coalesced Z and V accesses), wave = group of 16 columns kept in
-// registers; chunks of M staged in LDS and read by broadcast.  Plain FP64
-// FMAs, accumulated in the order of the buffered blocks, starting from Z.
-constexpr int kZR = 64, kZC = 64;
-
+// Mrows (nb*S x t, row-major).  Plain FP64 FMAs, accumulated in the order of
+// the buffered blocks, starting from Z.  The work is FP64 FMA bound (2 nb S t
+// flops per row against 16 t bytes of Z), so the tile is built for FMA issue:
+// a lane owns kZRT rows (r, r + 64, ...) by kZCW columns of Z in registers;
+// per block it reads its rows of V_b with one vector load each (the next
+// block's rows are loaded while this block's FMAs run), and the M entries,
+// the same for the whole wave, are scalar operands (no LDS traffic).  A
+// workgroup's kZW waves cover kZW * kZCW consecutive columns over the same
+// rows, so V is read from HBM once per workgroup.  FULL: all kZCW columns of
+// the wave exist (contiguous scalar loads of M); the last partial column tile
+// runs as a separate launch with FULL = false.
+constexpr int kZCW = 8, kZW = 8;
+// rows per lane: 8 for rows of up to 16 bytes, fewer for wider rows (registers)
 template <typename T, int S>
-__global__ __launch_bounds__(256) void k_zflush(BlockList bl, int nb, int n, const double* Mrows, int t, double* Z,
-                                                int64_t ldz) {
-  constexpr int KQ = S * (32 / S);  // q values per LDS chunk (a multiple of S)
-  __shared__ double Ms[KQ * kZC];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int r = blockIdx.x * kZR + lane;
-  const int c0 = blockIdx.y * kZC;
-  const int cw = c0 + wv * 16;
-  const bool rowok = r < n;
-  double acc[16];
+constexpr int zflush_rt() {
+  return S * (int)sizeof(T) <= 16 ? 8 : S * (int)sizeof(T) <= 32 ? 4 : 2;
+}
+
+template <typename T, int S, bool FULL>
+__global__ __launch_bounds__(64 * kZW) void k_zflush(BlockList bl, int nb, int n, const double* __restrict__ Mrows,
+                                                     int ldm, int t, double* __restrict__ Z, int64_t ldz) {
+  constexpr int kZRT = zflush_rt<T, S>();
+  constexpr int kZR = 64 * kZRT;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int c0 = (blockIdx.y * kZW + wv) * kZCW;
+  if (c0 >= t) return;
+  const int cmax = FULL ? kZCW - 1 : min(kZCW, t - c0) - 1;  // columns past t read column t-1, are not stored
+  const int r0 = blockIdx.x * kZR + lane;
+  // rows past n compute on row n-1 (branch-free loads) and are not stored
+  int rr[kZRT];
 #pragma unroll
-  for (int cc = 0; cc < 16; ++cc) acc[cc] = (rowok && cw + cc < t) ? Z[(size_t)(cw + cc) * ldz + r] : 0.0;
+  for (int i = 0; i < kZRT; ++i) rr[i] = min(r0 + 64 * i, n - 1);
+  double acc[kZRT][kZCW];
+#pragma unroll
+  for (int i = 0; i < kZRT; ++i)
+#pragma unroll
+    for (int c = 0; c < kZCW; ++c) acc[i][c] = Z[(size_t)(c0 + min(c, cmax)) * ldz + rr[i]];
+  T x[kZRT][S];
+#pragma unroll
+  for (int i = 0; i < kZRT; ++i) load_row<T, S>((const T*)bl.p[0] + (size_t)rr[i] * S, x[i]);
+  // M row of the current q; the next one is requested before this q's FMAs
+  // (scalar loads complete out of order, so a wait covers all of them)
   const int nq = nb * S;
-  for (int q0 = 0; q0 < nq; q0 += KQ) {
-    const int qn = min(KQ, nq - q0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < qn * kZC; e += 256) {
-      const int qi = e / kZC, cc = e - qi * kZC;
-      Ms[qi * kZC + cc] = (c0 + cc < t) ? Mrows[(size_t)(q0 + qi) * t + c0 + cc] : 0.0;
-    }
-    __syncthreads();
-    for (int bq = 0; bq < qn; bq += S) {
-      const int b = (q0 + bq) / S;
-      T x[S];
-      if (rowok) {
-        load_row<T, S>((const T*)bl.p[b] + (size_t)r * S, x);
-      } else {
+  double m[kZCW];
 #pragma unroll
-        for (int q = 0; q < S; ++q) x[q] = T(0);
+  for (int c = 0; c < kZCW; ++c) m[c] = Mrows[c0 + min(c, cmax)];
+#pragma unroll 1
+  for (int b = 0; b < nb; ++b) {
+    const T* Vn = (const T*)bl.p[b + 1 < nb ? b + 1 : b];
+    T xn[kZRT][S];
+#pragma unroll
+    for (int i = 0; i < kZRT; ++i) load_row<T, S>(Vn + (size_t)rr[i] * S, xn[i]);
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      // wait for this q's M row (lgkmcnt(0); vmcnt and expcnt left free)
+      // before the next one is requested
+      __builtin_amdgcn_s_waitcnt(0xC07F);
+      const int qn = min(b * S + q + 1, nq - 1);
+      const double* Mn = Mrows + (size_t)qn * ldm + c0;
+      double mn[kZCW];
+#pragma unroll
+      for (int c = 0; c < kZCW; ++c) mn[c] = Mn[min(c, cmax)];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < kZRT; ++i) {
+        const double a = (double)x[i][q];
+#pragma unroll
+        for (int c = 0; c < kZCW; ++c) acc[i][c] = fma(a, m[c], acc[i][c]);
       }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int q = 0; q < S; ++q) {
-        const double a = (double)x[q];
-        const double* mrow = Ms + (bq + q) * kZC + wv * 16;
-#pragma unroll
-        for (int cc = 0; cc < 16; ++cc) acc[cc] = fma(a, mrow[cc], acc[cc]);
-      }
+      for (int c = 0; c < kZCW; ++c) m[c] = mn[c];
     }
+#pragma unroll
+    for (int i = 0; i < kZRT; ++i)
+#pragma unroll
+      for (int q = 0; q < S; ++q) x[i][q] = xn[i][q];
   }
-  if (rowok) {
 #pragma unroll
-    for (int cc = 0; cc < 16; ++cc)
-      if (cw + cc < t) Z[(size_t)(cw + cc) * ldz + r] = acc[cc];
+  for (int i = 0; i < kZRT; ++i) {
+    const int r = r0 + 64 * i;
+    if (r < n) {
+#pragma unroll
+      for (int c = 0; c < kZCW; ++c)
+        if (c <= cmax) Z[(size_t)(c0 + c) * ldz + r] = acc[i][c];
+    }
   }
 }
 
@@ -666,9 +703,16 @@ void launch_zflush(const void* const* blocks, int nb, int n, int S, const double
       const int cnt = nb - done < 64 ? nb - done : 64;
       BlockList bl{};
       for (int b = 0; b < cnt; ++b) bl.p[b] = blocks[done + b];
-      dim3 grid((n + kZR - 1) / kZR, (t + kZC - 1) / kZC);
-      hipLaunchKernelGGL((k_zflush<T, S>), grid, dim3(256), 0, st, bl, cnt, n, Mrows + (size_t)done * S * t, t, Z,
-                         ldz);
+      const double* Mc = Mrows + (size_t)done * S * t;
+      const int tf = t / kZCW * kZCW;  // columns in full tiles
+      constexpr int kZR = 64 * zflush_rt<T, S>();
+      if (tf > 0) {
+        dim3 grid((n + kZR - 1) / kZR, (tf / kZCW + kZW - 1) / kZW);
+        hipLaunchKernelGGL((k_zflush<T, S, true>), grid, dim3(64 * kZW), 0, st, bl, cnt, n, Mc, t, tf, Z, ldz);
+      }
+      if (tf < t)
+        hipLaunchKernelGGL((k_zflush<T, S, false>), dim3((n + kZR - 1) / kZR, 1), dim3(64), 0, st, bl, cnt, n, Mc + tf,
+                           t, t - tf, Z + (size_t)tf * ldz, ldz);
       done += cnt;
     }
   });
