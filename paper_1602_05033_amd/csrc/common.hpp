@@ -156,6 +156,19 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sum over aligned groups of G lanes (G a power of two <= 64): the first
+// log2(G) butterfly steps of wave_sum; every lane gets its group's sum.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (G >= 2) v += lane_xor<1>(v);
+  if constexpr (G >= 4) v += lane_xor<2>(v);
+  if constexpr (G >= 8) v += lane_xor<7>(v);
+  if constexpr (G >= 16) v += lane_xor<15>(v);
+  if constexpr (G >= 32) v += lane_xor<16>(v);
+  if constexpr (G >= 64) v += lane_xor<32>(v);
+  return v;
+}
+
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, lane_xor<1>(v));
   v = fmax(v, lane_xor<2>(v));

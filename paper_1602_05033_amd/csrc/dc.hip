@@ -115,8 +115,7 @@ __device__ void svd_small(const double* B, int ell, double* U, double* sig, doub
 
 // ------------------------------------------------------------------ merge setup
 // Builds the sorted eigenvalues of diag(T_L, T_R) and the 4*ell tracked rows
-// [F_L 0; L_L 0; 0 F_R; 0 L_R] in that order; thread 0 of x-block 0 computes
-// the SVD of the coupling block.
+// [F_L 0; L_L 0; 0 F_R; 0 L_R] in that order.
 __global__ void k_merge_setup(const DcMerge* md, DcScal* ms, const double* band, int ldb, int ell, int k,
                               const double* Dm, const double* Fm, const double* Lm, double* Dw, double* Rw) {
   const DcMerge g = md[blockIdx.y];
@@ -146,18 +145,25 @@ __global__ void k_merge_setup(const DcMerge* md, DcScal* ms, const double* band,
       Rw[(size_t)(3 * ell + r) * k + a + pos] = left ? 0.0 : Lm[(size_t)r * k + col];
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double B[kMaxL * kMaxL];
-    // B[r][c] = T(a + K1 + r, a + K1 - ell + c)
-    for (int r = 0; r < ell; ++r)
-      for (int c = 0; c < ell; ++c) {
-        const int row = a + K1 + r, colT = a + K1 - ell + c;
-        const int d = row - colT;
-        B[r * ell + c] = (d >= 0 && d <= ell) ? band[(size_t)colT * ldb + d] : 0.0;
-      }
-    DcScal& s = ms[blockIdx.y];
-    svd_small(B, ell, s.U, s.sigma, s.V);
-  }
+}
+
+// SVD of every merge's coupling block (they depend on T only), one thread per
+// merge of the whole tree.
+__global__ void k_coupling_svd(const DcMerge* md, DcScal* ms, int nm, const double* band, int ldb, int ell) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nm) return;
+  const DcMerge g = md[q];
+  const int a = g.a, K1 = g.K1;
+  double B[kMaxL * kMaxL];
+  // B[r][c] = T(a + K1 + r, a + K1 - ell + c)
+  for (int r = 0; r < ell; ++r)
+    for (int c = 0; c < ell; ++c) {
+      const int row = a + K1 + r, colT = a + K1 - ell + c;
+      const int d = row - colT;
+      B[r * ell + c] = (d >= 0 && d <= ell) ? band[(size_t)colT * ldb + d] : 0.0;
+    }
+  DcScal& s = ms[q];
+  svd_small(B, ell, s.U, s.sigma, s.V);
 }
 
 // z = (R_a^T v_i + sg R_b^T u_i) / sqrt(2) for update u = 2i + (sg < 0)
@@ -347,8 +353,6 @@ __global__ __launch_bounds__(kDefThreads) void k_deflate(const DcMerge* md, DcSc
   if (t == 0) { s.skip = 0; s.Kn = s_Kn; s.Kd = Ks + Nr; s.r = r; }
 }
 
-constexpr int kSecReg = 8;  // merges with Kn <= 64 * kSecReg keep the poles in registers
-
 // sum z_i^2 / (d_i - dO - t) and sum z_i^2 / (d_i - dO - t)^2 over i = i0, i0 + 64,
 // ... < i1 (one lane's share), accumulated in that order; four terms per pass
 // so that their loads are in flight together.
@@ -387,10 +391,57 @@ __device__ __forceinline__ double quad_root_in(double a, double b, double c0, do
   return (x1 > L && x1 < R) ? x1 : x2;
 }
 
-// Secular equation 1/r + sum_i z_i^2/(d_i - lambda) = 0: one wave per root.
-// Root j lies in (d_j, d_{j+1}) (last: (d_{K-1}, d_{K-1} + r||z||^2)); it is
-// stored as the nearer pole index o_j and the offset tau_j = lambda_j - d_{o_j}
-// so that every difference d_i - lambda_j is formed accurately.
+// Secular equation 1/r + sum_i z_i^2/(d_i - lambda) = 0.  Root j lies in
+// (d_j, d_{j+1}) (last: (d_{K-1}, d_{K-1} + r||z||^2)); it is stored as the
+// nearer pole index o_j and the offset tau_j = lambda_j - d_{o_j} so that every
+// difference d_i - lambda_j is formed accurately.
+//
+// One iteration given the sums psi = sum_{i<=j} z_i^2/(d_i - lambda), phi (the
+// rest) and their derivatives at t = lambda - d_o: updates the bracket
+// (lo, hi) and t; returns true once t has converged.
+__device__ __forceinline__ bool secular_step(double ir, double psi, double phi, double dpsi, double dphi, bool last,
+                                             bool o_is_j, double Dj, double Dj1, int Kn, double& lo, double& hi,
+                                             double& t) {
+  const double f = ir + psi + phi;
+  if (f < 0.0) lo = fmax(lo, t); else hi = fmin(hi, t);
+  const double err = 8.0 * kEps * (ir + fabs(psi) + fabs(phi) + fabs(t) * (dpsi + dphi));
+  if (fabs(f) <= err || (hi - lo) <= 4.0 * kEps * fmax(fabs(lo), fabs(hi))) return true;
+  const double dlj = Dj - t;
+  const double b1 = dpsi * dlj * dlj;
+  const double a1 = psi - b1 / dlj;
+  double tn;
+  if (!last) {
+    const double dlj1 = Dj1 - t;
+    const double b2 = dphi * dlj1 * dlj1;
+    const double a2 = phi - b2 / dlj1;
+    const double c = ir + a1 + a2;
+    const double dd = Dj1 - Dj;
+    // root of c + b1/(Dj - x) + b2/(Dj1 - x), solved for its distance to the
+    // origin pole (Dj or Dj1 is 0) so that a root next to that pole keeps
+    // its relative accuracy: u = Dj - x in (-dd, 0) or w = Dj1 - x in (0, dd)
+    if (o_is_j) tn = Dj - quad_root_in(c, c * dd + b1 + b2, b1 * dd, -dd, 0.0);
+    else tn = Dj1 - quad_root_in(c, b1 + b2 - c * dd, -b2 * dd, 0.0, dd);
+  } else {
+    const double c = ir + a1;
+    tn = c != 0.0 ? Dj + b1 / c : 0.5 * (lo + hi);
+  }
+  // The model matches f and f' at t and increases between its poles, so a
+  // root of it on the side of t that the sign of f(t) points away from (or
+  // t itself) comes either from f(t) being at the rounding level of the sum
+  // (bound K eps sum|terms|: converged) or from a model without a root in
+  // the bracket (bisect).
+  if (f < 0.0 ? tn <= t : tn >= t) {
+    if (fabs(f) <= kEps * Kn * (ir + fabs(psi) + fabs(phi))) return true;
+    tn = 0.5 * (lo + hi);
+  } else if (!(tn > lo && tn < hi)) {
+    tn = 0.5 * (lo + hi);
+  }
+  t = tn;
+  return false;
+}
+
+// Merges too large for LDS: one wave per root, the sums stream d and z from
+// memory (L2) every iteration.
 __global__ __launch_bounds__(256) void k_secular(const DcMerge* md, const DcScal* ms, const double* Dn,
                                                  const double* zn, int* orig, double* tau, double* lamn) {
   const DcMerge g = md[blockIdx.y];
@@ -424,79 +475,196 @@ __global__ __launch_bounds__(256) void k_secular(const DcMerge* md, const DcScal
   double t = 0.5 * (lo + hi);
   const double Dj = d[j] - dO;
   const double Dj1 = last ? 0.0 : d[j + 1] - dO;
-  // small problems keep z_i and d_i - d_o (i = lane + 64 u) in registers for
-  // all iterations; padding (z = 0) adds nothing
-  const bool reg = Kn <= 64 * kSecReg;
-  double zr[kSecReg], er[kSecReg];
-  if (reg) {
-#pragma unroll
-    for (int u = 0; u < kSecReg; ++u) {
-      const int i = lane + 64 * u;
-      zr[u] = i < Kn ? zz[i] : 0.0;
-      er[u] = i < Kn ? d[i] - dO : 1e300;
-    }
-  }
   for (int it = 0; it < 120; ++it) {
     // with q = z_i / (d_i - lambda): z_i^2 / (d_i - lambda) = z_i q and its
     // derivative z_i^2 / (d_i - lambda)^2 = q^2 (one division per term)
     double psi = 0, phi = 0, dpsi = 0, dphi = 0;
-    if (reg) {
-#pragma unroll
-      for (int u = 0; u < kSecReg; ++u) {
-        const double q = zr[u] / (er[u] - t);
-        if (lane + 64 * u <= j) {
-          psi = fma(zr[u], q, psi);
-          dpsi = fma(q, q, dpsi);
-        } else {
-          phi = fma(zr[u], q, phi);
-          dphi = fma(q, q, dphi);
-        }
-      }
-    } else {
-      secular_terms(d, zz, dO, t, lane, j + 1, psi, dpsi);
-      secular_terms(d, zz, dO, t, j + 1 + lane, Kn, phi, dphi);
-    }
+    secular_terms(d, zz, dO, t, lane, j + 1, psi, dpsi);
+    secular_terms(d, zz, dO, t, j + 1 + lane, Kn, phi, dphi);
     psi = wave_sum(psi); phi = wave_sum(phi); dpsi = wave_sum(dpsi); dphi = wave_sum(dphi);
-    const double f = ir + psi + phi;
-    if (f < 0.0) lo = fmax(lo, t); else hi = fmin(hi, t);
-    const double err = 8.0 * kEps * (ir + fabs(psi) + fabs(phi) + fabs(t) * (dpsi + dphi));
-    if (fabs(f) <= err || (hi - lo) <= 4.0 * kEps * fmax(fabs(lo), fabs(hi))) break;
-    const double dlj = Dj - t;
-    const double b1 = dpsi * dlj * dlj;
-    const double a1 = psi - b1 / dlj;
-    double tn;
-    if (!last) {
-      const double dlj1 = Dj1 - t;
-      const double b2 = dphi * dlj1 * dlj1;
-      const double a2 = phi - b2 / dlj1;
-      const double c = ir + a1 + a2;
-      const double dd = Dj1 - Dj;
-      // root of c + b1/(Dj - x) + b2/(Dj1 - x), solved for its distance to the
-      // origin pole (Dj or Dj1 is 0) so that a root next to that pole keeps
-      // its relative accuracy: u = Dj - x in (-dd, 0) or w = Dj1 - x in (0, dd)
-      if (o == j) tn = Dj - quad_root_in(c, c * dd + b1 + b2, b1 * dd, -dd, 0.0);
-      else tn = Dj1 - quad_root_in(c, b1 + b2 - c * dd, -b2 * dd, 0.0, dd);
-    } else {
-      const double c = ir + a1;
-      tn = c != 0.0 ? Dj + b1 / c : 0.5 * (lo + hi);
-    }
-    // The model matches f and f' at t and increases between its poles, so a
-    // root of it on the side of t that the sign of f(t) points away from (or
-    // t itself) comes either from f(t) being at the rounding level of the
-    // sum (bound K eps sum|terms|: converged) or from a model without a root
-    // in the bracket (bisect).
-    if (f < 0.0 ? tn <= t : tn >= t) {
-      if (fabs(f) <= kEps * Kn * (ir + fabs(psi) + fabs(phi))) break;
-      tn = 0.5 * (lo + hi);
-    } else if (!(tn > lo && tn < hi)) {
-      tn = 0.5 * (lo + hi);
-    }
-    t = tn;
+    if (secular_step(ir, psi, phi, dpsi, dphi, last, o == j, Dj, Dj1, Kn, lo, hi, t)) break;
   }
   if (lane == 0) {
     orig[g.a + j] = o;
     tau[g.a + j] = t;
     lamn[g.a + j] = dO + t;
+  }
+}
+
+// Large merges whose poles fit in LDS (Kn <= kSecLdsMax): a 1024-thread
+// workgroup stages d and z once and its 16 waves (one root each) read them
+// from LDS at every iteration instead of from L2.
+constexpr int kSecLdsMax = 9216;  // 2 * 9216 doubles = 144 KB of LDS
+
+__global__ __launch_bounds__(1024) void k_secular_lds(const DcMerge* md, const DcScal* ms, const double* Dn,
+                                                      const double* zn, int* orig, double* tau, double* lamn) {
+  extern __shared__ double sm[];
+  const DcMerge g = md[blockIdx.y];
+  const DcScal& s = ms[blockIdx.y];
+  const int Kn = s.Kn;
+  if (blockIdx.x * 16 >= Kn) return;  // the whole workgroup
+  double* sd = sm;
+  double* sz = sm + Kn;
+  for (int i = threadIdx.x; i < Kn; i += 1024) {
+    sd[i] = Dn[g.a + i];
+    sz[i] = zn[g.a + i];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 16 + (threadIdx.x >> 6);
+  if (j >= Kn) return;
+  const double r = s.r;
+  const double ir = 1.0 / r;
+  const bool last = (j == Kn - 1);
+  int o;
+  double lo, hi;
+  if (!last) {
+    const double delta = sd[j + 1] - sd[j];
+    const double mid = sd[j] + 0.5 * delta;
+    double f = 0.0;
+    for (int i = lane; i < Kn; i += 64) f += sz[i] * sz[i] / (sd[i] - mid);
+    f = wave_sum(f) + ir;
+    if (f >= 0.0) { o = j; lo = 0.0; hi = 0.5 * delta; }
+    else { o = j + 1; lo = -0.5 * delta; hi = 0.0; }
+  } else {
+    double z2 = 0.0;
+    for (int i = lane; i < Kn; i += 64) z2 += sz[i] * sz[i];
+    z2 = wave_sum(z2);
+    o = j; lo = 0.0; hi = r * z2;
+  }
+  const double dO = sd[o];
+  double t = 0.5 * (lo + hi);
+  const double Dj = sd[j] - dO;
+  const double Dj1 = last ? 0.0 : sd[j + 1] - dO;
+  for (int it = 0; it < 120; ++it) {
+    double psi = 0, phi = 0, dpsi = 0, dphi = 0;
+    for (int i = lane; i <= j; i += 64) {
+      const double q = sz[i] / ((sd[i] - dO) - t);
+      psi = fma(sz[i], q, psi);
+      dpsi = fma(q, q, dpsi);
+    }
+    for (int i = j + 1 + lane; i < Kn; i += 64) {
+      const double q = sz[i] / ((sd[i] - dO) - t);
+      phi = fma(sz[i], q, phi);
+      dphi = fma(q, q, dphi);
+    }
+    psi = wave_sum(psi); phi = wave_sum(phi); dpsi = wave_sum(dpsi); dphi = wave_sum(dphi);
+    if (secular_step(ir, psi, phi, dpsi, dphi, last, o == j, Dj, Dj1, Kn, lo, hi, t)) break;
+  }
+  if (lane == 0) {
+    orig[g.a + j] = o;
+    tau[g.a + j] = t;
+    lamn[g.a + j] = dO + t;
+  }
+}
+
+// Merges with Kn <= G * NR: a group of G lanes per root (64 / G roots per
+// wave), each lane holding NR of the root's poles (i = lane-in-group + G u) in
+// registers for every iteration; the sums are group butterflies.  Every lane
+// takes part in every sum (a group whose root has converged keeps its state),
+// and the wave stops when all of its groups have.
+template <int G, int NR>
+__global__ __launch_bounds__(256) void k_secular_reg(const DcMerge* md, const DcScal* ms, const double* Dn,
+                                                     const double* zn, int* orig, double* tau, double* lamn) {
+  constexpr int RPW = 64 / G;
+  const DcMerge g = md[blockIdx.y];
+  const DcScal& s = ms[blockIdx.y];
+  const int Kn = s.Kn;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wave * RPW >= Kn) return;
+  const int lane = threadIdx.x & 63;
+  const int gl = lane & (G - 1);
+  const int jr = wave * RPW + lane / G;
+  const bool valid = jr < Kn;
+  const int j = valid ? jr : Kn - 1;  // idle groups repeat the last root and store nothing
+  const double* d = Dn + g.a;
+  const double* zz = zn + g.a;
+  const double r = s.r;
+  const double ir = 1.0 / r;
+  const bool last = (j == Kn - 1);
+  double zr[NR], dr[NR];
+#pragma unroll
+  for (int u = 0; u < NR; ++u) {
+    const int i = gl + G * u;
+    zr[u] = i < Kn ? zz[i] : 0.0;
+    dr[u] = i < Kn ? d[i] : 0.0;
+  }
+  // f at the midpoint of (d_j, d_{j+1}) and ||z||^2 (the last root's bracket),
+  // both formed by every group
+  const double dj = d[j];
+  const double delta = last ? 0.0 : d[j + 1] - dj;
+  const double mid = dj + 0.5 * delta;
+  double fm = 0.0, z2 = 0.0;
+#pragma unroll
+  for (int u = 0; u < NR; ++u) {
+    const bool in = gl + G * u < Kn;
+    fm += in ? zr[u] * zr[u] / (dr[u] - mid) : 0.0;
+    z2 += zr[u] * zr[u];
+  }
+  fm = group_sum<G>(fm) + ir;
+  z2 = group_sum<G>(z2);
+  int o;
+  double lo, hi;
+  if (last) { o = j; lo = 0.0; hi = r * z2; }
+  else if (fm >= 0.0) { o = j; lo = 0.0; hi = 0.5 * delta; }
+  else { o = j + 1; lo = -0.5 * delta; hi = 0.0; }
+  const double dO = d[o];
+  double t = 0.5 * (lo + hi);
+  const double Dj = dj - dO;
+  const double Dj1 = last ? 0.0 : d[j + 1] - dO;
+  double er[NR];
+#pragma unroll
+  for (int u = 0; u < NR; ++u) er[u] = gl + G * u < Kn ? dr[u] - dO : 1e300;
+  bool done = !valid;
+  for (int it = 0; it < 120; ++it) {
+    double psi = 0, phi = 0, dpsi = 0, dphi = 0;
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      const double q = zr[u] / (er[u] - t);
+      if (gl + G * u <= j) {
+        psi = fma(zr[u], q, psi);
+        dpsi = fma(q, q, dpsi);
+      } else {
+        phi = fma(zr[u], q, phi);
+        dphi = fma(q, q, dphi);
+      }
+    }
+    psi = group_sum<G>(psi); phi = group_sum<G>(phi); dpsi = group_sum<G>(dpsi); dphi = group_sum<G>(dphi);
+    if (!done) done = secular_step(ir, psi, phi, dpsi, dphi, last, o == j, Dj, Dj1, Kn, lo, hi, t);
+    if (__ballot(!done) == 0) break;
+  }
+  if (valid && gl == 0) {
+    orig[g.a + j] = o;
+    tau[g.a + j] = t;
+    lamn[g.a + j] = dO + t;
+  }
+}
+
+void launch_secular(int Kmax, int nm, const DcMerge* md, const DcScal* ms, const double* Dn, const double* zn,
+                    int* orig, double* tau, double* lamn, hipStream_t st) {
+  // roots per 256-thread block: 4 * 64 / G
+  auto grid = [&](int G) { return dim3((Kmax + 4 * (64 / G) - 1) / (4 * (64 / G)), nm); };
+  if (Kmax <= 64)
+    hipLaunchKernelGGL((k_secular_reg<8, 8>), grid(8), dim3(256), 0, st, md, ms, Dn, zn, orig, tau, lamn);
+  else if (Kmax <= 128)
+    hipLaunchKernelGGL((k_secular_reg<16, 8>), grid(16), dim3(256), 0, st, md, ms, Dn, zn, orig, tau, lamn);
+  else if (Kmax <= 256)
+    hipLaunchKernelGGL((k_secular_reg<32, 8>), grid(32), dim3(256), 0, st, md, ms, Dn, zn, orig, tau, lamn);
+  else if (Kmax <= 512)
+    hipLaunchKernelGGL((k_secular_reg<64, 8>), grid(64), dim3(256), 0, st, md, ms, Dn, zn, orig, tau, lamn);
+  else if (Kmax <= 1024)
+    hipLaunchKernelGGL((k_secular_reg<64, 16>), grid(64), dim3(256), 0, st, md, ms, Dn, zn, orig, tau, lamn);
+  else if (Kmax <= kSecLdsMax) {
+    static bool attr = false;  // more than the default 64 KB of dynamic LDS
+    if (!attr) {
+      LYAP_HIP(hipFuncSetAttribute((const void*)k_secular_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   2 * kSecLdsMax * (int)sizeof(double)));
+      attr = true;
+    }
+    hipLaunchKernelGGL(k_secular_lds, dim3((Kmax + 15) / 16, nm), dim3(1024), 2 * (size_t)Kmax * sizeof(double), st,
+                       md, ms, Dn, zn, orig, tau, lamn);
+  } else {
+    hipLaunchKernelGGL(k_secular, grid(64), dim3(256), 0, st, md, ms, Dn, zn, orig, tau, lamn);
   }
 }
 
@@ -727,29 +895,41 @@ void DcWork::run(const double* band, int ldb, int k, double* lam, double* F, dou
   hipLaunchKernelGGL(k_leaf_store, dim3(1, nl), dim3(64), 0, st, w.leafQ.as<double>(), w.leafL.as<double>(), b, ell,
                      k, lam, F, L);
   LYAP_LAUNCHED("dc leaves");
-  // nodes: (offset, size)
+  // the whole tree: merges of every level (offset, size), planned on the host
   std::vector<std::pair<int, int>> nodes;
   for (int i = 0; i < nl; ++i) nodes.emplace_back(i * b, nlist[i]);
+  std::vector<DcMerge> all;
+  std::vector<int> lvl_off, lvl_kmax;
   while (nodes.size() > 1) {
-    std::vector<DcMerge> hm;
     std::vector<std::pair<int, int>> next;
     int Kmax = 0;
+    lvl_off.push_back((int)all.size());
     for (size_t i = 0; i + 1 < nodes.size(); i += 2) {
       DcMerge g{nodes[i].first, nodes[i].second, nodes[i].second + nodes[i + 1].second, 0};
-      hm.push_back(g);
+      all.push_back(g);
       next.emplace_back(g.a, g.K);
       Kmax = std::max(Kmax, g.K);
     }
     if (nodes.size() % 2) next.push_back(nodes.back());
-    const int nm = (int)hm.size();
-    if (nm > w.md_cap) {
-      w.md.alloc((size_t)nm * sizeof(DcMerge));
-      w.ms.alloc((size_t)nm * sizeof(DcScal));
-      w.md_cap = nm;
-    }
-    LYAP_HIP(hipMemcpyAsync(w.md.p, hm.data(), nm * sizeof(DcMerge), hipMemcpyHostToDevice, st));
-    const DcMerge* md = w.md.as<DcMerge>();
-    DcScal* ms = w.ms.as<DcScal>();
+    lvl_kmax.push_back(Kmax);
+    nodes.swap(next);
+  }
+  lvl_off.push_back((int)all.size());
+  const int ntot = (int)all.size();
+  if (ntot == 0) return;
+  if (ntot > w.md_cap) {
+    w.md.alloc((size_t)ntot * sizeof(DcMerge));
+    w.ms.alloc((size_t)ntot * sizeof(DcScal));
+    w.md_cap = ntot;
+  }
+  LYAP_HIP(hipMemcpyAsync(w.md.p, all.data(), ntot * sizeof(DcMerge), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_coupling_svd, dim3((ntot + 63) / 64), dim3(64), 0, st, w.md.as<DcMerge>(), w.ms.as<DcScal>(),
+                     ntot, band, ldb, ell);
+  for (size_t lv = 0; lv + 1 < lvl_off.size(); ++lv) {
+    const int nm = lvl_off[lv + 1] - lvl_off[lv];
+    const int Kmax = lvl_kmax[lv];
+    const DcMerge* md = w.md.as<DcMerge>() + lvl_off[lv];
+    DcScal* ms = w.ms.as<DcScal>() + lvl_off[lv];
     const int gx = std::min((Kmax + 255) / 256, 64);
     const int gw = (Kmax + 3) / 4;  // one wave per element, 4 waves per block
     // k_vec: 64 roots per wave, candidate slices so that a level has ~2048 waves
@@ -769,8 +949,8 @@ void DcWork::run(const double* band, int ldb, int k, double* lam, double* F, dou
                          w.z.as<double>(), w.Dn.as<double>(), w.zn.as<double>(), w.nd.as<int>(), w.defl.as<int>(),
                          w.defv.as<double>(), w.sml.as<int>(), w.smv.as<double>(), w.rdl.as<int>(),
                          w.rdv.as<double>());
-      hipLaunchKernelGGL(k_secular, dim3(gw, nm), dim3(256), 0, st, md, ms, w.Dn.as<double>(), w.zn.as<double>(),
-                         w.orig.as<int>(), w.tau.as<double>(), w.lamn.as<double>());
+      launch_secular(Kmax, nm, md, ms, w.Dn.as<double>(), w.zn.as<double>(), w.orig.as<int>(), w.tau.as<double>(),
+                     w.lamn.as<double>(), st);
       hipLaunchKernelGGL(k_zhat, dim3(gw, nm), dim3(256), 0, st, md, ms, nr, vec_pad(nr), k, Rcur, w.nd.as<int>(),
                          w.Dn.as<double>(), w.zn.as<double>(), w.orig.as<int>(), w.tau.as<double>(),
                          w.zh.as<double>(), w.Rt.as<double>());
@@ -785,7 +965,6 @@ void DcWork::run(const double* band, int ldb, int k, double* lam, double* F, dou
     }
     hipLaunchKernelGGL(k_merge_finish, dim3(gx, nm), dim3(256), 0, st, md, ell, k, Dcur, Rcur, lam, F, L);
     LYAP_LAUNCHED("dc merge level");
-    nodes.swap(next);
   }
 }
 

@@ -96,7 +96,8 @@ def _lanczos_T(N, s, m, seed=1):
 
 
 @pytest.mark.parametrize("N,s,m", [(32, 1, 12), (32, 4, 4), (32, 1, 40), (32, 2, 30), (32, 4, 25), (32, 4, 60),
-                                   (60, 1, 300), (60, 2, 200), (100, 4, 175), (100, 3, 111)])
+                                   (60, 1, 300), (60, 2, 200), (100, 4, 175), (100, 3, 111), (100, 2, 600),
+                                   (60, 4, 400)])
 def test_ctri_parity(lib, N, s, m):
     """Eigenvalues (Jacobi for k <= 16, divide and conquer above) and the
     Proposition 1 residual against LAPACK-based Algorithm 3 in the oracle."""
