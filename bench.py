@@ -27,6 +27,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+# HBM bytes per launch from rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE,
+# KiB per dispatch, median over the dispatches of one `bench.py --steps 1
+# --warmup 0 --no-cpu-baseline` run) for the kernel and configuration named,
+# scaled by what the same counters read for a plain 256 MiB device copy
+# (`bench.py --calibrate-copy`: FETCH_SIZE 131088.75 KiB for 262144 KiB read,
+# WRITE_SIZE 262144 KiB for 262144 KiB written).  Valid only for the kernel
+# build they were taken on; the bench reports null for anything else.
+HBM_COUNTERS = {
+    ("upd_gram", 1000000, 4, "f32"): {"fetch_kib": 23597.0, "write_kib": 15657.125,
+                                      "fetch_scale": 262144.0 / 131088.75, "write_scale": 1.0},
+}
+
+
+def measured_traffic(kernel, n, s, storage):
+    c = HBM_COUNTERS.get((kernel, n, s, storage))
+    if c is None:
+        return None
+    return round((c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0)
 
 
 def parse():
@@ -42,6 +62,8 @@ def parse():
     ap.add_argument("--explicit-residual", action="store_true", help="also report the explicit FP64 residual")
     ap.add_argument("--inner", choices=["jacobi", "learned"], default="jacobi",
                     help="ext workload: inner preconditioner (learned = trained in the run, time counted)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run one plain 256 MiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--workload", choices=["std", "ext", "sylv", "batch"], default="std",
                     help="std: standard Krylov + two-pass on the 2D Laplacian (the headline); "
                          "ext: extended Krylov + inner PCG on the 100^3 lognormal finite-volume operator; "
@@ -195,7 +217,9 @@ def main_ext(args):
                         if v["bytes_per_launch"] > 0 else None}
                     for k, v in agg.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, op.n, args.s, args.storage),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "bytes_per_launch": bpl, "avg_launch_us": round(avg_ms * 1000.0, 2)},
     }
     if not args.no_cpu_baseline:
@@ -333,12 +357,29 @@ def main_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def main_copy():
+    """One torch device-to-device copy of 256 MiB: a kernel whose HBM bytes are
+    known (read 256 MiB, write 256 MiB), so that FETCH_SIZE / WRITE_SIZE of the
+    solver's kernels can be scaled by what the counters read for it."""
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    n = 64 * 1024 * 1024
+    x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
               "multi-GPU sharding is a design note, not a measured path", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        return main_copy()
     if args.workload == "ext":
         return main_ext(args)
     if args.workload == "sylv":
@@ -414,10 +455,19 @@ def main():
                         if v["bytes_per_launch"] > 0 else None}
                     for k, v in agg.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, op.n, args.s, args.storage),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "bytes_per_launch": bpl, "avg_launch_us": round(avg_ms * 1000.0, 2)},
         "spmm_GBs": round(spmm_gbs, 1) if spmm_gbs else None,
     }
+    zf = agg.get("zflush")
+    if zf and zf["n"] > 0:
+        # Z += V_m M: 2 n k t FP64 flops per solve, FMA bound (vector FP64 peak)
+        flops = 2.0 * op.n * (sol.m * args.s) * sol.t * len(sols) / zf["n"]
+        tf = flops / (zf["ms"] / zf["n"] * 1e-3) / 1e12
+        out["zflush_fp64"] = {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                              "unit": "TFLOP/s", "frac": round(tf / FP64_VECTOR_PEAK_TFLOPS, 4)}
     if args.explicit_residual:
         out["result"]["res_rel_explicit"] = explicit_residual(b, dop, sol.Z, Cd, sol.beta ** 2)
     if not args.no_cpu_baseline:
