@@ -107,28 +107,33 @@ __device__ __forceinline__ void take_gram(const double* pin, int nparts, double*
   __syncthreads();  // red is reused by the epilogue
 }
 
+// Rows of workgroup wg_id in the kernels that apply the operator: one contiguous
+// block of ceil(n / wg_cnt) rows, the blocks dealt so that the wg_cnt / 8
+// workgroups the hardware places on one XCD (consecutive ids go round-robin
+// over the 8 XCDs) hold adjacent blocks.  The rows r +- N a stencil reads then
+// mostly come from the same XCD's L2 instead of being fetched again by another
+// XCD (with rows dealt in a grid stride, each block was fetched about three
+// times).
+__device__ __forceinline__ void op_rows(int wg_id, int wg_cnt, int n, int& lo, int& hi) {
+  const int blk = (wg_cnt % 8 == 0) ? (wg_id % 8) * (wg_cnt / 8) + wg_id / 8 : wg_id;
+  const int64_t R = ((int64_t)n + wg_cnt - 1) / wg_cnt;
+  lo = (int)min((int64_t)n, (int64_t)blk * R);
+  hi = (int)min((int64_t)n, (int64_t)lo + R);
+}
+
 // K1: W = A V_j ; partial alpha1 = V_{j-1}^T W
 template <typename T, int S>
 __device__ __forceinline__ void spmm_gram_body(const StepArgs<T>& a, int wg_id, int wg_cnt, double* red) {
   double acc[S * S];
   zero<S>(acc);
-  const int str = wg_cnt * stream_threads(S);
-  LYAP_BATCH(r0, a.n) {
-    T w[kRPT][S], x[kRPT][S];
-    LYAP_FOR_U {
-      const int r = r0 + u * str;
-      if (r < a.n) {
-        op_row<T, S>(a.op, a.Vcur, r, w[u]);
-        load_row<T, S>(a.Vprev + (size_t)r * S, x[u]);
-      }
-    }
-    LYAP_FOR_U {
-      const int r = r0 + u * str;
-      if (r < a.n) {
-        store_row<T, S>(a.W + (size_t)r * S, w[u]);
-        outer_acc<T, T, S>(acc, x[u], w[u]);
-      }
-    }
+  int lo, hi;
+  op_rows(wg_id, wg_cnt, a.n, lo, hi);
+  for (int r = lo + threadIdx.x; r < hi; r += stream_threads(S)) {
+    T w[S], x[S];
+    op_row<T, S>(a.op, a.Vcur, r, w);
+    load_row<T, S>(a.Vprev + (size_t)r * S, x);
+    store_row<T, S>(a.W + (size_t)r * S, w);
+    outer_acc<T, T, S>(acc, x, w);
   }
   write_partial_at<S * S, stream_threads(S)>(acc, red, a.pout, wg_id);
 }
@@ -281,29 +286,19 @@ __device__ __forceinline__ void replay_body(const OpDev<T>& op, int n, const T* 
   load_coef<S>(log + L_A3 * S * S, a3);
   load_coef<S>(log + L_A4 * S * S, a4);
   load_coef<S>(log + L_RI * S * S, ri);
-  const int str = wg_cnt * stream_threads(S);
-  LYAP_BATCH(r0, n) {
-    T w[kRPT][S], x[kRPT][S], y[kRPT][S];
-    LYAP_FOR_U {
-      const int r = r0 + u * str;
-      if (r < n) {
-        op_row<T, S>(op, Vcur, r, w[u]);
-        load_row<T, S>(Vprev + (size_t)r * S, x[u]);
-        load_row<T, S>(Vcur + (size_t)r * S, y[u]);
-      }
-    }
-    LYAP_FOR_U {
-      const int r = r0 + u * str;
-      if (r < n) {
-        T v[S];
-        upd_row<T, S>(w[u], x[u], a1);
-        upd_row<T, S>(w[u], y[u], a2);
-        upd_row<T, S>(w[u], x[u], a3);
-        upd_row<T, S>(w[u], y[u], a4);
-        apply_upper<T, S>(w[u], ri, v);
-        store_row<T, S>(Vnext + (size_t)r * S, v);
-      }
-    }
+  int lo, hi;
+  op_rows(wg_id, wg_cnt, n, lo, hi);
+  for (int r = lo + threadIdx.x; r < hi; r += stream_threads(S)) {
+    T w[S], x[S], y[S], v[S];
+    op_row<T, S>(op, Vcur, r, w);
+    load_row<T, S>(Vprev + (size_t)r * S, x);
+    load_row<T, S>(Vcur + (size_t)r * S, y);
+    upd_row<T, S>(w, x, a1);
+    upd_row<T, S>(w, y, a2);
+    upd_row<T, S>(w, x, a3);
+    upd_row<T, S>(w, y, a4);
+    apply_upper<T, S>(w, ri, v);
+    store_row<T, S>(Vnext + (size_t)r * S, v);
   }
 }
 
