@@ -107,20 +107,6 @@ __device__ __forceinline__ void take_gram(const double* pin, int nparts, double*
   __syncthreads();  // red is reused by the epilogue
 }
 
-// Rows of workgroup wg_id in the kernels that apply the operator: one contiguous
-// block of ceil(n / wg_cnt) rows, the blocks dealt so that the wg_cnt / 8
-// workgroups the hardware places on one XCD (consecutive ids go round-robin
-// over the 8 XCDs) hold adjacent blocks.  The rows r +- N a stencil reads then
-// mostly come from the same XCD's L2 instead of being fetched again by another
-// XCD (with rows dealt in a grid stride, each block was fetched about three
-// times).
-__device__ __forceinline__ void op_rows(int wg_id, int wg_cnt, int n, int& lo, int& hi) {
-  const int blk = (wg_cnt % 8 == 0) ? (wg_id % 8) * (wg_cnt / 8) + wg_id / 8 : wg_id;
-  const int64_t R = ((int64_t)n + wg_cnt - 1) / wg_cnt;
-  lo = (int)min((int64_t)n, (int64_t)blk * R);
-  hi = (int)min((int64_t)n, (int64_t)lo + R);
-}
-
 // K1: W = A V_j ; partial alpha1 = V_{j-1}^T W
 template <typename T, int S>
 __device__ __forceinline__ void spmm_gram_body(const StepArgs<T>& a, int wg_id, int wg_cnt, double* red) {

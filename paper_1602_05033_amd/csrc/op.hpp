@@ -11,6 +11,31 @@
 
 namespace lyap {
 
+// Rows of workgroup wg_id in the kernels that apply the operator: one contiguous
+// block of ceil(n / wg_cnt) rows, the blocks dealt so that the wg_cnt / 8
+// workgroups the hardware places on one XCD (consecutive ids go round-robin
+// over the 8 XCDs) hold adjacent blocks.  The rows r +- N a stencil reads then
+// mostly come from the same XCD's L2 instead of being fetched again by another
+// XCD (with rows dealt in a grid stride, each block was fetched about three
+// times).
+__device__ __forceinline__ void op_rows(int wg_id, int wg_cnt, int n, int& lo, int& hi) {
+  const int blk = (wg_cnt % 8 == 0) ? (wg_id % 8) * (wg_cnt / 8) + wg_id / 8 : wg_id;
+  const int64_t R = ((int64_t)n + wg_cnt - 1) / wg_cnt;
+  lo = (int)min((int64_t)n, (int64_t)blk * R);
+  hi = (int)min((int64_t)n, (int64_t)lo + R);
+}
+
+// One-dimensional launches of G workgroups of consecutive points: launched as
+// 8 * ceil(G / 8) workgroups and renumbered so that the workgroups on one XCD
+// take consecutive logical blocks (same reason as op_rows).  -1 for padding.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+  const int per = (G + 7) / 8;
+  const int lb = (b % 8) * per + b / 8;
+  return lb < G ? lb : -1;
+}
+inline int xcd_grid(int G) { return (G + 7) / 8 * 8; }
+
+
 // Device-side description of the operator; coefficient arrays are stored in the
 // basis storage type T (converted once per solve).
 template <typename T>

@@ -120,7 +120,9 @@ __global__ __launch_bounds__(NT) void k_cg_dir(OpDev<double> op, const double* _
   double acc[S];
 #pragma unroll
   for (int c = 0; c < S; ++c) acc[c] = 0.0;
-  CG_ROWS(i, n) {
+  int lo, hi;
+  op_rows(blockIdx.x, gridDim.x, n, lo, hi);
+  for (int i = lo + threadIdx.x; i < hi; i += NT) {
     double p[S], w[S];
     dir_row<S>(r, dinv, po, beta, mask, i, p);
     store_row<double, S>(pnew + (size_t)i * S, p);
@@ -245,7 +247,9 @@ __global__ __launch_bounds__(NT) void k_fcg_dir(OpDev<double> op, const double* 
     return mask * (po ? fma(beta, po[i], zi) : zi);
   };
   double acc[2] = {0.0, 0.0};
-  for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+  int lo, hi;
+  op_rows(blockIdx.x, gridDim.x, n, lo, hi);
+  for (int i = lo + threadIdx.x; i < hi; i += NT) {
     const double pi = prow(i);
     pnew[i] = pi;
     double w[1];

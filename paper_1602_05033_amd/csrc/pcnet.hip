@@ -72,11 +72,13 @@ __global__ void k_pc_in_g(const float* __restrict__ g, const float* __restrict__
 template <int CI, int CO>
 __global__ __launch_bounds__(kPcThreads) void k_pc_conv(const float* __restrict__ in, const float* __restrict__ W,
                                                         float* __restrict__ out, int nx, int ny, int nz) {
+  const int n = nx * ny * nz;
+  const int lb = xcd_block(blockIdx.x, (n + kPcThreads - 1) / kPcThreads);
+  if (lb < 0) return;
   __shared__ float sW[CO * CI * 27];
   for (int e = threadIdx.x; e < CO * CI * 27; e += kPcThreads) sW[e] = W[e];
   __syncthreads();
-  const int n = nx * ny * nz;
-  const int p = blockIdx.x * kPcThreads + threadIdx.x;
+  const int p = lb * kPcThreads + threadIdx.x;
   if (p >= n) return;
   const int nxy = nx * ny;
   const int z = p / nxy, y = (p / nx) % ny, x = p % nx;
@@ -105,11 +107,13 @@ __global__ __launch_bounds__(kPcThreads) void k_pc_conv(const float* __restrict_
 template <int CO, int CI>
 __global__ __launch_bounds__(kPcThreads) void k_pc_convT(const float* __restrict__ in, const float* __restrict__ W,
                                                          float* __restrict__ out, int nx, int ny, int nz) {
+  const int n = nx * ny * nz;
+  const int lb = xcd_block(blockIdx.x, (n + kPcThreads - 1) / kPcThreads);
+  if (lb < 0) return;
   __shared__ float sW[CO * CI * 27];
   for (int e = threadIdx.x; e < CO * CI * 27; e += kPcThreads) sW[e] = W[e];
   __syncthreads();
-  const int n = nx * ny * nz;
-  const int p = blockIdx.x * kPcThreads + threadIdx.x;
+  const int p = lb * kPcThreads + threadIdx.x;
   if (p >= n) return;
   const int nxy = nx * ny;
   const int z = p / nxy, y = (p / nx) % ny, x = p % nx;
@@ -336,15 +340,15 @@ void PcNetGpu::get_weights(float* host) const {
 
 template <int CI, int CO>
 void PcNetGpu::conv(const float* in, const float* W, float* out) {
-  hipLaunchKernelGGL((k_pc_conv<CI, CO>), dim3((n_ + kPcThreads - 1) / kPcThreads), dim3(kPcThreads), 0, st_, in, W,
-                     out, nx_, ny_, nz_);
+  hipLaunchKernelGGL((k_pc_conv<CI, CO>), dim3(xcd_grid((n_ + kPcThreads - 1) / kPcThreads)), dim3(kPcThreads), 0,
+                     st_, in, W, out, nx_, ny_, nz_);
   LYAP_LAUNCHED("k_pc_conv");
 }
 
 template <int CO, int CI>
 void PcNetGpu::convT(const float* in, const float* W, float* out) {
-  hipLaunchKernelGGL((k_pc_convT<CO, CI>), dim3((n_ + kPcThreads - 1) / kPcThreads), dim3(kPcThreads), 0, st_, in,
-                     W, out, nx_, ny_, nz_);
+  hipLaunchKernelGGL((k_pc_convT<CO, CI>), dim3(xcd_grid((n_ + kPcThreads - 1) / kPcThreads)), dim3(kPcThreads), 0,
+                     st_, in, W, out, nx_, ny_, nz_);
   LYAP_LAUNCHED("k_pc_convT");
 }
 
