@@ -525,7 +525,9 @@ __global__ __launch_bounds__(64 * kZW) void k_zflush(BlockList bl, int nb, int n
 
 template <typename T, int S>
 __global__ __launch_bounds__(kBlock) void k_apply(OpDev<T> op, const T* V, T* W) {
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < op.n; r += gridDim.x * kBlock) {
+  int lo, hi;
+  op_rows(blockIdx.x, gridDim.x, op.n, lo, hi);
+  for (int r = lo + threadIdx.x; r < hi; r += kBlock) {
     T w[S];
     op_row<T, S>(op, V, r, w);
     store_row<T, S>(W + (size_t)r * S, w);

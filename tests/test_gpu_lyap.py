@@ -283,3 +283,48 @@ def test_max_iter_gives_not_converged_with_partial_Z(lib):
     sol = b.lyap_solve(b.device_op(op), _dev_C(C), max_iter=20, check_every=5)
     assert sol.status == b.NOT_CONVERGED and sol.m == 20 and sol.res > 1e-8
     assert sol.Z is not None and sol.Z.shape[0] == op.n
+
+
+# ------------------------------------------------------------------ full size (the bench configuration)
+def test_c2_full_size_properties(lib):
+    """The 1000 x 1000 Laplacian, s = 4, FP32 storage, adaptive checks, tol 1e-8
+    (the configuration bench.py times).  The oracle cannot run this size, so the
+    result is held to properties that hold at any size: the check history falls
+    to tol, the residual of Proposition 1 agrees with the explicit residual
+    ||A Z Z^T + Z Z^T A + C C^T||_F / ||C||_F^2 (factored QR in torch, FP64) up
+    to the FP32-storage floor, and sampled entries of the residual matrix,
+    formed on the CPU in FP64 from rows of A, are small against C C^T."""
+    b = _b()
+    op = laplace2d(1000)
+    C = gaussian_C(op.n, 4, 2)
+    dop = b.device_op(op)
+    Cd = _dev_C(C)
+    sol = b.lyap_solve(dop, Cd, tol=1e-8, storage=b.STORE_F32, check_every=0, two_pass=True)
+    assert sol.status == b.OK
+    assert sol.res <= 1e-8 and sol.hist_res[-1] == sol.res
+    assert all(np.diff(sol.hist_m) > 0)
+    assert 0 < sol.t <= 4 * sol.m
+    Z = sol.Z
+    n, t = Z.shape
+    beta2 = float(np.linalg.norm(C) ** 2)
+    AZ = torch.empty_like(Z)
+    for c0 in range(0, t, 8):
+        AZ[:, c0:c0 + 8] = b.op_apply(dop, Z[:, c0:c0 + 8].contiguous(), b.STORE_F64)
+    P = torch.cat([AZ, Z, Cd], dim=1)
+    R = torch.linalg.qr(P, mode="r")[1]
+    Phi = torch.zeros(2 * t + 4, 2 * t + 4, dtype=torch.float64, device=Z.device)
+    Phi[:t, t:2 * t] = torch.eye(t, dtype=torch.float64, device=Z.device)
+    Phi[t:2 * t, :t] = torch.eye(t, dtype=torch.float64, device=Z.device)
+    Phi[2 * t:, 2 * t:] = torch.eye(4, dtype=torch.float64, device=Z.device)
+    expl = float(torch.linalg.norm(R @ Phi @ R.T)) / beta2
+    # FP32 storage of the basis floors the explicit residual at a few 1e-8
+    assert expl <= 1.2e-7, expl
+    # sampled entries of the residual matrix from the definition (CPU, FP64)
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.concatenate([np.arange(0, 50), rng.integers(0, n, 400), np.arange(n - 50, n)]))
+    Zh = Z.cpu().numpy()
+    AZr = op.to_scipy()[rows] @ Zh
+    Zr = Zh[rows]
+    Rs = AZr @ Zr.T + Zr @ AZr.T + C[rows] @ C[rows].T
+    scale = np.max(np.abs(C[rows] @ C[rows].T))
+    assert np.max(np.abs(Rs)) <= 1e-5 * scale, np.max(np.abs(Rs)) / scale
