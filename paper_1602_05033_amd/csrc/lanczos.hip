@@ -530,7 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(OpDev<T> op, const T* V, T* W)
   for (int r = lo + threadIdx.x; r < hi; r += kBlock) {
     T w[S];
     op_row<T, S>(op, V, r, w);
-    store_row<T, S>(W + (size_t)r * S, w);
+    store_row_nt<T, S>(W + (size_t)r * S, w);
   }
 }
 

@@ -96,7 +96,7 @@ template <typename T>
 static double apply_impl(const lyap_op* A, const void* V, void* W, int s, int reps, hipStream_t st) {
   OpHolder<T> h;
   make_op<T>(A, h, st);
-  const int grid = xcd_grid(grid_for(A->n, 1, 4096));
+  const int grid = xcd_grid(grid_for(A->n, 2, 4096));  // two rows per thread
   if (reps <= 0) {
     launch_apply<T>(h.dev, s, (const T*)V, (T*)W, grid, st);
     LYAP_HIP(hipStreamSynchronize(st));

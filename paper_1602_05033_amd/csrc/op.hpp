@@ -104,6 +104,33 @@ __device__ __forceinline__ void store_row(T* __restrict__ p, const T (&v)[S]) {
   }
 }
 
+// store_row with non-temporal stores: for an output the same kernel never reads
+// back (the standalone operator application), so it need not stay in L2.
+template <typename T, int S>
+__device__ __forceinline__ void store_row_nt(T* __restrict__ p, const T (&v)[S]) {
+  constexpr int B = S * (int)sizeof(T);
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  if constexpr (B % 16 == 0) {
+#pragma unroll
+    for (int i = 0; i < B / 16; ++i) {
+      u32x4 x;
+      __builtin_memcpy(&x, reinterpret_cast<const char*>(v) + 16 * i, 16);
+      __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(p) + i);
+    }
+  } else if constexpr (B % 8 == 0) {
+#pragma unroll
+    for (int i = 0; i < B / 8; ++i) {
+      u32x2 x;
+      __builtin_memcpy(&x, reinterpret_cast<const char*>(v) + 8 * i, 8);
+      __builtin_nontemporal_store(x, reinterpret_cast<u32x2*>(p) + i);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < S; ++c) __builtin_nontemporal_store(v[c], p + c);
+  }
+}
+
 template <typename T, int S>
 __device__ __forceinline__ void axpy_row(T a, const T* __restrict__ p, T (&acc)[S]) {
   T v[S];
