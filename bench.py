@@ -64,7 +64,7 @@ def parse():
                     help="ext workload: inner preconditioner (learned = trained in the run, time counted)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run one plain 256 MiB device copy (reference for the HBM byte counters)")
-    ap.add_argument("--workload", choices=["std", "ext", "sylv", "batch"], default="std",
+    ap.add_argument("--workload", choices=["std", "ext", "sylv", "batch", "e1"], default="std",
                     help="std: standard Krylov + two-pass on the 2D Laplacian (the headline); "
                          "ext: extended Krylov + inner PCG on the 100^3 lognormal finite-volume operator; "
                          "sylv: Sylvester, 700^2 Laplacian and 80^3 lognormal FV, s=2; "
@@ -372,6 +372,56 @@ def main_copy():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
 
 
+# Table 1 of the paper (cTri, Matlab on a 2-GHz dual-processor CPU, FP64):
+# time tot in seconds for s = 1, 4, 8 with the residual checked every step
+# (d = 1) and every 10 steps (d = 10).  Context only (other hardware).
+PAPER_E1_TOTAL_S = {(1, 1): 7.25, (4, 1): 36.21, (8, 1): 67.89, (1, 10): 3.70, (4, 10): 7.98, (8, 10): 13.22}
+
+
+def main_e1(args):
+    """The paper's Example 1 (Section 6): (exp(-xy) u_x)_x + (exp(xy) u_y)_y on
+    148 x 148 interior points (n = 21904), C uniform (seeded) with unit norm,
+    tol 1e-6, FP64, two-pass Z; s = 1, 4, 8 with d = 1 and d = 10."""
+    import numpy as np
+    import torch
+    from paper_1602_05033_amd import binding as b
+    from workloads import fd2d_variable, uniform_C
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    b.load()
+    dev = torch.device("cuda:0")
+    op = fd2d_variable(148, lambda x, y: np.exp(-x * y), lambda x, y: np.exp(x * y), "e1")
+    dop = b.device_op(op, device=dev)
+    cases = []
+    for s in (1, 4, 8):
+        Cd = torch.from_numpy(uniform_C(op.n, s, 0)).to(dev)
+        for d in (1, 10):
+            kw = dict(tol=1e-6, storage=b.STORE_F64, check_every=d, two_pass=True)
+            for _ in range(args.warmup):
+                b.lyap_solve(dop, Cd, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                sol = b.lyap_solve(dop, Cd, **kw)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / args.steps
+            assert sol.status == b.OK, sol.status
+            cases.append({"s": s, "d": d, "m": sol.m, "t": sol.t, "n_checks": sol.n_checks, "time_s": round(sec, 4),
+                          "phases_ms": {k: round(v, 2) for k, v in sol.times_ms.items()},
+                          "paper_cpu_total_s": PAPER_E1_TOTAL_S[(s, d)]})
+    head = next(c for c in cases if c["s"] == 4 and c["d"] == 1)
+    out = {
+        "metric": "time to rel. residual 1e-6 on the paper's Example 1 (n=21904, s=4, residual at every step)",
+        "value": head["time_s"], "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(head["time_s"] * 1000.0, 2), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "Example 1: FD (exp(-xy)u_x)_x + (exp(xy)u_y)_y, 148x148 (n=21904), C uniform "
+                               "unit norm, tol 1e-6, s in {1,4,8}, d in {1,10}", "n": op.n},
+        "result": {"cases": cases},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -380,6 +430,8 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         return main_copy()
+    if args.workload == "e1":
+        return main_e1(args)
     if args.workload == "ext":
         return main_ext(args)
     if args.workload == "sylv":
