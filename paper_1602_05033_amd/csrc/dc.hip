@@ -44,9 +44,10 @@ struct DcScal {
 };
 
 // ------------------------------------------------------------------ leaves
-__global__ void k_leaf_extract(const double* band, int ldb, int ell, int k, int b, int nl, double* A) {
+// Leaves cover rows [r0 + i b, min(r0 + (i+1) b, k)).
+__global__ void k_leaf_extract(const double* band, int ldb, int ell, int k, int b, int r0, double* A) {
   const int leaf = blockIdx.y;
-  const int a0 = leaf * b;
+  const int a0 = r0 + leaf * b;
   const int n = min(b, k - a0);
   double* M = A + (size_t)leaf * b * b;
   for (int e = threadIdx.x + blockIdx.x * blockDim.x; e < n * n; e += blockDim.x * gridDim.x) {
@@ -57,17 +58,30 @@ __global__ void k_leaf_extract(const double* band, int ldb, int ell, int k, int 
   }
 }
 
-__global__ void k_leaf_store(const double* Q, const double* lam, int b, int ell, int k, double* D, double* F,
-                             double* L) {
+__global__ void k_leaf_store(const double* Q, const double* lam, int b, int ell, int k, int r0, int ld, double* D,
+                             double* F, double* L) {
   const int leaf = blockIdx.y;
-  const int a0 = leaf * b;
+  const int a0 = r0 + leaf * b;
   const int n = min(b, k - a0);
   const double* Ql = Q + (size_t)leaf * b * b;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     D[a0 + i] = lam[(size_t)leaf * b + i];
     for (int a = 0; a < ell; ++a) {
-      F[(size_t)a * k + a0 + i] = Ql[a * n + i];
-      L[(size_t)a * k + a0 + i] = Ql[(n - ell + a) * n + i];
+      F[(size_t)a * ld + a0 + i] = Ql[a * n + i];
+      L[(size_t)a * ld + a0 + i] = Ql[(n - ell + a) * n + i];
+    }
+  }
+}
+
+// The root's eigenvalues and first / last ell eigenvector rows to the caller
+// (internal stride ld, the caller's stride k).
+__global__ void k_root_out(int k, int ell, int ld, const double* D, const double* F, const double* L, double* lam,
+                           double* Fo, double* Lo) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < k; e += gridDim.x * blockDim.x) {
+    lam[e] = D[e];
+    for (int r = 0; r < ell; ++r) {
+      Fo[(size_t)r * k + e] = F[(size_t)r * ld + e];
+      Lo[(size_t)r * k + e] = L[(size_t)r * ld + e];
     }
   }
 }
@@ -844,6 +858,12 @@ struct DcWork::Impl {
   DevBuf leafA, leafQ, leafL, leafN;
   DevBuf md, ms;
   int md_cap = 0;
+  // node results (eigenvalues, first / last ell eigenvector rows), stride cap;
+  // after a run, rows [0, kc) hold the root of the last band decomposed
+  DevBuf Dres, Fres, Lres;
+  int kc = 0;
+  const double* cband = nullptr;
+  int cldb = 0;
 
   void ensure(int k) {
     if (k <= cap) return;
@@ -863,6 +883,10 @@ struct DcWork::Impl {
     leafQ.alloc((size_t)nl * leaf * leaf * sizeof(double));
     leafL.alloc((size_t)nl * leaf * sizeof(double));
     leafN.alloc((size_t)nl * sizeof(int));
+    Dres.alloc(d);
+    Fres.alloc(d * ell);
+    Lres.alloc(d * ell);
+    kc = 0;  // the stored root is gone
     cap = c;
   }
 };
@@ -884,20 +908,36 @@ void DcWork::run(const double* band, int ldb, int k, double* lam, double* F, dou
   const int b = w.leaf;
   hipStream_t st = w.st;
   w.ensure(k);
-  // leaves
-  const int nl = (k + b - 1) / b;
+  const int ld = w.cap;
+  // T_k extends the band decomposed last (same rows 0..kc-1, which never change
+  // once written): decompose only rows [kc, k) and merge that node with the
+  // stored root of rows [0, kc) -- one merge at the top instead of the whole
+  // tree below it.  Otherwise the whole tree.
+  if (band == w.cband && ldb == w.cldb && k == w.kc) {  // decomposed already
+    hipLaunchKernelGGL(k_root_out, dim3(std::min((k + 255) / 256, 1024)), dim3(256), 0, st, k, ell, ld,
+                       w.Dres.as<double>(), w.Fres.as<double>(), w.Lres.as<double>(), lam, F, L);
+    LYAP_LAUNCHED("dc root");
+    return;
+  }
+  const bool grow = band == w.cband && ldb == w.cldb && w.kc >= ell && k - w.kc >= ell;
+  const int r0 = grow ? w.kc : 0;
+  // leaves of rows [r0, k)
+  const int nl = (k - r0 + b - 1) / b;
   std::vector<int> nlist(nl);
-  for (int i = 0; i < nl; ++i) nlist[i] = std::min(b, k - i * b);
+  for (int i = 0; i < nl; ++i) nlist[i] = std::min(b, k - r0 - i * b);
   LYAP_HIP(hipMemcpyAsync(w.leafN.p, nlist.data(), nl * sizeof(int), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_leaf_extract, dim3(4, nl), dim3(256), 0, st, band, ldb, ell, k, b, nl, w.leafA.as<double>());
+  hipLaunchKernelGGL(k_leaf_extract, dim3(4, nl), dim3(256), 0, st, band, ldb, ell, k, b, r0, w.leafA.as<double>());
   launch_jacobi(w.leafA.as<double>(), (int64_t)b * b, w.leafQ.as<double>(), (int64_t)b * b, w.leafL.as<double>(), b,
                 w.leafN.as<int>(), b, nl, st);
+  double* Dm = w.Dres.as<double>();
+  double* Fm = w.Fres.as<double>();
+  double* Lm = w.Lres.as<double>();
   hipLaunchKernelGGL(k_leaf_store, dim3(1, nl), dim3(64), 0, st, w.leafQ.as<double>(), w.leafL.as<double>(), b, ell,
-                     k, lam, F, L);
+                     k, r0, ld, Dm, Fm, Lm);
   LYAP_LAUNCHED("dc leaves");
-  // the whole tree: merges of every level (offset, size), planned on the host
+  // the tree over [r0, k): merges of every level (offset, size), planned on the host
   std::vector<std::pair<int, int>> nodes;
-  for (int i = 0; i < nl; ++i) nodes.emplace_back(i * b, nlist[i]);
+  for (int i = 0; i < nl; ++i) nodes.emplace_back(r0 + i * b, nlist[i]);
   std::vector<DcMerge> all;
   std::vector<int> lvl_off, lvl_kmax;
   while (nodes.size() > 1) {
@@ -914,17 +954,23 @@ void DcWork::run(const double* band, int ldb, int k, double* lam, double* F, dou
     lvl_kmax.push_back(Kmax);
     nodes.swap(next);
   }
+  if (grow) {  // the stored root [0, r0) with the new node [r0, k)
+    lvl_off.push_back((int)all.size());
+    all.push_back(DcMerge{0, r0, k, 0});
+    lvl_kmax.push_back(k);
+  }
   lvl_off.push_back((int)all.size());
   const int ntot = (int)all.size();
-  if (ntot == 0) return;
   if (ntot > w.md_cap) {
     w.md.alloc((size_t)ntot * sizeof(DcMerge));
     w.ms.alloc((size_t)ntot * sizeof(DcScal));
     w.md_cap = ntot;
   }
-  LYAP_HIP(hipMemcpyAsync(w.md.p, all.data(), ntot * sizeof(DcMerge), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_coupling_svd, dim3((ntot + 63) / 64), dim3(64), 0, st, w.md.as<DcMerge>(), w.ms.as<DcScal>(),
-                     ntot, band, ldb, ell);
+  if (ntot > 0) {
+    LYAP_HIP(hipMemcpyAsync(w.md.p, all.data(), ntot * sizeof(DcMerge), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_coupling_svd, dim3((ntot + 63) / 64), dim3(64), 0, st, w.md.as<DcMerge>(),
+                       w.ms.as<DcScal>(), ntot, band, ldb, ell);
+  }
   for (size_t lv = 0; lv + 1 < lvl_off.size(); ++lv) {
     const int nm = lvl_off[lv + 1] - lvl_off[lv];
     const int Kmax = lvl_kmax[lv];
@@ -941,31 +987,37 @@ void DcWork::run(const double* band, int ldb, int k, double* lam, double* F, dou
     double* Dnx = w.Db.as<double>();
     double* Rcur = w.Ra.as<double>();
     double* Rnx = w.Rb.as<double>();
-    hipLaunchKernelGGL(k_merge_setup, dim3(gx, nm), dim3(256), 0, st, md, ms, band, ldb, ell, k, lam, F, L, Dcur,
+    hipLaunchKernelGGL(k_merge_setup, dim3(gx, nm), dim3(256), 0, st, md, ms, band, ldb, ell, ld, Dm, Fm, Lm, Dcur,
                        Rcur);
     for (int u = 0; u < 2 * ell; ++u) {
-      hipLaunchKernelGGL(k_zform, dim3(gx, nm), dim3(256), 0, st, md, ms, ell, k, u, Rcur, w.z.as<double>());
-      hipLaunchKernelGGL(k_deflate, dim3(nm), dim3(kDefThreads), 0, st, md, ms, ell, k, u, Dcur, Rcur,
+      hipLaunchKernelGGL(k_zform, dim3(gx, nm), dim3(256), 0, st, md, ms, ell, ld, u, Rcur, w.z.as<double>());
+      hipLaunchKernelGGL(k_deflate, dim3(nm), dim3(kDefThreads), 0, st, md, ms, ell, ld, u, Dcur, Rcur,
                          w.z.as<double>(), w.Dn.as<double>(), w.zn.as<double>(), w.nd.as<int>(), w.defl.as<int>(),
                          w.defv.as<double>(), w.sml.as<int>(), w.smv.as<double>(), w.rdl.as<int>(),
                          w.rdv.as<double>());
       launch_secular(Kmax, nm, md, ms, w.Dn.as<double>(), w.zn.as<double>(), w.orig.as<int>(), w.tau.as<double>(),
                      w.lamn.as<double>(), st);
-      hipLaunchKernelGGL(k_zhat, dim3(gw, nm), dim3(256), 0, st, md, ms, nr, vec_pad(nr), k, Rcur, w.nd.as<int>(),
+      hipLaunchKernelGGL(k_zhat, dim3(gw, nm), dim3(256), 0, st, md, ms, nr, vec_pad(nr), ld, Rcur, w.nd.as<int>(),
                          w.Dn.as<double>(), w.zn.as<double>(), w.orig.as<int>(), w.tau.as<double>(),
                          w.zh.as<double>(), w.Rt.as<double>());
-      launch_vec(dim3(nchunk * (nsp / 4), nm), md, ms, nr, k, nsp, w.Rt.as<double>(), w.Dn.as<double>(),
+      launch_vec(dim3(nchunk * (nsp / 4), nm), md, ms, nr, ld, nsp, w.Rt.as<double>(), w.Dn.as<double>(),
                  w.orig.as<int>(), w.tau.as<double>(), w.zh.as<double>(), w.part.as<double>(), st);
       hipLaunchKernelGGL(k_vec_sum, dim3(std::min(((nr + 1) * Kmax + 255) / 256, 1024), nm), dim3(256), 0, st, md,
-                         ms, nr, k, nsp, w.part.as<double>(), w.NR.as<double>(), w.nrm.as<double>());
-      hipLaunchKernelGGL(k_assemble, dim3(gx, nm), dim3(256), 0, st, md, ms, ell, k, Rcur, w.NR.as<double>(),
+                         ms, nr, ld, nsp, w.part.as<double>(), w.NR.as<double>(), w.nrm.as<double>());
+      hipLaunchKernelGGL(k_assemble, dim3(gx, nm), dim3(256), 0, st, md, ms, ell, ld, Rcur, w.NR.as<double>(),
                          w.nrm.as<double>(), w.defl.as<int>(), w.defv.as<double>(), w.lamn.as<double>(), Dnx, Rnx);
       std::swap(Dcur, Dnx);
       std::swap(Rcur, Rnx);
     }
-    hipLaunchKernelGGL(k_merge_finish, dim3(gx, nm), dim3(256), 0, st, md, ell, k, Dcur, Rcur, lam, F, L);
+    hipLaunchKernelGGL(k_merge_finish, dim3(gx, nm), dim3(256), 0, st, md, ell, ld, Dcur, Rcur, Dm, Fm, Lm);
     LYAP_LAUNCHED("dc merge level");
   }
+  hipLaunchKernelGGL(k_root_out, dim3(std::min((k + 255) / 256, 1024)), dim3(256), 0, st, k, ell, ld, Dm, Fm, Lm, lam,
+                     F, L);
+  LYAP_LAUNCHED("dc root");
+  w.cband = band;
+  w.cldb = ldb;
+  w.kc = k;
 }
 
 }  // namespace lyap
