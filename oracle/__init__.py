@@ -26,6 +26,9 @@ Modules
 ``extended`` the extended Krylov variant (Section 4).
 ``sylvester`` two-sided projection for A X + X B + C1 C2^T = 0 (Section 5.1)
             with the corrected Algorithm 4.
+``smallb``  large A and small B (Section 5.2): one Krylov space, the
+            one-sided Galerkin reduction, Algorithm 5, truncated Y~ and the
+            factors Z1 = V_m Q Y1, Z2 = P Y2.
 ``pcg``     IC(0)/Jacobi preconditioned CG for the inner solves.
 ``cnn``     forward/backward of the small convolutional preconditioner.
 """

@@ -9,6 +9,7 @@ from .problems import (  # noqa: F401
     laplace2d,
     fv3d,
     fd2d_variable,
+    fd1d_dense,
     gaussian_C,
     uniform_C,
     batch_c5,

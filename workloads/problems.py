@@ -195,6 +195,20 @@ def fd2d_variable(N: int, ax, ay, name: str = "fd2d") -> Operator:
                     meta={"name": name, "N": N})
 
 
+def fd1d_dense(N: int, a: float = 1.0) -> np.ndarray:
+    """Dense N x N matrix of a u_zz by centred second differences on (0, 1),
+    N interior points, h = 1/(N+1), zero Dirichlet boundary:
+    (a/h^2) tridiag(1, -2, 1), symmetric negative definite (the small B of a
+    separable 3-D operator split as A X + X B)."""
+    h = 1.0 / (N + 1)
+    B = np.zeros((N, N))
+    i = np.arange(N)
+    B[i, i] = -2.0 * a / (h * h)
+    B[i[:-1], i[:-1] + 1] = a / (h * h)
+    B[i[:-1] + 1, i[:-1]] = a / (h * h)
+    return B
+
+
 # ----------------------------------------------------------- right-hand sides
 def gaussian_C(n: int, s: int, seed: int) -> np.ndarray:
     """n x s standard Gaussian, column c from ``default_rng([seed, c])`` so that
