@@ -253,6 +253,51 @@ lyap_status sylv_solve(const lyap_op* A, const lyap_op* B, const double* C1, int
                        const double* C2, int64_t ldc2, int32_t s, const lyap_opts* opts,
                        sylv_result* out);
 
+/*
+ * sylv_solve_small_b — AX + XB + C1 C2^T = 0 with A large and sparse and B
+ * small and dense (Section 5.2, "Large A and small B").  Only A is projected:
+ * X_m = V_m Y_m with V_m a basis of K_m(A, C1) and the one-sided Galerkin
+ * condition V_m^T R_m = 0 (eq. (orthLargeAsmallB)), so Y_m solves the k x n2
+ * equation T_m Y + Y B + E_1 gamma_1 C2^T = 0 (eq. (reducedLargeASmallB)).
+ * B = P Upsilon P^T is computed once, before the iteration (lyap_sym_eig);
+ * the residual at a check is Algorithm 5 (no Y_m formed); at the first
+ * passing check Y_m = Q Y~ P^T (eq. (formulaLargeAsmallB)) is truncated to
+ * ||Y~ - Y1 Y2^T||_F <= eps (cross approximation with complete pivoting; the
+ * error bound of the paper's truncated SVD at a possibly larger rank) and
+ * Z1 = V_m Q Y1 (second Lanczos pass when two_pass = 1), Z2 = P Y2.
+ *  A      operator, symmetric negative definite, n1 = A->n rows.
+ *  B      device, n2 x n2 column-major FP64 (ldb >= n2), symmetric negative
+ *         definite, 1 <= n2 <= 2048; only its lower triangle is read.
+ *  C1     device, n1 x s column-major FP64 (ldc1 >= n1); C2 device, n2 x s
+ *         column-major FP64 (ldc2 >= n2); 1 <= s <= 8.
+ *  opts   as for sylv_solve (method STD); tol applies to
+ *         ||R_m||_F / (||C1||_F ||C2||_F); trunc_eps < 0 selects
+ *         eps = min(1e-12, 0.05 tol / nu) ||C1||_F ||C2||_F with
+ *         nu = max|lambda(T_m)| + ||tau_{m+1,m}||_F + max|upsilon|.
+ *  out    sylv_result: Z1 (n1 x t), Z2 (n2 x t), history; with want_T the
+ *         host T_band, gamma1 and tau (J_band, gamma2, iota stay NULL).
+ * Errors: E_ARG (sizes), E_INDEFINITE (B or a Ritz value of A not negative),
+ * E_NUMERIC (non-finite B, or Jacobi not converged in 60 sweeps), E_BREAKDOWN.
+ */
+lyap_status sylv_solve_small_b(const lyap_op* A, const double* B, int64_t n2, int64_t ldb, const double* C1,
+                               int64_t ldc1, const double* C2, int64_t ldc2, int32_t s, const lyap_opts* opts,
+                               sylv_result* out);
+
+/*
+ * lyap_sym_eig — B = P diag(w) P^T for a dense symmetric n x n matrix, the
+ * decomposition of the small B that Section 5.2 computes once; parallel
+ * cyclic Jacobi in FP64 on the GPU (round-robin pairs, n/2 commuting
+ * rotations per launch) until every |b_pq| <= 2^-52 sqrt(|b_pp b_qq|) (or the
+ * off-diagonal norm is below 2^-55 ||B||_F).
+ *  B      device, column-major (ldb >= n), lower triangle read; 1 <= n <= 2048.
+ *  w      device, n eigenvalues ascending.
+ *  P      device, n x n column-major (ldp >= n), orthonormal eigenvectors.
+ *  stream hipStream_t (NULL = null stream); synchronised before returning.
+ *  sweeps optional output: Jacobi sweeps taken.
+ */
+lyap_status lyap_sym_eig(const double* B, int64_t n, int64_t ldb, double* w, double* P, int64_t ldp, void* stream,
+                         int32_t* sweeps);
+
 /* Releases host arrays of a result and, when the library allocated Z with
  * hipMalloc (opts->alloc == NULL), Z itself.  Safe on a zeroed struct. */
 void lyap_result_free(lyap_result* r);

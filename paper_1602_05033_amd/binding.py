@@ -78,7 +78,7 @@ class SylvResult(ct.Structure):
 EXPORTS = ["lyap_opts_default", "lyap_solve", "sylv_solve", "lyap_result_free", "sylv_result_free",
            "lyap_last_error", "lyap_op_apply", "lyap_op_apply_timed", "lyap_ctri", "lyap_inner_solve",
            "lyap_solve_batched", "lyap_pcnet_init", "lyap_pcnet_apply", "lyap_pcnet_grad", "lyap_pcnet_train",
-           "lyap_pcnet_fcg"]
+           "lyap_pcnet_fcg", "sylv_solve_small_b", "lyap_sym_eig"]
 
 
 class LyapError(RuntimeError):
@@ -108,6 +108,13 @@ def load(path: str = LIB_PATH):
     lib.sylv_solve.restype = ct.c_int
     lib.lyap_result_free.argtypes = [ct.POINTER(LyapResult)]
     lib.lyap_result_free.restype = None
+    lib.sylv_solve_small_b.argtypes = [ct.POINTER(LyapOp), ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_void_p,
+                                       ct.c_int64, ct.c_void_p, ct.c_int64, ct.c_int32, ct.POINTER(LyapOpts),
+                                       ct.POINTER(SylvResult)]
+    lib.sylv_solve_small_b.restype = ct.c_int
+    lib.lyap_sym_eig.argtypes = [ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int64,
+                                 ct.c_void_p, ct.POINTER(ct.c_int32)]
+    lib.lyap_sym_eig.restype = ct.c_int
     lib.sylv_result_free.argtypes = [ct.POINTER(SylvResult)]
     lib.sylv_result_free.restype = None
     lib.lyap_last_error.argtypes = []
@@ -473,6 +480,75 @@ def sylv_solve(dopA: DeviceOp, dopB: DeviceOp, C1, C2, raise_on_error: bool = Tr
         return sol
     finally:
         lib.sylv_result_free(ct.byref(r))
+
+
+def sylv_solve_small_b(dopA: DeviceOp, B, C1, C2, raise_on_error: bool = True, **kw) -> SylvSolution:
+    """Solve A X + X B + C1 C2^T = 0 with a small dense B (n2, n2) float64
+    torch tensor on the device (only A is projected); C1 (n1, s), C2 (n2, s)
+    float64 device tensors.  Returns Z1 (n1, t), Z2 (n2, t), Z1 Z2^T ~ X."""
+    import torch
+    lib = load()
+    n1, s = C1.shape
+    n2, s2 = C2.shape
+    assert s == s2 and n1 == dopA.n and tuple(B.shape) == (n2, n2)
+    for x in (B, C1, C2):
+        assert x.dtype == torch.float64 and x.is_cuda
+    Bcm = B.t().contiguous()
+    C1cm = C1.t().contiguous()
+    C2cm = C2.t().contiguous()
+    alloc = _TorchAllocator(C1.device)
+    o = make_opts(stream=torch.cuda.current_stream(C1.device).cuda_stream, **kw)
+    o.alloc, o.release = alloc.alloc_cb, alloc.free_cb
+    r = SylvResult()
+    st = lib.sylv_solve_small_b(ct.byref(dopA.c), ct.c_void_p(Bcm.data_ptr()), n2, n2, ct.c_void_p(C1cm.data_ptr()),
+                                n1, ct.c_void_p(C2cm.data_ptr()), n2, s, ct.byref(o), ct.byref(r))
+    msg = lib.lyap_last_error().decode()
+    try:
+        if raise_on_error and st not in (OK, NOT_CONVERGED):
+            raise LyapError(st, msg)
+        Z1 = Z2 = None
+        if r.Z1 and r.Z2:
+            b1 = alloc.take(r.Z1)
+            b2 = alloc.take(r.Z2)
+            if r.t > 0:
+                Z1 = b1[: 8 * n1 * r.t].view(torch.float64).view(r.t, n1).t()
+                Z2 = b2[: 8 * n2 * r.t].view(torch.float64).view(r.t, n2).t()
+            else:
+                Z1 = torch.zeros((n1, 0), dtype=torch.float64, device=C1.device)
+                Z2 = torch.zeros((n2, 0), dtype=torch.float64, device=C1.device)
+        ell = r.ell
+        k = ell * r.m
+        sol = SylvSolution(
+            status=st, Z1=Z1, Z2=Z2, m=r.m, t=r.t, beta1=r.beta1, beta2=r.beta2, res=r.res,
+            hist_m=[r.hist_m[i] for i in range(r.n_hist)], hist_res=[r.hist_res[i] for i in range(r.n_hist)],
+            times_ms={k_: r.times_ms[i] for i, k_ in enumerate(TIME_KEYS)}, n_checks=r.n_checks,
+            trunc_eps=r.trunc_eps,
+            kernels={name: {"ms": r.kern_ms[i], "n": r.kern_n[i], "bytes_per_launch": r.kern_bytes[i]}
+                     for i, name in enumerate(KERNEL_KINDS) if r.kern_n[i] > 0})
+        if r.T_band:
+            sol.T_band = np.ctypeslib.as_array(r.T_band, shape=(k * (ell + 1),)).copy().reshape(k, ell + 1)
+            for name in ("gamma1", "tau"):
+                setattr(sol, name, np.ctypeslib.as_array(getattr(r, name), shape=(ell * ell,)).copy()
+                        .reshape(ell, ell, order="F"))
+        sol.error = msg
+        return sol
+    finally:
+        lib.sylv_result_free(ct.byref(r))
+
+
+def sym_eig(B):
+    """w (ascending), P, sweeps for a symmetric (n, n) float64 device tensor."""
+    import torch
+    lib = load()
+    n = B.shape[0]
+    assert tuple(B.shape) == (n, n) and B.dtype == torch.float64 and B.is_cuda
+    Bcm = B.t().contiguous()
+    w = torch.empty(n, dtype=torch.float64, device=B.device)
+    Pcm = torch.empty((n, n), dtype=torch.float64, device=B.device)
+    sw = ct.c_int32(0)
+    _check(lib.lyap_sym_eig(ct.c_void_p(Bcm.data_ptr()), n, n, ct.c_void_p(w.data_ptr()),
+                            ct.c_void_p(Pcm.data_ptr()), n, _stream(B.device), ct.byref(sw)))
+    return w, Pcm.t(), sw.value
 
 
 # ------------------------------------------------------------------ learned preconditioner components

@@ -28,6 +28,7 @@
 #include <cmath>
 #include <type_traits>
 
+#include "aca.hpp"
 #include "check.hpp"
 #include "side.hpp"
 #include "solver.hpp"
@@ -115,20 +116,20 @@ __global__ void k_ytilde(const double* lamA, const double* gA, const double* lam
 
 // E -= u v^T (when apply and not stopped); partial max |E| (first index on
 // ties) and sum of squares per workgroup.
-__global__ __launch_bounds__(kAcaThreads) void k_aca_update_scan(double* E, int k, const double* u, const double* v,
-                                                                 const AcaState* stt, int apply, double* pmax,
-                                                                 int64_t* pidx, double* pnorm) {
+__global__ __launch_bounds__(kAcaThreads) void k_aca_update_scan(double* E, int rows, int cols, const double* u,
+                                                                 const double* v, const AcaState* stt, int apply,
+                                                                 double* pmax, int64_t* pidx, double* pnorm) {
   __shared__ double red[kAcaThreads / 64];
   __shared__ double sv[kAcaThreads / 64];
   __shared__ int64_t si[kAcaThreads / 64];
   const bool upd = apply && !stt->stop;
-  const int64_t tot = (int64_t)k * k;
+  const int64_t tot = (int64_t)rows * cols;
   double best = -1.0, nrm = 0.0;
   int64_t bi = tot;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
     double x = E[e];
     if (upd) {
-      const int i = (int)(e / k), j = (int)(e - (int64_t)i * k);
+      const int i = (int)(e / cols), j = (int)(e - (int64_t)i * cols);
       x = fma(-u[i], v[j], x);
       E[e] = x;
     }
@@ -178,10 +179,10 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca_update_scan(double* E, int 
 // Total over the partials (fixed order); stop when ||E||_F <= eps, otherwise
 // record the pivot (I[t], J[t]).
 __global__ void k_aca_pick(const double* pmax, const int64_t* pidx, const double* pnorm, int nparts, const double* E,
-                           int k, double eps2, int tmax, AcaState* stt, int* I, int* J) {
+                           int rows, int cols, double eps2, int tmax, AcaState* stt, int* I, int* J) {
   if (threadIdx.x != 0 || blockIdx.x != 0 || stt->stop) return;
   double b = -1.0, s = 0.0;
-  int64_t ii = (int64_t)k * k;
+  int64_t ii = (int64_t)rows * cols;
   for (int p = 0; p < nparts; ++p) {
     if (pmax[p] > b || (pmax[p] == b && pidx[p] < ii)) { b = pmax[p]; ii = pidx[p]; }
     s += pnorm[p];
@@ -191,7 +192,7 @@ __global__ void k_aca_pick(const double* pmax, const int64_t* pidx, const double
     stt->stop = 1;
     return;
   }
-  const int i = (int)(ii / k), j = (int)(ii - (int64_t)i * k);
+  const int i = (int)(ii / cols), j = (int)(ii - (int64_t)i * cols);
   stt->i = i;
   stt->j = j;
   stt->pivot = E[ii];
@@ -201,27 +202,39 @@ __global__ void k_aca_pick(const double* pmax, const int64_t* pidx, const double
 }
 
 // u = E(:, j), v = E(i, :) / pivot.
-__global__ void k_aca_copy(const double* E, int k, const AcaState* stt, double* u, double* v) {
+__global__ void k_aca_copy(const double* E, int rows, int cols, const AcaState* stt, double* u, double* v) {
   if (stt->stop) return;
   const int i = stt->i, j = stt->j;
   const double pinv = 1.0 / stt->pivot;
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < k; r += gridDim.x * blockDim.x) {
-    u[r] = E[(size_t)r * k + j];
-    v[r] = E[(size_t)i * k + r] * pinv;
+  const int len = rows > cols ? rows : cols;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < len; r += gridDim.x * blockDim.x) {
+    if (r < rows) u[r] = E[(size_t)r * cols + j];
+    if (r < cols) v[r] = E[(size_t)i * cols + r] * pinv;
   }
 }
 
-// Core Y~(I, J) = L U without further pivoting (the complete-pivoting order);
-// B1 = U^{-1}, B2 = L^{-T} (t x t, row-major).  One workgroup; W: t x t scratch.
-__global__ __launch_bounds__(1024) void k_core_lu(const double* lamA, const double* gA, const double* lamB,
-                                                  const double* gB, int ell, const int* I, const int* J, int t,
-                                                  double* W, double* B1, double* B2) {
-  const int nt = blockDim.x;
-  for (int e = threadIdx.x; e < t * t; e += nt) {
+// Core W = Y~(I, J) of the two-sided method, generated from lambda and g.
+__global__ void k_core_fill_ytilde(const double* lamA, const double* gA, const double* lamB, const double* gB,
+                                   int ell, const int* I, const int* J, int t, double* W) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < t * t; e += gridDim.x * blockDim.x) {
     const int a = e / t, b = e - a * t;
     W[e] = ytilde(lamA, gA, lamB, gB, ell, I[a], J[b]);
   }
-  __syncthreads();
+}
+
+// Core W = E0(I, J) of an explicit row-major matrix (leading dimension lde).
+__global__ void k_core_fill(const double* E0, int64_t lde, const int* I, const int* J, int t, double* W) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < t * t; e += gridDim.x * blockDim.x) {
+    const int a = e / t, b = e - a * t;
+    W[e] = E0[(size_t)I[a] * lde + J[b]];
+  }
+}
+
+// Core W = L U without further pivoting (the complete-pivoting order makes
+// every pivot the largest remaining entry); B1 = U^{-1}, B2 = L^{-T} (t x t,
+// row-major).  One workgroup; W is overwritten by the factors.
+__global__ __launch_bounds__(1024) void k_core_lu(int t, double* W, double* B1, double* B2) {
+  const int nt = blockDim.x;
   for (int p = 0; p < t; ++p) {
     const double piv = W[(size_t)p * t + p];
     for (int a = p + 1 + threadIdx.x; a < t; a += nt) W[(size_t)a * t + p] /= piv;
@@ -251,6 +264,53 @@ __global__ __launch_bounds__(1024) void k_core_lu(const double* lamA, const doub
   }
 }
 
+// Cross approximation of the rows x cols row-major matrix E (overwritten by
+// the Schur complements): pivots I (rows), J (columns), t of them, chosen by
+// complete pivoting until ||E - E(:, J) E(I, J)^{-1} E(I, :)||_F <= eps.
+int aca_cross(double* E, int rows, int cols, double eps, int tmax, DevBuf& I, DevBuf& J, hipStream_t st) {
+  const int64_t tot = (int64_t)rows * cols;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((tot + kAcaThreads - 1) / kAcaThreads, 1024));
+  DevBuf u((size_t)rows * sizeof(double)), v((size_t)cols * sizeof(double));
+  DevBuf pmax(grid * sizeof(double)), pidx(grid * sizeof(int64_t)), pnorm(grid * sizeof(double));
+  DevBuf stt(sizeof(AcaState));
+  I.alloc(std::max(1, tmax) * sizeof(int));
+  J.alloc(std::max(1, tmax) * sizeof(int));
+  LYAP_HIP(hipMemsetAsync(stt.p, 0, sizeof(AcaState), st));
+  const int len = std::max(rows, cols);
+  AcaState h{};
+  const double eps2 = eps * eps;
+  for (int step = 0; step <= tmax; ++step) {
+    hipLaunchKernelGGL(k_aca_update_scan, dim3(grid), dim3(kAcaThreads), 0, st, E, rows, cols, u.as<double>(),
+                       v.as<double>(), stt.as<AcaState>(), step > 0 ? 1 : 0, pmax.as<double>(),
+                       pidx.as<int64_t>(), pnorm.as<double>());
+    hipLaunchKernelGGL(k_aca_pick, dim3(1), dim3(64), 0, st, pmax.as<double>(), pidx.as<int64_t>(),
+                       pnorm.as<double>(), grid, E, rows, cols, eps2, tmax, stt.as<AcaState>(), I.as<int>(),
+                       J.as<int>());
+    hipLaunchKernelGGL(k_aca_copy, dim3(std::max(1, std::min((len + 255) / 256, 256))), dim3(256), 0, st, E, rows,
+                       cols, stt.as<AcaState>(), u.as<double>(), v.as<double>());
+    LYAP_LAUNCHED("aca step");
+    if ((step + 1) % 16 == 0 || step == tmax) {
+      LYAP_HIP(hipMemcpyAsync(&h, stt.p, sizeof(AcaState), hipMemcpyDeviceToHost, st));
+      LYAP_HIP(hipStreamSynchronize(st));
+      if (h.stop) break;
+    }
+  }
+  LYAP_REQUIRE(h.stop, LYAP_E_UNSUPPORTED, "truncation rank exceeds %d", tmax);
+  LYAP_REQUIRE(!(h.norm2 > eps2) || h.t < tmax || tmax == std::min(rows, cols), LYAP_E_UNSUPPORTED,
+               "truncation rank exceeds %d", tmax);
+  return h.t;
+}
+
+void core_lu_explicit(const double* E0, int64_t lde, const int* I, const int* J, int t, double* B1, double* B2,
+                      hipStream_t st) {
+  DevBuf W((size_t)t * t * sizeof(double));
+  hipLaunchKernelGGL(k_core_fill, dim3(std::max(1, std::min((t * t + 255) / 256, 1024))), dim3(256), 0, st, E0, lde,
+                     I, J, t, W.as<double>());
+  hipLaunchKernelGGL(k_core_lu, dim3(1), dim3(1024), 0, st, t, W.as<double>(), B1, B2);
+  LYAP_LAUNCHED("k_core_lu");
+  LYAP_HIP(hipStreamSynchronize(st));  // W is released on return
+}
+
 namespace {
 
 // Returns t; M1, M2: k x t row-major.
@@ -261,43 +321,21 @@ int finalise_sylv(const Checker& ca, const Checker& cb, const double* bandA, con
   LYAP_REQUIRE(k <= 16384, LYAP_E_UNSUPPORTED, "Sylvester truncation limited to k <= 16384 (got %d)", k);
   const int tmax = std::min(k, 1024);
   DevBuf E((size_t)k * k * sizeof(double));
-  DevBuf u((size_t)k * sizeof(double)), v((size_t)k * sizeof(double));
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)k * k + kAcaThreads - 1) / kAcaThreads, 1024));
-  DevBuf pmax(grid * sizeof(double)), pidx(grid * sizeof(int64_t)), pnorm(grid * sizeof(double));
-  DevBuf stt(sizeof(AcaState)), I(tmax * sizeof(int)), J(tmax * sizeof(int));
-  LYAP_HIP(hipMemsetAsync(stt.p, 0, sizeof(AcaState), st));
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)k * k + 255) / 256, 1024));
   hipLaunchKernelGGL(k_ytilde, dim3(grid), dim3(256), 0, st, ca.lam(), ca.g(), cb.lam(), cb.g(), k, ell,
                      E.as<double>());
   LYAP_LAUNCHED("k_ytilde");
-  AcaState h{};
-  const double eps2 = eps * eps;
-  for (int step = 0; step <= tmax; ++step) {
-    hipLaunchKernelGGL(k_aca_update_scan, dim3(grid), dim3(kAcaThreads), 0, st, E.as<double>(), k, u.as<double>(),
-                       v.as<double>(), stt.as<AcaState>(), step > 0 ? 1 : 0, pmax.as<double>(),
-                       pidx.as<int64_t>(), pnorm.as<double>());
-    hipLaunchKernelGGL(k_aca_pick, dim3(1), dim3(64), 0, st, pmax.as<double>(), pidx.as<int64_t>(),
-                       pnorm.as<double>(), grid, E.as<double>(), k, eps2, tmax, stt.as<AcaState>(), I.as<int>(),
-                       J.as<int>());
-    hipLaunchKernelGGL(k_aca_copy, dim3(std::max(1, std::min((k + 255) / 256, 256))), dim3(256), 0, st,
-                       E.as<double>(), k, stt.as<AcaState>(), u.as<double>(), v.as<double>());
-    LYAP_LAUNCHED("aca step");
-    if ((step + 1) % 16 == 0 || step == tmax) {
-      LYAP_HIP(hipMemcpyAsync(&h, stt.p, sizeof(AcaState), hipMemcpyDeviceToHost, st));
-      LYAP_HIP(hipStreamSynchronize(st));
-      if (h.stop) break;
-    }
-  }
-  LYAP_REQUIRE(h.stop, LYAP_E_UNSUPPORTED, "Sylvester truncation rank exceeds %d", tmax);
-  LYAP_REQUIRE(!(h.norm2 > eps2) || h.t < tmax, LYAP_E_UNSUPPORTED, "Sylvester truncation rank exceeds %d", tmax);
-  const int t = h.t;
+  DevBuf I, J;
+  const int t = aca_cross(E.as<double>(), k, k, eps, tmax, I, J, st);
   if (t <= 0) {
     M1.alloc(8);
     M2.alloc(8);
     return 0;
   }
   DevBuf W((size_t)t * t * sizeof(double)), B1((size_t)t * t * sizeof(double)), B2((size_t)t * t * sizeof(double));
-  hipLaunchKernelGGL(k_core_lu, dim3(1), dim3(1024), 0, st, ca.lam(), ca.g(), cb.lam(), cb.g(), ell, I.as<int>(),
-                     J.as<int>(), t, W.as<double>(), B1.as<double>(), B2.as<double>());
+  hipLaunchKernelGGL(k_core_fill_ytilde, dim3(std::max(1, std::min((t * t + 255) / 256, 1024))), dim3(256), 0, st,
+                     ca.lam(), ca.g(), cb.lam(), cb.g(), ell, I.as<int>(), J.as<int>(), t, W.as<double>());
+  hipLaunchKernelGGL(k_core_lu, dim3(1), dim3(1024), 0, st, t, W.as<double>(), B1.as<double>(), B2.as<double>());
   LYAP_LAUNCHED("k_core_lu");
   DevBuf Lb((size_t)(ell + 1) * k * t * sizeof(double));
   DevBuf XC((size_t)k * t * sizeof(double)), XR((size_t)k * t * sizeof(double));

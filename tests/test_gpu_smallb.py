@@ -1,0 +1,219 @@
+"""GPU parity of the large-A / small-B Sylvester path (Section 5.2): the
+Jacobi eigensolver for B (lyap_sym_eig) and sylv_solve_small_b (one block
+Lanczos space, Algorithm 5 residual, cross-approximation truncation of
+Q Y~, two passes) against the CPU FP64 oracle on the same seeded inputs, the
+edge cases (n2 = 1, odd n2, repeated eigenvalues, the largest B), the error
+paths, and the paper's Example 5 sizes against tests/golden/example5_oracle.json
+(written by make_example5_oracle.py from the oracle only)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from workloads import fd1d_dense, fd2d_variable, laplace2d, gaussian_C, uniform_C
+from oracle import smallb as SB
+from oracle import sylvester as Y
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _b():
+    from paper_1602_05033_amd import binding
+    return binding
+
+
+def _dev(C):
+    return torch.from_numpy(np.ascontiguousarray(C)).cuda()
+
+
+def _snd(n, seed, lo=1.0, hi=50.0, mult=None):
+    """-(Q diag(d) Q^T), d uniform in [lo, hi) (or the given multiset)."""
+    rng = np.random.default_rng([seed])
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    d = np.asarray(mult, dtype=np.float64) if mult is not None else lo + (hi - lo) * rng.random(n)
+    B = -(Q * d) @ Q.T
+    return 0.5 * (B + B.T)
+
+
+# ------------------------------------------------------------------ B = P Upsilon P^T
+@pytest.mark.parametrize("n,kind", [(1, "rand"), (2, "rand"), (7, "rand"), (64, "rand"), (148, "fd1d"),
+                                    (301, "rand"), (40, "repeated"), (1024, "rand"), (2048, "rand")])
+def test_sym_eig(lib, n, kind):
+    b = _b()
+    if kind == "fd1d":
+        B = fd1d_dense(n, 10.0)
+    elif kind == "repeated":
+        B = _snd(n, 3, mult=np.repeat([1.0, 2.0, 5.0, 5.0 + 1e-13, 9.0], n // 5))
+    else:
+        B = _snd(n, n, 1.0, 1e4)
+    print(f"sym_eig n={n} {kind}", flush=True)
+    w, P, sweeps = b.sym_eig(_dev(B))
+    w = w.cpu().numpy()
+    P = P.cpu().numpy()
+    nb = np.linalg.norm(B, 2)
+    wr = np.linalg.eigvalsh(B)
+    ew = np.max(np.abs(w - wr)) / nb
+    er = np.linalg.norm(B @ P - P * w) / nb
+    eo = np.linalg.norm(P.T @ P - np.eye(n))
+    print(f"  sweeps {sweeps}, eigenvalues {ew:.1e}, residual {er:.1e}, orthogonality {eo:.1e}")
+    assert np.all(np.diff(w) >= 0)
+    assert ew <= 1e-12
+    assert er <= 1e-12 * np.sqrt(n)
+    assert eo <= 1e-12 * np.sqrt(n)
+    assert sweeps <= 15
+
+
+def test_sym_eig_errors(lib):
+    b = _b()
+    with pytest.raises(b.LyapError):
+        b.sym_eig(_dev(np.eye(2049)))
+
+
+# ------------------------------------------------------------------ solver parity
+def _case(opA, B, s, tol, storage=0, two_pass=True, check_every=1, seed1=7, seed2=8):
+    b = _b()
+    A = opA.to_scipy()
+    C1 = gaussian_C(opA.n, s, seed1)
+    C2 = gaussian_C(B.shape[0], s, seed2)
+    sol = b.sylv_solve_small_b(b.device_op(opA), _dev(B), _dev(C1), _dev(C2), tol=tol, storage=storage,
+                               two_pass=two_pass, check_every=check_every, want_T=True)
+    return A, C1, C2, sol
+
+
+@pytest.mark.parametrize("s", [1, 2, 3, 8])
+def test_smallb_parity_fp64(lib, s):
+    opA = laplace2d(37)            # n1 = 1369: several workgroups and a ragged tail
+    B = _snd(33, 21, 2.0, 900.0)   # n2 = 33 (odd)
+    print(f"smallb parity s={s}", flush=True)
+    A, C1, C2, sol = _case(opA, B, s, 1e-9)
+    ref = SB.sylv_small_b(A, B, C1, C2, tol=1e-9)
+    assert sol.status == 0 and ref.converged
+    assert abs(sol.m - ref.m) <= 1, (sol.m, ref.m)
+    gh = dict(zip(sol.hist_m, sol.hist_res))
+    for h in ref.hist:
+        if h["m"] in gh:
+            tolr = 1e-8 if h["m"] <= 20 else 1e-3
+            assert abs(gh[h["m"]] - h["res"]) <= tolr * h["res"], (h["m"], gh[h["m"]], h["res"])
+    Z1, Z2 = sol.Z1.cpu().numpy(), sol.Z2.cpu().numpy()
+    X = sla.solve_sylvester(A.toarray(), B, -(C1 @ C2.T))
+    nX = np.linalg.norm(X)
+    err_gpu = np.linalg.norm(Z1 @ Z2.T - X) / nX
+    err_ref = np.linalg.norm(ref.Z1 @ ref.Z2.T - X) / nX
+    assert err_gpu <= 10 * err_ref + 1e-11, (err_gpu, err_ref)
+    assert np.linalg.norm(Z1 @ Z2.T - ref.Z1 @ ref.Z2.T) <= 1e-8 * nX
+    ex = Y.explicit_residual(A, B, Z1, Z2, C1, C2) / (sol.beta1 * sol.beta2)
+    assert ex <= 1.2e-9
+    # T_m early columns and gamma_1
+    k = s * sol.m
+    for c in range(min(k, 4 * s)):
+        for d in range(s + 1):
+            if c + d < k:
+                assert abs(sol.T_band[c, d] - ref.T[c + d, c]) <= 1e-10 * np.abs(ref.T).max()
+    assert np.allclose(sol.gamma1, ref.gamma1, rtol=0, atol=1e-12 * np.abs(ref.gamma1).max())
+    assert sol.t <= min(k, B.shape[0])
+
+
+def test_smallb_two_pass_equals_stored(lib):
+    opA = laplace2d(30)
+    B = fd1d_dense(17, 10.0)
+    _, _, _, s1 = _case(opA, B, 2, 1e-8, two_pass=True)
+    _, _, _, s2 = _case(opA, B, 2, 1e-8, two_pass=False)
+    assert s1.m == s2.m and s1.t == s2.t
+    # the second pass regenerates the stored blocks bit for bit
+    assert torch.equal(s1.Z1, s2.Z1) and torch.equal(s1.Z2, s2.Z2)
+
+
+def test_smallb_scalar_b(lib):
+    """n2 = 1: a single shifted linear system (A + b I) x = -C1 c2^T."""
+    b = _b()
+    opA = laplace2d(25)
+    A = opA.to_scipy()
+    C1 = gaussian_C(opA.n, 1, 11)
+    C2 = np.array([[0.5]])
+    sol = b.sylv_solve_small_b(b.device_op(opA), _dev(np.array([[-37.0]])), _dev(C1), _dev(C2), tol=1e-12,
+                               check_every=1)
+    assert sol.status == 0 and sol.t == 1
+    x = -sla.solve(A.toarray() - 37.0 * np.eye(opA.n), C1[:, 0] * 0.5)
+    got = (sol.Z1.cpu().numpy() @ sol.Z2.cpu().numpy().T)[:, 0]
+    assert np.linalg.norm(got - x) <= 1e-10 * np.linalg.norm(x)
+
+
+def test_smallb_fp32_storage(lib):
+    """FP32 basis storage: converges; the explicit residual (FP64, on the
+    host) stays within a small factor of tol."""
+    opA = laplace2d(60)
+    B = fd1d_dense(40, 10.0)
+    A, C1, C2, sol = _case(opA, B, 3, 1e-6, storage=1)
+    assert sol.status == 0
+    ex = Y.explicit_residual(A, B, sol.Z1.cpu().numpy(), sol.Z2.cpu().numpy(), C1, C2) / (sol.beta1 * sol.beta2)
+    print(f"fp32 storage: m {sol.m}, reported {sol.res:.3e}, explicit {ex:.3e}")
+    assert ex <= 5e-6
+
+
+def test_smallb_errors(lib):
+    b = _b()
+    opA = laplace2d(10)
+    C1 = _dev(gaussian_C(opA.n, 2, 1))
+    dop = b.device_op(opA)
+    # B with a positive eigenvalue
+    Bpos = -_snd(6, 1)
+    with pytest.raises(b.LyapError) as e:
+        b.sylv_solve_small_b(dop, _dev(Bpos), C1, _dev(gaussian_C(6, 2, 2)))
+    assert e.value.status == b.E_INDEFINITE
+    # n2 above the limit
+    with pytest.raises(b.LyapError) as e:
+        b.sylv_solve_small_b(dop, _dev(-np.eye(2049)), C1, _dev(gaussian_C(2049, 2, 2)))
+    assert e.value.status == b.E_ARG
+    # s above the limit
+    C9 = _dev(gaussian_C(opA.n, 9, 1))
+    with pytest.raises(b.LyapError) as e:
+        b.sylv_solve_small_b(dop, _dev(-np.eye(4)), C9, _dev(gaussian_C(4, 9, 2)))
+    assert e.value.status == b.E_ARG
+    # extended Krylov is not built for this path
+    with pytest.raises(b.LyapError) as e:
+        b.sylv_solve_small_b(dop, _dev(-np.eye(4)), C1, _dev(gaussian_C(4, 2, 2)), method=b.METHOD_EXT)
+    assert e.value.status == b.E_UNSUPPORTED
+
+
+# ------------------------------------------------------------------ the paper's Example 5 sizes
+@pytest.mark.parametrize("s", [3, 8])
+def test_example5_against_oracle(lib, s):
+    b = _b()
+    orc = json.load(open(os.path.join(GOLD, "example5_oracle.json")))["cases"][str(s)]
+    N = 148
+    op = fd2d_variable(N, lambda x, y: np.exp(-x * y), lambda x, y: np.exp(x * y), "e1")
+    B = fd1d_dense(N, 10.0)
+    C1 = uniform_C(op.n, s, 0)
+    C2 = uniform_C(N, s, 1)
+    print(f"example 5 s={s}", flush=True)
+    sol = b.sylv_solve_small_b(b.device_op(op), _dev(B), _dev(C1), _dev(C2), tol=1e-6, check_every=1,
+                               storage=b.STORE_F64, two_pass=True)
+    assert sol.status == b.OK
+    assert sol.hist_m == list(range(1, sol.m + 1))
+    gh = dict(zip(sol.hist_m, sol.hist_res))
+    worst = 0.0
+    for m, res in orc["hist"]:
+        if m not in gh:
+            continue
+        dev = abs(gh[m] - res) / res
+        assert dev <= (1e-6 if m <= 40 else 0.15), (m, gh[m], res)
+        if m > 40:
+            worst = max(worst, dev)
+    print(f"  m {sol.m} (oracle {orc['m']}), t {sol.t} (oracle {orc['t']}), late deviation {worst:.3f}")
+    assert abs(sol.m - orc["m"]) <= 2
+    # sampled entries of X = Z1 Z2^T against the oracle's
+    Z1, Z2 = sol.Z1.cpu().numpy(), sol.Z2.cpu().numpy()
+    smp = np.array(orc["samples"])
+    ii, jj = smp[:, 0].astype(int), smp[:, 1].astype(int)
+    got = np.einsum("ka,ka->k", Z1[ii], Z2[jj])
+    dx = np.max(np.abs(got - smp[:, 2])) / orc["x_absmax_samples"]
+    print(f"  sampled X deviation {dx:.2e}")
+    assert dx <= 1e-6
+    ex = Y.explicit_residual(op.to_scipy(), B, Z1, Z2, C1, C2) / (sol.beta1 * sol.beta2)
+    print(f"  explicit residual {ex:.3e}, reported {sol.res:.3e}")
+    assert ex <= 1.2e-6
