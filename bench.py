@@ -56,7 +56,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=1000, help="grid side N (n = N^2)")
     ap.add_argument("--s", type=int, default=4)
-    ap.add_argument("--storage", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--storage", choices=["f32", "f64"], default=None,
+                    help="basis storage (default f32; f64 for smallb, whose uniform right-hand sides floor the "
+                         "true residual near 1e-4 with an f32 basis)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--explicit-residual", action="store_true", help="also report the explicit FP64 residual")
@@ -64,12 +66,17 @@ def parse():
                     help="ext workload: inner preconditioner (learned = trained in the run, time counted)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run one plain 256 MiB device copy (reference for the HBM byte counters)")
-    ap.add_argument("--workload", choices=["std", "ext", "sylv", "batch", "e1"], default="std",
+    ap.add_argument("--workload", choices=["std", "ext", "sylv", "batch", "e1", "e5", "smallb"], default="std",
                     help="std: standard Krylov + two-pass on the 2D Laplacian (the headline); "
                          "ext: extended Krylov + inner PCG on the 100^3 lognormal finite-volume operator; "
                          "sylv: Sylvester, 700^2 Laplacian and 80^3 lognormal FV, s=2; "
-                         "batch: 64 shifted Laplacians N_i in 64..512, s_i in {1,2,4}, grouped launches")
-    return ap.parse_args()
+                         "batch: 64 shifted Laplacians N_i in 64..512, s_i in {1,2,4}, grouped launches; "
+                         "e1 / e5: the paper's Examples 1 and 5 (FP64, residual at every step); "
+                         "smallb: Example 5's split on N^3 points (A: N^2 rows, B: N x N), FP64 basis by default")
+    args = ap.parse_args()
+    if args.storage is None:
+        args.storage = "f64" if args.workload == "smallb" else "f32"
+    return args
 
 
 def explicit_residual(b, dop, Z, C, beta2, storage_f64=True):
@@ -422,6 +429,75 @@ def main_e1(args):
     print(json.dumps(out), flush=True)
 
 
+PAPER_E5_TOTAL_S = {3: 6.51, 8: 16.35}   # Example 5, Table 7: cTri total CPU time, residual at every step
+PAPER_E5_RES_S = {3: 3.76, 8: 11.77}     # the residual-computation share of it
+
+
+def main_e5(args):
+    """The paper's Example 5 (Section 6): (exp(-xy) u_x)_x + (exp(xy) u_y)_y
+    + 10 u_zz on 148^3 interior points split as A X + X B (A: the x-y part,
+    n1 = 21904; B: 10 u_zz, n2 = 148), C1, C2 uniform (seeded) with unit norm,
+    tol 1e-6, residual (Algorithm 5) at every step, FP64, two-pass Z1; s = 3
+    and 8.  Workload smallb: the same split on N^3 points (--grid N; A: N^2
+    rows, B: N x N), --storage basis, adaptive checks, s = --s."""
+    import numpy as np
+    import torch
+    from paper_1602_05033_amd import binding as b
+    from workloads import fd1d_dense, fd2d_variable, uniform_C
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    b.load()
+    dev = torch.device("cuda:0")
+    paper = args.workload == "e5"
+    N = 148 if paper else args.grid
+    op = fd2d_variable(N, lambda x, y: np.exp(-x * y), lambda x, y: np.exp(x * y), "e5")
+    dop = b.device_op(op, device=dev)
+    Bd = torch.from_numpy(fd1d_dense(N, 10.0)).to(dev)
+    cases = []
+    for s in ((3, 8) if paper else (args.s,)):
+        C1 = torch.from_numpy(uniform_C(op.n, s, 0)).to(dev)
+        C2 = torch.from_numpy(uniform_C(N, s, 1)).to(dev)
+        if paper:
+            kw = dict(tol=1e-6, storage=b.STORE_F64, check_every=1, two_pass=True)
+        else:
+            kw = dict(tol=1e-6, storage=b.STORE_F32 if args.storage == "f32" else b.STORE_F64, check_every=0,
+                      two_pass=True, max_iter=20000)
+        for _ in range(args.warmup):
+            b.sylv_solve_small_b(dop, Bd, C1, C2, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            sol = b.sylv_solve_small_b(dop, Bd, C1, C2, **kw)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+        assert sol.status == b.OK, sol.status
+        c = {"s": s, "m": sol.m, "t": sol.t, "n_checks": sol.n_checks, "time_s": round(sec, 4),
+             "phases_ms": {k: round(v, 2) for k, v in sol.times_ms.items()}}
+        if paper:
+            c["paper_cpu_total_s"] = PAPER_E5_TOTAL_S[s]
+            c["paper_cpu_res_s"] = PAPER_E5_RES_S[s]
+        if args.explicit_residual:
+            from oracle import sylvester as Y
+            ex = Y.explicit_residual(op.to_scipy(), fd1d_dense(N, 10.0), sol.Z1.cpu().numpy(),
+                                     sol.Z2.cpu().numpy(), C1.cpu().numpy(), C2.cpu().numpy())
+            c["explicit_res"] = ex / (sol.beta1 * sol.beta2)
+        cases.append(c)
+        print(f"# s={s} m={sol.m} t={sol.t} {sec:.4f} s", file=sys.stderr, flush=True)
+    head = cases[0]
+    dt = "f64" if paper or args.storage == "f64" else "f32"
+    out = {
+        "metric": ("time to rel. residual 1e-6 on the paper's Example 5 (n1=21904, n2=148, s=3, residual at every "
+                   "step)") if paper else f"time to rel. residual 1e-6, large A / small B, N={N}, s={args.s}",
+        "value": head["time_s"], "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(head["time_s"] * 1000.0, 2), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": dt, "data": "synthetic",
+        "config": {"workload": f"Example 5 split: A = FD (exp(-xy)u_x)_x + (exp(xy)u_y)_y on {N}x{N}, B = 10 u_zz "
+                               f"on {N} points, C1, C2 uniform unit norm, tol 1e-6", "n1": op.n, "n2": N},
+        "result": {"cases": cases},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -432,6 +508,8 @@ def main():
         return main_copy()
     if args.workload == "e1":
         return main_e1(args)
+    if args.workload in ("e5", "smallb"):
+        return main_e5(args)
     if args.workload == "ext":
         return main_ext(args)
     if args.workload == "sylv":
