@@ -29,6 +29,9 @@ Modules
 ``smallb``  large A and small B (Section 5.2): one Krylov space, the
             one-sided Galerkin reduction, Algorithm 5, truncated Y~ and the
             factors Z1 = V_m Q Y1, Z2 = P Y2.
+``generalized`` A X E + E X A + C C^T = 0 with E symmetric positive definite,
+            by the Cholesky transformation to a standard equation (Section 6,
+            Example 3), and a dense Kronecker reference.
 ``pcg``     IC(0)/Jacobi preconditioned CG for the inner solves.
 ``cnn``     forward/backward of the small convolutional preconditioner.
 """

@@ -10,6 +10,7 @@ from .problems import (  # noqa: F401
     fv3d,
     fd2d_variable,
     fd1d_dense,
+    fe_p1_2d,
     gaussian_C,
     uniform_C,
     batch_c5,

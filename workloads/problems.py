@@ -10,6 +10,7 @@ Operators
               ``A[r,r] = cc``, ``A[r,nbr] = co`` for the four grid neighbours.
               ``laplace2d`` gives A = -(1/h^2)(I (x) T + T (x) I) - shift*I with
               T = tridiag(-1, 2, -1), h = 1/(N+1), zero Dirichlet boundary.
+``csr``       a general sparse matrix given by its CSR arrays (``fe_p1_2d``).
 ``stencil7``  variable-coefficient 7-point operator on Nx x Ny x Nz cells
               (Nz = 1 for 2D), given by per-cell arrays ``diag`` (the diagonal),
               ``tx``, ``ty``, ``tz`` (the coupling to the +x, +y, +z neighbour;
@@ -41,10 +42,13 @@ class Operator:
     ty: Optional[np.ndarray] = None
     tz: Optional[np.ndarray] = None
     meta: dict = field(default_factory=dict)
+    csr: Optional[tuple] = None    # kind "csr": (rowptr, col, val)
 
     # ------------------------------------------------------------------ CSR
     def to_csr(self):
         """Return (rowptr int64[n+1], col int32[nnz], val float64[nnz])."""
+        if self.kind == "csr":
+            return self.csr
         if self.kind == "stencil5":
             N = self.nx
             n = self.n
@@ -207,6 +211,60 @@ def fd1d_dense(N: int, a: float = 1.0) -> np.ndarray:
     B[i[:-1], i[:-1] + 1] = a / (h * h)
     B[i[:-1] + 1, i[:-1]] = a / (h * h)
     return B
+
+
+def fe_p1_2d(N: int):
+    """Linear (P1) finite elements on the unit square, N x N interior nodes,
+    h = 1/(N+1), every mesh square cut by its (i, j)-(i+1, j+1) diagonal, zero
+    Dirichlet boundary.  Returns (A, E) as CSR operators: A = -K (K the
+    stiffness matrix, so A is symmetric negative definite) and E = M (the
+    consistent mass matrix, symmetric positive definite), both assembled from
+    the element matrices; the pair of a semi-discrete heat equation
+    M x' = -K x + C u and of its generalized Lyapunov equation."""
+    import scipy.sparse as sp
+    h = 1.0 / (N + 1)
+    n = N * N
+    P = N + 2                                         # nodes per line, boundary included
+    gi, gj = np.meshgrid(np.arange(N + 1), np.arange(N + 1), indexing="xy")
+    gi, gj = gi.ravel(), gj.ravel()
+    node = lambda i, j: i + P * j                     # noqa: E731
+    tris = np.concatenate([
+        np.stack([node(gi, gj), node(gi + 1, gj), node(gi + 1, gj + 1)], axis=1),
+        np.stack([node(gi, gj), node(gi + 1, gj + 1), node(gi, gj + 1)], axis=1)])
+    # reference element: right triangle with legs h
+    Ke = np.array([[1.0, -1.0, 0.0], [-1.0, 2.0, -1.0], [0.0, -1.0, 1.0]])
+    Ke2 = np.array([[1.0, 0.0, -1.0], [0.0, 1.0, -1.0], [-1.0, -1.0, 2.0]])
+    Me = (h * h / 24.0) * np.array([[2.0, 1.0, 1.0], [1.0, 2.0, 1.0], [1.0, 1.0, 2.0]])
+    nt = tris.shape[0] // 2
+    rows, cols, kv, mv = [], [], [], []
+    for t_rng, Kloc in ((slice(0, nt), Ke), (slice(nt, 2 * nt), Ke2)):
+        T = tris[t_rng]
+        for a in range(3):
+            for b in range(3):
+                rows.append(T[:, a])
+                cols.append(T[:, b])
+                kv.append(np.full(T.shape[0], 0.5 * Kloc[a, b]))
+                mv.append(np.full(T.shape[0], Me[a, b]))
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    ii, jj = r % P, r // P
+    ic, jc = c % P, c // P
+    inner = (ii >= 1) & (ii <= N) & (jj >= 1) & (jj <= N) & (ic >= 1) & (ic <= N) & (jc >= 1) & (jc <= N)
+    ri = (ii - 1) + N * (jj - 1)
+    ci = (ic - 1) + N * (jc - 1)
+    K = sp.csr_matrix((np.concatenate(kv)[inner], (ri[inner], ci[inner])), shape=(n, n))
+    M = sp.csr_matrix((np.concatenate(mv)[inner], (ri[inner], ci[inner])), shape=(n, n))
+    out = []
+    for mat in (-K, M):
+        mat = mat.tocsr()
+        mat.sum_duplicates()
+        mat.sort_indices()
+        mat.eliminate_zeros()
+        out.append(Operator(kind="csr", n=n, nx=N, ny=N, nz=1, h=h,
+                            csr=(mat.indptr.astype(np.int64), mat.indices.astype(np.int32),
+                                 mat.data.astype(np.float64)),
+                            meta={"name": "fe_p1_2d", "N": N}))
+    return out[0], out[1]
 
 
 # ----------------------------------------------------------- right-hand sides
