@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--grid", type=int, default=1000, help="grid side N (n = N^2)")
+    ap.add_argument("--grid", type=int, default=None, help="grid side N (n = N^2; default 1000, gen 300)")
     ap.add_argument("--s", type=int, default=4)
     ap.add_argument("--storage", choices=["f32", "f64"], default=None,
                     help="basis storage (default f32; f64 for smallb, whose uniform right-hand sides floor the "
@@ -66,14 +66,17 @@ def parse():
                     help="ext workload: inner preconditioner (learned = trained in the run, time counted)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run one plain 256 MiB device copy (reference for the HBM byte counters)")
-    ap.add_argument("--workload", choices=["std", "ext", "sylv", "batch", "e1", "e5", "smallb"], default="std",
+    ap.add_argument("--workload", choices=["std", "ext", "sylv", "batch", "e1", "e5", "smallb", "gen"], default="std",
                     help="std: standard Krylov + two-pass on the 2D Laplacian (the headline); "
                          "ext: extended Krylov + inner PCG on the 100^3 lognormal finite-volume operator; "
                          "sylv: Sylvester, 700^2 Laplacian and 80^3 lognormal FV, s=2; "
                          "batch: 64 shifted Laplacians N_i in 64..512, s_i in {1,2,4}, grouped launches; "
                          "e1 / e5: the paper's Examples 1 and 5 (FP64, residual at every step); "
-                         "smallb: Example 5's split on N^3 points (A: N^2 rows, B: N x N), FP64 basis by default")
+                         "smallb: Example 5's split on N^3 points (A: N^2 rows, B: N x N), FP64 basis by default; "
+                         "gen: generalized A X E + E X A + C C^T = 0, P1 finite elements on N^2 nodes (N = 300)")
     args = ap.parse_args()
+    if args.grid is None:
+        args.grid = 300 if args.workload == "gen" else 1000
     if args.storage is None:
         args.storage = "f64" if args.workload == "smallb" else "f32"
     return args
@@ -498,6 +501,53 @@ def main_e5(args):
     print(json.dumps(out), flush=True)
 
 
+def main_gen(args):
+    """Generalized Lyapunov equation A X E + E X A + C C^T = 0 (Section 6,
+    Example 3's reduction for SPD E): P1 finite elements on the unit square
+    with N x N interior nodes (A = -stiffness, E = mass, both CSR), C n x 4
+    Gaussian, tol 1e-8, FP64, adaptive checks, two-pass Z (the inner solves
+    with E repeated)."""
+    import numpy as np
+    import torch
+    from paper_1602_05033_amd import binding as b
+    from workloads import fe_p1_2d, gaussian_C
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    b.load()
+    dev = torch.device("cuda:0")
+    Ao, Eo = fe_p1_2d(args.grid)
+    dA, dE = b.device_op(Ao, device=dev), b.device_op(Eo, device=dev)
+    Cd = torch.from_numpy(gaussian_C(Ao.n, args.s, 9)).to(dev)
+    kw = dict(tol=1e-8, storage=b.STORE_F64, check_every=0, two_pass=True)
+    for _ in range(args.warmup):
+        b.lyap_solve_gen(dA, dE, Cd, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sol = b.lyap_solve_gen(dA, dE, Cd, **kw)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    assert sol.status == b.OK, sol.status
+    res = {"m": sol.m, "t": sol.t, "n_checks": sol.n_checks, "inner_iters": sol.inner_iters, "n_inner": sol.n_inner,
+           "phases_ms": {k: round(v, 2) for k, v in sol.times_ms.items()}}
+    if args.explicit_residual:
+        from oracle import generalized as G
+        A, E = Ao.to_scipy(), Eo.to_scipy()
+        ex = G.explicit_residual(A, E, sol.Z.cpu().numpy(), Cd.cpu().numpy())
+        res["explicit_res_untransformed"] = ex
+        res["bound_lmaxE_tol_beta2"] = float(np.max(np.abs(E).sum(axis=1))) * 1e-8 * sol.beta ** 2
+    out = {
+        "metric": f"time to transformed rel. residual 1e-8, generalized Lyapunov (P1 FE, n={Ao.n}, s={args.s})",
+        "value": round(sec, 4), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(sec * 1000.0, 2), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"A X E + E X A + C C^T = 0, P1 FE stiffness/mass on {args.grid}x{args.grid} nodes, "
+                               f"C Gaussian, tol 1e-8", "n": Ao.n, "s": args.s},
+        "result": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -510,6 +560,8 @@ def main():
         return main_e1(args)
     if args.workload in ("e5", "smallb"):
         return main_e5(args)
+    if args.workload == "gen":
+        return main_gen(args)
     if args.workload == "ext":
         return main_ext(args)
     if args.workload == "sylv":

@@ -254,6 +254,30 @@ lyap_status sylv_solve(const lyap_op* A, const lyap_op* B, const double* C1, int
                        sylv_result* out);
 
 /*
+ * lyap_solve_gen — the generalized equation A X E + E X A + C C^T = 0 with E
+ * symmetric positive definite, treated as the standard equation of
+ * L^{-1} A L^{-T} and L^{-1} C (E = L L^T; Section 6, Example 3) without
+ * forming L: block Lanczos for E^{-1} A in the E inner product (basis W with
+ * W^T E W = I), one FP64 conjugate-gradient solve with E per step (Jacobi
+ * preconditioned unless inner_pc = LYAP_PC_NONE; accepted on the true relative
+ * residual <= inner_tol), Proposition 1 on T_m, truncation and Z = W_m M as in
+ * lyap_solve, so Z Z^T approximates X.
+ *  A     operator, symmetric negative definite; E operator (any kind),
+ *        symmetric positive definite, same n.
+ *  C     device, n x s column-major FP64 (ldc >= n); s = 1, 2 or 4.
+ *  opts  method STD, storage F64 only (E_UNSUPPORTED otherwise); two_pass = 1
+ *        repeats the steps (inner solves included) to form Z, two_pass = 0
+ *        keeps every block.  tol applies to the transformed residual
+ *        ||L^{-1} R L^{-T}||_F / ||L^{-1} C||_F^2, R = A X E + E X A + C C^T
+ *        (out->beta = ||L^{-1} C||_F, out->hist_res the same ratio).
+ *  out   as lyap_solve, with inner_iters / n_inner counting the E solves.
+ * Errors: E_ARG, E_INNER (an E solve missed inner_tol), E_INDEFINITE (a Ritz
+ * value >= 0 or a diagonal entry of E <= 0), E_BREAKDOWN, E_NUMERIC.
+ */
+lyap_status lyap_solve_gen(const lyap_op* A, const lyap_op* E, const double* C, int32_t s, int64_t ldc,
+                           const lyap_opts* opts, lyap_result* out);
+
+/*
  * sylv_solve_small_b — AX + XB + C1 C2^T = 0 with A large and sparse and B
  * small and dense (Section 5.2, "Large A and small B").  Only A is projected:
  * X_m = V_m Y_m with V_m a basis of K_m(A, C1) and the one-sided Galerkin

@@ -78,7 +78,7 @@ class SylvResult(ct.Structure):
 EXPORTS = ["lyap_opts_default", "lyap_solve", "sylv_solve", "lyap_result_free", "sylv_result_free",
            "lyap_last_error", "lyap_op_apply", "lyap_op_apply_timed", "lyap_ctri", "lyap_inner_solve",
            "lyap_solve_batched", "lyap_pcnet_init", "lyap_pcnet_apply", "lyap_pcnet_grad", "lyap_pcnet_train",
-           "lyap_pcnet_fcg", "sylv_solve_small_b", "lyap_sym_eig"]
+           "lyap_pcnet_fcg", "sylv_solve_small_b", "lyap_sym_eig", "lyap_solve_gen"]
 
 
 class LyapError(RuntimeError):
@@ -108,6 +108,9 @@ def load(path: str = LIB_PATH):
     lib.sylv_solve.restype = ct.c_int
     lib.lyap_result_free.argtypes = [ct.POINTER(LyapResult)]
     lib.lyap_result_free.restype = None
+    lib.lyap_solve_gen.argtypes = [ct.POINTER(LyapOp), ct.POINTER(LyapOp), ct.c_void_p, ct.c_int32, ct.c_int64,
+                                   ct.POINTER(LyapOpts), ct.POINTER(LyapResult)]
+    lib.lyap_solve_gen.restype = ct.c_int
     lib.sylv_solve_small_b.argtypes = [ct.POINTER(LyapOp), ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_void_p,
                                        ct.c_int64, ct.c_void_p, ct.c_int64, ct.c_int32, ct.POINTER(LyapOpts),
                                        ct.POINTER(SylvResult)]
@@ -176,7 +179,7 @@ def device_op(op, device="cuda", as_csr: bool = False, shift: float = 0.0) -> De
     c.nx, c.ny, c.nz = op.nx, op.ny, op.nz
     c.shift = shift
     keep = []
-    if as_csr:
+    if as_csr or op.kind == "csr":
         rp, ci, va = op.to_csr()
         trp = torch.from_numpy(rp).to(device)
         tci = torch.from_numpy(ci).to(device)
@@ -281,6 +284,29 @@ def lyap_solve(dop: DeviceOp, C, raise_on_error: bool = True, **kw) -> LyapSolut
     o.alloc, o.release = alloc.alloc_cb, alloc.free_cb
     r = LyapResult()
     st = lib.lyap_solve(ct.byref(dop.c), ct.c_void_p(Ccm.data_ptr()), s, n, ct.byref(o), ct.byref(r))
+    msg = lib.lyap_last_error().decode()
+    try:
+        if raise_on_error and st not in (OK, NOT_CONVERGED):
+            raise LyapError(st, msg)
+        return _solution(r, st, alloc, n, C.device, msg)
+    finally:
+        lib.lyap_result_free(ct.byref(r))
+
+
+def lyap_solve_gen(dopA: DeviceOp, dopE: DeviceOp, C, raise_on_error: bool = True, **kw) -> LyapSolution:
+    """Solve A X E + E X A + C C^T = 0 (E symmetric positive definite).  ``C``
+    is an (n, s) float64 device tensor, s in {1, 2, 4}; Z (n, t), Z Z^T ~ X."""
+    import torch
+    lib = load()
+    n, s = C.shape
+    assert n == dopA.n == dopE.n and C.dtype == torch.float64 and C.is_cuda
+    Ccm = C.t().contiguous()
+    alloc = _TorchAllocator(C.device)
+    o = make_opts(stream=torch.cuda.current_stream(C.device).cuda_stream, **kw)
+    o.alloc, o.release = alloc.alloc_cb, alloc.free_cb
+    r = LyapResult()
+    st = lib.lyap_solve_gen(ct.byref(dopA.c), ct.byref(dopE.c), ct.c_void_p(Ccm.data_ptr()), s, n, ct.byref(o),
+                            ct.byref(r))
     msg = lib.lyap_last_error().decode()
     try:
         if raise_on_error and st not in (OK, NOT_CONVERGED):

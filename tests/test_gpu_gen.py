@@ -1,0 +1,129 @@
+"""GPU parity of lyap_solve_gen (A X E + E X A + C C^T = 0, E symmetric
+positive definite; Section 6, Example 3): the E-inner-product block Lanczos
+with one FP64 CG solve with E per step, against the CPU oracle's Cholesky-
+transformed run on the same seeded inputs (P1 finite-element stiffness and
+mass matrices), the stored and regenerated bases, the E = I special case,
+the error paths, and a larger mesh checked by the untransformed residual."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from workloads import fe_p1_2d, laplace2d, gaussian_C
+from oracle import dense as D
+from oracle import generalized as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _b():
+    from paper_1602_05033_amd import binding
+    return binding
+
+
+def _dev(C):
+    return torch.from_numpy(np.ascontiguousarray(C)).cuda()
+
+
+@pytest.mark.parametrize("s", [1, 2, 4])
+def test_gen_parity(lib, s):
+    b = _b()
+    Ao, Eo = fe_p1_2d(30)                      # n = 900, CSR A and E
+    A, E = Ao.to_scipy(), Eo.to_scipy()
+    C = gaussian_C(Ao.n, s, 5)
+    print(f"gen parity s={s}", flush=True)
+    sol = b.lyap_solve_gen(b.device_op(Ao), b.device_op(Eo), _dev(C), tol=1e-9, check_every=1, want_T=True)
+    ref = G.lyap_gen(A, E, C, tol=1e-9, check_every=1)
+    assert sol.status == b.OK and ref.std.converged
+    assert abs(sol.m - ref.std.m) <= 1, (sol.m, ref.std.m)
+    assert abs(sol.beta - ref.std.beta) <= 1e-12 * ref.std.beta
+    for h in ref.std.hist:
+        if h["m"] in sol.hist_m:
+            g = sol.hist_res[sol.hist_m.index(h["m"])]
+            # inner solves to 1e-12 and the loss of orthogonality separate late histories
+            tolr = 1e-7 if h["m"] <= 20 else 0.15
+            assert abs(g - h["res"]) <= tolr * h["res"], (h["m"], g, h["res"])
+    k = s * sol.m
+    for c in range(min(k, 4 * s)):
+        for d in range(s + 1):
+            if c + d < k:
+                assert abs(sol.T_band[c, d] - ref.std.T[c + d, c]) <= 1e-9 * np.abs(ref.std.T).max()
+    Z = sol.Z.cpu().numpy()
+    # dense X from the transformed equation diagonalised (n = 900)
+    At, Ct, L = G.transform(A, E, C)
+    Xt = D.lyap_eig(At, Ct)
+    X = sla.solve_triangular(L.T, sla.solve_triangular(L.T, Xt, lower=False).T, lower=False).T
+    nX = np.linalg.norm(X)
+    err = np.linalg.norm(Z @ Z.T - X) / nX
+    err_ref = np.linalg.norm(ref.Z @ ref.Z.T - X) / nX
+    print(f"  m {sol.m} (oracle {ref.std.m}), t {sol.t}, error {err:.2e} (oracle {err_ref:.2e}), "
+          f"inner iterations {sol.inner_iters} in {sol.n_inner} solves")
+    assert err <= 10 * err_ref + 1e-10
+    ex = G.explicit_residual(A, E, Z, C)
+    Li = sla.solve_triangular(L, np.eye(Ao.n), lower=True)
+    R = A @ (Z @ Z.T) @ E + E @ (Z @ Z.T) @ A + C @ C.T
+    rt = np.linalg.norm(Li @ R @ Li.T) / sol.beta ** 2
+    assert abs(ex - np.linalg.norm(R)) <= 1e-10 * np.linalg.norm(C) ** 2
+    assert rt <= 1.2e-9
+
+
+def test_gen_two_pass_equals_stored(lib):
+    b = _b()
+    Ao, Eo = fe_p1_2d(25)
+    C = _dev(gaussian_C(Ao.n, 2, 6))
+    s1 = b.lyap_solve_gen(b.device_op(Ao), b.device_op(Eo), C, tol=1e-8, two_pass=True)
+    s2 = b.lyap_solve_gen(b.device_op(Ao), b.device_op(Eo), C, tol=1e-8, two_pass=False)
+    assert s1.m == s2.m and s1.t == s2.t
+    # the second pass repeats every step (inner solves included) bit for bit
+    assert torch.equal(s1.Z, s2.Z)
+    assert s1.n_inner == 2 * s2.n_inner - 1
+
+
+def test_gen_identity_mass_matches_lyap_solve(lib):
+    b = _b()
+    op = laplace2d(30)
+    eye = laplace2d(30)
+    eye.cc, eye.co = 1.0, 0.0
+    C = _dev(gaussian_C(op.n, 2, 7))
+    g = b.lyap_solve_gen(b.device_op(op), b.device_op(eye), C, tol=1e-9, check_every=1)
+    s = b.lyap_solve(b.device_op(op), C, tol=1e-9, check_every=1, storage=b.STORE_F64)
+    assert g.m == s.m
+    Zg, Zs = g.Z.cpu().numpy(), s.Z.cpu().numpy()
+    Xs = Zs @ Zs.T
+    assert np.linalg.norm(Zg @ Zg.T - Xs) <= 1e-9 * np.linalg.norm(Xs)
+    for a, c in zip(g.hist_res[:10], s.hist_res[:10]):
+        assert abs(a - c) <= 1e-9 * c
+
+
+def test_gen_errors(lib):
+    b = _b()
+    Ao, Eo = fe_p1_2d(10)
+    dA, dE = b.device_op(Ao), b.device_op(Eo)
+    with pytest.raises(b.LyapError) as e:
+        b.lyap_solve_gen(dA, dE, _dev(gaussian_C(Ao.n, 3, 1)))
+    assert e.value.status == b.E_ARG
+    with pytest.raises(b.LyapError) as e:
+        b.lyap_solve_gen(dA, dE, _dev(gaussian_C(Ao.n, 2, 1)), storage=b.STORE_F32)
+    assert e.value.status == b.E_UNSUPPORTED
+    neg = laplace2d(10)                       # symmetric negative definite: not a mass matrix
+    with pytest.raises(b.LyapError) as e:
+        b.lyap_solve_gen(dA, b.device_op(neg), _dev(gaussian_C(Ao.n, 2, 1)))
+    assert e.value.status == b.E_INDEFINITE
+
+
+def test_gen_larger_mesh_untransformed_residual(lib):
+    """n = 90000: ||R||_F <= lambda_max(E) ||L^{-1} R L^{-T}||_F, with
+    lambda_max(E) bounded by the largest absolute row sum of E."""
+    b = _b()
+    Ao, Eo = fe_p1_2d(300)
+    C = gaussian_C(Ao.n, 4, 8)
+    print("gen n=90000 s=4", flush=True)
+    sol = b.lyap_solve_gen(b.device_op(Ao), b.device_op(Eo), _dev(C), tol=1e-8)
+    assert sol.status == b.OK
+    A, E = Ao.to_scipy(), Eo.to_scipy()
+    ex = G.explicit_residual(A, E, sol.Z.cpu().numpy(), C)
+    lmax = float(np.max(np.abs(E).sum(axis=1)))
+    print(f"  m {sol.m}, t {sol.t}, inner {sol.inner_iters} in {sol.n_inner}, ||R|| {ex:.3e}, bound "
+          f"{lmax * 1.2e-8 * sol.beta ** 2:.3e}, {sol.times_ms['total']:.0f} ms")
+    assert ex <= lmax * 1.2e-8 * sol.beta ** 2
