@@ -43,9 +43,12 @@ struct StepArgs {
   int* flags;        // [0] first breakdown step+1, [1] first non-finite step+1
 };
 
-// Workgroups of the streaming kernels for an n-row block (<= 256, one per CU).
+// Workgroups of the streaming kernels for an n-row block: one per CU (256)
+// from n = 65536 up; below that one per 256 rows, so that a small block still
+// spreads over many CUs (these kernels wait on memory latency, not bandwidth,
+// at such sizes) instead of filling a few workgroups of 1024 threads.
 inline int stream_grid(int64_t n) {
-  int64_t g = (n + 2 * (int64_t)kSBlock - 1) / (2 * (int64_t)kSBlock);
+  int64_t g = (n + 255) / 256;
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, kSGrid));
 }
 

@@ -116,6 +116,13 @@ __global__ __launch_bounds__(NT) void k_cg_dir(OpDev<double> op, const double* _
       log[it].rr[c] = rr[c];
     }
   }
+  // Every column converged (the rest of the host's iteration chunk): x and r
+  // stay as they are, so nothing below would change, and the partials of the
+  // last update still hold r's sums for the next iteration.
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < S; ++c) any = any || mask[c] > 0.0;
+  if (!any) return;
   const double* po = it > 0 ? pold : nullptr;
   double acc[S];
 #pragma unroll
@@ -159,6 +166,10 @@ __global__ __launch_bounds__(NT) void k_cg_upd(double* __restrict__ x, double* _
     }
   }
   __syncthreads();
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < S; ++c) any = any || uniform_d(log[it].rr[c]) > uniform_d(state[c]);
+  if (!any) return;  // see k_cg_dir
   double acc[2 * S];
 #pragma unroll
   for (int c = 0; c < 2 * S; ++c) acc[c] = 0.0;

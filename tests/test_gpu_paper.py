@@ -43,6 +43,8 @@ def test_example1_against_oracle_and_table1(lib, s):
     gh = dict(zip(sol.hist_m, sol.hist_res))
     worst = 0.0
     for m, res in orc["hist"]:
+        if m not in gh:          # past the GPU run's own stop (m* is compared below)
+            continue
         dev = abs(gh[m] - res) / res
         assert dev <= (1e-6 if m <= 40 else 0.15), (m, gh[m], res)
         if m > 40:
