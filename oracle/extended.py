@@ -160,3 +160,47 @@ def _assemble(Tblocks, m: int, ell: int) -> np.ndarray:
             T[j * ell:(j + 1) * ell, (j - 1) * ell:j * ell] = B
             T[(j - 1) * ell:j * ell, j * ell:(j + 1) * ell] = B.T
     return T
+
+
+class EKSide:
+    """One extended Krylov space EK_m(A, C) advanced one block at a time with
+    the same operations as ``lyap_ext`` (steps 1-4 above), for drivers that
+    couple two spaces (the Sylvester equation, Section 5.1 with extended
+    spaces)."""
+
+    def __init__(self, A, C: np.ndarray, solve: Optional[Callable] = None):
+        self.A = A
+        self.s = C.shape[1]
+        self.ell = 2 * self.s
+        self.solve = solve if solve is not None else lu_solver(A)
+        self.beta = float(np.linalg.norm(C))
+        V1, self.gamma, _ = start_block(A, C, self.solve)
+        self.basis = [V1]
+        self.Tblocks = {}
+        self.m = 0
+
+    def step(self):
+        s = self.s
+        j = self.m + 1
+        Vj = self.basis[-1]
+        AVj = self.A @ Vj
+        W = np.concatenate([AVj[:, :s], self.solve(Vj[:, s:])], axis=1)
+        W = orthogonalise_full(W, self.basis)
+        _, R = qr_pos(W)
+        Vn = right_solve_upper(W, R)
+        self.basis.append(Vn)
+        Tjj = Vj.T @ AVj
+        self.Tblocks[(j, j)] = 0.5 * (Tjj + Tjj.T)
+        self.Tblocks[(j + 1, j)] = Vn.T @ AVj
+        self.m = j
+
+    def T(self, m: Optional[int] = None) -> np.ndarray:
+        """T_m as formed (full); ``band_of`` gives the banded one."""
+        return _assemble(self.Tblocks, self.m if m is None else m, self.ell)
+
+    def tau(self, m: Optional[int] = None) -> np.ndarray:
+        m = self.m if m is None else m
+        return self.Tblocks[(m + 1, m)]
+
+    def Vm(self, m: Optional[int] = None) -> np.ndarray:
+        return np.concatenate(self.basis[:self.m if m is None else m], axis=1)

@@ -207,3 +207,50 @@ def explicit_residual(A, B, Z1: np.ndarray, Z2: np.ndarray, C1: np.ndarray, C2: 
 
 def lowrank_error(Z1, Z2, X) -> float:
     return float(np.linalg.norm(Z1 @ Z2.T - X) / np.linalg.norm(X))
+
+
+def sylv_ext(A, B, C1: np.ndarray, C2: np.ndarray, tol: float = 1e-8, max_iter: int = 200,
+             solveA: Optional[Callable] = None, solveB: Optional[Callable] = None, check_every: int = 1,
+             check: Optional[Callable[[int], bool]] = None) -> SylvResult:
+    """Section 5.1 with the two extended spaces EK_m(A, C1), EK_m(B, C2) (the
+    generalisation the paper calls obvious): T_m and J_m formed as in
+    ``extended.lyap_ext`` (ell = 2s), the corrected Algorithm 4 with the first
+    s rows of tau_{m+1,m} and iota_{m+1,m} (their lower rows vanish in exact
+    arithmetic, Section 4), TSVD, Z1 = V_m Q Y1 and Z2 = U_m P Y2 from the
+    stored bases."""
+    from .extended import EKSide, band_of
+    s = C1.shape[1]
+    ell = 2 * s
+    sa = EKSide(A, C1, solveA)
+    sb = EKSide(B, C2, solveB)
+    beta1, beta2 = sa.beta, sb.beta
+    if check is None:
+        check = lambda m: (m % check_every) == 0  # noqa: E731
+    hist = []
+    converged = False
+    alg4 = None
+    m = 0
+    for j in range(1, max_iter + 1):
+        sa.step()
+        sb.step()
+        m = j
+        if check(j) or j == max_iter:
+            alg4 = residual_alg4(band_of(sa.T(), ell), band_of(sb.T(), ell), sa.gamma, sb.gamma,
+                                 sa.tau()[:s, :], sb.tau()[:s, :])
+            rr = alg4.res / (beta1 * beta2)
+            hist.append({"m": j, "res": rr})
+            if rr <= tol:
+                converged = True
+                break
+    T, Jm = band_of(sa.T(m), ell), band_of(sb.T(m), ell)
+    tau, iota = sa.tau(m), sb.tau(m)
+    if alg4 is None or alg4.lam.shape[0] != T.shape[0]:
+        alg4 = residual_alg4(T, Jm, sa.gamma, sb.gamma, tau[:s, :], iota[:s, :])
+    nu = (np.max(np.abs(alg4.lam)) + np.linalg.norm(tau) + np.max(np.abs(alg4.ups)) + np.linalg.norm(iota))
+    eps = min(1e-12, 0.05 * tol / nu) * beta1 * beta2
+    M1, M2, sv = tsvd_factors(alg4.lam, alg4.Q, alg4.ups, alg4.P, alg4.g1, alg4.g2, eps)
+    Z1 = sa.Vm(m) @ M1
+    Z2 = sb.Vm(m) @ M2
+    return SylvResult(Z1=Z1, Z2=Z2, m=m, t=M1.shape[1], hist=hist, converged=converged, T=T, J=Jm,
+                      gamma1=sa.gamma, gamma2=sb.gamma, tau=tau, iota=iota, beta1=beta1, beta2=beta2,
+                      status="ok" if converged else "not_converged", extra={"eps": eps, "sv": sv})

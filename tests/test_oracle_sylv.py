@@ -89,3 +89,65 @@ def test_tsvd_error_bound(case):
         M1, M2, _ = S.tsvd_factors(al.lam, al.Q, al.ups, al.P, al.g1, al.g2, eps)
         approx = al.Q.T @ M1 @ (al.P.T @ M2).T
         assert np.linalg.norm(Yt - approx) <= eps * (1 + 1e-8)
+
+
+# ------------------------------------------------------------------ extended spaces (Section 5.1 with Section 4)
+@pytest.fixture(scope="module")
+def ext_case():
+    A = laplace2d(12).to_scipy()
+    B = fv3d(5, 0.5, 4).to_scipy()
+    C1 = gaussian_C(A.shape[0], 2, 14)
+    C2 = gaussian_C(B.shape[0], 2, 15)
+    return A, B, C1, C2
+
+
+def test_sylv_ext_against_dense(ext_case):
+    A, B, C1, C2 = ext_case
+    r = Y.sylv_ext(A, B, C1, C2, tol=1e-9)
+    assert r.converged
+    X = D.sylv_eig(A.toarray(), B.toarray(), C1, C2)
+    assert Y.lowrank_error(r.Z1, r.Z2, X) <= 1e-8
+    ex = Y.explicit_residual(A, B, r.Z1, r.Z2, C1, C2) / (r.beta1 * r.beta2)
+    assert ex <= 1.2e-9
+    # extended spaces need fewer blocks than the standard ones on this pair
+    assert r.m < Y.sylv_std(A, B, C1, C2, tol=1e-9).m
+
+
+def test_sylv_ext_alg4_with_tau_bar_equals_reduced_and_explicit(ext_case):
+    from oracle.extended import EKSide, band_of
+    A, B, C1, C2 = ext_case
+    s, m = 2, 4
+    sa, sb = EKSide(A, C1), EKSide(B, C2)
+    for _ in range(m):
+        sa.step()
+        sb.step()
+    T, J = band_of(sa.T(), 2 * s), band_of(sb.T(), 2 * s)
+    a4 = Y.residual_alg4(T, J, sa.gamma, sb.gamma, sa.tau()[:s, :], sb.tau()[:s, :])
+    rr = Y.residual_reduced(T, J, sa.gamma, sb.gamma, sa.tau(), sb.tau())
+    assert abs(a4.res - rr) <= 1e-8 * rr
+    Yr = Y.reduced_solution(T, J, sa.gamma, sb.gamma)
+    X = sa.Vm() @ Yr @ sb.Vm().T
+    R = A @ X + X @ B + C1 @ C2.T
+    assert abs(np.linalg.norm(R) - a4.res) <= 1e-7 * a4.res
+
+
+def test_sylv_ext_lyapunov_special_case():
+    from oracle.extended import lyap_ext
+    A = laplace2d(12).to_scipy()
+    C = gaussian_C(A.shape[0], 2, 16)
+    r = Y.sylv_ext(A, A, C, C, tol=1e-9)
+    q = lyap_ext(A, C, tol=1e-9)
+    assert r.m == q.m
+    Xq = q.Z @ q.Z.T
+    assert np.linalg.norm(r.Z1 @ r.Z2.T - Xq) <= 1e-9 * np.linalg.norm(Xq)
+
+
+def test_ek_side_matches_lyap_ext():
+    from oracle.extended import EKSide, lyap_ext
+    A = laplace2d(10).to_scipy()
+    C = gaussian_C(A.shape[0], 1, 17)
+    q = lyap_ext(A, C, tol=1e-30, max_iter=5, check=lambda j: False)
+    e = EKSide(A, C)
+    for _ in range(5):
+        e.step()
+    assert np.array_equal(e.T(), q.T) and np.array_equal(e.tau(), q.tau) and np.array_equal(e.gamma, q.gamma)
