@@ -248,6 +248,11 @@ typedef struct sylv_result {
  * two diagonal matrices D'_i, D''_i taken as lambda_i I + Upsilon and
  * upsilon_j I + Lambda so that it agrees with eq. (resSylv)).  Z1 Z2^T
  * approximates X.  C1 is n1 x s, C2 is n2 x s (device, column-major FP64).
+ * opts->method = LYAP_METHOD_EXT builds the two extended spaces EK_m(A, C1),
+ * EK_m(B, C2) instead (Section 4's spaces in Section 5.1's method; ell = 2s,
+ * Algorithm 4 with the first s rows of tau and iota, factors from the stored
+ * bases): s = 1, 2 or 4, FP64 storage, inner CG with inner_pc NONE or JACOBI
+ * on each operator (E_UNSUPPORTED otherwise).
  */
 lyap_status sylv_solve(const lyap_op* A, const lyap_op* B, const double* C1, int64_t ldc1,
                        const double* C2, int64_t ldc2, int32_t s, const lyap_opts* opts,

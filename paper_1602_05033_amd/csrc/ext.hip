@@ -25,6 +25,7 @@
 #include "pcnet.hpp"
 #include "small.hpp"
 #include "solver.hpp"
+#include "sylv.hpp"
 
 namespace lyap {
 
@@ -249,6 +250,153 @@ void cholqr2(ExtWork& w, const double* const* wlist, double* W, const double* co
   LYAP_LAUNCHED("cholqr2");
 }
 
+// One extended Krylov space EK_m(A, C) on the device: the operator, its inner
+// CG, the stored basis, T_m's band, the tau log and the flags.  lyap_solve
+// (method EXT) drives one, sylv_solve (method EXT) two in lockstep.
+template <int S>
+class ExtSide {
+ public:
+  static constexpr int L = 2 * S;
+  static constexpr int LL = L * L;
+
+  ExtSide(const lyap_op* A, const lyap_opts& o, hipStream_t st, KernelTimer* kt) : st_(st), kt_(kt) {
+    n_ = (int)A->n;
+    maxit_ = o.max_iter;
+    make_op_f64(A, op_, st);
+    cg_.reset(new InnerCG(op_.dev, n_, S, o.inner_pc, o.inner_tol, o.inner_max_iter, st));
+    blkL_ = (size_t)n_ * L * sizeof(double);
+    blkS_ = (size_t)n_ * S * sizeof(double);
+    eg_ = grid_for(n_, 1, 1024);
+    w_.n = n_;
+    w_.S = S;
+    w_.L = L;
+    w_.G = stream_grid(n_);
+    w_.st = st;
+    w_.small.alloc(9 * LL * sizeof(double));
+    w_.flags.alloc(64);
+    LYAP_HIP(hipMemsetAsync(w_.flags.p, 0, 64, st));
+    V_.reserve((size_t)maxit_ + 2);
+    ptrs_.alloc(((size_t)maxit_ + 2) * sizeof(void*));
+    wlist_.alloc(sizeof(void*));
+    AV_.alloc(blkL_);
+    W_.alloc(blkL_);
+    Bs_.alloc(blkS_);
+    Xs_.alloc(blkS_);
+    band_.alloc((size_t)(L + 1) * L * (maxit_ + 2) * sizeof(double));
+    taulog_.alloc(((size_t)maxit_ + 1) * LL * sizeof(double));
+    R0_.alloc(LL * sizeof(double));
+    gamma_.alloc(LL * sizeof(double));
+    LYAP_HIP(hipMemsetAsync(band_.p, 0, band_.bytes, st));
+    const void* wp = W_.p;
+    LYAP_HIP(hipMemcpy(wlist_.p, &wp, sizeof(void*), hipMemcpyHostToDevice));
+  }
+
+  InnerCG& cg() { return *cg_; }
+  const OpHolder<double>& op() const { return op_; }
+  int n() const { return n_; }
+  int m() const { return m_; }
+  double beta() const { return beta_; }
+  const double* band() const { return band_.as<double>(); }
+  const double* gamma() const { return gamma_.as<double>(); }
+  const double* tau(int mm) const { return taulog_.as<double>() + (size_t)(mm - 1) * LL; }
+  const void* block(int i) const { return V_[i].p; }
+
+  void read_flags(int* f) {
+    LYAP_HIP(hipMemcpyAsync(f, w_.flags.p, 2 * sizeof(int), hipMemcpyDeviceToHost, st_));
+    LYAP_HIP(hipStreamSynchronize(st_));
+  }
+
+  // Start, first half: B = C packed, X = A^{-1} C (the inner solve).
+  void start_solve(const double* C, int64_t ldc) {
+    hipLaunchKernelGGL((k_ext_pack<S>), dim3(eg_), dim3(kBlock), 0, st_, C, ldc, n_, Bs_.as<double>());
+    cg_->solve(Bs_.as<double>(), Xs_.as<double>(), kt_);
+  }
+
+  // Start, second half: [C, A^{-1} C] = V_1 R, gamma = R[:, :s]; beta = ||C||_F.
+  void start_finish() {
+    hipLaunchKernelGGL((k_ext_merge<S>), dim3(eg_), dim3(kBlock), 0, st_, Bs_.as<double>(), S, Xs_.as<double>(), n_,
+                       W_.as<double>());
+    LYAP_LAUNCHED("ext start");
+    double* V1 = new_block();
+    if (kt_) kt_->mark(LYAP_K_INIT);
+    cholqr2<L>(w_, dwl(), W_.as<double>(), dptrs(), V1, R0_.as<double>(), -1);
+    hipLaunchKernelGGL((k_ext_gamma<L>), dim3(1), dim3(64), 0, st_, R0_.as<double>(), S, gamma_.as<double>());
+    if (kt_) kt_->collect();
+    int f[2];
+    std::vector<double> g(LL);
+    LYAP_HIP(hipMemcpyAsync(g.data(), gamma_.p, LL * sizeof(double), hipMemcpyDeviceToHost, st_));
+    read_flags(f);
+    double tr = 0.0;
+    bool fin = true;
+    for (double v : g) {
+      tr += v * v;
+      fin = fin && std::isfinite(v);
+    }
+    LYAP_REQUIRE(f[1] == 0 && fin, LYAP_E_NUMERIC, "C contains NaN or Inf");
+    LYAP_REQUIRE(tr > 0.0, LYAP_E_ARG, "C is zero");
+    LYAP_REQUIRE(f[0] == 0, LYAP_E_BREAKDOWN,
+                 "[C, A^{-1} C] is numerically rank deficient (deflation not implemented)");
+    beta_ = std::sqrt(tr);  // ||C||_F = ||gamma||_F
+  }
+
+  // One step: V_{m+1} and T_m's block column m.
+  void step() {
+    const int j = m_;
+    const double* Vj = V_[j].as<double>();
+    launch_apply<double>(op_.dev, L, Vj, AV_.as<double>(), eg_, st_);
+    hipLaunchKernelGGL((k_ext_split<S>), dim3(eg_), dim3(kBlock), 0, st_, Vj, n_, Bs_.as<double>());
+    cg_->solve(Bs_.as<double>(), Xs_.as<double>(), kt_);
+    if (kt_) kt_->mark(LYAP_K_EXT_ORTH);
+    hipLaunchKernelGGL((k_ext_merge<S>), dim3(eg_), dim3(kBlock), 0, st_, AV_.as<double>(), L, Xs_.as<double>(), n_,
+                       W_.as<double>());
+    for (int sweep = 0; sweep < 2; ++sweep) {
+      gram<L>(w_, dptrs(), j + 1, W_.as<double>());
+      hipLaunchKernelGGL((k_ext_update<L>), dim3(w_.G), dim3(kExtThreads), 0, st_, dptrs(), j + 1,
+                         w_.H.as<double>(), W_.as<double>(), n_);
+      LYAP_LAUNCHED("k_ext_update");
+    }
+    double* Vn = new_block();
+    cholqr2<L>(w_, dwl(), W_.as<double>(), dptrs() + j + 1, Vn, w_.small.as<double>() + 8 * LL, j + 1);
+    gram<L>(w_, dptrs() + j, 2, AV_.as<double>());
+    hipLaunchKernelGGL((k_ext_tband<L>), dim3(1), dim3(64), 0, st_, w_.H.as<double>(), band_.as<double>(), j,
+                       taulog_.as<double>());
+    LYAP_LAUNCHED("k_ext_tband");
+    ++m_;
+  }
+
+  // Host copies of T_m's band (ld = L + 1, entries past k cleared) and of tau.
+  double* band_host(int mm) const {
+    const int k = mm * L;
+    double* h = (double*)std::malloc((size_t)(L + 1) * k * sizeof(double));
+    LYAP_HIP(hipMemcpy(h, band_.p, (size_t)(L + 1) * k * sizeof(double), hipMemcpyDeviceToHost));
+    for (int c = 0; c < k; ++c)
+      for (int d = 0; d <= L; ++d)
+        if (c + d >= k) h[(size_t)c * (L + 1) + d] = 0.0;
+    return h;
+  }
+
+ private:
+  double* new_block() {
+    V_.emplace_back(blkL_);
+    const void* p = V_.back().p;
+    LYAP_HIP(hipMemcpy(ptrs_.as<const void*>() + (V_.size() - 1), &p, sizeof(void*), hipMemcpyHostToDevice));
+    return V_.back().as<double>();
+  }
+  const double* const* dptrs() const { return ptrs_.as<const double*>(); }
+  const double* const* dwl() const { return wlist_.as<const double*>(); }
+
+  hipStream_t st_;
+  KernelTimer* kt_;
+  int n_ = 0, maxit_ = 0, m_ = 0, eg_ = 1;
+  size_t blkL_ = 0, blkS_ = 0;
+  double beta_ = 0.0;
+  OpHolder<double> op_;
+  std::unique_ptr<InnerCG> cg_;
+  ExtWork w_;
+  std::vector<DevBuf> V_;
+  DevBuf ptrs_, wlist_, AV_, W_, Bs_, Xs_, band_, taulog_, R0_, gamma_;
+};
+
 template <int S>
 lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_opts& o, lyap_result* out) {
   constexpr int L = 2 * S;
@@ -259,69 +407,27 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
   out->n = n;
   out->s = S;
   out->ell = L;
-  OpHolder<double> op;
-  make_op_f64(A, op, st);
-  InnerCG cg(op.dev, n, S, o.inner_pc, o.inner_tol, o.inner_max_iter, st);
   KernelTimer kt;
   kt.st = st;
   kt.on = o.profile != 0;
-
   const int maxit = o.max_iter;
-  const size_t blkL = (size_t)n * L * sizeof(double);
-  const size_t blkS = (size_t)n * S * sizeof(double);
-  const int eg = grid_for(n, 1, 1024);
-
-  ExtWork w;
-  w.n = n;
-  w.S = S;
-  w.L = L;
-  w.G = stream_grid(n);
-  w.st = st;
-  w.small.alloc(9 * LL * sizeof(double));
-  w.flags.alloc(64);
-  LYAP_HIP(hipMemsetAsync(w.flags.p, 0, 64, st));
-
-  std::vector<DevBuf> V;
-  V.reserve((size_t)maxit + 2);
-  DevBuf ptrs(((size_t)maxit + 2) * sizeof(void*));
-  DevBuf wlist(sizeof(void*));
-  DevBuf AV(blkL), W(blkL), Bs(blkS), Xs(blkS);
-  DevBuf band((size_t)(L + 1) * L * (maxit + 2) * sizeof(double));
-  DevBuf taulog(((size_t)maxit + 1) * LL * sizeof(double));
-  DevBuf R0(LL * sizeof(double)), gamma(LL * sizeof(double));
+  ExtSide<S> side(A, o, st, &kt);
+  InnerCG& cg = side.cg();
   DevBuf chk(sizeof(CheckOut));
   HostBuf hchk(sizeof(CheckOut));
-  LYAP_HIP(hipMemsetAsync(band.p, 0, band.bytes, st));
-  {
-    const void* wp = W.p;
-    LYAP_HIP(hipMemcpy(wlist.p, &wp, sizeof(void*), hipMemcpyHostToDevice));
-  }
-  const double* const* dptrs = ptrs.as<const double*>();
-  const double* const* dwl = wlist.as<const double*>();
-  auto new_block = [&]() {
-    V.emplace_back(blkL);
-    const void* p = V.back().p;
-    LYAP_HIP(hipMemcpy(ptrs.as<const void*>() + (V.size() - 1), &p, sizeof(void*), hipMemcpyHostToDevice));
-    return V.back().as<double>();
-  };
-  auto read_flags = [&](int* f) {
-    LYAP_HIP(hipMemcpyAsync(f, w.flags.p, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    LYAP_HIP(hipStreamSynchronize(st));
-  };
 
   // ---- start: [C, A^{-1} C] = V_1 R, gamma = R[:, :s]
   const auto t_pass1 = Clock::now();
-  hipLaunchKernelGGL((k_ext_pack<S>), dim3(eg), dim3(kBlock), 0, st, C, ldc, n, Bs.as<double>());
   std::unique_ptr<PcNetGpu> net;
   double train_ms = 0.0;
   if (o.inner_pc == LYAP_PC_LEARNED) {
-    net = std::make_unique<PcNetGpu>(op.dev, kPcC, st);
+    net = std::make_unique<PcNetGpu>(side.op().dev, kPcC, st);
     std::vector<float> W(pcnet_param_count(kPcC));
     pcnet_init_weights(kPcC, kPcSeed, kPcScale, W.data());
     net->set_weights(W.data());
     cg.harvest(kPcEvery, kPcKeep);
   }
-  cg.solve(Bs.as<double>(), Xs.as<double>(), &kt);
+  side.start_solve(C, ldc);
   if (net) {
     // train on the start solve's own iterates, then switch to flexible CG
     const auto t_tr = Clock::now();
@@ -344,31 +450,8 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
     train_ms = ms_since(t_tr);
     cg.set_net(net.get());
   }
-  hipLaunchKernelGGL((k_ext_merge<S>), dim3(eg), dim3(kBlock), 0, st, Bs.as<double>(), S, Xs.as<double>(), n,
-                     W.as<double>());
-  LYAP_LAUNCHED("ext start");
-  double* V1 = new_block();
-  kt.mark(LYAP_K_INIT);
-  cholqr2<L>(w, dwl, W.as<double>(), dptrs, V1, R0.as<double>(), -1);
-  hipLaunchKernelGGL((k_ext_gamma<L>), dim3(1), dim3(64), 0, st, R0.as<double>(), S, gamma.as<double>());
-  kt.collect();
-  {
-    int f[2];
-    std::vector<double> g(LL);
-    LYAP_HIP(hipMemcpyAsync(g.data(), gamma.p, LL * sizeof(double), hipMemcpyDeviceToHost, st));
-    read_flags(f);
-    double tr = 0.0;
-    bool fin = true;
-    for (double v : g) {
-      tr += v * v;
-      fin = fin && std::isfinite(v);
-    }
-    LYAP_REQUIRE(f[1] == 0 && fin, LYAP_E_NUMERIC, "C contains NaN or Inf");
-    LYAP_REQUIRE(tr > 0.0, LYAP_E_ARG, "C is zero");
-    LYAP_REQUIRE(f[0] == 0, LYAP_E_BREAKDOWN,
-                 "[C, A^{-1} C] is numerically rank deficient (deflation not implemented)");
-    out->beta = std::sqrt(tr);  // ||C||_F = ||gamma||_F
-  }
+  side.start_finish();
+  out->beta = side.beta();
   const double beta2 = out->beta * out->beta;
 
   Checker ck(L, S, st);
@@ -383,8 +466,7 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
   auto run_check = [&](int mm) {
     const auto t0 = Clock::now();
     kt.mark(LYAP_K_CHECK);
-    ck.run(band.as<double>(), mm * L, gamma.as<double>(), taulog.as<double>() + (size_t)(mm - 1) * LL,
-           chk.as<CheckOut>());
+    ck.run(side.band(), mm * L, side.gamma(), side.tau(mm), chk.as<CheckOut>());
     kt.collect();
     LYAP_HIP(hipMemcpyAsync(hchk.p, chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, st));
     LYAP_HIP(hipStreamSynchronize(st));
@@ -397,30 +479,11 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
   };
 
   while (m < maxit) {
-    const int j = m;  // current block V_j (0-based)
-    const double* Vj = V[j].as<double>();
-    launch_apply<double>(op.dev, L, Vj, AV.as<double>(), eg, st);
-    hipLaunchKernelGGL((k_ext_split<S>), dim3(eg), dim3(kBlock), 0, st, Vj, n, Bs.as<double>());
-    cg.solve(Bs.as<double>(), Xs.as<double>(), &kt);
-    kt.mark(LYAP_K_EXT_ORTH);
-    hipLaunchKernelGGL((k_ext_merge<S>), dim3(eg), dim3(kBlock), 0, st, AV.as<double>(), L, Xs.as<double>(), n,
-                       W.as<double>());
-    for (int sweep = 0; sweep < 2; ++sweep) {
-      gram<L>(w, dptrs, j + 1, W.as<double>());
-      hipLaunchKernelGGL((k_ext_update<L>), dim3(w.G), dim3(kExtThreads), 0, st, dptrs, j + 1, w.H.as<double>(),
-                         W.as<double>(), n);
-      LYAP_LAUNCHED("k_ext_update");
-    }
-    double* Vn = new_block();
-    cholqr2<L>(w, dwl, W.as<double>(), dptrs + j + 1, Vn, w.small.as<double>() + 8 * LL, j + 1);
-    gram<L>(w, dptrs + j, 2, AV.as<double>());
-    hipLaunchKernelGGL((k_ext_tband<L>), dim3(1), dim3(64), 0, st, w.H.as<double>(), band.as<double>(), j,
-                       taulog.as<double>());
-    LYAP_LAUNCHED("k_ext_tband");
+    side.step();
     ++m;
     if (m == next_check || m == maxit) {
       int f[2];
-      read_flags(f);
+      side.read_flags(f);
       LYAP_REQUIRE(f[1] == 0, LYAP_E_NUMERIC, "non-finite values in the extended Krylov basis at step %d", f[1]);
       int mm = m;
       const bool broke = f[0] > 0 && f[0] <= m;
@@ -463,8 +526,7 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
   // ---- finalisation
   const auto t_fin = Clock::now();
   std::vector<double> tau_h(LL);
-  LYAP_HIP(hipMemcpyAsync(tau_h.data(), taulog.as<double>() + (size_t)(m - 1) * LL, LL * sizeof(double),
-                          hipMemcpyDeviceToHost, st));
+  LYAP_HIP(hipMemcpyAsync(tau_h.data(), side.tau(m), LL * sizeof(double), hipMemcpyDeviceToHost, st));
   LYAP_HIP(hipStreamSynchronize(st));
   double tau_f = 0.0;
   for (double v : tau_h) tau_f += v * v;
@@ -474,7 +536,7 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
   out->trunc_eps = eps;
   DevBuf M;
   kt.mark(LYAP_K_FINAL);
-  const int t = finalise_factor(ck, band.as<double>(), gamma.as<double>(), eps, M, st);
+  const int t = finalise_factor(ck, side.band(), side.gamma(), eps, M, st);
   kt.collect();
   out->t = t;
   const double fin_ms = ms_since(t_fin);
@@ -487,7 +549,7 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
   if (t > 0) {
     LYAP_HIP(hipMemsetAsync(out->Z, 0, (size_t)n * t * sizeof(double), st));
     std::vector<const void*> bp;
-    for (int i = 0; i < m; ++i) bp.push_back(V[i].p);
+    for (int i = 0; i < m; ++i) bp.push_back(side.block(i));
     kt.mark(LYAP_K_ZFLUSH);
     launch_zflush<double>(bp.data(), m, n, L, M.as<double>(), t, out->Z, n, 0, st);
   }
@@ -496,14 +558,9 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
   const double z_ms = ms_since(t_z);
 
   if (o.want_T) {
-    const int k = m * L;
-    out->T_band = (double*)std::malloc((size_t)(L + 1) * k * sizeof(double));
-    LYAP_HIP(hipMemcpy(out->T_band, band.p, (size_t)(L + 1) * k * sizeof(double), hipMemcpyDeviceToHost));
-    for (int c = 0; c < k; ++c)
-      for (int d = 0; d <= L; ++d)
-        if (c + d >= k) out->T_band[(size_t)c * (L + 1) + d] = 0.0;
+    out->T_band = side.band_host(m);
     std::vector<double> g(LL);
-    LYAP_HIP(hipMemcpy(g.data(), gamma.p, LL * sizeof(double), hipMemcpyDeviceToHost));
+    LYAP_HIP(hipMemcpy(g.data(), side.gamma(), LL * sizeof(double), hipMemcpyDeviceToHost));
     out->gamma = (double*)std::malloc(LL * sizeof(double));
     out->tau = (double*)std::malloc(LL * sizeof(double));
     for (int a = 0; a < L; ++a)
@@ -528,10 +585,202 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
     out->kern_n[i] = kt.n[i];
   }
   {
-    const double coef = op.coef_bytes_per_row();
+    const double coef = side.op().coef_bytes_per_row();
     // CG direction: r, M^{-1}, p_old in, p, q out (+ coefficients); update: x, r, p, q, M^{-1} in, x, r out
     out->kern_bytes[LYAP_K_CG_DIR] = (double)n * (5.0 * S * 8 + 8 + coef);
     out->kern_bytes[LYAP_K_CG_UPD] = (double)n * (6.0 * S * 8 + 8);
+  }
+  out->status = status;
+  return status;
+}
+
+// sylv_solve over EK_m(A, C1) and EK_m(B, C2) (Section 5.1 with the spaces of
+// Section 4): the two spaces advance in lockstep, the residual is the
+// corrected Algorithm 4 with ell = 2s and the first s rows of tau_{m+1,m} and
+// iota_{m+1,m}, and the truncated factors come from the stored bases.
+template <int S>
+lyap_status sylv_ext_impl(const lyap_op* A, const lyap_op* B, const double* C1, int64_t ldc1, const double* C2,
+                          int64_t ldc2, const lyap_opts& o, sylv_result* out) {
+  constexpr int L = 2 * S;
+  constexpr int LL = L * L;
+  const auto t_entry = Clock::now();
+  hipStream_t st = (hipStream_t)o.stream;
+  const int n1 = (int)A->n, n2 = (int)B->n;
+  out->n1 = n1;
+  out->n2 = n2;
+  out->s = S;
+  out->ell = L;
+  const int maxit = o.max_iter;
+  KernelTimer kt;
+  kt.st = st;
+  kt.on = o.profile != 0;
+  ExtSide<S> sa(A, o, st, &kt), sb(B, o, st, &kt);
+  const auto t_pass1 = Clock::now();
+  sa.start_solve(C1, ldc1);
+  sa.start_finish();
+  sb.start_solve(C2, ldc2);
+  sb.start_finish();
+  out->beta1 = sa.beta();
+  out->beta2 = sb.beta();
+  const double b12 = sa.beta() * sb.beta();
+
+  Checker ca(L, S, st), cb(L, S, st);
+  DevBuf part(4096 * sizeof(double)), counter(64), chk(sizeof(CheckOut));
+  HostBuf hchk(sizeof(CheckOut) + 4 * sizeof(double));
+  LYAP_HIP(hipMemsetAsync(counter.p, 0, 64, st));
+  CheckSchedule sched{o.check_every, maxit};
+  std::vector<int> hm;
+  std::vector<double> hr;
+  double check_ms = 0.0, t_to_tol = 0.0, lamA_abs = 0.0, lamB_abs = 0.0, last_res = INFINITY;
+  int next_check = sched.first(), m = 0, checked_m = 0;
+  lyap_status status = LYAP_NOT_CONVERGED;
+  CheckOut* hc = hchk.as<CheckOut>();
+  double* hl = reinterpret_cast<double*>(hchk.as<char>() + sizeof(CheckOut));
+
+  auto run_check = [&](int mm) -> double {
+    const auto t0 = Clock::now();
+    kt.mark(LYAP_K_CHECK);
+    const int k = mm * L;
+    ca.prepare(sa.band(), k, sa.gamma(), sa.tau(mm));
+    cb.prepare(sb.band(), k, sb.gamma(), sb.tau(mm));
+    launch_sylv_sum(ca, cb, k, L, S, part.as<double>(), counter.as<unsigned>(), chk.as<CheckOut>(), st);
+    kt.collect();
+    LYAP_HIP(hipMemcpyAsync(hc, chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipMemcpyAsync(&hl[0], ca.lam(), sizeof(double), hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipMemcpyAsync(&hl[1], ca.lam() + k - 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipMemcpyAsync(&hl[2], cb.lam(), sizeof(double), hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipMemcpyAsync(&hl[3], cb.lam() + k - 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipStreamSynchronize(st));
+    check_ms += ms_since(t0);
+    checked_m = mm;
+    out->n_checks++;
+    LYAP_REQUIRE(std::isfinite(hc->res), LYAP_E_NUMERIC, "residual is not finite at m=%d", mm);
+    const double rel = hc->res / b12;
+    hm.push_back(mm);
+    hr.push_back(rel);
+    last_res = rel;
+    lamA_abs = std::max(std::fabs(hl[0]), std::fabs(hl[1]));
+    lamB_abs = std::max(std::fabs(hl[2]), std::fabs(hl[3]));
+    if (o.verbose) std::fprintf(stderr, "[sylv-ext] m=%d k=%d res=%.3e\n", mm, k, rel);
+    LYAP_REQUIRE(hc->lam_max < 0.0, LYAP_E_INDEFINITE,
+                 "Ritz value %.3e >= 0 at m=%d: an operator is not negative definite", hc->lam_max, mm);
+    return rel;
+  };
+
+  while (m < maxit) {
+    sa.step();
+    sb.step();
+    ++m;
+    if (m == next_check || m == maxit) {
+      int fa[2], fb[2];
+      sa.read_flags(fa);
+      sb.read_flags(fb);
+      LYAP_REQUIRE(fa[1] == 0 && fb[1] == 0, LYAP_E_NUMERIC,
+                   "non-finite values in an extended Krylov basis at step %d", std::max(fa[1], fb[1]));
+      int bk = 0;
+      for (int f : {fa[0], fb[0]})
+        if (f > 0 && f <= m && (bk == 0 || f < bk)) bk = f;
+      const int mm = bk > 0 ? bk : m;  // the QR at step bk-1 found a dependent block
+      const double rel = run_check(mm);
+      if (rel <= o.tol) {
+        status = LYAP_OK;
+        m = mm;
+        t_to_tol = ms_since(t_entry);
+        break;
+      }
+      if (bk > 0) {
+        m = mm;
+        status = LYAP_E_BREAKDOWN;
+        set_error("extended Krylov breakdown at m=%d with residual %.3e above tol", mm, rel);
+        break;
+      }
+      next_check = sched.next(m, rel, o.tol);
+    }
+  }
+  if (checked_m != m) run_check(m);
+  const double pass1_ms = ms_since(t_pass1) - check_ms;
+  out->m = m;
+  out->res = last_res;
+  out->n_hist = (int)hm.size();
+  out->hist_m = (int32_t*)std::malloc(std::max<size_t>(1, hm.size()) * sizeof(int32_t));
+  out->hist_res = (double*)std::malloc(std::max<size_t>(1, hr.size()) * sizeof(double));
+  for (size_t i = 0; i < hm.size(); ++i) {
+    out->hist_m[i] = hm[i];
+    out->hist_res[i] = hr[i];
+  }
+
+  // ---- finalisation
+  const auto t_fin = Clock::now();
+  std::vector<double> tau_h(LL), iota_h(LL);
+  LYAP_HIP(hipMemcpyAsync(tau_h.data(), sa.tau(m), LL * sizeof(double), hipMemcpyDeviceToHost, st));
+  LYAP_HIP(hipMemcpyAsync(iota_h.data(), sb.tau(m), LL * sizeof(double), hipMemcpyDeviceToHost, st));
+  LYAP_HIP(hipStreamSynchronize(st));
+  auto fro = [](const std::vector<double>& v) {
+    double a = 0.0;
+    for (double x : v) a += x * x;
+    return std::sqrt(a);
+  };
+  // ||R(Y) - R(Y + dY)|| <= (||T_m underline|| + ||J_m underline||) ||dY||_F
+  const double nu = lamA_abs + fro(tau_h) + lamB_abs + fro(iota_h);
+  double eps = o.trunc_eps;
+  if (!(eps >= 0.0)) eps = std::min(1e-12, 0.05 * o.tol / nu) * b12;
+  out->trunc_eps = eps;
+  DevBuf M1, M2;
+  kt.mark(LYAP_K_FINAL);
+  const int t = finalise_sylv(ca, cb, sa.band(), sb.band(), sa.gamma(), sb.gamma(), L, eps, M1, M2, st);
+  kt.collect();
+  out->t = t;
+  const double fin_ms = ms_since(t_fin);
+
+  // ---- Z1 = V_m M1, Z2 = U_m M2 from the stored bases
+  const auto t_z = Clock::now();
+  bool own1 = false, own2 = false;
+  out->Z1 = alloc_output(o, (size_t)n1 * std::max(t, 1) * sizeof(double), &own1);
+  out->Z2 = alloc_output(o, (size_t)n2 * std::max(t, 1) * sizeof(double), &own2);
+  out->owns_Z = own1 ? 1 : 0;
+  if (t > 0) {
+    LYAP_HIP(hipMemsetAsync(out->Z1, 0, (size_t)n1 * t * sizeof(double), st));
+    LYAP_HIP(hipMemsetAsync(out->Z2, 0, (size_t)n2 * t * sizeof(double), st));
+    std::vector<const void*> ba, bb;
+    for (int i = 0; i < m; ++i) {
+      ba.push_back(sa.block(i));
+      bb.push_back(sb.block(i));
+    }
+    kt.mark(LYAP_K_ZFLUSH);
+    launch_zflush<double>(ba.data(), m, n1, L, M1.as<double>(), t, out->Z1, n1, 0, st);
+    launch_zflush<double>(bb.data(), m, n2, L, M2.as<double>(), t, out->Z2, n2, 0, st);
+  }
+  LYAP_HIP(hipStreamSynchronize(st));
+  kt.collect();
+  const double z_ms = ms_since(t_z);
+
+  if (o.want_T) {
+    out->T_band = sa.band_host(m);
+    out->J_band = sb.band_host(m);
+    auto sq = [&](const double* dev) {
+      std::vector<double> g(LL);
+      LYAP_HIP(hipMemcpy(g.data(), dev, LL * sizeof(double), hipMemcpyDeviceToHost));
+      double* h = (double*)std::malloc(LL * sizeof(double));
+      rowmajor_to_colmajor(g.data(), L, L, h);
+      return h;
+    };
+    out->gamma1 = sq(sa.gamma());
+    out->gamma2 = sq(sb.gamma());
+    out->tau = (double*)std::malloc(LL * sizeof(double));
+    out->iota = (double*)std::malloc(LL * sizeof(double));
+    rowmajor_to_colmajor(tau_h.data(), L, L, out->tau);
+    rowmajor_to_colmajor(iota_h.data(), L, L, out->iota);
+  }
+  out->times_ms[LYAP_T_PASS1] = pass1_ms;
+  out->times_ms[LYAP_T_CHECKS] = check_ms;
+  out->times_ms[LYAP_T_FINAL] = fin_ms;
+  out->times_ms[LYAP_T_PASS2] = z_ms;
+  out->times_ms[LYAP_T_INNER] = sa.cg().stats().ms + sb.cg().stats().ms;
+  out->times_ms[LYAP_T_TOTAL] = ms_since(t_entry);
+  out->times_ms[LYAP_T_TO_TOL] = t_to_tol;
+  for (int i = 0; i < 12; ++i) {
+    out->kern_ms[i] = kt.ms[i];
+    out->kern_n[i] = kt.n[i];
   }
   out->status = status;
   return status;
@@ -554,5 +803,19 @@ lyap_status solve_ext(const lyap_op* A, const double* C, int S, int64_t ldc, con
 
 template lyap_status solve_ext<float>(const lyap_op*, const double*, int, int64_t, const lyap_opts&, lyap_result*);
 template lyap_status solve_ext<double>(const lyap_op*, const double*, int, int64_t, const lyap_opts&, lyap_result*);
+
+lyap_status solve_sylv_ext(const lyap_op* A, const lyap_op* B, const double* C1, int64_t ldc1, const double* C2,
+                           int64_t ldc2, int S, const lyap_opts& o, sylv_result* out) {
+  LYAP_REQUIRE(o.storage == LYAP_STORE_F64, LYAP_E_UNSUPPORTED, "the extended Krylov method runs with FP64 storage only");
+  LYAP_REQUIRE(o.inner_pc == LYAP_PC_NONE || o.inner_pc == LYAP_PC_JACOBI, LYAP_E_UNSUPPORTED,
+               "extended Krylov Sylvester solves take inner_pc NONE or JACOBI");
+  switch (S) {
+    case 1: return sylv_ext_impl<1>(A, B, C1, ldc1, C2, ldc2, o, out);
+    case 2: return sylv_ext_impl<2>(A, B, C1, ldc1, C2, ldc2, o, out);
+    case 4: return sylv_ext_impl<4>(A, B, C1, ldc1, C2, ldc2, o, out);
+    default: LYAP_REQUIRE(false, LYAP_E_UNSUPPORTED, "extended Krylov supports s = 1, 2 or 4 (got %d)", S);
+  }
+  return LYAP_E_UNSUPPORTED;
+}
 
 }  // namespace lyap

@@ -32,6 +32,7 @@
 #include "check.hpp"
 #include "side.hpp"
 #include "solver.hpp"
+#include "sylv.hpp"
 
 namespace lyap {
 
@@ -311,7 +312,13 @@ void core_lu_explicit(const double* E0, int64_t lde, const int* I, const int* J,
   LYAP_HIP(hipStreamSynchronize(st));  // W is released on return
 }
 
-namespace {
+void launch_sylv_sum(const Checker& ca, const Checker& cb, int k, int ell, int nt, double* part, unsigned* counter,
+                     CheckOut* out, hipStream_t st) {
+  const int grid = std::max(1, std::min(2 * k, 2048));
+  hipLaunchKernelGGL(k_sylv_sum, dim3(grid), dim3(kBlock), 0, st, ca.lam(), ca.g(), ca.Wm(), cb.lam(), cb.g(),
+                     cb.Wm(), k, ell, nt, part, counter, out);
+  LYAP_LAUNCHED("k_sylv_sum");
+}
 
 // Returns t; M1, M2: k x t row-major.
 int finalise_sylv(const Checker& ca, const Checker& cb, const double* bandA, const double* bandB,
@@ -357,6 +364,8 @@ int finalise_sylv(const Checker& ca, const Checker& cb, const double* bandA, con
   LYAP_REQUIRE(hfail == 0, LYAP_E_INDEFINITE, "shifted operator not positive definite in the Sylvester factor");
   return t;
 }
+
+namespace {
 
 double host_fro(const std::vector<double>& v) {
   double s = 0.0;
@@ -646,10 +655,15 @@ extern "C" lyap_status sylv_solve(const lyap_op* A, const lyap_op* B, const doub
     LYAP_REQUIRE(o.max_iter >= 1 && (int64_t)o.max_iter * s <= (int64_t)1 << 20, LYAP_E_ARG,
                  "max_iter=%d out of range", o.max_iter);
     LYAP_REQUIRE(o.check_every >= 0, LYAP_E_ARG, "check_every must be >= 0");
-    LYAP_REQUIRE(o.method == LYAP_METHOD_STD, LYAP_E_UNSUPPORTED,
-                 "sylv_solve builds standard Krylov spaces (method must be LYAP_METHOD_STD)");
+    LYAP_REQUIRE(o.method == LYAP_METHOD_STD || o.method == LYAP_METHOD_EXT, LYAP_E_ARG, "unknown method %d",
+                 o.method);
     LYAP_REQUIRE(o.storage == LYAP_STORE_F64 || o.storage == LYAP_STORE_F32, LYAP_E_ARG, "unknown storage %d",
                  o.storage);
+    if (o.method == LYAP_METHOD_EXT) {
+      lyap_status st = solve_sylv_ext(A, B, C1, ldc1, C2, ldc2, s, o, out);
+      out->status = st;
+      return st;
+    }
     lyap_status st = o.storage == LYAP_STORE_F64 ? sylv_impl<double>(A, B, C1, ldc1, C2, ldc2, s, o, out)
                                                  : sylv_impl<float>(A, B, C1, ldc1, C2, ldc2, s, o, out);
     out->status = st;

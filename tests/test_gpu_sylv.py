@@ -97,8 +97,8 @@ def test_sylv_different_sizes_and_errors(lib):
     dA, dB = b.device_op(opA), b.device_op(opB)
     sol = b.sylv_solve(dA, dB, C1, C2, tol=1e-10)
     assert sol.status == 0 and sol.Z1.shape[0] == 81 and sol.Z2.shape[0] == 125
-    with pytest.raises(b.LyapError):
-        b.sylv_solve(dA, dB, C1, C2, method=b.METHOD_EXT)
+    se = b.sylv_solve(dA, dB, C1, C2, tol=1e-10, method=b.METHOD_EXT)   # extended spaces, unequal sizes
+    assert se.status == 0 and se.Z1.shape[0] == 81 and se.Z2.shape[0] == 125
     Cz = torch.zeros_like(C2)
     with pytest.raises(b.LyapError):
         b.sylv_solve(dA, dB, C1, Cz)
@@ -134,3 +134,62 @@ def test_sylv_full_size(lib):
         R2 = torch.linalg.qr(torch.cat([Z2, apply(dB, Z2), C2], dim=1), mode="r")[1]
         ex = float(torch.linalg.norm(R1 @ R2.T)) / (sol.beta1 * sol.beta2)
         assert ex <= bound, (storage, ex)
+
+
+# ------------------------------------------------------------------ two extended Krylov spaces
+@pytest.mark.parametrize("s", [1, 2])
+def test_sylv_ext_parity(lib, s):
+    b = _b()
+    opA, opB = laplace2d(14), fv3d(6, 0.5, 4)
+    A, B = opA.to_scipy(), opB.to_scipy()
+    C1 = gaussian_C(opA.n, s, 4)
+    C2 = gaussian_C(opB.n, s, 5)
+    print(f"sylv ext s={s}", flush=True)
+    sol = b.sylv_solve(b.device_op(opA), b.device_op(opB), _dev(C1), _dev(C2), tol=1e-9, method=b.METHOD_EXT,
+                       storage=b.STORE_F64, check_every=1, want_T=True)
+    ref = Y.sylv_ext(A, B, C1, C2, tol=1e-9)
+    assert sol.status == 0 and ref.converged
+    assert abs(sol.m - ref.m) <= 1, (sol.m, ref.m)
+    gh = dict(zip(sol.hist_m, sol.hist_res))
+    for h in ref.hist:
+        if h["m"] in gh:
+            assert abs(gh[h["m"]] - h["res"]) <= 1e-5 * h["res"] + 1e-14, (h["m"], gh[h["m"]], h["res"])
+    Z1, Z2 = sol.Z1.cpu().numpy(), sol.Z2.cpu().numpy()
+    X = D.sylv_eig(A.toarray(), B.toarray(), C1, C2)
+    assert Y.lowrank_error(Z1, Z2, X) <= 1e-8
+    assert np.linalg.norm(Z1 @ Z2.T - ref.Z1 @ ref.Z2.T) <= 1e-8 * np.linalg.norm(X)
+    ex = Y.explicit_residual(A, B, Z1, Z2, C1, C2) / (sol.beta1 * sol.beta2)
+    assert ex <= 1.2e-9
+    L = 2 * s
+    k = L * sol.m
+    for band, Tref in ((sol.T_band, ref.T), (sol.J_band, ref.J)):
+        for c in range(min(k, 2 * L)):
+            for d in range(L + 1):
+                if c + d < k:
+                    assert abs(band[c, d] - Tref[c + d, c]) <= 1e-9 * np.abs(Tref).max()
+    print(f"  m {sol.m} (oracle {ref.m}), t {sol.t}, explicit {ex:.2e}")
+
+
+def test_sylv_ext_lyapunov_special_case(lib):
+    b = _b()
+    op = laplace2d(20)
+    C = _dev(gaussian_C(op.n, 2, 9))
+    d = b.device_op(op)
+    sy = b.sylv_solve(d, d, C, C, tol=1e-9, method=b.METHOD_EXT, storage=b.STORE_F64, check_every=1)
+    ly = b.lyap_solve(d, C, tol=1e-9, method=b.METHOD_EXT, storage=b.STORE_F64, check_every=1)
+    assert sy.m == ly.m
+    Xl = ly.Z.cpu().numpy() @ ly.Z.cpu().numpy().T
+    Xs = sy.Z1.cpu().numpy() @ sy.Z2.cpu().numpy().T
+    assert np.linalg.norm(Xs - Xl) <= 1e-9 * np.linalg.norm(Xl)
+
+
+def test_sylv_ext_errors(lib):
+    b = _b()
+    opA, opB = laplace2d(8), laplace2d(9)
+    dA, dB = b.device_op(opA), b.device_op(opB)
+    for kw, s, status in ((dict(storage=b.STORE_F32), 2, b.E_UNSUPPORTED), (dict(), 3, b.E_UNSUPPORTED),
+                          (dict(inner_pc=b.PC_LEARNED), 1, b.E_UNSUPPORTED)):
+        with pytest.raises(b.LyapError) as e:
+            b.sylv_solve(dA, dB, _dev(gaussian_C(opA.n, s, 1)), _dev(gaussian_C(opB.n, s, 2)),
+                         method=b.METHOD_EXT, **{"storage": b.STORE_F64, **kw})
+        assert e.value.status == status
