@@ -208,7 +208,7 @@ def main_ext(args):
             a = agg.setdefault(name, {"ms": 0.0, "n": 0, "bytes_per_launch": kk["bytes_per_launch"]})
             a["ms"] += kk["ms"]
             a["n"] += kk["n"]
-    dom = max(("cg_dir", "cg_upd"), key=lambda k: agg[k]["ms"])
+    dom = max((k for k in ("cg_dir", "cg_upd") if k in agg), key=lambda k: agg[k]["ms"])
     avg_ms = agg[dom]["ms"] / agg[dom]["n"]
     bpl = agg[dom]["bytes_per_launch"]
     achieved = bpl / (avg_ms * 1e-3) / 1e9

@@ -586,8 +586,9 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
   }
   {
     const double coef = side.op().coef_bytes_per_row();
-    // CG direction: r, M^{-1}, p_old in, p, q out (+ coefficients); update: x, r, p, q, M^{-1} in, x, r out
-    out->kern_bytes[LYAP_K_CG_DIR] = (double)n * (5.0 * S * 8 + 8 + coef);
+    // one single-reduction CG iteration: x, r, w, s, p and M^{-1} in; x, r, w, s, p out (+ coefficients)
+    out->kern_bytes[LYAP_K_CG_DIR] = (double)n * (10.0 * S * 8 + 8 + coef);
+    // the flexible-CG update of the learned-preconditioner runs: x, r, p, q in; x, r out
     out->kern_bytes[LYAP_K_CG_UPD] = (double)n * (6.0 * S * 8 + 8);
   }
   out->status = status;

@@ -1,18 +1,17 @@
-// Preconditioned CG on -A for the inner solves of the extended Krylov method.
+// Preconditioned CG on -A for the inner solves of the extended Krylov method
+// (and on the mass matrix for the generalized equation).
 //
-// One iteration is two streaming kernels with consumer-side reductions (the
-// same scheme as the Lanczos step: each kernel writes one partial per
-// workgroup, the next kernel sums all partials in a fixed order):
-//
-//   D  beta = rho_k / rho_{k-1};  p = z + beta p_old  (z = M^{-1} r);
-//      q = (-A) p, where the rows of p that the stencil needs are recomputed
-//      from r, M^{-1} and p_old on the fly; partial p^T q
-//   U  alpha = rho_k / p^T q;  x += alpha p;  r -= alpha q;  z = M^{-1} r;
-//      partials r^T z and r^T r
+// With K = -A and the Jacobi preconditioner M, one iteration is a single
+// streaming kernel (the single-reduction form below, k_cgcg_iter): the two
+// inner products an iteration needs are taken in one grid-wide reduction, with
+// the consumer-side scheme of the Lanczos step (each kernel writes one partial
+// per workgroup, the next sums all partials in a fixed order).  The flexible
+// CG of the learned preconditioner keeps two kernels per iteration (k_fcg_dir,
+// k_fcg_upd), since its preconditioner is a network applied in between.
 //
 // The host launches iterations in chunks and reads the logged r^T r of each
 // chunk once; a column whose recursive residual is below the threshold is
-// frozen (alpha = 0, p = 0), so iterations after convergence change nothing.
+// frozen (alpha = beta = 0), so iterations after convergence change nothing.
 // Every solve is then certified by the true residual ||b - A x|| / ||b||; a
 // solve that fails it restarts from the current iterate (at most three times).
 #include <cmath>
@@ -24,25 +23,6 @@ namespace lyap {
 
 constexpr int kCgChunk = 32;
 constexpr int kCgRestarts = 3;
-
-// Row i of the search direction: active columns z_i + beta p_old_i, others 0.
-template <int S>
-__device__ __forceinline__ void dir_row(const double* __restrict__ r, const double* __restrict__ dinv,
-                                        const double* __restrict__ pold, const double (&beta)[S],
-                                        const double (&mask)[S], int i, double (&p)[S]) {
-  double rv[S];
-  load_row<double, S>(r + (size_t)i * S, rv);
-  const double di = dinv[i];
-  if (pold) {
-    double pv[S];
-    load_row<double, S>(pold + (size_t)i * S, pv);
-#pragma unroll
-    for (int c = 0; c < S; ++c) p[c] = mask[c] * fma(beta[c], pv[c], rv[c] * di);
-  } else {
-#pragma unroll
-    for (int c = 0; c < S; ++c) p[c] = mask[c] * (rv[c] * di);
-  }
-}
 
 #define CG_ROWS(r, n) for (int r = blockIdx.x * NT + threadIdx.x; r < (n); r += gridDim.x * NT)
 
@@ -89,108 +69,163 @@ __global__ __launch_bounds__(NT) void k_cg_init(const double* __restrict__ B, do
   write_partial<2 * S, NT>(acc, red, pout);
 }
 
+// ------------------------------------------------------------------ single-reduction CG
+// Preconditioned CG in the Chronopoulos-Gear form: with K = -A, M = D^{-1},
+// u = M r and w = K u, the two inner products of an iteration, gamma = r.u and
+// delta = w.u, are taken together, so one kernel (one grid-wide reduction)
+// does a whole iteration:
+//   beta = gamma_i / gamma_{i-1},  alpha = gamma_i / (delta_i - beta gamma_i / alpha_{i-1})
+//   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
+//   u = M r,  w = K u  and the next gamma, delta, r.r.
+// Mathematically the iterates are those of the two-kernel form above.  r, s
+// and w are double buffered: the product K u at a row needs u = M r of the
+// neighbouring rows, recomputed from the previous r, w, s there.
+
+// u_j = M (r_j - alpha (w_j + beta s_j)) of the new iterate at row j.
+template <int S>
+__device__ __forceinline__ void cgcg_u(const double* __restrict__ r, const double* __restrict__ w,
+                                       const double* __restrict__ sold, const double* __restrict__ dinv,
+                                       const double (&alpha)[S], const double (&beta)[S], int j, double (&u)[S]) {
+  double rv[S], wv[S];
+  load_row<double, S>(r + (size_t)j * S, rv);
+  load_row<double, S>(w + (size_t)j * S, wv);
+  if (sold) {
+    double sv[S];
+    load_row<double, S>(sold + (size_t)j * S, sv);
+#pragma unroll
+    for (int c = 0; c < S; ++c) wv[c] = fma(beta[c], sv[c], wv[c]);
+  }
+  const double dj = dinv[j];
+#pragma unroll
+  for (int c = 0; c < S; ++c) u[c] = dj * fma(-alpha[c], wv[c], rv[c]);
+}
+
+// Start of a (re)started solve: r given, w = K M r; partials gamma, delta, r.r.
 template <int S, int NT>
-__global__ __launch_bounds__(NT) void k_cg_dir(OpDev<double> op, const double* __restrict__ r,
-                                               const double* __restrict__ dinv, const double* __restrict__ pold,
-                                               double* __restrict__ pnew, double* __restrict__ q, CgIter* log, int it,
-                                               int first, double* state, double eta2, const double* pin, int nparts,
-                                               double* pout, int n) {
-  __shared__ double red[pow2_at_least(2 * S) * (NT / 64)];
-  reduce_partials<2 * S, NT>(pin, nparts, red);
-  double rho[S], rr[S], beta[S], mask[S];
+__global__ __launch_bounds__(NT) void k_cgcg_start(OpDev<double> op, const double* __restrict__ r,
+                                                   const double* __restrict__ dinv, double* __restrict__ w,
+                                                   double* pout, int n) {
+  __shared__ double red[pow2_at_least(3 * S) * (NT / 64)];
+  double acc[3 * S];
 #pragma unroll
-  for (int c = 0; c < S; ++c) {
-    rho[c] = uniform_d(red[c]);
-    rr[c] = uniform_d(red[S + c]);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < S; ++c) {
-    const double thr = (first && it == 0) ? eta2 * rr[c] : uniform_d(state[c]);
-    const bool active = rr[c] > thr;
-    mask[c] = active ? 1.0 : 0.0;
-    beta[c] = (active && it > 0) ? rho[c] / uniform_d(log[it - 1].rho[c]) : 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      if (first && it == 0) state[c] = thr;
-      log[it].rho[c] = rho[c];
-      log[it].rr[c] = rr[c];
-    }
-  }
-  // Every column converged (the rest of the host's iteration chunk): x and r
-  // stay as they are, so nothing below would change, and the partials of the
-  // last update still hold r's sums for the next iteration.
-  bool any = false;
-#pragma unroll
-  for (int c = 0; c < S; ++c) any = any || mask[c] > 0.0;
-  if (!any) return;
-  const double* po = it > 0 ? pold : nullptr;
-  double acc[S];
-#pragma unroll
-  for (int c = 0; c < S; ++c) acc[c] = 0.0;
+  for (int c = 0; c < 3 * S; ++c) acc[c] = 0.0;
   int lo, hi;
   op_rows(blockIdx.x, gridDim.x, n, lo, hi);
   for (int i = lo + threadIdx.x; i < hi; i += NT) {
-    double p[S], w[S];
-    dir_row<S>(r, dinv, po, beta, mask, i, p);
-    store_row<double, S>(pnew + (size_t)i * S, p);
-    op_row_fn<double, S>(op, i, [&](int j, double (&v)[S]) { dir_row<S>(r, dinv, po, beta, mask, j, v); }, w);
+    double wv[S], rv[S];
+    op_row_fn<double, S>(op, i, [&](int j, double (&u)[S]) {
+      double rj[S];
+      load_row<double, S>(r + (size_t)j * S, rj);
+      const double dj = dinv[j];
 #pragma unroll
-    for (int c = 0; c < S; ++c) {
-      w[c] = -w[c];
-      acc[c] = fma(p[c], w[c], acc[c]);
-    }
-    store_row<double, S>(q + (size_t)i * S, w);
-  }
-  write_partial<S, NT>(acc, red, pout);
-}
-
-template <int S, int NT>
-__global__ __launch_bounds__(NT) void k_cg_upd(double* __restrict__ x, double* __restrict__ r,
-                                               const double* __restrict__ p, const double* __restrict__ q,
-                                               const double* __restrict__ dinv, CgIter* log, int it,
-                                               const double* state, const double* pin, int nparts, double* pout,
-                                               int* flag, int n) {
-  __shared__ double red[pow2_at_least(2 * S) * (NT / 64)];
-  reduce_partials<S, NT>(pin, nparts, red);
-  double alpha[S];
-#pragma unroll
-  for (int c = 0; c < S; ++c) {
-    const double sigma = uniform_d(red[c]);
-    const double rho = uniform_d(log[it].rho[c]);
-    const bool active = uniform_d(log[it].rr[c]) > uniform_d(state[c]);
-    alpha[c] = (active && sigma > 0.0) ? rho / sigma : 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      log[it].sigma[c] = sigma;
-      log[it].alpha[c] = alpha[c];
-      if (active && !(sigma > 0.0)) flag[1] = it + 1;
-    }
-  }
-  __syncthreads();
-  bool any = false;
-#pragma unroll
-  for (int c = 0; c < S; ++c) any = any || uniform_d(log[it].rr[c]) > uniform_d(state[c]);
-  if (!any) return;  // see k_cg_dir
-  double acc[2 * S];
-#pragma unroll
-  for (int c = 0; c < 2 * S; ++c) acc[c] = 0.0;
-  CG_ROWS(i, n) {
-    double xv[S], rv[S], pv[S], qv[S];
-    load_row<double, S>(x + (size_t)i * S, xv);
+      for (int c = 0; c < S; ++c) u[c] = dj * rj[c];
+    }, wv);
     load_row<double, S>(r + (size_t)i * S, rv);
-    load_row<double, S>(p + (size_t)i * S, pv);
-    load_row<double, S>(q + (size_t)i * S, qv);
     const double di = dinv[i];
 #pragma unroll
     for (int c = 0; c < S; ++c) {
-      xv[c] = fma(alpha[c], pv[c], xv[c]);
-      rv[c] = fma(-alpha[c], qv[c], rv[c]);
-      acc[c] = fma(rv[c], rv[c] * di, acc[c]);
-      acc[S + c] = fma(rv[c], rv[c], acc[S + c]);
+      wv[c] = -wv[c];
+      const double u = di * rv[c];
+      acc[c] = fma(rv[c], u, acc[c]);
+      acc[S + c] = fma(wv[c], u, acc[S + c]);
+      acc[2 * S + c] = fma(rv[c], rv[c], acc[2 * S + c]);
     }
-    store_row<double, S>(x + (size_t)i * S, xv);
-    store_row<double, S>(r + (size_t)i * S, rv);
+    store_row<double, S>(w + (size_t)i * S, wv);
   }
-  write_partial<2 * S, NT>(acc, red, pout);
+  write_partial<3 * S, NT>(acc, red, pout);
+}
+
+// One iteration (it counted from the start of this (re)start).
+template <int S, int NT>
+__global__ __launch_bounds__(NT) void k_cgcg_iter(OpDev<double> op, double* __restrict__ x,
+                                                  const double* __restrict__ rin, double* __restrict__ rout,
+                                                  const double* __restrict__ win, double* __restrict__ wout,
+                                                  double* __restrict__ p, const double* __restrict__ sin,
+                                                  double* __restrict__ sout, const double* __restrict__ dinv,
+                                                  CgIter* log, int it, int first, double* state, double eta2,
+                                                  const double* pin, int nparts, double* pout, int* flag, int n) {
+  __shared__ double red[pow2_at_least(3 * S) * (NT / 64)];
+  reduce_partials<3 * S, NT>(pin, nparts, red);
+  double alpha[S], beta[S];
+#pragma unroll
+  for (int c = 0; c < S; ++c) {
+    const double g = uniform_d(red[c]);
+    const double d = uniform_d(red[S + c]);
+    const double rr = uniform_d(red[2 * S + c]);
+    const double thr = (first && it == 0) ? eta2 * rr : uniform_d(state[c]);
+    const bool active = rr > thr;
+    double a = 0.0, b = 0.0;
+    bool bad = false;
+    if (active) {
+      if (it == 0) {
+        bad = !(d > 0.0);
+        a = bad ? 0.0 : g / d;
+      } else {
+        const double gp = uniform_d(log[it - 1].rho[c]);
+        const double ap = uniform_d(log[it - 1].alpha[c]);
+        b = g / gp;
+        const double den = d - b * g / ap;
+        bad = !(den > 0.0) || !(gp > 0.0) || !(ap > 0.0);
+        a = bad ? 0.0 : g / den;
+        if (bad) b = 0.0;
+      }
+    }
+    alpha[c] = a;
+    beta[c] = b;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (first && it == 0) state[c] = thr;
+      log[it].rho[c] = g;
+      log[it].rr[c] = rr;
+      log[it].sigma[c] = d;
+      log[it].alpha[c] = a;
+      if (bad) flag[1] = it + 1;
+    }
+  }
+  __syncthreads();
+  const double* so = it > 0 ? sin : nullptr;
+  double acc[3 * S];
+#pragma unroll
+  for (int c = 0; c < 3 * S; ++c) acc[c] = 0.0;
+  int lo, hi;
+  op_rows(blockIdx.x, gridDim.x, n, lo, hi);
+  for (int i = lo + threadIdx.x; i < hi; i += NT) {
+    double rv[S], wv[S], pv[S], sv[S], xv[S];
+    load_row<double, S>(rin + (size_t)i * S, rv);
+    load_row<double, S>(win + (size_t)i * S, wv);
+    load_row<double, S>(x + (size_t)i * S, xv);
+    const double di = dinv[i];
+    if (so) {
+      load_row<double, S>(p + (size_t)i * S, pv);
+      load_row<double, S>(so + (size_t)i * S, sv);
+    } else {
+#pragma unroll
+      for (int c = 0; c < S; ++c) pv[c] = sv[c] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+      pv[c] = fma(beta[c], pv[c], di * rv[c]);
+      sv[c] = fma(beta[c], sv[c], wv[c]);
+      xv[c] = fma(alpha[c], pv[c], xv[c]);
+      rv[c] = fma(-alpha[c], sv[c], rv[c]);
+    }
+    store_row<double, S>(p + (size_t)i * S, pv);
+    store_row<double, S>(sout + (size_t)i * S, sv);
+    store_row<double, S>(x + (size_t)i * S, xv);
+    store_row<double, S>(rout + (size_t)i * S, rv);
+    double wn[S];
+    op_row_fn<double, S>(op, i, [&](int j, double (&u)[S]) { cgcg_u<S>(rin, win, so, dinv, alpha, beta, j, u); },
+                         wn);
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+      wn[c] = -wn[c];
+      const double u = di * rv[c];
+      acc[c] = fma(rv[c], u, acc[c]);
+      acc[S + c] = fma(wn[c], u, acc[S + c]);
+      acc[2 * S + c] = fma(rv[c], rv[c], acc[2 * S + c]);
+    }
+    store_row<double, S>(wout + (size_t)i * S, wn);
+  }
+  write_partial<3 * S, NT>(acc, red, pout);
 }
 
 // r = A x - B (the residual of (-A) x = -B); partials r^T r and B^T B.
@@ -326,8 +361,8 @@ InnerCG::InnerCG(const OpDev<double>& op, int n, int S, int pc, double eta, int 
   p0_.alloc(blk);
   p1_.alloc(blk);
   q_.alloc(blk);
-  partA_.alloc((size_t)kSGrid * 2 * S * sizeof(double));
-  partB_.alloc((size_t)kSGrid * 2 * S * sizeof(double));
+  partA_.alloc((size_t)kSGrid * 3 * S * sizeof(double));
+  partB_.alloc((size_t)kSGrid * 3 * S * sizeof(double));
   log_.alloc((size_t)(max_iter + kCgChunk) * sizeof(CgIter));
   state_.alloc(64 * sizeof(double));
   tot_.alloc(64 * sizeof(double));
@@ -353,19 +388,22 @@ static void cg_launch_init(const double* B, double* x, double* r, const double* 
 }
 
 template <int S>
-static void cg_launch_iter(const OpDev<double>& op, double* x, double* r, const double* dinv, const double* pold,
-                           double* pnew, double* q, CgIter* log, int it, int first, double* state, double eta2,
-                           double* partA, double* partB, int* flag, int n, int grid, hipStream_t st,
-                           KernelTimer* kt) {
+static void cg_launch_cgcg_start(const OpDev<double>& op, const double* r, const double* dinv, double* w, double* pout,
+                                 int n, int grid, hipStream_t st) {
   constexpr int NT = stream_threads(S);
-  if (kt) kt->mark(LYAP_K_CG_DIR);
-  hipLaunchKernelGGL((k_cg_dir<S, NT>), dim3(grid), dim3(NT), 0, st, op, r, dinv, pold, pnew, q, log, it, first,
-                     state, eta2, partA, grid, partB, n);
-  LYAP_LAUNCHED("k_cg_dir");
-  if (kt) kt->mark(LYAP_K_CG_UPD);
-  hipLaunchKernelGGL((k_cg_upd<S, NT>), dim3(grid), dim3(NT), 0, st, x, r, pnew, q, dinv, log, it, state, partB,
-                     grid, partA, flag, n);
-  LYAP_LAUNCHED("k_cg_upd");
+  hipLaunchKernelGGL((k_cgcg_start<S, NT>), dim3(grid), dim3(NT), 0, st, op, r, dinv, w, pout, n);
+  LYAP_LAUNCHED("k_cgcg_start");
+}
+
+template <int S>
+static void cg_launch_cgcg_iter(const OpDev<double>& op, double* x, const double* rin, double* rout, const double* win,
+                                double* wout, double* p, const double* sin, double* sout, const double* dinv,
+                                CgIter* log, int it, int first, double* state, double eta2, const double* pin,
+                                double* pout, int* flag, int n, int grid, hipStream_t st) {
+  constexpr int NT = stream_threads(S);
+  hipLaunchKernelGGL((k_cgcg_iter<S, NT>), dim3(grid), dim3(NT), 0, st, op, x, rin, rout, win, wout, p, sin, sout,
+                     dinv, log, it, first, state, eta2, pin, grid, pout, flag, n);
+  LYAP_LAUNCHED("k_cgcg_iter");
 }
 
 template <int S>
@@ -468,20 +506,40 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
       default: cg_launch_init<4>(B, X, r_.as<double>(), dinv_.as<double>(), n_, mode, partA_.as<double>(), grid_, st_); break;
     }
   };
-  auto iter = [&](int it, int first) {
-    double* pn = (it % 2 == 0) ? p0_.as<double>() : p1_.as<double>();
-    const double* po = (it % 2 == 0) ? p1_.as<double>() : p0_.as<double>();
-    CgIter* lg = log_.as<CgIter>();
+  if (!w0_.p) {
+    const size_t blk = (size_t)n_ * S * sizeof(double);
+    r1_.alloc(blk);
+    w0_.alloc(blk);
+    w1_.alloc(blk);
+    s0_.alloc(blk);
+    s1_.alloc(blk);
+  }
+  // buffers of iteration it: r, w in [it % 2], out [(it + 1) % 2]; s out [it % 2]
+  auto rbuf = [&](int k) { return (k % 2 == 0) ? r_.as<double>() : r1_.as<double>(); };
+  auto wbuf = [&](int k) { return (k % 2 == 0) ? w0_.as<double>() : w1_.as<double>(); };
+  auto sbuf = [&](int k) { return (k % 2 == 0) ? s0_.as<double>() : s1_.as<double>(); };
+  auto start_k = [&]() {
     switch (S) {
-      case 1: cg_launch_iter<1>(op_, X, r_.as<double>(), dinv_.as<double>(), po, pn, q_.as<double>(), lg, it, first,
-                                state_.as<double>(), eta2, partA_.as<double>(), partB_.as<double>(), flag_.as<int>(),
-                                n_, grid_, st_, kt); break;
-      case 2: cg_launch_iter<2>(op_, X, r_.as<double>(), dinv_.as<double>(), po, pn, q_.as<double>(), lg, it, first,
-                                state_.as<double>(), eta2, partA_.as<double>(), partB_.as<double>(), flag_.as<int>(),
-                                n_, grid_, st_, kt); break;
-      default: cg_launch_iter<4>(op_, X, r_.as<double>(), dinv_.as<double>(), po, pn, q_.as<double>(), lg, it, first,
-                                 state_.as<double>(), eta2, partA_.as<double>(), partB_.as<double>(), flag_.as<int>(),
-                                 n_, grid_, st_, kt); break;
+      case 1: cg_launch_cgcg_start<1>(op_, r_.as<double>(), dinv_.as<double>(), w0_.as<double>(), partA_.as<double>(), n_, grid_, st_); break;
+      case 2: cg_launch_cgcg_start<2>(op_, r_.as<double>(), dinv_.as<double>(), w0_.as<double>(), partA_.as<double>(), n_, grid_, st_); break;
+      default: cg_launch_cgcg_start<4>(op_, r_.as<double>(), dinv_.as<double>(), w0_.as<double>(), partA_.as<double>(), n_, grid_, st_); break;
+    }
+  };
+  auto iter = [&](int it, int first) {
+    double* pin = (it % 2 == 0) ? partA_.as<double>() : partB_.as<double>();
+    double* pout = (it % 2 == 0) ? partB_.as<double>() : partA_.as<double>();
+    CgIter* lg = log_.as<CgIter>();
+    if (kt) kt->mark(LYAP_K_CG_DIR);
+    switch (S) {
+      case 1: cg_launch_cgcg_iter<1>(op_, X, rbuf(it), rbuf(it + 1), wbuf(it), wbuf(it + 1), p0_.as<double>(),
+                                     sbuf(it + 1), sbuf(it), dinv_.as<double>(), lg, it, first, state_.as<double>(),
+                                     eta2, pin, pout, flag_.as<int>(), n_, grid_, st_); break;
+      case 2: cg_launch_cgcg_iter<2>(op_, X, rbuf(it), rbuf(it + 1), wbuf(it), wbuf(it + 1), p0_.as<double>(),
+                                     sbuf(it + 1), sbuf(it), dinv_.as<double>(), lg, it, first, state_.as<double>(),
+                                     eta2, pin, pout, flag_.as<int>(), n_, grid_, st_); break;
+      default: cg_launch_cgcg_iter<4>(op_, X, rbuf(it), rbuf(it + 1), wbuf(it), wbuf(it + 1), p0_.as<double>(),
+                                      sbuf(it + 1), sbuf(it), dinv_.as<double>(), lg, it, first, state_.as<double>(),
+                                      eta2, pin, pout, flag_.as<int>(), n_, grid_, st_); break;
     }
   };
   auto true_res = [&]() {
@@ -496,6 +554,7 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
   double worst = 0.0;
   for (int start = 0; start <= kCgRestarts; ++start) {
     init(start == 0 ? 0 : 1);
+    start_k();
     int it = 0;
     bool done = false;
     const bool harvesting = harvest_every_ > 0 && start == 0;
@@ -503,7 +562,7 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
       if (!harvesting || (int)hr_.size() >= harvest_keep_) return;
       hr_.emplace_back((size_t)n_ * S * sizeof(double));
       hx_.emplace_back((size_t)n_ * S * sizeof(double));
-      LYAP_HIP(hipMemcpyAsync(hr_.back().p, r_.p, (size_t)n_ * S * sizeof(double), hipMemcpyDeviceToDevice, st_));
+      LYAP_HIP(hipMemcpyAsync(hr_.back().p, rbuf(it), (size_t)n_ * S * sizeof(double), hipMemcpyDeviceToDevice, st_));
       LYAP_HIP(hipMemcpyAsync(hx_.back().p, X, (size_t)n_ * S * sizeof(double), hipMemcpyDeviceToDevice, st_));
     };
     snapshot();

@@ -58,6 +58,7 @@ class InnerCG {
   CgStats stats_;
   PcNetGpu* net_ = nullptr;
   DevBuf z_, partZ_;
+  DevBuf r1_, w0_, w1_, s0_, s1_;  // double-buffered r, w = K M r, s = K p of the single-reduction CG
   int harvest_every_ = 0, harvest_keep_ = 0;
   std::vector<DevBuf> hr_, hx_;
 };
