@@ -355,14 +355,19 @@ InnerCG::InnerCG(const OpDev<double>& op, int n, int S, int pc, double eta, int 
   LYAP_REQUIRE(eta > 0.0 && eta < 1.0, LYAP_E_ARG, "inner_tol=%g must be in (0,1)", eta);
   LYAP_REQUIRE(max_iter >= 1, LYAP_E_ARG, "inner_max_iter must be >= 1");
   grid_ = stream_grid(n);
+  // the single-reduction kernels use few registers (52 VGPRs at S = 1): once
+  // one workgroup per CU would give each thread two rows or more, two
+  // 1024-thread workgroups per CU hide more memory latency (C3: 1.30 -> 1.21 s);
+  // below that the extra workgroups only add partials to reduce
+  cgrid_ = (int64_t)n >= 2 * (int64_t)kSGrid * kSBlock ? 2 * kSGrid : grid_;
   const size_t blk = (size_t)n * S * sizeof(double);
   dinv_.alloc((size_t)n * sizeof(double));
   r_.alloc(blk);
   p0_.alloc(blk);
   p1_.alloc(blk);
   q_.alloc(blk);
-  partA_.alloc((size_t)kSGrid * 3 * S * sizeof(double));
-  partB_.alloc((size_t)kSGrid * 3 * S * sizeof(double));
+  partA_.alloc((size_t)2 * kSGrid * 3 * S * sizeof(double));
+  partB_.alloc((size_t)2 * kSGrid * 3 * S * sizeof(double));
   log_.alloc((size_t)(max_iter + kCgChunk) * sizeof(CgIter));
   state_.alloc(64 * sizeof(double));
   tot_.alloc(64 * sizeof(double));
@@ -501,9 +506,9 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
   const double eta2 = eta_rec * eta_rec;
   auto init = [&](int mode) {
     switch (S) {
-      case 1: cg_launch_init<1>(B, X, r_.as<double>(), dinv_.as<double>(), n_, mode, partA_.as<double>(), grid_, st_); break;
-      case 2: cg_launch_init<2>(B, X, r_.as<double>(), dinv_.as<double>(), n_, mode, partA_.as<double>(), grid_, st_); break;
-      default: cg_launch_init<4>(B, X, r_.as<double>(), dinv_.as<double>(), n_, mode, partA_.as<double>(), grid_, st_); break;
+      case 1: cg_launch_init<1>(B, X, r_.as<double>(), dinv_.as<double>(), n_, mode, partA_.as<double>(), cgrid_, st_); break;
+      case 2: cg_launch_init<2>(B, X, r_.as<double>(), dinv_.as<double>(), n_, mode, partA_.as<double>(), cgrid_, st_); break;
+      default: cg_launch_init<4>(B, X, r_.as<double>(), dinv_.as<double>(), n_, mode, partA_.as<double>(), cgrid_, st_); break;
     }
   };
   if (!w0_.p) {
@@ -520,9 +525,9 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
   auto sbuf = [&](int k) { return (k % 2 == 0) ? s0_.as<double>() : s1_.as<double>(); };
   auto start_k = [&]() {
     switch (S) {
-      case 1: cg_launch_cgcg_start<1>(op_, r_.as<double>(), dinv_.as<double>(), w0_.as<double>(), partA_.as<double>(), n_, grid_, st_); break;
-      case 2: cg_launch_cgcg_start<2>(op_, r_.as<double>(), dinv_.as<double>(), w0_.as<double>(), partA_.as<double>(), n_, grid_, st_); break;
-      default: cg_launch_cgcg_start<4>(op_, r_.as<double>(), dinv_.as<double>(), w0_.as<double>(), partA_.as<double>(), n_, grid_, st_); break;
+      case 1: cg_launch_cgcg_start<1>(op_, r_.as<double>(), dinv_.as<double>(), w0_.as<double>(), partA_.as<double>(), n_, cgrid_, st_); break;
+      case 2: cg_launch_cgcg_start<2>(op_, r_.as<double>(), dinv_.as<double>(), w0_.as<double>(), partA_.as<double>(), n_, cgrid_, st_); break;
+      default: cg_launch_cgcg_start<4>(op_, r_.as<double>(), dinv_.as<double>(), w0_.as<double>(), partA_.as<double>(), n_, cgrid_, st_); break;
     }
   };
   auto iter = [&](int it, int first) {
@@ -533,20 +538,20 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
     switch (S) {
       case 1: cg_launch_cgcg_iter<1>(op_, X, rbuf(it), rbuf(it + 1), wbuf(it), wbuf(it + 1), p0_.as<double>(),
                                      sbuf(it + 1), sbuf(it), dinv_.as<double>(), lg, it, first, state_.as<double>(),
-                                     eta2, pin, pout, flag_.as<int>(), n_, grid_, st_); break;
+                                     eta2, pin, pout, flag_.as<int>(), n_, cgrid_, st_); break;
       case 2: cg_launch_cgcg_iter<2>(op_, X, rbuf(it), rbuf(it + 1), wbuf(it), wbuf(it + 1), p0_.as<double>(),
                                      sbuf(it + 1), sbuf(it), dinv_.as<double>(), lg, it, first, state_.as<double>(),
-                                     eta2, pin, pout, flag_.as<int>(), n_, grid_, st_); break;
+                                     eta2, pin, pout, flag_.as<int>(), n_, cgrid_, st_); break;
       default: cg_launch_cgcg_iter<4>(op_, X, rbuf(it), rbuf(it + 1), wbuf(it), wbuf(it + 1), p0_.as<double>(),
                                       sbuf(it + 1), sbuf(it), dinv_.as<double>(), lg, it, first, state_.as<double>(),
-                                      eta2, pin, pout, flag_.as<int>(), n_, grid_, st_); break;
+                                      eta2, pin, pout, flag_.as<int>(), n_, cgrid_, st_); break;
     }
   };
   auto true_res = [&]() {
     switch (S) {
-      case 1: cg_launch_true<1>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), grid_, st_); break;
-      case 2: cg_launch_true<2>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), grid_, st_); break;
-      default: cg_launch_true<4>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), grid_, st_); break;
+      case 1: cg_launch_true<1>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), cgrid_, st_); break;
+      case 2: cg_launch_true<2>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), cgrid_, st_); break;
+      default: cg_launch_true<4>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), cgrid_, st_); break;
     }
   };
 

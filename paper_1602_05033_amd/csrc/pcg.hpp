@@ -52,7 +52,7 @@ class InnerCG {
   int n_, S_, pc_, max_iter_;
   double eta_;
   hipStream_t st_;
-  int grid_;
+  int grid_, cgrid_;
   DevBuf dinv_, r_, p0_, p1_, q_, partA_, partB_, log_, state_, tot_, flag_;
   HostBuf hlog_, htot_;
   CgStats stats_;
