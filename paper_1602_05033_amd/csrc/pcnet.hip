@@ -2,8 +2,9 @@
 // the energy-norm loss), Adam, and the component entry points used by the
 // tests.  See pcnet.hpp for the definition.
 //
-// Convolutions: one thread per cell, the weights in LDS, neighbours read
-// through the caches (channel counts are small: 2 -> C -> C, C <= 8).  Weight
+// Convolutions: the weights in LDS, neighbours read through the caches
+// (channel counts are small: 2 -> C -> C, C <= 8); four consecutive cells per
+// thread with vector loads when nx is a multiple of 4, else one per thread.  Weight
 // gradients: 8 x 8 x 4 cell tiles with a one-cell halo staged in LDS, each
 // thread accumulating a few of the C*CI*27 weights over the tile; per-tile
 // partials are summed in FP64 in a fixed order (two passes).
@@ -136,6 +137,85 @@ __global__ __launch_bounds__(kPcThreads) void k_pc_convT(const float* __restrict
   }
 #pragma unroll
   for (int i = 0; i < CI; ++i) out[(size_t)i * n + p] = acc[i];
+}
+
+// Both convolutions with four consecutive x cells per thread, for nx a
+// multiple of 4: per (dz, dy) and input channel, one aligned float4 load and
+// two edge loads give the six inputs x0-1 .. x0+4 that the three x taps of the
+// four cells read, so a cell costs about a quarter of the loads of the kernels
+// above.  TRANS = false: out[o][p] = sum_t sum_i W[o][i][t] in[i][p + t];
+// TRANS = true (the adjoint): out[i][q] = sum_t sum_o W[o][i][t] in[o][q - t].
+// The terms are added in the same order as in k_pc_conv / k_pc_convT; taps
+// outside the grid in x add an exact zero instead of being skipped.
+template <int CI, int CO, bool TRANS>
+__global__ __launch_bounds__(kPcThreads) void k_pc_conv4(const float* __restrict__ in, const float* __restrict__ W,
+                                                         float* __restrict__ out, int nx, int ny, int nz) {
+  constexpr int NIN = TRANS ? CO : CI;
+  constexpr int NOUT = TRANS ? CI : CO;
+  constexpr int SG = TRANS ? -1 : 1;
+  const int n = nx * ny * nz;
+  const int nq = n / 4;
+  const int lb = xcd_block(blockIdx.x, (nq + kPcThreads - 1) / kPcThreads);
+  if (lb < 0) return;
+  __shared__ float sW[CO * CI * 27];
+  for (int e = threadIdx.x; e < CO * CI * 27; e += kPcThreads) sW[e] = W[e];
+  __syncthreads();
+  const int qd = lb * kPcThreads + threadIdx.x;
+  if (qd >= nq) return;
+  const int p0 = 4 * qd;
+  const int nxy = nx * ny;
+  const int z = p0 / nxy, y = (p0 / nx) % ny, x0 = p0 % nx;
+  float acc[NOUT][4];
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[o][k] = 0.f;
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int zz = z + SG * dz;
+    if (zz < 0 || zz >= nz) continue;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int yy = y + SG * dy;
+      if (yy < 0 || yy >= ny) continue;
+      const size_t base = (size_t)zz * nxy + (size_t)yy * nx + x0;
+      float v[NIN][6];
+#pragma unroll
+      for (int c = 0; c < NIN; ++c) {
+        const float* row = in + (size_t)c * n + base;
+        const float4 mid = *reinterpret_cast<const float4*>(row);
+        v[c][0] = x0 > 0 ? row[-1] : 0.f;
+        v[c][1] = mid.x;
+        v[c][2] = mid.y;
+        v[c][3] = mid.z;
+        v[c][4] = mid.w;
+        v[c][5] = x0 + 4 < nx ? row[4] : 0.f;
+      }
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int t = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+        const int sh = SG * dx;
+#pragma unroll
+        for (int c = 0; c < NIN; ++c)
+#pragma unroll
+          for (int o = 0; o < NOUT; ++o) {
+            const float w = TRANS ? sW[(c * CI + o) * 27 + t] : sW[(o * CI + c) * 27 + t];
+            // a tap outside the grid in x reads the zero padding (adds 0)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[o][k] = fmaf(w, v[c][1 + k + sh], acc[o][k]);
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    float4 r;
+    r.x = acc[o][0];
+    r.y = acc[o][1];
+    r.z = acc[o][2];
+    r.w = acc[o][3];
+    *reinterpret_cast<float4*>(out + (size_t)o * n + p0) = r;
+  }
 }
 
 // z = dinv r + s (d0 + f d1); optional partial z.q per workgroup
@@ -340,15 +420,25 @@ void PcNetGpu::get_weights(float* host) const {
 
 template <int CI, int CO>
 void PcNetGpu::conv(const float* in, const float* W, float* out) {
-  hipLaunchKernelGGL((k_pc_conv<CI, CO>), dim3(xcd_grid((n_ + kPcThreads - 1) / kPcThreads)), dim3(kPcThreads), 0,
-                     st_, in, W, out, nx_, ny_, nz_);
+  if (nx_ % 4 == 0) {
+    hipLaunchKernelGGL((k_pc_conv4<CI, CO, false>), dim3(xcd_grid((n_ / 4 + kPcThreads - 1) / kPcThreads)),
+                       dim3(kPcThreads), 0, st_, in, W, out, nx_, ny_, nz_);
+  } else {
+    hipLaunchKernelGGL((k_pc_conv<CI, CO>), dim3(xcd_grid((n_ + kPcThreads - 1) / kPcThreads)), dim3(kPcThreads), 0,
+                       st_, in, W, out, nx_, ny_, nz_);
+  }
   LYAP_LAUNCHED("k_pc_conv");
 }
 
 template <int CO, int CI>
 void PcNetGpu::convT(const float* in, const float* W, float* out) {
-  hipLaunchKernelGGL((k_pc_convT<CO, CI>), dim3(xcd_grid((n_ + kPcThreads - 1) / kPcThreads)), dim3(kPcThreads), 0,
-                     st_, in, W, out, nx_, ny_, nz_);
+  if (nx_ % 4 == 0) {
+    hipLaunchKernelGGL((k_pc_conv4<CI, CO, true>), dim3(xcd_grid((n_ / 4 + kPcThreads - 1) / kPcThreads)),
+                       dim3(kPcThreads), 0, st_, in, W, out, nx_, ny_, nz_);
+  } else {
+    hipLaunchKernelGGL((k_pc_convT<CO, CI>), dim3(xcd_grid((n_ + kPcThreads - 1) / kPcThreads)), dim3(kPcThreads), 0,
+                       st_, in, W, out, nx_, ny_, nz_);
+  }
   LYAP_LAUNCHED("k_pc_convT");
 }
 

@@ -27,7 +27,8 @@ def _net_from(W32, C):
     return N.PcNet.from_flat(np.asarray(W32, dtype=np.float64), C)
 
 
-@pytest.mark.parametrize("shape,C", [((7, 6, 5), 4), ((9, 9, 9), 2), ((11, 10, 1), 8)])
+@pytest.mark.parametrize("shape,C", [((7, 6, 5), 4), ((9, 9, 9), 2), ((11, 10, 1), 8),
+                                     ((8, 6, 5), 4), ((12, 9, 7), 2), ((16, 16, 1), 8)])  # nx % 4 == 0: vector path
 def test_pcnet_apply_parity(lib, shape, C):
     b = _b()
     nx, ny, nz = shape
