@@ -263,9 +263,9 @@ lyap_status sylv_solve(const lyap_op* A, const lyap_op* B, const double* C1, int
  * symmetric positive definite, treated as the standard equation of
  * L^{-1} A L^{-T} and L^{-1} C (E = L L^T; Section 6, Example 3) without
  * forming L: block Lanczos for E^{-1} A in the E inner product (basis W with
- * W^T E W = I), one FP64 conjugate-gradient solve with E per step (Jacobi
- * preconditioned unless inner_pc = LYAP_PC_NONE; accepted on the true relative
- * residual <= inner_tol), Proposition 1 on T_m, truncation and Z = W_m M as in
+ * W^T E W = I), one FP64 conjugate-gradient solve with E per step (inner_pc
+ * LYAP_PC_JACOBI or LYAP_PC_NONE, others E_UNSUPPORTED; accepted on the true
+ * relative residual <= inner_tol), Proposition 1 on T_m, truncation and Z = W_m M as in
  * lyap_solve, so Z Z^T approximates X.
  *  A     operator, symmetric negative definite; E operator (any kind),
  *        symmetric positive definite, same n.

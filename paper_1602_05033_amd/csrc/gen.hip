@@ -343,8 +343,7 @@ lyap_status gen_impl(const lyap_op* A, const lyap_op* E, const double* C, int S,
   make_op_f64(A, run.opA, st);
   const lyap_op ne = negated_op(E, run, st);
   make_op_f64(&ne, run.opNegE, st);
-  run.cg.reset(new InnerCG(run.opNegE.dev, n, S, o.inner_pc == LYAP_PC_NONE ? LYAP_PC_NONE : LYAP_PC_JACOBI,
-                           o.inner_tol, o.inner_max_iter, st));
+  run.cg.reset(new InnerCG(run.opNegE.dev, n, S, o.inner_pc, o.inner_tol, o.inner_max_iter, st));
   const size_t blk = (size_t)n * S * sizeof(double);
   run.Q.alloc(blk);
   run.X.alloc(blk);
@@ -568,6 +567,8 @@ extern "C" lyap_status lyap_solve_gen(const lyap_op* A, const lyap_op* E, const 
     LYAP_REQUIRE(o.method == LYAP_METHOD_STD, LYAP_E_UNSUPPORTED,
                  "lyap_solve_gen builds a standard Krylov space (method must be LYAP_METHOD_STD)");
     LYAP_REQUIRE(o.storage == LYAP_STORE_F64, LYAP_E_UNSUPPORTED, "lyap_solve_gen stores the basis in FP64 only");
+    LYAP_REQUIRE(o.inner_pc == LYAP_PC_NONE || o.inner_pc == LYAP_PC_JACOBI, LYAP_E_UNSUPPORTED,
+                 "lyap_solve_gen solves with E by CG with inner_pc NONE or JACOBI");
     lyap_status st = gen_impl(A, E, C, s, ldc, o, out);
     out->status = st;
     return st;

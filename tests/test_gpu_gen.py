@@ -106,6 +106,9 @@ def test_gen_errors(lib):
     with pytest.raises(b.LyapError) as e:
         b.lyap_solve_gen(dA, dE, _dev(gaussian_C(Ao.n, 2, 1)), storage=b.STORE_F32)
     assert e.value.status == b.E_UNSUPPORTED
+    with pytest.raises(b.LyapError) as e:
+        b.lyap_solve_gen(dA, dE, _dev(gaussian_C(Ao.n, 1, 1)), inner_pc=b.PC_LEARNED)
+    assert e.value.status == b.E_UNSUPPORTED
     neg = laplace2d(10)                       # symmetric negative definite: not a mass matrix
     with pytest.raises(b.LyapError) as e:
         b.lyap_solve_gen(dA, b.device_op(neg), _dev(gaussian_C(Ao.n, 2, 1)))
