@@ -205,6 +205,7 @@ __global__ void k_zform(const DcMerge* md, const DcScal* ms, int ell, int k, int
 // test of a pair depends on the previous pair's outcome, so when any pair
 // qualifies one thread walks the compacted candidate list in order.
 constexpr int kDefThreads = 1024;
+constexpr int kDefLds = 2048;  // candidates staged in LDS for the run-by-run walk
 
 __device__ __forceinline__ int block_excl_scan(int v, int* sh, int* total) {
   // Hillis-Steele over kDefThreads values in shared memory
@@ -230,6 +231,8 @@ __global__ __launch_bounds__(kDefThreads) void k_deflate(const DcMerge* md, DcSc
   __shared__ int sh[kDefThreads];
   __shared__ double redd[kDefThreads / 64 * 2];
   __shared__ int any_trig, s_Kc, s_Ks, s_Kn, s_Nr;
+  __shared__ int s_nd[kDefLds], s_tr[kDefLds];
+  __shared__ double s_dn[kDefLds], s_zn[kDefLds];
   const DcMerge g = md[blockIdx.x];
   DcScal& s = ms[blockIdx.x];
   const int a = g.a, K = g.K;
@@ -305,8 +308,104 @@ __global__ __launch_bounds__(kDefThreads) void k_deflate(const DcMerge* md, DcSc
     if (t == 0) { s.skip = 0; s.Kn = Kc; s.Kd = Ks; s.r = r; }
     return;
   }
-  // ---- sequential walk over the candidates (rotations depend on the order)
-  if (t == 0) {
+  // ---- walk over the candidates (rotations depend on the order)
+  if (Kc <= kDefLds) {
+    // The walk's state only differs from the candidates' own values inside a
+    // run of consecutive rotations, and a run can only start at a pair that
+    // passes the test with the original values.  So one wave visits just the
+    // runs (from the list of such pairs) with the candidates staged in LDS,
+    // every lane taking the same decisions and rotating its own rows of R;
+    // the survivors are then compacted by the whole workgroup.  Rotations,
+    // values and order are those of the plain walk below.
+    for (int q = t; q < Kc; q += kDefThreads) {
+      s_nd[q] = nd[a + q];
+      s_dn[q] = Dn[a + q];
+      s_zn[q] = zn[a + q];
+    }
+    __syncthreads();
+    const int qc = (Kc + kDefThreads - 1) / kDefThreads;
+    const int q0 = min(t * qc, Kc), q1 = min(q0 + qc, Kc);
+    auto pair_rot = [&](int q) {
+      const double zp = s_zn[q - 1], zw = s_zn[q];
+      const double tt = hypot(zw, zp);
+      return fabs((s_dn[q] - s_dn[q - 1]) * (zw / tt) * (zp / tt)) <= tol;
+    };
+    int ntr = 0;
+    for (int q = max(q0, 1); q < q1; ++q) ntr += pair_rot(q) ? 1 : 0;
+    int T = 0;
+    {
+      int o = block_excl_scan(ntr, sh, &T);
+      for (int q = max(q0, 1); q < q1; ++q)
+        if (pair_rot(q)) s_tr[o++] = q;
+    }
+    __syncthreads();
+    if (t < 64) {
+      const int nr = 4 * ell;
+      int last = -1, Nr = 0;
+      for (int x = 0; x < T; ++x) {
+        const int qs = s_tr[x];
+        if (qs <= last) continue;
+        int p = qs - 1;
+        int pw = s_nd[p];
+        double pz = s_zn[p], pd = s_dn[p];
+        int q = qs;
+        for (; q < Kc; ++q) {
+          const int w = s_nd[q];
+          const double zw = s_zn[q], dw = s_dn[q];
+          const double tt = hypot(zw, pz);
+          const double cc = zw / tt, ss = pz / tt;
+          if (!(fabs((dw - pd) * cc * ss) <= tol)) break;
+          const int cp = col(pw), cw = col(w);
+          for (int row = t; row < nr; row += 64) {
+            double* R = Rw + (size_t)row * k + a;
+            const double qp = R[cp], qw = R[cw];
+            R[cp] = cc * qp - ss * qw;
+            R[cw] = ss * qp + cc * qw;
+          }
+          if (t == 0) {
+            rdl[a + Nr] = pw;
+            rdv[a + Nr] = pd * cc * cc + dw * ss * ss;
+          }
+          ++Nr;
+          s_nd[p] = -1;  // rotated out
+          p = q;
+          pw = w;
+          pz = tt;
+          pd = pd * ss * ss + dw * cc * cc;
+        }
+        s_zn[p] = pz;  // the run's survivor
+        s_dn[p] = pd;
+        last = q;
+      }
+      if (t == 0) s_Nr = Nr;
+    }
+    __syncthreads();
+    int kept = 0;
+    for (int q = q0; q < q1; ++q) kept += s_nd[q] >= 0 ? 1 : 0;
+    int Kn = 0;
+    {
+      int o = block_excl_scan(kept, sh, &Kn);
+      for (int q = q0; q < q1; ++q)
+        if (s_nd[q] >= 0) {
+          nd[a + o] = s_nd[q];
+          Dn[a + o] = s_dn[q];
+          zn[a + o] = s_zn[q];
+          ++o;
+        }
+    }
+    if (t == 0) {
+      const int Nr = s_Nr;
+      for (int x = 1; x < Nr; ++x) {  // rotated-out values are nearly sorted
+        const double v = rdv[a + x];
+        const int iw = rdl[a + x];
+        int y = x - 1;
+        while (y >= 0 && rdv[a + y] > v) { rdv[a + y + 1] = rdv[a + y]; rdl[a + y + 1] = rdl[a + y]; --y; }
+        rdv[a + y + 1] = v;
+        rdl[a + y + 1] = iw;
+      }
+      s_Kn = Kn;
+    }
+  } else if (t == 0) {
     const int nr = 4 * ell;
     int p = -1, Kn = 0, Nr = 0;
     double pz = 0.0, pd = 0.0;
