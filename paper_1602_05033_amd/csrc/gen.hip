@@ -343,7 +343,12 @@ lyap_status gen_impl(const lyap_op* A, const lyap_op* E, const double* C, int S,
   make_op_f64(A, run.opA, st);
   const lyap_op ne = negated_op(E, run, st);
   make_op_f64(&ne, run.opNegE, st);
-  run.cg.reset(new InnerCG(run.opNegE.dev, n, S, o.inner_pc, o.inner_tol, o.inner_max_iter, st));
+  try {
+    run.cg.reset(new InnerCG(run.opNegE.dev, n, S, o.inner_pc, o.inner_tol, o.inner_max_iter, st));
+  } catch (const Error& e) {
+    if (e.st == LYAP_E_INDEFINITE) set_error("E has a diagonal entry <= 0: not positive definite");
+    throw;
+  }
   const size_t blk = (size_t)n * S * sizeof(double);
   run.Q.alloc(blk);
   run.X.alloc(blk);
