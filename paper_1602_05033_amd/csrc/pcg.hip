@@ -267,14 +267,14 @@ __global__ __launch_bounds__(NT) void k_fcg_dir(OpDev<double> op, const double* 
                                                 const double* __restrict__ pold, double* __restrict__ pnew,
                                                 double* __restrict__ q, const double* __restrict__ r, CgIter* log,
                                                 int it, int first, double* state, double eta2, const double* partR,
-                                                const double* partZ, int nparts, double* pout, int n) {
+                                                int nparts, const double* partZ, int nzparts, double* pout, int n) {
   __shared__ double red[pow2_at_least(2) * (NT / 64)];
   reduce_partials<2, NT>(partR, nparts, red);
   const double rr = uniform_d(red[1]);
   __syncthreads();
   double zq = 0.0;
   if (it > 0) {
-    reduce_partials<1, NT>(partZ, nparts, red);
+    reduce_partials<1, NT>(partZ, nzparts, red);
     zq = uniform_d(red[0]);
     __syncthreads();
   }
@@ -429,8 +429,9 @@ void InnerCG::solve_fcg(const double* B, double* X, KernelTimer* kt) {
   const double eta2 = eta_rec * eta_rec;
   if (!z_.p) {
     z_.alloc((size_t)n_ * sizeof(double));
-    partZ_.alloc((size_t)kSGrid * sizeof(double));
+    partZ_.alloc((size_t)net_->max_out_parts() * sizeof(double));
   }
+  int zparts = 0;
   int total = 0;
   double worst = 0.0;
   for (int start = 0; start <= kCgRestarts; ++start) {
@@ -448,14 +449,14 @@ void InnerCG::solve_fcg(const double* B, double* X, KernelTimer* kt) {
         if (kt) kt->mark(LYAP_K_CG_DIR);
         hipLaunchKernelGGL((k_fcg_dir<NT>), dim3(grid_), dim3(NT), 0, st_, op_, z_.as<double>(), po, pn,
                            q_.as<double>(), r_.as<double>(), log_.as<CgIter>(), it, start == 0 ? 1 : 0,
-                           state_.as<double>(), eta2, partA_.as<double>(), partZ_.as<double>(), grid_,
+                           state_.as<double>(), eta2, partA_.as<double>(), grid_, partZ_.as<double>(), zparts,
                            partB_.as<double>(), n_);
         if (kt) kt->mark(LYAP_K_CG_UPD);
         hipLaunchKernelGGL((k_fcg_upd<NT>), dim3(grid_), dim3(NT), 0, st_, X, r_.as<double>(), pn, q_.as<double>(),
                            log_.as<CgIter>(), it, state_.as<double>(), partB_.as<double>(), grid_,
                            partA_.as<double>(), flag_.as<int>(), n_);
         LYAP_LAUNCHED("fcg iteration");
-        net_->apply(r_.as<double>(), z_.as<double>(), q_.as<double>(), partZ_.as<double>());
+        zparts = net_->apply(r_.as<double>(), z_.as<double>(), q_.as<double>(), partZ_.as<double>());
       }
       if (kt) kt->collect();
       LYAP_HIP(hipMemcpyAsync(hlog_.p, log_.as<CgIter>() + it0, (size_t)cnt * sizeof(CgIter), hipMemcpyDeviceToHost,

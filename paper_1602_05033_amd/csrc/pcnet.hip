@@ -4,11 +4,16 @@
 //
 // Convolutions: the weights in LDS, neighbours read through the caches
 // (channel counts are small: 2 -> C -> C, C <= 8); four consecutive cells per
-// thread with vector loads when nx is a multiple of 4, else one per thread.  Weight
+// thread with vector loads when nx is a multiple of 4, else one per thread.  In
+// the preconditioner's application (nx a multiple of 4) the input channels are
+// formed inside the first convolution and the output z inside the last one,
+// so the network costs four kernels.  Weight
 // gradients: 8 x 8 x 4 cell tiles with a one-cell halo staged in LDS, each
 // thread accumulating a few of the C*CI*27 weights over the tile; per-tile
 // partials are summed in FP64 in a fixed order (two passes).
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 
 #include "pcnet.hpp"
@@ -19,7 +24,7 @@ namespace lyap {
 constexpr int kPcThreads = 256;
 constexpr int kTX = 8, kTY = 8, kTZ = 4;                    // weight-gradient tile
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;  // with halo
-constexpr int kWSeg = 32;                                    // first-pass segments of the tile sums
+constexpr int kWSeg = 32;
 
 __device__ __forceinline__ void offset_of(int t, int& dz, int& dy, int& dx) {
   dz = t / 9 - 1;
@@ -216,6 +221,186 @@ __global__ __launch_bounds__(kPcThreads) void k_pc_conv4(const float* __restrict
     r.w = acc[o][3];
     *reinterpret_cast<float4*>(out + (size_t)o * n + p0) = r;
   }
+}
+
+// The first convolution with its two input channels x0 = [u, f u], u = s r
+// (rounded to FP32), formed from r, s, f as they are read (k_pc_in_r and
+// k_pc_conv4<2, CO, false> in one pass; the same values and order).
+template <int CO>
+__global__ __launch_bounds__(kPcThreads) void k_pc_conv4_r(const double* __restrict__ r, const float* __restrict__ s,
+                                                           const float* __restrict__ f, const float* __restrict__ W,
+                                                           float* __restrict__ out, int nx, int ny, int nz) {
+  constexpr int CI = 2;
+  const int n = nx * ny * nz;
+  const int nq = n / 4;
+  const int lb = xcd_block(blockIdx.x, (nq + kPcThreads - 1) / kPcThreads);
+  if (lb < 0) return;
+  __shared__ float sW[CO * CI * 27];
+  for (int e = threadIdx.x; e < CO * CI * 27; e += kPcThreads) sW[e] = W[e];
+  __syncthreads();
+  const int qd = lb * kPcThreads + threadIdx.x;
+  if (qd >= nq) return;
+  const int p0 = 4 * qd;
+  const int nxy = nx * ny;
+  const int z = p0 / nxy, y = (p0 / nx) % ny, x0 = p0 % nx;
+  float acc[CO][4];
+#pragma unroll
+  for (int o = 0; o < CO; ++o)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[o][k] = 0.f;
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int zz = z + dz;
+    if (zz < 0 || zz >= nz) continue;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int yy = y + dy;
+      if (yy < 0 || yy >= ny) continue;
+      const size_t base = (size_t)zz * nxy + (size_t)yy * nx + x0;
+      double rv[6];
+      float sv[6], fv[6];
+      {
+        const double2 r01 = *reinterpret_cast<const double2*>(r + base);
+        const double2 r23 = *reinterpret_cast<const double2*>(r + base + 2);
+        const float4 s4 = *reinterpret_cast<const float4*>(s + base);
+        const float4 f4 = *reinterpret_cast<const float4*>(f + base);
+        rv[1] = r01.x; rv[2] = r01.y; rv[3] = r23.x; rv[4] = r23.y;
+        sv[1] = s4.x; sv[2] = s4.y; sv[3] = s4.z; sv[4] = s4.w;
+        fv[1] = f4.x; fv[2] = f4.y; fv[3] = f4.z; fv[4] = f4.w;
+        const bool lo = x0 > 0, hi = x0 + 4 < nx;
+        rv[0] = lo ? r[base - 1] : 0.0;
+        sv[0] = lo ? s[base - 1] : 0.f;
+        fv[0] = lo ? f[base - 1] : 0.f;
+        rv[5] = hi ? r[base + 4] : 0.0;
+        sv[5] = hi ? s[base + 4] : 0.f;
+        fv[5] = hi ? f[base + 4] : 0.f;
+      }
+      float v[CI][6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        const float u = (float)((double)sv[j] * rv[j]);
+        v[0][j] = u;
+        v[1][j] = fv[j] * u;
+      }
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int t = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+#pragma unroll
+        for (int c = 0; c < CI; ++c)
+#pragma unroll
+          for (int o = 0; o < CO; ++o) {
+            const float w = sW[(o * CI + c) * 27 + t];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[o][k] = fmaf(w, v[c][1 + k + dx], acc[o][k]);
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < CO; ++o) {
+    float4 rr;
+    rr.x = acc[o][0];
+    rr.y = acc[o][1];
+    rr.z = acc[o][2];
+    rr.w = acc[o][3];
+    *reinterpret_cast<float4*>(out + (size_t)o * n + p0) = rr;
+  }
+}
+
+// The last transposed convolution (CO -> 2 channels, as k_pc_conv4<2, CO,
+// true>) followed by the output of k_pc_out for the same four cells:
+// z = dinv r + s (d0 + f d1), the two channels d kept in registers.  With q,
+// one partial z.q per workgroup at index lb (pc_out_parts(n) partials).
+template <int CO>
+__global__ __launch_bounds__(kPcThreads) void k_pc_conv4_out(const float* __restrict__ in, const float* __restrict__ W,
+                                                             const double* __restrict__ r,
+                                                             const double* __restrict__ dinv,
+                                                             const float* __restrict__ s, const float* __restrict__ f,
+                                                             int nx, int ny, int nz, double* __restrict__ z,
+                                                             const double* __restrict__ q, double* part) {
+  constexpr int CI = 2;
+  const int n = nx * ny * nz;
+  const int nq = n / 4;
+  const int lb = xcd_block(blockIdx.x, (nq + kPcThreads - 1) / kPcThreads);
+  if (lb < 0) return;
+  __shared__ float sW[CO * CI * 27];
+  __shared__ double red[kPcThreads / 64];
+  for (int e = threadIdx.x; e < CO * CI * 27; e += kPcThreads) sW[e] = W[e];
+  __syncthreads();
+  const int qd = lb * kPcThreads + threadIdx.x;
+  double zq[1] = {0.0};
+  if (qd < nq) {
+    const int p0 = 4 * qd;
+    const int nxy = nx * ny;
+    const int zc = p0 / nxy, y = (p0 / nx) % ny, x0 = p0 % nx;
+    float acc[CI][4];
+#pragma unroll
+    for (int i = 0; i < CI; ++i)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[i][k] = 0.f;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int zz = zc - dz;
+      if (zz < 0 || zz >= nz) continue;
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int yy = y - dy;
+        if (yy < 0 || yy >= ny) continue;
+        const size_t base = (size_t)zz * nxy + (size_t)yy * nx + x0;
+        float v[CO][6];
+#pragma unroll
+        for (int c = 0; c < CO; ++c) {
+          const float* row = in + (size_t)c * n + base;
+          const float4 mid = *reinterpret_cast<const float4*>(row);
+          v[c][0] = x0 > 0 ? row[-1] : 0.f;
+          v[c][1] = mid.x;
+          v[c][2] = mid.y;
+          v[c][3] = mid.z;
+          v[c][4] = mid.w;
+          v[c][5] = x0 + 4 < nx ? row[4] : 0.f;
+        }
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int t = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+#pragma unroll
+          for (int c = 0; c < CO; ++c)
+#pragma unroll
+            for (int i = 0; i < CI; ++i) {
+              const float w = sW[(c * CI + i) * 27 + t];
+#pragma unroll
+              for (int k = 0; k < 4; ++k) acc[i][k] = fmaf(w, v[c][1 + k - dx], acc[i][k]);
+            }
+        }
+      }
+    }
+    const double2 r01 = *reinterpret_cast<const double2*>(r + p0);
+    const double2 r23 = *reinterpret_cast<const double2*>(r + p0 + 2);
+    const double2 d01 = *reinterpret_cast<const double2*>(dinv + p0);
+    const double2 d23 = *reinterpret_cast<const double2*>(dinv + p0 + 2);
+    const float4 s4 = *reinterpret_cast<const float4*>(s + p0);
+    const float4 f4 = *reinterpret_cast<const float4*>(f + p0);
+    const double rv[4] = {r01.x, r01.y, r23.x, r23.y};
+    const double dv[4] = {d01.x, d01.y, d23.x, d23.y};
+    const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
+    const float fv[4] = {f4.x, f4.y, f4.z, f4.w};
+    double zv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double w = (double)acc[0][k] + (double)fv[k] * (double)acc[1][k];
+      zv[k] = fma(dv[k], rv[k], (double)sv[k] * w);
+    }
+    *reinterpret_cast<double2*>(z + p0) = make_double2(zv[0], zv[1]);
+    *reinterpret_cast<double2*>(z + p0 + 2) = make_double2(zv[2], zv[3]);
+    if (q) {
+      const double2 q01 = *reinterpret_cast<const double2*>(q + p0);
+      const double2 q23 = *reinterpret_cast<const double2*>(q + p0 + 2);
+      zq[0] = fma(zv[0], q01.x, zq[0]);
+      zq[0] = fma(zv[1], q01.y, zq[0]);
+      zq[0] = fma(zv[2], q23.x, zq[0]);
+      zq[0] = fma(zv[3], q23.y, zq[0]);
+    }
+  }
+  if (part) write_partial_at<1, kPcThreads>(zq, red, part, lb);
 }
 
 // z = dinv r + s (d0 + f d1); optional partial z.q per workgroup
@@ -472,26 +657,52 @@ void PcNetGpu::wgrad(const float* x, const float* g, double* gradW, bool accumul
     default: { constexpr int CC = 8; __VA_ARGS__; } break;    \
   }
 
-void PcNetGpu::forward(const double* r) {
+void PcNetGpu::forward(const double* r, bool fused) {
   const float* W1 = W_.as<float>();
   const float* W2 = W1 + C_ * 2 * 27;
   const int g = (n_ + kPcThreads - 1) / kPcThreads;
-  hipLaunchKernelGGL(k_pc_in_r, dim3(g), dim3(kPcThreads), 0, st_, r, s_.as<float>(), f_.as<float>(), n_,
-                     x0_.as<float>());
+  if (!fused) {
+    hipLaunchKernelGGL(k_pc_in_r, dim3(g), dim3(kPcThreads), 0, st_, r, s_.as<float>(), f_.as<float>(), n_,
+                       x0_.as<float>());
+  }
   LYAP_PC_SWITCH({
-    conv<2, CC>(x0_.as<float>(), W1, a1_.as<float>());
+    if (fused) {
+      hipLaunchKernelGGL((k_pc_conv4_r<CC>), dim3(xcd_grid((n_ / 4 + kPcThreads - 1) / kPcThreads)),
+                         dim3(kPcThreads), 0, st_, r, s_.as<float>(), f_.as<float>(), W1, a1_.as<float>(), nx_, ny_,
+                         nz_);
+      LYAP_LAUNCHED("k_pc_conv4_r");
+    } else {
+      conv<2, CC>(x0_.as<float>(), W1, a1_.as<float>());
+    }
     conv<CC, CC>(a1_.as<float>(), W2, k_.as<float>());
     convT<CC, CC>(k_.as<float>(), W2, t1_.as<float>());
-    convT<CC, 2>(t1_.as<float>(), W1, d_.as<float>());
+    if (!fused) convT<CC, 2>(t1_.as<float>(), W1, d_.as<float>());
   });
 }
 
-void PcNetGpu::apply(const double* r, double* z, const double* q, double* part) {
-  forward(r);
+int PcNetGpu::max_out_parts() const { return std::max((n_ / 4 + kPcThreads - 1) / kPcThreads, stream_grid(n_)); }
+
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+int PcNetGpu::apply(const double* r, double* z, const double* q, double* part) {
+  const bool fused = nx_ % 4 == 0 && aligned16(r) && aligned16(z) && (!q || aligned16(q));
+  forward(r, fused);
+  if (fused) {
+    // the last transposed convolution and the output in one kernel
+    const float* W1 = W_.as<float>();
+    LYAP_PC_SWITCH({
+      hipLaunchKernelGGL((k_pc_conv4_out<CC>), dim3(xcd_grid((n_ / 4 + kPcThreads - 1) / kPcThreads)),
+                         dim3(kPcThreads), 0, st_, t1_.as<float>(), W1, r, dinv_.as<double>(), s_.as<float>(),
+                         f_.as<float>(), nx_, ny_, nz_, z, q, part);
+    });
+    LYAP_LAUNCHED("k_pc_conv4_out");
+    return (n_ / 4 + kPcThreads - 1) / kPcThreads;
+  }
   constexpr int NT = stream_threads(1);
   hipLaunchKernelGGL((k_pc_out<NT>), dim3(stream_grid(n_)), dim3(NT), 0, st_, r, dinv_.as<double>(), s_.as<float>(),
                      f_.as<float>(), d_.as<float>(), n_, z, q, part);
   LYAP_LAUNCHED("k_pc_out");
+  return stream_grid(n_);
 }
 
 double PcNetGpu::energy(const double* e) {
@@ -518,7 +729,7 @@ double PcNetGpu::grad(const double* r, const double* e, double eAe, bool want_lo
   const float* W2 = W1 + C_ * 2 * 27;
   double* g1 = grad_.as<double>();
   double* g2 = g1 + C_ * 2 * 27;
-  forward(r);
+  forward(r, false);
   constexpr int NT = stream_threads(1);
   hipLaunchKernelGGL((k_pc_out<NT>), dim3(stream_grid(n_)), dim3(NT), 0, st_, r, dinv_.as<double>(), s_.as<float>(),
                      f_.as<float>(), d_.as<float>(), n_, z_.as<double>(), (const double*)nullptr, (double*)nullptr);

@@ -32,9 +32,11 @@ class PcNetGpu {
   int n() const { return n_; }
   void set_weights(const float* host);
   void get_weights(float* host) const;
-  // z = M r (device FP64 n-vectors).  With q != nullptr, also one partial
-  // z.q per workgroup of a stream_grid(n) launch into part.
-  void apply(const double* r, double* z, const double* q, double* part);
+  // z = M r (device FP64 n-vectors).  With q != nullptr, also the partial
+  // sums of z.q into part (at most max_out_parts() of them, in a fixed
+  // order); returns how many were written.
+  int apply(const double* r, double* z, const double* q, double* part);
+  int max_out_parts() const;
   // Loss of the pair (r, e) (eAe = e^T (-A) e) and its gradient into the
   // device FP64 buffer grad (param_count values); the loss is left on the
   // device (loss_dev) and returned when want_loss (host sync).
@@ -53,7 +55,10 @@ class PcNetGpu {
   void convT(const float* in, const float* W, float* out);
   template <int CI, int CO>
   void wgrad(const float* x, const float* g, double* gradW, bool accumulate);
-  void forward(const double* r);
+  // fused: the input channels x0 are formed inside the first convolution and
+  // the last transposed convolution is left to the caller (apply's fused
+  // output kernel); else x0 and d are stored (the weight gradients read x0).
+  void forward(const double* r, bool fused);
 
   OpDev<double> op_;
   int nx_, ny_, nz_, n_, C_, P_;

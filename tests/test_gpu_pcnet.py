@@ -81,11 +81,12 @@ def test_pcnet_train_parity(lib):
     assert np.linalg.norm(W2 - net.flat()) <= 1e-3 * np.linalg.norm(net.flat())
 
 
-def test_pcnet_fcg_parity(lib):
+@pytest.mark.parametrize("cells", [12, 13])  # nx % 4 == 0: fused input/output kernels; else the separate ones
+def test_pcnet_fcg_parity(lib, cells):
     """Flexible CG with weights trained by the oracle: certified solution,
     iteration count within a few of the oracle's, fewer than Jacobi."""
     b = _b()
-    op = fv3d(12, 1.0, 3)
+    op = fv3d(cells, 1.0, 3)
     A = op.to_scipy()
     g = N.grid_of(A, op.nx, op.ny, op.nz)
     bvec = gaussian_C(op.n, 1, 3)[:, 0]
