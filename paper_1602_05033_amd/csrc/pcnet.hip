@@ -9,8 +9,9 @@
 // formed inside the first convolution and the output z inside the last one,
 // so the network costs four kernels.  Weight
 // gradients: 8 x 8 x 4 cell tiles with a one-cell halo staged in LDS, each
-// thread accumulating a few of the C*CI*27 weights over the tile; per-tile
-// partials are summed in FP64 in a fixed order (two passes).
+// thread accumulating the three x taps of one (output, input, dz, dy) weight
+// group over the tile; per-tile partials are summed in FP64 in a fixed order
+// (two passes).
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -24,7 +25,7 @@ namespace lyap {
 constexpr int kPcThreads = 256;
 constexpr int kTX = 8, kTY = 8, kTZ = 4;                    // weight-gradient tile
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;  // with halo
-constexpr int kWSeg = 32;
+constexpr int kWSeg = 64;  // first-pass segments of the tile sums
 
 __device__ __forceinline__ void offset_of(int t, int& dz, int& dy, int& dx) {
   dz = t / 9 - 1;
@@ -479,41 +480,68 @@ __global__ __launch_bounds__(kPcThreads) void k_pc_wgrad(const float* __restrict
   __syncthreads();
   constexpr int E = CO * CI * 27;
   const size_t tile = blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
-  for (int e = threadIdx.x; e < E; e += kPcThreads) {
-    const int o = e / (CI * 27), i = (e / 27) % CI, t = e % 27;
-    int dz, dy, dx;
-    offset_of(t, dz, dy, dx);
-    float acc = 0.f;
+  // one thread per (o, i, dz, dy): its three dx taps read the same g row and
+  // overlapping x rows (kTX + 2 values), so the row is read from LDS once;
+  // each weight still sums over cz, cy, cx in that order
+  for (int grp = threadIdx.x; grp < CO * CI * 9; grp += kPcThreads) {
+    const int o = grp / (CI * 9), i = (grp / 9) % CI, dzy = grp % 9;
+    const int dz = dzy / 3 - 1, dy = dzy % 3 - 1;
+    float acc[3] = {0.f, 0.f, 0.f};
     for (int cz = 0; cz < kTZ; ++cz)
       for (int cy = 0; cy < kTY; ++cy) {
         const float* gr = &gs[o][(cz * kTY + cy) * kTX];
-        const float* xr = &xs[i][((cz + 1 + dz) * kHY + (cy + 1 + dy)) * kHX + 1 + dx];
+        const float* xr = &xs[i][((cz + 1 + dz) * kHY + (cy + 1 + dy)) * kHX];
+        float xv[kTX + 2];
 #pragma unroll
-        for (int cx = 0; cx < kTX; ++cx) acc = fmaf(gr[cx], xr[cx], acc);
+        for (int j = 0; j < kTX + 2; ++j) xv[j] = xr[j];
+#pragma unroll
+        for (int cx = 0; cx < kTX; ++cx) {
+          const float gv = gr[cx];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) acc[k] = fmaf(gv, xv[cx + k], acc[k]);
+        }
       }
-    part[tile * E + e] = acc;
+    const int e0 = (o * CI + i) * 27 + 3 * dzy;  // tap t = 9 (dz + 1) + 3 (dy + 1) + (dx + 1)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) part[tile * E + e0 + k] = acc[k];
   }
 }
 
-// tmp[seg][e] = sum over the tiles of segment seg (FP64, in order)
-__global__ void k_pc_wreduce1(const float* __restrict__ part, int ntiles, int E, int per, double* __restrict__ tmp) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= E) return;
+// tmp[seg][e] = sum over the tiles of segment seg (FP64).  A workgroup takes
+// 64 weights (one per lane) of one segment; its four waves sum the tiles
+// t = b + w, b + w + 4, ... (w = wave), and the four wave sums are added in
+// wave order: a fixed order, with four independent load streams per weight.
+__global__ __launch_bounds__(256) void k_pc_wreduce1(const float* __restrict__ part, int ntiles, int E, int per,
+                                                     double* __restrict__ tmp) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
   const int sgm = blockIdx.y;
   const int b = sgm * per, end = min(ntiles, b + per);
   double acc = 0.0;
-  for (int t = b; t < end; ++t) acc += (double)part[(size_t)t * E + e];
-  tmp[(size_t)sgm * E + e] = acc;
+  if (e < E)
+    for (int t = b + w; t < end; t += 4) acc += (double)part[(size_t)t * E + e];
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && e < E) tmp[(size_t)sgm * E + e] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
-// out[e] (+)= sum_seg tmp[seg][e]
-__global__ void k_pc_wreduce2(const double* __restrict__ tmp, int nseg, int E, double* __restrict__ out,
-                              int accumulate) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= E) return;
+// out[e] (+)= sum_seg tmp[seg][e], split over the four waves as in
+// k_pc_wreduce1 (segments w, w + 4, ...; wave sums added in wave order)
+__global__ __launch_bounds__(256) void k_pc_wreduce2(const double* __restrict__ tmp, int nseg, int E,
+                                                     double* __restrict__ out, int accumulate) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
   double acc = 0.0;
-  for (int sgm = 0; sgm < nseg; ++sgm) acc += tmp[(size_t)sgm * E + e];
-  out[e] = accumulate ? out[e] + acc : acc;
+  if (e < E)
+    for (int sgm = w; sgm < nseg; sgm += 4) acc += tmp[(size_t)sgm * E + e];
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && e < E) {
+    const double sum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    out[e] = accumulate ? out[e] + sum : sum;
+  }
 }
 
 __global__ void k_pc_loss(const double* part, int nparts, double eAe, double* loss) {
@@ -643,9 +671,9 @@ void PcNetGpu::wgrad(const float* x, const float* g, double* gradW, bool accumul
   const int per = (int)((ntiles + kWSeg - 1) / kWSeg);
   DevBuf& tmp = part_;
   LYAP_REQUIRE(tmp.bytes >= (size_t)kWSeg * E * sizeof(double), LYAP_E_UNSUPPORTED, "scratch too small");
-  hipLaunchKernelGGL(k_pc_wreduce1, dim3((E + 255) / 256, kWSeg), dim3(256), 0, st_, wpart_.as<float>(),
+  hipLaunchKernelGGL(k_pc_wreduce1, dim3((E + 63) / 64, kWSeg), dim3(256), 0, st_, wpart_.as<float>(),
                      (int)ntiles, E, per, tmp.as<double>());
-  hipLaunchKernelGGL(k_pc_wreduce2, dim3((E + 255) / 256), dim3(256), 0, st_, tmp.as<double>(), kWSeg, E, gradW,
+  hipLaunchKernelGGL(k_pc_wreduce2, dim3((E + 63) / 64), dim3(256), 0, st_, tmp.as<double>(), kWSeg, E, gradW,
                      accumulate ? 1 : 0);
   LYAP_LAUNCHED("k_pc_wgrad");
 }
