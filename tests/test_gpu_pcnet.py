@@ -106,11 +106,12 @@ def test_pcnet_fcg_parity(lib, cells):
     assert it < it_jac
 
 
-def test_ek_with_learned_preconditioner(lib):
+@pytest.mark.parametrize("cells", [14, 16])  # 16: the update fused with the network's first convolution
+def test_ek_with_learned_preconditioner(lib, cells):
     """Extended Krylov with inner_pc = LEARNED: harvest, train, flexible CG;
     same blocks and factor as the oracle with exact solves."""
     b = _b()
-    op = fv3d(14, 1.0, 3)
+    op = fv3d(cells, 1.0, 3)
     A = op.to_scipy()
     C = gaussian_C(op.n, 1, 3)
     sol = b.lyap_solve(b.device_op(op), _dev(C), method=b.METHOD_EXT, tol=1e-8, check_every=1,
