@@ -453,15 +453,26 @@ constexpr int zflush_rt() {
 
 template <typename T, int S, bool FULL>
 __global__ __launch_bounds__(64 * kZW) void k_zflush(BlockList bl, int nb, int n, const double* __restrict__ Mrows,
-                                                     int ldm, int t, double* __restrict__ Z, int64_t ldz) {
+                                                     int ldm, int t, double* __restrict__ Z, int64_t ldz, int ncg) {
   constexpr int kZRT = zflush_rt<T, S>();
   constexpr int kZR = 64 * kZRT;
+  // FULL: a 1-D launch over (row block, column group) pairs, dealt so that
+  // each XCD takes a contiguous run of pairs: the ncg column groups of a row
+  // block run back to back on one XCD, and all but the first read their rows
+  // of V from that XCD's L2 rather than from HBM
+  int rb = blockIdx.x, cg = 0;
+  if constexpr (FULL) {
+    const int lb = xcd_block(blockIdx.x, (int)((n + kZR - 1) / kZR) * ncg);
+    if (lb < 0) return;
+    rb = lb / ncg;
+    cg = lb % ncg;
+  }
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int c0 = (blockIdx.y * kZW + wv) * kZCW;
+  const int c0 = (cg * kZW + wv) * kZCW;
   if (c0 >= t) return;
   const int cmax = FULL ? kZCW - 1 : min(kZCW, t - c0) - 1;  // columns past t read column t-1, are not stored
-  const int r0 = blockIdx.x * kZR + lane;
+  const int r0 = rb * kZR + lane;
   // rows past n compute on row n-1 (branch-free loads) and are not stored
   int rr[kZRT];
 #pragma unroll
@@ -690,12 +701,14 @@ void launch_zflush(const void* const* blocks, int nb, int n, int S, const double
       const int tf = t / kZCW * kZCW;  // columns in full tiles
       constexpr int kZR = 64 * zflush_rt<T, S>();
       if (tf > 0) {
-        dim3 grid((n + kZR - 1) / kZR, (tf / kZCW + kZW - 1) / kZW);
-        hipLaunchKernelGGL((k_zflush<T, S, true>), grid, dim3(64 * kZW), 0, st, bl, cnt, n, Mc, t, tf, Z, ldz);
+        const int ncg = (tf / kZCW + kZW - 1) / kZW;  // column groups of kZW * kZCW columns
+        const int pairs = (n + kZR - 1) / kZR * ncg;
+        hipLaunchKernelGGL((k_zflush<T, S, true>), dim3(xcd_grid(pairs)), dim3(64 * kZW), 0, st, bl, cnt, n, Mc, t,
+                           tf, Z, ldz, ncg);
       }
       if (tf < t)
         hipLaunchKernelGGL((k_zflush<T, S, false>), dim3((n + kZR - 1) / kZR, 1), dim3(64), 0, st, bl, cnt, n, Mc + tf,
-                           t, t - tf, Z + (size_t)tf * ldz, ldz);
+                           t, t - tf, Z + (size_t)tf * ldz, ldz, 1);
       done += cnt;
     }
   });
