@@ -39,6 +39,9 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_COUNTERS = {
     ("upd_gram", 1000000, 4, "f32"): {"fetch_kib": 23597.0, "write_kib": 15657.125,
                                       "fetch_scale": 262144.0 / 131088.75, "write_scale": 1.0},
+    # k_cgcg_iter<1, 1024> of the extended Krylov run (inner Jacobi-PCG, FP64)
+    ("cg_dir", 1000000, 1, "f64"): {"fetch_kib": 56843.59375, "write_kib": 39733.21875,
+                                    "fetch_scale": 262144.0 / 131088.75, "write_scale": 1.0},
 }
 
 
@@ -230,7 +233,7 @@ def main_ext(args):
                     for k, v in agg.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(dom, op.n, args.s, args.storage),
+                     "traffic": measured_traffic(dom, op.n, 1, "f64"),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "bytes_per_launch": bpl, "avg_launch_us": round(avg_ms * 1000.0, 2)},
     }
