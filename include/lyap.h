@@ -425,6 +425,25 @@ lyap_status lyap_solve_batched(int32_t count, const lyap_op* A, const double* co
  */
 void lyap_pcnet_init(int32_t C, uint64_t seed, double scale, float* W);
 lyap_status lyap_pcnet_apply(const lyap_op* A, int32_t C, const float* W, const double* r, double* z, void* stream);
+/*
+ * lyap_pcnet_apply_noalloc -- lyap_pcnet_apply for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and the same result, with
+ * every intermediate buffer (the operator's FP64 coefficient copies, D^{-1},
+ * the network's activations, weights and partial sums) carved from one static
+ * 32 MiB device array per GPU instead of hipMalloc.  No device or pinned host
+ * memory is allocated; the array's address is looked up once per device, on
+ * the first call made with that device current.
+ *  Limit: n (64 + 12 C) bytes plus about 1 MiB must fit in 32 MiB for a
+ *  7-point operator (n (32 + 12 C) for a 5-point one): n <= 262144 at C = 4.
+ *  Larger inputs return LYAP_E_ARG with the bytes needed in the message.
+ *  A, C, W, r, z, stream as for lyap_pcnet_apply (stencil operators only).
+ *  Every call on one GPU uses that GPU's single array and returns only after
+ *  its work on `stream` has finished; calls that overlap on one GPU (from
+ *  several host threads, or on several streams at once) race on the array.
+ */
+lyap_status lyap_pcnet_apply_noalloc(const lyap_op* A, int32_t C, const float* W, const double* r, double* z,
+                                     void* stream);
 /* loss of (r, e) and its gradient (host, FP64, same layout as W) */
 lyap_status lyap_pcnet_grad(const lyap_op* A, int32_t C, const float* W, const double* r, const double* e,
                             double* loss, double* grad, void* stream);

@@ -78,7 +78,8 @@ class SylvResult(ct.Structure):
 EXPORTS = ["lyap_opts_default", "lyap_solve", "sylv_solve", "lyap_result_free", "sylv_result_free",
            "lyap_last_error", "lyap_op_apply", "lyap_op_apply_timed", "lyap_ctri", "lyap_inner_solve",
            "lyap_solve_batched", "lyap_pcnet_init", "lyap_pcnet_apply", "lyap_pcnet_grad", "lyap_pcnet_train",
-           "lyap_pcnet_fcg", "sylv_solve_small_b", "lyap_sym_eig", "lyap_solve_gen"]
+           "lyap_pcnet_fcg", "sylv_solve_small_b", "lyap_sym_eig", "lyap_solve_gen",
+           "lyap_pcnet_apply_noalloc"]
 
 
 class LyapError(RuntimeError):
@@ -142,6 +143,9 @@ def load(path: str = LIB_PATH):
     lib.lyap_pcnet_apply.argtypes = [ct.POINTER(LyapOp), ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                      ct.c_void_p]
     lib.lyap_pcnet_apply.restype = ct.c_int
+    lib.lyap_pcnet_apply_noalloc.argtypes = [ct.POINTER(LyapOp), ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                             ct.c_void_p]
+    lib.lyap_pcnet_apply_noalloc.restype = ct.c_int
     lib.lyap_pcnet_grad.argtypes = [ct.POINTER(LyapOp), ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                     ct.POINTER(ct.c_double), ct.c_void_p, ct.c_void_p]
     lib.lyap_pcnet_grad.restype = ct.c_int
@@ -599,6 +603,18 @@ def pcnet_apply(dop: DeviceOp, C: int, W: np.ndarray, r):
     z = torch.empty_like(r)
     _check(lib.lyap_pcnet_apply(ct.byref(dop.c), C, Wf.ctypes.data_as(ct.c_void_p), ct.c_void_p(r.data_ptr()),
                                 ct.c_void_p(z.data_ptr()), ct.c_void_p(_stream(r.device))))
+    return z
+
+
+def pcnet_apply_noalloc(dop: DeviceOp, C: int, W: np.ndarray, r, z):
+    """z = M r through the allocation-free entry point; z is a caller-owned
+    device tensor shaped like r."""
+    lib = load()
+    Wf = np.ascontiguousarray(W, dtype=np.float32)
+    assert z.shape == r.shape and z.dtype == r.dtype and z.device == r.device
+    _check(lib.lyap_pcnet_apply_noalloc(ct.byref(dop.c), C, Wf.ctypes.data_as(ct.c_void_p),
+                                        ct.c_void_p(r.data_ptr()), ct.c_void_p(z.data_ptr()),
+                                        ct.c_void_p(_stream(r.device))))
     return z
 
 

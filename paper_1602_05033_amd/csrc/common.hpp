@@ -46,23 +46,74 @@ struct Error {
 #define LYAP_LAUNCHED(name) LYAP_HIP(hipGetLastError())
 
 // ------------------------------------------------------------------ buffers
-// Owning device buffer (hipMalloc / hipFree).  Sizes in bytes.
+// Caller-provided device workspace.  While an Arena is installed on the
+// calling thread (ArenaScope), every DevBuf takes its bytes from it by bump
+// allocation (256-byte aligned) instead of hipMalloc, and gives nothing back
+// on release; a request past the capacity throws LYAP_E_ARG.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+};
+
+inline Arena*& current_arena() {
+  static thread_local Arena* a = nullptr;
+  return a;
+}
+
+struct ArenaScope {
+  explicit ArenaScope(Arena* a) : prev_(current_arena()) { current_arena() = a; }
+  ~ArenaScope() { current_arena() = prev_; }
+  ArenaScope(const ArenaScope&) = delete;
+  ArenaScope& operator=(const ArenaScope&) = delete;
+
+ private:
+  Arena* prev_;
+};
+
+// Owning device buffer (hipMalloc / hipFree, or a slice of the installed
+// Arena).  Sizes in bytes.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool borrowed = false;  // slice of an Arena: never freed
   DevBuf() = default;
   explicit DevBuf(size_t b) { alloc(b); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), borrowed(o.borrowed) {
+    o.p = nullptr;
+    o.bytes = 0;
+    o.borrowed = false;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      borrowed = o.borrowed;
+      o.p = nullptr;
+      o.bytes = 0;
+      o.borrowed = false;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   void alloc(size_t b) {
     release();
     if (b == 0) b = 256;
+    if (Arena* a = current_arena()) {
+      const size_t off = (a->used + 255) / 256 * 256;
+      if (off > a->cap || b > a->cap - off) {
+        set_error("workspace exhausted: %zu more bytes needed beyond %zu of %zu", b, off, a->cap);
+        throw Error{LYAP_E_ARG};
+      }
+      p = a->base + off;
+      a->used = off + b;
+      bytes = b;
+      borrowed = true;
+      return;
+    }
     hipError_t e = hipMalloc(&p, b);
     if (e != hipSuccess) {
       p = nullptr;
@@ -72,9 +123,10 @@ struct DevBuf {
     bytes = b;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && !borrowed) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    borrowed = false;
   }
   template <typename U> U* as() const { return static_cast<U*>(p); }
 };

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 
 #include "pcnet.hpp"
 #include "pcg.hpp"
@@ -905,5 +906,80 @@ extern "C" lyap_status lyap_pcnet_fcg(const lyap_op* A, int32_t C, const float* 
     return status;
   } catch (const Error& e2) {
     return e2.st;
+  }
+}
+
+// ------------------------------------------------------------------ allocation-free apply
+// Workspace of lyap_pcnet_apply_noalloc: one static device array per GPU (each
+// device that loads this code object holds its own copy until the process
+// ends).  Host code never passes the array's name to a kernel: its device
+// address, per device, comes from hipGetSymbolAddress on the first call made
+// with that device current, and the buffers of the apply are slices of it.
+namespace lyap {
+
+constexpr size_t kNoAllocBytes = (size_t)32 << 20;
+constexpr int kNoAllocMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+static char* scratch_base() {
+  int dev = 0;
+  LYAP_HIP(hipGetDevice(&dev));
+  LYAP_REQUIRE(dev >= 0 && dev < kNoAllocMaxDevices, LYAP_E_DEVICE, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    LYAP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    LYAP_REQUIRE(p != nullptr, LYAP_E_DEVICE, "no device address for the workspace array");
+    g_scratch_ptr[dev] = p;
+  }
+  return static_cast<char*>(g_scratch_ptr[dev]);
+}
+
+// Workspace bytes of one apply: the FP64 copies of a 7-point operator's four
+// coefficient arrays (32 n), D^{-1} (8 n), s and f (8 n), the input channels
+// and K^T's output (16 n), three C-channel activations (12 C n), and the
+// weights, optimizer state and reduction partials (under 1 MiB), with the
+// 256-byte alignment of every slice.
+static size_t pcnet_noalloc_bytes(const lyap_op* A, int C) {
+  const size_t n = (size_t)A->n;
+  const size_t P = (size_t)pcnet_param_count(C);
+  const size_t op = A->kind == LYAP_OP_STENCIL7 ? 32 * n : 0;
+  const size_t fixed = 4 * P * sizeof(float) + P * sizeof(double) + (size_t)kWSeg * kPcMaxC * kPcMaxC * 27 *
+                       sizeof(double) + 64 + 32 * 256;
+  return op + (8 + 8 + 16) * n + 12 * (size_t)C * n + fixed;
+}
+
+}  // namespace lyap
+
+extern "C" lyap_status lyap_pcnet_apply_noalloc(const lyap_op* A, int32_t C, const float* W, const double* r,
+                                                double* z, void* stream) {
+  using namespace lyap;
+  clear_error();
+  try {
+    validate_op(A);
+    LYAP_REQUIRE(W && r && z, LYAP_E_ARG, "NULL argument");
+    LYAP_REQUIRE(A->kind == LYAP_OP_STENCIL5 || A->kind == LYAP_OP_STENCIL7, LYAP_E_UNSUPPORTED,
+                 "the learned preconditioner needs a stencil operator (a grid)");
+    LYAP_REQUIRE(C == 2 || C == 4 || C == 8, LYAP_E_UNSUPPORTED, "network width C=%d not built (2, 4, 8)", C);
+    const size_t need = pcnet_noalloc_bytes(A, C);
+    LYAP_REQUIRE(need <= kNoAllocBytes, LYAP_E_ARG,
+                 "n=%lld with C=%d needs %zu bytes of workspace; the allocation-free apply has %zu",
+                 (long long)A->n, C, need, kNoAllocBytes);
+    hipStream_t st = (hipStream_t)stream;
+    Arena arena{scratch_base(), kNoAllocBytes, 0};
+    ArenaScope scope(&arena);
+    OpHolder<double> op;
+    make_op_f64(A, op, st);
+    PcNetGpu net(op.dev, C, st);
+    net.set_weights(W);
+    net.apply(r, z, nullptr, nullptr);
+    LYAP_HIP(hipStreamSynchronize(st));
+    return LYAP_OK;
+  } catch (const Error& e) {
+    return e.st;
   }
 }
