@@ -14,7 +14,20 @@ Preconditioners:
 * ``"none"``;
 * ``"jacobi"``: M = diag(-A);
 * ``"ic0"``: zero fill-in incomplete Cholesky of -A in the natural (given)
-  ordering, M = L L^T, applied by two sparse triangular solves.
+  ordering, M = L L^T, applied by two sparse triangular solves;
+* ``"ic0_rb"``: the same factorisation in red-black order (grid cells with
+  i + j + l even first, then the odd ones, each group in natural order; needs
+  the grid shape), M = P^T L L^T P with P that permutation.
+
+In red-black order the red cells are not coupled to each other, nor the black
+ones to each other, so with K = -A = [[D_r, E^T], [E, D_b]] the factor is
+L = [[D_r^{1/2}, 0], [E D_r^{-1/2}, S^{1/2}]], S = diag(Sigma) the diagonal of
+the black Schur complement Sigma = D_b - E D_r^{-1} E^T (every other entry of
+Sigma falls outside the pattern and is dropped).  Hence M^{-1} K is similar to
+diag(I, S^{-1} Sigma), and PCG with this M advances like CG on Sigma
+preconditioned by S, up to one iteration for the eigenvalue 1 of the red
+block.  ``schur_rb_cg`` is that condensed form: CG on the black unknowns,
+then x_r = D_r^{-1} (rhs_r - E^T x_b).
 """
 from __future__ import annotations
 
@@ -36,9 +49,21 @@ class PcgResult:
     history: list         # recursive ||r_k|| / ||b|| per iteration (first run)
 
 
+def red_black_order(nx: int, ny: int, nz: int = 1) -> np.ndarray:
+    """Row indices of the grid (lexicographic, x fastest) in red-black order:
+    cells with i + j + l even, then the odd ones, each in natural order."""
+    idx = np.arange(nx * ny * nz)
+    i = idx % nx
+    j = (idx // nx) % ny
+    l = idx // (nx * ny)
+    par = (i + j + l) % 2
+    return np.concatenate([idx[par == 0], idx[par == 1]])
+
+
 def ic0(Apos: sp.csr_matrix) -> sp.csr_matrix:
     """Lower triangular L with the sparsity of tril(Apos) and
-    (L L^T)_ij = Apos_ij on that pattern (IC(0), natural ordering).
+    (L L^T)_ij = Apos_ij on that pattern (IC(0) in the order of the rows
+    given: pass P Apos P^T for another ordering).
     Row-by-row (left-looking) form: for each entry (i, j), j <= i, of the
     pattern, L_ij = (a_ij - sum_{k<j} L_ik L_jk) / L_jj, L_ii = sqrt(a_ii - sum L_ik^2)."""
     A = sp.tril(Apos, format="csr")
@@ -70,9 +95,21 @@ def ic0(Apos: sp.csr_matrix) -> sp.csr_matrix:
     return sp.csr_matrix((vv, (ri, ci)), shape=(n, n))
 
 
-def make_preconditioner(A, kind: str):
-    """Returns z = M^{-1} r for the SPD matrix -A."""
+def make_preconditioner(A, kind: str, grid=None):
+    """Returns z = M^{-1} r for the SPD matrix -A (``grid`` = (nx, ny, nz) for
+    the red-black ordering)."""
     Apos = -sp.csr_matrix(A)
+    if kind == "ic0_rb":
+        perm = red_black_order(*grid)
+        L = ic0(Apos[perm][:, perm].tocsr())
+        Lt = L.T.tocsr()
+
+        def apply_rb(r):
+            y = spla.spsolve_triangular(L, r[perm], lower=True)
+            z = np.empty_like(r)
+            z[perm] = spla.spsolve_triangular(Lt, y, lower=False)
+            return z
+        return apply_rb
     if kind == "none":
         return lambda r: r.copy()
     if kind == "jacobi":
@@ -89,11 +126,11 @@ def make_preconditioner(A, kind: str):
 
 
 def pcg(A, b: np.ndarray, eta: float = 1e-12, max_iter: int = 10000, pc: str = "jacobi",
-        restarts: int = 3, precond=None, x0: Optional[np.ndarray] = None) -> PcgResult:
+        restarts: int = 3, precond=None, x0: Optional[np.ndarray] = None, grid=None) -> PcgResult:
     """Solve A x = b (A symmetric negative definite) by PCG on (-A) x = -b."""
     Apos = -sp.csr_matrix(A)
     if precond is None:
-        precond = make_preconditioner(A, pc)
+        precond = make_preconditioner(A, pc, grid)
     rhs = -b
     bn = float(np.linalg.norm(b))
     x = np.zeros_like(b) if x0 is None else x0.copy()
@@ -140,3 +177,69 @@ def pcg_block(A, B: np.ndarray, **kw):
         X[:, c] = r.x
         res.append(r)
     return X, res
+
+
+def schur_rb_cg(A, b: np.ndarray, grid, eta: float = 1e-12, max_iter: int = 10000,
+                restarts: int = 3) -> PcgResult:
+    """Red-black IC(0)-PCG in its condensed form (see the module header):
+    with K = -A split into red / black cells, rhs = -b,
+      Sigma = D_b - E D_r^{-1} E^T,  rhs~ = rhs_b - E D_r^{-1} rhs_r,
+    CG on Sigma x_b = rhs~ with the preconditioner diag(Sigma), stopped when
+    ||rhs~ - Sigma x_b|| <= eta ||b||, then x_r = D_r^{-1} (rhs_r - E^T x_b).
+    The residual of the whole system is then zero on the red cells and
+    rhs~ - Sigma x_b on the black ones.  Accepted on the true relative residual
+    ||b - A x|| / ||b|| <= eta; otherwise the condensed CG is run again on the
+    residual (x += the correction), at most ``restarts`` times."""
+    K = -sp.csr_matrix(A)
+    idx = np.arange(K.shape[0])
+    nx, ny, nz = grid
+    i, j, l = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    red = (i + j + l) % 2 == 0
+    blk = ~red
+    Krr = K[red][:, red]
+    Erb = K[red][:, blk]          # E^T: red rows, black columns
+    Ebr = K[blk][:, red]          # E
+    Kbb = K[blk][:, blk]
+    dr = Krr.diagonal()
+    if not np.all(dr > 0.0):
+        raise np.linalg.LinAlgError("red diagonal is not positive")
+    Sigma = (Kbb - Ebr @ sp.diags(1.0 / dr) @ Erb).tocsr()
+    S = Sigma.diagonal()
+    if not np.all(S > 0.0):
+        raise np.linalg.LinAlgError("IC(0) pivot is not positive")
+    bn = float(np.linalg.norm(b))
+    x = np.zeros_like(b)
+    if bn == 0.0:
+        return PcgResult(x, 0, 0.0, True, 0, [])
+    total, nrest, hist = 0, 0, []
+    res = -b - K @ x
+    while True:
+        rt = res[blk] - Ebr @ (res[red] / dr)
+        xb = np.zeros(int(blk.sum()))
+        r = rt.copy()
+        z = r / S
+        p = z.copy()
+        rho = float(r @ z)
+        while total < max_iter and float(np.linalg.norm(r)) > eta * bn:
+            q = Sigma @ p
+            alpha = rho / float(p @ q)
+            xb = xb + alpha * p
+            r = r - alpha * q
+            total += 1
+            if nrest == 0:
+                hist.append(float(np.linalg.norm(r)) / bn)
+            z = r / S
+            rho_new = float(r @ z)
+            p = z + (rho_new / rho) * p
+            rho = rho_new
+        dx = np.empty_like(b)
+        dx[blk] = xb
+        dx[red] = (res[red] - Erb @ xb) / dr
+        x = x + dx
+        res = -b - K @ x
+        true = float(np.linalg.norm(b - A @ x)) / bn
+        if true <= eta:
+            return PcgResult(x, total, true, True, nrest, hist)
+        if nrest >= restarts or total >= max_iter:
+            return PcgResult(x, total, true, False, nrest, hist)
+        nrest += 1
