@@ -111,8 +111,9 @@ typedef struct lyap_opts {
   double trunc_eps;     /* < 0: default truncation threshold (see lyap_solve);
                            >= 0: absolute threshold on ||Sigma_2||_F               */
   int32_t inner_pc;     /* extended Krylov inner CG preconditioner: LYAP_PC_NONE,
-                           LYAP_PC_JACOBI or LYAP_PC_LEARNED (see below);
-                           LYAP_PC_IC0: LYAP_E_UNSUPPORTED                        */
+                           LYAP_PC_JACOBI, LYAP_PC_IC0 (zero fill-in incomplete
+                           Cholesky in red-black order; stencil operators only,
+                           see lyap_inner_solve) or LYAP_PC_LEARNED (see below) */
   double inner_tol;     /* inner solves accepted when true ||b-Ax||/||b|| <= this  */
   int32_t inner_max_iter;
   int32_t flush_blocks; /* second pass: blocks buffered per Z update (0 = default)  */
@@ -251,8 +252,8 @@ typedef struct sylv_result {
  * opts->method = LYAP_METHOD_EXT builds the two extended spaces EK_m(A, C1),
  * EK_m(B, C2) instead (Section 4's spaces in Section 5.1's method; ell = 2s,
  * Algorithm 4 with the first s rows of tau and iota, factors from the stored
- * bases): s = 1, 2 or 4, FP64 storage, inner CG with inner_pc NONE or JACOBI
- * on each operator (E_UNSUPPORTED otherwise).
+ * bases): s = 1, 2 or 4, FP64 storage, inner CG with inner_pc NONE, JACOBI
+ * or IC0 on each operator (E_UNSUPPORTED otherwise).
  */
 lyap_status sylv_solve(const lyap_op* A, const lyap_op* B, const double* C1, int64_t ldc1,
                        const double* C2, int64_t ldc2, int32_t s, const lyap_opts* opts,
@@ -372,9 +373,18 @@ lyap_status lyap_ctri(const double* T_band, int32_t ell, int32_t k, const double
  *  B, X     device, n x s column-major FP64, leading dimensions ldb, ldx >= n;
  *           X is overwritten (B is not modified).
  *  s        1, 2 or 4.
- *  opts     inner_pc (LYAP_PC_NONE or LYAP_PC_JACOBI), inner_tol (bound on
- *           the true ||b - A x|| / ||b|| of every column), inner_max_iter and
- *           stream are used; NULL means defaults.
+ *  opts     inner_pc, inner_tol (bound on the true ||b - A x|| / ||b|| of
+ *           every column), inner_max_iter and stream are used; NULL means
+ *           defaults.  inner_pc: LYAP_PC_NONE; LYAP_PC_JACOBI; LYAP_PC_IC0,
+ *           zero fill-in incomplete Cholesky of -A with the grid cells in
+ *           red-black order (i + j + l even first), for 5- and 7-point
+ *           stencil operators (E_UNSUPPORTED for CSR): since a stencil couples
+ *           only cells of different colours, the factor is explicit and PCG
+ *           with it is run as CG on the black Schur complement
+ *           D_b - E D_r^{-1} E^T preconditioned by its diagonal (the same
+ *           iterates up to one iteration), then the red cells are solved for;
+ *           the true residual still certifies the whole solution.
+ *           LYAP_PC_LEARNED: E_UNSUPPORTED (trained inside lyap_solve).
  *  iters    optional output: CG iterations, restarts included.
  *  relres   optional output: largest true relative residual over the columns.
  * Returns LYAP_E_INNER when a column does not reach inner_tol (X then holds

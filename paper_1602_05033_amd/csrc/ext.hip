@@ -585,9 +585,9 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
     out->kern_n[i] = kt.n[i];
   }
   {
-    const double coef = side.op().coef_bytes_per_row();
-    // one single-reduction CG iteration: x, r, w, s, p and M^{-1} in; x, r, w, s, p out (+ coefficients)
-    out->kern_bytes[LYAP_K_CG_DIR] = (double)n * (10.0 * S * 8 + 8 + coef);
+    // one iteration kernel of the inner CG (Jacobi: the single-reduction iteration on the
+    // whole grid; IC(0): the condensed iteration on the black cells)
+    out->kern_bytes[LYAP_K_CG_DIR] = cg.iter_bytes();
     // the flexible-CG update of the learned-preconditioner runs: x, r, p, q in; x, r out
     out->kern_bytes[LYAP_K_CG_UPD] = (double)n * (6.0 * S * 8 + 8);
   }
@@ -808,8 +808,8 @@ template lyap_status solve_ext<double>(const lyap_op*, const double*, int, int64
 lyap_status solve_sylv_ext(const lyap_op* A, const lyap_op* B, const double* C1, int64_t ldc1, const double* C2,
                            int64_t ldc2, int S, const lyap_opts& o, sylv_result* out) {
   LYAP_REQUIRE(o.storage == LYAP_STORE_F64, LYAP_E_UNSUPPORTED, "the extended Krylov method runs with FP64 storage only");
-  LYAP_REQUIRE(o.inner_pc == LYAP_PC_NONE || o.inner_pc == LYAP_PC_JACOBI, LYAP_E_UNSUPPORTED,
-               "extended Krylov Sylvester solves take inner_pc NONE or JACOBI");
+  LYAP_REQUIRE(o.inner_pc == LYAP_PC_NONE || o.inner_pc == LYAP_PC_JACOBI || o.inner_pc == LYAP_PC_IC0,
+               LYAP_E_UNSUPPORTED, "extended Krylov Sylvester solves take inner_pc NONE, JACOBI or IC0");
   switch (S) {
     case 1: return sylv_ext_impl<1>(A, B, C1, ldc1, C2, ldc2, o, out);
     case 2: return sylv_ext_impl<2>(A, B, C1, ldc1, C2, ldc2, o, out);

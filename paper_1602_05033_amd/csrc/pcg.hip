@@ -348,8 +348,8 @@ __global__ void k_cg_errors(const double* __restrict__ xs, double* __restrict__ 
 InnerCG::InnerCG(const OpDev<double>& op, int n, int S, int pc, double eta, int max_iter, hipStream_t st)
     : op_(op), n_(n), S_(S), pc_(pc), max_iter_(max_iter), eta_(eta), st_(st) {
   LYAP_REQUIRE(S == 1 || S == 2 || S == 4, LYAP_E_UNSUPPORTED, "inner CG supports 1, 2 or 4 right-hand sides");
-  LYAP_REQUIRE(pc == LYAP_PC_NONE || pc == LYAP_PC_JACOBI || pc == LYAP_PC_LEARNED, LYAP_E_UNSUPPORTED,
-               "inner preconditioner %d is not available in this build", pc);
+  LYAP_REQUIRE(pc == LYAP_PC_NONE || pc == LYAP_PC_JACOBI || pc == LYAP_PC_IC0 || pc == LYAP_PC_LEARNED,
+               LYAP_E_UNSUPPORTED, "inner preconditioner %d is not available in this build", pc);
   LYAP_REQUIRE(pc != LYAP_PC_LEARNED || S == 1, LYAP_E_UNSUPPORTED,
                "the learned preconditioner handles one right-hand side per solve");
   LYAP_REQUIRE(eta > 0.0 && eta < 1.0, LYAP_E_ARG, "inner_tol=%g must be in (0,1)", eta);
@@ -382,7 +382,17 @@ InnerCG::InnerCG(const OpDev<double>& op, int n, int S, int pc, double eta, int 
   LYAP_HIP(hipMemcpyAsync(hf, flag_.p, sizeof(hf), hipMemcpyDeviceToHost, st_));
   LYAP_HIP(hipStreamSynchronize(st_));
   LYAP_REQUIRE(hf[0] == 0, LYAP_E_INDEFINITE, "A has a diagonal entry >= 0: not negative definite");
+  if (pc_ == LYAP_PC_IC0) setup_rb();
 }
+
+double InnerCG::iter_bytes() const {
+  if (pc_ == LYAP_PC_IC0) return rb_iter_bytes();
+  double coef = 0.0;
+  if (op_.kind == LYAP_OP_STENCIL7) coef = 4.0 * 8.0;
+  // single-reduction CG: x, r, w, s, p and M^{-1} in; x, r, w, s, p out (+ coefficients)
+  return (double)n_ * (10.0 * S_ * 8 + 8 + coef);
+}
+
 
 template <int S>
 static void cg_launch_init(const double* B, double* x, double* r, const double* dinv, int n, int mode, double* pout,
@@ -419,6 +429,15 @@ static void cg_launch_true(const OpDev<double>& op, const double* B, const doubl
   LYAP_LAUNCHED("k_cg_true");
   hipLaunchKernelGGL((k_sum_partials<2 * S>), dim3(1), dim3(256), 0, st, part, grid, tot);
   LYAP_LAUNCHED("k_sum_partials");
+}
+
+void cg_true(const OpDev<double>& op, const double* B, const double* x, double* r, int n, int S, double* part,
+             double* tot, int grid, hipStream_t st) {
+  switch (S) {
+    case 1: cg_launch_true<1>(op, B, x, r, n, part, tot, grid, st); break;
+    case 2: cg_launch_true<2>(op, B, x, r, n, part, tot, grid, st); break;
+    default: cg_launch_true<4>(op, B, x, r, n, part, tot, grid, st); break;
+  }
 }
 
 void InnerCG::solve_fcg(const double* B, double* X, KernelTimer* kt) {
@@ -501,6 +520,7 @@ void InnerCG::solve_fcg(const double* B, double* X, KernelTimer* kt) {
 
 void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
   if (net_) return solve_fcg(B, X, kt);
+  if (pc_ == LYAP_PC_IC0) return solve_rb(B, X, kt);
   const auto t0 = Clock::now();
   const int S = S_;
   const double eta_rec = 0.5 * eta_;  // recursive target, so that the true residual passes

@@ -30,13 +30,18 @@ class PcNetGpu;
 class InnerCG {
  public:
   // op: FP64 operator; S: right-hand sides per solve (1, 2 or 4); pc:
-  // LYAP_PC_NONE, LYAP_PC_JACOBI, or LYAP_PC_LEARNED (Jacobi until a network
-  // is attached with set_net, flexible CG with it afterwards; S = 1).
+  // LYAP_PC_NONE, LYAP_PC_JACOBI, LYAP_PC_IC0 (red-black IC(0), run as CG on
+  // the black Schur complement; stencil operators only, rbcg.hip), or
+  // LYAP_PC_LEARNED (Jacobi until a network is attached with set_net,
+  // flexible CG with it afterwards; S = 1).
   InnerCG(const OpDev<double>& op, int n, int S, int pc, double eta, int max_iter, hipStream_t st);
   // X = A^{-1} B for row-interleaved n x S blocks (device).  Throws
   // Error{LYAP_E_INNER} when a column does not reach eta.
   void solve(const double* B, double* X, KernelTimer* kt = nullptr);
   const CgStats& stats() const { return stats_; }
+  // Algorithmic HBM bytes of one iteration kernel (LYAP_K_CG_DIR) of this
+  // preconditioner's CG.
+  double iter_bytes() const;
   // Later solves use flexible CG with z = M(r) from the network.
   void set_net(PcNetGpu* net) { net_ = net; }
   // The next (Jacobi) solve keeps (r, x) every `every` iterations, at most
@@ -48,6 +53,11 @@ class InnerCG {
 
  private:
   void solve_fcg(const double* B, double* X, KernelTimer* kt);
+  void setup_rb();
+  void solve_rb(const double* B, double* X, KernelTimer* kt);
+  template <bool K7, int S>
+  void rb_solve_templ(const double* B, double* X, int restarts, int chunk, KernelTimer* kt);
+  double rb_iter_bytes() const;
   OpDev<double> op_;
   int n_, S_, pc_, max_iter_;
   double eta_;
@@ -60,7 +70,16 @@ class InnerCG {
   DevBuf z_, partZ_;
   DevBuf r1_, w0_, w1_, s0_, s1_;  // double-buffered r, w = K M r, s = K p of the single-reduction CG
   int harvest_every_ = 0, harvest_keep_ = 0;
+  // red-black IC(0): 1 / D_r (red slots), D_b and 1 / Sigma_bb (black slots),
+  // and the condensed iteration's vectors (r, w, s double buffered)
+  DevBuf rb_rinv_, rb_db_, rb_sinv_, rb_x_, rb_p_, rb_r0_, rb_r1_, rb_w0_, rb_w1_, rb_s0_, rb_s1_;
+  int rb_grid_ = 0;
   std::vector<DevBuf> hr_, hx_;
 };
+
+// r = A x - B for row-interleaved n x S blocks; tot[0..S) = r^T r and
+// tot[S..2S) = B^T B per column (part: grid * 2S partial sums).
+void cg_true(const OpDev<double>& op, const double* B, const double* x, double* r, int n, int S, double* part,
+             double* tot, int grid, hipStream_t st);
 
 }  // namespace lyap

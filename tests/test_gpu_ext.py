@@ -88,7 +88,9 @@ def test_inner_pcg_unsupported_pc(lib):
     dop = b.device_op(op)
     B = gaussian_C(op.n, 1, 2)
     with pytest.raises(b.LyapError):
-        b.inner_solve(dop, _dev(B), inner_pc=b.PC_IC0)
+        b.inner_solve(dop, _dev(B), inner_pc=7)          # no such preconditioner
+    with pytest.raises(b.LyapError):
+        b.inner_solve(dop, _dev(B), inner_pc=b.PC_LEARNED)  # trained only inside an EK solve
 
 
 # ------------------------------------------------------------------ extended Krylov
