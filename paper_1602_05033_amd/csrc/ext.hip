@@ -588,8 +588,7 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
     // one iteration kernel of the inner CG (Jacobi: the single-reduction iteration on the
     // whole grid; IC(0): the condensed iteration on the black cells)
     out->kern_bytes[LYAP_K_CG_DIR] = cg.iter_bytes();
-    // the flexible-CG update of the learned-preconditioner runs: x, r, p, q in; x, r out
-    out->kern_bytes[LYAP_K_CG_UPD] = (double)n * (6.0 * S * 8 + 8);
+    out->kern_bytes[LYAP_K_CG_UPD] = cg.upd_bytes();
   }
   out->status = status;
   return status;

@@ -431,6 +431,12 @@ static void cg_launch_true(const OpDev<double>& op, const double* B, const doubl
   LYAP_LAUNCHED("k_sum_partials");
 }
 
+double InnerCG::upd_bytes() const {
+  if (pc_ == LYAP_PC_IC0) return rb_w_bytes();
+  // the flexible-CG update of the learned-preconditioner runs: x, r, p, q in; x, r out
+  return (double)n_ * (6.0 * S_ * 8 + 8);
+}
+
 void cg_true(const OpDev<double>& op, const double* B, const double* x, double* r, int n, int S, double* part,
              double* tot, int grid, hipStream_t st) {
   switch (S) {

@@ -42,6 +42,9 @@ class InnerCG {
   // Algorithmic HBM bytes of one iteration kernel (LYAP_K_CG_DIR) of this
   // preconditioner's CG.
   double iter_bytes() const;
+  // ... and of the second kernel (LYAP_K_CG_UPD) where an iteration has two
+  // (IC(0): the Schur product sweep; the learned preconditioner's FCG update).
+  double upd_bytes() const;
   // Later solves use flexible CG with z = M(r) from the network.
   void set_net(PcNetGpu* net) { net_ = net; }
   // The next (Jacobi) solve keeps (r, x) every `every` iterations, at most
@@ -58,6 +61,7 @@ class InnerCG {
   template <bool K7, int S>
   void rb_solve_templ(const double* B, double* X, int restarts, int chunk, KernelTimer* kt);
   double rb_iter_bytes() const;
+  double rb_w_bytes() const;
   OpDev<double> op_;
   int n_, S_, pc_, max_iter_;
   double eta_;
@@ -71,8 +75,9 @@ class InnerCG {
   DevBuf r1_, w0_, w1_, s0_, s1_;  // double-buffered r, w = K M r, s = K p of the single-reduction CG
   int harvest_every_ = 0, harvest_keep_ = 0;
   // red-black IC(0): 1 / D_r (red slots), D_b and 1 / Sigma_bb (black slots),
-  // and the condensed iteration's vectors (r, w, s double buffered)
-  DevBuf rb_rinv_, rb_db_, rb_sinv_, rb_x_, rb_p_, rb_r0_, rb_r1_, rb_w0_, rb_w1_, rb_s0_, rb_s1_;
+  // the condensed iteration's vectors (r, w, s double buffered), u at the
+  // black slots and v = D_r^{-1} E^T u at the red slots
+  DevBuf rb_rinv_, rb_db_, rb_sinv_, rb_x_, rb_p_, rb_r0_, rb_r1_, rb_w0_, rb_w1_, rb_s0_, rb_s1_, rb_u_, rb_v_;
   int rb_grid_ = 0;
   std::vector<DevBuf> hr_, hx_;
 };

@@ -22,10 +22,11 @@
 // row-interleaved (slot q holds its S right-hand-side entries contiguously).
 //
 // The iteration is the single-reduction (Chronopoulos-Gear) form of the
-// Jacobi kernel in pcg.hip: one kernel per iteration, the product
-// Sigma u = D_b u - E D_r^{-1} E^T u taken at each black cell from u at the
-// 19 black cells within two stencil steps (through its six red neighbours),
-// u there recomputed from the previous iterate.
+// Jacobi kernel in pcg.hip, two kernels per iteration: the update with
+// v = D_r^{-1} E^T u at the red cells, then Sigma u = D_b u - E v with the
+// next iteration's inner products.  (One kernel that took Sigma u at each black
+// cell from u at the 19 black cells within two stencil steps, recomputed
+// there, issued about 170 loads per black cell and ran 2.7 times slower.)
 #include <cmath>
 
 #include "pcg.hpp"
@@ -91,39 +92,6 @@ __device__ __forceinline__ void for_neighbours(const OpDev<double>& op, const Rb
   if (i < nx - 1) f(i + 1, j, l, r + 1, fx<K7>(op, r), 3);
   if (j < g.ny - 1) f(i, j + 1, l, r + nx, fy<K7>(op, r), 4);
   if (l < g.nz - 1) f(i, j, l + 1, r + nxy, fz<K7>(op, r), 5);
-}
-
-// (Sigma u) at the black cell (i, j, l): D_b u_b - sum over its red
-// neighbours r of t_br / D_r * sum over r's neighbours b' of t_rb' u_b'.
-// db = D_b, ub = u at the cell itself; ueval(slot, out) gives u at another
-// black cell.
-template <bool K7, int S, typename U>
-__device__ __forceinline__ void schur_row(const OpDev<double>& op, const RbGeom& g, const double* __restrict__ rinv,
-                                          int i, int j, int l, double db, const double (&ub)[S], U&& ueval,
-                                          double (&out)[S]) {
-  const int r = i + g.nx * (j + g.ny * l);
-#pragma unroll
-  for (int c = 0; c < S; ++c) out[c] = db * ub[c];
-  for_neighbours<K7>(op, g, i, j, l, r, [&](int ri, int rj, int rl, int rr, double tbr, int d) {
-    const int back = 5 - d;  // direction from the red cell back to (i, j, l)
-    double acc[S];
-#pragma unroll
-    for (int c = 0; c < S; ++c) acc[c] = 0.0;
-    for_neighbours<K7>(op, g, ri, rj, rl, rr, [&](int bi, int bj, int bl, int, double t, int e) {
-      double u[S];
-      if (e == back) {
-#pragma unroll
-        for (int c = 0; c < S; ++c) u[c] = ub[c];
-      } else {
-        ueval(rb_slot(g, bi, bj, bl), u);
-      }
-#pragma unroll
-      for (int c = 0; c < S; ++c) acc[c] = fma(t, u[c], acc[c]);
-    });
-    const double f = tbr * rinv[rb_slot(g, ri, rj, rl)];
-#pragma unroll
-    for (int c = 0; c < S; ++c) out[c] = fma(-f, acc[c], out[c]);
-  });
 }
 
 // Once per operator: rinv = 1 / D_r at the red slots; at the black slots
@@ -219,153 +187,178 @@ __global__ __launch_bounds__(256) void k_rb_thr(const double* pin, int nparts, d
   if (threadIdx.x < S) state[threadIdx.x] = eta2 * red[threadIdx.x];
 }
 
-// Start of a condensed solve: r given, w = Sigma u, u = diag(Sigma)^{-1} r;
-// partials gamma = r.u, delta = w.u, r.r.
-template <bool K7, int S, int NT>
-__global__ __launch_bounds__(NT) void k_rb_start(OpDev<double> op, RbGeom g, const double* __restrict__ rinv,
-                                                 const double* __restrict__ db, const double* __restrict__ sinv, const double* __restrict__ r,
-                                                 double* __restrict__ w, double* pout) {
-  __shared__ double red[pow2_at_least(3 * S) * (NT / 64)];
-  double acc[3 * S];
+// The product Sigma u = D_b u - E D_r^{-1} E^T u is taken in two sweeps, each
+// one kernel over the compact slots: v = D_r^{-1} (T^T u) at the red cells
+// (T = -E, the transmissibilities), then D_b u - T v at the black cells.
+//
+// Sweep 1 of an iteration (it counted from the start of this (re)start),
+// the single-reduction CG update at the black slot and v at the red slot:
+//   beta = gamma_i / gamma_{i-1},  alpha = gamma_i / (delta_i - beta gamma_i / alpha_{i-1}),
+//   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
+//   u = diag(Sigma)^{-1} r  (stored),
+// and at the red cell v = D_r^{-1} sum_b t_rb u_b with u at its black
+// neighbours recomputed from their previous r, w, s (the same operations as
+// their own update, so the same bits).  START: no update (u = diag(Sigma)^{-1} r
+// of the given r).  A column whose r.r is at most state[c] is frozen
+// (alpha = beta = 0).
+template <bool K7, int S, int NT, bool START>
+__global__ __launch_bounds__(NT) void k_rb_upd(OpDev<double> op, RbGeom g, const double* __restrict__ rinv,
+                                               const double* __restrict__ sinv, double* __restrict__ x,
+                                               const double* __restrict__ rin, double* __restrict__ rout,
+                                               const double* __restrict__ win, double* __restrict__ p,
+                                               const double* __restrict__ sin, double* __restrict__ sout,
+                                               double* __restrict__ u, double* __restrict__ v, CgIter* log, int it,
+                                               const double* state, const double* pin, int nparts, int* flag) {
+  double alpha[S], beta[S];
 #pragma unroll
-  for (int c = 0; c < 3 * S; ++c) acc[c] = 0.0;
-  auto ueval = [&](int q, double (&u)[S]) {
-    load_row<double, S>(r + (size_t)q * S, u);
+  for (int c = 0; c < S; ++c) alpha[c] = beta[c] = 0.0;
+  if constexpr (!START) {
+    __shared__ double red[pow2_at_least(3 * S) * (NT / 64)];
+    reduce_partials<3 * S, NT>(pin, nparts, red);
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+      const double gm = uniform_d(red[c]);
+      const double dl = uniform_d(red[S + c]);
+      const double rr = uniform_d(red[2 * S + c]);
+      const bool active = rr > uniform_d(state[c]);
+      double a = 0.0, b = 0.0;
+      bool bad = false;
+      if (active) {
+        if (it == 0) {
+          bad = !(dl > 0.0);
+          a = bad ? 0.0 : gm / dl;
+        } else {
+          const double gp = uniform_d(log[it - 1].rho[c]);
+          const double ap = uniform_d(log[it - 1].alpha[c]);
+          b = gm / gp;
+          const double den = dl - b * gm / ap;
+          bad = !(den > 0.0) || !(gp > 0.0) || !(ap > 0.0);
+          a = bad ? 0.0 : gm / den;
+          if (bad) b = 0.0;
+        }
+      }
+      alpha[c] = a;
+      beta[c] = b;
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        log[it].rho[c] = gm;
+        log[it].rr[c] = rr;
+        log[it].sigma[c] = dl;
+        log[it].alpha[c] = a;
+        if (bad) flag[1] = it + 1;
+      }
+    }
+  }
+  const double* so = (!START && it > 0) ? sin : nullptr;
+  // u of the new iterate at black slot q from the previous r, w, s there
+  auto ueval = [&](int q, double (&uv)[S]) {
+    double rv[S];
+    load_row<double, S>(rin + (size_t)q * S, rv);
     const double m = sinv[q];
+    if constexpr (START) {
 #pragma unroll
-    for (int c = 0; c < S; ++c) u[c] *= m;
+      for (int c = 0; c < S; ++c) uv[c] = m * rv[c];
+    } else {
+      double wv[S];
+      load_row<double, S>(win + (size_t)q * S, wv);
+      if (so) {
+        double sv[S];
+        load_row<double, S>(so + (size_t)q * S, sv);
+#pragma unroll
+        for (int c = 0; c < S; ++c) wv[c] = fma(beta[c], sv[c], wv[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < S; ++c) uv[c] = m * fma(-alpha[c], wv[c], rv[c]);
+    }
   };
   int lo, hi;
   op_rows(blockIdx.x, gridDim.x, g.nb, lo, hi);
   for (int q = lo + threadIdx.x; q < hi; q += NT) {
     int i, j, l;
-    if (!rb_cell(g, q, 1, i, j, l)) continue;
-    double rv[S], ub[S], wv[S];
-    load_row<double, S>(r + (size_t)q * S, rv);
-    const double m = sinv[q];
+    if (rb_cell(g, q, 1, i, j, l)) {
+      double rv[S], uv[S];
+      load_row<double, S>(rin + (size_t)q * S, rv);
+      const double m = sinv[q];
+      if constexpr (START) {
 #pragma unroll
-    for (int c = 0; c < S; ++c) ub[c] = m * rv[c];
-    schur_row<K7, S>(op, g, rinv, i, j, l, db[q], ub, ueval, wv);
+        for (int c = 0; c < S; ++c) uv[c] = m * rv[c];
+      } else {
+        double wv[S], pv[S], sv[S], xv[S];
+        load_row<double, S>(win + (size_t)q * S, wv);
+        load_row<double, S>(x + (size_t)q * S, xv);
+        if (so) {
+          load_row<double, S>(p + (size_t)q * S, pv);
+          load_row<double, S>(so + (size_t)q * S, sv);
+        } else {
+#pragma unroll
+          for (int c = 0; c < S; ++c) pv[c] = sv[c] = 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+          pv[c] = fma(beta[c], pv[c], m * rv[c]);
+          sv[c] = fma(beta[c], sv[c], wv[c]);
+          xv[c] = fma(alpha[c], pv[c], xv[c]);
+          rv[c] = fma(-alpha[c], sv[c], rv[c]);
+          uv[c] = m * rv[c];
+        }
+        store_row<double, S>(p + (size_t)q * S, pv);
+        store_row<double, S>(sout + (size_t)q * S, sv);
+        store_row<double, S>(x + (size_t)q * S, xv);
+        store_row<double, S>(rout + (size_t)q * S, rv);
+      }
+      store_row<double, S>(u + (size_t)q * S, uv);
+    }
+    if (rb_cell(g, q, 0, i, j, l)) {
+      double acc[S];
+#pragma unroll
+      for (int c = 0; c < S; ++c) acc[c] = 0.0;
+      for_neighbours<K7>(op, g, i, j, l, i + g.nx * (j + g.ny * l), [&](int bi, int bj, int bl, int, double t, int) {
+        double uv[S];
+        ueval(rb_slot(g, bi, bj, bl), uv);
+#pragma unroll
+        for (int c = 0; c < S; ++c) acc[c] = fma(t, uv[c], acc[c]);
+      });
+      const double ri = rinv[q];
+#pragma unroll
+      for (int c = 0; c < S; ++c) acc[c] *= ri;
+      store_row<double, S>(v + (size_t)q * S, acc);
+    }
+  }
+}
+
+// Sweep 2: w = Sigma u = D_b u - sum_r t_br v_r at the black slots, and the
+// partials gamma = r.u, delta = w.u, r.r of the next iteration.
+template <bool K7, int S, int NT>
+__global__ __launch_bounds__(NT) void k_rb_w(OpDev<double> op, RbGeom g, const double* __restrict__ db,
+                                             const double* __restrict__ r, const double* __restrict__ u,
+                                             const double* __restrict__ v, double* __restrict__ w, double* pout) {
+  __shared__ double red[pow2_at_least(3 * S) * (NT / 64)];
+  double acc[3 * S];
+#pragma unroll
+  for (int c = 0; c < 3 * S; ++c) acc[c] = 0.0;
+  int lo, hi;
+  op_rows(blockIdx.x, gridDim.x, g.nb, lo, hi);
+  for (int q = lo + threadIdx.x; q < hi; q += NT) {
+    int i, j, l;
+    if (!rb_cell(g, q, 1, i, j, l)) continue;
+    double rv[S], uv[S], wv[S];
+    load_row<double, S>(r + (size_t)q * S, rv);
+    load_row<double, S>(u + (size_t)q * S, uv);
+    const double d = db[q];
+#pragma unroll
+    for (int c = 0; c < S; ++c) wv[c] = d * uv[c];
+    for_neighbours<K7>(op, g, i, j, l, i + g.nx * (j + g.ny * l), [&](int ri, int rj, int rl, int, double t, int) {
+      double vv[S];
+      load_row<double, S>(v + (size_t)rb_slot(g, ri, rj, rl) * S, vv);
+#pragma unroll
+      for (int c = 0; c < S; ++c) wv[c] = fma(-t, vv[c], wv[c]);
+    });
 #pragma unroll
     for (int c = 0; c < S; ++c) {
-      acc[c] = fma(rv[c], ub[c], acc[c]);
-      acc[S + c] = fma(wv[c], ub[c], acc[S + c]);
+      acc[c] = fma(rv[c], uv[c], acc[c]);
+      acc[S + c] = fma(wv[c], uv[c], acc[S + c]);
       acc[2 * S + c] = fma(rv[c], rv[c], acc[2 * S + c]);
     }
     store_row<double, S>(w + (size_t)q * S, wv);
-  }
-  write_partial<3 * S, NT>(acc, red, pout);
-}
-
-// One iteration of the single-reduction CG on Sigma (it counted from the
-// start of this (re)start):
-//   beta = gamma_i / gamma_{i-1},  alpha = gamma_i / (delta_i - beta gamma_i / alpha_{i-1}),
-//   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
-//   u = diag(Sigma)^{-1} r,  w = Sigma u  and the next gamma, delta, r.r.
-// A column whose r.r is at most state[c] is frozen (alpha = beta = 0).
-template <bool K7, int S, int NT>
-__global__ __launch_bounds__(NT) void k_rb_iter(OpDev<double> op, RbGeom g, const double* __restrict__ rinv,
-                                                const double* __restrict__ db, const double* __restrict__ sinv, double* __restrict__ x,
-                                                const double* __restrict__ rin, double* __restrict__ rout,
-                                                const double* __restrict__ win, double* __restrict__ wout,
-                                                double* __restrict__ p, const double* __restrict__ sin,
-                                                double* __restrict__ sout, CgIter* log, int it,
-                                                const double* state, const double* pin, int nparts, double* pout,
-                                                int* flag) {
-  __shared__ double red[pow2_at_least(3 * S) * (NT / 64)];
-  reduce_partials<3 * S, NT>(pin, nparts, red);
-  double alpha[S], beta[S];
-#pragma unroll
-  for (int c = 0; c < S; ++c) {
-    const double gm = uniform_d(red[c]);
-    const double dl = uniform_d(red[S + c]);
-    const double rr = uniform_d(red[2 * S + c]);
-    const bool active = rr > uniform_d(state[c]);
-    double a = 0.0, b = 0.0;
-    bool bad = false;
-    if (active) {
-      if (it == 0) {
-        bad = !(dl > 0.0);
-        a = bad ? 0.0 : gm / dl;
-      } else {
-        const double gp = uniform_d(log[it - 1].rho[c]);
-        const double ap = uniform_d(log[it - 1].alpha[c]);
-        b = gm / gp;
-        const double den = dl - b * gm / ap;
-        bad = !(den > 0.0) || !(gp > 0.0) || !(ap > 0.0);
-        a = bad ? 0.0 : gm / den;
-        if (bad) b = 0.0;
-      }
-    }
-    alpha[c] = a;
-    beta[c] = b;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      log[it].rho[c] = gm;
-      log[it].rr[c] = rr;
-      log[it].sigma[c] = dl;
-      log[it].alpha[c] = a;
-      if (bad) flag[1] = it + 1;
-    }
-  }
-  __syncthreads();
-  const double* so = it > 0 ? sin : nullptr;
-  // u of the new iterate at another black slot, from the previous r, w, s there
-  auto ueval = [&](int q, double (&u)[S]) {
-    double rv[S], wv[S];
-    load_row<double, S>(rin + (size_t)q * S, rv);
-    load_row<double, S>(win + (size_t)q * S, wv);
-    if (so) {
-      double sv[S];
-      load_row<double, S>(so + (size_t)q * S, sv);
-#pragma unroll
-      for (int c = 0; c < S; ++c) wv[c] = fma(beta[c], sv[c], wv[c]);
-    }
-    const double m = sinv[q];
-#pragma unroll
-    for (int c = 0; c < S; ++c) u[c] = m * fma(-alpha[c], wv[c], rv[c]);
-  };
-  double acc[3 * S];
-#pragma unroll
-  for (int c = 0; c < 3 * S; ++c) acc[c] = 0.0;
-  int lo, hi;
-  op_rows(blockIdx.x, gridDim.x, g.nb, lo, hi);
-  for (int q = lo + threadIdx.x; q < hi; q += NT) {
-    int i, j, l;
-    if (!rb_cell(g, q, 1, i, j, l)) continue;
-    double rv[S], wv[S], pv[S], sv[S], xv[S];
-    load_row<double, S>(rin + (size_t)q * S, rv);
-    load_row<double, S>(win + (size_t)q * S, wv);
-    load_row<double, S>(x + (size_t)q * S, xv);
-    const double m = sinv[q];
-    if (so) {
-      load_row<double, S>(p + (size_t)q * S, pv);
-      load_row<double, S>(so + (size_t)q * S, sv);
-    } else {
-#pragma unroll
-      for (int c = 0; c < S; ++c) pv[c] = sv[c] = 0.0;
-    }
-    double ub[S];
-#pragma unroll
-    for (int c = 0; c < S; ++c) {
-      pv[c] = fma(beta[c], pv[c], m * rv[c]);
-      sv[c] = fma(beta[c], sv[c], wv[c]);
-      xv[c] = fma(alpha[c], pv[c], xv[c]);
-      rv[c] = fma(-alpha[c], sv[c], rv[c]);
-      ub[c] = m * rv[c];
-    }
-    store_row<double, S>(p + (size_t)q * S, pv);
-    store_row<double, S>(sout + (size_t)q * S, sv);
-    store_row<double, S>(x + (size_t)q * S, xv);
-    store_row<double, S>(rout + (size_t)q * S, rv);
-    double wn[S];
-    schur_row<K7, S>(op, g, rinv, i, j, l, db[q], ub, ueval, wn);
-#pragma unroll
-    for (int c = 0; c < S; ++c) {
-      acc[c] = fma(rv[c], ub[c], acc[c]);
-      acc[S + c] = fma(wn[c], ub[c], acc[S + c]);
-      acc[2 * S + c] = fma(rv[c], rv[c], acc[2 * S + c]);
-    }
-    store_row<double, S>(wout + (size_t)q * S, wn);
   }
   write_partial<3 * S, NT>(acc, red, pout);
 }
@@ -442,7 +435,8 @@ void InnerCG::setup_rb() {
   rb_db_.alloc(slots * sizeof(double));
   rb_sinv_.alloc(slots * sizeof(double));
   const size_t blk = slots * S_ * sizeof(double);
-  for (DevBuf* b : {&rb_x_, &rb_p_, &rb_r0_, &rb_r1_, &rb_w0_, &rb_w1_, &rb_s0_, &rb_s1_}) b->alloc(blk);
+  for (DevBuf* b : {&rb_x_, &rb_p_, &rb_r0_, &rb_r1_, &rb_w0_, &rb_w1_, &rb_s0_, &rb_s1_, &rb_u_, &rb_v_})
+    b->alloc(blk);
   rb_grid_ = stream_grid(g.nb);
   LYAP_HIP(hipMemsetAsync(flag_.p, 0, 64, st_));
   const int gs = grid_for(g.nb, 1, 1024);
@@ -461,11 +455,18 @@ void InnerCG::setup_rb() {
 }
 
 double InnerCG::rb_iter_bytes() const {
-  // one condensed iteration over the black cells: x, r, w, s, p in and out, 1 / Sigma_bb
-  // and D_b; D_r^{-1} at the red cells; the face transmissibilities of the whole grid
-  const double nblack = (double)n_ / 2.0;
+  // sweep 1 (LYAP_K_CG_DIR): at the black cells x, r, w, s, p and 1 / Sigma_bb in, x, r, s, p, u
+  // out; at the red cells D_r^{-1} and the faces in, v out
+  const double half = (double)n_ / 2.0;
   const double faces = op_.kind == LYAP_OP_STENCIL7 ? (op_.nz > 1 ? 3.0 : 2.0) * 8.0 * n_ : 0.0;
-  return nblack * (10.0 * S_ * 8 + 16.0) + (double)n_ / 2.0 * 8.0 + faces;
+  return half * (10.0 * S_ * 8 + 8.0) + half * (8.0 + S_ * 8.0) + faces;
+}
+
+double InnerCG::rb_w_bytes() const {
+  // sweep 2 (LYAP_K_CG_UPD): r, u, D_b at the black cells, v at the red cells and the faces in, w out
+  const double half = (double)n_ / 2.0;
+  const double faces = op_.kind == LYAP_OP_STENCIL7 ? (op_.nz > 1 ? 3.0 : 2.0) * 8.0 * n_ : 0.0;
+  return half * (3.0 * S_ * 8 + 8.0) + half * S_ * 8.0 + faces;
 }
 
 template <bool K7, int S>
@@ -494,8 +495,12 @@ void InnerCG::rb_solve_templ(const double* B, double* X, int restarts, int chunk
                          state_.as<double>());
       LYAP_LAUNCHED("k_rb_thr");
     }
-    hipLaunchKernelGGL((k_rb_start<K7, S, NT>), dim3(G), dim3(NT), 0, st_, op_, g, rinv, db, sinv, rb[0], wb[0],
-                       partA_.as<double>());
+    hipLaunchKernelGGL((k_rb_upd<K7, S, NT, true>), dim3(G), dim3(NT), 0, st_, op_, g, rinv, sinv,
+                       rb_x_.as<double>(), rb[0], rb[1], wb[0], rb_p_.as<double>(), sb[1], sb[0], rb_u_.as<double>(),
+                       rb_v_.as<double>(), log_.as<CgIter>(), 0, state_.as<double>(), partA_.as<double>(), G,
+                       flag_.as<int>());
+    hipLaunchKernelGGL((k_rb_w<K7, S, NT>), dim3(G), dim3(NT), 0, st_, op_, g, db, rb[0], rb_u_.as<double>(),
+                       rb_v_.as<double>(), wb[0], partA_.as<double>());
     LYAP_LAUNCHED("k_rb_start");
     int it = 0;
     bool done = false;
@@ -503,13 +508,14 @@ void InnerCG::rb_solve_templ(const double* B, double* X, int restarts, int chunk
       const int it0 = it;
       const int cnt = std::min(chunk, max_iter_ - total - it);
       for (int c = 0; c < cnt; ++c, ++it) {
-        double* pin = (it % 2 == 0) ? partA_.as<double>() : partB_.as<double>();
-        double* pout = (it % 2 == 0) ? partB_.as<double>() : partA_.as<double>();
         if (kt) kt->mark(LYAP_K_CG_DIR);
-        hipLaunchKernelGGL((k_rb_iter<K7, S, NT>), dim3(G), dim3(NT), 0, st_, op_, g, rinv, db, sinv,
-                           rb_x_.as<double>(), rb[it % 2], rb[(it + 1) % 2], wb[it % 2], wb[(it + 1) % 2],
-                           rb_p_.as<double>(), sb[(it + 1) % 2], sb[it % 2], log_.as<CgIter>(), it,
-                           state_.as<double>(), pin, G, pout, flag_.as<int>());
+        hipLaunchKernelGGL((k_rb_upd<K7, S, NT, false>), dim3(G), dim3(NT), 0, st_, op_, g, rinv, sinv,
+                           rb_x_.as<double>(), rb[it % 2], rb[(it + 1) % 2], wb[it % 2], rb_p_.as<double>(),
+                           sb[(it + 1) % 2], sb[it % 2], rb_u_.as<double>(), rb_v_.as<double>(), log_.as<CgIter>(),
+                           it, state_.as<double>(), partA_.as<double>(), G, flag_.as<int>());
+        if (kt) kt->mark(LYAP_K_CG_UPD);
+        hipLaunchKernelGGL((k_rb_w<K7, S, NT>), dim3(G), dim3(NT), 0, st_, op_, g, db, rb[(it + 1) % 2],
+                           rb_u_.as<double>(), rb_v_.as<double>(), wb[(it + 1) % 2], partA_.as<double>());
       }
       LYAP_LAUNCHED("k_rb_iter");
       if (kt) kt->collect();
