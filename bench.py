@@ -1,21 +1,31 @@
 #!/usr/bin/env python3
-"""Benchmark: Lyapunov solve A X + X A + C C^T = 0 to relative residual 1e-8,
-standard block Krylov with the two-pass factor, on one MI355X.
+"""Benchmark: the extended Krylov method (Section 4) for A X + X A + C C^T = 0
+to relative residual 1e-8 at n = 1e6 on one MI355X, with the learned inner
+preconditioner against the plain incomplete-Cholesky one.
 
 Workload (one "step" = one whole solve through the C ABI, every row of the hot
-path: SpMM, block MGS x2, Cholesky-QR2, coefficient log and T_m band, residual
-checks by Proposition 1 with the GPU band eigensolver, truncation, second pass
-and Z accumulation):
-    A = -(5-point Laplacian) on a 1000 x 1000 interior grid (n = 1e6, h = 1/1001),
-    C = n x 4 standard Gaussian (column c from default_rng([2, c])),
-    FP32 storage of the basis and SpMM, FP64 coefficients / eigen / residual,
-    tol 1e-8, adaptive check schedule.
-Inputs are resident on the GPU before the timed region starts.
+path: the start block [C, A^{-1} C], per step W = [A V_j^(1), A^{-1} V_j^(2)]
+with FP64 inner conjugate gradients certified by their true residual (1e-12),
+full block reorthogonalisation and Cholesky QR, the projected matrix, residual
+checks by Proposition 1 with the GPU band eigensolver, truncation and Z):
+    A = -div(k grad u), cell-centred finite volumes on 100^3 cells (n = 1e6),
+    lognormal k (sigma 1, seed 3), C = n x 1 standard Gaussian (seed 3),
+    tol 1e-8, adaptive check schedule, FP64.
+`value` is the learned-preconditioner run (network trained inside the solve on
+its first inner solve, training time included); the plain run (IC(0) in
+red-black order, condensed form) and a Jacobi run are timed beside it, and
+every run's explicit FP64 residual ||A Z Z^T + Z Z^T A + C C^T||_F / ||C||_F^2
+is reported.  Extras: the standard Krylov + two-pass configuration on the
+1000 x 1000 Laplacian (n = 1e6, s = 4) in FP64 and FP32 storage (time,
+explicit residual), and the operator application (SpMM) alone in and out of
+the Infinity Cache.  Inputs are resident on the GPU before the timed region.
 
-Prints one JSON line.  `value` is the wall time of one solve (seconds, lower is
-better); the roofline object is for the kernel with the largest device time,
-with algorithmic bytes per launch over the launch time measured by HIP events
-on the solver's stream during the timed solves.
+Prints one JSON line (lower `value` is better).  `roofline` is for the kernel
+kind with the largest device time in the headline run, its launch time taken
+with HIP events on the solver's stream in separate profiled solves.  The
+`cpu_baseline` leg times the CPU FP64 oracle on a bounded sample of the same
+workload and states the GPU runs' errors against the oracle's Krylov-free
+references.
 """
 import argparse
 import json
@@ -28,6 +38,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# learned preconditioner, C = 4 channels: two 3x3x3 convolutions (2 -> 4 -> 4)
+# and their adjoints per application, 2 flops per multiply-add
+PCNET_FLOPS_PER_POINT = 2 * 27 * (4 * 4 + 2 * 4 * 4)
 
 # HBM bytes per launch from rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE,
 # KiB per dispatch, median over the dispatches of one `bench.py --steps 1
@@ -63,16 +77,20 @@ def parse():
                     help="basis storage (default f32; f64 for smallb, whose uniform right-hand sides floor the "
                          "true residual near 1e-4 with an f32 basis)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="c3: skip the standard Krylov and SpMM extras")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--explicit-residual", action="store_true", help="also report the explicit FP64 residual")
-    ap.add_argument("--inner", choices=["jacobi", "learned"], default="jacobi",
+    ap.add_argument("--inner", choices=["jacobi", "ic0", "learned"], default="jacobi",
                     help="ext workload: inner preconditioner (learned = trained in the run, time counted)")
     ap.add_argument("--method", choices=["std", "ext"], default="std",
                     help="sylv workload: standard or extended Krylov spaces (ext: FP64, inner Jacobi-PCG)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run one plain 256 MiB device copy (reference for the HBM byte counters)")
-    ap.add_argument("--workload", choices=["std", "ext", "sylv", "batch", "e1", "e5", "smallb", "gen"], default="std",
-                    help="std: standard Krylov + two-pass on the 2D Laplacian (the headline); "
+    ap.add_argument("--workload", choices=["c3", "std", "ext", "sylv", "batch", "e1", "e5", "smallb", "gen"],
+                    default="c3",
+                    help="c3: extended Krylov on the 100^3 lognormal FV operator, learned vs IC(0) inner "
+                         "preconditioner (the headline); "
+                         "std: standard Krylov + two-pass on the 2D Laplacian; "
                          "ext: extended Krylov + inner PCG on the 100^3 lognormal finite-volume operator; "
                          "sylv: Sylvester, 700^2 Laplacian and 80^3 lognormal FV, s=2; "
                          "batch: 64 shifted Laplacians N_i in 64..512, s_i in {1,2,4}, grouped launches; "
@@ -192,7 +210,7 @@ def main_ext(args):
     C = gaussian_C(op.n, 1, 3)
     dop = b.device_op(op, device=dev)
     Cd = torch.from_numpy(C).to(dev)
-    pc = b.PC_LEARNED if args.inner == "learned" else b.PC_JACOBI
+    pc = {"learned": b.PC_LEARNED, "ic0": b.PC_IC0}.get(args.inner, b.PC_JACOBI)
     kw = dict(tol=1e-8, method=b.METHOD_EXT, check_every=0, inner_pc=pc, inner_tol=1e-12)
     for _ in range(args.warmup):
         b.lyap_solve(dop, Cd, **kw)
@@ -585,6 +603,231 @@ def main_gen(args):
     print(json.dumps(out), flush=True)
 
 
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol = None
+    for _ in range(steps):
+        sol = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, sol
+
+
+def _host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except Exception:
+        return os.cpu_count()
+
+
+def oracle_leg_c3(op, C, m_gpu, budget_s):
+    """cpu_baseline of the headline: the CPU FP64 oracle's extended Krylov
+    method (oracle.extended, Section 4) with its red-black IC(0) inner solves
+    in condensed form (oracle.pcg.schur_rb_cg, true residual 1e-12) -- the
+    plain run's algorithm -- on the same operator and right-hand side, for
+    about ``budget_s`` seconds: the start block and as many steps as fit,
+    projected to the GPU run's m steps."""
+    import numpy as np
+    from oracle import extended as E
+    from oracle import pcg as P
+    A = op.to_scipy()
+    grid = (op.nx, op.ny, op.nz)
+
+    def solve(B):
+        X = np.empty_like(B)
+        for c in range(B.shape[1]):
+            X[:, c] = P.schur_rb_cg(A, B[:, c], grid, eta=1e-12, max_iter=20000).x
+        return X
+
+    t0 = time.perf_counter()
+    side = E.EKSide(A, C, solve)
+    t_start = time.perf_counter() - t0
+    steps = 0
+    while True:
+        side.step()
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= m_gpu:
+            break
+    per_step = (el - t_start) / steps
+    return {"value": round(t_start + per_step * m_gpu, 2), "unit": "s", "cores": _host_cores(), "kind": "oracle",
+            "sample": (f"the FP64 oracle's extended Krylov start block and its first {steps} steps (NumPy/SciPy; "
+                       f"inner solves by red-black IC(0) CG in condensed form to a true residual of 1e-12, the "
+                       f"plain run's algorithm; sparse products single-threaded) on the same n={op.n} problem in "
+                       f"{el:.1f} s, projected to the GPU's m={m_gpu} steps; the residual checks and Z are not "
+                       f"included, so this is a lower bound")}
+
+
+def laplace2d_factor_error(N, Z, C):
+    """||Z Z^T - X||_F / ||X||_F for the 5-point Laplacian on an N x N grid,
+    X the oracle's Krylov-free solution (sine-transform eigenbasis and an
+    exponential sum, oracle.dense): both factors taken to the eigenbasis (an
+    orthogonal change of basis) and compared through one QR of [Z^, Y^] on the
+    GPU (FP64).  Evaluation of a result, after the timed region."""
+    import numpy as np
+    import torch
+    from oracle import dense as D
+    Zh = torch.from_numpy(D.dst2_columns(Z.cpu().numpy(), N)).to(Z.device)
+    Yh = torch.from_numpy(D.laplace2d_expsum_factor(N, C)).to(Z.device)
+    t = Zh.shape[1]
+    R = torch.linalg.qr(torch.cat([Zh, Yh], dim=1), mode="r")[1]
+    sgn = torch.cat([torch.ones(t, dtype=R.dtype, device=R.device),
+                     -torch.ones(Yh.shape[1], dtype=R.dtype, device=R.device)])
+    num = torch.linalg.norm((R * sgn[None, :]) @ R.T)
+    den = torch.linalg.norm(Yh.T @ Yh)
+    return float(num / den)
+
+
+def main_c3(args):
+    import numpy as np
+    import torch
+    from paper_1602_05033_amd import binding as b
+    from workloads import fv3d, laplace2d, gaussian_C
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    b.load()
+    dev = torch.device("cuda:0")
+    N = 100
+    op = fv3d(N, 1.0, 3)
+    C = gaussian_C(op.n, 1, 3)
+    dop = b.device_op(op, device=dev)
+    Cd = torch.from_numpy(C).to(dev)
+    kw = dict(tol=1e-8, method=b.METHOD_EXT, check_every=0, inner_tol=1e-12)
+    legs = {}
+    plan = (("learned", b.PC_LEARNED, args.steps, args.warmup),
+            ("ic0", b.PC_IC0, args.steps, args.warmup),
+            ("jacobi", b.PC_JACOBI, min(args.steps, 3), min(args.warmup, 1)))
+    for name, pc, k, w in plan:
+        sec, sol = _timed(lambda pc=pc: b.lyap_solve(dop, Cd, inner_pc=pc, **kw), k, w)
+        assert sol.status == b.OK, (name, sol.status)
+        ex = explicit_residual(b, dop, sol.Z, Cd, sol.beta ** 2)
+        legs[name] = {"pc": pc, "sec": sec, "sol": sol, "steps": k, "explicit": ex}
+        print(f"# c3 {name}: {sec:.4f} s m={sol.m} inner_iters={sol.inner_iters} explicit={ex:.3e}",
+              file=sys.stderr, flush=True)
+    # per-kernel device times: one separate profiled solve per preconditioner
+    # (HIP events around every kernel on the solver's stream)
+    tables = {}
+    for name, leg in legs.items():
+        ps = b.lyap_solve(dop, Cd, inner_pc=leg["pc"], profile=True, **kw)
+        tables[name] = aggregate([ps])
+    head = legs["learned"]
+    agg = tables["learned"]
+    dom = max(agg, key=lambda k: agg[k]["ms"])
+    avg_ms = agg[dom]["ms"] / agg[dom]["n"]
+    if dom == "pcnet":
+        flops = PCNET_FLOPS_PER_POINT * op.n
+        tf = flops / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": "pcnet (k_pc_conv4_r, k_pc_conv4 x2, k_pc_conv4_out)",
+                "achieved": round(tf, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                "flops_per_launch": flops, "bytes_per_launch": agg[dom]["bytes_per_launch"],
+                "avg_launch_us": round(avg_ms * 1000.0, 2),
+                "note": "FP32 multiply-adds of the four convolutions of one network application; the peak counts "
+                        "packed FP32, which this build does not emit (the non-packed rate is half of it)"}
+    else:
+        bpl = agg[dom]["bytes_per_launch"]
+        gbs = bpl / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": bpl,
+                "avg_launch_us": round(avg_ms * 1000.0, 2)}
+
+    def plain_roof(tab):
+        out = {}
+        for k in ("cg_dir", "cg_upd"):
+            if k in tab and tab[k]["bytes_per_launch"] > 0:
+                a = tab[k]["ms"] / tab[k]["n"]
+                g = tab[k]["bytes_per_launch"] / (a * 1e-3) / 1e9
+                out[k] = {"bound": "hbm", "achieved": round(g, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(g / HBM_PEAK_GBS, 4), "bytes_per_launch": tab[k]["bytes_per_launch"],
+                          "avg_launch_us": round(a * 1000.0, 2)}
+        return out
+
+    def leg_result(name):
+        leg = legs[name]
+        sol = leg["sol"]
+        return {"time_s": round(leg["sec"], 4), "steps": leg["steps"], "m": sol.m, "t": sol.t,
+                "res_rel_prop1": sol.res, "res_rel_explicit": leg["explicit"],
+                "inner_iters": sol.inner_iters, "n_inner": sol.n_inner, "n_checks": sol.n_checks,
+                "time_to_tol_s": round(sol.times_ms["to_tol"] / 1000.0, 4),
+                "phases_ms": {k: round(v, 2) for k, v in sol.times_ms.items()},
+                "kernels": kernel_table(tables[name])}
+
+    res = {name: leg_result(name) for name in legs}
+    res["ic0"]["inner_cg_roofline"] = plain_roof(tables["ic0"])
+    res["jacobi"]["inner_cg_roofline"] = plain_roof(tables["jacobi"])
+    out = {
+        "metric": "time to rel. residual 1e-8 at n=1e6 (extended Krylov; learned-preconditioner inner solves, "
+                  "training included, vs plain IC(0)-CG)",
+        "value": round(head["sec"], 4), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(head["sec"] * 1000.0, 2), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"lyapunov extended Krylov, cell-centred FV -div(k grad u) on {N}^3 cells (n={op.n}), "
+                               f"lognormal k sigma=1 (seed 3), C n x 1 Gaussian (seed 3), tol 1e-8, inner CG to a "
+                               f"true residual of 1e-12: learned preconditioner (value) vs IC(0) red-black (plain)",
+                   "n": op.n, "s": 1, "tol": 1e-8, "check": "adaptive", "inner_tol": 1e-12,
+                   "network": "M = D^-1 + S K^T K S, K = two 3x3x3 convolutions 2 -> 4 -> 4 channels, FP32"},
+        "result": {"learned": res["learned"], "plain_ic0": res["ic0"], "jacobi": res["jacobi"],
+                   "plain_over_learned": round(legs["ic0"]["sec"] / head["sec"], 4)},
+        "roofline": roof,
+    }
+    if not args.no_extras:
+        out["extras"] = c3_extras(args, b, dev)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = oracle_leg_c3(op, C, head["sol"].m, args.cpu_seconds)
+        if "extras" in out:
+            # the FP64 / FP32-storage standard Krylov runs against the oracle's Krylov-free X
+            Cs = gaussian_C(1000 * 1000, 4, 2)
+            for key in ("std_laplace1000_s4_f64", "std_laplace1000_s4_f32"):
+                Z = out["extras"][key].pop("_Z")
+                out["extras"][key]["factor_error_vs_oracle_X"] = laplace2d_factor_error(1000, Z, Cs)
+                del Z
+                torch.cuda.empty_cache()
+    if "extras" in out:
+        for key in ("std_laplace1000_s4_f64", "std_laplace1000_s4_f32"):
+            out["extras"][key].pop("_Z", None)
+    print(json.dumps(out), flush=True)
+
+
+def c3_extras(args, b, dev):
+    """The standard Krylov + two-pass configuration (1000 x 1000 Laplacian,
+    s = 4, tol 1e-8) in FP64 and FP32 storage, and the SpMM alone."""
+    import torch
+    from workloads import laplace2d, gaussian_C
+    ex = {}
+    op = laplace2d(1000)
+    C = gaussian_C(op.n, 4, 2)
+    dop = b.device_op(op, device=dev)
+    Cd = torch.from_numpy(C).to(dev)
+    k = min(args.steps, 3)
+    for st, key in ((b.STORE_F64, "std_laplace1000_s4_f64"), (b.STORE_F32, "std_laplace1000_s4_f32")):
+        kw = dict(tol=1e-8, storage=st, check_every=0, two_pass=True)
+        sec, sol = _timed(lambda kw=kw: b.lyap_solve(dop, Cd, **kw), k, 1)
+        assert sol.status == b.OK, sol.status
+        e = explicit_residual(b, dop, sol.Z, Cd, sol.beta ** 2)
+        ex[key] = {"time_s": round(sec, 4), "steps": k, "m": sol.m, "t": sol.t, "res_rel_prop1": sol.res,
+                   "res_rel_explicit": e, "time_to_tol_s": round(sol.times_ms["to_tol"] / 1000.0, 4),
+                   "_Z": sol.Z}
+        print(f"# {key}: {sec:.4f} s m={sol.m} explicit={e:.3e}", file=sys.stderr, flush=True)
+    # SpMM alone (k_apply, FP32 n x 4 block, back-to-back launches timed with HIP
+    # events): n = 1e6 (V and W, 32 MB, stay in the 256 MB Infinity Cache) and
+    # n = 1.6e7 (4000 x 4000 grid, 512 MB: streamed from HBM)
+    for Ng in (1000, 4000):
+        opg = laplace2d(Ng)
+        dg = b.device_op(opg, device=dev)
+        V = torch.randn(opg.n, 4, device=dev, dtype=torch.float32)
+        ms = b.op_apply_timed(dg, V, b.STORE_F32, 100 if Ng == 1000 else 30)[1]
+        by = 2.0 * opg.n * 4 * 4
+        g = by / (ms * 1e-3) / 1e9
+        ex[f"spmm_laplace{Ng}_s4_f32"] = {"kernel": "k_apply", "bound": "hbm", "achieved": round(g, 1),
+                                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(g / HBM_PEAK_GBS, 4),
+                                          "bytes_per_launch": by, "avg_launch_us": round(ms * 1000.0, 2)}
+        del V
+    return ex
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -599,6 +842,8 @@ def main():
         return main_e5(args)
     if args.workload == "gen":
         return main_gen(args)
+    if args.workload == "c3":
+        return main_c3(args)
     if args.workload == "ext":
         return main_ext(args)
     if args.workload == "sylv":

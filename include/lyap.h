@@ -144,6 +144,24 @@ enum {
   LYAP_T_TO_TOL = 7    /* entry to the first passing check, ms            */
 };
 
+/* kernel kinds of lyap_result.kern_ms */
+enum {
+  LYAP_K_SPMM_GRAM = 0,  /* W = A V_j fused with the first block Gram product  */
+  LYAP_K_UPD_GRAM = 1,   /* block MGS update fused with the next Gram product  */
+  LYAP_K_CHOL_GRAM = 2,  /* Cholesky of W^T W and the second Gram product      */
+  LYAP_K_CHOL_STORE = 3, /* second Cholesky, V_{j+1} = W R^{-1}                */
+  LYAP_K_REPLAY = 4,     /* second pass: one whole step from the log            */
+  LYAP_K_ZFLUSH = 5,     /* Z += V_i M_i for a group of buffered blocks         */
+  LYAP_K_CHECK = 6,      /* one residual check (all its kernels)                */
+  LYAP_K_FINAL = 7,      /* truncation and Q Y-check (all its kernels)          */
+  LYAP_K_INIT = 8,       /* QR of C                                             */
+  LYAP_K_CG_DIR = 9,     /* inner CG: new direction fused with q = -A p         */
+  LYAP_K_CG_UPD = 10,    /* inner CG: x, r update and the next dot products     */
+  LYAP_K_EXT_ORTH = 11,  /* extended Krylov: full reorthogonalisation + QR + T  */
+  LYAP_K_PCNET = 12,     /* inner CG: one application of the learned network    */
+  LYAP_K_COUNT = 16      /* size of the per-kind arrays (kinds 13..15 unused)   */
+};
+
 typedef struct lyap_result {
   int32_t status;
   int32_t s;           /* block width of C                                 */
@@ -171,26 +189,11 @@ typedef struct lyap_result {
   double ms_spmm;      /* measured device time of SpMM calls, ms (0 if off) */
   int32_t owns_Z;      /* 1: Z came from hipMalloc and lyap_result_free frees it */
   /* opts->profile: device time and launch count per kernel kind (LYAP_K_*) */
-  double kern_ms[12];
-  int32_t kern_n[12];
-  double kern_bytes[12]; /* algorithmic HBM bytes per launch of each kind */
+  double kern_ms[LYAP_K_COUNT];
+  int32_t kern_n[LYAP_K_COUNT];
+  double kern_bytes[LYAP_K_COUNT]; /* algorithmic HBM bytes per launch of each kind */
 } lyap_result;
 
-/* kernel kinds of lyap_result.kern_ms */
-enum {
-  LYAP_K_SPMM_GRAM = 0,  /* W = A V_j fused with the first block Gram product  */
-  LYAP_K_UPD_GRAM = 1,   /* block MGS update fused with the next Gram product  */
-  LYAP_K_CHOL_GRAM = 2,  /* Cholesky of W^T W and the second Gram product      */
-  LYAP_K_CHOL_STORE = 3, /* second Cholesky, V_{j+1} = W R^{-1}                */
-  LYAP_K_REPLAY = 4,     /* second pass: one whole step from the log            */
-  LYAP_K_ZFLUSH = 5,     /* Z += V_i M_i for a group of buffered blocks         */
-  LYAP_K_CHECK = 6,      /* one residual check (all its kernels)                */
-  LYAP_K_FINAL = 7,      /* truncation and Q Y-check (all its kernels)          */
-  LYAP_K_INIT = 8,       /* QR of C                                             */
-  LYAP_K_CG_DIR = 9,     /* inner CG: new direction fused with q = -A p         */
-  LYAP_K_CG_UPD = 10,    /* inner CG: x, r update and the next dot products     */
-  LYAP_K_EXT_ORTH = 11   /* extended Krylov: full reorthogonalisation + QR + T  */
-};
 
 /*
  * lyap_solve — AX + XA + CC^T = 0 by Algorithm 1.
@@ -237,9 +240,9 @@ typedef struct sylv_result {
   double* gamma2;
   double* tau;         /* tau_{m+1,m} */
   double* iota;        /* iota_{m+1,m} */
-  double kern_ms[12];
-  int32_t kern_n[12];
-  double kern_bytes[12];
+  double kern_ms[LYAP_K_COUNT];
+  int32_t kern_n[LYAP_K_COUNT];
+  double kern_bytes[LYAP_K_COUNT];
 } sylv_result;
 
 /*

@@ -88,28 +88,43 @@ def exp_sum_nodes(a: float, b: float, rel: float = 1e-14):
     return np.exp(u), delta * np.exp(u)
 
 
-def lyap_laplace2d_lowrank(N: int, C: np.ndarray, shift: float = 0.0,
-                           rel: float = 1e-14, compress: float = 1e-15) -> np.ndarray:
-    """Low-rank factor Z_ref with X ~= Z_ref Z_ref^T for the 5-point Laplacian,
-    Krylov-free: -1/(l_i + l_j) = int_0^inf exp((l_i + l_j) t) dt is replaced by
-    the exponential sum of ``exp_sum_nodes`` (entrywise relative error ~rel in
-    the eigenbasis, hence ||X - Z Z^T||_F <= ~rel ||X||_F), and exp(A t) C is
-    applied exactly with the 2-D sine transform.  Columns are compressed by a
-    rank-revealing QR/SVD step at relative level ``compress``."""
+def dst2_columns(Z: np.ndarray, N: int) -> np.ndarray:
+    """Orthonormal 2-D DST-I of every column of an N^2 x t block (grid order,
+    x fastest): the coordinates of Z in the eigenvector basis of the 5-point
+    Laplacian (the transform is symmetric and orthogonal, so applying it twice
+    gives Z back)."""
+    t = Z.shape[1]
+    return _dst2(Z.reshape(N, N, t)).reshape(N * N, t)
+
+
+def laplace2d_expsum_factor(N: int, C: np.ndarray, shift: float = 0.0, rel: float = 1e-14) -> np.ndarray:
+    """Y^ in the sine-transform eigenbasis with X^ ~= Y^ Y^^T, X^ = S X S the
+    exact solution in that basis: -1/(l_i + l_j) = int_0^inf exp((l_i + l_j) t) dt
+    replaced by the exponential sum of ``exp_sum_nodes``, so that
+    Y^ = [sqrt(w_k) exp(Lambda t_k) C^] (n x s*K, uncompressed) with entrywise
+    relative error ~rel in X^, hence ||X - S Y^ Y^^T S||_F <= ~rel ||X||_F.
+    Krylov-free."""
     n, s = C.shape
     lam = laplace2d_eigs(N, shift)                  # all negative
     a = -2.0 * lam.max()
     b = -2.0 * lam.min()
     t, w = exp_sum_nodes(a, b, rel)
-    Ch = _dst2(C.reshape(N, N, s)).reshape(n, s)
-    cols = []
-    for tk, wk in zip(t, w):
-        cols.append(np.sqrt(wk) * np.exp(lam * tk)[:, None] * Ch)
-    Zh = np.concatenate(cols, axis=1)               # in the eigenbasis
+    Ch = dst2_columns(C, N)
+    return np.concatenate([np.sqrt(wk) * np.exp(lam * tk)[:, None] * Ch for tk, wk in zip(t, w)], axis=1)
+
+
+def lyap_laplace2d_lowrank(N: int, C: np.ndarray, shift: float = 0.0,
+                           rel: float = 1e-14, compress: float = 1e-15) -> np.ndarray:
+    """Low-rank factor Z_ref with X ~= Z_ref Z_ref^T for the 5-point Laplacian,
+    Krylov-free: the exponential-sum factor of ``laplace2d_expsum_factor``
+    (exp(A t) C applied exactly with the 2-D sine transform), its columns
+    compressed by a rank-revealing QR/SVD step at relative level ``compress``
+    and transformed back to grid coordinates."""
+    n, s = C.shape
+    Zh = laplace2d_expsum_factor(N, C, shift, rel)
     # compress: Zh = Q R, SVD of R
     Q, R = np.linalg.qr(Zh)
     U, sv, _ = np.linalg.svd(R)
     keep = sv > compress * sv[0]
     Zh = Q @ (U[:, keep] * sv[keep])
-    r = Zh.shape[1]
-    return _dst2(Zh.reshape(N, N, r)).reshape(n, r)
+    return dst2_columns(Zh, N)

@@ -26,6 +26,7 @@ OP_CSR, OP_STENCIL5, OP_STENCIL7 = 0, 1, 2
 STORE_F64, STORE_F32 = 0, 1
 METHOD_STD, METHOD_EXT = 0, 1
 PC_NONE, PC_JACOBI, PC_IC0, PC_LEARNED = 0, 1, 2, 3
+K_COUNT = 16   # LYAP_K_COUNT: per-kind arrays of the results
 
 ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_size_t, ct.c_void_p)
 FREE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p)
@@ -57,8 +58,8 @@ class LyapResult(ct.Structure):
                 ("n_checks", ct.c_int32), ("T_band", ct.POINTER(ct.c_double)),
                 ("gamma", ct.POINTER(ct.c_double)), ("tau", ct.POINTER(ct.c_double)),
                 ("bytes_pass1", ct.c_int64), ("bytes_spmm", ct.c_int64), ("ms_spmm", ct.c_double),
-                ("owns_Z", ct.c_int32), ("kern_ms", ct.c_double * 12), ("kern_n", ct.c_int32 * 12),
-                ("kern_bytes", ct.c_double * 12)]
+                ("owns_Z", ct.c_int32), ("kern_ms", ct.c_double * K_COUNT), ("kern_n", ct.c_int32 * K_COUNT),
+                ("kern_bytes", ct.c_double * K_COUNT)]
 
 
 class SylvResult(ct.Structure):
@@ -71,7 +72,7 @@ class SylvResult(ct.Structure):
                 ("T_band", ct.POINTER(ct.c_double)), ("J_band", ct.POINTER(ct.c_double)),
                 ("gamma1", ct.POINTER(ct.c_double)), ("gamma2", ct.POINTER(ct.c_double)),
                 ("tau", ct.POINTER(ct.c_double)), ("iota", ct.POINTER(ct.c_double)),
-                ("kern_ms", ct.c_double * 12), ("kern_n", ct.c_int32 * 12), ("kern_bytes", ct.c_double * 12)]
+                ("kern_ms", ct.c_double * K_COUNT), ("kern_n", ct.c_int32 * K_COUNT), ("kern_bytes", ct.c_double * K_COUNT)]
 
 
 # exported symbols declared in include/lyap.h
@@ -258,7 +259,7 @@ TIME_KEYS = ["pass1", "checks", "final", "pass2", "inner", "train", "total", "to
 
 
 KERNEL_KINDS = ["spmm_gram", "upd_gram", "chol_gram", "chol_store", "replay", "zflush", "check", "final", "init",
-                "cg_dir", "cg_upd", "ext_orth"]
+                "cg_dir", "cg_upd", "ext_orth", "pcnet"]
 
 
 def make_opts(tol=1e-8, max_iter=5000, method=METHOD_STD, check_every=0, storage=STORE_F64, two_pass=True,

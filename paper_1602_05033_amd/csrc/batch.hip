@@ -540,7 +540,7 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
     if (p->status != LYAP_OK && (worst == LYAP_OK || p->status < 0)) worst = p->status;
   }
   // batch-level kernel times in the first result
-  for (int i = 0; i < 12; ++i) {
+  for (int i = 0; i < LYAP_K_COUNT; ++i) {
     out[0].kern_ms[i] = kt.ms[i];
     out[0].kern_n[i] = kt.n[i];
   }

@@ -580,7 +580,7 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
   out->times_ms[LYAP_T_PASS2] = z_ms;
   out->times_ms[LYAP_T_TOTAL] = ms_since(t_entry);
   out->times_ms[LYAP_T_TO_TOL] = t_to_tol;
-  for (int i = 0; i < 12; ++i) {
+  for (int i = 0; i < LYAP_K_COUNT; ++i) {
     out->kern_ms[i] = kt.ms[i];
     out->kern_n[i] = kt.n[i];
   }
@@ -589,6 +589,7 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
     // whole grid; IC(0): the condensed iteration on the black cells)
     out->kern_bytes[LYAP_K_CG_DIR] = cg.iter_bytes();
     out->kern_bytes[LYAP_K_CG_UPD] = cg.upd_bytes();
+    if (net) out->kern_bytes[LYAP_K_PCNET] = net->apply_bytes();
   }
   out->status = status;
   return status;
@@ -778,7 +779,7 @@ lyap_status sylv_ext_impl(const lyap_op* A, const lyap_op* B, const double* C1, 
   out->times_ms[LYAP_T_INNER] = sa.cg().stats().ms + sb.cg().stats().ms;
   out->times_ms[LYAP_T_TOTAL] = ms_since(t_entry);
   out->times_ms[LYAP_T_TO_TOL] = t_to_tol;
-  for (int i = 0; i < 12; ++i) {
+  for (int i = 0; i < LYAP_K_COUNT; ++i) {
     out->kern_ms[i] = kt.ms[i];
     out->kern_n[i] = kt.n[i];
   }

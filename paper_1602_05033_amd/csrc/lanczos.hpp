@@ -60,8 +60,8 @@ struct KernelTimer {
   std::vector<hipEvent_t> ev;
   std::vector<int> kind;
   size_t used = 0;
-  double ms[12] = {0};
-  int n[12] = {0};
+  double ms[LYAP_K_COUNT] = {0};
+  int n[LYAP_K_COUNT] = {0};
   void mark(int k) {
     if (!on) return;
     if (used == ev.size()) {

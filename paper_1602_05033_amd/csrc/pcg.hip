@@ -481,6 +481,7 @@ void InnerCG::solve_fcg(const double* B, double* X, KernelTimer* kt) {
                            log_.as<CgIter>(), it, state_.as<double>(), partB_.as<double>(), grid_,
                            partA_.as<double>(), flag_.as<int>(), n_);
         LYAP_LAUNCHED("fcg iteration");
+        if (kt) kt->mark(LYAP_K_PCNET);
         zparts = net_->apply(r_.as<double>(), z_.as<double>(), q_.as<double>(), partZ_.as<double>());
       }
       if (kt) kt->collect();

@@ -37,6 +37,13 @@ class PcNetGpu {
   // order); returns how many were written.
   int apply(const double* r, double* z, const double* q, double* part);
   int max_out_parts() const;
+  // Algorithmic figures of one apply() on the operator's grid (the fused
+  // four-kernel form): FP32 multiply-adds x 2, and HBM bytes (r, D^{-1}, the
+  // channel scalings and the activations in and out of each convolution).
+  double apply_flops() const { return 2.0 * 27.0 * (4.0 * C_ + 2.0 * C_ * C_) * n_; }
+  double apply_bytes() const {
+    return (double)n_ * ((8 + 4 + 4 + 4.0 * C_) + 2 * (8.0 * C_) + (4.0 * C_ + 8 + 8 + 4 + 4 + 8 + 8));
+  }
   // Loss of the pair (r, e) (eAe = e^T (-A) e) and its gradient into the
   // device FP64 buffer grad (param_count values); the loss is left on the
   // device (loss_dev) and returned when want_loss (host sync).

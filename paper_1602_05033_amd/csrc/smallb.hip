@@ -665,7 +665,7 @@ lyap_status smallb_impl(const lyap_op* A, const double* B, int n2, int64_t ldb, 
   out->times_ms[LYAP_T_PASS2] = p2_ms;
   out->times_ms[LYAP_T_TOTAL] = ms_since(t_entry);
   out->times_ms[LYAP_T_TO_TOL] = t_to_tol;
-  for (int i = 0; i < 12; ++i) {
+  for (int i = 0; i < LYAP_K_COUNT; ++i) {
     out->kern_ms[i] = kt.ms[i];
     out->kern_n[i] = kt.n[i];
   }

@@ -468,7 +468,7 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   const double coef = side.op().coef_bytes_per_row();
   out->bytes_pass1 = (int64_t)((double)m * n * (21.0 * S * b + coef));
   out->bytes_spmm = (int64_t)((double)m * n * (2.0 * S * b + coef));
-  for (int i = 0; i < 12; ++i) {
+  for (int i = 0; i < LYAP_K_COUNT; ++i) {
     out->kern_ms[i] = kt.ms[i];
     out->kern_n[i] = kt.n[i];
   }

@@ -614,7 +614,7 @@ lyap_status sylv_impl(const lyap_op* A, const lyap_op* B, const double* C1, int6
   out->times_ms[LYAP_T_PASS2] = p2_ms;
   out->times_ms[LYAP_T_TOTAL] = ms_since(t_entry);
   out->times_ms[LYAP_T_TO_TOL] = t_to_tol;
-  for (int i = 0; i < 12; ++i) {
+  for (int i = 0; i < LYAP_K_COUNT; ++i) {
     out->kern_ms[i] = kt.ms[i];
     out->kern_n[i] = kt.n[i];
   }
@@ -622,7 +622,7 @@ lyap_status sylv_impl(const lyap_op* A, const lyap_op* B, const double* C1, int6
   double kb1[12] = {0}, kb2[12] = {0};
   fill_kernel_bytes<T>(n1, S, sa.op().coef_bytes_per_row(), kt, zbytes, kb1);
   fill_kernel_bytes<T>(n2, S, sb.op().coef_bytes_per_row(), kt, zbytes, kb2);
-  for (int i = 0; i < 12; ++i) out->kern_bytes[i] = 0.5 * (kb1[i] + kb2[i]);
+  for (int i = 0; i < LYAP_K_COUNT; ++i) out->kern_bytes[i] = 0.5 * (kb1[i] + kb2[i]);
   out->kern_bytes[LYAP_K_ZFLUSH] = kb1[LYAP_K_ZFLUSH];
   out->status = status;
   return status;
