@@ -90,6 +90,32 @@ def test_exp_sum_lowrank_matches_dense():
     assert np.linalg.norm(Z @ Z.T - X) / np.linalg.norm(X) < 1e-11
 
 
+def test_expsum_factor_in_eigenbasis_and_qr_error_route():
+    """The uncompressed exponential-sum factor Y^ in the sine-transform basis
+    reproduces the exact X (with a shift, too), and the error route the
+    full-size tests use -- Z^ = DST(Z), QR of [Z^, Y^] -- gives the same
+    ||Z Z^T - X||_F / ||X||_F as the dense difference."""
+    N = 14
+    for shift in (0.0, 3.5):
+        C = gaussian_C(N * N, 3, 6)
+        X = D.lyap_laplace2d_dense(N, C, shift) if shift == 0.0 else D.lyap_eig(
+            laplace2d(N, shift=shift).to_scipy().toarray(), C)
+        Yh = D.laplace2d_expsum_factor(N, C, shift)
+        S = D.dst2_columns(np.eye(N * N), N)              # the orthogonal transform itself
+        assert np.allclose(S @ S, np.eye(N * N), atol=1e-12)
+        assert np.linalg.norm(S @ Yh @ Yh.T @ S - X) <= 1e-12 * np.linalg.norm(X)
+        # a rank-truncated factor of X with a known error
+        w, U = np.linalg.eigh(X)
+        Z = U[:, -12:] * np.sqrt(w[-12:])
+        dense_err = np.linalg.norm(Z @ Z.T - X) / np.linalg.norm(X)
+        Zh = D.dst2_columns(Z, N)
+        t = Z.shape[1]
+        R = np.linalg.qr(np.concatenate([Zh, Yh], axis=1), mode="r")
+        sgn = np.concatenate([np.ones(t), -np.ones(Yh.shape[1])])
+        qr_err = np.linalg.norm((R * sgn[None, :]) @ R.T) / np.linalg.norm(Yh.T @ Yh)
+        assert dense_err > 1e-6 and abs(qr_err - dense_err) <= 1e-9 * dense_err
+
+
 def test_sylvester_eig_residual():
     A = laplace2d(4).to_scipy().toarray()
     B = fv3d(2, 0.5, 1).to_scipy().toarray()
