@@ -200,7 +200,10 @@ typedef struct lyap_result {
  *
  *  A     operator (device arrays), symmetric negative definite.
  *  C     device, n x s column-major FP64, leading dimension ldc >= n.
- *  s     1 <= s <= 8 (standard) or 1 <= s <= 8 (extended, ell = 2s).
+ *  s     1 <= s <= 8 (standard, method STD); s = 1, 2 or 4 (extended,
+ *        method EXT, ell = 2s; other s give LYAP_E_UNSUPPORTED).
+ *        method EXT also needs FP64 storage and solves with A by the inner
+ *        CG of lyap_inner_solve (opts->inner_pc, inner_tol, inner_max_iter).
  *  opts  may be NULL (defaults).
  *  out   filled on return (also on error, with status and history so far).
  *

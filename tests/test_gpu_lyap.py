@@ -110,6 +110,28 @@ def test_ctri_parity(lib, N, s, m):
     assert abs(res - ref.res) / ref.res < 1e-7 or abs(res - ref.res) / beta2 < 1e-14
 
 
+@pytest.mark.parametrize("case", [0, 1])
+def test_ctri_parity_large(lib, case):
+    """Orders k = 6000 and 10000 (bandwidth 8), whose top divide-and-conquer
+    merge takes the LDS-staged and the global-memory secular kernels, against
+    the oracle's Algorithm 3 on the same seeded band (tests/golden/ctri_large.json,
+    written by tests/golden/make_ctri_large.py from oracle/ only)."""
+    import json
+    import os
+    from workloads import random_band_T
+    b = _b()
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "ctri_large.json")))["cases"][case]
+    band, gamma, tau = random_band_T(gold["k"], gold["ell"], gold["seed"])
+    print(f"k={gold['k']}", flush=True)
+    res, lam = b.ctri(band, gamma, tau)
+    ref_lam = np.array(gold["lam"])
+    scale = np.max(np.abs(ref_lam))
+    assert np.max(np.abs(lam[gold["lam_idx"]] - ref_lam)) < 1e-12 * scale
+    assert np.all(np.diff(lam) >= 0.0)
+    beta2 = float(np.sum(gamma * gamma))
+    assert abs(res - gold["res"]) / gold["res"] < 1e-6 or abs(res - gold["res"]) / beta2 < 1e-14, (res, gold["res"])
+
+
 def test_band_eigen_with_ghost_clusters(lib):
     """Lanczos run far past convergence: T has ghost copies of converged Ritz
     values (relative gaps ~1e-13); all eigenvalues must still be found."""

@@ -270,6 +270,62 @@ def test_truncation_error_bound():
         assert np.linalg.norm(Y - M @ M.T) <= 1.01 * eps * np.linalg.norm(Y) + 1e-15 * np.linalg.norm(Y)
 
 
+def _scaled_runs(A, C, monkey=None):
+    """(t, m, Z) of the oracle's Algorithm 1 for C scaled by 1e-3, 1, 1e3 and
+    for A scaled by 10, 100 (optionally with a planted truncation threshold)."""
+    import oracle.krylov as KK
+    orig = KK.trunc_eps
+    if monkey is not None:
+        KK.trunc_eps = monkey
+    try:
+        out = {}
+        for c in (1e-3, 1.0, 1e3):
+            r = KK.lyap_std(A, c * C, tol=1e-8, check_every=1)
+            out[("C", c)] = (r.t, r.m, r.Z / c)
+        for a in (10.0, 100.0):
+            r = KK.lyap_std(a * A, C, tol=1e-8, check_every=1)
+            out[("A", a)] = (r.t, r.m, r.Z * np.sqrt(a))
+        return out
+    finally:
+        KK.trunc_eps = orig
+
+
+def test_truncation_threshold_scales_with_the_solution():
+    """Pin of the truncation threshold eps = min(1e-12, 0.05 tol / nu) beta^2
+    from both sides: X scales as c^2 when C -> c C and as 1/a when A -> a A,
+    while the relative residual and the Krylov space do not change, so a
+    threshold that scales like the solution leaves the kept rank t and the
+    scaled factor unchanged.  A threshold without beta^2, or with nu in the
+    numerator, changes t (planted); and dropping the tail moves the explicit
+    residual by at most 0.1 tol beta^2 (its bound 2 nu eps)."""
+    op = laplace2d(24)
+    A = op.to_scipy()
+    C = gaussian_C(op.n, 2, 3)
+    runs = _scaled_runs(A, C)
+    t0, m0, Z0 = runs[("C", 1.0)]
+    for key, (t, m, Z) in runs.items():
+        assert (t, m) == (t0, m0), key
+        assert K.factor_error(Z, Z0) <= 1e-9, key
+    bad_beta = lambda lam, tau, tol, beta: min(1e-12, 0.05 * tol / float(np.max(np.abs(lam)) + np.linalg.norm(tau)))
+    bad_nu = lambda lam, tau, tol, beta: min(1e-12, 0.05 * tol * float(np.max(np.abs(lam)) + np.linalg.norm(tau)) * 1e-8) * beta * beta
+    for bad in (bad_beta, bad_nu):
+        rb = _scaled_runs(A, C, bad)
+        assert len({v[0] for v in rb.values()}) > 1
+    # the truncation moves the explicit residual by at most 0.1 tol beta^2
+    r = K.lyap_std(A, C, tol=1e-8, check_every=1, two_pass=False)
+    beta2 = r.beta ** 2
+    import oracle.krylov as KK
+    orig = KK.trunc_eps
+    KK.trunc_eps = lambda lam, tau, tol, beta: 0.0
+    try:
+        full = KK.lyap_std(A, C, tol=1e-8, check_every=1, two_pass=False)
+    finally:
+        KK.trunc_eps = orig
+    assert full.t > r.t
+    d = abs(K.explicit_residual(A, r.Z, C) - K.explicit_residual(A, full.Z, C)) / beta2
+    assert d <= 0.1 * 1e-8, d
+
+
 @pytest.mark.parametrize("s", [1, 4])
 def test_c1_end_to_end_against_exact_solution(s):
     """Config: 32x32 Laplacian (n=1024), Gaussian C, tol 1e-8, check every step."""

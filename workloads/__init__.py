@@ -14,4 +14,5 @@ from .problems import (  # noqa: F401
     gaussian_C,
     uniform_C,
     batch_c5,
+    random_band_T,
 )

@@ -268,6 +268,29 @@ def fe_p1_2d(N: int):
 
 
 # ----------------------------------------------------------- right-hand sides
+def random_band_T(k: int, ell: int, seed: int, delta: float = 1e-4):
+    """A symmetric negative definite banded matrix of the shape of the
+    projected matrix T_m (bandwidth ell, order k), for exercising the residual
+    formula at sizes a short Krylov run does not reach: every band entry off
+    the diagonal is 1 and the diagonal is -(2 ell + delta (1 + u)), u uniform
+    in (0, 1) -- a Toeplitz symbol in [-(4 ell + delta), -delta] (so the
+    eigenvalues range over [-(4 ell + 2 delta), -delta] like a stiff
+    operator's Ritz values, and the eigenvectors spread over all rows) with
+    the diagonal jitter keeping the eigenvalues distinct.  Returns
+    (band, gamma, tau): band[c, d] = T[c + d, c] (k x (ell+1)), gamma ell x ell
+    upper triangular with diagonal in (1, 2), tau ell x ell, drawn from
+    ``numpy.random.default_rng([seed])`` and ``default_rng([seed, 1])``."""
+    rng = np.random.default_rng([seed])
+    band = np.zeros((k, ell + 1))
+    band[:, 0] = -(2.0 * ell + delta) - delta * rng.random(k)
+    for d in range(1, ell + 1):
+        band[:k - d, d] = 1.0
+    r2 = np.random.default_rng([seed, 1])
+    gamma = np.triu(r2.uniform(-1.0, 1.0, (ell, ell)), 1) + np.diag(1.0 + r2.random(ell))
+    tau = r2.uniform(-1.0, 1.0, (ell, ell))
+    return band, gamma, tau
+
+
 def gaussian_C(n: int, s: int, seed: int) -> np.ndarray:
     """n x s standard Gaussian, column c from ``default_rng([seed, c])`` so that
     the s=1 matrix is a prefix of any wider one.  Fortran (column-major) order."""
