@@ -22,6 +22,14 @@ iterate): energy-norm loss  L = (M r - e)^T (-A) (M r - e) / e^T (-A) e, Adam.
 
 Flexible CG (FCG(1)): q = (-A) p; alpha = p.r / p.q; x += alpha p;
 r -= alpha q; z = M(r); beta = -(z.q) / (p.q); p = z + beta p.
+
+The same network also corrects the red-black IC(0) preconditioner: the
+inner solve is then run on the black Schur complement Sigma (oracle.pcg), and
+M = diag(Sigma)^{-1} + s K^T K s acts on the compact array of the black cells
+(``condensed_grid``: nz x ny x hxp, compact column i // 2 of each grid line,
+padding slots held at zero), so that zero weights give IC(0) itself; pairs
+are harvested from the condensed IC(0) CG (``harvest_condensed``) and the
+loss uses Sigma in place of -A.
 """
 from __future__ import annotations
 
@@ -258,3 +266,42 @@ def fcg(A, b: np.ndarray, precond, eta: float = 1e-12, max_iter: int = 10000):
         beta = -float(z @ q) / pq
         p = z + beta * p
     return x, it, float(np.linalg.norm(b - A @ x)) / bn
+
+
+# ------------------------------------------------------------ on the Schur complement
+def condensed_grid(sysm) -> Grid:
+    """The network's grid for the black Schur complement of a red-black split
+    (``oracle.pcg.rb_system``): the compact array of the black cells, with
+    D = diag(Sigma) at the cells and dinv = s = f = 0 at the padding slots."""
+    nsl = int(np.prod(sysm.shape))
+    dinv = np.zeros(nsl)
+    dinv[sysm.slot] = 1.0 / sysm.S
+    f = np.zeros(nsl)
+    ld = np.log(sysm.S)
+    f[sysm.slot] = ld - ld.mean()
+    return Grid(sysm.shape, dinv, np.sqrt(dinv).reshape(sysm.shape), f.reshape(sysm.shape))
+
+
+def condensed_operator(sysm):
+    """-Sigma on the compact slots (zero rows and columns at the padding), the
+    "A" that ``loss_and_grad`` takes for the condensed system."""
+    nsl = int(np.prod(sysm.shape))
+    nb = sysm.slot.shape[0]
+    P = sp.csr_matrix((np.ones(nb), (sysm.slot, np.arange(nb))), shape=(nsl, nb))
+    return (-(P @ sysm.Sigma @ P.T)).tocsr()
+
+
+def condensed_precond(net: PcNet, sysm, g: Grid):
+    """z = M r for a black-cell residual r."""
+    return lambda rb: sysm.extract(apply(net, g, sysm.embed(rb)))
+
+
+def harvest_condensed(sysm, b: np.ndarray, every: int, keep: int, eta: float = 1e-12):
+    """Pairs (r_i, e_i) in compact-slot layout from the condensed IC(0) CG of
+    A x = b: CG on Sigma x_b = rhs~ (rhs~ = the condensed -b) preconditioned by
+    diag(Sigma), snapshots every `every` iterations (``harvest_pairs`` on
+    -Sigma)."""
+    rt = sysm.condense(-b)
+    pairs, xb, it = harvest_pairs(-sysm.Sigma, -rt, every=every, keep=keep, eta=eta)
+    return [(sysm.embed(r), sysm.embed(e)) for r, e in pairs], it
+

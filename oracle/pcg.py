@@ -179,26 +179,56 @@ def pcg_block(A, B: np.ndarray, **kw):
     return X, res
 
 
-def schur_rb_cg(A, b: np.ndarray, grid, eta: float = 1e-12, max_iter: int = 10000,
-                restarts: int = 3) -> PcgResult:
-    """Red-black IC(0)-PCG in its condensed form (see the module header):
-    with K = -A split into red / black cells, rhs = -b,
-      Sigma = D_b - E D_r^{-1} E^T,  rhs~ = rhs_b - E D_r^{-1} rhs_r,
-    CG on Sigma x_b = rhs~ with the preconditioner diag(Sigma), stopped when
-    ||rhs~ - Sigma x_b|| <= eta ||b||, then x_r = D_r^{-1} (rhs_r - E^T x_b).
-    The residual of the whole system is then zero on the red cells and
-    rhs~ - Sigma x_b on the black ones.  Accepted on the true relative residual
-    ||b - A x|| / ||b|| <= eta; otherwise the condensed CG is run again on the
-    residual (x += the correction), at most ``restarts`` times."""
+@dataclass
+class RbSystem:
+    """K = -A split into red and black cells (see the module header).  Black
+    vectors are in natural order of the black cells; ``slot`` gives each black
+    cell's place in the compact grid array (nz, ny, hxp): compact column
+    i // 2 of grid line (j, l), hxp = ceil(nx / 2) rounded up to a multiple of
+    ``align`` (the slots past a line's last black cell are padding)."""
+    red: np.ndarray        # bool mask over the grid
+    blk: np.ndarray
+    dr: np.ndarray         # D_r
+    Erb: sp.csr_matrix     # red rows, black columns of K (E^T)
+    Ebr: sp.csr_matrix     # black rows, red columns of K (E)
+    Sigma: sp.csr_matrix   # D_b - E D_r^{-1} E^T
+    S: np.ndarray          # diag(Sigma)
+    shape: tuple           # compact grid (nz, ny, hxp)
+    slot: np.ndarray       # compact slot of each black cell
+
+    def condense(self, res: np.ndarray) -> np.ndarray:
+        """rhs~ = res_b - E D_r^{-1} res_r."""
+        return res[self.blk] - self.Ebr @ (res[self.red] / self.dr)
+
+    def expand(self, res: np.ndarray, xb: np.ndarray) -> np.ndarray:
+        """The whole-grid correction: xb on the black cells and
+        D_r^{-1} (res_r - E^T xb) on the red ones."""
+        dx = np.empty(self.red.shape[0])
+        dx[self.blk] = xb
+        dx[self.red] = (res[self.red] - self.Erb @ xb) / self.dr
+        return dx
+
+    def embed(self, vb: np.ndarray) -> np.ndarray:
+        """Black vector -> compact grid array (zeros at padding), flattened."""
+        out = np.zeros(int(np.prod(self.shape)))
+        out[self.slot] = vb
+        return out
+
+    def extract(self, a: np.ndarray) -> np.ndarray:
+        return np.asarray(a).reshape(-1)[self.slot]
+
+
+def rb_system(A, grid, align: int = 4) -> RbSystem:
     K = -sp.csr_matrix(A)
-    idx = np.arange(K.shape[0])
+    n = K.shape[0]
+    idx = np.arange(n)
     nx, ny, nz = grid
     i, j, l = idx % nx, (idx // nx) % ny, idx // (nx * ny)
     red = (i + j + l) % 2 == 0
     blk = ~red
     Krr = K[red][:, red]
-    Erb = K[red][:, blk]          # E^T: red rows, black columns
-    Ebr = K[blk][:, red]          # E
+    Erb = K[red][:, blk].tocsr()
+    Ebr = K[blk][:, red].tocsr()
     Kbb = K[blk][:, blk]
     dr = Krr.diagonal()
     if not np.all(dr > 0.0):
@@ -207,6 +237,31 @@ def schur_rb_cg(A, b: np.ndarray, grid, eta: float = 1e-12, max_iter: int = 1000
     S = Sigma.diagonal()
     if not np.all(S > 0.0):
         raise np.linalg.LinAlgError("IC(0) pivot is not positive")
+    hx = (nx + 1) // 2
+    hxp = (hx + align - 1) // align * align
+    slot = ((j + ny * l) * hxp + i // 2)[blk]
+    return RbSystem(red, blk, dr, Erb, Ebr, Sigma, S, (nz, ny, hxp), slot)
+
+
+def schur_rb_cg(A, b: np.ndarray, grid, eta: float = 1e-12, max_iter: int = 10000,
+                restarts: int = 3, precond=None, system: Optional[RbSystem] = None) -> PcgResult:
+    """Red-black IC(0)-PCG in its condensed form (see the module header):
+    with K = -A split into red / black cells, rhs = -b,
+      Sigma = D_b - E D_r^{-1} E^T,  rhs~ = rhs_b - E D_r^{-1} rhs_r,
+    CG on Sigma x_b = rhs~ with the preconditioner diag(Sigma), stopped when
+    ||rhs~ - Sigma x_b|| <= eta ||b||, then x_r = D_r^{-1} (rhs_r - E^T x_b).
+    The residual of the whole system is then zero on the red cells and
+    rhs~ - Sigma x_b on the black ones.  Accepted on the true relative residual
+    ||b - A x|| / ||b|| <= eta; otherwise the condensed CG is run again on the
+    residual (x += the correction), at most ``restarts`` times.
+
+    ``precond`` (a function of the black residual) replaces diag(Sigma)^{-1};
+    the iteration is then flexible CG (FCG(1): beta = -(z.q) / (p.q)), which
+    with a fixed symmetric positive definite preconditioner gives the same
+    iterates as PCG."""
+    sysm = rb_system(A, grid) if system is None else system
+    K = -sp.csr_matrix(A)
+    Sigma, S = sysm.Sigma, sysm.S
     bn = float(np.linalg.norm(b))
     x = np.zeros_like(b)
     if bn == 0.0:
@@ -214,28 +269,41 @@ def schur_rb_cg(A, b: np.ndarray, grid, eta: float = 1e-12, max_iter: int = 1000
     total, nrest, hist = 0, 0, []
     res = -b - K @ x
     while True:
-        rt = res[blk] - Ebr @ (res[red] / dr)
-        xb = np.zeros(int(blk.sum()))
+        rt = sysm.condense(res)
+        xb = np.zeros(int(sysm.blk.sum()))
         r = rt.copy()
-        z = r / S
-        p = z.copy()
-        rho = float(r @ z)
-        while total < max_iter and float(np.linalg.norm(r)) > eta * bn:
-            q = Sigma @ p
-            alpha = rho / float(p @ q)
-            xb = xb + alpha * p
-            r = r - alpha * q
-            total += 1
-            if nrest == 0:
-                hist.append(float(np.linalg.norm(r)) / bn)
+        if precond is None:
             z = r / S
-            rho_new = float(r @ z)
-            p = z + (rho_new / rho) * p
-            rho = rho_new
-        dx = np.empty_like(b)
-        dx[blk] = xb
-        dx[red] = (res[red] - Erb @ xb) / dr
-        x = x + dx
+            p = z.copy()
+            rho = float(r @ z)
+            while total < max_iter and float(np.linalg.norm(r)) > eta * bn:
+                q = Sigma @ p
+                alpha = rho / float(p @ q)
+                xb = xb + alpha * p
+                r = r - alpha * q
+                total += 1
+                if nrest == 0:
+                    hist.append(float(np.linalg.norm(r)) / bn)
+                z = r / S
+                rho_new = float(r @ z)
+                p = z + (rho_new / rho) * p
+                rho = rho_new
+        else:
+            z = precond(r)
+            p = z.copy()
+            while total < max_iter and float(np.linalg.norm(r)) > eta * bn:
+                q = Sigma @ p
+                pq = float(p @ q)
+                alpha = float(p @ r) / pq
+                xb = xb + alpha * p
+                r = r - alpha * q
+                total += 1
+                if nrest == 0:
+                    hist.append(float(np.linalg.norm(r)) / bn)
+                z = precond(r)
+                beta = -float(z @ q) / pq
+                p = z + beta * p
+        x = x + sysm.expand(res, xb)
         res = -b - K @ x
         true = float(np.linalg.norm(b - A @ x)) / bn
         if true <= eta:
