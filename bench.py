@@ -39,9 +39,15 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-# learned preconditioner, C = 4 channels: two 3x3x3 convolutions (2 -> 4 -> 4)
-# and their adjoints per application, 2 flops per multiply-add
-PCNET_FLOPS_PER_POINT = 2 * 27 * (4 * 4 + 2 * 4 * 4)
+# learned preconditioner, C = 2 channels: two 3x3x3 convolutions (2 -> 2 -> 2)
+# and their adjoints per application, 2 flops per multiply-add, on the compact
+# grid of the black cells (ceil(nx / 2) rounded up to a multiple of 4, x ny x nz)
+PCNET_C = 2
+PCNET_FLOPS_PER_POINT = 2 * 27 * (4 * PCNET_C + 2 * PCNET_C * PCNET_C)
+
+
+def pcnet_points(nx, ny, nz):
+    return ((nx + 1) // 2 + 3) // 4 * 4 * ny * nz
 
 # HBM bytes per launch from rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE,
 # KiB per dispatch, median over the dispatches of one `bench.py --steps 1
@@ -718,7 +724,7 @@ def main_c3(args):
     dom = max(agg, key=lambda k: agg[k]["ms"])
     avg_ms = agg[dom]["ms"] / agg[dom]["n"]
     if dom == "pcnet":
-        flops = PCNET_FLOPS_PER_POINT * op.n
+        flops = PCNET_FLOPS_PER_POINT * pcnet_points(op.nx, op.ny, op.nz)
         tf = flops / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": "pcnet (k_pc_conv4_r, k_pc_conv4 x2, k_pc_conv4_out)",
                 "achieved": round(tf, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -768,7 +774,9 @@ def main_c3(args):
                                f"lognormal k sigma=1 (seed 3), C n x 1 Gaussian (seed 3), tol 1e-8, inner CG to a "
                                f"true residual of 1e-12: learned preconditioner (value) vs IC(0) red-black (plain)",
                    "n": op.n, "s": 1, "tol": 1e-8, "check": "adaptive", "inner_tol": 1e-12,
-                   "network": "M = D^-1 + S K^T K S, K = two 3x3x3 convolutions 2 -> 4 -> 4 channels, FP32"},
+                   "network": "M = diag(Sigma)^-1 + S K^T K S on the compact grid of the black cells (Sigma the "
+                              "Schur complement of the red-black split, zero weights = IC(0)), K = two 3x3x3 "
+                              "convolutions 2 -> 2 -> 2 channels, FP32"},
         "result": {"learned": res["learned"], "plain_ic0": res["ic0"], "jacobi": res["jacobi"],
                    "plain_over_learned": round(legs["ic0"]["sec"] / head["sec"], 4)},
         "roofline": roof,

@@ -424,15 +424,14 @@ lyap_status lyap_solve_batched(int32_t count, const lyap_op* A, const double* co
                                const int64_t* ldc, const lyap_opts* opts, int32_t tune, lyap_result* out);
 
 /* ------------------------------------------------------------------ learned preconditioner
- * Inner solves of the extended Krylov method with opts->inner_pc =
- * LYAP_PC_LEARNED (stencil operators, s = 1): the first inner solve runs
- * Jacobi-PCG and keeps its residual / iterate every 32 iterations (at most 16);
- * the network below is then trained for 200 Adam steps (learning rate 2e-3) on
- * those pairs, and later solves run flexible CG with z = M(r):
+ * The network, on an operator's whole grid (the entry points below; the
+ * solver's inner solves use it on IC(0)'s Schur complement, see the next
+ * block): trained for 200 Adam steps (learning rate 2e-3) on pairs harvested
+ * from a CG solve, then applied in flexible CG with z = M(r):
  *   M r = D^{-1} r + s (K^T K)(s r),  s = sqrt(D^{-1}),  D = diag(-A),
  *   K(u) = conv2(conv1([u, f u])),  f = log(-diag A) - mean,
- * two 3x3x3 convolutions (2 -> C -> C channels, C = 4, zero padding, no bias)
- * on the operator's grid, FP32 weights (SplitMix64 seed 0x5eed, uniform in
+ * two 3x3x3 convolutions (2 -> C -> C channels, C = 2, 4 or 8, zero padding,
+ * no bias) on the operator's grid, FP32 weights (SplitMix64 seed 0x5eed, uniform in
  * [-0.05, 0.05)).  M is symmetric positive definite for any weights.  The loss
  * of a pair (r, e), (-A) e = r, is (M r - e)^T (-A) (M r - e) / e^T (-A) e.
  * The entry points below expose the pieces for testing; W holds C*2*27 + C*C*27
@@ -470,6 +469,39 @@ lyap_status lyap_pcnet_train(const lyap_op* A, int32_t C, float* W, int32_t npai
 /* X = A^{-1} B (one column) by flexible CG with M; certified like lyap_inner_solve. */
 lyap_status lyap_pcnet_fcg(const lyap_op* A, int32_t C, const float* W, const double* B, double* X, double eta,
                            int32_t max_iter, int64_t* iters, double* relres, void* stream);
+
+/* ------------------------------------------------------------------ learned correction of IC(0)
+ * The inner solves of lyap_solve / sylv_solve with inner_pc = LYAP_PC_LEARNED
+ * use the same network as a correction of red-black IC(0) (stencil operators,
+ * one column): the solve runs on the black Schur complement
+ * Sigma = D_b - E D_r^{-1} E^T of the red-black split (see lyap_inner_solve)
+ * with
+ *   M r = D_S^{-1} r + s K^T K (s r),  D_S = diag(Sigma),  s = sqrt(D_S^{-1}),
+ *   f = log D_S - mean,
+ * the network acting on the compact grid of the black cells: an array of
+ * hx x ny x nz points, hx = ceil(nx / 2) rounded up to a multiple of 4, the
+ * black cell (i, j, l) at point (i / 2, j, l), the remaining points held at
+ * zero (D_S^{-1} = s = 0 there).  Zero weights give IC(0) itself.  Training
+ * pairs (r_i, e_i), Sigma e_i = r_i, come from the first inner solve (the
+ * condensed IC(0) CG, every 16 iterations, at most 16); the loss is
+ * (M r - e)^T Sigma (M r - e) / e^T Sigma e; 200 Adam steps as above; later
+ * solves run flexible CG on Sigma with M, then the red cells are solved for,
+ * and the whole-grid true residual certifies each solve.  C = 2 in the solver.
+ * The two entry points below expose this for testing (W as above, b, B, X
+ * device FP64 of length n):
+ *  lyap_pcnet_schur_train  solves A x = b by the condensed IC(0) CG to a true
+ *      relative residual 1e-12, keeping (r_i, e_i) every `every` iterations
+ *      (at most `keep`), then takes `steps` Adam steps over the pairs with
+ *      e^T Sigma e > 0, in order; W in/out (host), losses (host, optional) the
+ *      loss before each step, *npairs the pairs used.
+ *  lyap_pcnet_schur_fcg    X = A^{-1} B by flexible CG on Sigma with M and W,
+ *      certified like lyap_inner_solve.
+ * E_UNSUPPORTED for a CSR operator. */
+lyap_status lyap_pcnet_schur_train(const lyap_op* A, int32_t C, float* W, const double* b, int32_t every,
+                                   int32_t keep, int32_t steps, double lr, double* losses, int32_t* npairs,
+                                   void* stream);
+lyap_status lyap_pcnet_schur_fcg(const lyap_op* A, int32_t C, const float* W, const double* B, double* X,
+                                 double eta, int32_t max_iter, int64_t* iters, double* relres, void* stream);
 
 #ifdef __cplusplus
 }

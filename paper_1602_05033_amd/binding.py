@@ -80,7 +80,7 @@ EXPORTS = ["lyap_opts_default", "lyap_solve", "sylv_solve", "lyap_result_free", 
            "lyap_last_error", "lyap_op_apply", "lyap_op_apply_timed", "lyap_ctri", "lyap_inner_solve",
            "lyap_solve_batched", "lyap_pcnet_init", "lyap_pcnet_apply", "lyap_pcnet_grad", "lyap_pcnet_train",
            "lyap_pcnet_fcg", "sylv_solve_small_b", "lyap_sym_eig", "lyap_solve_gen",
-           "lyap_pcnet_apply_noalloc"]
+           "lyap_pcnet_apply_noalloc", "lyap_pcnet_schur_train", "lyap_pcnet_schur_fcg"]
 
 
 class LyapError(RuntimeError):
@@ -157,6 +157,14 @@ def load(path: str = LIB_PATH):
     lib.lyap_pcnet_fcg.argtypes = [ct.POINTER(LyapOp), ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_double,
                                    ct.c_int32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double), ct.c_void_p]
     lib.lyap_pcnet_fcg.restype = ct.c_int
+    lib.lyap_pcnet_schur_train.argtypes = [ct.POINTER(LyapOp), ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_int32,
+                                           ct.c_int32, ct.c_int32, ct.c_double, ct.c_void_p,
+                                           ct.POINTER(ct.c_int32), ct.c_void_p]
+    lib.lyap_pcnet_schur_train.restype = ct.c_int
+    lib.lyap_pcnet_schur_fcg.argtypes = [ct.POINTER(LyapOp), ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                         ct.c_double, ct.c_int32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double),
+                                         ct.c_void_p]
+    lib.lyap_pcnet_schur_fcg.restype = ct.c_int
     _LIB = lib
     return lib
 
@@ -652,4 +660,31 @@ def pcnet_fcg(dop: DeviceOp, C: int, W: np.ndarray, B, eta: float = 1e-12, max_i
     st = lib.lyap_pcnet_fcg(ct.byref(dop.c), C, Wf.ctypes.data_as(ct.c_void_p), ct.c_void_p(B.data_ptr()),
                             ct.c_void_p(X.data_ptr()), eta, max_iter, ct.byref(it), ct.byref(rel),
                             ct.c_void_p(_stream(B.device)))
+    return X, it.value, rel.value, st
+
+
+def pcnet_schur_train(dop: DeviceOp, C: int, W: np.ndarray, b, every: int, keep: int, steps: int, lr: float):
+    """Harvest pairs from the condensed IC(0) solve of A x = b and train the
+    network on the black Schur complement; returns (W, losses, pairs used)."""
+    lib = load()
+    Wf = np.array(W, dtype=np.float32)
+    losses = np.zeros(max(steps, 1))
+    npairs = ct.c_int32(0)
+    _check(lib.lyap_pcnet_schur_train(ct.byref(dop.c), C, Wf.ctypes.data_as(ct.c_void_p), ct.c_void_p(b.data_ptr()),
+                                      every, keep, steps, lr, losses.ctypes.data_as(ct.c_void_p), ct.byref(npairs),
+                                      ct.c_void_p(_stream(b.device))))
+    return Wf, losses[:steps], npairs.value
+
+
+def pcnet_schur_fcg(dop: DeviceOp, C: int, W: np.ndarray, B, eta: float = 1e-12, max_iter: int = 5000):
+    """X = A^{-1} B by flexible CG on IC(0)'s Schur complement with the network."""
+    import torch
+    lib = load()
+    Wf = np.ascontiguousarray(W, dtype=np.float32)
+    X = torch.empty_like(B)
+    it = ct.c_int64(0)
+    rel = ct.c_double(0.0)
+    st = lib.lyap_pcnet_schur_fcg(ct.byref(dop.c), C, Wf.ctypes.data_as(ct.c_void_p), ct.c_void_p(B.data_ptr()),
+                                  ct.c_void_p(X.data_ptr()), eta, max_iter, ct.byref(it), ct.byref(rel),
+                                  ct.c_void_p(_stream(B.device)))
     return X, it.value, rel.value, st

@@ -33,10 +33,10 @@ constexpr int kExtThreads = 256;
 
 // Learned inner preconditioner: width, SplitMix64 seed and scale of the
 // initial weights, harvest cadence and count, Adam steps and learning rate.
-constexpr int kPcC = 4;
+constexpr int kPcC = 2;
 constexpr uint64_t kPcSeed = 0x5eedULL;
 constexpr double kPcScale = 0.05;
-constexpr int kPcEvery = 32, kPcKeep = 16, kPcSteps = 200;
+constexpr int kPcEvery = 16, kPcKeep = 16, kPcSteps = 200;
 constexpr double kPcLr = 2e-3;
 
 // C (n x S column-major, leading dimension ldc) -> row-interleaved n x S.
@@ -421,7 +421,7 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
   std::unique_ptr<PcNetGpu> net;
   double train_ms = 0.0;
   if (o.inner_pc == LYAP_PC_LEARNED) {
-    net = std::make_unique<PcNetGpu>(side.op().dev, kPcC, st);
+    net = cg.make_schur_net(kPcC);
     std::vector<float> W(pcnet_param_count(kPcC));
     pcnet_init_weights(kPcC, kPcSeed, kPcScale, W.data());
     net->set_weights(W.data());
@@ -448,7 +448,7 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
     }
     LYAP_HIP(hipStreamSynchronize(st));
     train_ms = ms_since(t_tr);
-    cg.set_net(net.get());
+    cg.set_net_schur(net.get());
   }
   side.start_finish();
   out->beta = side.beta();

@@ -382,11 +382,20 @@ InnerCG::InnerCG(const OpDev<double>& op, int n, int S, int pc, double eta, int 
   LYAP_HIP(hipMemcpyAsync(hf, flag_.p, sizeof(hf), hipMemcpyDeviceToHost, st_));
   LYAP_HIP(hipStreamSynchronize(st_));
   LYAP_REQUIRE(hf[0] == 0, LYAP_E_INDEFINITE, "A has a diagonal entry >= 0: not negative definite");
-  if (pc_ == LYAP_PC_IC0) setup_rb();
+  if (pc_ == LYAP_PC_IC0 ||
+      (pc_ == LYAP_PC_LEARNED && S_ == 1 && (op_.kind == LYAP_OP_STENCIL5 || op_.kind == LYAP_OP_STENCIL7)))
+    setup_rb();
 }
 
 double InnerCG::iter_bytes() const {
-  if (pc_ == LYAP_PC_IC0) return rb_iter_bytes();
+  if (net_ && net_schur_) {
+    // the two sweeps of q = Sigma p: z, p_old in and p out at the black slots, D_r^{-1}
+    // and the faces, v out; then p, v, D_b, r in and q out with the faces again
+    const double half = (double)n_ / 2.0;
+    const double faces = op_.kind == LYAP_OP_STENCIL7 ? (op_.nz > 1 ? 3.0 : 2.0) * 8.0 * n_ : 0.0;
+    return half * 24.0 + half * 16.0 + half * 40.0 + 2.0 * faces;
+  }
+  if (pc_ == LYAP_PC_IC0 || rb_ready_) return rb_iter_bytes();
   double coef = 0.0;
   if (op_.kind == LYAP_OP_STENCIL7) coef = 4.0 * 8.0;
   // single-reduction CG: x, r, w, s, p and M^{-1} in; x, r, w, s, p out (+ coefficients)
@@ -432,7 +441,8 @@ static void cg_launch_true(const OpDev<double>& op, const double* B, const doubl
 }
 
 double InnerCG::upd_bytes() const {
-  if (pc_ == LYAP_PC_IC0) return rb_w_bytes();
+  if (net_ && net_schur_) return (double)n_ / 2.0 * 48.0;  // x, r, p, q in; x, r out (black slots)
+  if (pc_ == LYAP_PC_IC0 || (rb_ready_ && !net_)) return rb_w_bytes();
   // the flexible-CG update of the learned-preconditioner runs: x, r, p, q in; x, r out
   return (double)n_ * (6.0 * S_ * 8 + 8);
 }
@@ -526,8 +536,8 @@ void InnerCG::solve_fcg(const double* B, double* X, KernelTimer* kt) {
 }
 
 void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
-  if (net_) return solve_fcg(B, X, kt);
-  if (pc_ == LYAP_PC_IC0) return solve_rb(B, X, kt);
+  if (net_) return net_schur_ ? solve_rb_fcg(B, X, kt) : solve_fcg(B, X, kt);
+  if (rb_ready_) return solve_rb(B, X, kt);
   const auto t0 = Clock::now();
   const int S = S_;
   const double eta_rec = 0.5 * eta_;  // recursive target, so that the true residual passes

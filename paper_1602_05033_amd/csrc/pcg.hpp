@@ -4,6 +4,8 @@
 // true relative residual ||b - A x|| / ||b|| is at most eta.
 #pragma once
 
+#include <memory>
+
 #include "lanczos.hpp"
 #include "solver.hpp"
 
@@ -45,10 +47,22 @@ class InnerCG {
   // ... and of the second kernel (LYAP_K_CG_UPD) where an iteration has two
   // (IC(0): the Schur product sweep; the learned preconditioner's FCG update).
   double upd_bytes() const;
-  // Later solves use flexible CG with z = M(r) from the network.
-  void set_net(PcNetGpu* net) { net_ = net; }
-  // The next (Jacobi) solve keeps (r, x) every `every` iterations, at most
-  // `keep` times; after it, pair(i) gives r_i and e_i = x* - x_i ((-A) e_i = r_i).
+  // Later solves use flexible CG with z = M(r) from the network (on the
+  // operator's whole grid, K = -A).
+  void set_net(PcNetGpu* net) { net_ = net; net_schur_ = false; }
+  // Later solves use flexible CG on the black Schur complement of the
+  // red-black split (IC(0)'s condensed system) with z = M(r) from a network
+  // made by make_schur_net (LYAP_PC_LEARNED on a stencil operator, S = 1).
+  void set_net_schur(PcNetGpu* net) { net_ = net; net_schur_ = true; }
+  // A network on the compact grid of the black cells whose diagonal part is
+  // diag(Sigma)^{-1} (zero weights: IC(0) itself) and whose K is Sigma.
+  std::unique_ptr<PcNetGpu> make_schur_net(int C);
+  // y = Sigma x on the compact black slots (S = 1; IC(0) or LEARNED on a stencil).
+  void schur_apply(const double* x, double* y);
+  // The next solve keeps (r, x) every `every` iterations, at most `keep`
+  // times; after it, pair(i) gives r_i and e_i = x* - x_i (K e_i = r_i) --
+  // for the Jacobi iteration on the whole grid (K = -A), for IC(0) and
+  // LEARNED on a stencil in compact black-slot layout (K = Sigma).
   void harvest(int every, int keep) { harvest_every_ = every; harvest_keep_ = keep; }
   int pairs() const { return (int)hr_.size(); }
   const double* pair_r(int i) const { return hr_[i].as<double>(); }
@@ -58,6 +72,7 @@ class InnerCG {
   void solve_fcg(const double* B, double* X, KernelTimer* kt);
   void setup_rb();
   void solve_rb(const double* B, double* X, KernelTimer* kt);
+  void solve_rb_fcg(const double* B, double* X, KernelTimer* kt);
   template <bool K7, int S>
   void rb_solve_templ(const double* B, double* X, int restarts, int chunk, KernelTimer* kt);
   double rb_iter_bytes() const;
@@ -79,6 +94,7 @@ class InnerCG {
   // black slots and v = D_r^{-1} E^T u at the red slots
   DevBuf rb_rinv_, rb_db_, rb_sinv_, rb_x_, rb_p_, rb_r0_, rb_r1_, rb_w0_, rb_w1_, rb_s0_, rb_s1_, rb_u_, rb_v_;
   int rb_grid_ = 0;
+  bool rb_ready_ = false, net_schur_ = false;
   std::vector<DevBuf> hr_, hx_;
 };
 

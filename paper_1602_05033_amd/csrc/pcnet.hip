@@ -2,12 +2,12 @@
 // the energy-norm loss), Adam, and the component entry points used by the
 // tests.  See pcnet.hpp for the definition.
 //
-// Convolutions: the weights in LDS, neighbours read through the caches
-// (channel counts are small: 2 -> C -> C, C <= 8); four consecutive cells per
-// thread with vector loads when nx is a multiple of 4, else one per thread.  In
-// the preconditioner's application (nx a multiple of 4) the input channels are
-// formed inside the first convolution and the output z inside the last one,
-// so the network costs four kernels.  Weight
+// Convolutions of the application z = M r: four tiled kernels (8 x 8 x 4
+// output points per workgroup, input tile and halo staged in LDS), the input
+// channels formed inside the first and the output z inside the last.  The
+// training's convolutions keep their activations: the weights in LDS,
+// neighbours read through the caches, four consecutive cells per thread with
+// vector loads when nx is a multiple of 4, else one per thread.  Weight
 // gradients: 8 x 8 x 4 cell tiles with a one-cell halo staged in LDS, each
 // thread accumulating the three x taps of one (output, input, dz, dy) weight
 // group over the tile; per-tile partials are summed in FP64 in a fixed order
@@ -56,6 +56,63 @@ __global__ __launch_bounds__(kPcThreads) void k_pc_prep2(OpDev<double> op, int n
   const double mean = uniform_d(red[0]) / (double)n;
   for (int p = blockIdx.x * kPcThreads + threadIdx.x; p < n; p += gridDim.x * kPcThreads)
     f[p] = (float)(log(-op_diag<double>(op, p)) - mean);
+}
+
+// From a given diagonal part: s = sqrt(dinv) (FP32), partial sums of
+// log(1 / dinv) and of the count over the points with dinv > 0.
+__global__ __launch_bounds__(kPcThreads) void k_pc_prep_d1(const double* __restrict__ dinv, int n, float* s,
+                                                           double* part) {
+  __shared__ double red[2 * (kPcThreads / 64)];
+  double acc[2] = {0.0, 0.0};
+  for (int p = blockIdx.x * kPcThreads + threadIdx.x; p < n; p += gridDim.x * kPcThreads) {
+    const double d = dinv[p];
+    s[p] = (float)sqrt(d);
+    if (d > 0.0) {
+      acc[0] += -log(d);
+      acc[1] += 1.0;
+    }
+  }
+  write_partial<2, kPcThreads>(acc, red, part);
+}
+
+// f = log(1 / dinv) - mean over the points with dinv > 0, 0 elsewhere
+__global__ __launch_bounds__(kPcThreads) void k_pc_prep_d2(const double* __restrict__ dinv, int n, const double* part,
+                                                           int nparts, float* f) {
+  __shared__ double red[2 * (kPcThreads / 64)];
+  reduce_partials<2, kPcThreads>(part, nparts, red);
+  const double mean = uniform_d(red[0]) / uniform_d(red[1]);
+  for (int p = blockIdx.x * kPcThreads + threadIdx.x; p < n; p += gridDim.x * kPcThreads) {
+    const double d = dinv[p];
+    f[p] = d > 0.0 ? (float)(-log(d) - mean) : 0.0f;
+  }
+}
+
+// dd = z - e (the network's error for the pair)
+__global__ void k_pc_sub(const double* __restrict__ z, const double* __restrict__ e, int n, double* __restrict__ dd) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) dd[p] = z[p] - e[p];
+}
+
+// with Kd = K dd given: gw = s * 2 Kd / eAe (FP32), partial dd.Kd
+__global__ __launch_bounds__(kPcThreads) void k_pc_resid_k(const double* __restrict__ dd, const double* __restrict__ kd,
+                                                           const float* __restrict__ s, double eAe, int n,
+                                                           float* __restrict__ gw, double* part) {
+  __shared__ double red[kPcThreads / 64];
+  double acc[1] = {0.0};
+  for (int p = blockIdx.x * kPcThreads + threadIdx.x; p < n; p += gridDim.x * kPcThreads) {
+    acc[0] = fma(dd[p], kd[p], acc[0]);
+    gw[p] = (float)((double)s[p] * 2.0 * kd[p] / eAe);
+  }
+  write_partial<1, kPcThreads>(acc, red, part);
+}
+
+// partial x.y
+__global__ __launch_bounds__(kPcThreads) void k_pc_dot(const double* __restrict__ x, const double* __restrict__ y,
+                                                       int n, double* part) {
+  __shared__ double red[kPcThreads / 64];
+  double acc[1] = {0.0};
+  for (int p = blockIdx.x * kPcThreads + threadIdx.x; p < n; p += gridDim.x * kPcThreads) acc[0] = fma(x[p], y[p], acc[0]);
+  write_partial<1, kPcThreads>(acc, red, part);
 }
 
 // x0 = [s r, f s r]
@@ -225,184 +282,121 @@ __global__ __launch_bounds__(kPcThreads) void k_pc_conv4(const float* __restrict
   }
 }
 
-// The first convolution with its two input channels x0 = [u, f u], u = s r
-// (rounded to FP32), formed from r, s, f as they are read (k_pc_in_r and
-// k_pc_conv4<2, CO, false> in one pass; the same values and order).
-template <int CO>
-__global__ __launch_bounds__(kPcThreads) void k_pc_conv4_r(const double* __restrict__ r, const float* __restrict__ s,
-                                                           const float* __restrict__ f, const float* __restrict__ W,
-                                                           float* __restrict__ out, int nx, int ny, int nz) {
-  constexpr int CI = 2;
-  const int n = nx * ny * nz;
-  const int nq = n / 4;
-  const int lb = xcd_block(blockIdx.x, (nq + kPcThreads - 1) / kPcThreads);
+// ------------------------------------------------------------------ tiled application
+// The preconditioner's application z = M r as four tiled convolutions: one
+// output point per thread over an 8 x 8 x 4 tile, the input channels of the
+// tile and its one-point halo staged in LDS first (each input value is read
+// from memory once per tile instead of once per tap through the caches; the
+// channel counts are too small to keep a wave busy otherwise).  Tiles are
+// dealt XCD by XCD (neighbouring tiles share halo rows in one L2).
+//   MODE 0: FP32 channels in[c][n] -> out[o][n];
+//   MODE 1: the input channels x0 = [u, f u], u = s r rounded to FP32, formed
+//           from r, s, f while staging (the first convolution);
+//   MODE 2: the output of the last transposed convolution (two channels d)
+//           as z = dinv r + s (d0 + f d1) (FP64), with one partial z.q per tile.
+// TRANS = false: out[o][p] = sum_t sum_i W[o][i][t] in[i][p + t];
+// TRANS = true (the adjoint): out[i][p] = sum_t sum_o W[o][i][t] in[o][p - t].
+constexpr int kQX = 8, kQY = 8, kQZ = 4;
+constexpr int kQHX = kQX + 2, kQHY = kQY + 2, kQHZ = kQZ + 2;
+constexpr int kQH = kQHX * kQHY * kQHZ;
+
+template <int CI, int CO, bool TRANS, int MODE>
+__global__ __launch_bounds__(kPcThreads) void k_pc_tile(const float* __restrict__ in, const double* __restrict__ r,
+                                                        const float* __restrict__ s, const float* __restrict__ f,
+                                                        const double* __restrict__ dinv, const float* __restrict__ W,
+                                                        float* __restrict__ out, double* __restrict__ z,
+                                                        const double* __restrict__ q, double* part, int nx, int ny,
+                                                        int nz, int tx, int ty, int tz) {
+  static_assert(kQX * kQY * kQZ == kPcThreads, "one output point per thread");
+  constexpr int NIN = TRANS ? CO : CI;
+  constexpr int NOUT = TRANS ? CI : CO;
+  constexpr int SG = TRANS ? -1 : 1;
+  static_assert(MODE != 1 || NIN == 2, "the formed input has two channels");
+  static_assert(MODE != 2 || NOUT == 2, "the output is formed from two channels");
+  const int lb = xcd_block(blockIdx.x, tx * ty * tz);
   if (lb < 0) return;
   __shared__ float sW[CO * CI * 27];
+  __shared__ float sx[NIN * kQH];
+  __shared__ double red[kPcThreads / 64];
+  const int bx = lb % tx, by = (lb / tx) % ty, bz = lb / (tx * ty);
+  const int x0 = bx * kQX, y0 = by * kQY, z0 = bz * kQZ;
+  const int n = nx * ny * nz;
   for (int e = threadIdx.x; e < CO * CI * 27; e += kPcThreads) sW[e] = W[e];
+  // every thread loads its (at most three) halo-tile points before storing
+  // any, so that all loads are in flight together
+  constexpr int NST = (kQH + kPcThreads - 1) / kPcThreads;
+  float v0[NST], v1[NST][NIN > 1 ? NIN - 1 : 1];
+#pragma unroll
+  for (int k = 0; k < NST; ++k) {
+    const int h = threadIdx.x + k * kPcThreads;
+    const int hx = h % kQHX, hy = (h / kQHX) % kQHY, hz = h / (kQHX * kQHY);
+    const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+    const bool inside = h < kQH && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+    const int p = inside ? gx + nx * (gy + ny * gz) : 0;
+    if constexpr (MODE == 1) {
+      float u = 0.f, fu = 0.f;
+      if (inside) {
+        u = (float)((double)s[p] * r[p]);
+        fu = f[p] * u;
+      }
+      v0[k] = u;
+      v1[k][0] = fu;
+    } else {
+      v0[k] = inside ? in[p] : 0.f;
+#pragma unroll
+      for (int c = 1; c < NIN; ++c) v1[k][c - 1] = inside ? in[(size_t)c * n + p] : 0.f;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NST; ++k) {
+    const int h = threadIdx.x + k * kPcThreads;
+    if (h < kQH) {
+      sx[h] = v0[k];
+#pragma unroll
+      for (int c = 1; c < NIN; ++c) sx[c * kQH + h] = v1[k][c - 1];
+    }
+  }
   __syncthreads();
-  const int qd = lb * kPcThreads + threadIdx.x;
-  if (qd >= nq) return;
-  const int p0 = 4 * qd;
-  const int nxy = nx * ny;
-  const int z = p0 / nxy, y = (p0 / nx) % ny, x0 = p0 % nx;
-  float acc[CO][4];
+  const int lx = threadIdx.x % kQX, ly = (threadIdx.x / kQX) % kQY, lz = threadIdx.x / (kQX * kQY);
+  const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+  const bool own = gx < nx && gy < ny && gz < nz;
+  float acc[NOUT];
 #pragma unroll
-  for (int o = 0; o < CO; ++o)
+  for (int o = 0; o < NOUT; ++o) acc[o] = 0.f;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc[o][k] = 0.f;
+  for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int zz = z + dz;
-    if (zz < 0 || zz >= nz) continue;
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int yy = y + dy;
-      if (yy < 0 || yy >= ny) continue;
-      const size_t base = (size_t)zz * nxy + (size_t)yy * nx + x0;
-      double rv[6];
-      float sv[6], fv[6];
-      {
-        const double2 r01 = *reinterpret_cast<const double2*>(r + base);
-        const double2 r23 = *reinterpret_cast<const double2*>(r + base + 2);
-        const float4 s4 = *reinterpret_cast<const float4*>(s + base);
-        const float4 f4 = *reinterpret_cast<const float4*>(f + base);
-        rv[1] = r01.x; rv[2] = r01.y; rv[3] = r23.x; rv[4] = r23.y;
-        sv[1] = s4.x; sv[2] = s4.y; sv[3] = s4.z; sv[4] = s4.w;
-        fv[1] = f4.x; fv[2] = f4.y; fv[3] = f4.z; fv[4] = f4.w;
-        const bool lo = x0 > 0, hi = x0 + 4 < nx;
-        rv[0] = lo ? r[base - 1] : 0.0;
-        sv[0] = lo ? s[base - 1] : 0.f;
-        fv[0] = lo ? f[base - 1] : 0.f;
-        rv[5] = hi ? r[base + 4] : 0.0;
-        sv[5] = hi ? s[base + 4] : 0.f;
-        fv[5] = hi ? f[base + 4] : 0.f;
-      }
-      float v[CI][6];
-#pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        const float u = (float)((double)sv[j] * rv[j]);
-        v[0][j] = u;
-        v[1][j] = fv[j] * u;
-      }
+    for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
         const int t = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+        const int idx = ((lz + 1 + SG * dz) * kQHY + (ly + 1 + SG * dy)) * kQHX + (lx + 1 + SG * dx);
 #pragma unroll
-        for (int c = 0; c < CI; ++c)
+        for (int c = 0; c < NIN; ++c) {
+          const float v = sx[c * kQH + idx];
 #pragma unroll
-          for (int o = 0; o < CO; ++o) {
-            const float w = sW[(o * CI + c) * 27 + t];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) acc[o][k] = fmaf(w, v[c][1 + k + dx], acc[o][k]);
+          for (int o = 0; o < NOUT; ++o) {
+            const float w = TRANS ? sW[(c * CI + o) * 27 + t] : sW[(o * CI + c) * 27 + t];
+            acc[o] = fmaf(w, v, acc[o]);
           }
-      }
-    }
-  }
-#pragma unroll
-  for (int o = 0; o < CO; ++o) {
-    float4 rr;
-    rr.x = acc[o][0];
-    rr.y = acc[o][1];
-    rr.z = acc[o][2];
-    rr.w = acc[o][3];
-    *reinterpret_cast<float4*>(out + (size_t)o * n + p0) = rr;
-  }
-}
-
-// The last transposed convolution (CO -> 2 channels, as k_pc_conv4<2, CO,
-// true>) followed by the output of k_pc_out for the same four cells:
-// z = dinv r + s (d0 + f d1), the two channels d kept in registers.  With q,
-// one partial z.q per workgroup at index lb (pc_out_parts(n) partials).
-template <int CO>
-__global__ __launch_bounds__(kPcThreads) void k_pc_conv4_out(const float* __restrict__ in, const float* __restrict__ W,
-                                                             const double* __restrict__ r,
-                                                             const double* __restrict__ dinv,
-                                                             const float* __restrict__ s, const float* __restrict__ f,
-                                                             int nx, int ny, int nz, double* __restrict__ z,
-                                                             const double* __restrict__ q, double* part) {
-  constexpr int CI = 2;
-  const int n = nx * ny * nz;
-  const int nq = n / 4;
-  const int lb = xcd_block(blockIdx.x, (nq + kPcThreads - 1) / kPcThreads);
-  if (lb < 0) return;
-  __shared__ float sW[CO * CI * 27];
-  __shared__ double red[kPcThreads / 64];
-  for (int e = threadIdx.x; e < CO * CI * 27; e += kPcThreads) sW[e] = W[e];
-  __syncthreads();
-  const int qd = lb * kPcThreads + threadIdx.x;
-  double zq[1] = {0.0};
-  if (qd < nq) {
-    const int p0 = 4 * qd;
-    const int nxy = nx * ny;
-    const int zc = p0 / nxy, y = (p0 / nx) % ny, x0 = p0 % nx;
-    float acc[CI][4];
-#pragma unroll
-    for (int i = 0; i < CI; ++i)
-#pragma unroll
-      for (int k = 0; k < 4; ++k) acc[i][k] = 0.f;
-#pragma unroll
-    for (int dz = -1; dz <= 1; ++dz) {
-      const int zz = zc - dz;
-      if (zz < 0 || zz >= nz) continue;
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy) {
-        const int yy = y - dy;
-        if (yy < 0 || yy >= ny) continue;
-        const size_t base = (size_t)zz * nxy + (size_t)yy * nx + x0;
-        float v[CO][6];
-#pragma unroll
-        for (int c = 0; c < CO; ++c) {
-          const float* row = in + (size_t)c * n + base;
-          const float4 mid = *reinterpret_cast<const float4*>(row);
-          v[c][0] = x0 > 0 ? row[-1] : 0.f;
-          v[c][1] = mid.x;
-          v[c][2] = mid.y;
-          v[c][3] = mid.z;
-          v[c][4] = mid.w;
-          v[c][5] = x0 + 4 < nx ? row[4] : 0.f;
-        }
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int t = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
-#pragma unroll
-          for (int c = 0; c < CO; ++c)
-#pragma unroll
-            for (int i = 0; i < CI; ++i) {
-              const float w = sW[(c * CI + i) * 27 + t];
-#pragma unroll
-              for (int k = 0; k < 4; ++k) acc[i][k] = fmaf(w, v[c][1 + k - dx], acc[i][k]);
-            }
         }
       }
+  const int p = gx + nx * (gy + ny * gz);
+  if constexpr (MODE == 2) {
+    double zq[1] = {0.0};
+    if (own) {
+      const double w = (double)acc[0] + (double)f[p] * (double)acc[1];
+      const double zv = fma(dinv[p], r[p], (double)s[p] * w);
+      z[p] = zv;
+      if (q) zq[0] = zv * q[p];
     }
-    const double2 r01 = *reinterpret_cast<const double2*>(r + p0);
-    const double2 r23 = *reinterpret_cast<const double2*>(r + p0 + 2);
-    const double2 d01 = *reinterpret_cast<const double2*>(dinv + p0);
-    const double2 d23 = *reinterpret_cast<const double2*>(dinv + p0 + 2);
-    const float4 s4 = *reinterpret_cast<const float4*>(s + p0);
-    const float4 f4 = *reinterpret_cast<const float4*>(f + p0);
-    const double rv[4] = {r01.x, r01.y, r23.x, r23.y};
-    const double dv[4] = {d01.x, d01.y, d23.x, d23.y};
-    const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
-    const float fv[4] = {f4.x, f4.y, f4.z, f4.w};
-    double zv[4];
+    if (part) write_partial_at<1, kPcThreads>(zq, red, part, lb);
+  } else {
+    if (own) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double w = (double)acc[0][k] + (double)fv[k] * (double)acc[1][k];
-      zv[k] = fma(dv[k], rv[k], (double)sv[k] * w);
-    }
-    *reinterpret_cast<double2*>(z + p0) = make_double2(zv[0], zv[1]);
-    *reinterpret_cast<double2*>(z + p0 + 2) = make_double2(zv[2], zv[3]);
-    if (q) {
-      const double2 q01 = *reinterpret_cast<const double2*>(q + p0);
-      const double2 q23 = *reinterpret_cast<const double2*>(q + p0 + 2);
-      zq[0] = fma(zv[0], q01.x, zq[0]);
-      zq[0] = fma(zv[1], q01.y, zq[0]);
-      zq[0] = fma(zv[2], q23.x, zq[0]);
-      zq[0] = fma(zv[3], q23.y, zq[0]);
+      for (int o = 0; o < NOUT; ++o) out[(size_t)o * n + p] = acc[o];
     }
   }
-  if (part) write_partial_at<1, kPcThreads>(zq, red, part, lb);
 }
 
 // z = dinv r + s (d0 + f d1); optional partial z.q per workgroup
@@ -593,7 +587,34 @@ PcNetGpu::PcNetGpu(const OpDev<double>& op, int C, hipStream_t st) : op_(op), C_
   ny_ = op.ny;
   nz_ = op.kind == LYAP_OP_STENCIL5 ? 1 : op.nz;
   n_ = op.n;
-  P_ = pcnet_param_count(C);
+  alloc_common();
+  const int g = grid_for(n_, 1, 1024);
+  hipLaunchKernelGGL(k_pc_prep1, dim3(g), dim3(kPcThreads), 0, st_, op_, n_, dinv_.as<double>(), s_.as<float>(),
+                     part_.as<double>());
+  hipLaunchKernelGGL(k_pc_prep2, dim3(g), dim3(kPcThreads), 0, st_, op_, n_, part_.as<double>(), g, f_.as<float>());
+  LYAP_LAUNCHED("pcnet prep");
+}
+
+PcNetGpu::PcNetGpu(int nx, int ny, int nz, const double* dinv, SpdApply kapply, int C, hipStream_t st)
+    : op_{}, kapply_(std::move(kapply)), C_(C), st_(st) {
+  LYAP_REQUIRE(C == 2 || C == 4 || C == 8, LYAP_E_UNSUPPORTED, "network width C=%d not built (2, 4, 8)", C);
+  LYAP_REQUIRE(nx > 0 && ny > 0 && nz > 0 && dinv && kapply_, LYAP_E_ARG, "bad network grid");
+  nx_ = nx;
+  ny_ = ny;
+  nz_ = nz;
+  n_ = nx * ny * nz;
+  alloc_common();
+  LYAP_HIP(hipMemcpyAsync(dinv_.p, dinv, (size_t)n_ * sizeof(double), hipMemcpyDeviceToDevice, st_));
+  const int g = grid_for(n_, 1, 1024);
+  hipLaunchKernelGGL(k_pc_prep_d1, dim3(g), dim3(kPcThreads), 0, st_, dinv_.as<double>(), n_, s_.as<float>(),
+                     part_.as<double>());
+  hipLaunchKernelGGL(k_pc_prep_d2, dim3(g), dim3(kPcThreads), 0, st_, dinv_.as<double>(), n_, part_.as<double>(), g,
+                     f_.as<float>());
+  LYAP_LAUNCHED("pcnet prep");
+}
+
+void PcNetGpu::alloc_common() {
+  P_ = pcnet_param_count(C_);
   const size_t n = (size_t)n_;
   W_.alloc(P_ * sizeof(float));
   m_.alloc(P_ * sizeof(float));
@@ -606,17 +627,12 @@ PcNetGpu::PcNetGpu(const OpDev<double>& op, int C, hipStream_t st) : op_(op), C_
   s_.alloc(n * sizeof(float));
   f_.alloc(n * sizeof(float));
   x0_.alloc(2 * n * sizeof(float));
-  a1_.alloc(C * n * sizeof(float));
-  k_.alloc(C * n * sizeof(float));
-  t1_.alloc(C * n * sizeof(float));
+  a1_.alloc(C_ * n * sizeof(float));
+  k_.alloc(C_ * n * sizeof(float));
+  t1_.alloc(C_ * n * sizeof(float));
   d_.alloc(2 * n * sizeof(float));
   part_.alloc((size_t)kWSeg * kPcMaxC * kPcMaxC * 27 * sizeof(double));
   loss_.alloc(64);
-  const int g = grid_for(n_, 1, 1024);
-  hipLaunchKernelGGL(k_pc_prep1, dim3(g), dim3(kPcThreads), 0, st_, op_, n_, dinv_.as<double>(), s_.as<float>(),
-                     part_.as<double>());
-  hipLaunchKernelGGL(k_pc_prep2, dim3(g), dim3(kPcThreads), 0, st_, op_, n_, part_.as<double>(), g, f_.as<float>());
-  LYAP_LAUNCHED("pcnet prep");
 }
 
 void PcNetGpu::set_weights(const float* host) {
@@ -686,57 +702,59 @@ void PcNetGpu::wgrad(const float* x, const float* g, double* gradW, bool accumul
     default: { constexpr int CC = 8; __VA_ARGS__; } break;    \
   }
 
-void PcNetGpu::forward(const double* r, bool fused) {
+void PcNetGpu::forward(const double* r) {
   const float* W1 = W_.as<float>();
   const float* W2 = W1 + C_ * 2 * 27;
   const int g = (n_ + kPcThreads - 1) / kPcThreads;
-  if (!fused) {
-    hipLaunchKernelGGL(k_pc_in_r, dim3(g), dim3(kPcThreads), 0, st_, r, s_.as<float>(), f_.as<float>(), n_,
-                       x0_.as<float>());
-  }
+  hipLaunchKernelGGL(k_pc_in_r, dim3(g), dim3(kPcThreads), 0, st_, r, s_.as<float>(), f_.as<float>(), n_,
+                     x0_.as<float>());
   LYAP_PC_SWITCH({
-    if (fused) {
-      hipLaunchKernelGGL((k_pc_conv4_r<CC>), dim3(xcd_grid((n_ / 4 + kPcThreads - 1) / kPcThreads)),
-                         dim3(kPcThreads), 0, st_, r, s_.as<float>(), f_.as<float>(), W1, a1_.as<float>(), nx_, ny_,
-                         nz_);
-      LYAP_LAUNCHED("k_pc_conv4_r");
-    } else {
-      conv<2, CC>(x0_.as<float>(), W1, a1_.as<float>());
-    }
+    conv<2, CC>(x0_.as<float>(), W1, a1_.as<float>());
     conv<CC, CC>(a1_.as<float>(), W2, k_.as<float>());
     convT<CC, CC>(k_.as<float>(), W2, t1_.as<float>());
-    if (!fused) convT<CC, 2>(t1_.as<float>(), W1, d_.as<float>());
+    convT<CC, 2>(t1_.as<float>(), W1, d_.as<float>());
   });
 }
 
-int PcNetGpu::max_out_parts() const { return std::max((n_ / 4 + kPcThreads - 1) / kPcThreads, stream_grid(n_)); }
+int PcNetGpu::tiles() const {
+  return ((nx_ + kQX - 1) / kQX) * ((ny_ + kQY - 1) / kQY) * ((nz_ + kQZ - 1) / kQZ);
+}
 
-static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+int PcNetGpu::max_out_parts() const { return std::max(tiles(), stream_grid(n_)); }
 
 int PcNetGpu::apply(const double* r, double* z, const double* q, double* part) {
-  const bool fused = nx_ % 4 == 0 && aligned16(r) && aligned16(z) && (!q || aligned16(q));
-  forward(r, fused);
-  if (fused) {
-    // the last transposed convolution and the output in one kernel
-    const float* W1 = W_.as<float>();
-    LYAP_PC_SWITCH({
-      hipLaunchKernelGGL((k_pc_conv4_out<CC>), dim3(xcd_grid((n_ / 4 + kPcThreads - 1) / kPcThreads)),
-                         dim3(kPcThreads), 0, st_, t1_.as<float>(), W1, r, dinv_.as<double>(), s_.as<float>(),
-                         f_.as<float>(), nx_, ny_, nz_, z, q, part);
-    });
-    LYAP_LAUNCHED("k_pc_conv4_out");
-    return (n_ / 4 + kPcThreads - 1) / kPcThreads;
-  }
-  constexpr int NT = stream_threads(1);
-  hipLaunchKernelGGL((k_pc_out<NT>), dim3(stream_grid(n_)), dim3(NT), 0, st_, r, dinv_.as<double>(), s_.as<float>(),
-                     f_.as<float>(), d_.as<float>(), n_, z, q, part);
-  LYAP_LAUNCHED("k_pc_out");
-  return stream_grid(n_);
+  const float* W1 = W_.as<float>();
+  const float* W2 = W1 + C_ * 2 * 27;
+  const int tx = (nx_ + kQX - 1) / kQX, ty = (ny_ + kQY - 1) / kQY, tz = (nz_ + kQZ - 1) / kQZ;
+  const int G = tx * ty * tz;
+  const dim3 grid(xcd_grid(G)), blk(kPcThreads);
+  const float* fn = nullptr;
+  float* fo = nullptr;
+  const double* dn = nullptr;
+  double* dno = nullptr;
+  LYAP_PC_SWITCH({
+    hipLaunchKernelGGL((k_pc_tile<2, CC, false, 1>), grid, blk, 0, st_, fn, r, s_.as<float>(), f_.as<float>(), dn, W1,
+                       a1_.as<float>(), dno, dn, dno, nx_, ny_, nz_, tx, ty, tz);
+    hipLaunchKernelGGL((k_pc_tile<CC, CC, false, 0>), grid, blk, 0, st_, a1_.as<float>(), dn, fn, fn, dn, W2,
+                       k_.as<float>(), dno, dn, dno, nx_, ny_, nz_, tx, ty, tz);
+    hipLaunchKernelGGL((k_pc_tile<CC, CC, true, 0>), grid, blk, 0, st_, k_.as<float>(), dn, fn, fn, dn, W2,
+                       t1_.as<float>(), dno, dn, dno, nx_, ny_, nz_, tx, ty, tz);
+    hipLaunchKernelGGL((k_pc_tile<2, CC, true, 2>), grid, blk, 0, st_, t1_.as<float>(), r, s_.as<float>(),
+                       f_.as<float>(), dinv_.as<double>(), W1, fo, z, q, part, nx_, ny_, nz_, tx, ty, tz);
+  });
+  LYAP_LAUNCHED("pcnet apply");
+  return G;
 }
 
 double PcNetGpu::energy(const double* e) {
   const int g = grid_for(n_, 1, 1024);
-  hipLaunchKernelGGL(k_pc_energy, dim3(g), dim3(kPcThreads), 0, st_, op_, e, n_, part_.as<double>());
+  if (kapply_) {
+    if (!ky_.p) ky_.alloc((size_t)n_ * sizeof(double));
+    kapply_(e, ky_.as<double>());
+    hipLaunchKernelGGL(k_pc_dot, dim3(g), dim3(kPcThreads), 0, st_, e, ky_.as<double>(), n_, part_.as<double>());
+  } else {
+    hipLaunchKernelGGL(k_pc_energy, dim3(g), dim3(kPcThreads), 0, st_, op_, e, n_, part_.as<double>());
+  }
   hipLaunchKernelGGL(k_pc_sum1, dim3(1), dim3(kPcThreads), 0, st_, part_.as<double>(), g, loss_.as<double>() + 1);
   double h = 0.0;
   LYAP_HIP(hipMemcpyAsync(&h, loss_.as<double>() + 1, sizeof(double), hipMemcpyDeviceToHost, st_));
@@ -758,13 +776,22 @@ double PcNetGpu::grad(const double* r, const double* e, double eAe, bool want_lo
   const float* W2 = W1 + C_ * 2 * 27;
   double* g1 = grad_.as<double>();
   double* g2 = g1 + C_ * 2 * 27;
-  forward(r, false);
+  forward(r);
   constexpr int NT = stream_threads(1);
   hipLaunchKernelGGL((k_pc_out<NT>), dim3(stream_grid(n_)), dim3(NT), 0, st_, r, dinv_.as<double>(), s_.as<float>(),
                      f_.as<float>(), d_.as<float>(), n_, z_.as<double>(), (const double*)nullptr, (double*)nullptr);
   const int gr = grid_for(n_, 1, 1024);
-  hipLaunchKernelGGL(k_pc_resid, dim3(gr), dim3(kPcThreads), 0, st_, op_, z_.as<double>(), e, s_.as<float>(), eAe,
-                     n_, gw_.as<float>(), part_.as<double>());
+  if (kapply_) {
+    if (!ky_.p) ky_.alloc((size_t)n_ * sizeof(double));
+    if (!kd_.p) kd_.alloc((size_t)n_ * sizeof(double));
+    hipLaunchKernelGGL(k_pc_sub, dim3((n_ + 255) / 256), dim3(256), 0, st_, z_.as<double>(), e, n_, kd_.as<double>());
+    kapply_(kd_.as<double>(), ky_.as<double>());
+    hipLaunchKernelGGL(k_pc_resid_k, dim3(gr), dim3(kPcThreads), 0, st_, kd_.as<double>(), ky_.as<double>(),
+                       s_.as<float>(), eAe, n_, gw_.as<float>(), part_.as<double>());
+  } else {
+    hipLaunchKernelGGL(k_pc_resid, dim3(gr), dim3(kPcThreads), 0, st_, op_, z_.as<double>(), e, s_.as<float>(), eAe,
+                       n_, gw_.as<float>(), part_.as<double>());
+  }
   hipLaunchKernelGGL(k_pc_loss, dim3(1), dim3(kPcThreads), 0, st_, part_.as<double>(), gr, eAe, loss_.as<double>());
   const int g = (n_ + kPcThreads - 1) / kPcThreads;
   hipLaunchKernelGGL(k_pc_in_g, dim3(g), dim3(kPcThreads), 0, st_, gw_.as<float>(), f_.as<float>(), n_,
@@ -893,6 +920,80 @@ extern "C" lyap_status lyap_pcnet_fcg(const lyap_op* A, int32_t C, const float* 
     net.set_weights(W);
     InnerCG cg(op.dev, (int)A->n, 1, LYAP_PC_LEARNED, eta, max_iter, st);
     cg.set_net(&net);
+    lyap_status status = LYAP_OK;
+    try {
+      cg.solve(B, X);
+    } catch (const Error& e) {
+      if (e.st != LYAP_E_INNER) throw;
+      status = LYAP_E_INNER;
+    }
+    LYAP_HIP(hipStreamSynchronize(st));
+    if (iters) *iters = cg.stats().iters;
+    if (relres) *relres = cg.stats().worst_relres;
+    return status;
+  } catch (const Error& e2) {
+    return e2.st;
+  }
+}
+
+// ------------------------------------------------------------------ on the Schur complement
+extern "C" lyap_status lyap_pcnet_schur_train(const lyap_op* A, int32_t C, float* W, const double* b, int32_t every,
+                                              int32_t keep, int32_t steps, double lr, double* losses,
+                                              int32_t* npairs, void* stream) {
+  using namespace lyap;
+  clear_error();
+  try {
+    validate_op(A);
+    LYAP_REQUIRE(W && b && every > 0 && keep > 0 && steps >= 0, LYAP_E_ARG, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    OpHolder<double> op;
+    make_op_f64(A, op, st);
+    const int n = (int)A->n;
+    InnerCG cg(op.dev, n, 1, LYAP_PC_LEARNED, 1e-12, 100000, st);
+    auto net = cg.make_schur_net(C);
+    net->set_weights(W);
+    cg.harvest(every, keep);
+    DevBuf x((size_t)n * sizeof(double));
+    cg.solve(b, x.as<double>());
+    std::vector<int> use;
+    std::vector<double> eAe;
+    for (int i = 0; i < cg.pairs(); ++i) {
+      const double v = net->energy(cg.pair_e(i));
+      if (v > 0.0) {
+        use.push_back(i);
+        eAe.push_back(v);
+      }
+    }
+    LYAP_REQUIRE(!use.empty(), LYAP_E_INNER, "no training pairs");
+    for (int t = 0; t < steps; ++t) {
+      const int q = t % (int)use.size();
+      const double L = net->grad(cg.pair_r(use[q]), cg.pair_e(use[q]), eAe[q], losses != nullptr);
+      if (losses) losses[t] = L;
+      net->adam(lr);
+    }
+    net->get_weights(W);
+    if (npairs) *npairs = (int32_t)use.size();
+    return LYAP_OK;
+  } catch (const Error& e2) {
+    return e2.st;
+  }
+}
+
+extern "C" lyap_status lyap_pcnet_schur_fcg(const lyap_op* A, int32_t C, const float* W, const double* B, double* X,
+                                            double eta, int32_t max_iter, int64_t* iters, double* relres,
+                                            void* stream) {
+  using namespace lyap;
+  clear_error();
+  try {
+    validate_op(A);
+    LYAP_REQUIRE(W && B && X, LYAP_E_ARG, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    OpHolder<double> op;
+    make_op_f64(A, op, st);
+    InnerCG cg(op.dev, (int)A->n, 1, LYAP_PC_LEARNED, eta, max_iter, st);
+    auto net = cg.make_schur_net(C);
+    net->set_weights(W);
+    cg.set_net_schur(net.get());
     lyap_status status = LYAP_OK;
     try {
       cg.solve(B, X);

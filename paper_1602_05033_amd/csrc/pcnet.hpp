@@ -11,6 +11,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <vector>
 
 #include "lanczos.hpp"
@@ -24,10 +25,20 @@ inline int pcnet_param_count(int C) { return C * 2 * 27 + C * C * 27; }
 // SplitMix64 initial weights, uniform in [-scale, scale): u = (top 53 bits) / 2^53.
 void pcnet_init_weights(int C, uint64_t seed, double scale, float* W);
 
+// y = K x for the symmetric positive definite matrix K of the system the
+// network preconditions (device FP64 vectors on the network's grid, stream-ordered).
+using SpdApply = std::function<void(const double* x, double* y)>;
+
 class PcNetGpu {
  public:
-  // op: FP64 stencil operator (5- or 7-point; its grid is the network's grid).
+  // op: FP64 stencil operator (5- or 7-point; its grid is the network's grid,
+  // K = -A).
   PcNetGpu(const OpDev<double>& op, int C, hipStream_t st);
+  // A network on an nx x ny x nz grid (x fastest) for a given K: dinv is the
+  // diagonal part D^{-1} (device FP64, copied; 0 marks grid points outside
+  // the system, which the network then leaves at zero) and kapply applies K
+  // (used by energy() and grad()).
+  PcNetGpu(int nx, int ny, int nz, const double* dinv, SpdApply kapply, int C, hipStream_t st);
   int C() const { return C_; }
   int n() const { return n_; }
   void set_weights(const float* host);
@@ -37,20 +48,19 @@ class PcNetGpu {
   // order); returns how many were written.
   int apply(const double* r, double* z, const double* q, double* part);
   int max_out_parts() const;
-  // Algorithmic figures of one apply() on the operator's grid (the fused
-  // four-kernel form): FP32 multiply-adds x 2, and HBM bytes (r, D^{-1}, the
-  // channel scalings and the activations in and out of each convolution).
+  int tiles() const;  // workgroups (and z.q partials) of one apply()
+  // Algorithmic figures of one apply() (the four tiled kernels): FP32
+  // multiply-adds x 2, and HBM bytes (r, s, f in; a1 out; a1 in, k out; k in,
+  // t1 out; t1, r, D^{-1}, s, f, q in, z out).
   double apply_flops() const { return 2.0 * 27.0 * (4.0 * C_ + 2.0 * C_ * C_) * n_; }
-  double apply_bytes() const {
-    return (double)n_ * ((8 + 4 + 4 + 4.0 * C_) + 2 * (8.0 * C_) + (4.0 * C_ + 8 + 8 + 4 + 4 + 8 + 8));
-  }
+  double apply_bytes() const { return (double)n_ * (56.0 + 24.0 * C_); }
   // Loss of the pair (r, e) (eAe = e^T (-A) e) and its gradient into the
   // device FP64 buffer grad (param_count values); the loss is left on the
   // device (loss_dev) and returned when want_loss (host sync).
   double grad(const double* r, const double* e, double eAe, bool want_loss);
   // One Adam step with the gradient of the last grad() call.
   void adam(double lr);
-  // e^T (-A) e on the device, returned to the host.
+  // e^T K e on the device, returned to the host.
   double energy(const double* e);
   const double* dinv() const { return dinv_.as<double>(); }
   const double* grad_dev() const { return grad_.as<double>(); }
@@ -62,18 +72,18 @@ class PcNetGpu {
   void convT(const float* in, const float* W, float* out);
   template <int CI, int CO>
   void wgrad(const float* x, const float* g, double* gradW, bool accumulate);
-  // fused: the input channels x0 are formed inside the first convolution and
-  // the last transposed convolution is left to the caller (apply's fused
-  // output kernel); else x0 and d are stored (the weight gradients read x0).
-  void forward(const double* r, bool fused);
+  // x0 = [s r, f s r], a1, k = K(x0) and d = K^T k, kept for the weight gradients.
+  void forward(const double* r);
 
+  void alloc_common();
   OpDev<double> op_;
+  SpdApply kapply_;   // set: K given by the caller (else K = -A of op_)
   int nx_, ny_, nz_, n_, C_, P_;
   hipStream_t st_;
   int adam_t_ = 0;
   DevBuf W_, m_, v_, grad_, dinv_, s_, f_;
   DevBuf x0_, a1_, k_, t1_, d_, x0g_, a1g_, kg_, t2_, z_, gw_;
-  DevBuf part_, wpart_, loss_;
+  DevBuf part_, wpart_, loss_, ky_, kd_;
   size_t wpart_cap_ = 0;
 };
 

@@ -16,9 +16,9 @@
 // (both triangular factors are explicit), then x_r = D_r^{-1}(rhs_r - E^T x_b).
 //
 // Layout: the black cells of grid line (j, l) sit at compact slots
-// (j + ny l) hx + i / 2, hx = ceil(nx / 2) (one padding slot per line of odd
-// parity when nx is odd; padding slots are never read or written).  The red
-// cells use the same formula.  Vectors of the condensed iteration are
+// (j + ny l) hx + i / 2, hx = ceil(nx / 2) rounded up to a multiple of 4 (the
+// slots past a line's last cell are padding: zero from allocation on, never
+// written by the iteration).  The red cells use the same formula.  Vectors of the condensed iteration are
 // row-interleaved (slot q holds its S right-hand-side entries contiguously).
 //
 // The iteration is the single-reduction (Chronopoulos-Gear) form of the
@@ -30,6 +30,7 @@
 #include <cmath>
 
 #include "pcg.hpp"
+#include "pcnet.hpp"
 
 namespace lyap {
 
@@ -413,12 +414,167 @@ __global__ void k_rb_finish(OpDev<double> op, RbGeom g, const double* __restrict
   }
 }
 
+// ------------------------------------------------------------------ Sigma x for a given x
+// (one right-hand side, compact black slots; the network's training applies it)
+// v = D_r^{-1} T^T x at the red slots
+template <bool K7>
+__global__ void k_rb_vx(OpDev<double> op, RbGeom g, const double* __restrict__ rinv, const double* __restrict__ x,
+                        double* __restrict__ v) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nb; q += gridDim.x * blockDim.x) {
+    int i, j, l;
+    if (!rb_cell(g, q, 0, i, j, l)) continue;
+    double acc = 0.0;
+    for_neighbours<K7>(op, g, i, j, l, i + g.nx * (j + g.ny * l),
+                       [&](int bi, int bj, int bl, int, double t, int) { acc = fma(t, x[rb_slot(g, bi, bj, bl)], acc); });
+    v[q] = acc * rinv[q];
+  }
+}
+
+// y = D_b x - T v at the black slots, 0 at the padding slots
+template <bool K7>
+__global__ void k_rb_yx(OpDev<double> op, RbGeom g, const double* __restrict__ db, const double* __restrict__ x,
+                        const double* __restrict__ v, double* __restrict__ y) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nb; q += gridDim.x * blockDim.x) {
+    int i, j, l;
+    if (!rb_cell(g, q, 1, i, j, l)) {
+      y[q] = 0.0;
+      continue;
+    }
+    double acc = db[q] * x[q];
+    for_neighbours<K7>(op, g, i, j, l, i + g.nx * (j + g.ny * l),
+                       [&](int ri, int rj, int rl, int, double t, int) { acc = fma(-t, v[rb_slot(g, ri, rj, rl)], acc); });
+    y[q] = acc;
+  }
+}
+
+// e_i = x* - x_i in place over the compact slots
+__global__ void k_rb_err(const double* __restrict__ xs, double* __restrict__ xi, int n) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) xi[p] = xs[p] - xi[p];
+}
+
+// ------------------------------------------------------------------ flexible CG on Sigma
+// with the network z = M(r) (one right-hand side).  Per iteration: sweep A
+// (direction at the black slots, v = D_r^{-1} T^T p at the red slots), sweep B
+// (q = Sigma p, partials p.q and p.r), the update (x, r, partial r.r), then
+// the network.
+
+// partial r.r over the black slots
+template <int NT>
+__global__ __launch_bounds__(NT) void k_rbf_rr(RbGeom g, const double* __restrict__ r, double* pout) {
+  __shared__ double red[NT / 64];
+  double acc[1] = {0.0};
+  int lo, hi;
+  op_rows(blockIdx.x, gridDim.x, g.nb, lo, hi);
+  for (int q = lo + threadIdx.x; q < hi; q += NT) acc[0] = fma(r[q], r[q], acc[0]);
+  write_partial<1, NT>(acc, red, pout);
+}
+
+// Sweep A: beta = -(z.q_old) / (p_old.q_old) (0 at it = 0), p = z + beta p_old
+// (0 once r.r <= state); v at the red slots from p at the black neighbours
+// (recomputed from z, p_old there).
+template <bool K7, int NT>
+__global__ __launch_bounds__(NT) void k_rbf_dira(OpDev<double> op, RbGeom g, const double* __restrict__ rinv,
+                                                 const double* __restrict__ z, const double* __restrict__ pold,
+                                                 double* __restrict__ pnew, double* __restrict__ v, CgIter* log, int it,
+                                                 const double* state, const double* partR, int nparts,
+                                                 const double* partZ, int nzparts) {
+  __shared__ double red[NT / 64];
+  reduce_partials<1, NT>(partR, nparts, red);
+  const double rr = uniform_d(red[0]);
+  __syncthreads();
+  double zq = 0.0;
+  if (it > 0) {
+    reduce_partials<1, NT>(partZ, nzparts, red);
+    zq = uniform_d(red[0]);
+    __syncthreads();
+  }
+  const bool active = rr > uniform_d(state[0]);
+  const double pq_old = it > 0 ? uniform_d(log[it - 1].sigma[0]) : 1.0;
+  const double beta = (active && it > 0 && pq_old > 0.0) ? -zq / pq_old : 0.0;
+  const double mask = active ? 1.0 : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) log[it].rr[0] = rr;
+  const double* po = it > 0 ? pold : nullptr;
+  auto prow = [&](int q) -> double { return mask * (po ? fma(beta, po[q], z[q]) : z[q]); };
+  int lo, hi;
+  op_rows(blockIdx.x, gridDim.x, g.nb, lo, hi);
+  for (int q = lo + threadIdx.x; q < hi; q += NT) {
+    int i, j, l;
+    if (rb_cell(g, q, 1, i, j, l)) pnew[q] = prow(q);
+    if (rb_cell(g, q, 0, i, j, l)) {
+      double acc = 0.0;
+      for_neighbours<K7>(op, g, i, j, l, i + g.nx * (j + g.ny * l),
+                         [&](int bi, int bj, int bl, int, double t, int) { acc = fma(t, prow(rb_slot(g, bi, bj, bl)), acc); });
+      v[q] = acc * rinv[q];
+    }
+  }
+}
+
+// Sweep B: q = D_b p - T v at the black slots (0 at padding); partials p.q, p.r
+template <bool K7, int NT>
+__global__ __launch_bounds__(NT) void k_rbf_dirb(OpDev<double> op, RbGeom g, const double* __restrict__ db,
+                                                 const double* __restrict__ p, const double* __restrict__ v,
+                                                 const double* __restrict__ r, double* __restrict__ qv, double* pout) {
+  __shared__ double red[2 * (NT / 64)];
+  double acc[2] = {0.0, 0.0};
+  int lo, hi;
+  op_rows(blockIdx.x, gridDim.x, g.nb, lo, hi);
+  for (int q = lo + threadIdx.x; q < hi; q += NT) {
+    int i, j, l;
+    if (!rb_cell(g, q, 1, i, j, l)) {
+      qv[q] = 0.0;
+      continue;
+    }
+    const double pq = p[q];
+    double w = db[q] * pq;
+    for_neighbours<K7>(op, g, i, j, l, i + g.nx * (j + g.ny * l),
+                       [&](int ri, int rj, int rl, int, double t, int) { w = fma(-t, v[rb_slot(g, ri, rj, rl)], w); });
+    qv[q] = w;
+    acc[0] = fma(pq, w, acc[0]);
+    acc[1] = fma(pq, r[q], acc[1]);
+  }
+  write_partial<2, NT>(acc, red, pout);
+}
+
+// Update: alpha = p.r / p.q; x += alpha p; r -= alpha q; partial r.r
+template <int NT>
+__global__ __launch_bounds__(NT) void k_rbf_upd(RbGeom g, double* __restrict__ x, double* __restrict__ r,
+                                                const double* __restrict__ p, const double* __restrict__ qv,
+                                                CgIter* log, int it, const double* state, const double* pin,
+                                                int nparts, double* pout, int* flag) {
+  __shared__ double red[2 * (NT / 64)];
+  reduce_partials<2, NT>(pin, nparts, red);
+  const double pq = uniform_d(red[0]), pr = uniform_d(red[1]);
+  __syncthreads();
+  const bool active = uniform_d(log[it].rr[0]) > uniform_d(state[0]);
+  const double alpha = (active && pq > 0.0) ? pr / pq : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    log[it].sigma[0] = pq;
+    log[it].rho[0] = pr;
+    log[it].alpha[0] = alpha;
+    if (active && !(pq > 0.0)) flag[1] = it + 1;
+  }
+  double acc[1] = {0.0};
+  int lo, hi;
+  op_rows(blockIdx.x, gridDim.x, g.nb, lo, hi);
+  for (int q = lo + threadIdx.x; q < hi; q += NT) {
+    const double xq = fma(alpha, p[q], x[q]);
+    const double rq = fma(-alpha, qv[q], r[q]);
+    x[q] = xq;
+    r[q] = rq;
+    acc[0] = fma(rq, rq, acc[0]);
+  }
+  (void)red;
+  __shared__ double red1[NT / 64];
+  write_partial<1, NT>(acc, red1, pout);
+}
+
 inline RbGeom rb_geom(const OpDev<double>& op) {
   RbGeom g;
   g.nx = op.nx;
   g.ny = op.ny;
   g.nz = op.nz;
-  g.hx = (op.nx + 1) / 2;
+  g.hx = ((op.nx + 1) / 2 + 3) / 4 * 4;  // a multiple of 4 (the network's vector loads)
   g.nb = g.hx * g.ny * g.nz;
   return g;
 }
@@ -435,8 +591,11 @@ void InnerCG::setup_rb() {
   rb_db_.alloc(slots * sizeof(double));
   rb_sinv_.alloc(slots * sizeof(double));
   const size_t blk = slots * S_ * sizeof(double);
-  for (DevBuf* b : {&rb_x_, &rb_p_, &rb_r0_, &rb_r1_, &rb_w0_, &rb_w1_, &rb_s0_, &rb_s1_, &rb_u_, &rb_v_})
+  for (DevBuf* b : {&rb_x_, &rb_p_, &rb_r0_, &rb_r1_, &rb_w0_, &rb_w1_, &rb_s0_, &rb_s1_, &rb_u_, &rb_v_}) {
     b->alloc(blk);
+    LYAP_HIP(hipMemsetAsync(b->p, 0, blk, st_));
+  }
+  for (DevBuf* b : {&rb_rinv_, &rb_db_, &rb_sinv_}) LYAP_HIP(hipMemsetAsync(b->p, 0, b->bytes, st_));
   rb_grid_ = stream_grid(g.nb);
   LYAP_HIP(hipMemsetAsync(flag_.p, 0, 64, st_));
   const int gs = grid_for(g.nb, 1, 1024);
@@ -452,6 +611,33 @@ void InnerCG::setup_rb() {
   LYAP_HIP(hipStreamSynchronize(st_));
   LYAP_REQUIRE(hf[0] == 0, LYAP_E_INDEFINITE,
                "IC(0) pivot is not positive: A is not negative definite with a diagonally dominant pattern");
+  rb_ready_ = true;
+}
+
+void InnerCG::schur_apply(const double* x, double* y) {
+  LYAP_REQUIRE(rb_ready_ && S_ == 1, LYAP_E_UNSUPPORTED, "Sigma x needs the red-black split and one column");
+  const RbGeom g = rb_geom(op_);
+  const int gs = grid_for(g.nb, 1, 1024);
+  if (op_.kind == LYAP_OP_STENCIL7) {
+    hipLaunchKernelGGL((k_rb_vx<true>), dim3(gs), dim3(kBlock), 0, st_, op_, g, rb_rinv_.as<double>(), x,
+                       rb_v_.as<double>());
+    hipLaunchKernelGGL((k_rb_yx<true>), dim3(gs), dim3(kBlock), 0, st_, op_, g, rb_db_.as<double>(), x,
+                       rb_v_.as<double>(), y);
+  } else {
+    hipLaunchKernelGGL((k_rb_vx<false>), dim3(gs), dim3(kBlock), 0, st_, op_, g, rb_rinv_.as<double>(), x,
+                       rb_v_.as<double>());
+    hipLaunchKernelGGL((k_rb_yx<false>), dim3(gs), dim3(kBlock), 0, st_, op_, g, rb_db_.as<double>(), x,
+                       rb_v_.as<double>(), y);
+  }
+  LYAP_LAUNCHED("schur_apply");
+}
+
+std::unique_ptr<PcNetGpu> InnerCG::make_schur_net(int C) {
+  LYAP_REQUIRE(rb_ready_ && S_ == 1, LYAP_E_UNSUPPORTED,
+               "the learned correction of IC(0) needs a stencil operator and one right-hand side");
+  const RbGeom g = rb_geom(op_);
+  return std::make_unique<PcNetGpu>(g.hx, g.ny, g.nz, rb_sinv_.as<double>(),
+                                    [this](const double* x, double* y) { schur_apply(x, y); }, C, st_);
 }
 
 double InnerCG::rb_iter_bytes() const {
@@ -504,9 +690,20 @@ void InnerCG::rb_solve_templ(const double* B, double* X, int restarts, int chunk
     LYAP_LAUNCHED("k_rb_start");
     int it = 0;
     bool done = false;
+    const bool harvesting = S == 1 && harvest_every_ > 0 && start == 0;
+    auto snapshot = [&]() {
+      if (!harvesting || (int)hr_.size() >= harvest_keep_) return;
+      const size_t bytes = (size_t)g.nb * sizeof(double);
+      hr_.emplace_back(bytes);
+      hx_.emplace_back(bytes);
+      LYAP_HIP(hipMemcpyAsync(hr_.back().p, rb[it % 2], bytes, hipMemcpyDeviceToDevice, st_));
+      LYAP_HIP(hipMemcpyAsync(hx_.back().p, rb_x_.p, bytes, hipMemcpyDeviceToDevice, st_));
+    };
+    snapshot();
     while (!done && total + it < max_iter_) {
       const int it0 = it;
-      const int cnt = std::min(chunk, max_iter_ - total - it);
+      int cnt = std::min(chunk, max_iter_ - total - it);
+      if (harvesting) cnt = std::min(cnt, harvest_every_ - it % harvest_every_);
       for (int c = 0; c < cnt; ++c, ++it) {
         if (kt) kt->mark(LYAP_K_CG_DIR);
         hipLaunchKernelGGL((k_rb_upd<K7, S, NT, false>), dim3(G), dim3(NT), 0, st_, op_, g, rinv, sinv,
@@ -539,6 +736,7 @@ void InnerCG::rb_solve_templ(const double* B, double* X, int restarts, int chunk
           it = it0 + c;  // iterations that changed x
         }
       }
+      if (!done && harvesting && it % harvest_every_ == 0) snapshot();
     }
     total += it;
     const int gf = grid_for(g.nb, 1, 1024);
@@ -556,6 +754,13 @@ void InnerCG::rb_solve_templ(const double* B, double* X, int restarts, int chunk
       worst = std::max(worst, rel);
     }
     if (worst <= eta_) {
+      if (harvest_every_ > 0) {  // e_i = x* - x_i for the kept iterates (compact slots)
+        for (auto& xi : hx_)
+          hipLaunchKernelGGL(k_rb_err, dim3((g.nb + 255) / 256), dim3(256), 0, st_, rb_x_.as<double>(),
+                             xi.as<double>(), g.nb);
+        LYAP_LAUNCHED("k_rb_err");
+        harvest_every_ = 0;
+      }
       stats_.iters += total;
       stats_.solves += 1;
       stats_.restarts += start;
@@ -569,6 +774,121 @@ void InnerCG::rb_solve_templ(const double* B, double* X, int restarts, int chunk
   stats_.worst_relres = std::max(stats_.worst_relres, worst);
   LYAP_REQUIRE(false, LYAP_E_INNER,
                "IC(0) CG did not reach the true relative residual %.1e in %d iterations", eta_, total);
+}
+
+template <bool K7>
+static void rbf_launch_dir(hipStream_t st, int G, const OpDev<double>& op, const RbGeom& g, const double* rinv,
+                           const double* db, const double* z, const double* po, double* pn, double* v,
+                           const double* r, double* qv, CgIter* log, int it, const double* state,
+                           const double* partR, const double* partZ, int zparts, double* pout) {
+  constexpr int NT = stream_threads(1);
+  hipLaunchKernelGGL((k_rbf_dira<K7, NT>), dim3(G), dim3(NT), 0, st, op, g, rinv, z, po, pn, v, log, it, state,
+                     partR, G, partZ, zparts);
+  hipLaunchKernelGGL((k_rbf_dirb<K7, NT>), dim3(G), dim3(NT), 0, st, op, g, db, pn, v, r, qv, pout);
+}
+
+void InnerCG::solve_rb_fcg(const double* B, double* X, KernelTimer* kt) {
+  constexpr int NT = stream_threads(1);
+  constexpr int kChunk = 16, kRestarts = 3;
+  const auto t0 = Clock::now();
+  const RbGeom g = rb_geom(op_);
+  const bool k7 = op_.kind == LYAP_OP_STENCIL7;
+  const double eta_rec = 0.5 * eta_;
+  const double eta2 = eta_rec * eta_rec;
+  const int G = rb_grid_;
+  const double* rinv = rb_rinv_.as<double>();
+  const double* db = rb_db_.as<double>();
+  double* x = rb_x_.as<double>();
+  double* r = rb_r0_.as<double>();
+  double* z = rb_u_.as<double>();
+  double* qv = rb_w0_.as<double>();
+  double* v = rb_v_.as<double>();
+  double* pb[2] = {rb_p_.as<double>(), rb_s0_.as<double>()};
+  if (!partZ_.p) partZ_.alloc((size_t)net_->max_out_parts() * sizeof(double));
+  int zparts = 0;
+  int total = 0;
+  double worst = 0.0;
+  for (int start = 0; start <= kRestarts; ++start) {
+    const int mode = start == 0 ? 0 : 1;
+    if (k7)
+      hipLaunchKernelGGL((k_rb_rhs<true, 1, NT>), dim3(G), dim3(NT), 0, st_, op_, g, B, r_.as<double>(), mode, rinv,
+                         r, x, partA_.as<double>());
+    else
+      hipLaunchKernelGGL((k_rb_rhs<false, 1, NT>), dim3(G), dim3(NT), 0, st_, op_, g, B, r_.as<double>(), mode, rinv,
+                         r, x, partA_.as<double>());
+    if (start == 0)
+      hipLaunchKernelGGL((k_rb_thr<1>), dim3(1), dim3(256), 0, st_, partA_.as<double>(), G, eta2, state_.as<double>());
+    hipLaunchKernelGGL((k_rbf_rr<NT>), dim3(G), dim3(NT), 0, st_, g, r, partA_.as<double>());
+    LYAP_LAUNCHED("k_rbf_start");
+    net_->apply(r, z, nullptr, nullptr);
+    int it = 0;
+    bool done = false;
+    while (!done && total + it < max_iter_) {
+      const int it0 = it;
+      const int cnt = std::min(kChunk, max_iter_ - total - it);
+      for (int c = 0; c < cnt; ++c, ++it) {
+        double* pn = pb[it % 2];
+        const double* po = pb[(it + 1) % 2];
+        if (kt) kt->mark(LYAP_K_CG_DIR);
+        (k7 ? rbf_launch_dir<true> : rbf_launch_dir<false>)(st_, G, op_, g, rinv, db, z, po, pn, v, r, qv,
+                                                          log_.as<CgIter>(), it, state_.as<double>(),
+                                                          partA_.as<double>(), partZ_.as<double>(), zparts,
+                                                          partB_.as<double>());
+        if (kt) kt->mark(LYAP_K_CG_UPD);
+        hipLaunchKernelGGL((k_rbf_upd<NT>), dim3(G), dim3(NT), 0, st_, g, x, r, pn, qv, log_.as<CgIter>(), it,
+                           state_.as<double>(), partB_.as<double>(), G, partA_.as<double>(), flag_.as<int>());
+        LYAP_LAUNCHED("condensed fcg iteration");
+        if (kt) kt->mark(LYAP_K_PCNET);
+        zparts = net_->apply(r, z, qv, partZ_.as<double>());
+      }
+      if (kt) kt->collect();
+      LYAP_HIP(hipMemcpyAsync(hlog_.p, log_.as<CgIter>() + it0, (size_t)cnt * sizeof(CgIter), hipMemcpyDeviceToHost,
+                              st_));
+      LYAP_HIP(hipMemcpyAsync(htot_.as<char>() + 64 * sizeof(double), flag_.p, 8, hipMemcpyDeviceToHost, st_));
+      LYAP_HIP(hipMemcpyAsync(htot_.p, state_.p, sizeof(double), hipMemcpyDeviceToHost, st_));
+      LYAP_HIP(hipStreamSynchronize(st_));
+      const int* hf = reinterpret_cast<const int*>(htot_.as<char>() + 64 * sizeof(double));
+      LYAP_REQUIRE(hf[1] == 0, LYAP_E_INNER, "flexible CG breakdown (p^T Sigma p <= 0) at iteration %d", hf[1]);
+      const double thr = htot_.as<double>()[0];
+      const CgIter* lg = hlog_.as<CgIter>();
+      for (int c = 0; c < cnt && !done; ++c) {
+        LYAP_REQUIRE(std::isfinite(lg[c].rr[0]), LYAP_E_NUMERIC, "flexible CG produced a non-finite residual");
+        if (!(lg[c].rr[0] > thr)) {
+          done = true;
+          it = it0 + c;
+        }
+      }
+    }
+    total += it;
+    const int gf = grid_for(g.nb, 1, 1024);
+    if (k7)
+      hipLaunchKernelGGL((k_rb_finish<true, 1>), dim3(gf), dim3(kBlock), 0, st_, op_, g, B, r_.as<double>(), mode,
+                         rinv, x, X);
+    else
+      hipLaunchKernelGGL((k_rb_finish<false, 1>), dim3(gf), dim3(kBlock), 0, st_, op_, g, B, r_.as<double>(), mode,
+                         rinv, x, X);
+    LYAP_LAUNCHED("k_rb_finish");
+    cg_true(op_, B, X, r_.as<double>(), n_, 1, partA_.as<double>(), tot_.as<double>(), cgrid_, st_);
+    LYAP_HIP(hipMemcpyAsync(htot_.p, tot_.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st_));
+    LYAP_HIP(hipStreamSynchronize(st_));
+    const double* h = htot_.as<double>();
+    worst = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : 0.0;
+    LYAP_REQUIRE(std::isfinite(worst), LYAP_E_NUMERIC, "inner solve produced non-finite values");
+    if (worst <= eta_) {
+      stats_.iters += total;
+      stats_.solves += 1;
+      stats_.restarts += start;
+      stats_.worst_relres = std::max(stats_.worst_relres, worst);
+      stats_.ms += ms_since(t0);
+      return;
+    }
+    if (total >= max_iter_) break;
+  }
+  stats_.iters += total;
+  stats_.worst_relres = std::max(stats_.worst_relres, worst);
+  LYAP_REQUIRE(false, LYAP_E_INNER,
+               "flexible CG on the Schur complement did not reach the true relative residual %.1e in %d iterations",
+               eta_, total);
 }
 
 void InnerCG::solve_rb(const double* B, double* X, KernelTimer* kt) {

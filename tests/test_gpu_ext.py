@@ -226,7 +226,7 @@ def test_ek_full_size_100cubed(lib):
     assert sol.status == b.OK and sol.res <= 1e-8
     assert 30 <= sol.m <= 70 and sol.n_inner == sol.m + 1
     ex = _explicit_residual_gpu(b, dop, sol.Z, Cd) / sol.beta ** 2
-    assert ex <= 2e-8, ex
+    assert ex <= 1.2e-8, ex
     # T_m symmetric negative definite: dense from the band
     k = sol.T_band.shape[0]
     ell = sol.T_band.shape[1] - 1
@@ -240,8 +240,9 @@ def test_ek_full_size_100cubed(lib):
 
 def test_ek_full_size_learned_preconditioner(lib):
     """The full-size extended Krylov configuration with the learned inner
-    preconditioner (trained in the run): same acceptance as with Jacobi, every
-    inner solve certified, and fewer inner iterations than the Jacobi run."""
+    preconditioner (a correction of red-black IC(0) trained in the run): same
+    acceptance as with IC(0), every inner solve certified, fewer inner
+    iterations than IC(0) itself and than Jacobi."""
     b = _b()
     op = fv3d(100, 1.0, 3)
     C = gaussian_C(op.n, 1, 3)
@@ -251,7 +252,9 @@ def test_ek_full_size_learned_preconditioner(lib):
                        inner_tol=1e-12)
     assert sol.status == b.OK and sol.res <= 1e-8
     ex = _explicit_residual_gpu(b, dop, sol.Z, Cd) / sol.beta ** 2
-    assert ex <= 2e-8, ex
+    assert ex <= 1.2e-8, ex
+    ic0 = b.lyap_solve(dop, Cd, method=b.METHOD_EXT, tol=1e-8, check_every=0, inner_pc=b.PC_IC0, inner_tol=1e-12)
     jac = b.lyap_solve(dop, Cd, method=b.METHOD_EXT, tol=1e-8, check_every=0, inner_pc=b.PC_JACOBI, inner_tol=1e-12)
-    assert abs(sol.m - jac.m) <= 2
-    assert sol.inner_iters < jac.inner_iters
+    assert abs(sol.m - ic0.m) <= 2 and abs(sol.m - jac.m) <= 2
+    print(f"inner iterations: learned {sol.inner_iters}, IC(0) {ic0.inner_iters}, Jacobi {jac.inner_iters}")
+    assert sol.inner_iters < 0.5 * ic0.inner_iters and ic0.inner_iters < jac.inner_iters

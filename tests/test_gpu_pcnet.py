@@ -134,3 +134,65 @@ def test_learned_pc_errors(lib):
                      inner_pc=b.PC_LEARNED)
     with pytest.raises(b.LyapError):
         b.inner_solve(b.device_op(op), B[:, :1].contiguous(), inner_pc=b.PC_LEARNED)
+
+
+# ------------------------------------------------------------------ on IC(0)'s Schur complement
+from oracle import pcg as P  # noqa: E402
+
+
+@pytest.mark.parametrize("shape", [(12, 12, 12), (11, 10, 9)])   # hx = 6 and 6: padding slots in both
+def test_schur_train_parity(lib, shape):
+    """Pairs harvested from the condensed IC(0) CG and twenty Adam steps on
+    the black Schur complement, from the same initial weights, against the
+    oracle (oracle.cnn.harvest_condensed / train with Sigma)."""
+    b = _b()
+    nx, ny, nz = shape
+    op = fv3d(nx, 1.0, 3, Ny=ny, Nz=nz)
+    A = op.to_scipy()
+    sysm = P.rb_system(A, (op.nx, op.ny, op.nz))
+    g, Ap = N.condensed_grid(sysm), N.condensed_operator(sysm)
+    bvec = gaussian_C(op.n, 1, 3)[:, 0]
+    C = 2
+    W0 = b.pcnet_init(C, 0x5eed, 0.05)
+    W, losses, npairs = b.pcnet_schur_train(b.device_op(op), C, W0, _dev(bvec), every=3, keep=6, steps=20, lr=2e-3)
+    pairs, _ = N.harvest_condensed(sysm, bvec, every=3, keep=6)
+    pairs = [p for p in pairs if np.linalg.norm(p[1]) > 0]
+    assert npairs == len(pairs) == 6
+    net = _net_from(W0, C)
+    losses_ref = N.train(net, g, Ap, pairs, steps=20, lr=2e-3)
+    assert np.allclose(losses, losses_ref, rtol=1e-4), (losses[:4], losses_ref[:4])
+    assert np.linalg.norm(W - net.flat()) <= 1e-3 * np.linalg.norm(net.flat())
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (13, 12, 11)])
+def test_schur_fcg_parity(lib, shape):
+    """Flexible CG on the Schur complement with weights trained by the oracle:
+    certified solution, iteration count within a few of the oracle's, fewer
+    than IC(0) itself."""
+    b = _b()
+    nx, ny, nz = shape
+    op = fv3d(nx, 1.0, 3, Ny=ny, Nz=nz)
+    A = op.to_scipy()
+    grid = (op.nx, op.ny, op.nz)
+    sysm = P.rb_system(A, grid)
+    g, Ap = N.condensed_grid(sysm), N.condensed_operator(sysm)
+    pairs, _ = N.harvest_condensed(sysm, gaussian_C(op.n, 1, 3)[:, 0], every=4, keep=16)
+    pairs = [p for p in pairs if np.linalg.norm(p[1]) > 0]
+    C = 2
+    net = _net_from(b.pcnet_init(C, 0x5eed, 0.05), C)
+    N.train(net, g, Ap, pairs, steps=200, lr=2e-3)
+    W = net.flat().astype(np.float32)
+    b2 = gaussian_C(op.n, 1, 11)[:, 0]
+    X, it, rel, st = b.pcnet_schur_fcg(b.device_op(op), C, W, _dev(b2))
+    assert st == b.OK and rel <= 1e-12
+    Xh = X.cpu().numpy()
+    assert np.linalg.norm(A @ Xh - b2) <= 1e-12 * np.linalg.norm(b2)
+    ref = P.schur_rb_cg(A, b2, grid, eta=0.5e-12, system=sysm,
+                        precond=N.condensed_precond(_net_from(W, C), sysm, g))
+    ic0 = P.schur_rb_cg(A, b2, grid, eta=0.5e-12, system=sysm)
+    assert np.linalg.norm(Xh - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    assert abs(it - ref.iters) <= max(2, 0.05 * ref.iters), (it, ref.iters)
+    assert it < ic0.iters
+    # zero weights: IC(0)'s own iteration count
+    _, it0, rel0, st0 = b.pcnet_schur_fcg(b.device_op(op), C, np.zeros_like(W), _dev(b2))
+    assert st0 == b.OK and abs(it0 - ic0.iters) <= 1, (it0, ic0.iters)
