@@ -62,6 +62,14 @@ HBM_COUNTERS = {
     # k_cgcg_iter<1, 1024> of the extended Krylov run (inner Jacobi-PCG, FP64)
     ("cg_dir", 1000000, 1, "f64"): {"fetch_kib": 56843.59375, "write_kib": 39733.21875,
                                     "fetch_scale": 262144.0 / 131088.75, "write_scale": 1.0},
+    # the two sweeps of the red-black IC(0) condensed CG (k_rb_upd, k_rb_w), same run with --inner ic0
+    ("rb_upd", 1000000, 1, "f64"): {"fetch_kib": 37145.94, "write_kib": 24375.12,
+                                    "fetch_scale": 262144.0 / 131088.69, "write_scale": 1.0},
+    ("rb_w", 1000000, 1, "f64"): {"fetch_kib": 21554.12, "write_kib": 4074.50,
+                                  "fetch_scale": 262144.0 / 131088.69, "write_scale": 1.0},
+    # k_apply<float, 4> on the 4000 x 4000 grid (bench.py --workload spmm --grid 4000)
+    ("spmm", 16000000, 4, "f32"): {"fetch_kib": 132070.94, "write_kib": 257261.72,
+                                   "fetch_scale": 262144.0 / 131088.69, "write_scale": 1.0},
 }
 
 
@@ -92,11 +100,12 @@ def parse():
                     help="sylv workload: standard or extended Krylov spaces (ext: FP64, inner Jacobi-PCG)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run one plain 256 MiB device copy (reference for the HBM byte counters)")
-    ap.add_argument("--workload", choices=["c3", "std", "ext", "sylv", "batch", "e1", "e5", "smallb", "gen"],
+    ap.add_argument("--workload", choices=["c3", "std", "ext", "sylv", "batch", "e1", "e5", "smallb", "gen", "spmm"],
                     default="c3",
                     help="c3: extended Krylov on the 100^3 lognormal FV operator, learned vs IC(0) inner "
                          "preconditioner (the headline); "
                          "std: standard Krylov + two-pass on the 2D Laplacian; "
+                         "spmm: the operator application alone (5-point, FP32 n x 4, --grid N, default 4000); "
                          "ext: extended Krylov + inner PCG on the 100^3 lognormal finite-volume operator; "
                          "sylv: Sylvester, 700^2 Laplacian and 80^3 lognormal FV, s=2; "
                          "batch: 64 shifted Laplacians N_i in 64..512, s_i in {1,2,4}, grouped launches; "
@@ -105,7 +114,7 @@ def parse():
                          "gen: generalized A X E + E X A + C C^T = 0, P1 finite elements on N^2 nodes (N = 300)")
     args = ap.parse_args()
     if args.grid is None:
-        args.grid = 300 if args.workload == "gen" else 1000
+        args.grid = {"gen": 300, "spmm": 4000}.get(args.workload, 1000)
     if args.storage is None:
         args.storage = "f64" if args.workload == "smallb" else "f32"
     return args
@@ -740,7 +749,7 @@ def main_c3(args):
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": bpl,
                 "avg_launch_us": round(avg_ms * 1000.0, 2)}
 
-    def plain_roof(tab):
+    def plain_roof(tab, counters):
         out = {}
         for k in ("cg_dir", "cg_upd"):
             if k in tab and tab[k]["bytes_per_launch"] > 0:
@@ -748,7 +757,8 @@ def main_c3(args):
                 g = tab[k]["bytes_per_launch"] / (a * 1e-3) / 1e9
                 out[k] = {"bound": "hbm", "achieved": round(g, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(g / HBM_PEAK_GBS, 4), "bytes_per_launch": tab[k]["bytes_per_launch"],
-                          "avg_launch_us": round(a * 1000.0, 2)}
+                          "avg_launch_us": round(a * 1000.0, 2),
+                          "traffic": measured_traffic(counters.get(k, ""), op.n, 1, "f64")}
         return out
 
     def leg_result(name):
@@ -762,8 +772,8 @@ def main_c3(args):
                 "kernels": kernel_table(tables[name])}
 
     res = {name: leg_result(name) for name in legs}
-    res["ic0"]["inner_cg_roofline"] = plain_roof(tables["ic0"])
-    res["jacobi"]["inner_cg_roofline"] = plain_roof(tables["jacobi"])
+    res["ic0"]["inner_cg_roofline"] = plain_roof(tables["ic0"], {"cg_dir": "rb_upd", "cg_upd": "rb_w"})
+    res["jacobi"]["inner_cg_roofline"] = plain_roof(tables["jacobi"], {"cg_dir": "cg_dir"})
     out = {
         "metric": "time to rel. residual 1e-8 at n=1e6 (extended Krylov; learned-preconditioner inner solves, "
                   "training included, vs plain IC(0)-CG)",
@@ -831,9 +841,38 @@ def c3_extras(args, b, dev):
         g = by / (ms * 1e-3) / 1e9
         ex[f"spmm_laplace{Ng}_s4_f32"] = {"kernel": "k_apply", "bound": "hbm", "achieved": round(g, 1),
                                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(g / HBM_PEAK_GBS, 4),
-                                          "bytes_per_launch": by, "avg_launch_us": round(ms * 1000.0, 2)}
+                                          "bytes_per_launch": by, "avg_launch_us": round(ms * 1000.0, 2),
+                                          "traffic": measured_traffic("spmm", opg.n, 4, "f32")}
         del V
     return ex
+
+
+def main_spmm(args):
+    """W = A V alone: 5-point Laplacian on an N x N grid, FP32 n x s block,
+    back-to-back launches timed with HIP events (the SpMM figure of the
+    metric; N = 4000 streams 512 MB from HBM at s = 4)."""
+    import torch
+    from paper_1602_05033_amd import binding as b
+    from workloads import laplace2d
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    b.load()
+    dev = torch.device("cuda:0")
+    op = laplace2d(args.grid)
+    dop = b.device_op(op, device=dev)
+    V = torch.randn(op.n, args.s, device=dev, dtype=torch.float32)
+    reps = max(10, args.steps)
+    ms = b.op_apply_timed(dop, V, b.STORE_F32, reps)[1]
+    by = 2.0 * op.n * args.s * 4
+    g = by / (ms * 1e-3) / 1e9
+    print(json.dumps({"metric": "SpMM HBM GB/s (k_apply, 5-point, FP32)", "value": round(g, 1), "unit": "GB/s",
+                      "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": round(ms, 4), "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": f"W = A V, A = 5-point Laplacian {args.grid}^2 (n={op.n}), V n x {args.s}",
+                                 "n": op.n, "s": args.s},
+                      "roofline": {"bound": "hbm", "kernel": "k_apply", "achieved": round(g, 1), "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": round(g / HBM_PEAK_GBS, 4), "bytes_per_launch": by,
+                                   "avg_launch_us": round(ms * 1000.0, 2),
+                                   "traffic": measured_traffic("spmm", op.n, args.s, "f32")}}), flush=True)
 
 
 def main():
@@ -852,6 +891,8 @@ def main():
         return main_gen(args)
     if args.workload == "c3":
         return main_c3(args)
+    if args.workload == "spmm":
+        return main_spmm(args)
     if args.workload == "ext":
         return main_ext(args)
     if args.workload == "sylv":
