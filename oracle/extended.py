@@ -31,6 +31,10 @@ Readings taken where the paper leaves a choice (also in the design notes):
   sub-diagonal blocks below the ell-th subdiagonal, which vanish in exact
   arithmetic, are dropped when T_m is banded.
 * Solves with A are exact (sparse LU) unless a solver is passed in.
+* A rank-deficient C is deflated to C_r = C W_r (r columns) as in the
+  standard method's reading, and the space built on it; a start block
+  [C_r, A^{-1} C_r] that still loses rank (span(C_r) meets an invariant
+  subspace of A) is a breakdown.
 """
 from __future__ import annotations
 
@@ -41,7 +45,8 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .krylov import qr_pos, right_solve_upper, residual_alg3, trunc_eps, truncated_factor
+from .krylov import (qr_pos, right_solve_upper, residual_alg3, trunc_eps, truncated_factor,
+                     deflate_columns)
 
 
 def lu_solver(A):
@@ -97,14 +102,16 @@ class ExtResult:
 def lyap_ext(A, C: np.ndarray, tol: float = 1e-8, max_iter: int = 200,
              solve: Optional[Callable] = None, check_every: int = 1,
              check: Optional[Callable[[int], bool]] = None) -> ExtResult:
-    """Algorithm 1 over EK_m(A, C)."""
+    """Algorithm 1 over EK_m(A, C); a rank-deficient C runs on its deflated
+    columns C_r (C_r C_r^T = C C^T up to the dropped sigma_i^2), beta = ||C||_F."""
+    beta = float(np.linalg.norm(C))
+    C = deflate_columns(C)
     n, s = C.shape
     ell = 2 * s
     if solve is None:
         solve = lu_solver(A)
     if check is None:
         check = lambda m: (m % check_every) == 0  # noqa: E731
-    beta = float(np.linalg.norm(C))
     V1, gamma, _ = start_block(A, C, solve)
     basis = [V1]
     AV = []                       # A V_j for the projected matrix

@@ -22,6 +22,14 @@ Readings of the paper taken here (also listed in the design notes):
   factors tau_{j+1,j} below it (their transposes above).
 * Convergence is ||R_m||_F / beta^2 <= tol with beta = ||C||_F (Algorithm 1
   step 6.3).
+* Rank-deficient start block (the paper assumes a full-rank basis and leaves
+  deflation to the customary practice of block methods): the numerical rank r
+  of C is the number of eigenvalues sigma_i^2 of C^T C above 10 n eps sigma_1^2
+  (eps = 2^-52; the test a Gram matrix in floating point can make).
+  When r < s the method runs on C_r = U_r Sigma_r = C W_r from the SVD
+  C = U Sigma W^T, so that C_r C_r^T equals C C^T up to the dropped
+  sigma_i^2, with blocks of r columns.  beta stays ||C||_F.  A later block
+  that loses rank still ends the run (breakdown).
 * The truncation threshold is absolute in the paper with C normalised; here it
   is eps = min(1e-12, 0.05 tol / nu) beta^2 with nu = max|lambda_i(T_m)| +
   ||tau_{m+1,m}||_F >= ||T_m underline||_2, so that dropping Sigma_2 changes
@@ -48,6 +56,29 @@ def qr_pos(W: np.ndarray):
 def right_solve_upper(W: np.ndarray, R: np.ndarray) -> np.ndarray:
     """W R^{-1} for upper triangular R."""
     return sla.solve_triangular(R, W.T, trans="T", lower=False).T
+
+
+def numerical_rank(C: np.ndarray) -> int:
+    """Eigenvalues sigma_i^2 of C^T C above 10 n eps sigma_1^2 (eps = 2^-52,
+    machine epsilon), taken from the singular values of C."""
+    sv = np.linalg.svd(C, compute_uv=False)
+    if sv.shape[0] == 0 or sv[0] == 0.0:
+        return 0
+    lam = sv ** 2
+    return int(np.sum(lam > 10.0 * C.shape[0] * np.finfo(float).eps * lam[0]))
+
+
+def deflate_columns(C: np.ndarray) -> np.ndarray:
+    """C itself at full numerical rank; otherwise C_r = U_r Sigma_r (n x r)
+    from the SVD of C, so that C_r C_r^T is C C^T without the dropped
+    sigma_i^2.  A zero C raises ValueError (the solution is X = 0)."""
+    r = numerical_rank(C)
+    if r == 0:
+        raise ValueError("C is zero: the solution is X = 0")
+    if r == C.shape[1]:
+        return C
+    U, sv, _ = np.linalg.svd(C, full_matrices=False)
+    return U[:, :r] * sv[None, :r]
 
 
 # ----------------------------------------------------------------- Algorithm 2
@@ -209,10 +240,11 @@ def lyap_std(A, C: np.ndarray, tol: float = 1e-8, max_iter: int = 2000,
     (default: every ``check_every`` steps, as the paper's d).  The basis is
     stored only when ``two_pass`` is False (Algorithm 1 step 9); otherwise Z is
     accumulated in a second Lanczos pass from the logged coefficients."""
-    n, s = C.shape
     beta = float(np.linalg.norm(C))
-    _, gamma = qr_pos(C)
-    V1 = right_solve_upper(C, gamma)
+    Cr = deflate_columns(C)
+    n, s = Cr.shape
+    _, gamma = qr_pos(Cr)
+    V1 = right_solve_upper(Cr, gamma)
     if check is None:
         check = lambda m: (m % check_every) == 0  # noqa: E731
     Vprev = np.zeros_like(V1)
@@ -253,7 +285,7 @@ def lyap_std(A, C: np.ndarray, tol: float = 1e-8, max_iter: int = 2000,
     eps = trunc_eps(alg3.lam, records[m - 1].R, tol, beta)
     M, _ = truncated_factor(alg3.lam, alg3.Q, alg3.g, eps)
     if two_pass:
-        Z = two_pass_Z(A, C, gamma, records, M, m)
+        Z = two_pass_Z(A, V1, records, M, m)
     else:
         Z = np.concatenate(basis[:m], axis=1) @ M
     return LyapResult(Z=Z, m=m, t=M.shape[1], hist=hist, converged=converged, T=T,
@@ -261,12 +293,12 @@ def lyap_std(A, C: np.ndarray, tol: float = 1e-8, max_iter: int = 2000,
                       beta=beta, M=M, status=status, extra={"eps": eps})
 
 
-def two_pass_Z(A, C, gamma, records, M, m):
-    """Second Lanczos pass (Section 3.3): regenerate V_1..V_m from the logged
-    coefficients and accumulate Z = sum_i V_i E_i^T (Q Y-check), eq. (twopasseq)."""
-    s = C.shape[1]
-    V1 = right_solve_upper(C, gamma)
-    Z = np.zeros((C.shape[0], M.shape[1]))
+def two_pass_Z(A, V1, records, M, m):
+    """Second Lanczos pass (Section 3.3): regenerate V_1..V_m from the start
+    block and the logged coefficients and accumulate Z = sum_i V_i E_i^T
+    (Q Y-check), eq. (twopasseq)."""
+    s = V1.shape[1]
+    Z = np.zeros((V1.shape[0], M.shape[1]))
     Vprev = np.zeros_like(V1)
     Vcur = V1
     for i in range(1, m + 1):

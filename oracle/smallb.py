@@ -148,7 +148,7 @@ def sylv_small_b(A, B: np.ndarray, C1: np.ndarray, C2: np.ndarray, tol: float = 
     Y1, Y2, sv = tsvd_factors(ytilde(a5.lam, a5.Q, ups, G), eps)
     M1 = a5.Q @ Y1
     if two_pass:
-        Z1 = two_pass_Z(A, C1, gamma1, recs, M1, m)
+        Z1 = two_pass_Z(A, right_solve_upper(C1, gamma1), recs, M1, m)
     else:
         Z1 = np.concatenate(basis[:m], axis=1) @ M1
     Z2 = P @ Y2

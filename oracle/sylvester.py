@@ -184,8 +184,8 @@ def sylv_std(A, B, C1: np.ndarray, C2: np.ndarray, tol: float = 1e-8, max_iter: 
     eps = min(1e-12, 0.05 * tol / nu) * beta1 * beta2
     M1, M2, sv = tsvd_factors(alg4.lam, alg4.Q, alg4.ups, alg4.P, alg4.g1, alg4.g2, eps)
     if two_pass:
-        Z1 = two_pass_Z(A, C1, gamma1, sides[0]["recs"], M1, m)
-        Z2 = two_pass_Z(B, C2, gamma2, sides[1]["recs"], M2, m)
+        Z1 = two_pass_Z(A, right_solve_upper(C1, gamma1), sides[0]["recs"], M1, m)
+        Z2 = two_pass_Z(B, right_solve_upper(C2, gamma2), sides[1]["recs"], M2, m)
     else:
         Z1 = np.concatenate(sides[0]["basis"][:m], axis=1) @ M1
         Z2 = np.concatenate(sides[1]["basis"][:m], axis=1) @ M2
