@@ -41,8 +41,8 @@ typedef enum lyap_status {
   LYAP_OK = 0,               /* converged: ||R||_F / beta^2 <= tol            */
   LYAP_NOT_CONVERGED = 1,    /* max_iter reached; Z is from the last check     */
   LYAP_E_ARG = -1,           /* invalid argument (message says which)          */
-  LYAP_E_BREAKDOWN = -2,     /* rank-deficient block (C or W) with the residual
-                                still above tol; deflation is not implemented */
+  LYAP_E_BREAKDOWN = -2,     /* a block W loses rank with the residual still
+                                above tol (C itself is deflated by lyap_solve) */
   LYAP_E_INDEFINITE = -3,    /* a Ritz value >= 0: A is not negative definite  */
   LYAP_E_NUMERIC = -4,       /* NaN/Inf met (input or arithmetic)              */
   LYAP_E_INNER = -5,         /* an inner solve (extended Krylov) failed        */
@@ -205,7 +205,18 @@ typedef struct lyap_result {
  *        method EXT also needs FP64 storage and solves with A by the inner
  *        CG of lyap_inner_solve (opts->inner_pc, inner_tol, inner_max_iter).
  *  opts  may be NULL (defaults).
- *  out   filled on return (also on error, with status and history so far).
+ *  out   filled on return (also on error, with status and history so far);
+ *        out->s is the block width used (the numerical rank of C, below).
+ *
+ * A rank-deficient C is deflated (the paper takes a full-rank start block and
+ * leaves deflation to the customary practice of block methods): r is the
+ * number of eigenvalues of C^T C above 10 n eps lambda_max (eps = 2^-52; the
+ * Gram matrix is formed on the device in FP64, its eigenvalues on the host),
+ * and for r < s the method runs on C W_r, n x r, with W_r the eigenvectors of
+ * the r largest; (C W_r)(C W_r)^T is C C^T without the dropped eigenvalues.
+ * C = 0 gives LYAP_E_ARG (the solution is X = 0), NaN/Inf LYAP_E_NUMERIC; with
+ * method EXT an r other than 1, 2 or 4 gives LYAP_E_UNSUPPORTED.  The C passed
+ * in is only read; the deflated copy is freed on return.
  *
  * The residual is checked after m blocks when the schedule asks for it
  * (every d steps, or adaptively: spaced checks that tighten near the

@@ -261,6 +261,7 @@ class LyapSolution:
     n_inner: int = 0
     ell: int = 0
     kernels: dict = field(default_factory=dict)
+    s: int = 0           # block width used: the numerical rank of C
 
 
 TIME_KEYS = ["pass1", "checks", "final", "pass2", "inner", "train", "total", "to_tol"]
@@ -345,7 +346,7 @@ def _solution(r, st, alloc, n, device, msg) -> LyapSolution:
         hist_m=[r.hist_m[i] for i in range(r.n_hist)], hist_res=[r.hist_res[i] for i in range(r.n_hist)],
         times_ms={k_: r.times_ms[i] for i, k_ in enumerate(TIME_KEYS)}, n_checks=r.n_checks,
         trunc_eps=r.trunc_eps, bytes_pass1=r.bytes_pass1, bytes_spmm=r.bytes_spmm,
-        inner_iters=r.inner_iters, n_inner=r.n_inner, ell=ell,
+        inner_iters=r.inner_iters, n_inner=r.n_inner, ell=ell, s=r.s,
         kernels={name: {"ms": r.kern_ms[i], "n": r.kern_n[i], "bytes_per_launch": r.kern_bytes[i]}
                  for i, name in enumerate(KERNEL_KINDS) if r.kern_n[i] > 0})
     if r.T_band:

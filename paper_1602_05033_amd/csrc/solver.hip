@@ -6,7 +6,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <limits>
 #include <type_traits>
+#include <vector>
 
 #include "check.hpp"
 #include "lanczos.hpp"
@@ -480,6 +482,151 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
 template lyap_status solve_std<float>(const lyap_op*, const double*, int, int64_t, const lyap_opts&, lyap_result*);
 template lyap_status solve_std<double>(const lyap_op*, const double*, int, int64_t, const lyap_opts&, lyap_result*);
 
+// ------------------------------------------------------ rank-deficient start block
+// Gram matrix C^T C of an n x S column-major block: FP64 partials per
+// workgroup, summed in a fixed order by one workgroup.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_cols_gram(const double* __restrict__ C, int64_t ldc, int n,
+                                                      double* __restrict__ part) {
+  __shared__ double red[pow2_at_least(S * S) * (kBlock / 64)];
+  double acc[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) acc[i] = 0.0;
+  for (int r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
+    double c[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) c[i] = C[(size_t)i * ldc + r];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = 0; j < S; ++j) acc[i * S + j] = fma(c[i], c[j], acc[i * S + j]);
+  }
+  write_partial<S * S, kBlock>(acc, red, part);
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_cols_gram_sum(const double* __restrict__ part, int nparts,
+                                                          double* __restrict__ out) {
+  __shared__ double red[pow2_at_least(S * S) * (kBlock / 64)];
+  reduce_partials<S * S, kBlock>(part, nparts, red);
+  if (threadIdx.x < S * S) out[threadIdx.x] = red[threadIdx.x];
+}
+
+// Ce = C W: n x s times s x r (W row-major), Ce column-major with leading dimension n.
+__global__ __launch_bounds__(kBlock) void k_cols_mix(const double* __restrict__ C, int64_t ldc, int n, int s,
+                                                     const double* __restrict__ W, int r, double* __restrict__ Ce) {
+  for (int row = blockIdx.x * kBlock + threadIdx.x; row < n; row += gridDim.x * kBlock) {
+    double c[8];
+    for (int i = 0; i < s; ++i) c[i] = C[(size_t)i * ldc + row];
+    for (int j = 0; j < r; ++j) {
+      double acc = 0.0;
+      for (int i = 0; i < s; ++i) acc = fma(c[i], W[i * r + j], acc);
+      Ce[(size_t)j * n + row] = acc;
+    }
+  }
+}
+
+// Eigenvalues (descending) and eigenvectors (columns of V, row-major s x s) of
+// a small symmetric matrix by cyclic Jacobi rotations (host, s <= 8).
+static void sym_eig_jacobi(std::vector<double> G, int s, std::vector<double>& lam, std::vector<double>& V) {
+  std::vector<double> U((size_t)s * s, 0.0);
+  for (int i = 0; i < s; ++i) U[i * s + i] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < s; ++i)
+      for (int j = 0; j < s; ++j) {
+        tot += G[i * s + j] * G[i * s + j];
+        if (i != j) off += G[i * s + j] * G[i * s + j];
+      }
+    if (off <= 1e-36 * tot) break;
+    for (int p = 0; p < s; ++p)
+      for (int q = p + 1; q < s; ++q) {
+        const double apq = G[p * s + q];
+        if (apq == 0.0) continue;
+        const double theta = (G[q * s + q] - G[p * s + p]) / (2.0 * apq);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < s; ++k) {  // G <- G J
+          const double gp = G[k * s + p], gq = G[k * s + q];
+          G[k * s + p] = c * gp - sn * gq;
+          G[k * s + q] = sn * gp + c * gq;
+        }
+        for (int k = 0; k < s; ++k) {  // G <- J^T G
+          const double gp = G[p * s + k], gq = G[q * s + k];
+          G[p * s + k] = c * gp - sn * gq;
+          G[q * s + k] = sn * gp + c * gq;
+        }
+        for (int k = 0; k < s; ++k) {  // U <- U J
+          const double up = U[k * s + p], uq = U[k * s + q];
+          U[k * s + p] = c * up - sn * uq;
+          U[k * s + q] = sn * up + c * uq;
+        }
+      }
+  }
+  std::vector<int> ord(s);
+  for (int i = 0; i < s; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return G[a * s + a] > G[b * s + b]; });
+  lam.assign(s, 0.0);
+  V.assign((size_t)s * s, 0.0);
+  for (int j = 0; j < s; ++j) {
+    lam[j] = G[ord[j] * s + ord[j]];
+    for (int i = 0; i < s; ++i) V[i * s + j] = U[i * s + ord[j]];
+  }
+}
+
+// Numerical rank of C: the eigenvalues of C^T C above 10 n eps lambda_max
+// (eps = 2^-52).  The paper takes a full-rank start block and leaves
+// deflation to the customary practice of block methods; for r < s the solve
+// runs on Ce = C W_r (W_r the eigenvectors of the r largest eigenvalues), whose
+// Ce Ce^T is C C^T without the dropped eigenvalues.  Returns r (Ce untouched
+// when r = s); throws E_ARG for C = 0 and E_NUMERIC for NaN/Inf.
+int deflate_start(const double* C, int n, int s, int64_t ldc, hipStream_t st, DevBuf& Ce) {
+  const int grid = grid_for(n, 8, 1024);
+  DevBuf part((size_t)grid * s * s * sizeof(double)), tot((size_t)s * s * sizeof(double));
+  switch (s) {
+#define LYAP_GRAM_CASE(SS)                                                                                      \
+  case SS:                                                                                                      \
+    hipLaunchKernelGGL((k_cols_gram<SS>), dim3(grid), dim3(kBlock), 0, st, C, ldc, n, part.as<double>());       \
+    hipLaunchKernelGGL((k_cols_gram_sum<SS>), dim3(1), dim3(kBlock), 0, st, part.as<double>(), grid,            \
+                       tot.as<double>());                                                                       \
+    break;
+    LYAP_GRAM_CASE(1)
+    LYAP_GRAM_CASE(2)
+    LYAP_GRAM_CASE(3)
+    LYAP_GRAM_CASE(4)
+    LYAP_GRAM_CASE(5)
+    LYAP_GRAM_CASE(6)
+    LYAP_GRAM_CASE(7)
+    LYAP_GRAM_CASE(8)
+#undef LYAP_GRAM_CASE
+    default:
+      LYAP_REQUIRE(false, LYAP_E_ARG, "s=%d out of range 1..8", s);
+  }
+  LYAP_LAUNCHED("k_cols_gram");
+  std::vector<double> G((size_t)s * s);
+  LYAP_HIP(hipMemcpyAsync(G.data(), tot.p, G.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  LYAP_HIP(hipStreamSynchronize(st));
+  for (double g : G) LYAP_REQUIRE(std::isfinite(g), LYAP_E_NUMERIC, "C contains NaN or Inf");
+  std::vector<double> lam, V;
+  sym_eig_jacobi(G, s, lam, V);
+  LYAP_REQUIRE(lam[0] > 0.0, LYAP_E_ARG, "C is zero");
+  const double thr = 10.0 * n * std::numeric_limits<double>::epsilon() * lam[0];
+  int r = 0;
+  while (r < s && lam[r] > thr) ++r;
+  if (r == s) return s;
+  std::vector<double> Wr((size_t)s * r);
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < r; ++j) Wr[i * r + j] = V[i * s + j];
+  DevBuf Wd(Wr.size() * sizeof(double));
+  LYAP_HIP(hipMemcpyAsync(Wd.p, Wr.data(), Wr.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  Ce.alloc((size_t)n * r * sizeof(double));
+  hipLaunchKernelGGL(k_cols_mix, dim3(grid_for(n, 1, 2048)), dim3(kBlock), 0, st, C, ldc, n, s, Wd.as<double>(), r,
+                     Ce.as<double>());
+  LYAP_LAUNCHED("k_cols_mix");
+  LYAP_HIP(hipStreamSynchronize(st));  // Wd and the partials are released on return
+  return r;
+}
+
 }  // namespace lyap
 
 extern "C" lyap_status lyap_solve(const lyap_op* A, const double* C, int32_t s, int64_t ldc, const lyap_opts* opts,
@@ -505,6 +652,19 @@ extern "C" lyap_status lyap_solve(const lyap_op* A, const double* C, int32_t s, 
     LYAP_REQUIRE(o.check_every >= 0, LYAP_E_ARG, "check_every must be >= 0");
     LYAP_REQUIRE(o.storage == LYAP_STORE_F64 || o.storage == LYAP_STORE_F32, LYAP_E_ARG, "unknown storage %d",
                  o.storage);
+    LYAP_REQUIRE(o.method == LYAP_METHOD_STD || o.method == LYAP_METHOD_EXT, LYAP_E_ARG, "unknown method %d",
+                 o.method);
+    // a rank-deficient C runs on its deflated columns (r of them)
+    DevBuf Ce;
+    const int r = deflate_start(C, (int)A->n, s, ldc, (hipStream_t)o.stream, Ce);
+    if (r < s) {
+      LYAP_REQUIRE(o.method == LYAP_METHOD_STD || r == 1 || r == 2 || r == 4, LYAP_E_UNSUPPORTED,
+                   "C has numerical rank %d < s=%d; the extended Krylov kernels take blocks of 1, 2 or 4 columns",
+                   r, s);
+      C = Ce.as<double>();
+      ldc = A->n;
+      s = r;
+    }
     if (o.method == LYAP_METHOD_STD) {
       lyap_status st = o.storage == LYAP_STORE_F64 ? solve_std<double>(A, C, s, ldc, o, out)
                                                    : solve_std<float>(A, C, s, ldc, o, out);

@@ -272,15 +272,6 @@ def test_csr_matches_stencil(lib):
 
 
 # ------------------------------------------------------------------ failure handling
-def test_rank_deficient_C_is_breakdown(lib):
-    b = _b()
-    op = laplace2d(16)
-    C = gaussian_C(op.n, 2, 1)
-    C[:, 1] = C[:, 0]
-    sol = b.lyap_solve(b.device_op(op), _dev_C(C), raise_on_error=False)
-    assert sol.status == b.E_BREAKDOWN
-
-
 def test_positive_definite_operator_is_rejected(lib):
     b = _b()
     op = laplace2d(16)
