@@ -193,3 +193,55 @@ def test_sylv_ext_errors(lib):
             b.sylv_solve(dA, dB, _dev(gaussian_C(opA.n, s, 1)), _dev(gaussian_C(opB.n, s, 2)),
                          method=b.METHOD_EXT, **{"storage": b.STORE_F64, **kw})
         assert e.value.status == status
+
+
+# ------------------------------------------------------------------ the paper's Example 4 pair
+@pytest.mark.parametrize("s", [3, 8])
+def test_example4_against_oracle(lib, s):
+    """Section 6, Example 4 (Table 5): A and B from centred differences of
+    (exp(-xy) u_x)_x + (exp(xy) u_y)_y and (sin(xy) u_x)_x + (cos(xy) u_y)_y
+    on 128^2 points, uniform C1, C2 of unit norm, tol 1e-6, residual at every
+    step, FP64, two passes -- against the oracle's run of the same reading
+    (tests/golden/example4_oracle.json, written from oracle/ only).  The
+    paper's 217 / 145 iterations are not reproduced by this reading of the
+    operators (the oracle needs 311 / 238); parity is with the oracle."""
+    import json
+    import os
+    from workloads import fd2d_variable, uniform_C
+    b = _b()
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "example4_oracle.json")))
+    orc = gold["cases"][str(s)]
+    N = 128
+    opA = fd2d_variable(N, lambda x, y: np.exp(-x * y), lambda x, y: np.exp(x * y), "e4a")
+    opB = fd2d_variable(N, lambda x, y: np.sin(x * y), lambda x, y: np.cos(x * y), "e4b")
+    C1 = uniform_C(opA.n, s, 0)
+    C2 = uniform_C(opB.n, s, 1)
+    print(f"example 4 s={s}", flush=True)
+    sol = b.sylv_solve(b.device_op(opA), b.device_op(opB), _dev(C1), _dev(C2), tol=1e-6, check_every=1,
+                       storage=b.STORE_F64, two_pass=True)
+    assert sol.status == b.OK
+    assert sol.hist_m == list(range(1, sol.m + 1))
+    gh = dict(zip(sol.hist_m, sol.hist_res))
+    worst = 0.0
+    for m, res in orc["hist"]:
+        if m not in gh:
+            continue
+        dev = abs(gh[m] - res) / res
+        # bitwise-different rounding: tight while the bases are orthogonal,
+        # then the usual drift of two Lanczos runs
+        assert dev <= (1e-6 if m <= 40 else 0.15), (m, gh[m], res)
+        if m > 40:
+            worst = max(worst, dev)
+    print(f"  m {sol.m} (oracle {orc['m']}, paper {gold['paper_iterations'][str(s)]}), t {sol.t} "
+          f"(oracle {orc['t']}), late deviation {worst:.3f}")
+    assert abs(sol.m - orc["m"]) <= 2
+    Z1, Z2 = sol.Z1.cpu().numpy(), sol.Z2.cpu().numpy()
+    smp = np.array(orc["samples"])
+    ii, jj = smp[:, 0].astype(int), smp[:, 1].astype(int)
+    got = np.einsum("ka,ka->k", Z1[ii], Z2[jj])
+    dx = np.max(np.abs(got - smp[:, 2])) / orc["x_absmax_samples"]
+    print(f"  sampled X deviation {dx:.2e}")
+    assert dx <= 1e-6
+    ex = Y.explicit_residual(opA.to_scipy(), opB.to_scipy(), Z1, Z2, C1, C2) / (sol.beta1 * sol.beta2)
+    print(f"  explicit residual {ex:.3e}, reported {sol.res:.3e}")
+    assert ex <= 1.2e-6
