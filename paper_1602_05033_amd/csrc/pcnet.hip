@@ -315,13 +315,11 @@ __global__ __launch_bounds__(kPcThreads) void k_pc_tile(const float* __restrict_
   static_assert(MODE != 2 || NOUT == 2, "the output is formed from two channels");
   const int lb = xcd_block(blockIdx.x, tx * ty * tz);
   if (lb < 0) return;
-  __shared__ float sW[CO * CI * 27];
   __shared__ float sx[NIN * kQH];
   __shared__ double red[kPcThreads / 64];
   const int bx = lb % tx, by = (lb / tx) % ty, bz = lb / (tx * ty);
   const int x0 = bx * kQX, y0 = by * kQY, z0 = bz * kQZ;
   const int n = nx * ny * nz;
-  for (int e = threadIdx.x; e < CO * CI * 27; e += kPcThreads) sW[e] = W[e];
   // every thread loads its (at most three) halo-tile points before storing
   // any, so that all loads are in flight together
   constexpr int NST = (kQH + kPcThreads - 1) / kPcThreads;
@@ -376,7 +374,8 @@ __global__ __launch_bounds__(kPcThreads) void k_pc_tile(const float* __restrict_
           const float v = sx[c * kQH + idx];
 #pragma unroll
           for (int o = 0; o < NOUT; ++o) {
-            const float w = TRANS ? sW[(c * CI + o) * 27 + t] : sW[(o * CI + c) * 27 + t];
+            // uniform address: a scalar load, the weight an SGPR operand of the FMA
+            const float w = TRANS ? W[(c * CI + o) * 27 + t] : W[(o * CI + c) * 27 + t];
             acc[o] = fmaf(w, v, acc[o]);
           }
         }
