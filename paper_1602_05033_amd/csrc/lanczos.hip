@@ -57,8 +57,18 @@ __device__ __forceinline__ void apply_upper(const T (&w)[S], const double* __res
 
 template <int S>
 __device__ __forceinline__ void load_coef(const double* __restrict__ src, double (&dst)[S * S]) {
+  // the coefficients are the same for every lane: read them through the
+  // constant address space from a wave-uniform address, so that they become
+  // scalar loads (SGPR operands) also when the pointer was itself loaded from
+  // memory (the grouped kernels' descriptors), where it would otherwise be a
+  // generic pointer and the loads per-lane
+  const unsigned long long a = reinterpret_cast<unsigned long long>(src);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(a & 0xffffffffull));
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+  using cptr = const __attribute__((address_space(4))) double*;
+  const cptr c = (cptr)(((unsigned long long)hi << 32) | lo);
 #pragma unroll
-  for (int i = 0; i < S * S; ++i) dst[i] = src[i];
+  for (int i = 0; i < S * S; ++i) dst[i] = c[i];
 }
 
 // ------------------------------------------------------------------ kernels
@@ -568,7 +578,7 @@ __device__ __forceinline__ StepArgs<T> batch_args(const BatchDesc<T>& d, int j, 
 }
 
 template <typename T, int S>
-__global__ __launch_bounds__(stream_threads(S)) void kb_spmm_gram(const BatchDesc<T>* d, const int2* map, int j) {
+__global__ __launch_bounds__(stream_threads(S)) void kb_spmm_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j) {
   __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
   const int2 pm = map[blockIdx.x];
   const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, false);
@@ -577,7 +587,7 @@ __global__ __launch_bounds__(stream_threads(S)) void kb_spmm_gram(const BatchDes
 
 // mode 0: X = V_{j-1}, Y = V_j; 1: X = V_j, Y = V_{j-1}; 2: as 0; 3: X = V_j, Y = none
 template <typename T, int S>
-__global__ __launch_bounds__(stream_threads(S)) void kb_upd_gram(const BatchDesc<T>* d, const int2* map, int j,
+__global__ __launch_bounds__(stream_threads(S)) void kb_upd_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j,
                                                                  int mode, int slot, int flip) {
   __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
   const int2 pm = map[blockIdx.x];
@@ -588,7 +598,7 @@ __global__ __launch_bounds__(stream_threads(S)) void kb_upd_gram(const BatchDesc
 }
 
 template <typename T, int S>
-__global__ __launch_bounds__(stream_threads(S)) void kb_chol_gram(const BatchDesc<T>* d, const int2* map, int j) {
+__global__ __launch_bounds__(stream_threads(S)) void kb_chol_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j) {
   __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
   const int2 pm = map[blockIdx.x];
   const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, true);
@@ -596,7 +606,7 @@ __global__ __launch_bounds__(stream_threads(S)) void kb_chol_gram(const BatchDes
 }
 
 template <typename T, int S>
-__global__ __launch_bounds__(stream_threads(S)) void kb_chol_store(const BatchDesc<T>* d, const int2* map, int j) {
+__global__ __launch_bounds__(stream_threads(S)) void kb_chol_store(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j) {
   __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
   const int2 pm = map[blockIdx.x];
   const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, false);
@@ -606,7 +616,7 @@ __global__ __launch_bounds__(stream_threads(S)) void kb_chol_store(const BatchDe
 // Second pass step i of every problem in the map: V_{i+1} from V_i, V_{i-1}
 // and log entry i, in the problem's ring of R blocks.
 template <typename T, int S>
-__global__ __launch_bounds__(stream_threads(S)) void kb_replay(const BatchDesc<T>* d, const int2* map, int i) {
+__global__ __launch_bounds__(stream_threads(S)) void kb_replay(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int i) {
   const int2 pm = map[blockIdx.x];
   const BatchDesc<T>& b = d[pm.x];
   const size_t nS = (size_t)b.n * S;
