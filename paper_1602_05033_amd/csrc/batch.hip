@@ -19,8 +19,8 @@
 #include <cmath>
 #include <map>
 #include <memory>
-#include <tuple>
 #include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "check.hpp"
@@ -162,11 +162,13 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
   kt.on = o.profile != 0;
 
   // residual checks run on kCS extra streams (problem i on stream i mod kCS)
-  // while the grouped steps continue; with opts->profile on the solver's stream
-  constexpr int kCS = 4;
+  // while the grouped steps continue; with opts->profile on the solver's
+  // stream.  Three check streams and the solver's stream fill the four
+  // hardware queues a process gets by default.
+  constexpr int kCS = 3;
   const bool overlap = o.profile == 0;
   struct Streams {
-    hipStream_t s[kCS] = {nullptr, nullptr, nullptr, nullptr};
+    hipStream_t s[kCS] = {nullptr, nullptr, nullptr};
     ~Streams() { for (auto x : s) if (x) (void)hipStreamDestroy(x); }
   } cs;
   for (int i = 0; i < kCS; ++i) {
@@ -205,6 +207,11 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
     p->nparts = nparts_for(p->n, chunk);
     p->ck = std::make_unique<Checker>(p->S, p->S, cstream(i));
     p->sched = CheckSchedule{o.check_every, maxit};
+    // a check costs the host a few hundred launches, a grouped step a handful
+    // for all problems together: the batch checks less often (the next check
+    // at most m steps ahead, aimed at 0.9 of the predicted crossing)
+    p->sched.grow = 1.0;
+    p->sched.aim = 0.9;
     p->next_check = p->sched.first();
     out[i].n = p->n;
     out[i].s = p->S;
@@ -288,55 +295,44 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
   HostBuf hchk((size_t)count * sizeof(CheckOut));
   double check_ms = 0.0;
   constexpr int kAhead = 24;
+  // events: kAhead for the step throttle, one for "steps launched so far",
+  // one per problem for its check in flight
   struct EventRing {
     std::vector<hipEvent_t> ev;
     ~EventRing() { for (auto e : ev) (void)hipEventDestroy(e); }
   } er;
-  er.ev.resize(kAhead + 1 + kCS);
+  er.ev.resize(kAhead + 1 + 2 * count);
   for (auto& e : er.ev) LYAP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   hipEvent_t ev_step = er.ev[kAhead];
-  hipEvent_t* ev_cs = &er.ev[kAhead + 1];
-  bool pending = false;
-  std::vector<Problem<T>*> pend_chk;
-  std::vector<int> pend_mm;
+  hipEvent_t* ev_chk = &er.ev[kAhead + 1];
+  hipEvent_t* ev_start = &er.ev[kAhead + 1 + count];
+  // a problem's check is launched as soon as it is due (its stream waits for
+  // the steps launched so far) and processed as soon as its own event has
+  // completed, independently of the other problems' checks
+  std::vector<char> chk_pending(count, 0);
+  std::vector<int> chk_mm(count, 0);
+  int n_pending = 0;
   int n_active = count;
-  auto launch_checks = [&](const std::vector<Problem<T>*>& due, int j) {
-    LYAP_HIP(hipEventRecord(ev_step, st));
-    for (int i = 0; i < kCS; ++i)
-      if (overlap) LYAP_HIP(hipStreamWaitEvent(cs.s[i], ev_step, 0));
+  auto launch_check = [&](Problem<T>* p, int j) {
+    // the check reads T_m's band and the log up to step mm, written by the
+    // steps launched so far on the solver's stream
+    hipStream_t cq = cstream(p->id);
+    if (overlap) LYAP_HIP(hipEventRecord(ev_start[p->id], st));
     kt.mark(LYAP_K_CHECK);
-    pend_chk.clear();
-    pend_mm.clear();
-    for (Problem<T>* p : due) {
-      const int mm = std::min(p->next_check, j);
-      const size_t LS = log_stride(p->S);
-      hipStream_t cq = cstream(p->id);
-      p->ck->run(p->band.template as<double>(), mm * p->S, p->glog.template as<double>() + L_R * p->S * p->S,
-                 p->log.template as<double>() + (size_t)(mm - 1) * LS + L_R * p->S * p->S,
-                 chk.template as<CheckOut>() + p->id);
-      LYAP_HIP(hipMemcpyAsync(hchk.template as<CheckOut>() + p->id, chk.template as<CheckOut>() + p->id,
-                              sizeof(CheckOut), hipMemcpyDeviceToHost, cq));
-      LYAP_HIP(hipMemcpyAsync(hflags.template as<int>() + 16 * p->id, flags_all.template as<int>() + 16 * p->id,
-                              2 * sizeof(int), hipMemcpyDeviceToHost, cq));
-      pend_chk.push_back(p);
-      pend_mm.push_back(mm);
-    }
-    for (int i = 0; i < kCS; ++i) LYAP_HIP(hipEventRecord(ev_cs[i], overlap ? cs.s[i] : st));
-    pending = true;
-  };
-  auto checks_ready = [&]() {
-    for (int i = 0; i < kCS; ++i) {
-      const hipError_t q = hipEventQuery(ev_cs[i]);
-      if (q == hipErrorNotReady) return false;
-      LYAP_HIP(q);
-    }
-    return true;
-  };
-  auto wait_checks = [&]() {
-    const auto t0 = Clock::now();
-    for (int i = 0; i < kCS; ++i) LYAP_HIP(hipEventSynchronize(ev_cs[i]));
-    check_ms += ms_since(t0);
-    kt.collect();
+    const int mm = std::min(p->next_check, j);
+    if (overlap) LYAP_HIP(hipStreamWaitEvent(cq, ev_start[p->id], 0));
+    const size_t LS = log_stride(p->S);
+    p->ck->run(p->band.template as<double>(), mm * p->S, p->glog.template as<double>() + L_R * p->S * p->S,
+               p->log.template as<double>() + (size_t)(mm - 1) * LS + L_R * p->S * p->S,
+               chk.template as<CheckOut>() + p->id);
+    LYAP_HIP(hipMemcpyAsync(hchk.template as<CheckOut>() + p->id, chk.template as<CheckOut>() + p->id,
+                            sizeof(CheckOut), hipMemcpyDeviceToHost, cq));
+    LYAP_HIP(hipMemcpyAsync(hflags.template as<int>() + 16 * p->id, flags_all.template as<int>() + 16 * p->id,
+                            2 * sizeof(int), hipMemcpyDeviceToHost, cq));
+    LYAP_HIP(hipEventRecord(ev_chk[p->id], cq));
+    chk_pending[p->id] = 1;
+    chk_mm[p->id] = mm;
+    ++n_pending;
   };
   // a check at m on problem p's stream, waited for (breakdown re-checks)
   auto check_now = [&](Problem<T>* p, int mm) {
@@ -350,90 +346,103 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
                             sizeof(CheckOut), hipMemcpyDeviceToHost, cq));
     LYAP_HIP(hipStreamSynchronize(cq));
   };
-  auto process_checks = [&](int j) {
-    pending = false;
-    bool changed = false;
-    for (size_t q = 0; q < pend_chk.size(); ++q) {
-      Problem<T>* p = pend_chk[q];
-      int mm = pend_mm[q];
-      const int* f = hflags.template as<int>() + 16 * p->id;
-      LYAP_REQUIRE(!(f[1] > 0 && f[1] <= mm && (f[0] == 0 || f[1] <= f[0])), LYAP_E_NUMERIC,
-                   "problem %d: non-finite values at step %d", p->id, f[1]);
-      bool broke = false;
-      if (f[0] > 0 && f[0] <= mm) {
-        mm = f[0];
-        broke = true;
-        check_now(p, mm);
-      }
-      const CheckOut& c = hchk.template as<CheckOut>()[p->id];
-      LYAP_REQUIRE(std::isfinite(c.res), LYAP_E_NUMERIC, "problem %d: residual not finite", p->id);
-      LYAP_REQUIRE(c.lam_max < 0.0, LYAP_E_INDEFINITE, "problem %d: Ritz value %.3e >= 0", p->id, c.lam_max);
-      const double rel = c.res / (p->beta * p->beta);
-      p->hm.push_back(mm);
-      p->hr.push_back(rel);
-      p->last_res = rel;
-      p->checked_m = mm;
-      p->lam_absmax = std::max(std::fabs(c.lam_min), std::fabs(c.lam_max));
-      out[p->id].n_checks++;
-      if (o.verbose) std::fprintf(stderr, "[batch] problem %d m=%d res=%.3e\n", p->id, mm, rel);
-      if (rel <= o.tol) {
-        p->status = LYAP_OK;
-        p->m_final = mm;
-        p->active = false;
-        p->t_to_tol = ms_since(t_entry);
-      } else if (broke) {
-        p->status = LYAP_E_BREAKDOWN;
-        p->m_final = mm;
-        p->active = false;
-      } else if (mm >= maxit) {
-        p->m_final = mm;
-        p->active = false;
-      } else {
-        p->next_check = p->sched.next(mm, rel, o.tol);
-      }
-      if (!p->active) {
-        changed = true;
-        --n_active;
-      }
+  // the result of p's completed check; returns true when p left the active set
+  auto process_check = [&](Problem<T>* p) {
+    chk_pending[p->id] = 0;
+    --n_pending;
+    int mm = chk_mm[p->id];
+    const int* f = hflags.template as<int>() + 16 * p->id;
+    LYAP_REQUIRE(!(f[1] > 0 && f[1] <= mm && (f[0] == 0 || f[1] <= f[0])), LYAP_E_NUMERIC,
+                 "problem %d: non-finite values at step %d", p->id, f[1]);
+    bool broke = false;
+    if (f[0] > 0 && f[0] <= mm) {
+      mm = f[0];
+      broke = true;
+      check_now(p, mm);
     }
-    (void)j;
+    const CheckOut& c = hchk.template as<CheckOut>()[p->id];
+    LYAP_REQUIRE(std::isfinite(c.res), LYAP_E_NUMERIC, "problem %d: residual not finite", p->id);
+    LYAP_REQUIRE(c.lam_max < 0.0, LYAP_E_INDEFINITE, "problem %d: Ritz value %.3e >= 0", p->id, c.lam_max);
+    const double rel = c.res / (p->beta * p->beta);
+    p->hm.push_back(mm);
+    p->hr.push_back(rel);
+    p->last_res = rel;
+    p->checked_m = mm;
+    p->lam_absmax = std::max(std::fabs(c.lam_min), std::fabs(c.lam_max));
+    out[p->id].n_checks++;
+    if (o.verbose) std::fprintf(stderr, "[batch] problem %d m=%d res=%.3e\n", p->id, mm, rel);
+    if (rel <= o.tol) {
+      p->status = LYAP_OK;
+      p->m_final = mm;
+      p->active = false;
+      p->t_to_tol = ms_since(t_entry);
+    } else if (broke) {
+      p->status = LYAP_E_BREAKDOWN;
+      p->m_final = mm;
+      p->active = false;
+    } else if (mm >= maxit) {
+      p->m_final = mm;
+      p->active = false;
+    } else {
+      p->next_check = p->sched.next(mm, rel, o.tol);
+    }
+    if (!p->active) {
+      --n_active;
+      return true;
+    }
+    return false;
+  };
+  // process every completed check (all pending ones when wait is set)
+  auto poll_checks = [&](bool wait) {
+    bool changed = false;
+    for (auto& p : P) {
+      if (!chk_pending[p->id]) continue;
+      if (wait) {
+        const auto t0 = Clock::now();
+        LYAP_HIP(hipEventSynchronize(ev_chk[p->id]));
+        check_ms += ms_since(t0);
+      } else {
+        const hipError_t q = hipEventQuery(ev_chk[p->id]);
+        if (q == hipErrorNotReady) continue;
+        LYAP_HIP(q);
+      }
+      changed = process_check(p.get()) || changed;
+    }
     if (changed)
       for (auto& g : groups) upload(g, false, 0);
+    if (!overlap) kt.collect();
   };
 
   const auto t_pass1 = Clock::now();
   int j = 0;
   while (n_active > 0) {
-    if (pending) {
-      if (!overlap || j >= maxit || checks_ready()) {
-        wait_checks();
-        process_checks(j);
-        continue;
-      }
+    if (n_pending > 0) poll_checks(!overlap);
+    if (n_active == 0) break;
+    // launch the checks that are due now
+    for (auto& p : P) {
+      if (!p->active || chk_pending[p->id]) continue;
+      if (j >= p->next_check || j >= maxit) launch_check(p.get(), j);
     }
-    if (!pending) {
-      std::vector<Problem<T>*> due;
-      for (auto& p : P)
-        if (p->active && (j >= p->next_check || j >= maxit)) due.push_back(p.get());
-      if (!due.empty()) {
-        launch_checks(due, j);
-        continue;
-      }
-    }
+    if (!overlap && n_pending > 0) continue;
     if (j >= maxit) {
-      if (!pending) break;
+      // every remaining active problem has a check in flight: wait for them
+      if (n_pending > 0) poll_checks(true);
       continue;
     }
+    // a problem whose check is still in flight keeps stepping (its next check
+    // is decided when the result arrives)
     if (j >= kAhead) LYAP_HIP(hipEventSynchronize(er.ev[j % kAhead]));
     for (auto& g : groups)
-      launch_batch_step<T>(g.desc.template as<BatchDesc<T>>(), g.map.template as<int2>(), g.nwg, g.S, j, st, &kt);
+      if (g.nwg > 0)
+        launch_batch_step<T>(g.desc.template as<BatchDesc<T>>(), g.map.template as<int2>(), g.nwg, g.S, j, st, &kt);
     LYAP_HIP(hipEventRecord(er.ev[j % kAhead], st));
     ++j;
     for (auto& p : P)
       if (p->active) p->m = j;
   }
+  if (n_pending > 0) poll_checks(true);
   if (overlap)
-    for (int i = 0; i < kCS; ++i) LYAP_HIP(hipStreamWaitEvent(st, ev_cs[i], 0));
+    for (int i = 0; i < count; ++i) LYAP_HIP(hipStreamWaitEvent(st, ev_chk[i], 0));
   for (auto& p : P)
     if (p->m_final == 0) p->m_final = p->m;
   const double pass1_ms = ms_since(t_pass1) - check_ms;

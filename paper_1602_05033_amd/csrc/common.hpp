@@ -19,6 +19,7 @@ namespace lyap {
 // ------------------------------------------------------------------ errors
 void set_error(const char* fmt, ...);
 void clear_error();
+const char* last_error();
 
 struct Error {
   lyap_status st;

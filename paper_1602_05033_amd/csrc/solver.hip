@@ -59,16 +59,16 @@ int CheckSchedule::first() const {
 int CheckSchedule::next(int m, double res, double tol) {
   hist.emplace_back(m, std::log10(std::max(res, 1e-300)));
   if (d > 0) return std::min(m + d, max_iter);
-  const int grow = std::max(5, m / 2);
-  int nxt = m + grow;
+  const int grow_by = std::max(5, (int)(this->grow * m));
+  int nxt = m + grow_by;
   if (hist.size() >= 2) {
     const auto& a = hist[hist.size() - 2];
     const auto& b = hist[hist.size() - 1];
     const double slope = (b.second - a.second) / double(b.first - a.first);
     if (slope < 0) {
       const double gap = (std::log10(tol) - b.second) / slope;  // steps to the predicted crossing
-      const int step = (int)std::ceil(gap);
-      nxt = m + std::max(1, std::min(step, grow));
+      const int step = (int)std::ceil(aim * gap);
+      nxt = m + std::max(1, std::min(step, grow_by));
     }
   }
   return std::min(nxt, max_iter);

@@ -20,6 +20,10 @@ double ms_since(Clock::time_point t0);
 struct CheckSchedule {
   int d;
   int max_iter;
+  // adaptive schedule (d = 0): the next check is at most grow * m steps
+  // ahead, and aim times the predicted distance to the tolerance crossing
+  double grow = 0.5;
+  double aim = 1.0;
   std::vector<std::pair<int, double>> hist;
   int first() const;
   int next(int m, double res, double tol);

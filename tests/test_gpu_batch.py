@@ -66,19 +66,35 @@ def test_batched_parity_fp64(lib, tune):
 
 
 def test_batched_matches_single_problem_path(lib):
+    """With a fixed check schedule (every 4 steps) the batch reproduces the
+    single-problem path: the same check points, m and residuals, and Z Z^T.
+    With the adaptive schedule the batch checks less often by design (a check
+    costs the host a few hundred launches, a grouped step a handful for all
+    problems): its m may exceed the single path's by a few percent, and the
+    residuals agree wherever both checked."""
     b = _b()
     probs = _small_batch()[:4]
     dops = [b.device_op(op) for op, _ in probs]
     Cs = [_dev(C) for _, C in probs]
-    st, sols = b.lyap_solve_batched(dops, Cs, tol=1e-8, check_every=0, storage=b.STORE_F32)
+    st, sols = b.lyap_solve_batched(dops, Cs, tol=1e-8, check_every=4, storage=b.STORE_F32)
     assert st == b.OK
     for dop, C, sol in zip(dops, Cs, sols):
-        one = b.lyap_solve(dop, C, tol=1e-8, check_every=0, storage=b.STORE_F32)
+        one = b.lyap_solve(dop, C, tol=1e-8, check_every=4, storage=b.STORE_F32)
         assert sol.m == one.m and sol.hist_m == one.hist_m
         for a, c in zip(sol.hist_res, one.hist_res):
             assert abs(a - c) <= 1e-4 * c
         Za, Zb = sol.Z.cpu().numpy(), one.Z.cpu().numpy()
         assert K.factor_error(Za, Zb) <= 1e-6
+    st, sols = b.lyap_solve_batched(dops, Cs, tol=1e-8, check_every=0, storage=b.STORE_F32)
+    assert st == b.OK
+    for dop, C, sol in zip(dops, Cs, sols):
+        one = b.lyap_solve(dop, C, tol=1e-8, check_every=0, storage=b.STORE_F32)
+        assert sol.res <= 1e-8 and abs(sol.m - one.m) <= max(5, 0.1 * one.m), (sol.m, one.m)
+        common = dict(zip(one.hist_m, one.hist_res))
+        for m, r in zip(sol.hist_m, sol.hist_res):
+            if m in common:
+                assert abs(r - common[m]) <= 1e-4 * common[m]
+        assert K.factor_error(sol.Z.cpu().numpy(), one.Z.cpu().numpy()) <= 1e-5
 
 
 def test_batched_mixed_operators_and_errors(lib):
@@ -120,4 +136,5 @@ def test_batched_full_workload(lib):
         assert ex <= 2e-7, ex
     for i in (0, 17, 40, 63):
         one = b.lyap_solve(dops[i], Cs[i], tol=1e-8, storage=b.STORE_F32, check_every=0)
-        assert abs(one.m - sols[i].m) <= max(5, 0.05 * one.m)
+        # the batch's own check schedule (fewer checks) may stop a few percent later
+        assert abs(one.m - sols[i].m) <= max(5, 0.1 * one.m)
