@@ -466,18 +466,51 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
       p->hr.push_back(p->last_res);
       p->lam_absmax = std::max(std::fabs(c.lam_min), std::fabs(c.lam_max));
     }
-    std::vector<double> tau(S * S);
-    LYAP_HIP(hipMemcpy(tau.data(), p->log.template as<double>() + (size_t)(p->m_final - 1) * LS + L_R * S * S,
-                       S * S * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  // tau_{m+1,m} of every problem in one pass (for the truncation threshold)
+  HostBuf htau((size_t)count * 64 * sizeof(double));
+  for (auto& p : P) {
+    const int S = p->S;
+    LYAP_HIP(hipMemcpyAsync(htau.template as<double>() + 64 * p->id,
+                            p->log.template as<double>() + (size_t)(p->m_final - 1) * log_stride(S) + L_R * S * S,
+                            S * S * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  LYAP_HIP(hipStreamSynchronize(st));
+  // the problems are finalised side by side, each on its check stream: the
+  // pivoted Cholesky factorisations advance in turn (32 pivots per round, one
+  // wait per round for all of them), then every shifted solve and assembly
+  std::vector<std::unique_ptr<FinaliseJob>> jobs(count);
+  for (auto& p : P) {
+    const int S = p->S;
+    const double* tau = htau.template as<double>() + 64 * p->id;
     double tf = 0.0;
-    for (double v : tau) tf += v * v;
+    for (int i = 0; i < S * S; ++i) tf += tau[i] * tau[i];
     tf = std::sqrt(tf);
     const double b2 = p->beta * p->beta;
     double eps = o.trunc_eps;
     if (!(eps >= 0.0)) eps = std::min(1e-12, 0.05 * o.tol / (p->lam_absmax + tf)) * b2;
     out[p->id].trunc_eps = eps;
-    p->t = finalise_factor(*p->ck, p->band.template as<double>(), p->glog.template as<double>() + L_R * S * S, eps, p->M, st);
+    jobs[p->id] = std::make_unique<FinaliseJob>(*p->ck, p->band.template as<double>(),
+                                                p->glog.template as<double>() + L_R * S * S, eps, cstream(p->id));
   }
+  auto sync_checks = [&]() {
+    if (overlap)
+      for (int i = 0; i < kCS; ++i) LYAP_HIP(hipStreamSynchronize(cs.s[i]));
+    else
+      LYAP_HIP(hipStreamSynchronize(st));
+  };
+  for (;;) {
+    std::vector<int> launched;
+    for (auto& p : P)
+      if (jobs[p->id]->pchol_launch()) launched.push_back(p->id);
+    if (launched.empty()) break;
+    sync_checks();
+    for (int id : launched) jobs[id]->pchol_read();
+  }
+  for (auto& p : P) p->t = jobs[p->id]->launch_tail(p->M);
+  sync_checks();
+  for (auto& p : P) jobs[p->id]->finish();
+  jobs.clear();
   kt.collect();
   const double fin_ms = ms_since(t_fin);
 

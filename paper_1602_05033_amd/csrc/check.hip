@@ -2,6 +2,9 @@
 #include <algorithm>
 #include <cmath>
 
+#include <cstring>
+#include <memory>
+
 #include "check.hpp"
 #include "dc.hpp"
 
@@ -62,38 +65,86 @@ void Checker::run(const double* band, int k, const double* gamma, const double* 
                   counter_.as<unsigned>(), dev_out, st_);
 }
 
-int finalise_factor(const Checker& ck, const double* band, const double* gamma, double eps, DevBuf& M,
-                    hipStream_t st) {
-  const int k = ck.k();
-  const int ell = ck.ell();
-  const int tmax = std::min(k, 1024);
-  DevBuf d((size_t)k * sizeof(double));
-  DevBuf Lc((size_t)k * tmax * sizeof(double));
-  DevBuf piv((size_t)tmax * sizeof(int));
+struct FinaliseJob::Impl {
+  const Checker& ck;
+  const double* band;
+  const double* gamma;
+  hipStream_t st;
+  int k, ell, tmax, t = 0;
+  DevBuf d, Lc, piv, Lb, X, fail, B;
+  HostBuf hfail;
+  std::unique_ptr<PcholRun> pc;
+  Impl(const Checker& c) : ck(c) {}
+};
+
+FinaliseJob::FinaliseJob(const Checker& ck, const double* band, const double* gamma, double eps, hipStream_t st)
+    : w_(new Impl(ck)) {
+  Impl& w = *w_;
+  w.band = band;
+  w.gamma = gamma;
+  w.st = st;
+  w.k = ck.k();
+  w.ell = ck.ell();
+  w.tmax = std::min(w.k, 1024);
+  w.d.alloc((size_t)w.k * sizeof(double));
+  w.Lc.alloc((size_t)w.k * w.tmax * sizeof(double));
+  w.piv.alloc((size_t)w.tmax * sizeof(int));
   // Y~ ~= L L^T with trace(Y~ - L L^T) <= eps, hence ||Y~ - L L^T||_F <= eps
   // (the error bound of the paper's eigenvalue truncation, at a rank at most a
   // few columns above it)
-  const int t = run_pchol(ck.lam(), ck.g(), k, ell, eps, tmax, d.as<double>(), Lc.as<double>(), piv.as<int>(), st);
+  w.pc = std::make_unique<PcholRun>(ck.lam(), ck.g(), w.k, w.ell, eps, w.tmax, w.d.as<double>(), w.Lc.as<double>(),
+                                    w.piv.as<int>(), st);
+}
+
+FinaliseJob::~FinaliseJob() { delete w_; }
+
+bool FinaliseJob::pchol_launch() { return w_->pc->launch_chunk(); }
+void FinaliseJob::pchol_read() { w_->pc->read(); }
+bool FinaliseJob::pchol_finished() const { return w_->pc->finished(); }
+
+int FinaliseJob::launch_tail(DevBuf& M) {
+  Impl& w = *w_;
+  const int t = w.pc->t();
+  w.t = t;
   if (t <= 0) {
     M.alloc(8);
     return 0;
   }
-  LYAP_REQUIRE(t < tmax || tmax == k, LYAP_E_UNSUPPORTED, "truncation rank exceeds %d", tmax);
+  LYAP_REQUIRE(t < w.tmax || w.tmax == w.k, LYAP_E_UNSUPPORTED, "truncation rank exceeds %d", w.tmax);
   // Q L = Q Y~(:, P) L_PP^{-T}, with Q Y~(:, p) from a banded shifted solve
-  DevBuf Lb((size_t)(ell + 1) * k * t * sizeof(double));
-  DevBuf X((size_t)k * t * sizeof(double));
-  DevBuf fail(sizeof(int) * 4);
-  LYAP_HIP(hipMemsetAsync(fail.p, 0, sizeof(int) * 4, st));
-  launch_shift_solve(band, ell + 1, ell, k, ck.lam(), ck.g(), gamma, piv.as<int>(), t, Lb.as<double>(),
-                     X.as<double>(), fail.as<int>(), st);
-  DevBuf B((size_t)t * t * sizeof(double));
+  const int k = w.k, ell = w.ell;
+  w.Lb.alloc((size_t)(ell + 1) * k * t * sizeof(double));
+  w.X.alloc((size_t)k * t * sizeof(double));
+  w.fail.alloc(sizeof(int) * 4);
+  w.hfail.alloc(sizeof(int) * 4);
+  std::memset(w.hfail.p, 0, sizeof(int) * 4);
+  LYAP_HIP(hipMemsetAsync(w.fail.p, 0, sizeof(int) * 4, w.st));
+  launch_shift_solve(w.band, ell + 1, ell, k, w.ck.lam(), w.ck.g(), w.gamma, w.piv.as<int>(), t, w.Lb.as<double>(),
+                     w.X.as<double>(), w.fail.as<int>(), w.st);
+  w.B.alloc((size_t)t * t * sizeof(double));
   M.alloc((size_t)k * t * sizeof(double));
-  launch_assemble_M(Lc.as<double>(), k, piv.as<int>(), t, nullptr, t, X.as<double>(), nullptr, B.as<double>(),
-                    M.as<double>(), st);
-  int hfail = 0;
-  LYAP_HIP(hipMemcpyAsync(&hfail, fail.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  launch_assemble_M(w.Lc.as<double>(), k, w.piv.as<int>(), t, nullptr, t, w.X.as<double>(), nullptr, w.B.as<double>(),
+                    M.as<double>(), w.st);
+  LYAP_HIP(hipMemcpyAsync(w.hfail.p, w.fail.p, sizeof(int), hipMemcpyDeviceToHost, w.st));
+  return t;
+}
+
+void FinaliseJob::finish() {
+  Impl& w = *w_;
+  if (w.t <= 0) return;
+  LYAP_REQUIRE(*w.hfail.as<int>() == 0, LYAP_E_INDEFINITE, "shifted operator -(T + lambda I) not positive definite");
+}
+
+int finalise_factor(const Checker& ck, const double* band, const double* gamma, double eps, DevBuf& M,
+                    hipStream_t st) {
+  FinaliseJob job(ck, band, gamma, eps, st);
+  while (job.pchol_launch()) {
+    LYAP_HIP(hipStreamSynchronize(st));
+    job.pchol_read();
+  }
+  const int t = job.launch_tail(M);
   LYAP_HIP(hipStreamSynchronize(st));
-  LYAP_REQUIRE(hfail == 0, LYAP_E_INDEFINITE, "shifted operator -(T + lambda I) not positive definite");
+  job.finish();
   return t;
 }
 

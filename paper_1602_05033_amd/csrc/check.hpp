@@ -44,4 +44,26 @@ class Checker {
 int finalise_factor(const Checker& ck, const double* band, const double* gamma, double eps, DevBuf& M,
                     hipStream_t st);
 
+// The same finalisation in steps, so that several problems (each on its own
+// stream) can be finalised in turn by one host thread: pchol_launch() /
+// pchol_read() advance the pivoted Cholesky (false / finished when done),
+// launch_tail() queues the shifted solves and the assembly of M and returns
+// t, finish() checks the solves' failure flag once the stream has completed.
+class FinaliseJob {
+ public:
+  FinaliseJob(const Checker& ck, const double* band, const double* gamma, double eps, hipStream_t st);
+  ~FinaliseJob();
+  FinaliseJob(const FinaliseJob&) = delete;
+  FinaliseJob& operator=(const FinaliseJob&) = delete;
+  bool pchol_launch();
+  void pchol_read();
+  bool pchol_finished() const;
+  int launch_tail(DevBuf& M);
+  void finish();
+
+ private:
+  struct Impl;
+  Impl* w_;
+};
+
 }  // namespace lyap

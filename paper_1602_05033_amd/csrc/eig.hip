@@ -13,6 +13,7 @@
 //    lambda and g), the Gram matrix of its factor, banded shifted solves that
 //    give Q Y~(:,p) = -(T + lambda_p I)^{-1} E_1 gamma g_p^T without forming Q,
 //    and the small triangular/GEMM steps that assemble M = Q Y-check.
+#include <cstring>
 #include "eig.hpp"
 
 namespace lyap {
@@ -596,29 +597,90 @@ void launch_ctri_sum(const double* lam, const double* g, const double* Wm, int k
   LYAP_LAUNCHED("ctri_sum");
 }
 
-int run_pchol(const double* lam, const double* g, int k, int ell, double delta, int tmax, double* d, double* Lc,
-              int* piv, hipStream_t st) {
-  const int grid = std::max(1, std::min((k + kPcThreads - 1) / kPcThreads, 256));
-  DevBuf pvA(grid * sizeof(double)), pvB(grid * sizeof(double)), psA(grid * sizeof(double)),
-      psB(grid * sizeof(double)), piA(grid * sizeof(int)), piB(grid * sizeof(int)), stt(sizeof(PcState));
-  hipLaunchKernelGGL(k_pchol_init, dim3(grid), dim3(kPcThreads), 0, st, lam, g, k, ell, d, pvA.as<double>(),
-                     piA.as<int>(), psA.as<double>(), stt.as<PcState>());
-  PcState h{};
-  for (int r = 0; r < tmax; ++r) {
-    const bool even = (r % 2) == 0;
-    hipLaunchKernelGGL(k_pchol_step, dim3(grid), dim3(kPcThreads), 0, st, lam, g, k, ell, delta, r, d, Lc, piv,
-                       even ? pvA.as<double>() : pvB.as<double>(), even ? piA.as<int>() : piB.as<int>(),
-                       even ? psA.as<double>() : psB.as<double>(), grid, even ? pvB.as<double>() : pvA.as<double>(),
-                       even ? piB.as<int>() : piA.as<int>(), even ? psB.as<double>() : psA.as<double>(),
-                       stt.as<PcState>());
-    if ((r + 1) % 32 == 0 || r + 1 == tmax) {
-      LYAP_HIP(hipMemcpyAsync(&h, stt.p, sizeof(PcState), hipMemcpyDeviceToHost, st));
-      LYAP_HIP(hipStreamSynchronize(st));
-      if (h.stop) break;
-    }
+struct PcholRun::Impl {
+  const double* lam;
+  const double* g;
+  int k, ell, tmax, grid, r = 0;
+  double delta;
+  double* d;
+  double* Lc;
+  int* piv;
+  hipStream_t st;
+  DevBuf pvA, pvB, psA, psB, piA, piB, stt;
+  HostBuf hst;
+  bool finished = false;
+  int t = 0;
+};
+
+PcholRun::PcholRun(const double* lam, const double* g, int k, int ell, double delta, int tmax, double* d, double* Lc,
+                   int* piv, hipStream_t st)
+    : w_(new Impl) {
+  Impl& w = *w_;
+  w.lam = lam;
+  w.g = g;
+  w.k = k;
+  w.ell = ell;
+  w.tmax = tmax;
+  w.delta = delta;
+  w.d = d;
+  w.Lc = Lc;
+  w.piv = piv;
+  w.st = st;
+  w.grid = std::max(1, std::min((k + kPcThreads - 1) / kPcThreads, 256));
+  const int grid = w.grid;
+  w.pvA.alloc(grid * sizeof(double));
+  w.pvB.alloc(grid * sizeof(double));
+  w.psA.alloc(grid * sizeof(double));
+  w.psB.alloc(grid * sizeof(double));
+  w.piA.alloc(grid * sizeof(int));
+  w.piB.alloc(grid * sizeof(int));
+  w.stt.alloc(sizeof(PcState));
+  w.hst.alloc(sizeof(PcState));
+  std::memset(w.hst.p, 0, sizeof(PcState));
+  hipLaunchKernelGGL(k_pchol_init, dim3(grid), dim3(kPcThreads), 0, st, lam, g, k, ell, d, w.pvA.as<double>(),
+                     w.piA.as<int>(), w.psA.as<double>(), w.stt.as<PcState>());
+  LYAP_LAUNCHED("pchol init");
+  if (tmax <= 0) w.finished = true;
+}
+
+PcholRun::~PcholRun() { delete w_; }
+
+bool PcholRun::launch_chunk() {
+  Impl& w = *w_;
+  if (w.finished) return false;
+  // pivot steps up to the next multiple of 32 (or tmax), then the state
+  const int end = std::min(w.tmax, (w.r / 32 + 1) * 32);
+  for (; w.r < end; ++w.r) {
+    const bool even = (w.r % 2) == 0;
+    hipLaunchKernelGGL(k_pchol_step, dim3(w.grid), dim3(kPcThreads), 0, w.st, w.lam, w.g, w.k, w.ell, w.delta, w.r, w.d,
+                       w.Lc, w.piv, even ? w.pvA.as<double>() : w.pvB.as<double>(),
+                       even ? w.piA.as<int>() : w.piB.as<int>(), even ? w.psA.as<double>() : w.psB.as<double>(),
+                       w.grid, even ? w.pvB.as<double>() : w.pvA.as<double>(), even ? w.piB.as<int>() : w.piA.as<int>(),
+                       even ? w.psB.as<double>() : w.psA.as<double>(), w.stt.as<PcState>());
   }
   LYAP_LAUNCHED("pchol");
-  return h.t;
+  LYAP_HIP(hipMemcpyAsync(w.hst.p, w.stt.p, sizeof(PcState), hipMemcpyDeviceToHost, w.st));
+  return true;
+}
+
+void PcholRun::read() {
+  Impl& w = *w_;
+  const PcState& h = *w.hst.as<PcState>();
+  w.t = h.t;
+  if (h.stop || w.r >= w.tmax) w.finished = true;
+}
+
+bool PcholRun::finished() const { return w_->finished; }
+int PcholRun::t() const { return w_->t; }
+
+int run_pchol(const double* lam, const double* g, int k, int ell, double delta, int tmax, double* d, double* Lc,
+              int* piv, hipStream_t st) {
+  PcholRun run(lam, g, k, ell, delta, tmax, d, Lc, piv, st);
+  while (run.launch_chunk()) {
+    LYAP_HIP(hipStreamSynchronize(st));
+    run.read();
+  }
+  return run.t();
 }
 
 void launch_gram_cols(const double* Lc, int k, int tp, double* G, hipStream_t st) {

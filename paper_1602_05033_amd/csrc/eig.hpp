@@ -24,6 +24,26 @@ void launch_ctri_sum(const double* lam, const double* g, const double* Wm, int k
 // number of columns formed (<= tmax).  Lc: k x tmax column-major, piv: tmax.
 int run_pchol(const double* lam, const double* g, int k, int ell, double delta, int tmax, double* d, double* Lc,
               int* piv, hipStream_t st);
+// The same factorisation driven step by step, so that the host can advance
+// several of them (on different streams) in turn: launch_chunk() queues up to
+// 32 pivot steps and the copy of the state to host memory (false once
+// finished); read() takes that state after the stream has passed the copy.
+class PcholRun {
+ public:
+  PcholRun(const double* lam, const double* g, int k, int ell, double delta, int tmax, double* d, double* Lc,
+           int* piv, hipStream_t st);
+  ~PcholRun();
+  PcholRun(const PcholRun&) = delete;
+  PcholRun& operator=(const PcholRun&) = delete;
+  bool launch_chunk();
+  void read();
+  bool finished() const;
+  int t() const;
+
+ private:
+  struct Impl;
+  Impl* w_;
+};
 void launch_gram_cols(const double* Lc, int k, int tp, double* G, hipStream_t st);
 void launch_shift_solve(const double* band, int ldb, int ell, int k, const double* lam, const double* g,
                         const double* gamma, const int* piv, int tp, double* Lb, double* X, int* fail,
