@@ -17,7 +17,9 @@ Checker::~Checker() { delete static_cast<DcWork*>(dc_); }
 
 void Checker::ensure(int k) {
   if (k <= cap_) return;
-  int cap = std::max(k, cap_ * 3 / 2);
+  // geometric growth by 4 from 1024 rows: each reallocation frees the old
+  // buffers, and a free waits for the device
+  int cap = std::max({k, cap_ * 4, 1024});
   cap = (cap + 255) / 256 * 256;
   lam_.alloc((size_t)cap * sizeof(double));
   F_.alloc((size_t)cap * ell_ * sizeof(double));
