@@ -245,11 +245,25 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
   for (auto& p : P)
     if (std::find(widths.begin(), widths.end(), p->S) == widths.end()) widths.push_back(p->S);
   std::sort(widths.begin(), widths.end());
+  // descriptors and work map of one block width; updated in stream order
+  // from pinned staging (two slots, each reused once its previous copy has
+  // executed), so the host never waits for the steps in flight
   struct Group {
     int S;
     std::vector<Problem<T>*> probs;
     DevBuf desc, map;
+    HostBuf hdesc[2], hmap[2];
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool ev_used[2] = {false, false};
+    int slot = 0;
     int nwg = 0;
+    Group() = default;
+    Group(const Group&) = delete;
+    Group& operator=(const Group&) = delete;
+    ~Group() {
+      for (auto e : ev)
+        if (e) (void)hipEventDestroy(e);
+    }
   };
   std::vector<Group> groups(widths.size());
   for (size_t g = 0; g < widths.size(); ++g) {
@@ -258,11 +272,28 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
       if (p->S == widths[g]) groups[g].probs.push_back(p.get());
   }
   auto upload = [&](Group& g, bool replay, int step) {
-    std::vector<BatchDesc<T>> d(g.probs.size());
-    std::vector<int2> map;
+    if (!g.desc.p) {  // sized once: every problem of the group, every workgroup of each
+      size_t wgs = 0;
+      for (Problem<T>* p : g.probs) wgs += p->nparts;
+      wgs = std::max<size_t>(wgs, 1);
+      g.desc.alloc(g.probs.size() * sizeof(BatchDesc<T>));
+      g.map.alloc(wgs * sizeof(int2));
+      for (int sl = 0; sl < 2; ++sl) {
+        g.hdesc[sl].alloc(g.probs.size() * sizeof(BatchDesc<T>));
+        g.hmap[sl].alloc(wgs * sizeof(int2));
+        LYAP_HIP(hipEventCreateWithFlags(&g.ev[sl], hipEventDisableTiming));
+      }
+    }
+    const int sl = g.slot;
+    g.slot ^= 1;
+    if (g.ev_used[sl]) LYAP_HIP(hipEventSynchronize(g.ev[sl]));  // its previous copies have executed
+    BatchDesc<T>* d = g.hdesc[sl].template as<BatchDesc<T>>();
+    int2* map = g.hmap[sl].template as<int2>();
+    int nmap = 0;
     for (size_t q = 0; q < g.probs.size(); ++q) {
       Problem<T>* p = g.probs[q];
       BatchDesc<T>& b = d[q];
+      b = BatchDesc<T>{};
       b.op = p->op.dev;
       b.n = p->n;
       b.nparts = p->nparts;
@@ -279,15 +310,14 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
       b.zero = p->zero.template as<T>();
       const bool take = replay ? (step + 1 < p->m_final) : p->active;
       if (take)
-        for (int w = 0; w < p->nparts; ++w) map.push_back(make_int2((int)q, w));
+        for (int w = 0; w < p->nparts; ++w) map[nmap++] = make_int2((int)q, w);
     }
-    LYAP_HIP(hipStreamSynchronize(st));  // the previous descriptors / map may still be read
-    if (g.desc.bytes < d.size() * sizeof(BatchDesc<T>)) g.desc.alloc(d.size() * sizeof(BatchDesc<T>));
-    if (g.map.bytes < std::max<size_t>(1, map.size()) * sizeof(int2))
-      g.map.alloc(std::max<size_t>(1, map.size()) * sizeof(int2));
-    LYAP_HIP(hipMemcpy(g.desc.p, d.data(), d.size() * sizeof(BatchDesc<T>), hipMemcpyHostToDevice));
-    if (!map.empty()) LYAP_HIP(hipMemcpy(g.map.p, map.data(), map.size() * sizeof(int2), hipMemcpyHostToDevice));
-    g.nwg = (int)map.size();
+    // in stream order: the steps launched before read the previous contents
+    LYAP_HIP(hipMemcpyAsync(g.desc.p, d, g.probs.size() * sizeof(BatchDesc<T>), hipMemcpyHostToDevice, st));
+    if (nmap > 0) LYAP_HIP(hipMemcpyAsync(g.map.p, map, nmap * sizeof(int2), hipMemcpyHostToDevice, st));
+    LYAP_HIP(hipEventRecord(g.ev[sl], st));
+    g.ev_used[sl] = true;
+    g.nwg = nmap;
   };
   for (auto& g : groups) upload(g, false, 0);
 
@@ -620,6 +650,10 @@ extern "C" lyap_status lyap_solve_batched(int32_t count, const lyap_op* A, const
     LYAP_REQUIRE(o.two_pass != 0, LYAP_E_UNSUPPORTED, "the batched solver uses the two-pass strategy");
     LYAP_REQUIRE(o.storage == LYAP_STORE_F64 || o.storage == LYAP_STORE_F32, LYAP_E_ARG, "unknown storage %d",
                  o.storage);
+    // the per-problem buffers (a few thousand, most of them small) come from
+    // the device block cache and go back to it: every buffer is released
+    // after the streams that use it have been synchronised
+    BlockCacheScope cache;
     return o.storage == LYAP_STORE_F64 ? batched_impl<double>(count, A, C, s, ldc, o, tune, out)
                                        : batched_impl<float>(count, A, C, s, ldc, o, tune, out);
   } catch (const Error& e) {

@@ -9,7 +9,11 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <exception>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "lyap.h"
@@ -72,20 +76,87 @@ struct ArenaScope {
   Arena* prev_;
 };
 
-// Owning device buffer (hipMalloc / hipFree, or a slice of the installed
-// Arena).  Sizes in bytes.
+// Device block cache.  While a BlockCacheScope is installed on the calling
+// thread, DevBuf takes its memory from a process-wide cache of released blocks
+// (per device, sizes rounded up to a quarter of their power of two) and gives
+// it back there instead of calling hipMalloc / hipFree, which are slow and
+// make the device wait.  Code that installs the scope must release a buffer
+// only once no kernel can still use it (the guarantee hipFree's wait would
+// otherwise give); during exception unwinding blocks are freed for real.
+class BlockCache {
+ public:
+  static BlockCache& get() {
+    static BlockCache c;
+    return c;
+  }
+  static size_t size_class(size_t b) {
+    size_t c = 4096;
+    while (c < b) c <<= 1;
+    if (c > 16384) {  // quarters of the power of two
+      const size_t q = c / 8;
+      size_t r = c / 2;
+      while (r < b) r += q;
+      c = r;
+    }
+    return c;
+  }
+  void* take(int dev, size_t cls) {
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = free_.find(std::make_pair(dev, cls));
+    if (it == free_.end()) return nullptr;
+    void* p = it->second;
+    free_.erase(it);
+    held_ -= cls;
+    return p;
+  }
+  // false: the cache is full, the caller frees the block
+  bool give(int dev, size_t cls, void* p) {
+    std::lock_guard<std::mutex> g(mu_);
+    if (held_ + cls > kMaxHeld) return false;
+    free_.emplace(std::make_pair(dev, cls), p);
+    held_ += cls;
+    return true;
+  }
+
+ private:
+  static constexpr size_t kMaxHeld = size_t(8) << 30;  // bytes kept for reuse
+  std::mutex mu_;
+  std::multimap<std::pair<int, size_t>, void*> free_;
+  size_t held_ = 0;
+};
+
+inline bool& block_cache_on() {
+  static thread_local bool on = false;
+  return on;
+}
+
+struct BlockCacheScope {
+  BlockCacheScope() : prev_(block_cache_on()) { block_cache_on() = true; }
+  ~BlockCacheScope() { block_cache_on() = prev_; }
+  BlockCacheScope(const BlockCacheScope&) = delete;
+  BlockCacheScope& operator=(const BlockCacheScope&) = delete;
+
+ private:
+  bool prev_;
+};
+
+// Owning device buffer (hipMalloc / hipFree, a block of the BlockCache, or a
+// slice of the installed Arena).  Sizes in bytes.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   bool borrowed = false;  // slice of an Arena: never freed
+  size_t cached = 0;      // size class of a BlockCache block (0: own allocation)
+  int dev = 0;
   DevBuf() = default;
   explicit DevBuf(size_t b) { alloc(b); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), borrowed(o.borrowed) {
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), borrowed(o.borrowed), cached(o.cached), dev(o.dev) {
     o.p = nullptr;
     o.bytes = 0;
     o.borrowed = false;
+    o.cached = 0;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
@@ -93,9 +164,12 @@ struct DevBuf {
       p = o.p;
       bytes = o.bytes;
       borrowed = o.borrowed;
+      cached = o.cached;
+      dev = o.dev;
       o.p = nullptr;
       o.bytes = 0;
       o.borrowed = false;
+      o.cached = 0;
     }
     return *this;
   }
@@ -115,19 +189,36 @@ struct DevBuf {
       borrowed = true;
       return;
     }
-    hipError_t e = hipMalloc(&p, b);
+    size_t req = b;
+    if (block_cache_on()) {
+      (void)hipGetDevice(&dev);
+      req = BlockCache::size_class(b);
+      p = BlockCache::get().take(dev, req);
+      if (p) {
+        bytes = b;
+        cached = req;
+        return;
+      }
+    }
+    hipError_t e = hipMalloc(&p, req);
     if (e != hipSuccess) {
       p = nullptr;
-      set_error("hipMalloc(%zu bytes) failed: %s", b, hipGetErrorString(e));
+      set_error("hipMalloc(%zu bytes) failed: %s", req, hipGetErrorString(e));
       throw Error{LYAP_E_NOMEM};
     }
     bytes = b;
+    cached = block_cache_on() ? req : 0;
   }
   void release() {
-    if (p && !borrowed) (void)hipFree(p);
+    if (p && !borrowed) {
+      // a cached block goes back to the cache, except while an exception
+      // unwinds (work may still be in flight: hipFree waits for it)
+      if (!(cached && std::uncaught_exceptions() == 0 && BlockCache::get().give(dev, cached, p))) (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
     borrowed = false;
+    cached = 0;
   }
   template <typename U> U* as() const { return static_cast<U*>(p); }
 };
