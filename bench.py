@@ -740,13 +740,14 @@ def main_c3(args):
     if dom == "pcnet":
         flops = PCNET_FLOPS_PER_POINT * pcnet_points(op.nx, op.ny, op.nz)
         tf = flops / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": "pcnet (k_pc_conv4_r, k_pc_conv4 x2, k_pc_conv4_out)",
+        roof = {"bound": "alu", "kernel": "pcnet (four k_pc_tile convolutions, the flexible-CG update fused into the first)",
                 "achieved": round(tf, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
                 "flops_per_launch": flops, "bytes_per_launch": agg[dom]["bytes_per_launch"],
                 "avg_launch_us": round(avg_ms * 1000.0, 2),
-                "note": "FP32 multiply-adds of the four convolutions of one network application; the peak counts "
-                        "packed FP32, which this build does not emit (the non-packed rate is half of it)"}
+                "note": "FP32 multiply-adds of the four convolutions of one network application (the x, r update "
+                        "fused into the first adds HBM bytes, no flops counted); the peak counts packed FP32, which "
+                        "this build does not emit (the non-packed rate is half of it)"}
     else:
         bpl = agg[dom]["bytes_per_launch"]
         gbs = bpl / (avg_ms * 1e-3) / 1e9

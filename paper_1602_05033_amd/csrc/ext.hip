@@ -589,7 +589,9 @@ lyap_status ext_impl(const lyap_op* A, const double* C, int64_t ldc, const lyap_
     // whole grid; IC(0): the condensed iteration on the black cells)
     out->kern_bytes[LYAP_K_CG_DIR] = cg.iter_bytes();
     out->kern_bytes[LYAP_K_CG_UPD] = cg.upd_bytes();
-    if (net) out->kern_bytes[LYAP_K_PCNET] = net->apply_bytes();
+    // on the Schur complement the x, r update runs inside the network's first
+    // convolution (x, r, p, q in; x, r out at the black slots)
+    if (net) out->kern_bytes[LYAP_K_PCNET] = net->apply_bytes() + cg.upd_bytes();
   }
   out->status = status;
   return status;

@@ -441,6 +441,7 @@ static void cg_launch_true(const OpDev<double>& op, const double* B, const doubl
 }
 
 double InnerCG::upd_bytes() const {
+  // (on the Schur complement the update is fused into the network's first convolution)
   if (net_ && net_schur_) return (double)n_ / 2.0 * 48.0;  // x, r, p, q in; x, r out (black slots)
   if (pc_ == LYAP_PC_IC0 || (rb_ready_ && !net_)) return rb_w_bytes();
   // the flexible-CG update of the learned-preconditioner runs: x, r, p, q in; x, r out

@@ -86,7 +86,7 @@ class InnerCG {
   HostBuf hlog_, htot_;
   CgStats stats_;
   PcNetGpu* net_ = nullptr;
-  DevBuf z_, partZ_;
+  DevBuf z_, partZ_, partRR_;
   DevBuf r1_, w0_, w1_, s0_, s1_;  // double-buffered r, w = K M r, s = K p of the single-reduction CG
   int harvest_every_ = 0, harvest_keep_ = 0;
   // red-black IC(0): 1 / D_r (red slots), D_b and 1 / Sigma_bb (black slots),

@@ -293,7 +293,10 @@ __global__ __launch_bounds__(kPcThreads) void k_pc_conv4(const float* __restrict
 //   MODE 1: the input channels x0 = [u, f u], u = s r rounded to FP32, formed
 //           from r, s, f while staging (the first convolution);
 //   MODE 2: the output of the last transposed convolution (two channels d)
-//           as z = dinv r + s (d0 + f d1) (FP64), with one partial z.q per tile.
+//           as z = dinv r + s (d0 + f d1) (FP64), with one partial z.q per tile;
+//   MODE 3: as MODE 1 from r = r_in - alpha q, with the flexible CG update of
+//           x and r at the tile's own points and one partial r.r per tile
+//           (the PcUpd argument).
 // TRANS = false: out[o][p] = sum_t sum_i W[o][i][t] in[i][p + t];
 // TRANS = true (the adjoint): out[i][p] = sum_t sum_o W[o][i][t] in[o][p - t].
 constexpr int kQX = 8, kQY = 8, kQZ = 4;
@@ -306,12 +309,12 @@ __global__ __launch_bounds__(kPcThreads) void k_pc_tile(const float* __restrict_
                                                         const double* __restrict__ dinv, const float* __restrict__ W,
                                                         float* __restrict__ out, double* __restrict__ z,
                                                         const double* __restrict__ q, double* part, int nx, int ny,
-                                                        int nz, int tx, int ty, int tz) {
+                                                        int nz, int tx, int ty, int tz, PcUpd u) {
   static_assert(kQX * kQY * kQZ == kPcThreads, "one output point per thread");
   constexpr int NIN = TRANS ? CO : CI;
   constexpr int NOUT = TRANS ? CI : CO;
   constexpr int SG = TRANS ? -1 : 1;
-  static_assert(MODE != 1 || NIN == 2, "the formed input has two channels");
+  static_assert((MODE != 1 && MODE != 3) || NIN == 2, "the formed input has two channels");
   static_assert(MODE != 2 || NOUT == 2, "the output is formed from two channels");
   const int lb = xcd_block(blockIdx.x, tx * ty * tz);
   if (lb < 0) return;
@@ -320,6 +323,22 @@ __global__ __launch_bounds__(kPcThreads) void k_pc_tile(const float* __restrict_
   const int bx = lb % tx, by = (lb / tx) % ty, bz = lb / (tx * ty);
   const int x0 = bx * kQX, y0 = by * kQY, z0 = bz * kQZ;
   const int n = nx * ny * nz;
+  double alpha = 0.0;
+  if constexpr (MODE == 3) {
+    // alpha = p.r / p.q, identical in every workgroup (fixed summation order)
+    __shared__ double redu[2 * (kPcThreads / 64)];
+    reduce_partials<2, kPcThreads>(u.pin, u.nparts, redu);
+    const double pq = uniform_d(redu[0]), pr = uniform_d(redu[1]);
+    __syncthreads();
+    const bool active = uniform_d(u.log[u.it].rr[0]) > uniform_d(u.state[0]);
+    alpha = (active && pq > 0.0) ? pr / pq : 0.0;
+    if (lb == 0 && threadIdx.x == 0) {
+      u.log[u.it].sigma[0] = pq;
+      u.log[u.it].rho[0] = pr;
+      u.log[u.it].alpha[0] = alpha;
+      if (active && !(pq > 0.0)) u.flag[1] = u.it + 1;
+    }
+  }
   // every thread loads its (at most three) halo-tile points before storing
   // any, so that all loads are in flight together
   constexpr int NST = (kQH + kPcThreads - 1) / kPcThreads;
@@ -331,13 +350,14 @@ __global__ __launch_bounds__(kPcThreads) void k_pc_tile(const float* __restrict_
     const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
     const bool inside = h < kQH && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
     const int p = inside ? gx + nx * (gy + ny * gz) : 0;
-    if constexpr (MODE == 1) {
-      float u = 0.f, fu = 0.f;
+    if constexpr (MODE == 1 || MODE == 3) {
+      float su = 0.f, fu = 0.f;
       if (inside) {
-        u = (float)((double)s[p] * r[p]);
-        fu = f[p] * u;
+        const double rp = MODE == 3 ? fma(-alpha, u.q[p], u.r_in[p]) : r[p];
+        su = (float)((double)s[p] * rp);
+        fu = f[p] * su;
       }
-      v0[k] = u;
+      v0[k] = su;
       v1[k][0] = fu;
     } else {
       v0[k] = inside ? in[p] : 0.f;
@@ -394,6 +414,16 @@ __global__ __launch_bounds__(kPcThreads) void k_pc_tile(const float* __restrict_
     if (own) {
 #pragma unroll
       for (int o = 0; o < NOUT; ++o) out[(size_t)o * n + p] = acc[o];
+    }
+    if constexpr (MODE == 3) {
+      double rr[1] = {0.0};
+      if (own) {
+        const double rq = fma(-alpha, u.q[p], u.r_in[p]);
+        u.r_out[p] = rq;
+        u.x[p] = fma(alpha, u.p[p], u.x[p]);
+        rr[0] = rq * rq;
+      }
+      write_partial_at<1, kPcThreads>(rr, red, u.rr_part, lb);
     }
   }
 }
@@ -722,6 +752,16 @@ int PcNetGpu::tiles() const {
 int PcNetGpu::max_out_parts() const { return std::max(tiles(), stream_grid(n_)); }
 
 int PcNetGpu::apply(const double* r, double* z, const double* q, double* part) {
+  return launch_apply(r, nullptr, r, z, q, part);
+}
+
+int PcNetGpu::apply_upd(const PcUpd& u, double* z, const double* q, double* part) {
+  LYAP_REQUIRE(u.r_out != u.r_in, LYAP_E_ARG, "fused update: r_out must not alias r_in");
+  return launch_apply(nullptr, &u, u.r_out, z, q, part);
+}
+
+int PcNetGpu::launch_apply(const double* r_first, const PcUpd* up, const double* r_last, double* z, const double* q,
+                           double* part) {
   const float* W1 = W_.as<float>();
   const float* W2 = W1 + C_ * 2 * 27;
   const int tx = (nx_ + kQX - 1) / kQX, ty = (ny_ + kQY - 1) / kQY, tz = (nz_ + kQZ - 1) / kQZ;
@@ -731,15 +771,20 @@ int PcNetGpu::apply(const double* r, double* z, const double* q, double* part) {
   float* fo = nullptr;
   const double* dn = nullptr;
   double* dno = nullptr;
+  const PcUpd none{};
   LYAP_PC_SWITCH({
-    hipLaunchKernelGGL((k_pc_tile<2, CC, false, 1>), grid, blk, 0, st_, fn, r, s_.as<float>(), f_.as<float>(), dn, W1,
-                       a1_.as<float>(), dno, dn, dno, nx_, ny_, nz_, tx, ty, tz);
+    if (up)
+      hipLaunchKernelGGL((k_pc_tile<2, CC, false, 3>), grid, blk, 0, st_, fn, dn, s_.as<float>(), f_.as<float>(), dn,
+                         W1, a1_.as<float>(), dno, dn, dno, nx_, ny_, nz_, tx, ty, tz, *up);
+    else
+      hipLaunchKernelGGL((k_pc_tile<2, CC, false, 1>), grid, blk, 0, st_, fn, r_first, s_.as<float>(), f_.as<float>(),
+                         dn, W1, a1_.as<float>(), dno, dn, dno, nx_, ny_, nz_, tx, ty, tz, none);
     hipLaunchKernelGGL((k_pc_tile<CC, CC, false, 0>), grid, blk, 0, st_, a1_.as<float>(), dn, fn, fn, dn, W2,
-                       k_.as<float>(), dno, dn, dno, nx_, ny_, nz_, tx, ty, tz);
+                       k_.as<float>(), dno, dn, dno, nx_, ny_, nz_, tx, ty, tz, none);
     hipLaunchKernelGGL((k_pc_tile<CC, CC, true, 0>), grid, blk, 0, st_, k_.as<float>(), dn, fn, fn, dn, W2,
-                       t1_.as<float>(), dno, dn, dno, nx_, ny_, nz_, tx, ty, tz);
-    hipLaunchKernelGGL((k_pc_tile<2, CC, true, 2>), grid, blk, 0, st_, t1_.as<float>(), r, s_.as<float>(),
-                       f_.as<float>(), dinv_.as<double>(), W1, fo, z, q, part, nx_, ny_, nz_, tx, ty, tz);
+                       t1_.as<float>(), dno, dn, dno, nx_, ny_, nz_, tx, ty, tz, none);
+    hipLaunchKernelGGL((k_pc_tile<2, CC, true, 2>), grid, blk, 0, st_, t1_.as<float>(), r_last, s_.as<float>(),
+                       f_.as<float>(), dinv_.as<double>(), W1, fo, z, q, part, nx_, ny_, nz_, tx, ty, tz, none);
   });
   LYAP_LAUNCHED("pcnet apply");
   return G;

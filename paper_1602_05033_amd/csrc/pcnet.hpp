@@ -25,6 +25,30 @@ inline int pcnet_param_count(int C) { return C * 2 * 27 + C * C * 27; }
 // SplitMix64 initial weights, uniform in [-scale, scale): u = (top 53 bits) / 2^53.
 void pcnet_init_weights(int C, uint64_t seed, double scale, float* W);
 
+struct CgIter;
+
+// The flexible CG update of one iteration fused into the first convolution of
+// the next application: alpha = p.r / p.q from the partials pin (nparts
+// pairs; 0 once r.r <= *state), x += alpha p, r_out = r_in - alpha q (r_in is
+// read at every tile's halo, where the update is recomputed, so r_out must
+// not alias it), the network applied to r_out, partial sums of
+// r_out.r_out per tile into rr_part; log[it] receives p.q, p.r and alpha, and
+// flag[1] = it + 1 when p.q <= 0 while active.
+struct PcUpd {
+  double* x;
+  const double* r_in;
+  double* r_out;
+  const double* p;
+  const double* q;
+  CgIter* log;
+  int it;
+  const double* state;
+  const double* pin;
+  int nparts;
+  double* rr_part;
+  int* flag;
+};
+
 // y = K x for the symmetric positive definite matrix K of the system the
 // network preconditions (device FP64 vectors on the network's grid, stream-ordered).
 using SpdApply = std::function<void(const double* x, double* y)>;
@@ -47,6 +71,9 @@ class PcNetGpu {
   // sums of z.q into part (at most max_out_parts() of them, in a fixed
   // order); returns how many were written.
   int apply(const double* r, double* z, const double* q, double* part);
+  // The same with the flexible CG update fused in (see PcUpd): z = M r_out.
+  // Returns the number of z.q partials, which equals that of the r.r partials.
+  int apply_upd(const PcUpd& u, double* z, const double* q, double* part);
   int max_out_parts() const;
   int tiles() const;  // workgroups (and z.q partials) of one apply()
   // Algorithmic figures of one apply() (the four tiled kernels): FP32
@@ -76,6 +103,8 @@ class PcNetGpu {
   void forward(const double* r);
 
   void alloc_common();
+  int launch_apply(const double* r_first, const PcUpd* u, const double* r_last, double* z, const double* q,
+                   double* part);
   OpDev<double> op_;
   SpdApply kapply_;   // set: K given by the caller (else K = -A of op_)
   int nx_, ny_, nz_, n_, C_, P_;

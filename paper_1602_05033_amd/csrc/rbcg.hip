@@ -536,39 +536,6 @@ __global__ __launch_bounds__(NT) void k_rbf_dirb(OpDev<double> op, RbGeom g, con
   write_partial<2, NT>(acc, red, pout);
 }
 
-// Update: alpha = p.r / p.q; x += alpha p; r -= alpha q; partial r.r
-template <int NT>
-__global__ __launch_bounds__(NT) void k_rbf_upd(RbGeom g, double* __restrict__ x, double* __restrict__ r,
-                                                const double* __restrict__ p, const double* __restrict__ qv,
-                                                CgIter* log, int it, const double* state, const double* pin,
-                                                int nparts, double* pout, int* flag) {
-  __shared__ double red[2 * (NT / 64)];
-  reduce_partials<2, NT>(pin, nparts, red);
-  const double pq = uniform_d(red[0]), pr = uniform_d(red[1]);
-  __syncthreads();
-  const bool active = uniform_d(log[it].rr[0]) > uniform_d(state[0]);
-  const double alpha = (active && pq > 0.0) ? pr / pq : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    log[it].sigma[0] = pq;
-    log[it].rho[0] = pr;
-    log[it].alpha[0] = alpha;
-    if (active && !(pq > 0.0)) flag[1] = it + 1;
-  }
-  double acc[1] = {0.0};
-  int lo, hi;
-  op_rows(blockIdx.x, gridDim.x, g.nb, lo, hi);
-  for (int q = lo + threadIdx.x; q < hi; q += NT) {
-    const double xq = fma(alpha, p[q], x[q]);
-    const double rq = fma(-alpha, qv[q], r[q]);
-    x[q] = xq;
-    r[q] = rq;
-    acc[0] = fma(rq, rq, acc[0]);
-  }
-  (void)red;
-  __shared__ double red1[NT / 64];
-  write_partial<1, NT>(acc, red1, pout);
-}
-
 inline RbGeom rb_geom(const OpDev<double>& op) {
   RbGeom g;
   g.nx = op.nx;
@@ -780,10 +747,10 @@ template <bool K7>
 static void rbf_launch_dir(hipStream_t st, int G, const OpDev<double>& op, const RbGeom& g, const double* rinv,
                            const double* db, const double* z, const double* po, double* pn, double* v,
                            const double* r, double* qv, CgIter* log, int it, const double* state,
-                           const double* partR, const double* partZ, int zparts, double* pout) {
+                           const double* partR, int rparts, const double* partZ, int zparts, double* pout) {
   constexpr int NT = stream_threads(1);
   hipLaunchKernelGGL((k_rbf_dira<K7, NT>), dim3(G), dim3(NT), 0, st, op, g, rinv, z, po, pn, v, log, it, state,
-                     partR, G, partZ, zparts);
+                     partR, rparts, partZ, zparts);
   hipLaunchKernelGGL((k_rbf_dirb<K7, NT>), dim3(G), dim3(NT), 0, st, op, g, db, pn, v, r, qv, pout);
 }
 
@@ -805,6 +772,10 @@ void InnerCG::solve_rb_fcg(const double* B, double* X, KernelTimer* kt) {
   double* v = rb_v_.as<double>();
   double* pb[2] = {rb_p_.as<double>(), rb_s0_.as<double>()};
   if (!partZ_.p) partZ_.alloc((size_t)net_->max_out_parts() * sizeof(double));
+  if (!partRR_.p) partRR_.alloc((size_t)net_->max_out_parts() * sizeof(double));
+  // r alternates between two buffers: the update fused into the network's
+  // first convolution reads the old r at the tile halos while writing the new
+  double* rbuf[2] = {r, rb_r1_.as<double>()};
   int zparts = 0;
   int total = 0;
   double worst = 0.0;
@@ -821,6 +792,9 @@ void InnerCG::solve_rb_fcg(const double* B, double* X, KernelTimer* kt) {
     hipLaunchKernelGGL((k_rbf_rr<NT>), dim3(G), dim3(NT), 0, st_, g, r, partA_.as<double>());
     LYAP_LAUNCHED("k_rbf_start");
     net_->apply(r, z, nullptr, nullptr);
+    int cur = 0;  // r in rbuf[cur] (the start's residual is in rbuf[0])
+    const double* partR = partA_.as<double>();
+    int rparts = G;
     int it = 0;
     bool done = false;
     while (!done && total + it < max_iter_) {
@@ -830,16 +804,18 @@ void InnerCG::solve_rb_fcg(const double* B, double* X, KernelTimer* kt) {
         double* pn = pb[it % 2];
         const double* po = pb[(it + 1) % 2];
         if (kt) kt->mark(LYAP_K_CG_DIR);
-        (k7 ? rbf_launch_dir<true> : rbf_launch_dir<false>)(st_, G, op_, g, rinv, db, z, po, pn, v, r, qv,
-                                                          log_.as<CgIter>(), it, state_.as<double>(),
-                                                          partA_.as<double>(), partZ_.as<double>(), zparts,
-                                                          partB_.as<double>());
-        if (kt) kt->mark(LYAP_K_CG_UPD);
-        hipLaunchKernelGGL((k_rbf_upd<NT>), dim3(G), dim3(NT), 0, st_, g, x, r, pn, qv, log_.as<CgIter>(), it,
-                           state_.as<double>(), partB_.as<double>(), G, partA_.as<double>(), flag_.as<int>());
+        (k7 ? rbf_launch_dir<true> : rbf_launch_dir<false>)(st_, G, op_, g, rinv, db, z, po, pn, v, rbuf[cur], qv,
+                                                          log_.as<CgIter>(), it, state_.as<double>(), partR, rparts,
+                                                          partZ_.as<double>(), zparts, partB_.as<double>());
         LYAP_LAUNCHED("condensed fcg iteration");
+        // x, r update fused into the network's first convolution; z = M r
         if (kt) kt->mark(LYAP_K_PCNET);
-        zparts = net_->apply(r, z, qv, partZ_.as<double>());
+        const PcUpd u{x, rbuf[cur], rbuf[cur ^ 1], pn, qv, log_.as<CgIter>(), it, state_.as<double>(),
+                      partB_.as<double>(), G, partRR_.as<double>(), flag_.as<int>()};
+        zparts = net_->apply_upd(u, z, qv, partZ_.as<double>());
+        cur ^= 1;
+        partR = partRR_.as<double>();
+        rparts = zparts;
       }
       if (kt) kt->collect();
       LYAP_HIP(hipMemcpyAsync(hlog_.p, log_.as<CgIter>() + it0, (size_t)cnt * sizeof(CgIter), hipMemcpyDeviceToHost,
