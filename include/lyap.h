@@ -422,9 +422,19 @@ lyap_status lyap_inner_solve(const lyap_op* A, const double* B, int64_t ldb, dou
  *  s      host array, 1 <= s_i <= 8;  ldc: host array, ldc_i >= n_i.
  *  opts   shared by all problems (tol, max_iter, check_every, storage,
  *         allocator, stream, profile); method must be STD and two_pass 1.
- *  tune   0: fixed workgroups per problem (reproducible bits); 1: autotuned
- *         per (block width, size bucket) once per process by timing one
- *         grouped step on scratch data for each candidate.
+ *  tune   0: the fixed tile shape (the single-problem kernels' workgroup
+ *         size, 2048 rows per workgroup; reproducible bits); 1: tile shapes
+ *         from the autotuner -- per (device, storage, block width, size
+ *         bucket) and workgroup size (256 or 1024 threads, 256 only above 4
+ *         columns) the fastest of 2048..16384 rows per workgroup, found by
+ *         timing grouped steps on scratch data; each block width's launches
+ *         take the workgroup size whose tuned step times sum lowest over its
+ *         problems.  Results are kept in the process and in a text file that
+ *         persists across processes ($LYAP_TUNE_CACHE, else
+ *         $XDG_CACHE_HOME/lyap_tune.txt, else $HOME/.cache/lyap_tune.txt;
+ *         a file that cannot be read or written is ignored); 2: as 1 but
+ *         timing again and replacing what the caches hold.  Autotuned runs
+ *         are reproducible when the same shapes are chosen.
  *  out    array of `count` results, filled like lyap_solve's; phase times are
  *         those of the whole batch (times_ms[LYAP_T_TO_TOL] is per problem);
  *         kern_ms / kern_n of out[0] cover the whole batch.

@@ -374,7 +374,8 @@ def lyap_solve_batched(dops, Cs, tune: bool = False, raise_on_error: bool = True
     o = make_opts(stream=torch.cuda.current_stream(Cs[0].device).cuda_stream, **kw)
     o.alloc, o.release = alloc.alloc_cb, alloc.free_cb
     res = (LyapResult * count)()
-    st = lib.lyap_solve_batched(count, ops, ptrs, ss, lds, ct.byref(o), int(bool(tune)), res)
+    # tune: False / 0 fixed tile shape, True / 1 autotuned (persistent cache), 2 re-tune
+    st = lib.lyap_solve_batched(count, ops, ptrs, ss, lds, ct.byref(o), int(tune), res)
     msg = lib.lyap_last_error().decode()
     try:
         if raise_on_error and st not in (OK, NOT_CONVERGED):

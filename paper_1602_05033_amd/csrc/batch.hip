@@ -14,9 +14,14 @@
 // The choice sets the order of the partial sums, so autotuned runs are
 // reproducible within a process (and across processes when the timings pick
 // the same candidates); the fixed rule is reproducible always.
+#include <sys/stat.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -44,8 +49,88 @@ int size_bucket(int64_t n) {
   return b;
 }
 
+// ------------------------------------------------------------------ tile autotuner
+// A tile shape of the grouped step is (threads per workgroup, rows per
+// workgroup).  For each (device, storage, block width, size bucket) and each
+// workgroup size the autotuner times a grouped step on a scratch problem of
+// the bucket's size for every row count and keeps the fastest with its time.
+// Results live in the process and in a text file that persists across
+// processes: $LYAP_TUNE_CACHE, else $XDG_CACHE_HOME/lyap_tune.txt, else
+// $HOME/.cache/lyap_tune.txt (one line per entry: "lyap-tune-1 arch cus
+// storage S bucket threads rows ms"; unreadable or unwritable files are
+// ignored).
+struct TuneEntry {
+  int chunk;
+  float ms;
+};
+using TuneKey = std::tuple<std::string, int, int, int, int>;  // (device, storage, S, bucket, threads)
+
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, int> g_tune;  // (storage, S, bucket) -> rows per workgroup
+std::map<TuneKey, TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+std::string device_tag() {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  static std::mutex mu;
+  static std::map<int, std::string> tags;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = tags.find(dev);
+  if (it != tags.end()) return it->second;
+  hipDeviceProp_t prop;
+  std::string tag = "unknown";
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    std::string arch = prop.gcnArchName;
+    for (char& c : arch)
+      if (c == ' ' || c == '\t') c = '_';
+    tag = arch + ":" + std::to_string(prop.multiProcessorCount);
+  }
+  tags[dev] = tag;
+  return tag;
+}
+
+std::string tune_cache_path() {
+  if (const char* p = std::getenv("LYAP_TUNE_CACHE")) return p;
+  if (const char* x = std::getenv("XDG_CACHE_HOME")) return std::string(x) + "/lyap_tune.txt";
+  if (const char* h = std::getenv("HOME")) return std::string(h) + "/.cache/lyap_tune.txt";
+  return "";
+}
+
+// caller holds g_tune_mu
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char tag[16], dev[128];
+  int storage, S, bucket, nt, chunk;
+  float ms;
+  while (std::fscanf(f, "%15s %127s %d %d %d %d %d %f", tag, dev, &storage, &S, &bucket, &nt, &chunk, &ms) == 8) {
+    if (std::string(tag) != "lyap-tune-1" || chunk <= 0 || !(ms > 0.f)) continue;
+    g_tune[TuneKey(dev, storage, S, bucket, nt)] = TuneEntry{chunk, ms};
+  }
+  std::fclose(f);
+}
+
+void tune_store_locked(const TuneKey& k, const TuneEntry& e) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) {  // a missing ~/.cache: create that one directory
+    const size_t sl = path.rfind('/');
+    if (sl != std::string::npos && mkdir(path.substr(0, sl).c_str(), 0755) == 0) f = std::fopen(path.c_str(), "a");
+  }
+  if (!f) return;
+  std::fprintf(f, "lyap-tune-1 %s %d %d %d %d %d %.6g\n", std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k),
+               std::get<3>(k), std::get<4>(k), e.chunk, e.ms);
+  std::fclose(f);
+}
+
+std::vector<int> thread_candidates(int S) {
+  return S <= 4 ? std::vector<int>{256, 1024} : std::vector<int>{256};
+}
 
 template <typename T>
 struct Problem {
@@ -71,20 +156,24 @@ struct Problem {
   std::vector<int> hm;
   std::vector<double> hr;
   int nparts = 1;
+  std::vector<std::pair<int, TuneEntry>> shapes;  // per workgroup size: best rows per workgroup, step time
   DevBuf M;
   int t = 0;
 };
 
-// Times one grouped step on a scratch problem (random block, the 5-point
-// operator of the bucket's size) for each candidate; returns the fastest.
+// Times one grouped step on a scratch problem (a fixed pseudo-random block,
+// the 5-point operator of the bucket's size) with nt threads per workgroup for
+// every row count; returns the fastest (from the caches when known, unless
+// refresh is set).
 template <typename T>
-int autotune_chunk(int S, int64_t n, hipStream_t st) {
+TuneEntry autotune_shape(int S, int64_t n, int nt, bool refresh, hipStream_t st) {
   const int storage = std::is_same_v<T, double> ? LYAP_STORE_F64 : LYAP_STORE_F32;
-  const auto key = std::make_tuple(storage, S, size_bucket(n));
+  const TuneKey key(device_tag(), storage, S, size_bucket(n), nt);
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_load_locked();
     auto it = g_tune.find(key);
-    if (it != g_tune.end()) return it->second;
+    if (it != g_tune.end() && !refresh) return it->second;
   }
   const int N = (int)std::max<int64_t>(8, (int64_t)std::sqrt((double)n));
   const int nn = N * N;
@@ -98,7 +187,8 @@ int autotune_chunk(int S, int64_t n, hipStream_t st) {
   {
     std::vector<T> h((size_t)nn * S);
     for (size_t i = 0; i < h.size(); ++i) h[i] = (T)(((i * 2654435761u) % 1000) * 1e-3 - 0.5);
-    LYAP_HIP(hipMemcpy(Vb1.p, h.data(), blk, hipMemcpyHostToDevice));
+    LYAP_HIP(hipMemcpyAsync(Vb1.p, h.data(), blk, hipMemcpyHostToDevice, st));
+    LYAP_HIP(hipStreamSynchronize(st));
   }
   BatchDesc<T> d{};
   d.op.kind = LYAP_OP_STENCIL5;
@@ -120,34 +210,32 @@ int autotune_chunk(int S, int64_t n, hipStream_t st) {
   hipEvent_t e0, e1;
   LYAP_HIP(hipEventCreate(&e0));
   LYAP_HIP(hipEventCreate(&e1));
-  int best = kChunkCandidates[0];
-  float best_ms = 1e30f;
+  TuneEntry best{kChunkCandidates[0], 1e30f};
+  DevBuf dm((size_t)kSGrid * sizeof(int2));
   for (int chunk : kChunkCandidates) {
     d.nparts = nparts_for(nn, chunk);
     std::vector<int2> map(d.nparts);
     for (int w = 0; w < d.nparts; ++w) map[w] = make_int2(0, w);
-    DevBuf dm(map.size() * sizeof(int2));
-    LYAP_HIP(hipMemcpy(dd.p, &d, sizeof(d), hipMemcpyHostToDevice));
-    LYAP_HIP(hipMemcpy(dm.p, map.data(), map.size() * sizeof(int2), hipMemcpyHostToDevice));
+    LYAP_HIP(hipMemcpyAsync(dd.p, &d, sizeof(d), hipMemcpyHostToDevice, st));
+    LYAP_HIP(hipMemcpyAsync(dm.p, map.data(), map.size() * sizeof(int2), hipMemcpyHostToDevice, st));
     // step 0 twice (the same inputs every time), then timed
     for (int r = 0; r < 2; ++r)
-      launch_batch_step<T>(dd.template as<BatchDesc<T>>(), dm.template as<int2>(), d.nparts, S, 0, st);
+      launch_batch_step<T>(dd.template as<BatchDesc<T>>(), dm.template as<int2>(), d.nparts, S, nt, 0, st);
     LYAP_HIP(hipEventRecord(e0, st));
     for (int r = 0; r < 5; ++r)
-      launch_batch_step<T>(dd.template as<BatchDesc<T>>(), dm.template as<int2>(), d.nparts, S, 0, st);
+      launch_batch_step<T>(dd.template as<BatchDesc<T>>(), dm.template as<int2>(), d.nparts, S, nt, 0, st);
     LYAP_HIP(hipEventRecord(e1, st));
     LYAP_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
     LYAP_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = chunk;
-    }
+    const float per_step = ms / 5.0f;
+    if (per_step < best.ms) best = TuneEntry{chunk, per_step};
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   std::lock_guard<std::mutex> g(g_tune_mu);
   g_tune[key] = best;
+  tune_store_locked(key, best);
   return best;
 }
 
@@ -203,8 +291,11 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
     LYAP_HIP(hipMemsetAsync(p->zero.p, 0, blk, st));
     LYAP_HIP(hipMemsetAsync(p->Vb0.p, 0, blk, st));
     LYAP_HIP(hipMemsetAsync(p->band.p, 0, p->band.bytes, st));
-    const int chunk = tune ? autotune_chunk<T>(p->S, p->n, st) : 2048;
-    p->nparts = nparts_for(p->n, chunk);
+    // tile shapes: the fixed rule (the single-problem kernels' workgroup size,
+    // 2048 rows per workgroup) or the autotuner's table for this size
+    if (tune)
+      for (int nt : thread_candidates(p->S)) p->shapes.emplace_back(nt, autotune_shape<T>(p->S, p->n, nt, tune == 2, st));
+    p->nparts = nparts_for(p->n, 2048);
     p->ck = std::make_unique<Checker>(p->S, p->S, cstream(i));
     p->sched = CheckSchedule{o.check_every, maxit};
     // a check costs the host a few hundred launches, a grouped step a handful
@@ -257,6 +348,7 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
     bool ev_used[2] = {false, false};
     int slot = 0;
     int nwg = 0;
+    int nt = 256;  // threads per workgroup of the group's launches
     Group() = default;
     Group(const Group&) = delete;
     Group& operator=(const Group&) = delete;
@@ -268,8 +360,29 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
   std::vector<Group> groups(widths.size());
   for (size_t g = 0; g < widths.size(); ++g) {
     groups[g].S = widths[g];
+    groups[g].nt = batch_default_threads(widths[g]);
     for (auto& p : P)
       if (p->S == widths[g]) groups[g].probs.push_back(p.get());
+    if (!tune) continue;
+    // one workgroup size per group (a template parameter of its launches):
+    // the one whose tuned step times sum lowest over the group's problems;
+    // then every problem takes its own tuned row count for that size
+    double best = 1e300;
+    for (int nt : thread_candidates(widths[g])) {
+      double tot = 0.0;
+      for (Problem<T>* p : groups[g].probs)
+        for (auto& sh : p->shapes)
+          if (sh.first == nt) tot += sh.second.ms;
+      if (tot < best) {
+        best = tot;
+        groups[g].nt = nt;
+      }
+    }
+    for (Problem<T>* p : groups[g].probs)
+      for (auto& sh : p->shapes)
+        if (sh.first == groups[g].nt) p->nparts = nparts_for(p->n, sh.second.chunk);
+    if (o.verbose)
+      std::fprintf(stderr, "[batch] width %d: %d threads per workgroup\n", widths[g], groups[g].nt);
   }
   auto upload = [&](Group& g, bool replay, int step) {
     if (!g.desc.p) {  // sized once: every problem of the group, every workgroup of each
@@ -464,7 +577,8 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
     if (j >= kAhead) LYAP_HIP(hipEventSynchronize(er.ev[j % kAhead]));
     for (auto& g : groups)
       if (g.nwg > 0)
-        launch_batch_step<T>(g.desc.template as<BatchDesc<T>>(), g.map.template as<int2>(), g.nwg, g.S, j, st, &kt);
+        launch_batch_step<T>(g.desc.template as<BatchDesc<T>>(), g.map.template as<int2>(), g.nwg, g.S, g.nt, j, st,
+                             &kt);
     LYAP_HIP(hipEventRecord(er.ev[j % kAhead], st));
     ++j;
     for (auto& p : P)
@@ -570,7 +684,7 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
     for (auto& g : groups) {
       if (g.nwg > 0) {
         kt.mark(LYAP_K_REPLAY);
-        launch_batch_replay<T>(g.desc.template as<BatchDesc<T>>(), g.map.template as<int2>(), g.nwg, g.S, i, st);
+        launch_batch_replay<T>(g.desc.template as<BatchDesc<T>>(), g.map.template as<int2>(), g.nwg, g.S, g.nt, i, st);
       }
       for (Problem<T>* p : g.probs)
         if (i + 2 == p->m_final) map_changes = true;  // leaves the replay map after this step
@@ -646,6 +760,7 @@ extern "C" lyap_status lyap_solve_batched(int32_t count, const lyap_op* A, const
     LYAP_REQUIRE(o.max_iter >= 1 && (int64_t)o.max_iter * 8 <= (int64_t)1 << 20, LYAP_E_ARG,
                  "max_iter=%d out of range", o.max_iter);
     LYAP_REQUIRE(o.check_every >= 0, LYAP_E_ARG, "check_every must be >= 0");
+    LYAP_REQUIRE(tune >= 0 && tune <= 2, LYAP_E_ARG, "tune=%d must be 0, 1 or 2", tune);
     LYAP_REQUIRE(o.method == LYAP_METHOD_STD, LYAP_E_UNSUPPORTED, "the batched solver builds standard Krylov spaces");
     LYAP_REQUIRE(o.two_pass != 0, LYAP_E_UNSUPPORTED, "the batched solver uses the two-pass strategy");
     LYAP_REQUIRE(o.storage == LYAP_STORE_F64 || o.storage == LYAP_STORE_F32, LYAP_E_ARG, "unknown storage %d",

@@ -88,7 +88,7 @@ constexpr int rows_per_thread() {
 // in a grouped launch over several problems.
 #define LYAP_BATCH(r0, n) \
   constexpr int kRPT = rows_per_thread<T, S>(); \
-  for (int r0 = wg_id * stream_threads(S) + threadIdx.x; r0 < (n); r0 += wg_cnt * stream_threads(S) * kRPT)
+  for (int r0 = wg_id * NT + threadIdx.x; r0 < (n); r0 += wg_cnt * NT * kRPT)
 #define LYAP_FOR_U _Pragma("unroll") for (int u = 0; u < kRPT; ++u)
 
 template <int S>
@@ -107,10 +107,10 @@ __device__ __forceinline__ void outer_acc(double (&acc)[S * S], const X (&x)[S],
 
 // Prologue: total of the previous kernel's partial Gram matrices into g[];
 // workgroup 0 also records it in the log slot (if slot >= 0).
-template <int S>
+template <int S, int NT = stream_threads(S)>
 __device__ __forceinline__ void take_gram(const double* pin, int nparts, double* red, double (&g)[S * S],
                                           double* log_slot, bool lead) {
-  reduce_partials<S * S, stream_threads(S)>(pin, nparts, red);
+  reduce_partials<S * S, NT>(pin, nparts, red);
 #pragma unroll
   for (int i = 0; i < S * S; ++i) g[i] = uniform_d(red[i]);
   if (lead && log_slot && threadIdx.x < S * S) log_slot[threadIdx.x] = red[threadIdx.x];
@@ -118,32 +118,32 @@ __device__ __forceinline__ void take_gram(const double* pin, int nparts, double*
 }
 
 // K1: W = A V_j ; partial alpha1 = V_{j-1}^T W
-template <typename T, int S>
+template <typename T, int S, int NT = stream_threads(S)>
 __device__ __forceinline__ void spmm_gram_body(const StepArgs<T>& a, int wg_id, int wg_cnt, double* red) {
   double acc[S * S];
   zero<S>(acc);
   int lo, hi;
   op_rows(wg_id, wg_cnt, a.n, lo, hi);
-  for (int r = lo + threadIdx.x; r < hi; r += stream_threads(S)) {
+  for (int r = lo + threadIdx.x; r < hi; r += NT) {
     T w[S], x[S];
     op_row<T, S>(a.op, a.Vcur, r, w);
     load_row<T, S>(a.Vprev + (size_t)r * S, x);
     store_row<T, S>(a.W + (size_t)r * S, w);
     outer_acc<T, T, S>(acc, x, w);
   }
-  write_partial_at<S * S, stream_threads(S)>(acc, red, a.pout, wg_id);
+  write_partial_at<S * S, NT>(acc, red, a.pout, wg_id);
 }
 
 // K2..K5: alpha_in = total of the previous partials (logged), W -= X alpha_in,
 // partial Y^T W (Y == nullptr: W^T W for the QR that follows).
-template <typename T, int S>
+template <typename T, int S, int NT = stream_threads(S)>
 __device__ __forceinline__ void upd_gram_body(const StepArgs<T>& a, const T* X, const T* Y, int slot_in, int wg_id,
                                               int wg_cnt, double* red) {
   double al[S * S];
-  take_gram<S>(a.pin, a.nparts, red, al, a.log + slot_in * S * S, wg_id == 0);
+  take_gram<S, NT>(a.pin, a.nparts, red, al, a.log + slot_in * S * S, wg_id == 0);
   double acc[S * S];
   zero<S>(acc);
-  const int str = wg_cnt * stream_threads(S);
+  const int str = wg_cnt * NT;
   LYAP_BATCH(r0, a.n) {
     T w[kRPT][S], x[kRPT][S], y[kRPT][S];
     LYAP_FOR_U {
@@ -164,16 +164,16 @@ __device__ __forceinline__ void upd_gram_body(const StepArgs<T>& a, const T* X, 
       }
     }
   }
-  write_partial_at<S * S, stream_threads(S)>(acc, red, a.pout, wg_id);
+  write_partial_at<S * S, NT>(acc, red, a.pout, wg_id);
 }
 
 // K6: G1 = W^T W (logged), R1 = chol(G1) ; partial (W R1^{-1})^T (W R1^{-1})
-template <typename T, int S>
+template <typename T, int S, int NT = stream_threads(S)>
 __device__ __forceinline__ void chol_gram_body(const StepArgs<T>& a, int wg_id, int wg_cnt, double* red) {
   __shared__ double sR1[S * S], sR1I[S * S];
   __shared__ double sratio;
   double G[S * S];
-  take_gram<S>(a.pin, a.nparts, red, G, a.log + L_G1 * S * S, wg_id == 0);
+  take_gram<S, NT>(a.pin, a.nparts, red, G, a.log + L_G1 * S * S, wg_id == 0);
   if (threadIdx.x == 0) {
     sratio = chol_upper<S>(G, sR1);
     inv_upper<S>(sR1, sR1I);
@@ -196,7 +196,7 @@ __device__ __forceinline__ void chol_gram_body(const StepArgs<T>& a, int wg_id, 
   for (int i = 0; i < S * S; ++i) ri[i] = uniform_d(sR1I[i]);
   double acc[S * S];
   zero<S>(acc);
-  const int str = wg_cnt * stream_threads(S);
+  const int str = wg_cnt * NT;
   LYAP_BATCH(r0, a.n) {
     T w[kRPT][S];
     LYAP_FOR_U {
@@ -212,17 +212,17 @@ __device__ __forceinline__ void chol_gram_body(const StepArgs<T>& a, int wg_id, 
       }
     }
   }
-  write_partial_at<S * S, stream_threads(S)>(acc, red, a.pout, wg_id);
+  write_partial_at<S * S, NT>(acc, red, a.pout, wg_id);
 }
 
 // K7: G2 (logged), R2 = chol(G2), tau_{j+1,j} = R2 R1, V_{j+1} = W (R1^{-1} R2^{-1});
 // workgroup 0 writes the log and the T_m band (diagonal block sym(alpha2 +
 // alpha4), sub-diagonal block tau_{j+1,j}).
-template <typename T, int S>
+template <typename T, int S, int NT = stream_threads(S)>
 __device__ __forceinline__ void chol_store_body(const StepArgs<T>& a, int wg_id, int wg_cnt, double* red) {
   __shared__ double sRI[S * S];
   double G[S * S];
-  take_gram<S>(a.pin, a.nparts, red, G, a.log + L_G2 * S * S, wg_id == 0);
+  take_gram<S, NT>(a.pin, a.nparts, red, G, a.log + L_G2 * S * S, wg_id == 0);
   if (threadIdx.x == 0) {
     double R2[S * S], R2i[S * S], R[S * S];
     const double ratio = chol_upper<S>(G, R2);
@@ -254,7 +254,7 @@ __device__ __forceinline__ void chol_store_body(const StepArgs<T>& a, int wg_id,
   double ri[S * S];
 #pragma unroll
   for (int i = 0; i < S * S; ++i) ri[i] = uniform_d(sRI[i]);
-  const int str = wg_cnt * stream_threads(S);
+  const int str = wg_cnt * NT;
   LYAP_BATCH(r0, a.n) {
     T w[kRPT][S];
     LYAP_FOR_U {
@@ -273,7 +273,7 @@ __device__ __forceinline__ void chol_store_body(const StepArgs<T>& a, int wg_id,
 }
 
 // Second pass: the whole step from the log, one kernel (V_{j+1} may alias V_{j-1}).
-template <typename T, int S>
+template <typename T, int S, int NT = stream_threads(S)>
 __device__ __forceinline__ void replay_body(const OpDev<T>& op, int n, const T* Vprev, const T* Vcur, T* Vnext,
                                             const double* log, int wg_id, int wg_cnt) {
   double a1[S * S], a2[S * S], a3[S * S], a4[S * S], ri[S * S];
@@ -284,7 +284,7 @@ __device__ __forceinline__ void replay_body(const OpDev<T>& op, int n, const T* 
   load_coef<S>(log + L_RI * S * S, ri);
   int lo, hi;
   op_rows(wg_id, wg_cnt, n, lo, hi);
-  for (int r = lo + threadIdx.x; r < hi; r += stream_threads(S)) {
+  for (int r = lo + threadIdx.x; r < hi; r += NT) {
     T w[S], x[S], y[S], v[S];
     op_row<T, S>(op, Vcur, r, w);
     load_row<T, S>(Vprev + (size_t)r * S, x);
@@ -577,53 +577,53 @@ __device__ __forceinline__ StepArgs<T> batch_args(const BatchDesc<T>& d, int j, 
   return a;
 }
 
-template <typename T, int S>
-__global__ __launch_bounds__(stream_threads(S)) void kb_spmm_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j) {
-  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+template <typename T, int S, int NT>
+__global__ __launch_bounds__(NT) void kb_spmm_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j) {
+  __shared__ double red[pow2_at_least(S * S) * (NT / 64)];
   const int2 pm = map[blockIdx.x];
   const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, false);
-  spmm_gram_body<T, S>(a, pm.y, a.nparts, red);
+  spmm_gram_body<T, S, NT>(a, pm.y, a.nparts, red);
 }
 
 // mode 0: X = V_{j-1}, Y = V_j; 1: X = V_j, Y = V_{j-1}; 2: as 0; 3: X = V_j, Y = none
-template <typename T, int S>
-__global__ __launch_bounds__(stream_threads(S)) void kb_upd_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j,
+template <typename T, int S, int NT>
+__global__ __launch_bounds__(NT) void kb_upd_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j,
                                                                  int mode, int slot, int flip) {
-  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+  __shared__ double red[pow2_at_least(S * S) * (NT / 64)];
   const int2 pm = map[blockIdx.x];
   const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, flip != 0);
   const T* X = (mode == 0 || mode == 2) ? a.Vprev : a.Vcur;
   const T* Y = mode == 3 ? nullptr : ((mode == 1) ? a.Vprev : a.Vcur);
-  upd_gram_body<T, S>(a, X, Y, slot, pm.y, a.nparts, red);
+  upd_gram_body<T, S, NT>(a, X, Y, slot, pm.y, a.nparts, red);
 }
 
-template <typename T, int S>
-__global__ __launch_bounds__(stream_threads(S)) void kb_chol_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j) {
-  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+template <typename T, int S, int NT>
+__global__ __launch_bounds__(NT) void kb_chol_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j) {
+  __shared__ double red[pow2_at_least(S * S) * (NT / 64)];
   const int2 pm = map[blockIdx.x];
   const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, true);
-  chol_gram_body<T, S>(a, pm.y, a.nparts, red);
+  chol_gram_body<T, S, NT>(a, pm.y, a.nparts, red);
 }
 
-template <typename T, int S>
-__global__ __launch_bounds__(stream_threads(S)) void kb_chol_store(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j) {
-  __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
+template <typename T, int S, int NT>
+__global__ __launch_bounds__(NT) void kb_chol_store(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j) {
+  __shared__ double red[pow2_at_least(S * S) * (NT / 64)];
   const int2 pm = map[blockIdx.x];
   const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, false);
-  chol_store_body<T, S>(a, pm.y, a.nparts, red);
+  chol_store_body<T, S, NT>(a, pm.y, a.nparts, red);
 }
 
 // Second pass step i of every problem in the map: V_{i+1} from V_i, V_{i-1}
 // and log entry i, in the problem's ring of R blocks.
-template <typename T, int S>
-__global__ __launch_bounds__(stream_threads(S)) void kb_replay(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int i) {
+template <typename T, int S, int NT>
+__global__ __launch_bounds__(NT) void kb_replay(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int i) {
   const int2 pm = map[blockIdx.x];
   const BatchDesc<T>& b = d[pm.x];
   const size_t nS = (size_t)b.n * S;
   const T* Vprev = i > 0 ? b.ring + (size_t)((i - 1) % b.R) * nS : b.zero;
   const T* Vcur = b.ring + (size_t)(i % b.R) * nS;
   T* Vnext = b.ring + (size_t)((i + 1) % b.R) * nS;
-  replay_body<T, S>(b.op, b.n, Vprev, Vcur, Vnext, b.log + (size_t)i * log_stride(S), pm.y, b.nparts);
+  replay_body<T, S, NT>(b.op, b.n, Vprev, Vcur, Vnext, b.log + (size_t)i * log_stride(S), pm.y, b.nparts);
 }
 
 // ------------------------------------------------------------------ host launchers
@@ -727,35 +727,53 @@ void launch_zflush(const void* const* blocks, int nb, int n, int S, const double
 
 int zflush_max_blocks(int) { return 64; }
 
+// Grouped launches with nt threads per workgroup: 256 or 1024 for blocks of
+// at most 4 columns (the autotuner's choice), 256 above (register budget).
+#define LYAP_SWITCH_NT(S, ntv, ...)                                              \
+  if ((S) <= 4 && (ntv) == 1024) {                                               \
+    constexpr int NT = 1024;                                                     \
+    __VA_ARGS__;                                                                 \
+  } else {                                                                       \
+    LYAP_REQUIRE((ntv) == 256 || ((ntv) == 1024 && (S) > 4), LYAP_E_ARG,         \
+                 "workgroup size %d not built for block width %d", (ntv), (S));  \
+    constexpr int NT = 256;                                                      \
+    __VA_ARGS__;                                                                 \
+  }
+
+int batch_default_threads(int S) { return stream_threads(S); }
+
 template <typename T>
-void launch_batch_step(const BatchDesc<T>* d, const int2* map, int nwg, int S, int j, hipStream_t st,
+void launch_batch_step(const BatchDesc<T>* d, const int2* map, int nwg, int S, int nt, int j, hipStream_t st,
                        KernelTimer* kt) {
   if (nwg <= 0) return;
   auto mark = [&](int k) { if (kt) kt->mark(k); };
   LYAP_SWITCH_S(S, {
-    constexpr int NT = stream_threads(S);
-    mark(LYAP_K_SPMM_GRAM);
-    hipLaunchKernelGGL((kb_spmm_gram<T, S>), dim3(nwg), dim3(NT), 0, st, d, map, j);
-    mark(LYAP_K_UPD_GRAM);
-    hipLaunchKernelGGL((kb_upd_gram<T, S>), dim3(nwg), dim3(NT), 0, st, d, map, j, 0, (int)L_A1, 1);
-    mark(LYAP_K_UPD_GRAM);
-    hipLaunchKernelGGL((kb_upd_gram<T, S>), dim3(nwg), dim3(NT), 0, st, d, map, j, 1, (int)L_A2, 0);
-    mark(LYAP_K_UPD_GRAM);
-    hipLaunchKernelGGL((kb_upd_gram<T, S>), dim3(nwg), dim3(NT), 0, st, d, map, j, 2, (int)L_A3, 1);
-    mark(LYAP_K_UPD_GRAM);
-    hipLaunchKernelGGL((kb_upd_gram<T, S>), dim3(nwg), dim3(NT), 0, st, d, map, j, 3, (int)L_A4, 0);
-    mark(LYAP_K_CHOL_GRAM);
-    hipLaunchKernelGGL((kb_chol_gram<T, S>), dim3(nwg), dim3(NT), 0, st, d, map, j);
-    mark(LYAP_K_CHOL_STORE);
-    hipLaunchKernelGGL((kb_chol_store<T, S>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+    LYAP_SWITCH_NT(S, nt, {
+      mark(LYAP_K_SPMM_GRAM);
+      hipLaunchKernelGGL((kb_spmm_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+      mark(LYAP_K_UPD_GRAM);
+      hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 0, (int)L_A1, 1);
+      mark(LYAP_K_UPD_GRAM);
+      hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 1, (int)L_A2, 0);
+      mark(LYAP_K_UPD_GRAM);
+      hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 2, (int)L_A3, 1);
+      mark(LYAP_K_UPD_GRAM);
+      hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 3, (int)L_A4, 0);
+      mark(LYAP_K_CHOL_GRAM);
+      hipLaunchKernelGGL((kb_chol_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+      mark(LYAP_K_CHOL_STORE);
+      hipLaunchKernelGGL((kb_chol_store<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+    });
   });
   LYAP_LAUNCHED("batched lanczos step");
 }
 
 template <typename T>
-void launch_batch_replay(const BatchDesc<T>* d, const int2* map, int nwg, int S, int i, hipStream_t st) {
+void launch_batch_replay(const BatchDesc<T>* d, const int2* map, int nwg, int S, int nt, int i, hipStream_t st) {
   if (nwg <= 0) return;
-  LYAP_SWITCH_S(S, { hipLaunchKernelGGL((kb_replay<T, S>), dim3(nwg), dim3(stream_threads(S)), 0, st, d, map, i); });
+  LYAP_SWITCH_S(S, {
+    LYAP_SWITCH_NT(S, nt, { hipLaunchKernelGGL((kb_replay<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, i); });
+  });
   LYAP_LAUNCHED("batched replay");
 }
 
@@ -774,8 +792,9 @@ void launch_apply(const OpDev<T>& op, int S, const T* V, T* W, int grid, hipStre
   template void launch_zflush<T>(const void* const*, int, int, int, const double*, int, double*, int64_t, int, \
                                  hipStream_t);                                                               \
   template void launch_apply<T>(const OpDev<T>&, int, const T*, T*, int, hipStream_t);                     \
-  template void launch_batch_step<T>(const BatchDesc<T>*, const int2*, int, int, int, hipStream_t, KernelTimer*); \
-  template void launch_batch_replay<T>(const BatchDesc<T>*, const int2*, int, int, int, hipStream_t);
+  template void launch_batch_step<T>(const BatchDesc<T>*, const int2*, int, int, int, int, hipStream_t,          \
+                                     KernelTimer*);                                                            \
+  template void launch_batch_replay<T>(const BatchDesc<T>*, const int2*, int, int, int, int, hipStream_t);
 
 LYAP_INST(float)
 LYAP_INST(double)

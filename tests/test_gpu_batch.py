@@ -138,3 +138,35 @@ def test_batched_full_workload(lib):
         one = b.lyap_solve(dops[i], Cs[i], tol=1e-8, storage=b.STORE_F32, check_every=0)
         # the batch's own check schedule (fewer checks) may stop a few percent later
         assert abs(one.m - sols[i].m) <= max(5, 0.1 * one.m)
+
+
+def test_tile_autotuner_persistent_cache(lib, tmp_path, monkeypatch):
+    """tune=2 times every (block width, size bucket, workgroup size) of the
+    batch and writes the results to the file named by LYAP_TUNE_CACHE; a
+    later tune=1 run takes them from the caches.  Every run converges to the
+    same solution as the fixed tile shape (tune=0), within rounding."""
+    b = _b()
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("LYAP_TUNE_CACHE", str(path))
+    probs = _small_batch()
+    dops = [b.device_op(op) for op, _ in probs]
+    Cs = [_dev(C) for _, C in probs]
+    st0, ref = b.lyap_solve_batched(dops, Cs, tune=0, tol=1e-8, check_every=2)
+    st2, sols2 = b.lyap_solve_batched(dops, Cs, tune=2, tol=1e-8, check_every=2)
+    assert st0 == b.OK and st2 == b.OK
+    lines = [ln.split() for ln in path.read_text().splitlines()]
+    # "lyap-tune-1 device storage S bucket threads rows ms"
+    assert lines and all(ln[0] == "lyap-tune-1" and len(ln) == 8 for ln in lines)
+    widths = {C.shape[1] for _, C in probs}
+    # every block width appears, with 256 and (for s <= 4) 1024 threads
+    assert {int(ln[3]) for ln in lines} == widths
+    assert {int(ln[5]) for ln in lines} == {256, 1024}
+    assert all(int(ln[6]) in (2048, 4096, 8192, 16384) and float(ln[7]) > 0 for ln in lines)
+    n_lines = len(lines)
+    st1, sols1 = b.lyap_solve_batched(dops, Cs, tune=1, tol=1e-8, check_every=2)
+    assert st1 == b.OK
+    assert len(path.read_text().splitlines()) == n_lines  # nothing timed again
+    for r, a, c in zip(ref, sols2, sols1):
+        assert a.m == r.m and c.m == r.m
+        assert K.factor_error(a.Z.cpu().numpy(), r.Z.cpu().numpy()) <= 1e-10
+        assert K.factor_error(c.Z.cpu().numpy(), r.Z.cpu().numpy()) <= 1e-10
