@@ -179,8 +179,8 @@ TuneEntry autotune_shape(int S, int64_t n, int nt, bool refresh, hipStream_t st)
   const int nn = N * N;
   const size_t blk = (size_t)nn * S * sizeof(T);
   DevBuf Vb0(blk), Vb1(blk), W(blk), zero(blk), log(4 * log_stride(S) * sizeof(double)),
-      band((size_t)(S + 1) * S * 8 * sizeof(double)), pA((size_t)kSGrid * S * S * sizeof(double)),
-      pB((size_t)kSGrid * S * S * sizeof(double)), flags(64), dd(sizeof(BatchDesc<T>));
+      band((size_t)(S + 1) * S * 8 * sizeof(double)), pA((size_t)kSGrid * 2 * S * S * sizeof(double)),
+      pB((size_t)kSGrid * 2 * S * S * sizeof(double)), flags(64), dd(sizeof(BatchDesc<T>));
   LYAP_HIP(hipMemsetAsync(Vb0.p, 0, blk, st));
   LYAP_HIP(hipMemsetAsync(W.p, 0, blk, st));
   LYAP_HIP(hipMemsetAsync(flags.p, 0, 64, st));
@@ -286,8 +286,8 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
     p->log.alloc(((size_t)maxit + 1) * LS * sizeof(double));
     p->glog.alloc(LS * sizeof(double));
     p->band.alloc((size_t)(p->S + 1) * p->S * (maxit + 2) * sizeof(double));
-    p->partA.alloc((size_t)kSGrid * p->S * p->S * sizeof(double));
-    p->partB.alloc((size_t)kSGrid * p->S * p->S * sizeof(double));
+    p->partA.alloc((size_t)kSGrid * 2 * p->S * p->S * sizeof(double));
+    p->partB.alloc((size_t)kSGrid * 2 * p->S * p->S * sizeof(double));
     LYAP_HIP(hipMemsetAsync(p->zero.p, 0, blk, st));
     LYAP_HIP(hipMemsetAsync(p->Vb0.p, 0, blk, st));
     LYAP_HIP(hipMemsetAsync(p->band.p, 0, p->band.bytes, st));

@@ -167,6 +167,93 @@ __device__ __forceinline__ void upd_gram_body(const StepArgs<T>& a, const T* X, 
   write_partial_at<S * S, NT>(acc, red, a.pout, wg_id);
 }
 
+// Block classical Gram-Schmidt, twice (blocks of at most 4 columns): each
+// sweep takes both coefficient blocks [V_{j-1}, V_j]^T W from one Gram pass
+// and applies them in one update pass, in the order the replay uses
+// (W -= V_{j-1} a1, then W -= V_j a2).  a1, a2 equal the block modified
+// Gram-Schmidt coefficients up to rounding (V_j^T V_{j-1} is O(u)).
+constexpr bool cgs2_width(int S) { return S <= 4; }
+
+// Prologue of a CGS2 sweep: both coefficient blocks from the previous
+// kernel's 2 S x S partials, logged in slot1 / slot2 by workgroup 0.
+template <int S, int NT = stream_threads(S)>
+__device__ __forceinline__ void take_gram2(const double* pin, int nparts, double* red, double (&g1)[S * S],
+                                           double (&g2)[S * S], double* log1, double* log2, bool lead) {
+  reduce_partials<2 * S * S, NT>(pin, nparts, red);
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) {
+    g1[i] = uniform_d(red[i]);
+    g2[i] = uniform_d(red[S * S + i]);
+  }
+  if (lead && threadIdx.x < S * S) {
+    log1[threadIdx.x] = red[threadIdx.x];
+    log2[threadIdx.x] = red[S * S + threadIdx.x];
+  }
+  __syncthreads();  // red is reused by the epilogue
+}
+
+// K1 (CGS2): W = A V_j ; partials [V_{j-1}, V_j]^T W
+template <typename T, int S, int NT = stream_threads(S)>
+__device__ __forceinline__ void spmm_gram2_body(const StepArgs<T>& a, int wg_id, int wg_cnt, double* red) {
+  double acc[2 * S * S];
+#pragma unroll
+  for (int i = 0; i < 2 * S * S; ++i) acc[i] = 0.0;
+  int lo, hi;
+  op_rows(wg_id, wg_cnt, a.n, lo, hi);
+  for (int r = lo + threadIdx.x; r < hi; r += NT) {
+    T w[S], x[S], y[S];
+    op_row<T, S>(a.op, a.Vcur, r, w);
+    load_row<T, S>(a.Vprev + (size_t)r * S, x);
+    load_row<T, S>(a.Vcur + (size_t)r * S, y);
+    store_row<T, S>(a.W + (size_t)r * S, w);
+#pragma unroll
+    for (int p = 0; p < S; ++p)
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        acc[p * S + q] = fma((double)x[p], (double)w[q], acc[p * S + q]);
+        acc[S * S + p * S + q] = fma((double)y[p], (double)w[q], acc[S * S + p * S + q]);
+      }
+  }
+  write_partial_at<2 * S * S, NT>(acc, red, a.pout, wg_id);
+}
+
+// K2 / K3 (CGS2): W -= V_{j-1} c1, W -= V_j c2 with (c1, c2) the totals of the
+// previous partials (logged in slot1, slot2); then the partials
+// [V_{j-1}, V_j]^T W (first sweep) or W^T W (LAST: for the QR that follows).
+template <typename T, int S, bool LAST, int NT = stream_threads(S)>
+__device__ __forceinline__ void upd2_gram_body(const StepArgs<T>& a, int slot1, int slot2, int wg_id, int wg_cnt,
+                                               double* red) {
+  constexpr int K = LAST ? S * S : 2 * S * S;
+  double c1[S * S], c2[S * S];
+  take_gram2<S, NT>(a.pin, a.nparts, red, c1, c2, a.log + slot1 * S * S, a.log + slot2 * S * S, wg_id == 0);
+  double acc[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) acc[i] = 0.0;
+  int lo, hi;
+  op_rows(wg_id, wg_cnt, a.n, lo, hi);
+  for (int r = lo + threadIdx.x; r < hi; r += NT) {
+    T w[S], x[S], y[S];
+    load_row<T, S>(a.W + (size_t)r * S, w);
+    load_row<T, S>(a.Vprev + (size_t)r * S, x);
+    load_row<T, S>(a.Vcur + (size_t)r * S, y);
+    upd_row<T, S>(w, x, c1);
+    upd_row<T, S>(w, y, c2);
+    store_row<T, S>(a.W + (size_t)r * S, w);
+    if constexpr (LAST) {
+      outer_acc<T, T, S>(acc, w, w);
+    } else {
+#pragma unroll
+      for (int p = 0; p < S; ++p)
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+          acc[p * S + q] = fma((double)x[p], (double)w[q], acc[p * S + q]);
+          acc[S * S + p * S + q] = fma((double)y[p], (double)w[q], acc[S * S + p * S + q]);
+        }
+    }
+  }
+  write_partial_at<K, NT>(acc, red, a.pout, wg_id);
+}
+
 // K6: G1 = W^T W (logged), R1 = chol(G1) ; partial (W R1^{-1})^T (W R1^{-1})
 template <typename T, int S, int NT = stream_threads(S)>
 __device__ __forceinline__ void chol_gram_body(const StepArgs<T>& a, int wg_id, int wg_cnt, double* red) {
@@ -309,6 +396,18 @@ template <typename T, int S>
 __global__ __launch_bounds__(stream_threads(S)) void k_upd_gram(StepArgs<T> a, const T* X, const T* Y, int slot_in) {
   __shared__ double red[pow2_at_least(S * S) * (stream_threads(S) / 64)];
   upd_gram_body<T, S>(a, X, Y, slot_in, blockIdx.x, gridDim.x, red);
+}
+
+template <typename T, int S>
+__global__ __launch_bounds__(stream_threads(S)) void k_spmm_gram2(StepArgs<T> a) {
+  __shared__ double red[pow2_at_least(2 * S * S) * (stream_threads(S) / 64)];
+  spmm_gram2_body<T, S>(a, blockIdx.x, gridDim.x, red);
+}
+
+template <typename T, int S, bool LAST>
+__global__ __launch_bounds__(stream_threads(S)) void k_upd2_gram(StepArgs<T> a, int slot1, int slot2) {
+  __shared__ double red[pow2_at_least(2 * S * S) * (stream_threads(S) / 64)];
+  upd2_gram_body<T, S, LAST>(a, slot1, slot2, blockIdx.x, gridDim.x, red);
 }
 
 template <typename T, int S>
@@ -598,6 +697,23 @@ __global__ __launch_bounds__(NT) void kb_upd_gram(const BatchDesc<T>* __restrict
 }
 
 template <typename T, int S, int NT>
+__global__ __launch_bounds__(NT) void kb_spmm_gram2(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j) {
+  __shared__ double red[pow2_at_least(2 * S * S) * (NT / 64)];
+  const int2 pm = map[blockIdx.x];
+  const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, false);
+  spmm_gram2_body<T, S, NT>(a, pm.y, a.nparts, red);
+}
+
+template <typename T, int S, bool LAST, int NT>
+__global__ __launch_bounds__(NT) void kb_upd2_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j,
+                                                  int slot1, int slot2, int flip) {
+  __shared__ double red[pow2_at_least(2 * S * S) * (NT / 64)];
+  const int2 pm = map[blockIdx.x];
+  const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, flip != 0);
+  upd2_gram_body<T, S, LAST, NT>(a, slot1, slot2, pm.y, a.nparts, red);
+}
+
+template <typename T, int S, int NT>
 __global__ __launch_bounds__(NT) void kb_chol_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j) {
   __shared__ double red[pow2_at_least(S * S) * (NT / 64)];
   const int2 pm = map[blockIdx.x];
@@ -647,27 +763,47 @@ void launch_step(const StepArgs<T>& a0, int S, int grid, double* partA, double* 
   a.nparts = grid;
   auto mark = [&](int k) { if (kt) kt->mark(k); };
   LYAP_SWITCH_S(S, {
-    a.pin = nullptr; a.pout = partA;
-    mark(LYAP_K_SPMM_GRAM);
-    hipLaunchKernelGGL((k_spmm_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a);
-    a.pin = partA; a.pout = partB;
-    mark(LYAP_K_UPD_GRAM);
-    hipLaunchKernelGGL((k_upd_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a, a.Vprev, a.Vcur, (int)L_A1);
-    a.pin = partB; a.pout = partA;
-    mark(LYAP_K_UPD_GRAM);
-    hipLaunchKernelGGL((k_upd_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a, a.Vcur, a.Vprev, (int)L_A2);
-    a.pin = partA; a.pout = partB;
-    mark(LYAP_K_UPD_GRAM);
-    hipLaunchKernelGGL((k_upd_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a, a.Vprev, a.Vcur, (int)L_A3);
-    a.pin = partB; a.pout = partA;
-    mark(LYAP_K_UPD_GRAM);
-    hipLaunchKernelGGL((k_upd_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a, a.Vcur, (const T*)nullptr, (int)L_A4);
-    a.pin = partA; a.pout = partB;
-    mark(LYAP_K_CHOL_GRAM);
-    hipLaunchKernelGGL((k_chol_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a);
-    a.pin = partB; a.pout = partA;
-    mark(LYAP_K_CHOL_STORE);
-    hipLaunchKernelGGL((k_chol_store<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a);
+    if constexpr (cgs2_width(S)) {
+      a.pin = nullptr; a.pout = partA;
+      mark(LYAP_K_SPMM_GRAM);
+      hipLaunchKernelGGL((k_spmm_gram2<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a);
+      a.pin = partA; a.pout = partB;
+      mark(LYAP_K_UPD_GRAM);
+      hipLaunchKernelGGL((k_upd2_gram<T, S, false>), dim3(grid), dim3(stream_threads(S)), 0, st, a, (int)L_A1,
+                         (int)L_A2);
+      a.pin = partB; a.pout = partA;
+      mark(LYAP_K_UPD_GRAM);
+      hipLaunchKernelGGL((k_upd2_gram<T, S, true>), dim3(grid), dim3(stream_threads(S)), 0, st, a, (int)L_A3,
+                         (int)L_A4);
+      a.pin = partA; a.pout = partB;
+      mark(LYAP_K_CHOL_GRAM);
+      hipLaunchKernelGGL((k_chol_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a);
+      a.pin = partB; a.pout = partA;
+      mark(LYAP_K_CHOL_STORE);
+      hipLaunchKernelGGL((k_chol_store<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a);
+    } else {
+      a.pin = nullptr; a.pout = partA;
+      mark(LYAP_K_SPMM_GRAM);
+      hipLaunchKernelGGL((k_spmm_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a);
+      a.pin = partA; a.pout = partB;
+      mark(LYAP_K_UPD_GRAM);
+      hipLaunchKernelGGL((k_upd_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a, a.Vprev, a.Vcur, (int)L_A1);
+      a.pin = partB; a.pout = partA;
+      mark(LYAP_K_UPD_GRAM);
+      hipLaunchKernelGGL((k_upd_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a, a.Vcur, a.Vprev, (int)L_A2);
+      a.pin = partA; a.pout = partB;
+      mark(LYAP_K_UPD_GRAM);
+      hipLaunchKernelGGL((k_upd_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a, a.Vprev, a.Vcur, (int)L_A3);
+      a.pin = partB; a.pout = partA;
+      mark(LYAP_K_UPD_GRAM);
+      hipLaunchKernelGGL((k_upd_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a, a.Vcur, (const T*)nullptr, (int)L_A4);
+      a.pin = partA; a.pout = partB;
+      mark(LYAP_K_CHOL_GRAM);
+      hipLaunchKernelGGL((k_chol_gram<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a);
+      a.pin = partB; a.pout = partA;
+      mark(LYAP_K_CHOL_STORE);
+      hipLaunchKernelGGL((k_chol_store<T, S>), dim3(grid), dim3(stream_threads(S)), 0, st, a);
+    }
   });
   LYAP_LAUNCHED("lanczos step");
 }
@@ -749,20 +885,35 @@ void launch_batch_step(const BatchDesc<T>* d, const int2* map, int nwg, int S, i
   auto mark = [&](int k) { if (kt) kt->mark(k); };
   LYAP_SWITCH_S(S, {
     LYAP_SWITCH_NT(S, nt, {
-      mark(LYAP_K_SPMM_GRAM);
-      hipLaunchKernelGGL((kb_spmm_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
-      mark(LYAP_K_UPD_GRAM);
-      hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 0, (int)L_A1, 1);
-      mark(LYAP_K_UPD_GRAM);
-      hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 1, (int)L_A2, 0);
-      mark(LYAP_K_UPD_GRAM);
-      hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 2, (int)L_A3, 1);
-      mark(LYAP_K_UPD_GRAM);
-      hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 3, (int)L_A4, 0);
-      mark(LYAP_K_CHOL_GRAM);
-      hipLaunchKernelGGL((kb_chol_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
-      mark(LYAP_K_CHOL_STORE);
-      hipLaunchKernelGGL((kb_chol_store<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+      if constexpr (cgs2_width(S)) {
+        mark(LYAP_K_SPMM_GRAM);
+        hipLaunchKernelGGL((kb_spmm_gram2<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+        mark(LYAP_K_UPD_GRAM);
+        hipLaunchKernelGGL((kb_upd2_gram<T, S, false, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, (int)L_A1,
+                           (int)L_A2, 1);
+        mark(LYAP_K_UPD_GRAM);
+        hipLaunchKernelGGL((kb_upd2_gram<T, S, true, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, (int)L_A3,
+                           (int)L_A4, 0);
+        mark(LYAP_K_CHOL_GRAM);
+        hipLaunchKernelGGL((kb_chol_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+        mark(LYAP_K_CHOL_STORE);
+        hipLaunchKernelGGL((kb_chol_store<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+      } else {
+        mark(LYAP_K_SPMM_GRAM);
+        hipLaunchKernelGGL((kb_spmm_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+        mark(LYAP_K_UPD_GRAM);
+        hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 0, (int)L_A1, 1);
+        mark(LYAP_K_UPD_GRAM);
+        hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 1, (int)L_A2, 0);
+        mark(LYAP_K_UPD_GRAM);
+        hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 2, (int)L_A3, 1);
+        mark(LYAP_K_UPD_GRAM);
+        hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 3, (int)L_A4, 0);
+        mark(LYAP_K_CHOL_GRAM);
+        hipLaunchKernelGGL((kb_chol_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+        mark(LYAP_K_CHOL_STORE);
+        hipLaunchKernelGGL((kb_chol_store<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+      }
     });
   });
   LYAP_LAUNCHED("batched lanczos step");

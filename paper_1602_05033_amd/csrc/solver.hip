@@ -109,7 +109,8 @@ template <typename T>
 void fill_kernel_bytes(int n, int S, double coef, const KernelTimer& kt, double zflush_bytes, double* kb) {
   const double nsb = (double)n * S * sizeof(T);
   kb[LYAP_K_SPMM_GRAM] = 3.0 * nsb + coef * n;
-  kb[LYAP_K_UPD_GRAM] = 3.75 * nsb;
+  // CGS2 (S <= 4): two update sweeps of 4 nsb; block MGS twice: four of 3.75 nsb on average
+  kb[LYAP_K_UPD_GRAM] = (S <= 4 ? 4.0 : 3.75) * nsb;
   kb[LYAP_K_CHOL_GRAM] = 1.0 * nsb;
   kb[LYAP_K_CHOL_STORE] = 2.0 * nsb;
   kb[LYAP_K_REPLAY] = 3.0 * nsb + coef * n;
@@ -135,8 +136,9 @@ LanczosSide<T>::LanczosSide(const lyap_op* A, const double* C, int S, int64_t ld
   logb_.alloc(((size_t)maxit_ + 1) * LS_ * sizeof(double));
   glog_.alloc(LS_ * sizeof(double));
   band_.alloc((size_t)(S + 1) * S * (maxit_ + 2) * sizeof(double));
-  partA_.alloc((size_t)kSGrid * S * S * sizeof(double));
-  partB_.alloc((size_t)kSGrid * S * S * sizeof(double));
+  // partial Gram matrices of every workgroup: 2 S x S per workgroup in the CGS2 sweeps
+  partA_.alloc((size_t)kSGrid * 2 * S * S * sizeof(double));
+  partB_.alloc((size_t)kSGrid * 2 * S * S * sizeof(double));
   flags_.alloc(64);
   hflags_.alloc(64);
   LYAP_HIP(hipMemsetAsync(flags_.p, 0, 64, st_));
@@ -468,7 +470,8 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   out->times_ms[LYAP_T_TO_TOL] = t_to_tol;
   const double b = sizeof(T);
   const double coef = side.op().coef_bytes_per_row();
-  out->bytes_pass1 = (int64_t)((double)m * n * (21.0 * S * b + coef));
+  // per step: 14 nsb with CGS2 (S <= 4), 21 nsb with block MGS twice
+  out->bytes_pass1 = (int64_t)((double)m * n * ((S <= 4 ? 14.0 : 21.0) * S * b + coef));
   out->bytes_spmm = (int64_t)((double)m * n * (2.0 * S * b + coef));
   for (int i = 0; i < LYAP_K_COUNT; ++i) {
     out->kern_ms[i] = kt.ms[i];
