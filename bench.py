@@ -57,6 +57,9 @@ def pcnet_points(nx, ny, nz):
 # WRITE_SIZE 262144 KiB for 262144 KiB written).  Valid only for the kernel
 # build they were taken on; the bench reports null for anything else.
 HBM_COUNTERS = {
+    # k_upd2_gram<float, 4, *> (the two CGS2 update sweeps; median of the two kernels' medians)
+    ("upd_gram", 1000000, 4, "f32"): {"fetch_kib": 23773.2, "write_kib": 15687.6,
+                                      "fetch_scale": 262144.0 / 131092.31, "write_scale": 1.0},
     # k_cgcg_iter<1, 1024> of the extended Krylov run (inner Jacobi-PCG, FP64)
     ("cg_dir", 1000000, 1, "f64"): {"fetch_kib": 56843.59375, "write_kib": 39733.21875,
                                     "fetch_scale": 262144.0 / 131088.75, "write_scale": 1.0},
