@@ -505,7 +505,8 @@ lyap_status lyap_pcnet_fcg(const lyap_op* A, int32_t C, const float* W, const do
  * zero (D_S^{-1} = s = 0 there).  Zero weights give IC(0) itself.  Training
  * pairs (r_i, e_i), Sigma e_i = r_i, come from the first inner solve (the
  * condensed IC(0) CG, every 16 iterations, at most 16); the loss is
- * (M r - e)^T Sigma (M r - e) / e^T Sigma e; 200 Adam steps as above; later
+ * (M r - e)^T Sigma (M r - e) / e^T Sigma e; 50 Adam steps at learning rate
+ * 1e-2 inside lyap_solve (the entry points below take steps and rate); later
  * solves run flexible CG on Sigma with M, then the red cells are solved for,
  * and the whole-grid true residual certifies each solve.  C = 2 in the solver.
  * The two entry points below expose this for testing (W as above, b, B, X
