@@ -79,57 +79,101 @@ __global__ void k_ext_merge(const double* __restrict__ A1, int lda1, const doubl
   }
 }
 
+// Gram partials of up to NB consecutive blocks against Y in one pass over Y
+// (Y is read once per NB blocks instead of once per block):
 // part[(b * G + g) * L*L + p*L + q] = sum over the rows of workgroup g of
-// X_b[r][p] * Y[r][q]; grid (G, nb).
+// X_b[r][p] * Y[r][q], b = blockIdx.y * NB + i < nb; grid (G, ceil(nb / NB)).
 template <int L>
-__global__ __launch_bounds__(kExtThreads) void k_ext_gram(const double* const* X, const double* __restrict__ Y, int n,
-                                                         double* part) {
-  __shared__ double red[pow2_at_least(L * L) * (kExtThreads / 64)];
-  const double* __restrict__ Xb = X[blockIdx.y];
-  double acc[L * L];
+constexpr int gram_chunk() {
+  return L <= 2 ? 8 : (L <= 4 ? 4 : 1);
+}
+
+template <int L>
+__global__ __launch_bounds__(kExtThreads) void k_ext_gram(const double* const* X, int nb, const double* __restrict__ Y,
+                                                         int n, double* part) {
+  constexpr int NB = gram_chunk<L>();
+  constexpr int LL = L * L, K = NB * LL;
+  __shared__ double red[pow2_at_least(K) * (kExtThreads / 64)];
+  const int b0 = blockIdx.y * NB;
+  const int nbl = min(NB, nb - b0);  // blocks of this chunk (uniform)
+  const double* Xb[NB];
 #pragma unroll
-  for (int e = 0; e < L * L; ++e) acc[e] = 0.0;
+  for (int i = 0; i < NB; ++i) Xb[i] = X[b0 + (i < nbl ? i : 0)];
+  double acc[K];
+#pragma unroll
+  for (int e = 0; e < K; ++e) acc[e] = 0.0;
   for (int r = blockIdx.x * kExtThreads + threadIdx.x; r < n; r += gridDim.x * kExtThreads) {
-    double x[L], y[L];
-    load_row<double, L>(Xb + (size_t)r * L, x);
+    double y[L], x[NB][L];
     load_row<double, L>(Y + (size_t)r * L, y);
 #pragma unroll
-    for (int p = 0; p < L; ++p)
+    for (int i = 0; i < NB; ++i)
+      if (i < nbl) load_row<double, L>(Xb[i] + (size_t)r * L, x[i]);
 #pragma unroll
-      for (int q = 0; q < L; ++q) acc[p * L + q] = fma(x[p], y[q], acc[p * L + q]);
+    for (int i = 0; i < NB; ++i)
+      if (i < nbl)
+#pragma unroll
+        for (int p = 0; p < L; ++p)
+#pragma unroll
+          for (int q = 0; q < L; ++q) acc[i * LL + p * L + q] = fma(x[i][p], y[q], acc[i * LL + p * L + q]);
   }
-  write_partial<L * L, kExtThreads>(acc, red, part + (size_t)blockIdx.y * gridDim.x * L * L);
+  block_sum<K, kExtThreads>(acc, red);
+  if (threadIdx.x < K) {
+    const int i = threadIdx.x / LL, e = threadIdx.x - i * LL;
+    if (i < nbl) part[((size_t)(b0 + i) * gridDim.x + blockIdx.x) * LL + e] = red[threadIdx.x];
+  }
 }
 
-// H[b * LL + e] = sum_g part[(b * G + g) * LL + e], in order of g.
-__global__ void k_ext_sum(const double* __restrict__ part, int G, int nb, int LL, double* __restrict__ H) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb * LL) return;
+// H[b * LL + e] = sum_g part[(b * G + g) * LL + e]: one wave per entry (lanes
+// take g = lane, lane + 64, ..., then a butterfly; a fixed order).
+__global__ __launch_bounds__(256) void k_ext_sum(const double* __restrict__ part, int G, int nb, int LL,
+                                                 double* __restrict__ H) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= nb * LL) return;  // the whole wave
   const int b = i / LL, e = i - b * LL;
+  const double* src = part + (size_t)b * G * LL + e;
   double s = 0.0;
-  for (int g = 0; g < G; ++g) s += part[((size_t)b * G + g) * LL + e];
-  H[i] = s;
+  for (int g = lane; g < G; g += 64) s += src[(size_t)g * LL];
+  s = wave_sum(s);
+  if (lane == 0) H[i] = s;
 }
 
-// W -= sum_b X_b H_b.
+// W -= sum_b X_b H_b; the rows of U blocks are loaded before they are used
+// (one 16-byte row per block and thread would leave too few bytes in flight).
 template <int L>
 __global__ __launch_bounds__(kExtThreads) void k_ext_update(const double* const* X, int nb, const double* __restrict__ H,
                                                            double* __restrict__ W, int n) {
+  constexpr int U = L <= 2 ? 8 : (L <= 4 ? 4 : 2);
+  constexpr int LL = L * L;
   for (int r = blockIdx.x * kExtThreads + threadIdx.x; r < n; r += gridDim.x * kExtThreads) {
-    double w[L];
-    load_row<double, L>(W + (size_t)r * L, w);
     double acc[L];
 #pragma unroll
     for (int c = 0; c < L; ++c) acc[c] = 0.0;
-    for (int b = 0; b < nb; ++b) {
+    int b = 0;
+    for (; b + U <= nb; b += U) {
+      double x[U][L];
+#pragma unroll
+      for (int u = 0; u < U; ++u) load_row<double, L>(X[b + u] + (size_t)r * L, x[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double* h = H + (size_t)(b + u) * LL;
+#pragma unroll
+        for (int a = 0; a < L; ++a)
+#pragma unroll
+          for (int c = 0; c < L; ++c) acc[c] = fma(x[u][a], h[a * L + c], acc[c]);
+      }
+    }
+    for (; b < nb; ++b) {
       double x[L];
       load_row<double, L>(X[b] + (size_t)r * L, x);
-      const double* h = H + (size_t)b * L * L;
+      const double* h = H + (size_t)b * LL;
 #pragma unroll
       for (int a = 0; a < L; ++a)
 #pragma unroll
         for (int c = 0; c < L; ++c) acc[c] = fma(x[a], h[a * L + c], acc[c]);
     }
+    double w[L];
+    load_row<double, L>(W + (size_t)r * L, w);
 #pragma unroll
     for (int c = 0; c < L; ++c) w[c] -= acc[c];
     store_row<double, L>(W + (size_t)r * L, w);
@@ -208,7 +252,9 @@ __global__ void k_ext_gamma(const double* R, int s, double* gamma) {
 namespace {
 
 struct ExtWork {
-  int n, S, L, G;
+  int n, S, L;
+  int G;   // Gram partials per block (workgroups along the rows)
+  int Gu;  // workgroups of the row sweeps (update, scale)
   hipStream_t st;
   DevBuf part, H, small, flags;
   size_t part_blocks = 0;
@@ -225,11 +271,13 @@ struct ExtWork {
 
 template <int L>
 void gram(ExtWork& w, const double* const* X, int nb, const double* Y) {
+  constexpr int NB = gram_chunk<L>();
   w.ensure(nb);
-  hipLaunchKernelGGL((k_ext_gram<L>), dim3(w.G, nb), dim3(kExtThreads), 0, w.st, X, Y, w.n, w.part.as<double>());
+  hipLaunchKernelGGL((k_ext_gram<L>), dim3(w.G, (nb + NB - 1) / NB), dim3(kExtThreads), 0, w.st, X, nb, Y, w.n,
+                     w.part.as<double>());
   LYAP_LAUNCHED("k_ext_gram");
   const int tot = nb * L * L;
-  hipLaunchKernelGGL(k_ext_sum, dim3((tot + 255) / 256), dim3(256), 0, w.st, w.part.as<double>(), w.G, nb, L * L,
+  hipLaunchKernelGGL(k_ext_sum, dim3((tot + 3) / 4), dim3(256), 0, w.st, w.part.as<double>(), w.G, nb, L * L,
                      w.H.as<double>());
   LYAP_LAUNCHED("k_ext_sum");
 }
@@ -243,11 +291,11 @@ void cholqr2(ExtWork& w, const double* const* wlist, double* W, const double* co
   gram<L>(w, wlist, 1, W);
   hipLaunchKernelGGL((k_ext_chol<L>), dim3(1), dim3(64), 0, w.st, w.H.as<double>(), (const double*)nullptr, sm, w.S,
                      w.flags.as<int>(), tag);
-  hipLaunchKernelGGL((k_ext_scale<L>), dim3(w.G), dim3(kExtThreads), 0, w.st, W, sm + LL, out, w.n);
+  hipLaunchKernelGGL((k_ext_scale<L>), dim3(w.Gu), dim3(kExtThreads), 0, w.st, W, sm + LL, out, w.n);
   gram<L>(w, olist, 1, out);
   hipLaunchKernelGGL((k_ext_chol<L>), dim3(1), dim3(64), 0, w.st, w.H.as<double>(), sm, sm + 4 * LL, w.S,
                      w.flags.as<int>(), tag);
-  hipLaunchKernelGGL((k_ext_scale<L>), dim3(w.G), dim3(kExtThreads), 0, w.st, out, sm + 5 * LL, out, w.n);
+  hipLaunchKernelGGL((k_ext_scale<L>), dim3(w.Gu), dim3(kExtThreads), 0, w.st, out, sm + 5 * LL, out, w.n);
   LYAP_HIP(hipMemcpyAsync(Rdst, sm + 6 * LL, LL * sizeof(double), hipMemcpyDeviceToDevice, w.st));
   LYAP_LAUNCHED("cholqr2");
 }
@@ -272,13 +320,15 @@ class ExtSide {
     w_.n = n_;
     w_.S = S;
     w_.L = L;
-    w_.G = stream_grid(n_);
+    w_.G = grid_for(n_, 1, 1024);
+    w_.Gu = grid_for(n_, 1, 2048);
     w_.st = st;
     w_.small.alloc(9 * LL * sizeof(double));
     w_.flags.alloc(64);
     LYAP_HIP(hipMemsetAsync(w_.flags.p, 0, 64, st));
     V_.reserve((size_t)maxit_ + 2);
     ptrs_.alloc(((size_t)maxit_ + 2) * sizeof(void*));
+    hptrs_.alloc(((size_t)maxit_ + 2) * sizeof(void*));
     wlist_.alloc(sizeof(void*));
     AV_.alloc(blkL_);
     W_.alloc(blkL_);
@@ -353,7 +403,7 @@ class ExtSide {
                        W_.as<double>());
     for (int sweep = 0; sweep < 2; ++sweep) {
       gram<L>(w_, dptrs(), j + 1, W_.as<double>());
-      hipLaunchKernelGGL((k_ext_update<L>), dim3(w_.G), dim3(kExtThreads), 0, st_, dptrs(), j + 1,
+      hipLaunchKernelGGL((k_ext_update<L>), dim3(w_.Gu), dim3(kExtThreads), 0, st_, dptrs(), j + 1,
                          w_.H.as<double>(), W_.as<double>(), n_);
       LYAP_LAUNCHED("k_ext_update");
     }
@@ -378,10 +428,14 @@ class ExtSide {
   }
 
  private:
+  // A new basis block; its address goes to the device table from a pinned
+  // slot written once (an ordered asynchronous copy, no host wait).
   double* new_block() {
     V_.emplace_back(blkL_);
-    const void* p = V_.back().p;
-    LYAP_HIP(hipMemcpy(ptrs_.as<const void*>() + (V_.size() - 1), &p, sizeof(void*), hipMemcpyHostToDevice));
+    const size_t i = V_.size() - 1;
+    hptrs_.as<const void*>()[i] = V_.back().p;
+    LYAP_HIP(hipMemcpyAsync(ptrs_.as<const void*>() + i, hptrs_.as<const void*>() + i, sizeof(void*),
+                            hipMemcpyHostToDevice, st_));
     return V_.back().as<double>();
   }
   const double* const* dptrs() const { return ptrs_.as<const double*>(); }
@@ -397,6 +451,7 @@ class ExtSide {
   ExtWork w_;
   std::vector<DevBuf> V_;
   DevBuf ptrs_, wlist_, AV_, W_, Bs_, Xs_, band_, taulog_, R0_, gamma_;
+  HostBuf hptrs_;
 };
 
 template <int S>
