@@ -406,6 +406,17 @@ def main_batch(args):
     ms_per_step = (time.perf_counter() - t0) * 1000.0 / args.steps
     st, sols = timed[-1]
     assert st == b.OK, st
+    # the same solves with the first pass replaying one captured graph per step
+    b.lyap_solve_batched(dops, Cs, graphs=True, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gtimed = [b.lyap_solve_batched(dops, Cs, graphs=True, **kw) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    ms_graphs = (time.perf_counter() - t0) * 1000.0 / args.steps
+    gst, gsols = gtimed[-1]
+    assert gst == b.OK, gst
+    graphs = {"ms_per_step": round(ms_graphs, 2), "total_steps": sum(s.m for s in gsols),
+              "phases_ms": {k: round(v, 2) for k, v in gsols[0].times_ms.items()}}
     # per-kernel HIP-event timing in a separate, untimed solve (with profiling
     # on, the checks run on the solver's stream instead of overlapping)
     runs = [b.lyap_solve_batched(dops, Cs, profile=True, **kw)]
@@ -436,7 +447,8 @@ def main_batch(args):
                    "count": 64, "sum_n": n_tot, "storage": args.storage, "tune": True},
         "result": {"m": [s.m for s in sols], "t": [s.t for s in sols], "total_steps": steps_all,
                    "phases_ms": {k: round(v, 2) for k, v in sols[0].times_ms.items()},
-                   "phases_ms_profiled": {k: round(v, 2) for k, v in runs[0][1][0].times_ms.items()}},
+                   "phases_ms_profiled": {k: round(v, 2) for k, v in runs[0][1][0].times_ms.items()},
+                   "step_graphs": graphs},
         "kernels": kernel_table(agg),
         "roofline": roofline(agg, ("spmm_gram", "upd_gram", "chol_gram", "chol_store", "replay")),
         "block_bytes_sum": nsb_tot,

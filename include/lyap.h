@@ -410,6 +410,9 @@ lyap_status lyap_ctri(const double* T_band, int32_t ell, int32_t k, const double
 lyap_status lyap_inner_solve(const lyap_op* A, const double* B, int64_t ldb, double* X, int64_t ldx, int32_t s,
                              const lyap_opts* opts, int64_t* iters, double* relres);
 
+/* flag of lyap_solve_batched's tune argument */
+#define LYAP_BATCH_GRAPHS 4
+
 /*
  * lyap_solve_batched -- `count` independent equations A_i X + X A_i + C_i C_i^T = 0
  * advanced together: the block Lanczos steps of all unconverged problems of
@@ -435,6 +438,13 @@ lyap_status lyap_inner_solve(const lyap_op* A, const double* B, int64_t ldb, dou
  *         a file that cannot be read or written is ignored); 2: as 1 but
  *         timing again and replacing what the caches hold.  Autotuned runs
  *         are reproducible when the same shapes are chosen.
+ *         Or-ed with LYAP_BATCH_GRAPHS: the first pass issues every step of
+ *         all problems as one replay of a captured HIP graph (the grouped
+ *         step kernels of every block width, the step index read from device
+ *         memory), captured again whenever a work map changes; the work runs
+ *         on a stream of the solver's own, ordered after opts->stream, and
+ *         the results are bit-identical to direct launches.  Not combined
+ *         with opts->profile (LYAP_E_ARG).
  *  out    array of `count` results, filled like lyap_solve's; phase times are
  *         those of the whole batch (times_ms[LYAP_T_TO_TOL] is per problem);
  *         kern_ms / kern_n of out[0] cover the whole batch.

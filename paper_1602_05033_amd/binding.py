@@ -357,9 +357,13 @@ def _solution(r, st, alloc, n, device, msg) -> LyapSolution:
     return sol
 
 
-def lyap_solve_batched(dops, Cs, tune: bool = False, raise_on_error: bool = True, **kw):
+BATCH_GRAPHS = 4  # LYAP_BATCH_GRAPHS
+
+
+def lyap_solve_batched(dops, Cs, tune: bool = False, raise_on_error: bool = True, graphs: bool = False, **kw):
     """Solve a batch of Lyapunov equations in grouped launches.  ``dops``:
-    list of DeviceOp; ``Cs``: list of (n_i, s_i) float64 device tensors.
+    list of DeviceOp; ``Cs``: list of (n_i, s_i) float64 device tensors;
+    ``graphs``: replay one captured graph per first-pass step.
     Returns (status, [LyapSolution])."""
     import torch
     lib = load()
@@ -375,7 +379,8 @@ def lyap_solve_batched(dops, Cs, tune: bool = False, raise_on_error: bool = True
     o.alloc, o.release = alloc.alloc_cb, alloc.free_cb
     res = (LyapResult * count)()
     # tune: False / 0 fixed tile shape, True / 1 autotuned (persistent cache), 2 re-tune
-    st = lib.lyap_solve_batched(count, ops, ptrs, ss, lds, ct.byref(o), int(tune), res)
+    st = lib.lyap_solve_batched(count, ops, ptrs, ss, lds, ct.byref(o), int(tune) | (BATCH_GRAPHS if graphs else 0),
+                                res)
     msg = lib.lyap_last_error().decode()
     try:
         if raise_on_error and st not in (OK, NOT_CONVERGED):

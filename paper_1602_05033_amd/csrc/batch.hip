@@ -239,11 +239,38 @@ TuneEntry autotune_shape(int S, int64_t n, int nt, bool refresh, hipStream_t st)
   return best;
 }
 
+// The step index of replayed step graphs, on the device: set when a graph is
+// captured, advanced by the last node of every replay.
+__global__ void k_step_set(int* jp, int j) {
+  if (threadIdx.x == 0) *jp = j;
+}
+__global__ void k_step_next(int* jp) {
+  if (threadIdx.x == 0) *jp += 1;
+}
+
 template <typename T>
 lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, const int32_t* s, const int64_t* ldc,
                          const lyap_opts& o, int tune, lyap_result* out) {
   const auto t_entry = Clock::now();
+  // LYAP_BATCH_GRAPHS: pass 1 replays one captured graph per step (all
+  // groups' step kernels) instead of launching them one by one; capture needs
+  // a stream of its own, ordered after the caller's
+  const bool graphs = (tune & LYAP_BATCH_GRAPHS) != 0;
+  tune &= 3;
+  struct OwnStream {
+    hipStream_t s = nullptr;
+    ~OwnStream() { if (s) (void)hipStreamDestroy(s); }
+  } own;
   hipStream_t st = (hipStream_t)o.stream;
+  if (graphs) {
+    LYAP_HIP(hipStreamCreateWithFlags(&own.s, hipStreamNonBlocking));
+    hipEvent_t e;
+    LYAP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    LYAP_HIP(hipEventRecord(e, st));
+    LYAP_HIP(hipStreamWaitEvent(own.s, e, 0));
+    LYAP_HIP(hipEventDestroy(e));
+    st = own.s;
+  }
   const int maxit = o.max_iter;
   KernelTimer kt;
   kt.st = st;
@@ -384,7 +411,23 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
     if (o.verbose)
       std::fprintf(stderr, "[batch] width %d: %d threads per workgroup\n", widths[g], groups[g].nt);
   }
+  DevBuf dstep(64);  // the step index of the replayed graphs
+  // captured step graphs, one per stretch of steps whose work maps do not
+  // change (an upload ends the stretch); destroyed once the stream is idle
+  struct StepGraphs {
+    hipStream_t st = nullptr;
+    std::vector<hipGraph_t> g;
+    std::vector<hipGraphExec_t> x;
+    ~StepGraphs() {
+      if (st) (void)hipStreamSynchronize(st);
+      for (auto e : x) (void)hipGraphExecDestroy(e);
+      for (auto h : g) (void)hipGraphDestroy(h);
+    }
+  } sgs;
+  sgs.st = st;
+  bool sg_valid = false;
   auto upload = [&](Group& g, bool replay, int step) {
+    sg_valid = false;
     if (!g.desc.p) {  // sized once: every problem of the group, every workgroup of each
       size_t wgs = 0;
       for (Problem<T>* p : g.probs) wgs += p->nparts;
@@ -556,6 +599,34 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
     if (!overlap) kt.collect();
   };
 
+  // one step of every group as a graph: the kernels read the step index from
+  // dstep, which the graph's last node advances
+  auto capture_step = [&](int j0) {
+    int* jp = dstep.template as<int>();
+    hipLaunchKernelGGL(k_step_set, dim3(1), dim3(64), 0, st, jp, j0);
+    LYAP_LAUNCHED("k_step_set");
+    LYAP_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipGraph_t gr = nullptr;
+    try {
+      for (auto& g : groups)
+        if (g.nwg > 0)
+          launch_batch_step<T>(g.desc.template as<BatchDesc<T>>(), g.map.template as<int2>(), g.nwg, g.S, g.nt, j0,
+                               st, nullptr, jp);
+      hipLaunchKernelGGL(k_step_next, dim3(1), dim3(64), 0, st, jp);
+      LYAP_LAUNCHED("k_step_next");
+    } catch (...) {
+      (void)hipStreamEndCapture(st, &gr);
+      if (gr) (void)hipGraphDestroy(gr);
+      throw;
+    }
+    LYAP_HIP(hipStreamEndCapture(st, &gr));
+    sgs.g.push_back(gr);
+    hipGraphExec_t ex = nullptr;
+    LYAP_HIP(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+    sgs.x.push_back(ex);
+    sg_valid = true;
+  };
+
   const auto t_pass1 = Clock::now();
   int j = 0;
   while (n_active > 0) {
@@ -575,10 +646,15 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
     // a problem whose check is still in flight keeps stepping (its next check
     // is decided when the result arrives)
     if (j >= kAhead) LYAP_HIP(hipEventSynchronize(er.ev[j % kAhead]));
-    for (auto& g : groups)
-      if (g.nwg > 0)
-        launch_batch_step<T>(g.desc.template as<BatchDesc<T>>(), g.map.template as<int2>(), g.nwg, g.S, g.nt, j, st,
-                             &kt);
+    if (graphs) {
+      if (!sg_valid) capture_step(j);
+      LYAP_HIP(hipGraphLaunch(sgs.x.back(), st));
+    } else {
+      for (auto& g : groups)
+        if (g.nwg > 0)
+          launch_batch_step<T>(g.desc.template as<BatchDesc<T>>(), g.map.template as<int2>(), g.nwg, g.S, g.nt, j,
+                               st, &kt);
+    }
     LYAP_HIP(hipEventRecord(er.ev[j % kAhead], st));
     ++j;
     for (auto& p : P)
@@ -760,7 +836,10 @@ extern "C" lyap_status lyap_solve_batched(int32_t count, const lyap_op* A, const
     LYAP_REQUIRE(o.max_iter >= 1 && (int64_t)o.max_iter * 8 <= (int64_t)1 << 20, LYAP_E_ARG,
                  "max_iter=%d out of range", o.max_iter);
     LYAP_REQUIRE(o.check_every >= 0, LYAP_E_ARG, "check_every must be >= 0");
-    LYAP_REQUIRE(tune >= 0 && tune <= 2, LYAP_E_ARG, "tune=%d must be 0, 1 or 2", tune);
+    LYAP_REQUIRE((tune & ~(3 | LYAP_BATCH_GRAPHS)) == 0 && (tune & 3) <= 2, LYAP_E_ARG,
+                 "tune=%d must be 0, 1 or 2, optionally with LYAP_BATCH_GRAPHS", tune);
+    LYAP_REQUIRE(!(tune & LYAP_BATCH_GRAPHS) || o.profile == 0, LYAP_E_ARG,
+                 "LYAP_BATCH_GRAPHS cannot be combined with per-kernel profiling");
     LYAP_REQUIRE(o.method == LYAP_METHOD_STD, LYAP_E_UNSUPPORTED, "the batched solver builds standard Krylov spaces");
     LYAP_REQUIRE(o.two_pass != 0, LYAP_E_UNSUPPORTED, "the batched solver uses the two-pass strategy");
     LYAP_REQUIRE(o.storage == LYAP_STORE_F64 || o.storage == LYAP_STORE_F32, LYAP_E_ARG, "unknown storage %d",

@@ -677,19 +677,21 @@ __device__ __forceinline__ StepArgs<T> batch_args(const BatchDesc<T>& d, int j, 
 }
 
 template <typename T, int S, int NT>
-__global__ __launch_bounds__(NT) void kb_spmm_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j) {
+__global__ __launch_bounds__(NT) void kb_spmm_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, const int* jp, int j) {
   __shared__ double red[pow2_at_least(S * S) * (NT / 64)];
   const int2 pm = map[blockIdx.x];
+  if (jp) j = *jp;  // the step index held on the device (replayed graphs)
   const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, false);
   spmm_gram_body<T, S, NT>(a, pm.y, a.nparts, red);
 }
 
 // mode 0: X = V_{j-1}, Y = V_j; 1: X = V_j, Y = V_{j-1}; 2: as 0; 3: X = V_j, Y = none
 template <typename T, int S, int NT>
-__global__ __launch_bounds__(NT) void kb_upd_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j,
+__global__ __launch_bounds__(NT) void kb_upd_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, const int* jp, int j,
                                                                  int mode, int slot, int flip) {
   __shared__ double red[pow2_at_least(S * S) * (NT / 64)];
   const int2 pm = map[blockIdx.x];
+  if (jp) j = *jp;  // the step index held on the device (replayed graphs)
   const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, flip != 0);
   const T* X = (mode == 0 || mode == 2) ? a.Vprev : a.Vcur;
   const T* Y = mode == 3 ? nullptr : ((mode == 1) ? a.Vprev : a.Vcur);
@@ -697,34 +699,38 @@ __global__ __launch_bounds__(NT) void kb_upd_gram(const BatchDesc<T>* __restrict
 }
 
 template <typename T, int S, int NT>
-__global__ __launch_bounds__(NT) void kb_spmm_gram2(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j) {
+__global__ __launch_bounds__(NT) void kb_spmm_gram2(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, const int* jp, int j) {
   __shared__ double red[pow2_at_least(2 * S * S) * (NT / 64)];
   const int2 pm = map[blockIdx.x];
+  if (jp) j = *jp;  // the step index held on the device (replayed graphs)
   const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, false);
   spmm_gram2_body<T, S, NT>(a, pm.y, a.nparts, red);
 }
 
 template <typename T, int S, bool LAST, int NT>
-__global__ __launch_bounds__(NT) void kb_upd2_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j,
+__global__ __launch_bounds__(NT) void kb_upd2_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, const int* jp, int j,
                                                   int slot1, int slot2, int flip) {
   __shared__ double red[pow2_at_least(2 * S * S) * (NT / 64)];
   const int2 pm = map[blockIdx.x];
+  if (jp) j = *jp;  // the step index held on the device (replayed graphs)
   const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, flip != 0);
   upd2_gram_body<T, S, LAST, NT>(a, slot1, slot2, pm.y, a.nparts, red);
 }
 
 template <typename T, int S, int NT>
-__global__ __launch_bounds__(NT) void kb_chol_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j) {
+__global__ __launch_bounds__(NT) void kb_chol_gram(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, const int* jp, int j) {
   __shared__ double red[pow2_at_least(S * S) * (NT / 64)];
   const int2 pm = map[blockIdx.x];
+  if (jp) j = *jp;  // the step index held on the device (replayed graphs)
   const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, true);
   chol_gram_body<T, S, NT>(a, pm.y, a.nparts, red);
 }
 
 template <typename T, int S, int NT>
-__global__ __launch_bounds__(NT) void kb_chol_store(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, int j) {
+__global__ __launch_bounds__(NT) void kb_chol_store(const BatchDesc<T>* __restrict__ d, const int2* __restrict__ map, const int* jp, int j) {
   __shared__ double red[pow2_at_least(S * S) * (NT / 64)];
   const int2 pm = map[blockIdx.x];
+  if (jp) j = *jp;  // the step index held on the device (replayed graphs)
   const StepArgs<T> a = batch_args<T, S>(d[pm.x], j, false);
   chol_store_body<T, S, NT>(a, pm.y, a.nparts, red);
 }
@@ -880,39 +886,39 @@ int batch_default_threads(int S) { return stream_threads(S); }
 
 template <typename T>
 void launch_batch_step(const BatchDesc<T>* d, const int2* map, int nwg, int S, int nt, int j, hipStream_t st,
-                       KernelTimer* kt) {
+                       KernelTimer* kt, const int* jp) {
   if (nwg <= 0) return;
   auto mark = [&](int k) { if (kt) kt->mark(k); };
   LYAP_SWITCH_S(S, {
     LYAP_SWITCH_NT(S, nt, {
       if constexpr (cgs2_width(S)) {
         mark(LYAP_K_SPMM_GRAM);
-        hipLaunchKernelGGL((kb_spmm_gram2<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+        hipLaunchKernelGGL((kb_spmm_gram2<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, jp, j);
         mark(LYAP_K_UPD_GRAM);
-        hipLaunchKernelGGL((kb_upd2_gram<T, S, false, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, (int)L_A1,
+        hipLaunchKernelGGL((kb_upd2_gram<T, S, false, NT>), dim3(nwg), dim3(NT), 0, st, d, map, jp, j, (int)L_A1,
                            (int)L_A2, 1);
         mark(LYAP_K_UPD_GRAM);
-        hipLaunchKernelGGL((kb_upd2_gram<T, S, true, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, (int)L_A3,
+        hipLaunchKernelGGL((kb_upd2_gram<T, S, true, NT>), dim3(nwg), dim3(NT), 0, st, d, map, jp, j, (int)L_A3,
                            (int)L_A4, 0);
         mark(LYAP_K_CHOL_GRAM);
-        hipLaunchKernelGGL((kb_chol_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+        hipLaunchKernelGGL((kb_chol_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, jp, j);
         mark(LYAP_K_CHOL_STORE);
-        hipLaunchKernelGGL((kb_chol_store<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+        hipLaunchKernelGGL((kb_chol_store<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, jp, j);
       } else {
         mark(LYAP_K_SPMM_GRAM);
-        hipLaunchKernelGGL((kb_spmm_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+        hipLaunchKernelGGL((kb_spmm_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, jp, j);
         mark(LYAP_K_UPD_GRAM);
-        hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 0, (int)L_A1, 1);
+        hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, jp, j, 0, (int)L_A1, 1);
         mark(LYAP_K_UPD_GRAM);
-        hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 1, (int)L_A2, 0);
+        hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, jp, j, 1, (int)L_A2, 0);
         mark(LYAP_K_UPD_GRAM);
-        hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 2, (int)L_A3, 1);
+        hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, jp, j, 2, (int)L_A3, 1);
         mark(LYAP_K_UPD_GRAM);
-        hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j, 3, (int)L_A4, 0);
+        hipLaunchKernelGGL((kb_upd_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, jp, j, 3, (int)L_A4, 0);
         mark(LYAP_K_CHOL_GRAM);
-        hipLaunchKernelGGL((kb_chol_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+        hipLaunchKernelGGL((kb_chol_gram<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, jp, j);
         mark(LYAP_K_CHOL_STORE);
-        hipLaunchKernelGGL((kb_chol_store<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, j);
+        hipLaunchKernelGGL((kb_chol_store<T, S, NT>), dim3(nwg), dim3(NT), 0, st, d, map, jp, j);
       }
     });
   });
@@ -944,7 +950,7 @@ void launch_apply(const OpDev<T>& op, int S, const T* V, T* W, int grid, hipStre
                                  hipStream_t);                                                               \
   template void launch_apply<T>(const OpDev<T>&, int, const T*, T*, int, hipStream_t);                     \
   template void launch_batch_step<T>(const BatchDesc<T>*, const int2*, int, int, int, int, hipStream_t,          \
-                                     KernelTimer*);                                                            \
+                                     KernelTimer*, const int*);                                                \
   template void launch_batch_replay<T>(const BatchDesc<T>*, const int2*, int, int, int, int, hipStream_t);
 
 LYAP_INST(float)

@@ -139,11 +139,13 @@ struct BatchDesc {
 // map[w] = (problem, workgroup index within the problem) for every workgroup
 // of a grouped launch over the problems of one block width S; nt threads per
 // workgroup (256, or 1024 for S <= 4; batch_default_threads(S) is the size
-// the single-problem kernels use).
+// the single-problem kernels use).  With jp set the kernels read the step
+// index from *jp (device memory) instead of j, so that one captured graph of a
+// step can be replayed for successive steps.
 int batch_default_threads(int S);
 template <typename T>
 void launch_batch_step(const BatchDesc<T>* d, const int2* map, int nwg, int S, int nt, int j, hipStream_t st,
-                       KernelTimer* kt = nullptr);
+                       KernelTimer* kt = nullptr, const int* jp = nullptr);
 template <typename T>
 void launch_batch_replay(const BatchDesc<T>* d, const int2* map, int nwg, int S, int nt, int i, hipStream_t st);
 

@@ -170,3 +170,29 @@ def test_tile_autotuner_persistent_cache(lib, tmp_path, monkeypatch):
         assert a.m == r.m and c.m == r.m
         assert K.factor_error(a.Z.cpu().numpy(), r.Z.cpu().numpy()) <= 1e-10
         assert K.factor_error(c.Z.cpu().numpy(), r.Z.cpu().numpy()) <= 1e-10
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_batched_step_graphs_match_direct_launches(lib, storage):
+    """LYAP_BATCH_GRAPHS: the first pass replays one captured graph per step
+    (every block width's step kernels, the step index read from device
+    memory), captured again whenever a problem leaves its group.  With a
+    fixed check schedule the solutions are bit-identical to direct launches:
+    the same m, residual histories and Z, on every problem (each replay's
+    output feeds the next, with the checks' eager work and the uploads
+    between replays)."""
+    b = _b()
+    st_ = b.STORE_F64 if storage == "f64" else b.STORE_F32
+    probs = _small_batch()
+    dops = [b.device_op(op) for op, _ in probs]
+    Cs = [_dev(C) for _, C in probs]
+    st0, ref = b.lyap_solve_batched(dops, Cs, tol=1e-8, check_every=2, storage=st_)
+    st1, sols = b.lyap_solve_batched(dops, Cs, tol=1e-8, check_every=2, storage=st_, graphs=True)
+    assert st0 == b.OK and st1 == b.OK
+    assert len({s.m for s in ref}) > 1  # problems leave at different steps: several captures
+    for r, g in zip(ref, sols):
+        assert g.m == r.m and g.t == r.t
+        assert g.hist_m == r.hist_m and g.hist_res == r.hist_res
+        assert torch.equal(g.Z, r.Z)
+    with pytest.raises(b.LyapError):
+        b.lyap_solve_batched(dops, Cs, graphs=True, profile=1)
