@@ -544,27 +544,41 @@ __global__ __launch_bounds__(stream_threads(S)) void k_init_apply(const double* 
 // (nb <= 64), i.e. Z (n x t, column-major) += [V_b ...] (n x nb*S) times
 // Mrows (nb*S x t, row-major).  Plain FP64 FMAs, accumulated in the order of
 // the buffered blocks, starting from Z.  The work is FP64 FMA bound (2 nb S t
-// flops per row against 16 t bytes of Z), so the tile is built for FMA issue:
-// a lane owns kZRT rows (r, r + 64, ...) by kZCW columns of Z in registers;
-// per block it reads its rows of V_b with one vector load each (the next
-// block's rows are loaded while this block's FMAs run), and the M entries,
-// the same for the whole wave, are scalar operands (no LDS traffic).  A
-// workgroup's kZW waves cover kZW * kZCW consecutive columns over the same
-// rows, so V is read from HBM once per workgroup.  FULL: all kZCW columns of
-// the wave exist (contiguous scalar loads of M); the last partial column tile
-// runs as a separate launch with FULL = false.
-constexpr int kZCW = 8, kZW = 8;
-// rows per lane: 8 for rows of up to 16 bytes, fewer for wider rows (registers)
+// flops per row against 16 t bytes of Z), so the tile is built for FMA issue
+// and latency hiding: a lane owns zflush_rt rows (r, r + 64, ...) by kZCW
+// columns of Z in registers (few enough registers for four or five waves per
+// SIMD); the M row of a q-step, the same for the whole wave, is read with
+// ordinary vector loads three q-steps ahead into a ring of four rows (vector
+// loads return in order, so only the oldest is waited for; scalar loads
+// would have to be waited for all together), and the rows of the next U
+// blocks of V are loaded while the current ones are used (U blocks per
+// iteration keep every q-step's ring slot static).  A workgroup's waves
+// (blockDim / 64 of them) cover consecutive tiles of kZCW columns over the
+// same rows, so V is read from HBM once per workgroup.  FULL: all kZCW
+// columns of the wave exist; the last partial column tile runs as a separate
+// launch with FULL = false (its columns past t read column t - 1 and are not
+// stored).
+constexpr int kZCW = 8, kZW = 8, kZRing = 4;
+// blocks per iteration: the smallest U with U * S a multiple of the ring
+constexpr int zflush_u(int S) {
+  return S % 4 == 0 ? 1 : (S % 2 == 0 ? 2 : 4);
+}
+// rows per lane: at most 4, and the V rows of U blocks (twice: current and
+// next) within 64 registers
 template <typename T, int S>
 constexpr int zflush_rt() {
-  return S * (int)sizeof(T) <= 16 ? 8 : S * (int)sizeof(T) <= 32 ? 4 : 2;
+  constexpr int regs = zflush_u(S) * S * (int)sizeof(T) / 4;  // per row
+  return 32 / regs >= 4 ? 4 : (32 / regs >= 2 ? 2 : 1);
 }
 
 template <typename T, int S, bool FULL>
 __global__ __launch_bounds__(64 * kZW) void k_zflush(BlockList bl, int nb, int n, const double* __restrict__ Mrows,
                                                      int ldm, int t, double* __restrict__ Z, int64_t ldz, int ncg) {
-  constexpr int kZRT = zflush_rt<T, S>();
-  constexpr int kZR = 64 * kZRT;
+  constexpr int RT = zflush_rt<T, S>();
+  constexpr int kZR = 64 * RT;
+  constexpr int U = zflush_u(S);
+  constexpr int R = kZRing, PD = kZRing - 1;
+  static_assert((U * S) % R == 0, "every q-step's ring slot is static");
   // FULL: a 1-D launch over (row block, column group) pairs, dealt so that
   // each XCD takes a contiguous run of pairs: the ncg column groups of a row
   // block run back to back on one XCD, and all but the first read their rows
@@ -578,62 +592,70 @@ __global__ __launch_bounds__(64 * kZW) void k_zflush(BlockList bl, int nb, int n
   }
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int c0 = (cg * kZW + wv) * kZCW;
+  const int nw = blockDim.x >> 6;
+  const int c0 = (cg * nw + wv) * kZCW;
   if (c0 >= t) return;
-  const int cmax = FULL ? kZCW - 1 : min(kZCW, t - c0) - 1;  // columns past t read column t-1, are not stored
+  const int cmax = FULL ? kZCW - 1 : min(kZCW, t - c0) - 1;
   const int r0 = rb * kZR + lane;
   // rows past n compute on row n-1 (branch-free loads) and are not stored
-  int rr[kZRT];
+  int rr[RT];
 #pragma unroll
-  for (int i = 0; i < kZRT; ++i) rr[i] = min(r0 + 64 * i, n - 1);
-  double acc[kZRT][kZCW];
+  for (int i = 0; i < RT; ++i) rr[i] = min(r0 + 64 * i, n - 1);
+  double acc[RT][kZCW];
 #pragma unroll
-  for (int i = 0; i < kZRT; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int c = 0; c < kZCW; ++c) acc[i][c] = Z[(size_t)(c0 + min(c, cmax)) * ldz + rr[i]];
-  T x[kZRT][S];
-#pragma unroll
-  for (int i = 0; i < kZRT; ++i) load_row<T, S>((const T*)bl.p[0] + (size_t)rr[i] * S, x[i]);
-  // M row of the current q; the next one is requested before this q's FMAs
-  // (scalar loads complete out of order, so a wait covers all of them)
   const int nq = nb * S;
-  double m[kZCW];
+  double mr[R][kZCW];
+  auto loadm = [&](int qq, double (&dst)[kZCW]) {
+    const double* src = Mrows + (size_t)min(qq, nq - 1) * ldm + c0;
 #pragma unroll
-  for (int c = 0; c < kZCW; ++c) m[c] = Mrows[c0 + min(c, cmax)];
+    for (int c = 0; c < kZCW; ++c) dst[c] = src[FULL ? c : min(c, cmax)];
+  };
+#pragma unroll
+  for (int d = 0; d < PD; ++d) loadm(d, mr[d]);
+  T xs[U][RT][S];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int i = 0; i < RT; ++i) load_row<T, S>((const T*)bl.p[min(u, nb - 1)] + (size_t)rr[i] * S, xs[u][i]);
 #pragma unroll 1
-  for (int b = 0; b < nb; ++b) {
-    const T* Vn = (const T*)bl.p[b + 1 < nb ? b + 1 : b];
-    T xn[kZRT][S];
+  for (int b = 0; b < nb; b += U) {
+    T xn[U][RT][S];
 #pragma unroll
-    for (int i = 0; i < kZRT; ++i) load_row<T, S>(Vn + (size_t)rr[i] * S, xn[i]);
+    for (int u = 0; u < U; ++u) {
+      const T* Vn = (const T*)bl.p[min(b + U + u, nb - 1)];
 #pragma unroll
-    for (int q = 0; q < S; ++q) {
-      // wait for this q's M row (lgkmcnt(0); vmcnt and expcnt left free)
-      // before the next one is requested
-      __builtin_amdgcn_s_waitcnt(0xC07F);
-      const int qn = min(b * S + q + 1, nq - 1);
-      const double* Mn = Mrows + (size_t)qn * ldm + c0;
-      double mn[kZCW];
-#pragma unroll
-      for (int c = 0; c < kZCW; ++c) mn[c] = Mn[min(c, cmax)];
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int i = 0; i < kZRT; ++i) {
-        const double a = (double)x[i][q];
-#pragma unroll
-        for (int c = 0; c < kZCW; ++c) acc[i][c] = fma(a, m[c], acc[i][c]);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int c = 0; c < kZCW; ++c) m[c] = mn[c];
+      for (int i = 0; i < RT; ++i) load_row<T, S>(Vn + (size_t)rr[i] * S, xn[u][i]);
     }
 #pragma unroll
-    for (int i = 0; i < kZRT; ++i)
+    for (int u = 0; u < U; ++u) {
+      const bool live = b + u < nb;  // (uniform) the last group may be partial
 #pragma unroll
-      for (int q = 0; q < S; ++q) x[i][q] = xn[i][q];
+      for (int q = 0; q < S; ++q) {
+        const int ql = u * S + q;
+        loadm((b + u) * S + q + PD, mr[(ql + PD) % R]);
+        if (live) {
+          const double(&cur)[kZCW] = mr[ql % R];
+#pragma unroll
+          for (int i = 0; i < RT; ++i) {
+            const double a = (double)xs[u][i][q];
+#pragma unroll
+            for (int c = 0; c < kZCW; ++c) acc[i][c] = fma(a, cur[c], acc[i][c]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int q = 0; q < S; ++q) xs[u][i][q] = xn[u][i][q];
   }
 #pragma unroll
-  for (int i = 0; i < kZRT; ++i) {
+  for (int i = 0; i < RT; ++i) {
     const int r = r0 + 64 * i;
     if (r < n) {
 #pragma unroll
@@ -853,9 +875,12 @@ void launch_zflush(const void* const* blocks, int nb, int n, int S, const double
       const int tf = t / kZCW * kZCW;  // columns in full tiles
       constexpr int kZR = 64 * zflush_rt<T, S>();
       if (tf > 0) {
-        const int ncg = (tf / kZCW + kZW - 1) / kZW;  // column groups of kZW * kZCW columns
+        // column groups of at most kZW tiles, the tiles spread evenly over them
+        const int tiles = tf / kZCW;
+        const int ncg = (tiles + kZW - 1) / kZW;
+        const int nw = (tiles + ncg - 1) / ncg;  // waves per workgroup
         const int pairs = (n + kZR - 1) / kZR * ncg;
-        hipLaunchKernelGGL((k_zflush<T, S, true>), dim3(xcd_grid(pairs)), dim3(64 * kZW), 0, st, bl, cnt, n, Mc, t,
+        hipLaunchKernelGGL((k_zflush<T, S, true>), dim3(xcd_grid(pairs)), dim3(64 * nw), 0, st, bl, cnt, n, Mc, t,
                            tf, Z, ldz, ncg);
       }
       if (tf < t)
