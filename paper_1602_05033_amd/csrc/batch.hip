@@ -17,6 +17,7 @@
 #include <sys/stat.h>
 
 #include <algorithm>
+#include <deque>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -290,6 +291,11 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
     if (overlap) LYAP_HIP(hipStreamCreateWithFlags(&cs.s[i], hipStreamNonBlocking));
   }
   auto cstream = [&](int id) { return overlap ? cs.s[id % kCS] : st; };
+  // second-pass ring of V blocks per problem: with the checks overlapping,
+  // the Z accumulation runs on the problem's check stream and its blocks stay
+  // in the ring for kFlushSlack more replay steps while the replays go on
+  constexpr int kFlushSlack = 16;
+  auto ring_blocks = [&](int S) { return zflush_max_blocks(S) + 2 + (overlap ? kFlushSlack : 0); };
 
   std::vector<std::unique_ptr<Problem<T>>> P;
   DevBuf flags_all((size_t)count * 16 * sizeof(int));
@@ -462,7 +468,7 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
       b.partB = p->partB.template as<double>();
       b.flags = flags_all.template as<int>() + 16 * p->id;
       b.ring = p->ring.p ? p->ring.template as<T>() : nullptr;
-      b.R = zflush_max_blocks(p->S) + 2;
+      b.R = ring_blocks(p->S);
       b.zero = p->zero.template as<T>();
       const bool take = replay ? (step + 1 < p->m_final) : p->active;
       if (take)
@@ -741,7 +747,7 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
     bool owned = false;
     out[p->id].Z = alloc_output(o, (size_t)p->n * std::max(p->t, 1) * sizeof(double), &owned);
     out[p->id].owns_Z = owned ? 1 : 0;
-    const int R = zflush_max_blocks(p->S) + 2;
+    const int R = ring_blocks(p->S);
     p->ring.alloc((size_t)R * p->n * p->S * sizeof(T));
     if (p->t > 0) {
       LYAP_HIP(hipMemsetAsync(out[p->id].Z, 0, (size_t)p->n * p->t * sizeof(double), st));
@@ -755,8 +761,34 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
   for (auto& g : groups) upload(g, true, 0);
   std::vector<int> first(count, 0);
   std::vector<std::vector<const void*>> pend(count);
+  // Z accumulation beside the replays: a flush of blocks [f, f + cnt) waits for
+  // the replays launched so far (the last of its blocks was written by replay
+  // f + cnt - 2), and replay f + R - 1, the first to overwrite one of its ring
+  // slots (block f + R), waits for the flush.  At most two flushes of a problem
+  // are outstanding, so four events per problem rotate.
+  constexpr int kFlushEv = 4;
+  struct FlushWait {
+    int step;
+    hipEvent_t ev;
+  };
+  std::vector<std::deque<FlushWait>> fwait(count);
+  struct EventPool {
+    std::vector<hipEvent_t> ev;
+    ~EventPool() { for (auto e : ev) (void)hipEventDestroy(e); }
+  } fpool;
+  std::vector<int> fnext(count, 0);
+  if (overlap) {
+    fpool.ev.resize((size_t)count * kFlushEv + 1);
+    for (auto& e : fpool.ev) LYAP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   for (int i = 0; i < mmax; ++i) {
     bool map_changes = false;
+    if (overlap)
+      for (auto& p : P)
+        while (!fwait[p->id].empty() && fwait[p->id].front().step <= i) {
+          LYAP_HIP(hipStreamWaitEvent(st, fwait[p->id].front().ev, 0));
+          fwait[p->id].pop_front();
+        }
     for (auto& g : groups) {
       if (g.nwg > 0) {
         kt.mark(LYAP_K_REPLAY);
@@ -765,16 +797,34 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
       for (Problem<T>* p : g.probs)
         if (i + 2 == p->m_final) map_changes = true;  // leaves the replay map after this step
     }
+    bool replays_marked = false;
     for (auto& p : P) {
       if (i >= p->m_final) continue;
       const int S = p->S;
-      const int R = zflush_max_blocks(S) + 2;
+      const int R = ring_blocks(S);
       if (pend[p->id].empty()) first[p->id] = i;
       pend[p->id].push_back(p->ring.template as<T>() + (size_t)(i % R) * p->n * S);
-      if ((int)pend[p->id].size() == zflush_max_blocks(S) || i == p->m_final - 1) {
+      // (the first flush of each problem is shortened by a problem-dependent
+      // amount so that the problems' flushes spread over the replay steps)
+      const int flen = zflush_max_blocks(S) - (overlap && first[p->id] == 0 ? (p->id * 17) % 32 : 0);
+      if ((int)pend[p->id].size() == flen || i == p->m_final - 1) {
+        hipStream_t fq = st;
+        if (overlap) {
+          fq = cstream(p->id);
+          hipEvent_t er_ = fpool.ev.back();
+          if (!replays_marked) LYAP_HIP(hipEventRecord(er_, st));
+          replays_marked = true;
+          LYAP_HIP(hipStreamWaitEvent(fq, er_, 0));
+        }
         kt.mark(LYAP_K_ZFLUSH);
         launch_zflush<T>(pend[p->id].data(), (int)pend[p->id].size(), p->n, S,
-                         p->M.template as<double>() + (size_t)first[p->id] * S * p->t, p->t, out[p->id].Z, p->n, 0, st);
+                         p->M.template as<double>() + (size_t)first[p->id] * S * p->t, p->t, out[p->id].Z, p->n, 0, fq);
+        if (overlap) {
+          hipEvent_t fe = fpool.ev[(size_t)p->id * kFlushEv + fnext[p->id]];
+          fnext[p->id] = (fnext[p->id] + 1) % kFlushEv;
+          LYAP_HIP(hipEventRecord(fe, fq));
+          fwait[p->id].push_back(FlushWait{first[p->id] + R - 1, fe});
+        }
         pend[p->id].clear();
       }
     }
@@ -782,6 +832,7 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
       for (auto& g : groups) upload(g, true, i + 1);
   }
   LYAP_HIP(hipStreamSynchronize(st));
+  if (overlap) sync_checks();
   kt.collect();
   const double p2_ms = ms_since(t_p2);
 
