@@ -69,9 +69,10 @@ def test_batched_matches_single_problem_path(lib):
     """With a fixed check schedule (every 4 steps) the batch reproduces the
     single-problem path: the same check points, m and residuals, and Z Z^T.
     With the adaptive schedule the batch checks less often by design (a check
-    costs the host a few hundred launches, a grouped step a handful for all
-    problems): its m may exceed the single path's by a few percent, and the
-    residuals agree wherever both checked."""
+    costs the host about 170 launches, a grouped step a handful for all
+    problems; its next check may be up to 3 m ahead, aimed at 0.9 of the
+    predicted crossing): its m may exceed the single path's by up to a quarter
+    on small problems, and the residuals agree wherever both checked."""
     b = _b()
     probs = _small_batch()[:4]
     dops = [b.device_op(op) for op, _ in probs]
@@ -89,7 +90,7 @@ def test_batched_matches_single_problem_path(lib):
     assert st == b.OK
     for dop, C, sol in zip(dops, Cs, sols):
         one = b.lyap_solve(dop, C, tol=1e-8, check_every=0, storage=b.STORE_F32)
-        assert sol.res <= 1e-8 and abs(sol.m - one.m) <= max(5, 0.1 * one.m), (sol.m, one.m)
+        assert sol.res <= 1e-8 and abs(sol.m - one.m) <= max(5, 0.25 * one.m), (sol.m, one.m)
         common = dict(zip(one.hist_m, one.hist_res))
         for m, r in zip(sol.hist_m, sol.hist_res):
             if m in common:
@@ -136,8 +137,8 @@ def test_batched_full_workload(lib):
         assert ex <= 2e-7, ex
     for i in (0, 17, 40, 63):
         one = b.lyap_solve(dops[i], Cs[i], tol=1e-8, storage=b.STORE_F32, check_every=0)
-        # the batch's own check schedule (fewer checks) may stop a few percent later
-        assert abs(one.m - sols[i].m) <= max(5, 0.1 * one.m)
+        # the batch's own check schedule (fewer checks) may stop later
+        assert abs(one.m - sols[i].m) <= max(5, 0.25 * one.m), (one.m, sols[i].m)
 
 
 def test_tile_autotuner_persistent_cache(lib, tmp_path, monkeypatch):
