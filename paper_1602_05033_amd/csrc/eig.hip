@@ -397,6 +397,99 @@ __global__ __launch_bounds__(kPcThreads) void k_pchol_step(const double* lam, co
   pc_partials(d, k, pv, pi, ps);
 }
 
+// The whole factorisation in one workgroup, for k up to kPcOneMax rows: the
+// pivot rule (largest remaining diagonal entry, the lowest index on ties),
+// the stopping rule (remaining trace <= delta) and the column arithmetic of
+// k_pchol_init / k_pchol_step, with the pivot search and the trace reduced
+// inside the workgroup between pivots instead of one launch per pivot.  Each
+// pivot costs a thread k / 1024 rows times r loads in sequence, so above
+// about a thousand rows the one-launch-per-pivot kernels are faster (measured:
+// 1.6 ms per factorisation on the 64-problem batch, k up to about 3000,
+// against about 1 ms of step kernels; 22 against 14 ms at k = 5348, t = 131).
+constexpr int kPcOneThreads = 1024;
+constexpr int kPcOneMax = 1024;
+
+__global__ __launch_bounds__(kPcOneThreads) void k_pchol_one(const double* lam, const double* g, int k, int ell,
+                                                             double delta, int tmax, double* d, double* Lc, int* piv,
+                                                             PcState* stt) {
+  constexpr int NW = kPcOneThreads / 64;
+  __shared__ double rv[NW], rs[NW];
+  __shared__ int ri[NW];
+  __shared__ int sp;
+  __shared__ double spiv, strace;
+  __shared__ double gp[kMaxEll];
+  for (int i = threadIdx.x; i < k; i += kPcOneThreads) {
+    double nn = 0.0;
+    for (int a = 0; a < ell; ++a) nn = fma(g[(size_t)i * ell + a], g[(size_t)i * ell + a], nn);
+    d[i] = -nn / (2.0 * lam[i]);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int t = 0;
+  for (int r = 0; r < tmax; ++r) {
+    double best = -1.0, sum = 0.0;
+    int bi = 0x7fffffff;
+    for (int i = threadIdx.x; i < k; i += kPcOneThreads) {
+      const double v = d[i];
+      sum += v;
+      if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+    }
+    auto merge = [&](double ob, int oi) {
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    };
+    merge(lane_xor<1>(best), lane_xor<1>(bi));
+    merge(lane_xor<2>(best), lane_xor<2>(bi));
+    merge(lane_xor<7>(best), lane_xor<7>(bi));
+    merge(lane_xor<15>(best), lane_xor<15>(bi));
+    merge(lane_xor<16>(best), lane_xor<16>(bi));
+    merge(lane_xor<32>(best), lane_xor<32>(bi));
+    sum = wave_sum(sum);
+    if (lane == 0) { rv[wave] = best; ri[wave] = bi; rs[wave] = sum; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double b = rv[0], sm = rs[0];
+      int ii = ri[0];
+      for (int w = 1; w < NW; ++w) {
+        if (rv[w] > b || (rv[w] == b && ri[w] < ii)) { b = rv[w]; ii = ri[w]; }
+        sm += rs[w];
+      }
+      sp = ii; spiv = b; strace = sm;
+    }
+    __syncthreads();
+    if (!(strace > delta) || !(spiv > 0.0)) break;  // the same values in every thread
+    const int p = sp;
+    const double sq = sqrt(spiv);
+    if (threadIdx.x < ell) gp[threadIdx.x] = g[(size_t)p * ell + threadIdx.x];
+    __syncthreads();
+    const double lp = lam[p];
+    for (int i = threadIdx.x; i < k; i += kPcOneThreads) {
+      double v;
+      const double di = d[i];
+      if (i == p) {
+        v = sq;
+      } else if (di == 0.0) {
+        v = 0.0;
+      } else {
+        double dot = 0.0;
+        for (int a = 0; a < ell; ++a) dot = fma(g[(size_t)i * ell + a], gp[a], dot);
+        double y = -dot / (lam[i] + lp);
+        for (int q = 0; q < r; ++q) y = fma(-Lc[(size_t)q * k + i], Lc[(size_t)q * k + p], y);
+        v = y / sq;
+      }
+      Lc[(size_t)r * k + i] = v;
+      const double nd = (i == p) ? 0.0 : di - v * v;
+      d[i] = nd > 0.0 ? nd : 0.0;
+    }
+    if (threadIdx.x == 0) piv[r] = p;
+    t = r + 1;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    stt->stop = 1;
+    stt->t = t;
+  }
+}
+
 // G = Lc^T Lc (tp x tp, row-major); one workgroup per entry (a <= b).
 __global__ __launch_bounds__(kBlock) void k_gram_cols(const double* Lc, int k, int tp, double* G) {
   __shared__ double red[kWaves];
@@ -417,11 +510,17 @@ __global__ __launch_bounds__(kBlock) void k_gram_cols(const double* Lc, int k, i
 
 // Banded shifted solves: thread p factors S_p = -(T + lambda_{piv[p]} I) =
 // L L^T (lower band, bandwidth ELL; S_p is positive definite since T is
-// negative definite) row by row with the last ELL rows of L kept in registers,
-// solves L z = E_1 (gamma g_{piv[p]}^T) on the fly, stores the rows of L
-// (interleaved by thread), then solves L^T x = z backwards.  x is
-// Q Y~(:, piv[p]) = -(T + lambda I)^{-1} E_1 gamma g^T written as S_p^{-1} E_1 gamma g^T.
-// X: k x tp column-major.
+// negative definite) row by row with the last ELL rows of L (and the
+// reciprocals of their diagonal entries) kept in registers, solves
+// L z = E_1 (gamma g_{piv[p]}^T) on the fly, stores the rows of L (interleaved
+// by thread, the reciprocal of the diagonal in the diagonal's slot), then
+// solves L^T x = z backwards.  x is Q Y~(:, piv[p]) = -(T + lambda I)^{-1} E_1
+// gamma g^T written as S_p^{-1} E_1 gamma g^T.  X: k x tp column-major.
+// The recurrences are sequential in the rows, so each thread keeps the loads
+// of the next U rows (band entries forward, rows of L and z backward) in
+// flight while it works on the current U rows: the chain per row is then a
+// few FMAs, one square root and one division instead of a memory round trip
+// and ELL + 2 divisions.
 template <int ELL>
 __global__ __launch_bounds__(64) void k_shift_solve(const double* band, int ldb, int k, const double* lam,
                                                     const double* g, const double* gamma, const int* piv, int tp,
@@ -429,6 +528,7 @@ __global__ __launch_bounds__(64) void k_shift_solve(const double* band, int ldb,
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= tp) return;
   constexpr int LB = ELL + 1;
+  constexpr int U = ELL <= 4 ? 8 : (ELL <= 8 ? 4 : 2);
   const int ip = piv[p];
   const double sh = lam[ip];
   double rhs[ELL];
@@ -438,61 +538,90 @@ __global__ __launch_bounds__(64) void k_shift_solve(const double* band, int ldb,
     for (int c = 0; c < ELL; ++c) acc = fma(gamma[a * ELL + c], g[(size_t)ip * ELL + c], acc);
     rhs[a] = acc;
   }
-  // window: W[i][m] = L(j-ELL+i, j-ELL+i-ELL+m) for the previous ELL rows (m = 0..ELL, m == ELL is diagonal)
-  double W[ELL][LB];
+  // window: W[i][m] = L(j-ELL+i, j-ELL+i-ELL+m) for the previous ELL rows (m = 0..ELL, m == ELL is diagonal);
+  // rd[i] = 1 / W[i][ELL]
+  double W[ELL][LB], rd[ELL];
   double zw[ELL];  // z of the previous ELL rows
 #pragma unroll
   for (int i = 0; i < ELL; ++i) {
     zw[i] = 0.0;
+    rd[i] = 1.0;
 #pragma unroll
     for (int m = 0; m < LB; ++m) W[i][m] = (m == ELL) ? 1.0 : 0.0;
   }
   double* x = X + (size_t)p * k;
-  for (int j = 0; j < k; ++j) {
-    // row j of L: Lj[m] = L(j, j-ELL+m), m = 0..ELL
-    double Lj[LB];
+  // B[u][m] = T(j-ELL+m, j) for m < ELL (0 above the first row), B[u][ELL] = T(j, j), j = j0 + u
+  auto band_rows = [&](int j0, double (&B)[U][LB]) {
 #pragma unroll
-    for (int m = 0; m < ELL; ++m) {
-      const int i = j - ELL + m;  // column
-      double v = 0.0;
-      if (i >= 0) {
-        v = -band[(size_t)i * ldb + (j - i)];
-        // subtract sum_{mm < m} L(j, j-ELL+mm) L(i, j-ELL+mm); row i is window slot m
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u;
 #pragma unroll
-        for (int mm = 0; mm < m; ++mm) {
-          // L(i, j-ELL+mm) = W[m][mm + (ELL - m)] (row i = j-ELL+m, its column offset base i-ELL)
-          v = fma(-Lj[mm], W[m][mm + ELL - m], v);
-        }
-        v = v / W[m][ELL];
+      for (int m = 0; m < ELL; ++m) {
+        const int i = j - ELL + m;
+        B[u][m] = (i >= 0 && j < k) ? band[(size_t)i * ldb + (j - i)] : 0.0;
       }
-      Lj[m] = v;
+      B[u][ELL] = j < k ? band[(size_t)j * ldb] : 0.0;
     }
-    double djj = -(band[(size_t)j * ldb] + sh);
+  };
+  double Bc[U][LB];
+  band_rows(0, Bc);
+  for (int j0 = 0; j0 < k; j0 += U) {
+    double Bn[U][LB];
+    band_rows(j0 + U, Bn);
 #pragma unroll
-    for (int m = 0; m < ELL; ++m) djj = fma(-Lj[m], Lj[m], djj);
-    if (!(djj > 0.0)) { fail[0] = 1; djj = 1e-300; }
-    Lj[ELL] = sqrt(djj);
-    // forward substitution
-    double zj = j < ELL ? rhs[j] : 0.0;
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u;
+      if (j >= k) break;  // (the same j in every thread)
+      // row j of L: Lj[m] = L(j, j-ELL+m), m = 0..ELL
+      double Lj[LB];
 #pragma unroll
-    for (int m = 0; m < ELL; ++m) zj = fma(-Lj[m], zw[m], zj);
-    zj /= Lj[ELL];
-    // store row j, slide the window
+      for (int m = 0; m < ELL; ++m) {
+        const int i = j - ELL + m;  // column
+        double v = 0.0;
+        if (i >= 0) {
+          v = -Bc[u][m];
+          // subtract sum_{mm < m} L(j, j-ELL+mm) L(i, j-ELL+mm); row i is window slot m
 #pragma unroll
-    for (int m = 0; m < LB; ++m) Lb[((size_t)j * LB + m) * tp + p] = Lj[m];
-    x[j] = zj;
+          for (int mm = 0; mm < m; ++mm) v = fma(-Lj[mm], W[m][mm + ELL - m], v);
+          v *= rd[m];
+        }
+        Lj[m] = v;
+      }
+      double djj = -(Bc[u][ELL] + sh);
 #pragma unroll
-    for (int i = 0; i < ELL - 1; ++i) {
-      zw[i] = zw[i + 1];
+      for (int m = 0; m < ELL; ++m) djj = fma(-Lj[m], Lj[m], djj);
+      if (!(djj > 0.0)) { fail[0] = 1; djj = 1e-300; }
+      Lj[ELL] = sqrt(djj);
+      const double rj = 1.0 / Lj[ELL];
+      // forward substitution
+      double zj = j < ELL ? rhs[j < ELL ? j : 0] : 0.0;
 #pragma unroll
-      for (int m = 0; m < LB; ++m) W[i][m] = W[i + 1][m];
+      for (int m = 0; m < ELL; ++m) zj = fma(-Lj[m], zw[m], zj);
+      zj *= rj;
+      // store row j (the reciprocal in the diagonal's slot), slide the window
+#pragma unroll
+      for (int m = 0; m < ELL; ++m) Lb[((size_t)j * LB + m) * tp + p] = Lj[m];
+      Lb[((size_t)j * LB + ELL) * tp + p] = rj;
+      x[j] = zj;
+#pragma unroll
+      for (int i = 0; i < ELL - 1; ++i) {
+        zw[i] = zw[i + 1];
+        rd[i] = rd[i + 1];
+#pragma unroll
+        for (int m = 0; m < LB; ++m) W[i][m] = W[i + 1][m];
+      }
+      zw[ELL - 1] = zj;
+      rd[ELL - 1] = rj;
+#pragma unroll
+      for (int m = 0; m < LB; ++m) W[ELL - 1][m] = Lj[m];
     }
-    zw[ELL - 1] = zj;
 #pragma unroll
-    for (int m = 0; m < LB; ++m) W[ELL - 1][m] = Lj[m];
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int m = 0; m < LB; ++m) Bc[u][m] = Bn[u][m];
   }
   // backward: x_j = (z_j - sum_{r=j+1}^{j+ELL} L(r, j) x_r) / L(j, j); L(r, j) = row r slot j-r+ELL
-  double xw[ELL];   // x of rows j+1..j+ELL
+  double xw[ELL];      // x of rows j+1..j+ELL
   double Rw[ELL][LB];  // rows j+1..j+ELL of L
 #pragma unroll
   for (int i = 0; i < ELL; ++i) {
@@ -500,22 +629,46 @@ __global__ __launch_bounds__(64) void k_shift_solve(const double* band, int ldb,
 #pragma unroll
     for (int m = 0; m < LB; ++m) Rw[i][m] = 0.0;
   }
-  for (int j = k - 1; j >= 0; --j) {
-    double v = x[j];
+  // R[u] = row j of L and Z[u] = z_j for j = j1 - u (descending)
+  auto lrows = [&](int j1, double (&R)[U][LB], double (&Z)[U]) {
 #pragma unroll
-    for (int i = 0; i < ELL; ++i) v = fma(-Rw[i][ELL - 1 - i], xw[i], v);  // row j+1+i, column j: slot ELL-(1+i)
-    const double ljj = Lb[((size_t)j * LB + ELL) * tp + p];
-    v /= ljj;
-    x[j] = v;
+    for (int u = 0; u < U; ++u) {
+      const int j = j1 - u;
 #pragma unroll
-    for (int i = ELL - 1; i > 0; --i) {
-      xw[i] = xw[i - 1];
-#pragma unroll
-      for (int m = 0; m < LB; ++m) Rw[i][m] = Rw[i - 1][m];
+      for (int m = 0; m < LB; ++m) R[u][m] = j >= 0 ? Lb[((size_t)j * LB + m) * tp + p] : 0.0;
+      Z[u] = j >= 0 ? x[j] : 0.0;
     }
-    xw[0] = v;
+  };
+  double Rc[U][LB], Zc[U];
+  lrows(k - 1, Rc, Zc);
+  for (int j1 = k - 1; j1 >= 0; j1 -= U) {
+    double Rn[U][LB], Zn[U];
+    lrows(j1 - U, Rn, Zn);
 #pragma unroll
-    for (int m = 0; m < LB; ++m) Rw[0][m] = Lb[((size_t)j * LB + m) * tp + p];
+    for (int u = 0; u < U; ++u) {
+      const int j = j1 - u;
+      if (j < 0) break;
+      double v = Zc[u];
+#pragma unroll
+      for (int i = 0; i < ELL; ++i) v = fma(-Rw[i][ELL - 1 - i], xw[i], v);  // row j+1+i, column j: slot ELL-(1+i)
+      v *= Rc[u][ELL];
+      x[j] = v;
+#pragma unroll
+      for (int i = ELL - 1; i > 0; --i) {
+        xw[i] = xw[i - 1];
+#pragma unroll
+        for (int m = 0; m < LB; ++m) Rw[i][m] = Rw[i - 1][m];
+      }
+      xw[0] = v;
+#pragma unroll
+      for (int m = 0; m < LB; ++m) Rw[0][m] = Rc[u][m];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      Zc[u] = Zn[u];
+#pragma unroll
+      for (int m = 0; m < LB; ++m) Rc[u][m] = Rn[u][m];
+    }
   }
 }
 
@@ -609,6 +762,7 @@ struct PcholRun::Impl {
   DevBuf pvA, pvB, psA, psB, piA, piB, stt;
   HostBuf hst;
   bool finished = false;
+  bool one = false;  // k_pchol_one: the whole factorisation in one launch
   int t = 0;
 };
 
@@ -627,6 +781,12 @@ PcholRun::PcholRun(const double* lam, const double* g, int k, int ell, double de
   w.piv = piv;
   w.st = st;
   w.grid = std::max(1, std::min((k + kPcThreads - 1) / kPcThreads, 256));
+  w.one = k <= kPcOneMax;
+  w.stt.alloc(sizeof(PcState));
+  w.hst.alloc(sizeof(PcState));
+  std::memset(w.hst.p, 0, sizeof(PcState));
+  if (tmax <= 0) w.finished = true;
+  if (w.one) return;
   const int grid = w.grid;
   w.pvA.alloc(grid * sizeof(double));
   w.pvB.alloc(grid * sizeof(double));
@@ -634,13 +794,9 @@ PcholRun::PcholRun(const double* lam, const double* g, int k, int ell, double de
   w.psB.alloc(grid * sizeof(double));
   w.piA.alloc(grid * sizeof(int));
   w.piB.alloc(grid * sizeof(int));
-  w.stt.alloc(sizeof(PcState));
-  w.hst.alloc(sizeof(PcState));
-  std::memset(w.hst.p, 0, sizeof(PcState));
   hipLaunchKernelGGL(k_pchol_init, dim3(grid), dim3(kPcThreads), 0, st, lam, g, k, ell, d, w.pvA.as<double>(),
                      w.piA.as<int>(), w.psA.as<double>(), w.stt.as<PcState>());
   LYAP_LAUNCHED("pchol init");
-  if (tmax <= 0) w.finished = true;
 }
 
 PcholRun::~PcholRun() { delete w_; }
@@ -648,6 +804,14 @@ PcholRun::~PcholRun() { delete w_; }
 bool PcholRun::launch_chunk() {
   Impl& w = *w_;
   if (w.finished) return false;
+  if (w.one) {
+    hipLaunchKernelGGL(k_pchol_one, dim3(1), dim3(kPcOneThreads), 0, w.st, w.lam, w.g, w.k, w.ell, w.delta, w.tmax,
+                       w.d, w.Lc, w.piv, w.stt.as<PcState>());
+    LYAP_LAUNCHED("pchol one");
+    LYAP_HIP(hipMemcpyAsync(w.hst.p, w.stt.p, sizeof(PcState), hipMemcpyDeviceToHost, w.st));
+    w.r = w.tmax;
+    return true;
+  }
   // pivot steps up to the next multiple of 32 (or tmax), then the state
   const int end = std::min(w.tmax, (w.r / 32 + 1) * 32);
   for (; w.r < end; ++w.r) {

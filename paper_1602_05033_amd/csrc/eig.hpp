@@ -26,8 +26,9 @@ int run_pchol(const double* lam, const double* g, int k, int ell, double delta, 
               int* piv, hipStream_t st);
 // The same factorisation driven step by step, so that the host can advance
 // several of them (on different streams) in turn: launch_chunk() queues up to
-// 32 pivot steps and the copy of the state to host memory (false once
-// finished); read() takes that state after the stream has passed the copy.
+// 32 pivot steps (for k <= 1024 the whole factorisation, one workgroup in one
+// launch) and the copy of the state to host memory (false once finished);
+// read() takes that state after the stream has passed the copy.
 class PcholRun {
  public:
   PcholRun(const double* lam, const double* g, int k, int ell, double delta, int tmax, double* d, double* Lc,
