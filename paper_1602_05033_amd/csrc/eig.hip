@@ -684,6 +684,34 @@ __global__ void k_trsm_lt(const double* Lc, int k, const int* piv, int tp, const
   }
 }
 
+// The same solve with one wave per column: the sum over b > a is split over
+// the 64 lanes (a butterfly adds the parts; every lane ends with the same
+// total), the solved entries of the column and the pivots are kept in LDS.
+// tp <= kTrsmLds.
+constexpr int kTrsmLds = 4096;
+__global__ __launch_bounds__(64) void k_trsm_lt_wave(const double* Lc, int k, const int* piv, int tp,
+                                                     const double* V1, int t, double* B) {
+  __shared__ double sB[kTrsmLds];
+  __shared__ int sp[kTrsmLds];
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int b = lane; b < tp; b += 64) sp[b] = piv[b];
+  __syncthreads();
+  for (int a = tp - 1; a >= 0; --a) {
+    const double* La = Lc + (size_t)a * k;
+    double part = 0.0;
+    for (int b = a + 1 + lane; b < tp; b += 64) part = fma(La[sp[b]], sB[b], part);
+    const double tot = wave_sum(part);
+    const double v = (V1 ? V1[(size_t)a * t + c] : (a == c ? 1.0 : 0.0)) - tot;
+    const double x = v / La[sp[a]];
+    if (lane == 0) {
+      sB[a] = x;
+      B[(size_t)a * t + c] = x;
+    }
+    __syncthreads();
+  }
+}
+
 // M (k x t, row-major) = X (k x tp, column-major) B (tp x t, row-major)
 __global__ void k_gemm_xb(const double* X, int k, int tp, const double* B, int t, double* M) {
   const int64_t tot = (int64_t)k * t;
@@ -880,7 +908,10 @@ void launch_assemble_M(const double* Lc, int k, const int* piv, int tp, const do
   int64_t tot = (int64_t)tp * t;
   int grid = (int)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 4096));
   if (Qg) hipLaunchKernelGGL(k_pick_top, dim3(grid), dim3(256), 0, st, Qg, tp, t, V1);
-  hipLaunchKernelGGL(k_trsm_lt, dim3((t + 63) / 64), dim3(64), 0, st, Lc, k, piv, tp, V1, t, B);
+  if (tp <= kTrsmLds)
+    hipLaunchKernelGGL(k_trsm_lt_wave, dim3(t), dim3(64), 0, st, Lc, k, piv, tp, V1, t, B);
+  else
+    hipLaunchKernelGGL(k_trsm_lt, dim3((t + 63) / 64), dim3(64), 0, st, Lc, k, piv, tp, V1, t, B);
   tot = (int64_t)k * t;
   grid = (int)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 8192));
   hipLaunchKernelGGL(k_gemm_xb, dim3(grid), dim3(256), 0, st, X, k, tp, B, t, M);
