@@ -636,15 +636,25 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
   };
 
   const auto t_pass1 = Clock::now();
+  // host time by activity (printed with opts->verbose)
+  double h_poll = 0.0, h_check = 0.0, h_wait = 0.0, h_step = 0.0;
+  int n_launched_checks = 0;
   int j = 0;
   while (n_active > 0) {
+    auto th = Clock::now();
     if (n_pending > 0) poll_checks(!overlap);
+    h_poll += ms_since(th);
     if (n_active == 0) break;
     // launch the checks that are due now
+    th = Clock::now();
     for (auto& p : P) {
       if (!p->active || chk_pending[p->id]) continue;
-      if (j >= p->next_check || j >= maxit) launch_check(p.get(), j);
+      if (j >= p->next_check || j >= maxit) {
+        launch_check(p.get(), j);
+        ++n_launched_checks;
+      }
     }
+    h_check += ms_since(th);
     if (!overlap && n_pending > 0) continue;
     if (j >= maxit) {
       // every remaining active problem has a check in flight: wait for them
@@ -653,7 +663,10 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
     }
     // a problem whose check is still in flight keeps stepping (its next check
     // is decided when the result arrives)
+    th = Clock::now();
     if (j >= kAhead) LYAP_HIP(hipEventSynchronize(er.ev[j % kAhead]));
+    h_wait += ms_since(th);
+    th = Clock::now();
     if (graphs) {
       if (!sg_valid) capture_step(j);
       LYAP_HIP(hipGraphLaunch(sgs.x.back(), st));
@@ -664,10 +677,16 @@ lyap_status batched_impl(int count, const lyap_op* A, const double* const* C, co
                                st, &kt);
     }
     LYAP_HIP(hipEventRecord(er.ev[j % kAhead], st));
+    h_step += ms_since(th);
     ++j;
     for (auto& p : P)
       if (p->active) p->m = j;
   }
+  if (o.verbose)
+    std::fprintf(stderr,
+                 "[batch] pass 1: %d steps, %d checks; host ms: polling %.1f, check launches %.1f, "
+                 "step throttle waits %.1f, step launches %.1f\n",
+                 j, n_launched_checks, h_poll, h_check, h_wait, h_step);
   if (n_pending > 0) poll_checks(true);
   if (overlap)
     for (int i = 0; i < count; ++i) LYAP_HIP(hipStreamWaitEvent(st, ev_chk[i], 0));

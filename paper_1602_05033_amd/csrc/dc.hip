@@ -181,22 +181,6 @@ __global__ void k_coupling_svd(const DcMerge* md, DcScal* ms, int nm, const doub
   svd_small(B, ell, s.U, s.sigma, s.V);
 }
 
-// z = (R_a^T v_i + sg R_b^T u_i) / sqrt(2) for update u = 2i + (sg < 0)
-__global__ void k_zform(const DcMerge* md, const DcScal* ms, int ell, int k, int upd, const double* Rw, double* z) {
-  const DcMerge g = md[blockIdx.y];
-  const DcScal& s = ms[blockIdx.y];
-  const int i = upd >> 1;
-  const double sg = (upd & 1) ? -1.0 : 1.0;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < g.K; e += gridDim.x * blockDim.x) {
-    const int col = g.a + e;
-    double zx = 0.0, zy = 0.0;
-    for (int r = 0; r < ell; ++r) {
-      zx = fma(Rw[(size_t)(ell + r) * k + col], s.V[r * ell + i], zx);
-      zy = fma(Rw[(size_t)(2 * ell + r) * k + col], s.U[r * ell + i], zy);
-    }
-    z[col] = (zx + sg * zy) * 0.70710678118654752440;
-  }
-}
 
 // Deflation, one 1024-thread workgroup per merge.  Working index w runs over
 // the columns in ascending order of sg*D (sg = sign(rho)): column c(w) = w
@@ -226,7 +210,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sh, int* total) {
 }
 
 __global__ __launch_bounds__(kDefThreads) void k_deflate(const DcMerge* md, DcScal* ms, int ell, int k, int upd,
-                                                         double* Dw, double* Rw, const double* z, double* Dn,
+                                                         double* Dw, double* Rw, double* z, double* Dn,
                                                          double* zn, int* nd, int* defl, double* defv, int* sml,
                                                          double* smv, int* rdl, double* rdv) {
   __shared__ int sh[kDefThreads];
@@ -243,6 +227,21 @@ __global__ __launch_bounds__(kDefThreads) void k_deflate(const DcMerge* md, DcSc
   const int chunk = (K + kDefThreads - 1) / kDefThreads;
   const int w0 = min(t * chunk, K), w1 = min(w0 + chunk, K);
   auto col = [&](int w) { return sg > 0 ? w : K - 1 - w; };
+  // ---- z = (R_a^T v_i + sg R_b^T u_i) / sqrt(2) of update 2i + (sg < 0),
+  // each thread for its own columns, visible to the workgroup after the barrier
+  {
+    const double zs = sg > 0 ? 1.0 : -1.0;
+    for (int w = w0; w < w1; ++w) {
+      const int cl = a + col(w);
+      double zx = 0.0, zy = 0.0;
+      for (int r = 0; r < ell; ++r) {
+        zx = fma(Rw[(size_t)(ell + r) * k + cl], s.V[r * ell + i], zx);
+        zy = fma(Rw[(size_t)(2 * ell + r) * k + cl], s.U[r * ell + i], zy);
+      }
+      z[cl] = (zx + zs * zy) * 0.70710678118654752440;
+    }
+    __syncthreads();
+  }
   // ---- norms
   double nz2 = 0.0, dmax = 0.0;
   for (int w = w0; w < w1; ++w) {
@@ -821,7 +820,7 @@ __global__ __launch_bounds__(256) void k_zhat(const DcMerge* md, const DcScal* m
 // wave = one of nsp slices of the candidates i; the candidate data (d_i,
 // zhat_i, Rt[i][:]) is the same for every lane, so each wave streams it once
 // for 64 roots.  Per slice sp, rows r < nr and (r = nr) the squared norm go to
-// part[(sp (nr+1) + r) k + a + j]; k_vec_sum adds the slices up.
+// part[(sp (nr+1) + r) k + a + j]; k_assemble adds the slices up.
 template <int NRP>
 __global__ __launch_bounds__(256) void k_vec(const DcMerge* __restrict__ md, const DcScal* __restrict__ ms, int nr,
                                              int k, int nsp, const double* __restrict__ Rt,
@@ -865,22 +864,6 @@ __global__ __launch_bounds__(256) void k_vec(const DcMerge* __restrict__ md, con
 
 constexpr int kMaxSplit = 16;
 
-// NR[r][a + j] = sum over slices of part (rows r < nr), nrm[a + j] = the squared
-// norm; one thread per (row, root).
-__global__ void k_vec_sum(const DcMerge* md, const DcScal* ms, int nr, int k, int nsp, const double* part, double* NR,
-                          double* nrm) {
-  const DcMerge g = md[blockIdx.y];
-  const int Kn = ms[blockIdx.y].Kn;
-  const size_t ps = (size_t)(nr + 1) * k;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < (nr + 1) * Kn; e += gridDim.x * blockDim.x) {
-    const int r = e / Kn, j = e - r * Kn;
-    const double* P = part + (size_t)r * k + g.a + j;
-    double v = 0.0;
-    for (int sp = 0; sp < nsp; ++sp) v += P[sp * ps];
-    if (r < nr) NR[(size_t)r * k + g.a + j] = v;
-    else nrm[g.a + j] = v;
-  }
-}
 
 inline int vec_pad(int nr) { return nr <= 8 ? 8 : nr <= 16 ? 16 : nr <= 32 ? 32 : 64; }
 
@@ -899,13 +882,22 @@ void launch_vec(dim3 grid, const DcMerge* md, const DcScal* ms, int nr, int k, i
 
 // New spectrum = deflated values U new roots, merged in ascending order (ties:
 // deflated first), mapped back to the original orientation.
-__global__ void k_assemble(const DcMerge* md, const DcScal* ms, int ell, int k, const double* Rin, const double* NR,
-                           const double* nrm, const int* defl, const double* defv, const double* lamn, double* Dout,
+// The eigenvector rows of a new root (and its squared norm, row nr) are the
+// sums of k_vec's slices, added in slice order for the root's own column.
+__global__ void k_assemble(const DcMerge* md, const DcScal* ms, int ell, int k, const double* Rin, int nsp,
+                           const double* part, const int* defl, const double* defv, const double* lamn, double* Dout,
                            double* Rout) {
   const DcMerge g = md[blockIdx.y];
   const DcScal& s = ms[blockIdx.y];
   const int a = g.a, K = g.K, Kn = s.Kn, Kd = s.Kd, sg = s.sg;
   const int nr = 4 * ell;
+  const size_t ps = (size_t)(nr + 1) * k;
+  auto slices = [&](int r, int j) {
+    const double* P = part + (size_t)r * k + a + j;
+    double v = 0.0;
+    for (int sp = 0; sp < nsp; ++sp) v += P[sp * ps];
+    return v;
+  };
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < K; e += gridDim.x * blockDim.x) {
     int pos;
     double v;
@@ -929,8 +921,8 @@ __global__ void k_assemble(const DcMerge* md, const DcScal* ms, int ell, int k, 
       for (int r = 0; r < nr; ++r) Rout[(size_t)r * k + a + P] = Rin[(size_t)r * k + a + c];
     } else {
       const int j = e - Kd;
-      const double inv = 1.0 / sqrt(nrm[a + j]);
-      for (int r = 0; r < nr; ++r) Rout[(size_t)r * k + a + P] = NR[(size_t)r * k + a + j] * inv;
+      const double inv = 1.0 / sqrt(slices(nr, j));
+      for (int r = 0; r < nr; ++r) Rout[(size_t)r * k + a + P] = slices(r, j) * inv;
     }
   }
 }
@@ -954,7 +946,7 @@ struct DcWork::Impl {
   hipStream_t st;
   int cap = 0;
   int leaf = 32;
-  DevBuf Da, Db, Ra, Rb, z, Dn, zn, nd, defl, defv, orig, tau, lamn, zh, Rt, part, NR, nrm, sml, smv, rdl, rdv;
+  DevBuf Da, Db, Ra, Rb, z, Dn, zn, nd, defl, defv, orig, tau, lamn, zh, Rt, part, sml, smv, rdl, rdv;
   DevBuf leafA, leafQ, leafL, leafN;
   DevBuf md, ms;
   int md_cap = 0;
@@ -981,8 +973,6 @@ struct DcWork::Impl {
     Da.alloc(d); Db.alloc(d);
     Ra.alloc(d * 4 * ell); Rb.alloc(d * 4 * ell); Rt.alloc(d * vec_pad(4 * ell));
     part.alloc(d * (4 * ell + 1) * kMaxSplit);
-    NR.alloc(d * 4 * ell);
-    nrm.alloc(d);
     z.alloc(d); Dn.alloc(d); zn.alloc(d); defv.alloc(d); tau.alloc(d); lamn.alloc(d); zh.alloc(d);
     nd.alloc(ii); defl.alloc(ii); orig.alloc(ii); sml.alloc(ii); rdl.alloc(ii);
     smv.alloc(d); rdv.alloc(d);
@@ -1113,7 +1103,6 @@ void DcWork::run(const double* band, int ldb, int k, double* lam, double* F, dou
     hipLaunchKernelGGL(k_merge_setup, dim3(gx, nm), dim3(256), 0, st, md, ms, band, ldb, ell, ld, Dm, Fm, Lm, Dcur,
                        Rcur);
     for (int u = 0; u < 2 * ell; ++u) {
-      hipLaunchKernelGGL(k_zform, dim3(gx, nm), dim3(256), 0, st, md, ms, ell, ld, u, Rcur, w.z.as<double>());
       hipLaunchKernelGGL(k_deflate, dim3(nm), dim3(kDefThreads), 0, st, md, ms, ell, ld, u, Dcur, Rcur,
                          w.z.as<double>(), w.Dn.as<double>(), w.zn.as<double>(), w.nd.as<int>(), w.defl.as<int>(),
                          w.defv.as<double>(), w.sml.as<int>(), w.smv.as<double>(), w.rdl.as<int>(),
@@ -1125,10 +1114,8 @@ void DcWork::run(const double* band, int ldb, int k, double* lam, double* F, dou
                          w.zh.as<double>(), w.Rt.as<double>());
       launch_vec(dim3(nchunk * (nsp / 4), nm), md, ms, nr, ld, nsp, w.Rt.as<double>(), w.Dn.as<double>(),
                  w.orig.as<int>(), w.tau.as<double>(), w.zh.as<double>(), w.part.as<double>(), st);
-      hipLaunchKernelGGL(k_vec_sum, dim3(std::min(((nr + 1) * Kmax + 255) / 256, 1024), nm), dim3(256), 0, st, md,
-                         ms, nr, ld, nsp, w.part.as<double>(), w.NR.as<double>(), w.nrm.as<double>());
-      hipLaunchKernelGGL(k_assemble, dim3(gx, nm), dim3(256), 0, st, md, ms, ell, ld, Rcur, w.NR.as<double>(),
-                         w.nrm.as<double>(), w.defl.as<int>(), w.defv.as<double>(), w.lamn.as<double>(), Dnx, Rnx);
+      hipLaunchKernelGGL(k_assemble, dim3(gx, nm), dim3(256), 0, st, md, ms, ell, ld, Rcur, nsp,
+                         w.part.as<double>(), w.defl.as<int>(), w.defv.as<double>(), w.lamn.as<double>(), Dnx, Rnx);
       std::swap(Dcur, Dnx);
       std::swap(Rcur, Rnx);
     }
