@@ -502,6 +502,47 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
   __syncthreads();
 }
 
+// Two scalar totals at once: red[0] = sum of a[0..na), red[1] = sum of
+// b[0..nb), each added in exactly the order of reduce_partials<1, NT> (the
+// same bits), with the loads of both arrays in flight together and one pair of
+// barriers instead of two.
+template <int NT>
+__device__ __forceinline__ void reduce_partials_pair(const double* __restrict__ a, int na,
+                                                     const double* __restrict__ b, int nb, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = threadIdx.x;
+  double sa = 0.0, sb = 0.0;
+  for (int i = g; i < na; i += NT) sa += a[i];
+  for (int i = g; i < nb; i += NT) sb += b[i];
+  sa += lane_xor<1>(sa);
+  sb += lane_xor<1>(sb);
+  sa += lane_xor<2>(sa);
+  sb += lane_xor<2>(sb);
+  sa += lane_xor<7>(sa);
+  sb += lane_xor<7>(sb);
+  sa += lane_xor<15>(sa);
+  sb += lane_xor<15>(sb);
+  sa += lane_xor<16>(sa);
+  sb += lane_xor<16>(sb);
+  sa += lane_xor<32>(sa);
+  sb += lane_xor<32>(sb);
+  constexpr int W = NT / 64;
+  if (lane == 0) {
+    red[wave] = sa;
+    red[W + wave] = sb;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) t += red[threadIdx.x * W + w];
+    red[2 * W + threadIdx.x] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) red[threadIdx.x] = red[2 * W + threadIdx.x];
+  __syncthreads();
+}
+
 template <int K, int NT>
 __device__ __forceinline__ void write_partial_at(double (&v)[K], double* red, double* part, int idx) {
   block_sum<K, NT>(v, red);

@@ -479,16 +479,11 @@ __global__ __launch_bounds__(NT) void k_rbf_dira(OpDev<double> op, RbGeom g, con
                                                  double* __restrict__ pnew, double* __restrict__ v, CgIter* log, int it,
                                                  const double* state, const double* partR, int nparts,
                                                  const double* partZ, int nzparts) {
-  __shared__ double red[NT / 64];
-  reduce_partials<1, NT>(partR, nparts, red);
+  __shared__ double red[2 * (NT / 64) + 2];
+  // r.r of the updated residual and (after the first iteration) z.q_old
+  reduce_partials_pair<NT>(partR, nparts, partZ, it > 0 ? nzparts : 0, red);
   const double rr = uniform_d(red[0]);
-  __syncthreads();
-  double zq = 0.0;
-  if (it > 0) {
-    reduce_partials<1, NT>(partZ, nzparts, red);
-    zq = uniform_d(red[0]);
-    __syncthreads();
-  }
+  const double zq = uniform_d(red[1]);
   const bool active = rr > uniform_d(state[0]);
   const double pq_old = it > 0 ? uniform_d(log[it - 1].sigma[0]) : 1.0;
   const double beta = (active && it > 0 && pq_old > 0.0) ? -zq / pq_old : 0.0;
