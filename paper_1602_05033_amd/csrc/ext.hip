@@ -394,6 +394,9 @@ class ExtSide {
   // One step: V_{m+1} and T_m's block column m.
   void step() {
     const int j = m_;
+    // the next block is allocated first, while the device still works on the
+    // previous step (the inner solve ends with a host wait)
+    double* Vn = new_block();
     const double* Vj = V_[j].as<double>();
     launch_apply<double>(op_.dev, L, Vj, AV_.as<double>(), eg_, st_);
     hipLaunchKernelGGL((k_ext_split<S>), dim3(eg_), dim3(kBlock), 0, st_, Vj, n_, Bs_.as<double>());
@@ -407,7 +410,6 @@ class ExtSide {
                          w_.H.as<double>(), W_.as<double>(), n_);
       LYAP_LAUNCHED("k_ext_update");
     }
-    double* Vn = new_block();
     cholqr2<L>(w_, dwl(), W_.as<double>(), dptrs() + j + 1, Vn, w_.small.as<double>() + 8 * LL, j + 1);
     gram<L>(w_, dptrs() + j, 2, AV_.as<double>());
     hipLaunchKernelGGL((k_ext_tband<L>), dim3(1), dim3(64), 0, st_, w_.H.as<double>(), band_.as<double>(), j,

@@ -372,7 +372,7 @@ InnerCG::InnerCG(const OpDev<double>& op, int n, int S, int pc, double eta, int 
   state_.alloc(64 * sizeof(double));
   tot_.alloc(64 * sizeof(double));
   flag_.alloc(64);
-  hlog_.alloc((size_t)kCgChunk * sizeof(CgIter));
+  hlog_.alloc((size_t)(max_iter + kCgChunk) * sizeof(CgIter));  // a chunk may run to max_iter
   htot_.alloc(64 * sizeof(double) + 64);
   LYAP_HIP(hipMemsetAsync(flag_.p, 0, 64, st_));
   hipLaunchKernelGGL(k_cg_diag, dim3(grid_for(n, 1, 1024)), dim3(kBlock), 0, st_, op_, n_, pc_,
@@ -610,9 +610,12 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
       LYAP_HIP(hipMemcpyAsync(hx_.back().p, X, (size_t)n_ * S * sizeof(double), hipMemcpyDeviceToDevice, st_));
     };
     snapshot();
+    int nchk = 0;
     while (!done && total + it < max_iter_) {
       const int it0 = it;
-      const int cnt = std::min(kCgChunk, max_iter_ - total - it);
+      const int want = start == 0 && !harvesting ? chunk_len(it, nchk, kCgChunk, kCgChunk / 4) : kCgChunk;
+      const int cnt = std::min(want, max_iter_ - total - it);
+      ++nchk;
       for (int c = 0; c < cnt; ++c) iter(it++, start == 0 ? 1 : 0);
       if (harvesting && it % std::max(1, harvest_every_) == 0) snapshot();
       kt ? kt->collect() : (void)0;
@@ -638,6 +641,7 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
       }
     }
     total += it;
+    if (start == 0 && done) pred_ = it;
     true_res();
     LYAP_HIP(hipMemcpyAsync(htot_.p, tot_.p, 2 * S * sizeof(double), hipMemcpyDeviceToHost, st_));
     LYAP_HIP(hipStreamSynchronize(st_));

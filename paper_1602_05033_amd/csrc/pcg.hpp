@@ -3,6 +3,7 @@
 // hand sides at once (independent scalars per column), accepted only when the
 // true relative residual ||b - A x|| / ||b|| is at most eta.
 #pragma once
+#include <algorithm>
 
 #include <memory>
 
@@ -49,11 +50,11 @@ class InnerCG {
   double upd_bytes() const;
   // Later solves use flexible CG with z = M(r) from the network (on the
   // operator's whole grid, K = -A).
-  void set_net(PcNetGpu* net) { net_ = net; net_schur_ = false; }
+  void set_net(PcNetGpu* net) { net_ = net; net_schur_ = false; pred_ = 0; }
   // Later solves use flexible CG on the black Schur complement of the
   // red-black split (IC(0)'s condensed system) with z = M(r) from a network
   // made by make_schur_net (LYAP_PC_LEARNED on a stencil operator, S = 1).
-  void set_net_schur(PcNetGpu* net) { net_ = net; net_schur_ = true; }
+  void set_net_schur(PcNetGpu* net) { net_ = net; net_schur_ = true; pred_ = 0; }
   // A network on the compact grid of the black cells whose diagonal part is
   // diag(Sigma)^{-1} (zero weights: IC(0) itself) and whose K is Sigma.
   std::unique_ptr<PcNetGpu> make_schur_net(int C);
@@ -89,6 +90,15 @@ class InnerCG {
   DevBuf z_, partZ_, partRR_;
   DevBuf r1_, w0_, w1_, s0_, s1_;  // double-buffered r, w = K M r, s = K p of the single-reduction CG
   int harvest_every_ = 0, harvest_keep_ = 0;
+  // iterations of the last solve that converged without a restart: the next
+  // solve's first host check is placed just before it (the right-hand sides of
+  // consecutive solves are alike), later checks every few iterations
+  int pred_ = 0;
+  int chunk_len(int it, int nchk, int base, int tail) const {
+    if (pred_ <= 0) return base;
+    if (it == 0) return std::max(tail, pred_ - tail);
+    return tail << std::min(nchk - 1, 3);
+  }
   // red-black IC(0): 1 / D_r (red slots), D_b and 1 / Sigma_bb (black slots),
   // the condensed iteration's vectors (r, w, s double buffered), u at the
   // black slots and v = D_r^{-1} E^T u at the red slots

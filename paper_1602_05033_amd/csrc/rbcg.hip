@@ -662,9 +662,11 @@ void InnerCG::rb_solve_templ(const double* B, double* X, int restarts, int chunk
       LYAP_HIP(hipMemcpyAsync(hx_.back().p, rb_x_.p, bytes, hipMemcpyDeviceToDevice, st_));
     };
     snapshot();
+    int nchk = 0;
     while (!done && total + it < max_iter_) {
       const int it0 = it;
-      int cnt = std::min(chunk, max_iter_ - total - it);
+      int cnt = std::min(start == 0 ? chunk_len(it, nchk, chunk, chunk / 4) : chunk, max_iter_ - total - it);
+      ++nchk;
       if (harvesting) cnt = std::min(cnt, harvest_every_ - it % harvest_every_);
       for (int c = 0; c < cnt; ++c, ++it) {
         if (kt) kt->mark(LYAP_K_CG_DIR);
@@ -701,6 +703,7 @@ void InnerCG::rb_solve_templ(const double* B, double* X, int restarts, int chunk
       if (!done && harvesting && it % harvest_every_ == 0) snapshot();
     }
     total += it;
+    if (start == 0 && done) pred_ = it;
     const int gf = grid_for(g.nb, 1, 1024);
     hipLaunchKernelGGL((k_rb_finish<K7, S>), dim3(gf), dim3(kBlock), 0, st_, op_, g, B, r_.as<double>(), mode, rinv,
                        rb_x_.as<double>(), X);
@@ -792,9 +795,11 @@ void InnerCG::solve_rb_fcg(const double* B, double* X, KernelTimer* kt) {
     int rparts = G;
     int it = 0;
     bool done = false;
+    int nchk = 0;
     while (!done && total + it < max_iter_) {
       const int it0 = it;
-      const int cnt = std::min(kChunk, max_iter_ - total - it);
+      const int cnt = std::min(start == 0 ? chunk_len(it, nchk, kChunk, kChunk / 4) : kChunk, max_iter_ - total - it);
+      ++nchk;
       for (int c = 0; c < cnt; ++c, ++it) {
         double* pn = pb[it % 2];
         const double* po = pb[(it + 1) % 2];
@@ -831,6 +836,7 @@ void InnerCG::solve_rb_fcg(const double* B, double* X, KernelTimer* kt) {
       }
     }
     total += it;
+    if (start == 0 && done) pred_ = it;
     const int gf = grid_for(g.nb, 1, 1024);
     if (k7)
       hipLaunchKernelGGL((k_rb_finish<true, 1>), dim3(gf), dim3(kBlock), 0, st_, op_, g, B, r_.as<double>(), mode,
