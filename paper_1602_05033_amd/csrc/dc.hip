@@ -820,7 +820,7 @@ __global__ __launch_bounds__(256) void k_zhat(const DcMerge* md, const DcScal* m
 // wave = one of nsp slices of the candidates i; the candidate data (d_i,
 // zhat_i, Rt[i][:]) is the same for every lane, so each wave streams it once
 // for 64 roots.  Per slice sp, rows r < nr and (r = nr) the squared norm go to
-// part[(sp (nr+1) + r) k + a + j]; k_assemble adds the slices up.
+// part[(sp (nr+1) + r) k + a + j]; k_vec_sum adds the slices up.
 template <int NRP>
 __global__ __launch_bounds__(256) void k_vec(const DcMerge* __restrict__ md, const DcScal* __restrict__ ms, int nr,
                                              int k, int nsp, const double* __restrict__ Rt,
@@ -864,6 +864,22 @@ __global__ __launch_bounds__(256) void k_vec(const DcMerge* __restrict__ md, con
 
 constexpr int kMaxSplit = 16;
 
+// NR[r][a + j] = sum over slices of part (rows r < nr), nrm[a + j] = the squared
+// norm; one thread per (row, root).
+__global__ void k_vec_sum(const DcMerge* md, const DcScal* ms, int nr, int k, int nsp, const double* part, double* NR,
+                          double* nrm) {
+  const DcMerge g = md[blockIdx.y];
+  const int Kn = ms[blockIdx.y].Kn;
+  const size_t ps = (size_t)(nr + 1) * k;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < (nr + 1) * Kn; e += gridDim.x * blockDim.x) {
+    const int r = e / Kn, j = e - r * Kn;
+    const double* P = part + (size_t)r * k + g.a + j;
+    double v = 0.0;
+    for (int sp = 0; sp < nsp; ++sp) v += P[sp * ps];
+    if (r < nr) NR[(size_t)r * k + g.a + j] = v;
+    else nrm[g.a + j] = v;
+  }
+}
 
 inline int vec_pad(int nr) { return nr <= 8 ? 8 : nr <= 16 ? 16 : nr <= 32 ? 32 : 64; }
 
@@ -882,22 +898,13 @@ void launch_vec(dim3 grid, const DcMerge* md, const DcScal* ms, int nr, int k, i
 
 // New spectrum = deflated values U new roots, merged in ascending order (ties:
 // deflated first), mapped back to the original orientation.
-// The eigenvector rows of a new root (and its squared norm, row nr) are the
-// sums of k_vec's slices, added in slice order for the root's own column.
-__global__ void k_assemble(const DcMerge* md, const DcScal* ms, int ell, int k, const double* Rin, int nsp,
-                           const double* part, const int* defl, const double* defv, const double* lamn, double* Dout,
+__global__ void k_assemble(const DcMerge* md, const DcScal* ms, int ell, int k, const double* Rin, const double* NR,
+                           const double* nrm, const int* defl, const double* defv, const double* lamn, double* Dout,
                            double* Rout) {
   const DcMerge g = md[blockIdx.y];
   const DcScal& s = ms[blockIdx.y];
   const int a = g.a, K = g.K, Kn = s.Kn, Kd = s.Kd, sg = s.sg;
   const int nr = 4 * ell;
-  const size_t ps = (size_t)(nr + 1) * k;
-  auto slices = [&](int r, int j) {
-    const double* P = part + (size_t)r * k + a + j;
-    double v = 0.0;
-    for (int sp = 0; sp < nsp; ++sp) v += P[sp * ps];
-    return v;
-  };
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < K; e += gridDim.x * blockDim.x) {
     int pos;
     double v;
@@ -921,8 +928,8 @@ __global__ void k_assemble(const DcMerge* md, const DcScal* ms, int ell, int k, 
       for (int r = 0; r < nr; ++r) Rout[(size_t)r * k + a + P] = Rin[(size_t)r * k + a + c];
     } else {
       const int j = e - Kd;
-      const double inv = 1.0 / sqrt(slices(nr, j));
-      for (int r = 0; r < nr; ++r) Rout[(size_t)r * k + a + P] = slices(r, j) * inv;
+      const double inv = 1.0 / sqrt(nrm[a + j]);
+      for (int r = 0; r < nr; ++r) Rout[(size_t)r * k + a + P] = NR[(size_t)r * k + a + j] * inv;
     }
   }
 }
@@ -946,7 +953,7 @@ struct DcWork::Impl {
   hipStream_t st;
   int cap = 0;
   int leaf = 32;
-  DevBuf Da, Db, Ra, Rb, z, Dn, zn, nd, defl, defv, orig, tau, lamn, zh, Rt, part, sml, smv, rdl, rdv;
+  DevBuf Da, Db, Ra, Rb, z, Dn, zn, nd, defl, defv, orig, tau, lamn, zh, Rt, part, NR, nrm, sml, smv, rdl, rdv;
   DevBuf leafA, leafQ, leafL, leafN;
   DevBuf md, ms;
   int md_cap = 0;
@@ -973,6 +980,8 @@ struct DcWork::Impl {
     Da.alloc(d); Db.alloc(d);
     Ra.alloc(d * 4 * ell); Rb.alloc(d * 4 * ell); Rt.alloc(d * vec_pad(4 * ell));
     part.alloc(d * (4 * ell + 1) * kMaxSplit);
+    NR.alloc(d * 4 * ell);
+    nrm.alloc(d);
     z.alloc(d); Dn.alloc(d); zn.alloc(d); defv.alloc(d); tau.alloc(d); lamn.alloc(d); zh.alloc(d);
     nd.alloc(ii); defl.alloc(ii); orig.alloc(ii); sml.alloc(ii); rdl.alloc(ii);
     smv.alloc(d); rdv.alloc(d);
@@ -1114,8 +1123,10 @@ void DcWork::run(const double* band, int ldb, int k, double* lam, double* F, dou
                          w.zh.as<double>(), w.Rt.as<double>());
       launch_vec(dim3(nchunk * (nsp / 4), nm), md, ms, nr, ld, nsp, w.Rt.as<double>(), w.Dn.as<double>(),
                  w.orig.as<int>(), w.tau.as<double>(), w.zh.as<double>(), w.part.as<double>(), st);
-      hipLaunchKernelGGL(k_assemble, dim3(gx, nm), dim3(256), 0, st, md, ms, ell, ld, Rcur, nsp,
-                         w.part.as<double>(), w.defl.as<int>(), w.defv.as<double>(), w.lamn.as<double>(), Dnx, Rnx);
+      hipLaunchKernelGGL(k_vec_sum, dim3(std::min(((nr + 1) * Kmax + 255) / 256, 1024), nm), dim3(256), 0, st, md,
+                         ms, nr, ld, nsp, w.part.as<double>(), w.NR.as<double>(), w.nrm.as<double>());
+      hipLaunchKernelGGL(k_assemble, dim3(gx, nm), dim3(256), 0, st, md, ms, ell, ld, Rcur, w.NR.as<double>(),
+                         w.nrm.as<double>(), w.defl.as<int>(), w.defv.as<double>(), w.lamn.as<double>(), Dnx, Rnx);
       std::swap(Dcur, Dnx);
       std::swap(Rcur, Rnx);
     }

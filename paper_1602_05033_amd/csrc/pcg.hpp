@@ -91,12 +91,13 @@ class InnerCG {
   DevBuf r1_, w0_, w1_, s0_, s1_;  // double-buffered r, w = K M r, s = K p of the single-reduction CG
   int harvest_every_ = 0, harvest_keep_ = 0;
   // iterations of the last solve that converged without a restart: the next
-  // solve's first host check is placed just before it (the right-hand sides of
-  // consecutive solves are alike), later checks every few iterations
+  // solve's first host check is placed just after it (the right-hand sides of
+  // consecutive solves are alike, and a host round trip costs more than a few
+  // iterations), later checks every few iterations
   int pred_ = 0;
   int chunk_len(int it, int nchk, int base, int tail) const {
     if (pred_ <= 0) return base;
-    if (it == 0) return std::max(tail, pred_ - tail);
+    if (it == 0) return pred_ + tail / 2;
     return tail << std::min(nchk - 1, 3);
   }
   // red-black IC(0): 1 / D_r (red slots), D_b and 1 / Sigma_bb (black slots),
