@@ -436,6 +436,20 @@ def main_batch(args):
                                 for (op, C), s in zip(probs, sols)) * per_step_launches * len(runs)
             agg[k]["bytes_per_launch"] = tot_bytes / n_launch
     n_tot = sum(op.n for op, _ in probs)
+    # the error of the equations' Z (FP32 storage) against FP64 evaluations,
+    # after the timed region: the explicit residual of every equation, and the
+    # factor error against the oracle's Krylov-free X of the shifted Laplacian
+    # for 8 equations spread over the sizes (its exponential-sum factor has
+    # about 150 s columns, too large to form for all 64 in a bench run)
+    ex_all = [explicit_residual(b, dop, sol.Z, Cd, sol.beta ** 2) for dop, Cd, sol in zip(dops, Cs, sols)]
+    by_n = sorted(range(len(probs)), key=lambda i: probs[i][0].n)
+    fe = []
+    for i in by_n[::8]:
+        op, C = probs[i]
+        fe.append({"N": op.nx, "s": C.shape[1], "shift": round(op.meta["shift"], 3),
+                   "factor_error": laplace2d_factor_error(op.nx, sols[i].Z, C, op.meta["shift"])})
+    err = {"res_rel_explicit_max": max(ex_all), "res_rel_explicit_median": float(np.median(ex_all)),
+           "factor_error_vs_oracle_X_sample": fe}
     out = {
         "metric": "time to rel. residual 1e-8 for all 64 equations of the batch (grouped launches, two-pass Z)",
         "value": round(ms_per_step / 1000.0, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
@@ -448,7 +462,7 @@ def main_batch(args):
         "result": {"m": [s.m for s in sols], "t": [s.t for s in sols], "total_steps": steps_all,
                    "phases_ms": {k: round(v, 2) for k, v in sols[0].times_ms.items()},
                    "phases_ms_profiled": {k: round(v, 2) for k, v in runs[0][1][0].times_ms.items()},
-                   "step_graphs": graphs},
+                   "step_graphs": graphs, "error_vs_fp64": err},
         "kernels": kernel_table(agg),
         "roofline": roofline(agg, ("spmm_gram", "upd_gram", "chol_gram", "chol_store", "replay")),
         "block_bytes_sum": nsb_tot,
@@ -695,7 +709,7 @@ def oracle_leg_c3(op, C, m_gpu, budget_s):
                        f"included, so this is a lower bound")}
 
 
-def laplace2d_factor_error(N, Z, C):
+def laplace2d_factor_error(N, Z, C, shift=0.0):
     """||Z Z^T - X||_F / ||X||_F for the 5-point Laplacian on an N x N grid,
     X the oracle's Krylov-free solution (sine-transform eigenbasis and an
     exponential sum, oracle.dense): both factors taken to the eigenbasis (an
@@ -705,7 +719,7 @@ def laplace2d_factor_error(N, Z, C):
     import torch
     from oracle import dense as D
     Zh = torch.from_numpy(D.dst2_columns(Z.cpu().numpy(), N)).to(Z.device)
-    Yh = torch.from_numpy(D.laplace2d_expsum_factor(N, C)).to(Z.device)
+    Yh = torch.from_numpy(D.laplace2d_expsum_factor(N, C, shift)).to(Z.device)
     t = Zh.shape[1]
     R = torch.linalg.qr(torch.cat([Zh, Yh], dim=1), mode="r")[1]
     sgn = torch.cat([torch.ones(t, dtype=R.dtype, device=R.device),
