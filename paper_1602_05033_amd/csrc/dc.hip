@@ -87,47 +87,6 @@ __global__ void k_root_out(int k, int ell, int ld, const double* D, const double
   }
 }
 
-// ------------------------------------------------------------------ small SVD (one-sided Jacobi)
-__device__ void svd_small(const double* B, int ell, double* U, double* sig, double* V) {
-  double W[kMaxL * kMaxL];
-  for (int i = 0; i < ell * ell; ++i) W[i] = B[i];  // W[r*ell + c], columns are vectors
-  for (int i = 0; i < ell; ++i)
-    for (int j = 0; j < ell; ++j) V[i * ell + j] = i == j ? 1.0 : 0.0;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0;
-    for (int p = 0; p < ell; ++p)
-      for (int q = p + 1; q < ell; ++q) {
-        double al = 0, be = 0, ga = 0;
-        for (int r = 0; r < ell; ++r) {
-          al += W[r * ell + p] * W[r * ell + p];
-          be += W[r * ell + q] * W[r * ell + q];
-          ga += W[r * ell + p] * W[r * ell + q];
-        }
-        if (fabs(ga) <= 1e-300 || fabs(ga) <= kEps * sqrt(al * be)) continue;
-        off = fmax(off, fabs(ga) / sqrt(al * be));
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int r = 0; r < ell; ++r) {
-          const double wp = W[r * ell + p], wq = W[r * ell + q];
-          W[r * ell + p] = c * wp - s * wq;
-          W[r * ell + q] = s * wp + c * wq;
-          const double vp = V[r * ell + p], vq = V[r * ell + q];
-          V[r * ell + p] = c * vp - s * vq;
-          V[r * ell + q] = s * vp + c * vq;
-        }
-      }
-    if (off <= 2 * kEps) break;
-  }
-  for (int c = 0; c < ell; ++c) {
-    double nn = 0;
-    for (int r = 0; r < ell; ++r) nn += W[r * ell + c] * W[r * ell + c];
-    nn = sqrt(nn);
-    sig[c] = nn;
-    for (int r = 0; r < ell; ++r) U[r * ell + c] = nn > 0 ? W[r * ell + c] / nn : (r == c ? 1.0 : 0.0);
-  }
-}
-
 // ------------------------------------------------------------------ merge setup
 // Builds the sorted eigenvalues of diag(T_L, T_R) and the 4*ell tracked rows
 // [F_L 0; L_L 0; 0 F_R; 0 L_R] in that order.
@@ -162,23 +121,98 @@ __global__ void k_merge_setup(const DcMerge* md, DcScal* ms, const double* band,
   }
 }
 
-// SVD of every merge's coupling block (they depend on T only), one thread per
-// merge of the whole tree.
-__global__ void k_coupling_svd(const DcMerge* md, DcScal* ms, int nm, const double* band, int ldb, int ell) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+// SVD of every merge's coupling block (they depend on T only): one-sided
+// Jacobi, one wave per merge of the whole tree, W and V in LDS.  Each sweep
+// visits the column pairs in the parallel (round-robin) order, the disjoint
+// pairs of a round together: lane k < ell/2 forms the pair's inner products
+// over the rows (in row order) and its rotation, then the lanes apply the
+// round's rotations row by row.  A sweep with no off-diagonal ratio above
+// 2 eps ends it.  (One thread per merge with W in private memory and V
+// updated in place in the output took 0.2 ms per launch.)
+__global__ __launch_bounds__(64) void k_coupling_svd(const DcMerge* md, DcScal* ms, int nm, const double* band,
+                                                     int ldb, int ell) {
+  const int q = blockIdx.x;
   if (q >= nm) return;
+  __shared__ double W[kMaxL * kMaxL], V[kMaxL * kMaxL];
+  __shared__ double sc[kMaxL / 2], ss[kMaxL / 2], soff[kMaxL / 2];
+  __shared__ int sp[kMaxL / 2], sq[kMaxL / 2];
   const DcMerge g = md[q];
   const int a = g.a, K1 = g.K1;
-  double B[kMaxL * kMaxL];
-  // B[r][c] = T(a + K1 + r, a + K1 - ell + c)
-  for (int r = 0; r < ell; ++r)
-    for (int c = 0; c < ell; ++c) {
-      const int row = a + K1 + r, colT = a + K1 - ell + c;
-      const int d = row - colT;
-      B[r * ell + c] = (d >= 0 && d <= ell) ? band[(size_t)colT * ldb + d] : 0.0;
+  const int t = threadIdx.x;
+  // W[r][c] = T(a + K1 + r, a + K1 - ell + c), V = I
+  for (int e = t; e < ell * ell; e += 64) {
+    const int r = e / ell, c = e - r * ell;
+    const int row = a + K1 + r, colT = a + K1 - ell + c;
+    const int d = row - colT;
+    W[e] = (d >= 0 && d <= ell) ? band[(size_t)colT * ldb + d] : 0.0;
+    V[e] = r == c ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int np = (ell + 1) & ~1;  // players (one dummy when ell is odd)
+  const int rot = np - 1;
+  const int half = np / 2;
+  for (int sweep = 0; sweep < 60 && ell > 1; ++sweep) {
+    double off = 0.0;
+    for (int round = 0; round < rot; ++round) {
+      if (t < half) {
+        int p, qq;
+        if (t == 0) { p = 0; qq = 1 + round; }
+        else {
+          p = round + t; if (p >= rot) p -= rot; p += 1;
+          qq = round - t; if (qq < 0) qq += rot; qq += 1;
+        }
+        if (p > qq) { const int x = p; p = qq; qq = x; }
+        double c = 1.0, sn = 0.0;
+        if (qq < ell) {
+          double al = 0, be = 0, ga = 0;
+          for (int r = 0; r < ell; ++r) {
+            const double wp = W[r * ell + p], wq = W[r * ell + qq];
+            al += wp * wp;
+            be += wq * wq;
+            ga += wp * wq;
+          }
+          if (!(fabs(ga) <= 1e-300 || fabs(ga) <= kEps * sqrt(al * be))) {
+            off = fmax(off, fabs(ga) / sqrt(al * be));
+            const double zeta = (be - al) / (2.0 * ga);
+            const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            sn = c * tt;
+          }
+        }
+        sp[t] = p; sq[t] = qq; sc[t] = c; ss[t] = sn;
+      }
+      __syncthreads();
+      for (int e = t; e < half * ell; e += 64) {
+        const int k = e / ell, r = e - k * ell;
+        const int p = sp[k], qq = sq[k];
+        const double sn = ss[k];
+        if (qq >= ell || sn == 0.0) continue;
+        const double c = sc[k];
+        const double wp = W[r * ell + p], wq = W[r * ell + qq];
+        W[r * ell + p] = c * wp - sn * wq;
+        W[r * ell + qq] = sn * wp + c * wq;
+        const double vp = V[r * ell + p], vq = V[r * ell + qq];
+        V[r * ell + p] = c * vp - sn * vq;
+        V[r * ell + qq] = sn * vp + c * vq;
+      }
+      __syncthreads();
     }
+    if (t < half) soff[t] = off;
+    __syncthreads();
+    double mo = 0.0;
+    for (int k = 0; k < half; ++k) mo = fmax(mo, soff[k]);
+    __syncthreads();
+    if (mo <= 2 * kEps) break;  // the same value in every lane
+  }
   DcScal& s = ms[q];
-  svd_small(B, ell, s.U, s.sigma, s.V);
+  for (int c = t; c < ell; c += 64) {
+    double nn = 0;
+    for (int r = 0; r < ell; ++r) nn += W[r * ell + c] * W[r * ell + c];
+    nn = sqrt(nn);
+    s.sigma[c] = nn;
+    for (int r = 0; r < ell; ++r) s.U[r * ell + c] = nn > 0 ? W[r * ell + c] / nn : (r == c ? 1.0 : 0.0);
+  }
+  for (int e = t; e < ell * ell; e += 64) s.V[e] = V[e];
 }
 
 
@@ -1087,7 +1121,7 @@ void DcWork::run(const double* band, int ldb, int k, double* lam, double* F, dou
     if (w.hmd.bytes < ntot * sizeof(DcMerge)) w.hmd.alloc(std::max<size_t>(ntot * sizeof(DcMerge), 4096));
     std::memcpy(w.hmd.p, all.data(), ntot * sizeof(DcMerge));
     LYAP_HIP(hipMemcpyAsync(w.md.p, w.hmd.p, ntot * sizeof(DcMerge), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_coupling_svd, dim3((ntot + 63) / 64), dim3(64), 0, st, w.md.as<DcMerge>(),
+    hipLaunchKernelGGL(k_coupling_svd, dim3(ntot), dim3(64), 0, st, w.md.as<DcMerge>(),
                        w.ms.as<DcScal>(), ntot, band, ldb, ell);
   }
   if (!w.copied) LYAP_HIP(hipEventCreateWithFlags(&w.copied, hipEventDisableTiming));
