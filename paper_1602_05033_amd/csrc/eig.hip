@@ -30,6 +30,103 @@ __global__ void k_band_to_dense(const double* band, int ldb, int ell, int k, dou
 }
 
 // ------------------------------------------------------------------ Jacobi
+// The same sweeps for n <= NN <= 32 with every lane of the wave busy: after
+// the round's rotations are chosen, each index i carries (alpha_i, beta_i,
+// partner i') with row i of J^T A = alpha_i row i + beta_i row i' (c and -s
+// for the first of a pair, c and s for the second, 1 and 0 when not rotated),
+// and the lanes form every entry of J^T A J at once from the four entries it
+// depends on, into a second buffer (then the exact values of the rotated
+// pairs), and every pair of Q's columns row by row.  Two barriers per round;
+// the previous form had 16 lanes working through the rotations one after
+// another in three phases.  Returns the sweeps; the result is in *Aout.
+template <int NN>
+__device__ int jacobi_core_wave(double* A, double* B, double* Q, int n, int max_sweeps, double** Aout) {
+  static_assert(NN <= 32, "one wave, LDS double buffer");
+  __shared__ double sal[NN], sbe[NN], sdn[NN];
+  __shared__ int spa[NN], srot[NN];
+  const int lane = threadIdx.x & 63;
+  for (int e = lane; e < n * n; e += 64) {
+    const int r = e / n;
+    Q[e] = (r == e - r * n) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  *Aout = A;
+  if (n == 1) return 0;
+  const int np = (n + 1) & ~1;
+  const int rot = np - 1;
+  const int half = np / 2;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    int nrot = 0;
+    for (int round = 0; round < rot; ++round) {
+      bool rotated = false;
+      if (lane < half) {
+        const int kp = lane;
+        int p, q;
+        if (kp == 0) { p = 0; q = 1 + round; }
+        else {
+          p = round + kp; if (p >= rot) p -= rot; p += 1;
+          q = round - kp; if (q < 0) q += rot; q += 1;
+        }
+        if (p > q) { int t = p; p = q; q = t; }
+        double c = 1.0, sn = 0.0, dp = 0.0, dq = 0.0;
+        if (q < n) {
+          const double apq = A[p * n + q];
+          const double app = A[p * n + p], aqq = A[q * n + q];
+          if (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app) * fabs(aqq)) && fabs(apq) > 1e-300) {
+            const double theta = (aqq - app) / (2.0 * apq);
+            const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            sn = t * c;
+            dp = app - t * apq;
+            dq = aqq + t * apq;
+            rotated = true;
+          }
+        }
+        sal[p] = c; sbe[p] = -sn; spa[p] = rotated ? q : p; srot[p] = rotated; sdn[p] = dp;
+        if (q < n) { sal[q] = c; sbe[q] = sn; spa[q] = rotated ? p : q; srot[q] = rotated; sdn[q] = dq; }
+      }
+      nrot += __popcll(__ballot(rotated));
+      __syncthreads();
+      for (int e = lane; e < n * n; e += 64) {
+        const int i = e / n, j = e - i * n;
+        const int pi = spa[i], pj = spa[j];
+        double v;
+        if (srot[i] && j == pi) {
+          v = 0.0;  // the rotated pair's off-diagonal entry, set exactly
+        } else if (srot[i] && i == j) {
+          v = sdn[i];
+        } else {
+          const double ai = sal[i], bi = sbe[i], aj = sal[j], bj = sbe[j];
+          const double r0 = ai * A[i * n + j] + bi * A[pi * n + j];    // row update at column j
+          const double r1 = ai * A[i * n + pj] + bi * A[pi * n + pj];  // and at column j'
+          v = aj * r0 + bj * r1;
+        }
+        B[e] = v;
+      }
+      for (int e = lane; e < n * half; e += 64) {  // Q <- Q J, a pair of columns per item
+        const int row = e / half, kp = e - row * half;
+        int p, q;
+        if (kp == 0) { p = 0; q = 1 + round; }
+        else {
+          p = round + kp; if (p >= rot) p -= rot; p += 1;
+          q = round - kp; if (q < 0) q += rot; q += 1;
+        }
+        if (p > q) { int t = p; p = q; q = t; }
+        if (q >= n || !srot[p]) continue;
+        const double c = sal[p], sn = sbe[q];
+        const double qp = Q[row * n + p], qv = Q[row * n + q];
+        Q[row * n + p] = c * qp - sn * qv;
+        Q[row * n + q] = sn * qp + c * qv;
+      }
+      __syncthreads();
+      double* t = A; A = B; B = t;
+    }
+    if (nrot == 0) { *Aout = A; return sweep + 1; }
+  }
+  *Aout = A;
+  return max_sweeps;
+}
+
 // Matrix b of the batch: A + b*strideA (n x n, row-major, lda = n), eigenvector
 // matrix Q + b*strideQ (row-major, eigenvector i in column i), eigenvalues
 // lam + b*strideL, ascending.  On exit A is destroyed.
@@ -177,21 +274,24 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(double* Aall, int64_t st
   __shared__ int sp[MAXN / 2 + 1], sq[MAXN / 2 + 1];
   __shared__ double sc[MAXN / 2 + 1], ss[MAXN / 2 + 1];
   __shared__ double As[LDSN * LDSN], Qs[LDSN * LDSN];
+  __shared__ double Bs[(NN > 0 && NN <= 32) ? LDSN * LDSN : 1];
   __shared__ double stt[3 * (MAXN / 2 + 1)];
   __shared__ int nrot;
   __shared__ int rk[MAXN];
   if (n <= 0) return;
   constexpr bool lds = NN > 0;
   int nsw;
+  double* Ares = As;
   if constexpr (lds) {
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) As[e] = Ag[e];
     __syncthreads();
-    nsw = jacobi_core<NN>(As, Qs, n, max_sweeps, sp, sq, sc, ss, stt, &nrot);
+    if constexpr (NN <= 32) nsw = jacobi_core_wave<NN>(As, Bs, Qs, n, max_sweeps, &Ares);
+    else nsw = jacobi_core<NN>(As, Qs, n, max_sweeps, sp, sq, sc, ss, stt, &nrot);
   } else {
     nsw = jacobi_core<0>(Ag, Qg, n, max_sweeps, sp, sq, sc, ss, stt, &nrot);
   }
   if (sweeps_out && threadIdx.x == 0) sweeps_out[bidx] = nsw;
-  const double* A = lds ? As : Ag;
+  const double* A = lds ? Ares : Ag;
   // sort ascending: rank of each eigenvalue (ties by index), permute columns
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const double li = A[i * n + i];
