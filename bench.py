@@ -775,7 +775,7 @@ def main_c3(args):
                 "avg_launch_us": round(avg_ms * 1000.0, 2),
                 "note": "FP32 multiply-adds of the four convolutions of one network application (the x, r update "
                         "fused into the first adds HBM bytes, no flops counted); the peak counts packed FP32, which "
-                        "this build does not emit (the non-packed rate is half of it)"}
+                        "these kernels do not emit (the non-packed rate is half of it)"}
     else:
         bpl = agg[dom]["bytes_per_launch"]
         gbs = bpl / (avg_ms * 1e-3) / 1e9
@@ -912,7 +912,7 @@ def main_spmm(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+        print(f"bench.py: the solver runs on one GPU only (got --gpus {args.gpus}); "
               "multi-GPU sharding is a design note, not a measured path", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
@@ -1033,7 +1033,7 @@ def main():
                                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                                "frac": round(tf / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
                                "flops_per_launch": flops, "avg_launch_us": round(zf["ms"] / zf["n"] * 1000.0, 2)}
-    # the operator alone (the SpMM of the benchmark spec's HBM figure): W = A V on the
+    # the operator alone (the SpMM whose HBM rate is the headline bandwidth figure): W = A V on the
     # same n x s FP32 block, back-to-back launches timed with HIP events
     Vs = torch.randn(op.n, args.s, device=dev, dtype=torch.float32 if storage == b.STORE_F32 else torch.float64)
     spmm_ms = b.op_apply_timed(dop, Vs, storage, 200)[1]

@@ -349,7 +349,7 @@ InnerCG::InnerCG(const OpDev<double>& op, int n, int S, int pc, double eta, int 
     : op_(op), n_(n), S_(S), pc_(pc), max_iter_(max_iter), eta_(eta), st_(st) {
   LYAP_REQUIRE(S == 1 || S == 2 || S == 4, LYAP_E_UNSUPPORTED, "inner CG supports 1, 2 or 4 right-hand sides");
   LYAP_REQUIRE(pc == LYAP_PC_NONE || pc == LYAP_PC_JACOBI || pc == LYAP_PC_IC0 || pc == LYAP_PC_LEARNED,
-               LYAP_E_UNSUPPORTED, "inner preconditioner %d is not available in this build", pc);
+               LYAP_E_UNSUPPORTED, "inner preconditioner %d is not supported", pc);
   LYAP_REQUIRE(pc != LYAP_PC_LEARNED || S == 1, LYAP_E_UNSUPPORTED,
                "the learned preconditioner handles one right-hand side per solve");
   LYAP_REQUIRE(eta > 0.0 && eta < 1.0, LYAP_E_ARG, "inner_tol=%g must be in (0,1)", eta);
