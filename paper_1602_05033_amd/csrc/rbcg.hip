@@ -471,8 +471,8 @@ __global__ __launch_bounds__(NT) void k_rbf_rr(RbGeom g, const double* __restric
 }
 
 // Sweep A: beta = -(z.q_old) / (p_old.q_old) (0 at it = 0), p = z + beta p_old
-// (0 once r.r <= state); v at the red slots from p at the black neighbours
-// (recomputed from z, p_old there).
+// (0 once r.r <= state); v = D_r^{-1} T^T p at the red slots, by linearity from
+// z at the black neighbours and the previous iteration's v.
 template <bool K7, int NT>
 __global__ __launch_bounds__(NT) void k_rbf_dira(OpDev<double> op, RbGeom g, const double* __restrict__ rinv,
                                                  const double* __restrict__ z, const double* __restrict__ pold,
@@ -497,10 +497,13 @@ __global__ __launch_bounds__(NT) void k_rbf_dira(OpDev<double> op, RbGeom g, con
     int i, j, l;
     if (rb_cell(g, q, 1, i, j, l)) pnew[q] = prow(q);
     if (rb_cell(g, q, 0, i, j, l)) {
+      // v = D_r^{-1} T^T p = D_r^{-1} T^T z + beta v_old (v_old = D_r^{-1} T^T p_old from
+      // the previous iteration): the neighbours' z only, not their p recomputed
       double acc = 0.0;
       for_neighbours<K7>(op, g, i, j, l, i + g.nx * (j + g.ny * l),
-                         [&](int bi, int bj, int bl, int, double t, int) { acc = fma(t, prow(rb_slot(g, bi, bj, bl)), acc); });
-      v[q] = acc * rinv[q];
+                         [&](int bi, int bj, int bl, int, double t, int) { acc = fma(t, z[rb_slot(g, bi, bj, bl)], acc); });
+      const double vz = acc * rinv[q];
+      v[q] = mask * (po ? fma(beta, v[q], vz) : vz);
     }
   }
 }
