@@ -1,7 +1,6 @@
 """Generalized Lyapunov equation A X E + E X A + C C^T = 0 with A symmetric
-negative definite and E symmetric positive definite (Section 6, Example 3:
-for symmetric positive definite E the equation is treated as a standard
-Lyapunov equation).
+negative definite and E symmetric positive definite (Section 6, Example 3,
+where such an equation is reduced to a standard Lyapunov equation).
 
 Oracle -- test infrastructure only.  Plain float64 NumPy/SciPy, dense E (the
 oracle's sizes only).
