@@ -214,28 +214,68 @@ void LanczosSide<T>::accumulate_Z(int m, const double* Mrows, int t, double* Z, 
     LYAP_HIP(hipMemsetAsync(Z, 0, (size_t)ldz * t * sizeof(double), st_));
     const int QB = zflush_max_blocks(S);
     if (two_pass_) {
-      const int R = QB + 2;
-      std::vector<DevBuf> ring;
-      for (int i = 0; i < R; ++i) ring.emplace_back(blk_);
-      launch_init_store<T>(C_, ldc_, n, S, glog_.as<double>(), ring[0].as<T>(), grid_, st_);
+      // Without per-kernel timing the Z accumulation runs on a stream of its
+      // own beside the replays: a flush of blocks [f, f + cnt) waits for the
+      // replays launched so far, and the replay that first overwrites one of
+      // its ring slots (block f + R) waits for the flush; the ring holds two
+      // flushes' blocks.  The flushes stay in order on their stream, so Z has
+      // the same bits either way.
+      const bool side_z = kt_ == nullptr || !kt_->on;
+      const int R = (side_z ? 2 : 1) * QB + 2;
+      DevBuf ringbuf((size_t)R * blk_);
+      auto slot = [&](int i) { return (T*)((char*)ringbuf.p + (size_t)(i % R) * blk_); };
+      struct ZStream {
+        hipStream_t s = nullptr;
+        std::vector<hipEvent_t> ev;
+        ~ZStream() {
+          if (s) (void)hipStreamSynchronize(s);
+          for (auto e : ev) (void)hipEventDestroy(e);
+          if (s) (void)hipStreamDestroy(s);
+        }
+      } zs;
+      constexpr int kZEv = 4;  // at most two flushes outstanding
+      if (side_z) {
+        LYAP_HIP(hipStreamCreateWithFlags(&zs.s, hipStreamNonBlocking));
+        zs.ev.resize(kZEv + 1);
+        for (auto& e : zs.ev) LYAP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      }
+      std::vector<std::pair<int, hipEvent_t>> waits;  // (replay step, flush done)
+      int nev = 0;
+      launch_init_store<T>(C_, ldc_, n, S, glog_.as<double>(), slot(0), grid_, st_);
       std::vector<const void*> pend;
       int first = 0;
       for (int i = 0; i < m; ++i) {
         if (i + 1 < m) {
-          const T* vp = i > 0 ? ring[(i - 1) % R].as<T>() : zero_.as<T>();
+          while (!waits.empty() && waits.front().first <= i) {
+            LYAP_HIP(hipStreamWaitEvent(st_, waits.front().second, 0));
+            waits.erase(waits.begin());
+          }
+          const T* vp = i > 0 ? slot(i - 1) : zero_.as<T>();
           if (kt_) kt_->mark(LYAP_K_REPLAY);
-          launch_replay<T>(op_.dev, S, vp, ring[i % R].as<T>(), ring[(i + 1) % R].as<T>(),
-                           logb_.as<double>() + (size_t)i * LS_, grid_, st_);
+          launch_replay<T>(op_.dev, S, vp, slot(i), slot(i + 1), logb_.as<double>() + (size_t)i * LS_, grid_, st_);
         }
         if (pend.empty()) first = i;
-        pend.push_back(ring[i % R].p);
+        pend.push_back(slot(i));
         if ((int)pend.size() == QB || i == m - 1) {
           if (kt_) kt_->mark(LYAP_K_ZFLUSH);
           zbytes += (double)pend.size() * blk_ + 2.0 * n * t * sizeof(double);
-          launch_zflush<T>(pend.data(), (int)pend.size(), n, S, Mrows + (size_t)first * S * t, t, Z, ldz, 0, st_);
+          hipStream_t fq = st_;
+          if (side_z) {
+            LYAP_HIP(hipEventRecord(zs.ev[kZEv], st_));
+            LYAP_HIP(hipStreamWaitEvent(zs.s, zs.ev[kZEv], 0));
+            fq = zs.s;
+          }
+          launch_zflush<T>(pend.data(), (int)pend.size(), n, S, Mrows + (size_t)first * S * t, t, Z, ldz, 0, fq);
+          if (side_z) {
+            hipEvent_t fe = zs.ev[nev];
+            nev = (nev + 1) % kZEv;
+            LYAP_HIP(hipEventRecord(fe, zs.s));
+            waits.emplace_back(first + R - 1, fe);
+          }
           pend.clear();
         }
       }
+      if (side_z) LYAP_HIP(hipStreamSynchronize(zs.s));
       LYAP_HIP(hipStreamSynchronize(st_));  // the ring is released on return
     } else {
       std::vector<const void*> ptrs;
