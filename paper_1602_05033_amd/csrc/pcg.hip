@@ -586,13 +586,14 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
                                       eta2, pin, pout, flag_.as<int>(), n_, cgrid_, st_); break;
     }
   };
-  auto true_res = [&]() {
+  auto true_res_into = [&](double* r, double* part, double* tot) {
     switch (S) {
-      case 1: cg_launch_true<1>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), cgrid_, st_); break;
-      case 2: cg_launch_true<2>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), cgrid_, st_); break;
-      default: cg_launch_true<4>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), cgrid_, st_); break;
+      case 1: cg_launch_true<1>(op_, B, X, r, n_, part, tot, cgrid_, st_); break;
+      case 2: cg_launch_true<2>(op_, B, X, r, n_, part, tot, cgrid_, st_); break;
+      default: cg_launch_true<4>(op_, B, X, r, n_, part, tot, cgrid_, st_); break;
     }
   };
+  auto true_res = [&]() { true_res_into(r_.as<double>(), partA_.as<double>(), tot_.as<double>()); };
 
   int total = 0;
   double worst = 0.0;
@@ -611,6 +612,7 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
     };
     snapshot();
     int nchk = 0;
+    bool spec = false;  // the last chunk also computed the true residual of X
     while (!done && total + it < max_iter_) {
       const int it0 = it;
       const int want = start == 0 && !harvesting ? chunk_len(it, nchk, kCgChunk, kCgChunk / 4) : kCgChunk;
@@ -619,6 +621,19 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
       for (int c = 0; c < cnt; ++c) iter(it++, start == 0 ? 1 : 0);
       if (harvesting && it % std::max(1, harvest_every_) == 0) snapshot();
       kt ? kt->collect() : (void)0;
+      // when the chunk is expected to end the solve, its true residual goes
+      // out with the same host wait (X does not change after convergence)
+      spec = start == 0 && !harvesting && pred_ > 0;
+      if (spec) {
+        if (!rt_.p) {
+          rt_.alloc((size_t)n_ * S * sizeof(double));
+          partT_.alloc(partA_.bytes);
+          totT_.alloc(64 * sizeof(double));
+          htotT_.alloc(64 * sizeof(double));
+        }
+        true_res_into(rt_.as<double>(), partT_.as<double>(), totT_.as<double>());
+        LYAP_HIP(hipMemcpyAsync(htotT_.p, totT_.p, 2 * S * sizeof(double), hipMemcpyDeviceToHost, st_));
+      }
       LYAP_HIP(hipMemcpyAsync(hlog_.p, log_.as<CgIter>() + it0, (size_t)cnt * sizeof(CgIter), hipMemcpyDeviceToHost,
                               st_));
       LYAP_HIP(hipMemcpyAsync(htot_.as<char>() + 64 * sizeof(double), flag_.p, 8, hipMemcpyDeviceToHost, st_));
@@ -642,10 +657,13 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
     }
     total += it;
     if (start == 0 && done) pred_ = it;
-    true_res();
-    LYAP_HIP(hipMemcpyAsync(htot_.p, tot_.p, 2 * S * sizeof(double), hipMemcpyDeviceToHost, st_));
-    LYAP_HIP(hipStreamSynchronize(st_));
-    const double* h = htot_.as<double>();
+    const double* h = htotT_.as<double>();
+    if (!(done && spec)) {
+      true_res();
+      LYAP_HIP(hipMemcpyAsync(htot_.p, tot_.p, 2 * S * sizeof(double), hipMemcpyDeviceToHost, st_));
+      LYAP_HIP(hipStreamSynchronize(st_));
+      h = htot_.as<double>();
+    }
     worst = 0.0;
     for (int k = 0; k < S; ++k) {
       const double rel = h[S + k] > 0.0 ? std::sqrt(h[k] / h[S + k]) : 0.0;
@@ -667,6 +685,9 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
       return;
     }
     if (total >= max_iter_) break;
+    // the restart starts from the true residual of x
+    if (done && spec)
+      LYAP_HIP(hipMemcpyAsync(r_.p, rt_.p, (size_t)n_ * S * sizeof(double), hipMemcpyDeviceToDevice, st_));
   }
   stats_.iters += total;
   stats_.worst_relres = std::max(stats_.worst_relres, worst);

@@ -88,6 +88,10 @@ class InnerCG {
   CgStats stats_;
   PcNetGpu* net_ = nullptr;
   DevBuf z_, partZ_, partRR_;
+  // the speculative true residual of the Jacobi / plain CG (its own vector,
+  // partials and totals, so that the iteration state is not touched)
+  DevBuf rt_, partT_, totT_;
+  HostBuf htotT_;
   DevBuf r1_, w0_, w1_, s0_, s1_;  // double-buffered r, w = K M r, s = K p of the single-reduction CG
   int harvest_every_ = 0, harvest_keep_ = 0;
   // iterations of the last solve that converged without a restart: the next
