@@ -457,6 +457,17 @@ void cg_true(const OpDev<double>& op, const double* B, const double* x, double* 
   }
 }
 
+void InnerCG::spec_true(const double* B, const double* X) {
+  if (!rt_.p) {
+    rt_.alloc((size_t)n_ * S_ * sizeof(double));
+    partT_.alloc(partA_.bytes);
+    totT_.alloc(64 * sizeof(double));
+    htotT_.alloc(64 * sizeof(double));
+  }
+  cg_true(op_, B, X, rt_.as<double>(), n_, S_, partT_.as<double>(), totT_.as<double>(), cgrid_, st_);
+  LYAP_HIP(hipMemcpyAsync(htotT_.p, totT_.p, 2 * S_ * sizeof(double), hipMemcpyDeviceToHost, st_));
+}
+
 void InnerCG::solve_fcg(const double* B, double* X, KernelTimer* kt) {
   const auto t0 = Clock::now();
   constexpr int NT = stream_threads(1);
@@ -586,14 +597,13 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
                                       eta2, pin, pout, flag_.as<int>(), n_, cgrid_, st_); break;
     }
   };
-  auto true_res_into = [&](double* r, double* part, double* tot) {
+  auto true_res = [&]() {
     switch (S) {
-      case 1: cg_launch_true<1>(op_, B, X, r, n_, part, tot, cgrid_, st_); break;
-      case 2: cg_launch_true<2>(op_, B, X, r, n_, part, tot, cgrid_, st_); break;
-      default: cg_launch_true<4>(op_, B, X, r, n_, part, tot, cgrid_, st_); break;
+      case 1: cg_launch_true<1>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), cgrid_, st_); break;
+      case 2: cg_launch_true<2>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), cgrid_, st_); break;
+      default: cg_launch_true<4>(op_, B, X, r_.as<double>(), n_, partA_.as<double>(), tot_.as<double>(), cgrid_, st_); break;
     }
   };
-  auto true_res = [&]() { true_res_into(r_.as<double>(), partA_.as<double>(), tot_.as<double>()); };
 
   int total = 0;
   double worst = 0.0;
@@ -624,16 +634,7 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
       // when the chunk is expected to end the solve, its true residual goes
       // out with the same host wait (X does not change after convergence)
       spec = start == 0 && !harvesting && pred_ > 0;
-      if (spec) {
-        if (!rt_.p) {
-          rt_.alloc((size_t)n_ * S * sizeof(double));
-          partT_.alloc(partA_.bytes);
-          totT_.alloc(64 * sizeof(double));
-          htotT_.alloc(64 * sizeof(double));
-        }
-        true_res_into(rt_.as<double>(), partT_.as<double>(), totT_.as<double>());
-        LYAP_HIP(hipMemcpyAsync(htotT_.p, totT_.p, 2 * S * sizeof(double), hipMemcpyDeviceToHost, st_));
-      }
+      if (spec) spec_true(B, X);
       LYAP_HIP(hipMemcpyAsync(hlog_.p, log_.as<CgIter>() + it0, (size_t)cnt * sizeof(CgIter), hipMemcpyDeviceToHost,
                               st_));
       LYAP_HIP(hipMemcpyAsync(htot_.as<char>() + 64 * sizeof(double), flag_.p, 8, hipMemcpyDeviceToHost, st_));

@@ -76,6 +76,9 @@ class InnerCG {
   void solve_rb_fcg(const double* B, double* X, KernelTimer* kt);
   template <bool K7, int S>
   void rb_solve_templ(const double* B, double* X, int restarts, int chunk, KernelTimer* kt);
+  // true residual of X = A^{-1} B into rt_ and its totals towards htotT_,
+  // queued behind a chunk that is expected to end the solve
+  void spec_true(const double* B, const double* X);
   double rb_iter_bytes() const;
   double rb_w_bytes() const;
   OpDev<double> op_;
@@ -88,8 +91,8 @@ class InnerCG {
   CgStats stats_;
   PcNetGpu* net_ = nullptr;
   DevBuf z_, partZ_, partRR_;
-  // the speculative true residual of the Jacobi / plain CG (its own vector,
-  // partials and totals, so that the iteration state is not touched)
+  // the speculative true residual (its own vector, partials and totals, so
+  // that the iteration state is not touched)
   DevBuf rt_, partT_, totT_;
   HostBuf htotT_;
   DevBuf r1_, w0_, w1_, s0_, s1_;  // double-buffered r, w = K M r, s = K p of the single-reduction CG

@@ -666,6 +666,8 @@ void InnerCG::rb_solve_templ(const double* B, double* X, int restarts, int chunk
     };
     snapshot();
     int nchk = 0;
+    bool spec = false;  // the last chunk also computed x and its true residual
+    const int gf = grid_for(g.nb, 1, 1024);
     while (!done && total + it < max_iter_) {
       const int it0 = it;
       int cnt = std::min(start == 0 ? chunk_len(it, nchk, chunk, chunk / 4) : chunk, max_iter_ - total - it);
@@ -683,6 +685,14 @@ void InnerCG::rb_solve_templ(const double* B, double* X, int restarts, int chunk
       }
       LYAP_LAUNCHED("k_rb_iter");
       if (kt) kt->collect();
+      // a chunk expected to end the solve also forms x and its true residual
+      // (x does not change after convergence; mode 0 overwrites X)
+      spec = start == 0 && !harvesting && pred_ > 0;
+      if (spec) {
+        hipLaunchKernelGGL((k_rb_finish<K7, S>), dim3(gf), dim3(kBlock), 0, st_, op_, g, B, r_.as<double>(), 0, rinv,
+                           rb_x_.as<double>(), X);
+        spec_true(B, X);
+      }
       LYAP_HIP(hipMemcpyAsync(hlog_.p, log_.as<CgIter>() + it0, (size_t)cnt * sizeof(CgIter), hipMemcpyDeviceToHost,
                               st_));
       LYAP_HIP(hipMemcpyAsync(htot_.as<char>() + 64 * sizeof(double), flag_.p, 8, hipMemcpyDeviceToHost, st_));
@@ -707,14 +717,16 @@ void InnerCG::rb_solve_templ(const double* B, double* X, int restarts, int chunk
     }
     total += it;
     if (start == 0 && done) pred_ = it;
-    const int gf = grid_for(g.nb, 1, 1024);
-    hipLaunchKernelGGL((k_rb_finish<K7, S>), dim3(gf), dim3(kBlock), 0, st_, op_, g, B, r_.as<double>(), mode, rinv,
-                       rb_x_.as<double>(), X);
-    LYAP_LAUNCHED("k_rb_finish");
-    cg_true(op_, B, X, r_.as<double>(), n_, S, partA_.as<double>(), tot_.as<double>(), cgrid_, st_);
-    LYAP_HIP(hipMemcpyAsync(htot_.p, tot_.p, 2 * S * sizeof(double), hipMemcpyDeviceToHost, st_));
-    LYAP_HIP(hipStreamSynchronize(st_));
-    const double* h = htot_.as<double>();
+    const double* h = htotT_.as<double>();
+    if (!(done && spec)) {
+      hipLaunchKernelGGL((k_rb_finish<K7, S>), dim3(gf), dim3(kBlock), 0, st_, op_, g, B, r_.as<double>(), mode, rinv,
+                         rb_x_.as<double>(), X);
+      LYAP_LAUNCHED("k_rb_finish");
+      cg_true(op_, B, X, r_.as<double>(), n_, S, partA_.as<double>(), tot_.as<double>(), cgrid_, st_);
+      LYAP_HIP(hipMemcpyAsync(htot_.p, tot_.p, 2 * S * sizeof(double), hipMemcpyDeviceToHost, st_));
+      LYAP_HIP(hipStreamSynchronize(st_));
+      h = htot_.as<double>();
+    }
     worst = 0.0;
     for (int k = 0; k < S; ++k) {
       const double rel = h[S + k] > 0.0 ? std::sqrt(h[k] / h[S + k]) : 0.0;
@@ -737,6 +749,9 @@ void InnerCG::rb_solve_templ(const double* B, double* X, int restarts, int chunk
       return;
     }
     if (total >= max_iter_) break;
+    // the restart starts from the true residual of x
+    if (done && spec)
+      LYAP_HIP(hipMemcpyAsync(r_.p, rt_.p, (size_t)n_ * S * sizeof(double), hipMemcpyDeviceToDevice, st_));
   }
   stats_.iters += total;
   stats_.worst_relres = std::max(stats_.worst_relres, worst);
@@ -764,6 +779,7 @@ void InnerCG::solve_rb_fcg(const double* B, double* X, KernelTimer* kt) {
   const double eta_rec = 0.5 * eta_;
   const double eta2 = eta_rec * eta_rec;
   const int G = rb_grid_;
+  const int gf = grid_for(g.nb, 1, 1024);
   const double* rinv = rb_rinv_.as<double>();
   const double* db = rb_db_.as<double>();
   double* x = rb_x_.as<double>();
@@ -799,6 +815,7 @@ void InnerCG::solve_rb_fcg(const double* B, double* X, KernelTimer* kt) {
     int it = 0;
     bool done = false;
     int nchk = 0;
+    bool spec = false;  // the last chunk also computed x and its true residual
     while (!done && total + it < max_iter_) {
       const int it0 = it;
       const int cnt = std::min(start == 0 ? chunk_len(it, nchk, kChunk, kChunk / 4) : kChunk, max_iter_ - total - it);
@@ -821,6 +838,18 @@ void InnerCG::solve_rb_fcg(const double* B, double* X, KernelTimer* kt) {
         rparts = zparts;
       }
       if (kt) kt->collect();
+      // a chunk expected to end the solve also forms x and its true residual
+      // (x does not change after convergence; mode 0 overwrites X)
+      spec = start == 0 && pred_ > 0;
+      if (spec) {
+        if (k7)
+          hipLaunchKernelGGL((k_rb_finish<true, 1>), dim3(gf), dim3(kBlock), 0, st_, op_, g, B, r_.as<double>(), 0,
+                             rinv, x, X);
+        else
+          hipLaunchKernelGGL((k_rb_finish<false, 1>), dim3(gf), dim3(kBlock), 0, st_, op_, g, B, r_.as<double>(), 0,
+                             rinv, x, X);
+        spec_true(B, X);
+      }
       LYAP_HIP(hipMemcpyAsync(hlog_.p, log_.as<CgIter>() + it0, (size_t)cnt * sizeof(CgIter), hipMemcpyDeviceToHost,
                               st_));
       LYAP_HIP(hipMemcpyAsync(htot_.as<char>() + 64 * sizeof(double), flag_.p, 8, hipMemcpyDeviceToHost, st_));
@@ -840,18 +869,20 @@ void InnerCG::solve_rb_fcg(const double* B, double* X, KernelTimer* kt) {
     }
     total += it;
     if (start == 0 && done) pred_ = it;
-    const int gf = grid_for(g.nb, 1, 1024);
-    if (k7)
-      hipLaunchKernelGGL((k_rb_finish<true, 1>), dim3(gf), dim3(kBlock), 0, st_, op_, g, B, r_.as<double>(), mode,
-                         rinv, x, X);
-    else
-      hipLaunchKernelGGL((k_rb_finish<false, 1>), dim3(gf), dim3(kBlock), 0, st_, op_, g, B, r_.as<double>(), mode,
-                         rinv, x, X);
-    LYAP_LAUNCHED("k_rb_finish");
-    cg_true(op_, B, X, r_.as<double>(), n_, 1, partA_.as<double>(), tot_.as<double>(), cgrid_, st_);
-    LYAP_HIP(hipMemcpyAsync(htot_.p, tot_.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st_));
-    LYAP_HIP(hipStreamSynchronize(st_));
-    const double* h = htot_.as<double>();
+    const double* h = htotT_.as<double>();
+    if (!(done && spec)) {
+      if (k7)
+        hipLaunchKernelGGL((k_rb_finish<true, 1>), dim3(gf), dim3(kBlock), 0, st_, op_, g, B, r_.as<double>(), mode,
+                           rinv, x, X);
+      else
+        hipLaunchKernelGGL((k_rb_finish<false, 1>), dim3(gf), dim3(kBlock), 0, st_, op_, g, B, r_.as<double>(), mode,
+                           rinv, x, X);
+      LYAP_LAUNCHED("k_rb_finish");
+      cg_true(op_, B, X, r_.as<double>(), n_, 1, partA_.as<double>(), tot_.as<double>(), cgrid_, st_);
+      LYAP_HIP(hipMemcpyAsync(htot_.p, tot_.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st_));
+      LYAP_HIP(hipStreamSynchronize(st_));
+      h = htot_.as<double>();
+    }
     worst = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : 0.0;
     LYAP_REQUIRE(std::isfinite(worst), LYAP_E_NUMERIC, "inner solve produced non-finite values");
     if (worst <= eta_) {
@@ -863,6 +894,8 @@ void InnerCG::solve_rb_fcg(const double* B, double* X, KernelTimer* kt) {
       return;
     }
     if (total >= max_iter_) break;
+    // the restart starts from the true residual of x
+    if (done && spec) LYAP_HIP(hipMemcpyAsync(r_.p, rt_.p, (size_t)n_ * sizeof(double), hipMemcpyDeviceToDevice, st_));
   }
   stats_.iters += total;
   stats_.worst_relres = std::max(stats_.worst_relres, worst);
