@@ -657,7 +657,7 @@ void InnerCG::solve(const double* B, double* X, KernelTimer* kt) {
       }
     }
     total += it;
-    if (start == 0 && done) pred_ = it;
+    if (start == 0 && done) learn_pred(it, nchk, kCgChunk / 4, !harvesting);
     const double* h = htotT_.as<double>();
     if (!(done && spec)) {
       true_res();

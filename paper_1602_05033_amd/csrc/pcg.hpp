@@ -50,11 +50,11 @@ class InnerCG {
   double upd_bytes() const;
   // Later solves use flexible CG with z = M(r) from the network (on the
   // operator's whole grid, K = -A).
-  void set_net(PcNetGpu* net) { net_ = net; net_schur_ = false; pred_ = 0; }
+  void set_net(PcNetGpu* net) { net_ = net; net_schur_ = false; pred_ = marg_ = 0; }
   // Later solves use flexible CG on the black Schur complement of the
   // red-black split (IC(0)'s condensed system) with z = M(r) from a network
   // made by make_schur_net (LYAP_PC_LEARNED on a stencil operator, S = 1).
-  void set_net_schur(PcNetGpu* net) { net_ = net; net_schur_ = true; pred_ = 0; }
+  void set_net_schur(PcNetGpu* net) { net_ = net; net_schur_ = true; pred_ = marg_ = 0; }
   // A network on the compact grid of the black cells whose diagonal part is
   // diag(Sigma)^{-1} (zero weights: IC(0) itself) and whose K is Sigma.
   std::unique_ptr<PcNetGpu> make_schur_net(int C);
@@ -98,14 +98,29 @@ class InnerCG {
   DevBuf r1_, w0_, w1_, s0_, s1_;  // double-buffered r, w = K M r, s = K p of the single-reduction CG
   int harvest_every_ = 0, harvest_keep_ = 0;
   // iterations of the last solve that converged without a restart: the next
-  // solve's first host check is placed just after it (the right-hand sides of
-  // consecutive solves are alike, and a host round trip costs more than a few
-  // iterations), later checks every few iterations
-  int pred_ = 0;
+  // solve's first host check is placed just after it plus a margin (the
+  // right-hand sides of consecutive solves are alike, and a host round trip
+  // costs more than a few iterations), later checks every few iterations.
+  // Iterations past convergence are masked (they leave x unchanged) but cost
+  // as much as the others, so the margin adapts: one less after a first chunk
+  // that sufficed with room to spare (down to one, the least that still sees
+  // convergence at the predicted count), twice as many after one that did not
+  // (at most `tail`).  The chunking changes no result.
+  int pred_ = 0, marg_ = 0;
+  int margin(int tail) const { return marg_ > 0 ? marg_ : std::max(1, tail / 2); }
   int chunk_len(int it, int nchk, int base, int tail) const {
     if (pred_ <= 0) return base;
-    if (it == 0) return pred_ + tail / 2;
+    if (it == 0) return pred_ + margin(tail);
     return tail << std::min(nchk - 1, 3);
+  }
+  // after a solve without a restart that converged after `it` iterations in
+  // `nchk` chunks (`chunked`: the chunks came from chunk_len)
+  void learn_pred(int it, int nchk, int tail, bool chunked) {
+    if (pred_ > 0 && chunked) {
+      const int m = margin(tail);
+      marg_ = nchk == 1 ? (pred_ + m - it > 1 ? std::max(1, m - 1) : m) : std::min(tail, 2 * m);
+    }
+    pred_ = it;
   }
   // red-black IC(0): 1 / D_r (red slots), D_b and 1 / Sigma_bb (black slots),
   // the condensed iteration's vectors (r, w, s double buffered), u at the

@@ -716,7 +716,7 @@ void InnerCG::rb_solve_templ(const double* B, double* X, int restarts, int chunk
       if (!done && harvesting && it % harvest_every_ == 0) snapshot();
     }
     total += it;
-    if (start == 0 && done) pred_ = it;
+    if (start == 0 && done) learn_pred(it, nchk, chunk / 4, !harvesting);
     const double* h = htotT_.as<double>();
     if (!(done && spec)) {
       hipLaunchKernelGGL((k_rb_finish<K7, S>), dim3(gf), dim3(kBlock), 0, st_, op_, g, B, r_.as<double>(), mode, rinv,
@@ -868,7 +868,7 @@ void InnerCG::solve_rb_fcg(const double* B, double* X, KernelTimer* kt) {
       }
     }
     total += it;
-    if (start == 0 && done) pred_ = it;
+    if (start == 0 && done) learn_pred(it, nchk, kChunk / 4, true);
     const double* h = htotT_.as<double>();
     if (!(done && spec)) {
       if (k7)
