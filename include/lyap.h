@@ -180,7 +180,7 @@ typedef struct lyap_result {
   double times_ms[8];
   int64_t inner_iters; /* total inner iterations (extended Krylov)         */
   int32_t n_inner;     /* number of inner solves                           */
-  int32_t n_checks;
+  int32_t n_checks;    /* residual checks whose results were read           */
   double* T_band;      /* host, (ell+1) x (ell*m) lower band of T_m (want_T) */
   double* gamma;       /* host, ell x ell, column-major (want_T)            */
   double* tau;         /* host, ell x ell tau_{m+1,m}, column-major (want_T) */

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <limits>
 #include <type_traits>
+#include <memory>
 #include <vector>
 
 #include "check.hpp"
@@ -73,6 +74,24 @@ int CheckSchedule::next(int m, double res, double tol) {
   }
   return std::min(nxt, max_iter);
 }
+
+// One residual check in flight: its stream (owned unless it is the solver's),
+// completion event, workspace and result buffers, and the step it checks.
+struct CheckSlot {
+  hipStream_t st = nullptr;
+  bool own = false;
+  hipEvent_t ev = nullptr;
+  std::unique_ptr<Checker> ck;
+  DevBuf chk;
+  HostBuf hchk, hflags;
+  int mm = 0;
+  ~CheckSlot() {
+    // a check still running reads the Lanczos side's buffers: let it end
+    if (own && st) (void)hipStreamSynchronize(st);
+    if (ev) (void)hipEventDestroy(ev);
+    if (own && st) (void)hipStreamDestroy(st);
+  }
+};
 
 // -------------------------------------------------------------- result helpers
 void store_history(lyap_result* out, const std::vector<int>& hm, const std::vector<double>& hr) {
@@ -305,40 +324,52 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   kt.st = st;
   kt.on = o.profile != 0;
   LanczosSide<T> side(A, C, S, ldc, maxit, o.two_pass != 0, st, &kt);
-  DevBuf chk(sizeof(CheckOut));
-  HostBuf hchk(sizeof(CheckOut));
 
   side.init();
   out->beta = side.beta();
   const double beta2 = out->beta * out->beta;
 
-  // Residual checks run on a second stream while the Lanczos steps continue:
+  // Residual checks run on other streams while the Lanczos steps continue:
   // a check at mm reads only T_mm's band, gamma and tau_{mm+1,mm}, which later
   // steps never write.  The host keeps at most kAhead steps queued ahead of
   // the GPU, so after the converging check the extra steps are few; they are
-  // simply not used (the accepted basis is the checked one).  With
+  // simply not used (the accepted basis is the checked one).  With a fixed
+  // schedule (opts->check_every > 0) the check points do not depend on the
+  // results, so up to kSlots checks run at once, each on a stream and with a
+  // workspace of its own, and are read in the order they were issued: the
+  // first that meets the tolerance ends the iteration, exactly as with one
+  // check at a time (later ones still running are not used), and the steps
+  // stay at most kAhead past the next check point.  The adaptive schedule
+  // places each check from the previous result: one at a time.  With
   // opts->profile the checks run on the solver's stream, one at a time.
-  constexpr int kAhead = 24;
+  constexpr int kAhead = 24, kSlots = 3;
   const bool overlap = o.profile == 0;
-  hipStream_t cst = st;
-  struct StreamGuard {
-    hipStream_t s = nullptr;
-    ~StreamGuard() { if (s) (void)hipStreamDestroy(s); }
-  } sg;
-  if (overlap) {
-    LYAP_HIP(hipStreamCreateWithFlags(&sg.s, hipStreamNonBlocking));
-    cst = sg.s;
+  const bool fixed = o.check_every > 0;
+  const int nslots = overlap && fixed ? kSlots : 1;
+  std::vector<std::unique_ptr<CheckSlot>> slots;
+  for (int i = 0; i < nslots; ++i) {
+    slots.emplace_back(new CheckSlot);
+    CheckSlot& sl = *slots.back();
+    if (overlap) {
+      LYAP_HIP(hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking));
+      sl.own = true;
+    } else {
+      sl.st = st;
+    }
+    LYAP_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+    sl.ck.reset(new Checker(S, S, sl.st));
+    sl.chk.alloc(sizeof(CheckOut));
+    sl.hchk.alloc(sizeof(CheckOut));
+    sl.hflags.alloc(64);
   }
   struct EventRing {
     std::vector<hipEvent_t> ev;
     ~EventRing() { for (auto e : ev) (void)hipEventDestroy(e); }
   } er;
-  er.ev.resize(kAhead + 2);
+  er.ev.resize(kAhead + 1);
   for (auto& e : er.ev) LYAP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  hipEvent_t ev_step = er.ev[kAhead], ev_chk = er.ev[kAhead + 1];
-  HostBuf hflags(64);
+  hipEvent_t ev_step = er.ev[kAhead];
 
-  Checker ck(S, S, cst);
   CheckSchedule sched{o.check_every, maxit};
   std::vector<int> hm;
   std::vector<double> hr;
@@ -350,43 +381,43 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   double lam_absmax = 0.0;
   int checked_m = 0;
   double t_to_tol = 0.0;
-  bool pending = false;
-  int pending_mm = 0;
+  int head = 0, npend = 0;  // checks in flight: slots head, head + 1, ... (mod nslots)
+  int last_launched = 0;
+  CheckSlot* done_slot = slots[0].get();  // the slot of the last check read
 
-  auto launch_check = [&](int mm) {
+  auto launch_check = [&](CheckSlot& sl, int mm) {
     LYAP_HIP(hipEventRecord(ev_step, st));
-    LYAP_HIP(hipStreamWaitEvent(cst, ev_step, 0));
+    LYAP_HIP(hipStreamWaitEvent(sl.st, ev_step, 0));
     kt.mark(LYAP_K_CHECK);
-    ck.run(side.band(), mm * S, side.gamma_dev(), side.tau_dev(mm), chk.as<CheckOut>());
-    LYAP_HIP(hipMemcpyAsync(hchk.p, chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, cst));
-    LYAP_HIP(hipMemcpyAsync(hflags.p, side.flags_dev(), 2 * sizeof(int), hipMemcpyDeviceToHost, cst));
-    LYAP_HIP(hipEventRecord(ev_chk, cst));
-    pending = true;
-    pending_mm = mm;
-    out->n_checks++;
+    sl.ck->run(side.band(), mm * S, side.gamma_dev(), side.tau_dev(mm), sl.chk.as<CheckOut>());
+    LYAP_HIP(hipMemcpyAsync(sl.hchk.p, sl.chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, sl.st));
+    LYAP_HIP(hipMemcpyAsync(sl.hflags.p, side.flags_dev(), 2 * sizeof(int), hipMemcpyDeviceToHost, sl.st));
+    LYAP_HIP(hipEventRecord(sl.ev, sl.st));
+    sl.mm = mm;
   };
-  auto wait_check = [&]() {
+  auto wait_check = [&](CheckSlot& sl) {
     const auto t0 = Clock::now();
-    LYAP_HIP(hipEventSynchronize(ev_chk));
+    LYAP_HIP(hipEventSynchronize(sl.ev));
     check_ms += ms_since(t0);
     kt.collect();
   };
   // Reads the finished check; returns true when the iteration stops.
-  auto finish_check = [&]() -> bool {
-    pending = false;
-    const int mm = pending_mm;
-    const CheckOut c = *hchk.as<CheckOut>();
-    const int fb = hflags.as<int>()[0], fn = hflags.as<int>()[1];
+  auto finish_check = [&](CheckSlot& sl) -> bool {
+    done_slot = &sl;
+    out->n_checks++;
+    const int mm = sl.mm;
+    const CheckOut c = *sl.hchk.as<CheckOut>();
+    const int fb = sl.hflags.as<int>()[0], fn = sl.hflags.as<int>()[1];
     // non-finite values that follow a breakdown belong to the breakdown
     LYAP_REQUIRE(!(fn > 0 && fn <= mm && (fb == 0 || fn <= fb)), LYAP_E_NUMERIC,
                  "non-finite values in the Lanczos recurrence at step %d", fn);
     if (fb > 0 && fb <= mm) {
       // a rank-deficient block at step fb-1: check the basis it ends instead
       LYAP_HIP(hipStreamSynchronize(st));
-      launch_check(fb);
-      wait_check();
-      const CheckOut cb = *hchk.as<CheckOut>();
-      pending = false;
+      launch_check(sl, fb);
+      out->n_checks++;
+      wait_check(sl);
+      const CheckOut cb = *sl.hchk.as<CheckOut>();
       LYAP_REQUIRE(std::isfinite(cb.res), LYAP_E_NUMERIC, "residual is not finite at m=%d", fb);
       const double rel = cb.res / beta2;
       hm.push_back(fb);
@@ -424,35 +455,49 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
       m = mm;
       return true;
     }
-    next_check = sched.next(mm, rel, o.tol);
+    if (!fixed) next_check = sched.next(mm, rel, o.tol);
     return false;
   };
 
   const auto t_pass1 = Clock::now();
   int steps = 0;  // steps enqueued
   while (true) {
-    if (pending) {
-      const hipError_t q = hipEventQuery(ev_chk);
-      if (q == hipSuccess || steps >= maxit || !overlap) {
-        if (q != hipSuccess) wait_check();
-        if (finish_check()) break;
+    if (npend > 0) {
+      CheckSlot& sl = *slots[head];
+      const hipError_t q = hipEventQuery(sl.ev);
+      // wait when nothing else can proceed: the steps are done, or (fixed
+      // schedule) every slot is busy and the steps are kAhead past the next
+      // check point
+      const bool stuck = steps >= maxit || (fixed && npend == nslots && steps >= next_check + kAhead);
+      if (q == hipSuccess || stuck || !overlap) {
+        if (q != hipSuccess) wait_check(sl);
+        --npend;
+        head = (head + 1) % nslots;
+        if (finish_check(sl)) break;
+        continue;
       } else if (q != hipErrorNotReady) {
         LYAP_HIP(q);
       }
     }
-    if (!pending && (steps >= next_check || steps >= maxit)) {
+    if (npend < nslots && next_check > last_launched && (steps >= next_check || steps >= maxit)) {
       // always at the scheduled point (not at however far the steps have run
       // ahead), so that the result does not depend on timing
-      launch_check(std::min(next_check, steps));
+      const int mm = std::min(next_check, steps);
+      launch_check(*slots[(head + npend) % nslots], mm);
+      ++npend;
+      last_launched = mm;
+      if (fixed) next_check = std::min(mm + sched.d, maxit);
       continue;
     }
     if (steps >= maxit) continue;  // a check is pending
+    if (fixed && steps >= next_check + kAhead) continue;  // waits for a slot
     if (steps >= kAhead) LYAP_HIP(hipEventSynchronize(er.ev[steps % kAhead]));
     side.step();
     LYAP_HIP(hipEventRecord(er.ev[steps % kAhead], st));
     ++steps;
   }
-  if (overlap) LYAP_HIP(hipStreamWaitEvent(st, ev_chk, 0));  // finalisation reads the checker's results
+  // finalisation reads the results of the check that ended the iteration
+  if (overlap) LYAP_HIP(hipStreamWaitEvent(st, done_slot->ev, 0));
   const double pass1_ms = ms_since(t_pass1) - check_ms;
   out->m = m;
   out->res = last_res;
@@ -472,7 +517,7 @@ lyap_status solve_std(const lyap_op* A, const double* C, int S, int64_t ldc, con
   out->trunc_eps = eps;
   DevBuf M;
   kt.mark(LYAP_K_FINAL);
-  const int t = finalise_factor(ck, side.band(), side.gamma_dev(), eps, M, st);
+  const int t = finalise_factor(*done_slot->ck, side.band(), side.gamma_dev(), eps, M, st);
   kt.collect();
   out->t = t;
   const double fin_ms = ms_since(t_fin);
