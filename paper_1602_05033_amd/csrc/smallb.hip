@@ -21,6 +21,7 @@
 // Z2 = P N, so that Z1 Z2^T ~= V_m Y1 P^T = X_m.
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <vector>
 
 #include "aca.hpp"
@@ -381,6 +382,29 @@ inline int grid_for_elems(int64_t tot, int cap = 4096) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, cap));
 }
 
+// One Algorithm 5 check in flight: its stream (owned unless it is the
+// solver's), completion event, workspace, result buffers (the check's output,
+// the extreme Ritz values, the Lanczos flags) and the step it checks.
+struct Alg5Slot {
+  hipStream_t st = nullptr;
+  bool own = false;
+  hipEvent_t ev = nullptr;
+  std::unique_ptr<Checker> ck;
+  DevBuf part, counter, chk;
+  HostBuf hchk;
+  int mm = 0;
+  CheckOut* hc() const { return hchk.as<CheckOut>(); }
+  double* hl() const { return reinterpret_cast<double*>(hchk.as<char>() + sizeof(CheckOut)); }
+  int* hf() const { return reinterpret_cast<int*>(hchk.as<char>() + sizeof(CheckOut) + 2 * sizeof(double)); }
+  ~Alg5Slot() {
+    // a check still running reads the Lanczos side's buffers: let it end
+    if (own && st) (void)hipStreamSynchronize(st);
+    if (ev) (void)hipEventDestroy(ev);
+    if (own && st) (void)hipStreamDestroy(st);
+  }
+};
+
+
 template <typename T>
 lyap_status smallb_impl(const lyap_op* A, const double* B, int n2, int64_t ldb, const double* C1, int64_t ldc1,
                         const double* C2, int64_t ldc2, int S, const lyap_opts& o, sylv_result* out) {
@@ -418,97 +442,106 @@ lyap_status smallb_impl(const lyap_op* A, const double* B, int n2, int64_t ldb, 
   const double ups_abs = std::max(std::fabs(hb[1]), std::fabs(hb[2]));
   const double b12 = out->beta1 * out->beta2;
 
-  // Checks on a second stream while the Lanczos steps proceed (as in
-  // lyap_solve): a check at mm reads only the leading band and the log.
-  constexpr int kAhead = 24;
+  // Checks on other streams while the Lanczos steps proceed (as in
+  // lyap_solve): a check at mm reads only the leading band and the log.  With
+  // a fixed schedule up to kSlots checks are in flight at once, each with a
+  // stream and workspace of its own, read in the order issued (the first
+  // under the tolerance ends the iteration, as with one at a time); the steps
+  // stay at most kAhead past the next check point.
+  constexpr int kAhead = 24, kSlots = 3;
   const bool overlap = o.profile == 0;
-  hipStream_t cst = st;
-  struct StreamGuard {
-    hipStream_t s = nullptr;
-    ~StreamGuard() { if (s) (void)hipStreamDestroy(s); }
-  } sg;
-  if (overlap) {
-    LYAP_HIP(hipStreamCreateWithFlags(&sg.s, hipStreamNonBlocking));
-    cst = sg.s;
+  const bool fixed = o.check_every > 0;
+  const int nslots = overlap && fixed ? kSlots : 1;
+  std::vector<std::unique_ptr<Alg5Slot>> slots;
+  for (int i = 0; i < nslots; ++i) {
+    slots.emplace_back(new Alg5Slot);
+    Alg5Slot& sl = *slots.back();
+    if (overlap) {
+      LYAP_HIP(hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking));
+      sl.own = true;
+    } else {
+      sl.st = st;
+    }
+    LYAP_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+    sl.ck.reset(new Checker(S, S, sl.st));
+    sl.part.alloc(4096 * sizeof(double));
+    sl.counter.alloc(64);
+    sl.chk.alloc(sizeof(CheckOut));
+    sl.hchk.alloc(sizeof(CheckOut) + 2 * sizeof(double) + 2 * sizeof(int));
+    LYAP_HIP(hipMemsetAsync(sl.counter.p, 0, 64, st));
   }
   struct EventRing {
     std::vector<hipEvent_t> ev;
     ~EventRing() { for (auto e : ev) (void)hipEventDestroy(e); }
   } er;
-  er.ev.resize(kAhead + 2);
+  er.ev.resize(kAhead + 1);
   for (auto& e : er.ev) LYAP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  hipEvent_t ev_step = er.ev[kAhead], ev_chk = er.ev[kAhead + 1];
-
-  Checker ca(S, S, cst);
-  DevBuf part(4096 * sizeof(double)), counter(64), chk(sizeof(CheckOut));
-  HostBuf hchk(sizeof(CheckOut) + 2 * sizeof(double) + 2 * sizeof(int));
-  LYAP_HIP(hipMemsetAsync(counter.p, 0, 64, st));
+  hipEvent_t ev_step = er.ev[kAhead];
   LYAP_HIP(hipStreamSynchronize(st));
+
   CheckSchedule sched{o.check_every, maxit};
   std::vector<int> hm;
   std::vector<double> hr;
   double check_ms = 0.0, t_to_tol = 0.0, lam_abs = 0.0, last_res = INFINITY;
   int next_check = sched.first(), m = 0;
   lyap_status status = LYAP_NOT_CONVERGED;
-  bool pending = false;
-  int pending_mm = 0;
-  CheckOut* hc = hchk.as<CheckOut>();
-  double* hl = reinterpret_cast<double*>(hchk.as<char>() + sizeof(CheckOut));
-  int* hf = reinterpret_cast<int*>(hchk.as<char>() + sizeof(CheckOut) + 2 * sizeof(double));
+  int head = 0, npend = 0;  // checks in flight: slots head, head + 1, ... (mod nslots)
+  int last_launched = 0;
+  Alg5Slot* done_slot = slots[0].get();  // the slot of the last check read
 
-  auto launch_check = [&](int mm) {
+  auto launch_check = [&](Alg5Slot& sl, int mm) {
     LYAP_HIP(hipEventRecord(ev_step, st));
-    LYAP_HIP(hipStreamWaitEvent(cst, ev_step, 0));
+    LYAP_HIP(hipStreamWaitEvent(sl.st, ev_step, 0));
     kt.mark(LYAP_K_CHECK);
     const int k = mm * S;
+    Checker& ca = *sl.ck;
     ca.prepare(sa.band(), k, sa.gamma_dev(), sa.tau_dev(mm));
     const int grid = std::max(1, std::min(n2, 2048));
-    hipLaunchKernelGGL(k_alg5_sum, dim3(grid), dim3(kBlock), 0, cst, ca.lam(), ca.g(), ca.Wm(), k, S,
-                       ups.as<double>(), H.as<double>(), n2, part.as<double>(), counter.as<unsigned>(),
-                       chk.as<CheckOut>());
+    hipLaunchKernelGGL(k_alg5_sum, dim3(grid), dim3(kBlock), 0, sl.st, ca.lam(), ca.g(), ca.Wm(), k, S,
+                       ups.as<double>(), H.as<double>(), n2, sl.part.as<double>(), sl.counter.as<unsigned>(),
+                       sl.chk.as<CheckOut>());
     LYAP_LAUNCHED("k_alg5_sum");
-    LYAP_HIP(hipMemcpyAsync(hc, chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, cst));
-    LYAP_HIP(hipMemcpyAsync(&hl[0], ca.lam(), sizeof(double), hipMemcpyDeviceToHost, cst));
-    LYAP_HIP(hipMemcpyAsync(&hl[1], ca.lam() + k - 1, sizeof(double), hipMemcpyDeviceToHost, cst));
-    LYAP_HIP(hipMemcpyAsync(&hf[0], sa.flags_dev(), 2 * sizeof(int), hipMemcpyDeviceToHost, cst));
-    LYAP_HIP(hipEventRecord(ev_chk, cst));
-    pending = true;
-    pending_mm = mm;
-    out->n_checks++;
+    LYAP_HIP(hipMemcpyAsync(sl.hc(), sl.chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, sl.st));
+    LYAP_HIP(hipMemcpyAsync(&sl.hl()[0], ca.lam(), sizeof(double), hipMemcpyDeviceToHost, sl.st));
+    LYAP_HIP(hipMemcpyAsync(&sl.hl()[1], ca.lam() + k - 1, sizeof(double), hipMemcpyDeviceToHost, sl.st));
+    LYAP_HIP(hipMemcpyAsync(&sl.hf()[0], sa.flags_dev(), 2 * sizeof(int), hipMemcpyDeviceToHost, sl.st));
+    LYAP_HIP(hipEventRecord(sl.ev, sl.st));
+    sl.mm = mm;
   };
-  auto wait_check = [&]() {
+  auto wait_check = [&](Alg5Slot& sl) {
     const auto t0 = Clock::now();
-    LYAP_HIP(hipEventSynchronize(ev_chk));
+    LYAP_HIP(hipEventSynchronize(sl.ev));
     check_ms += ms_since(t0);
     kt.collect();
   };
-  auto record = [&](int mm) -> double {
-    const CheckOut c = *hc;
+  auto record = [&](Alg5Slot& sl, int mm) -> double {
+    const CheckOut c = *sl.hc();
     LYAP_REQUIRE(std::isfinite(c.res), LYAP_E_NUMERIC, "residual is not finite at m=%d", mm);
     const double rel = c.res / b12;
     hm.push_back(mm);
     hr.push_back(rel);
     last_res = rel;
-    lam_abs = std::max(std::fabs(hl[0]), std::fabs(hl[1]));
+    lam_abs = std::max(std::fabs(sl.hl()[0]), std::fabs(sl.hl()[1]));
     if (o.verbose) std::fprintf(stderr, "[sylv-small-b] m=%d k=%d res=%.3e\n", mm, mm * S, rel);
     LYAP_REQUIRE(c.lam_max < 0.0, LYAP_E_INDEFINITE,
                  "Ritz value %.3e >= 0 at m=%d: A is not negative definite", c.lam_max, mm);
     return rel;
   };
-  auto finish_check = [&]() -> bool {
-    pending = false;
-    const int mm = pending_mm;
-    const int fbk = hf[0], fnf = hf[1];
+  auto finish_check = [&](Alg5Slot& sl) -> bool {
+    done_slot = &sl;
+    out->n_checks++;
+    const int mm = sl.mm;
+    const int fbk = sl.hf()[0], fnf = sl.hf()[1];
     const bool bk = fbk > 0 && fbk <= mm;
     // non-finite values that follow a breakdown belong to the breakdown
     LYAP_REQUIRE(!(fnf > 0 && fnf <= mm && (!bk || fnf <= fbk)), LYAP_E_NUMERIC,
                  "non-finite values in the Lanczos recurrence at step %d", fnf);
     if (bk) {  // a rank-deficient block: check the basis it ends instead
       LYAP_HIP(hipStreamSynchronize(st));
-      launch_check(fbk);
-      wait_check();
-      pending = false;
-      const double rel = record(fbk);
+      launch_check(sl, fbk);
+      out->n_checks++;
+      wait_check(sl);
+      const double rel = record(sl, fbk);
       m = fbk;
       if (rel <= o.tol) {
         status = LYAP_OK;
@@ -519,7 +552,7 @@ lyap_status smallb_impl(const lyap_op* A, const double* B, int n2, int64_t ldb, 
       }
       return true;
     }
-    const double rel = record(mm);
+    const double rel = record(sl, mm);
     if (rel <= o.tol) {
       status = LYAP_OK;
       m = mm;
@@ -530,33 +563,43 @@ lyap_status smallb_impl(const lyap_op* A, const double* B, int n2, int64_t ldb, 
       m = mm;
       return true;
     }
-    next_check = sched.next(mm, rel, o.tol);
+    if (!fixed) next_check = sched.next(mm, rel, o.tol);
     return false;
   };
 
   const auto t_pass1 = Clock::now();
   int steps = 0;
   while (true) {
-    if (pending) {
-      const hipError_t q = hipEventQuery(ev_chk);
-      if (q == hipSuccess || steps >= maxit || !overlap) {
-        if (q != hipSuccess) wait_check();
-        if (finish_check()) break;
+    if (npend > 0) {
+      Alg5Slot& sl = *slots[head];
+      const hipError_t q = hipEventQuery(sl.ev);
+      const bool stuck = steps >= maxit || (fixed && npend == nslots && steps >= next_check + kAhead);
+      if (q == hipSuccess || stuck || !overlap) {
+        if (q != hipSuccess) wait_check(sl);
+        --npend;
+        head = (head + 1) % nslots;
+        if (finish_check(sl)) break;
+        continue;
       } else if (q != hipErrorNotReady) {
         LYAP_HIP(q);
       }
     }
-    if (!pending && (steps >= next_check || steps >= maxit)) {
-      launch_check(std::min(next_check, steps));
+    if (npend < nslots && next_check > last_launched && (steps >= next_check || steps >= maxit)) {
+      const int mm = std::min(next_check, steps);
+      launch_check(*slots[(head + npend) % nslots], mm);
+      ++npend;
+      last_launched = mm;
+      if (fixed) next_check = std::min(mm + sched.d, maxit);
       continue;
     }
     if (steps >= maxit) continue;
+    if (fixed && steps >= next_check + kAhead) continue;  // waits for a slot
     if (steps >= kAhead) LYAP_HIP(hipEventSynchronize(er.ev[steps % kAhead]));
     sa.step();
     LYAP_HIP(hipEventRecord(er.ev[steps % kAhead], st));
     ++steps;
   }
-  if (overlap) LYAP_HIP(hipStreamWaitEvent(st, ev_chk, 0));
+  if (overlap) LYAP_HIP(hipStreamWaitEvent(st, done_slot->ev, 0));
   const double pass1_ms = ms_since(t_pass1) - check_ms;
   out->m = m;
   out->res = last_res;
