@@ -26,7 +26,9 @@
 //   Z2 = U_m M2 (second pass on each side), Z1 Z2^T ~= X.
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <type_traits>
+#include <vector>
 
 #include "aca.hpp"
 #include "check.hpp"
@@ -373,6 +375,29 @@ double host_fro(const std::vector<double>& v) {
   return std::sqrt(s);
 }
 
+// One Sylvester check in flight: its stream (owned unless it is the
+// solver's), completion event, the two sides' workspaces, result buffers (the
+// check's output, the extreme Ritz values of both sides, their Lanczos flags)
+// and the step it checks.
+struct SylvSlot {
+  hipStream_t st = nullptr;
+  bool own = false;
+  hipEvent_t ev = nullptr;
+  std::unique_ptr<Checker> ca, cb;
+  DevBuf part, counter, chk;
+  HostBuf hchk;
+  int mm = 0;
+  CheckOut* hc() const { return hchk.as<CheckOut>(); }
+  double* hl() const { return reinterpret_cast<double*>(hchk.as<char>() + sizeof(CheckOut)); }
+  int* hf() const { return reinterpret_cast<int*>(hchk.as<char>() + sizeof(CheckOut) + 4 * sizeof(double)); }
+  ~SylvSlot() {
+    // a check still running reads the Lanczos sides' buffers: let it end
+    if (own && st) (void)hipStreamSynchronize(st);
+    if (ev) (void)hipEventDestroy(ev);
+    if (own && st) (void)hipStreamDestroy(st);
+  }
+};
+
 template <typename T>
 lyap_status sylv_impl(const lyap_op* A, const lyap_op* B, const double* C1, int64_t ldc1, const double* C2,
                       int64_t ldc2, int S, const lyap_opts& o, sylv_result* out) {
@@ -395,75 +420,87 @@ lyap_status sylv_impl(const lyap_op* A, const lyap_op* B, const double* C1, int6
   out->beta2 = sb.beta();
   const double b12 = sa.beta() * sb.beta();
 
-  // Checks run on a second stream while both sides keep stepping (see
+  // Checks run on other streams while both sides keep stepping (see
   // solve_std): a check at mm reads only the two leading bands and logs.
-  constexpr int kAhead = 24;
+  // With a fixed schedule up to kSlots checks are in flight at once, each
+  // with a stream and workspaces of its own, read in the order issued (the
+  // first under the tolerance ends the iteration, as with one at a time); the
+  // steps stay at most kAhead past the next check point.
+  constexpr int kAhead = 24, kSlots = 3;
   const bool overlap = o.profile == 0;
-  hipStream_t cst = st;
-  struct StreamGuard {
-    hipStream_t s = nullptr;
-    ~StreamGuard() { if (s) (void)hipStreamDestroy(s); }
-  } sg;
-  if (overlap) {
-    LYAP_HIP(hipStreamCreateWithFlags(&sg.s, hipStreamNonBlocking));
-    cst = sg.s;
+  const bool fixed = o.check_every > 0;
+  const int nslots = overlap && fixed ? kSlots : 1;
+  std::vector<std::unique_ptr<SylvSlot>> slots;
+  for (int i = 0; i < nslots; ++i) {
+    slots.emplace_back(new SylvSlot);
+    SylvSlot& sl = *slots.back();
+    if (overlap) {
+      LYAP_HIP(hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking));
+      sl.own = true;
+    } else {
+      sl.st = st;
+    }
+    LYAP_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+    sl.ca.reset(new Checker(S, S, sl.st));
+    sl.cb.reset(new Checker(S, S, sl.st));
+    sl.part.alloc(4096 * sizeof(double));
+    sl.counter.alloc(64);
+    sl.chk.alloc(sizeof(CheckOut));
+    sl.hchk.alloc(sizeof(CheckOut) + 4 * sizeof(double) + 4 * sizeof(int));
+    LYAP_HIP(hipMemsetAsync(sl.counter.p, 0, 64, st));
   }
   struct EventRing {
     std::vector<hipEvent_t> ev;
     ~EventRing() { for (auto e : ev) (void)hipEventDestroy(e); }
   } er;
-  er.ev.resize(kAhead + 2);
+  er.ev.resize(kAhead + 1);
   for (auto& e : er.ev) LYAP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  hipEvent_t ev_step = er.ev[kAhead], ev_chk = er.ev[kAhead + 1];
-
-  Checker ca(S, S, cst), cb(S, S, cst);
-  DevBuf part(4096 * sizeof(double)), counter(64), chk(sizeof(CheckOut));
-  HostBuf hchk(sizeof(CheckOut) + 4 * sizeof(double) + 4 * sizeof(int));
-  LYAP_HIP(hipMemsetAsync(counter.p, 0, 64, st));
+  hipEvent_t ev_step = er.ev[kAhead];
   LYAP_HIP(hipStreamSynchronize(st));
+
   CheckSchedule sched{o.check_every, maxit};
   std::vector<int> hm;
   std::vector<double> hr;
   double check_ms = 0.0, t_to_tol = 0.0, lamA_abs = 0.0, lamB_abs = 0.0, last_res = INFINITY;
   int next_check = sched.first(), m = 0;
   lyap_status status = LYAP_NOT_CONVERGED;
-  bool pending = false;
-  int pending_mm = 0;
-  CheckOut* hc = hchk.as<CheckOut>();
-  double* hl = reinterpret_cast<double*>(hchk.as<char>() + sizeof(CheckOut));
-  int* hf = reinterpret_cast<int*>(hchk.as<char>() + sizeof(CheckOut) + 4 * sizeof(double));
+  int head = 0, npend = 0;  // checks in flight: slots head, head + 1, ... (mod nslots)
+  int last_launched = 0;
+  SylvSlot* done_slot = slots[0].get();  // the slot of the last check read
 
-  auto launch_check = [&](int mm) {
+  auto launch_check = [&](SylvSlot& sl, int mm) {
     LYAP_HIP(hipEventRecord(ev_step, st));
-    LYAP_HIP(hipStreamWaitEvent(cst, ev_step, 0));
+    LYAP_HIP(hipStreamWaitEvent(sl.st, ev_step, 0));
     kt.mark(LYAP_K_CHECK);
     const int k = mm * S;
+    Checker &ca = *sl.ca, &cb = *sl.cb;
     ca.prepare(sa.band(), k, sa.gamma_dev(), sa.tau_dev(mm));
     cb.prepare(sb.band(), k, sb.gamma_dev(), sb.tau_dev(mm));
     const int grid = std::max(1, std::min(2 * k, 2048));
-    hipLaunchKernelGGL(k_sylv_sum, dim3(grid), dim3(kBlock), 0, cst, ca.lam(), ca.g(), ca.Wm(), cb.lam(), cb.g(),
-                       cb.Wm(), k, S, S, part.as<double>(), counter.as<unsigned>(), chk.as<CheckOut>());
+    hipLaunchKernelGGL(k_sylv_sum, dim3(grid), dim3(kBlock), 0, sl.st, ca.lam(), ca.g(), ca.Wm(), cb.lam(), cb.g(),
+                       cb.Wm(), k, S, S, sl.part.as<double>(), sl.counter.as<unsigned>(), sl.chk.as<CheckOut>());
     LYAP_LAUNCHED("k_sylv_sum");
-    LYAP_HIP(hipMemcpyAsync(hc, chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, cst));
-    LYAP_HIP(hipMemcpyAsync(&hl[0], ca.lam(), sizeof(double), hipMemcpyDeviceToHost, cst));
-    LYAP_HIP(hipMemcpyAsync(&hl[1], ca.lam() + k - 1, sizeof(double), hipMemcpyDeviceToHost, cst));
-    LYAP_HIP(hipMemcpyAsync(&hl[2], cb.lam(), sizeof(double), hipMemcpyDeviceToHost, cst));
-    LYAP_HIP(hipMemcpyAsync(&hl[3], cb.lam() + k - 1, sizeof(double), hipMemcpyDeviceToHost, cst));
-    LYAP_HIP(hipMemcpyAsync(&hf[0], sa.flags_dev(), 2 * sizeof(int), hipMemcpyDeviceToHost, cst));
-    LYAP_HIP(hipMemcpyAsync(&hf[2], sb.flags_dev(), 2 * sizeof(int), hipMemcpyDeviceToHost, cst));
-    LYAP_HIP(hipEventRecord(ev_chk, cst));
-    pending = true;
-    pending_mm = mm;
-    out->n_checks++;
+    double* hl = sl.hl();
+    int* hf = sl.hf();
+    LYAP_HIP(hipMemcpyAsync(sl.hc(), sl.chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, sl.st));
+    LYAP_HIP(hipMemcpyAsync(&hl[0], ca.lam(), sizeof(double), hipMemcpyDeviceToHost, sl.st));
+    LYAP_HIP(hipMemcpyAsync(&hl[1], ca.lam() + k - 1, sizeof(double), hipMemcpyDeviceToHost, sl.st));
+    LYAP_HIP(hipMemcpyAsync(&hl[2], cb.lam(), sizeof(double), hipMemcpyDeviceToHost, sl.st));
+    LYAP_HIP(hipMemcpyAsync(&hl[3], cb.lam() + k - 1, sizeof(double), hipMemcpyDeviceToHost, sl.st));
+    LYAP_HIP(hipMemcpyAsync(&hf[0], sa.flags_dev(), 2 * sizeof(int), hipMemcpyDeviceToHost, sl.st));
+    LYAP_HIP(hipMemcpyAsync(&hf[2], sb.flags_dev(), 2 * sizeof(int), hipMemcpyDeviceToHost, sl.st));
+    LYAP_HIP(hipEventRecord(sl.ev, sl.st));
+    sl.mm = mm;
   };
-  auto wait_check = [&]() {
+  auto wait_check = [&](SylvSlot& sl) {
     const auto t0 = Clock::now();
-    LYAP_HIP(hipEventSynchronize(ev_chk));
+    LYAP_HIP(hipEventSynchronize(sl.ev));
     check_ms += ms_since(t0);
     kt.collect();
   };
-  auto record = [&](int mm) -> double {
-    const CheckOut c = *hc;
+  auto record = [&](SylvSlot& sl, int mm) -> double {
+    const CheckOut c = *sl.hc();
+    const double* hl = sl.hl();
     LYAP_REQUIRE(std::isfinite(c.res), LYAP_E_NUMERIC, "residual is not finite at m=%d", mm);
     const double rel = c.res / b12;
     hm.push_back(mm);
@@ -477,9 +514,11 @@ lyap_status sylv_impl(const lyap_op* A, const lyap_op* B, const double* C1, int6
     return rel;
   };
   // returns true when the iteration stops
-  auto finish_check = [&]() -> bool {
-    pending = false;
-    const int mm = pending_mm;
+  auto finish_check = [&](SylvSlot& sl) -> bool {
+    done_slot = &sl;
+    out->n_checks++;
+    const int mm = sl.mm;
+    const int* hf = sl.hf();
     int fbk = 0, fnf = 0;
     for (int f : {hf[0], hf[2]})
       if (f > 0 && f <= mm && (fbk == 0 || f < fbk)) fbk = f;
@@ -490,10 +529,10 @@ lyap_status sylv_impl(const lyap_op* A, const lyap_op* B, const double* C1, int6
                  "non-finite values in the Lanczos recurrences at step %d", fnf);
     if (fbk > 0) {  // a rank-deficient block: check the basis it ends instead
       LYAP_HIP(hipStreamSynchronize(st));
-      launch_check(fbk);
-      wait_check();
-      pending = false;
-      const double rel = record(fbk);
+      launch_check(sl, fbk);
+      out->n_checks++;
+      wait_check(sl);
+      const double rel = record(sl, fbk);
       m = fbk;
       if (rel <= o.tol) {
         status = LYAP_OK;
@@ -504,7 +543,7 @@ lyap_status sylv_impl(const lyap_op* A, const lyap_op* B, const double* C1, int6
       }
       return true;
     }
-    const double rel = record(mm);
+    const double rel = record(sl, mm);
     if (rel <= o.tol) {
       status = LYAP_OK;
       m = mm;
@@ -515,34 +554,46 @@ lyap_status sylv_impl(const lyap_op* A, const lyap_op* B, const double* C1, int6
       m = mm;
       return true;
     }
-    next_check = sched.next(mm, rel, o.tol);
+    if (!fixed) next_check = sched.next(mm, rel, o.tol);
     return false;
   };
 
   const auto t_pass1 = Clock::now();
   int steps = 0;
   while (true) {
-    if (pending) {
-      const hipError_t q = hipEventQuery(ev_chk);
-      if (q == hipSuccess || steps >= maxit || !overlap) {
-        if (q != hipSuccess) wait_check();
-        if (finish_check()) break;
+    if (npend > 0) {
+      SylvSlot& sl = *slots[head];
+      const hipError_t q = hipEventQuery(sl.ev);
+      const bool stuck = steps >= maxit || (fixed && npend == nslots && steps >= next_check + kAhead);
+      if (q == hipSuccess || stuck || !overlap) {
+        if (q != hipSuccess) wait_check(sl);
+        --npend;
+        head = (head + 1) % nslots;
+        if (finish_check(sl)) break;
+        continue;
       } else if (q != hipErrorNotReady) {
         LYAP_HIP(q);
       }
     }
-    if (!pending && (steps >= next_check || steps >= maxit)) {
-      launch_check(std::min(next_check, steps));
+    if (npend < nslots && next_check > last_launched && (steps >= next_check || steps >= maxit)) {
+      const int mm = std::min(next_check, steps);
+      launch_check(*slots[(head + npend) % nslots], mm);
+      ++npend;
+      last_launched = mm;
+      if (fixed) next_check = std::min(mm + sched.d, maxit);
       continue;
     }
     if (steps >= maxit) continue;
+    if (fixed && steps >= next_check + kAhead) continue;  // waits for a slot
     if (steps >= kAhead) LYAP_HIP(hipEventSynchronize(er.ev[steps % kAhead]));
     sa.step();
     sb.step();
     LYAP_HIP(hipEventRecord(er.ev[steps % kAhead], st));
     ++steps;
   }
-  if (overlap) LYAP_HIP(hipStreamWaitEvent(st, ev_chk, 0));
+  // finalisation reads the eigendecompositions of the check that ended the iteration
+  if (overlap) LYAP_HIP(hipStreamWaitEvent(st, done_slot->ev, 0));
+  Checker &ca = *done_slot->ca, &cb = *done_slot->cb;
   const double pass1_ms = ms_since(t_pass1) - check_ms;
   out->m = m;
   out->res = last_res;
