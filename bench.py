@@ -68,6 +68,11 @@ HBM_COUNTERS = {
                                     "fetch_scale": 262144.0 / 131088.69, "write_scale": 1.0},
     ("rb_w", 1000000, 1, "f64"): {"fetch_kib": 21554.12, "write_kib": 4074.50,
                                   "fetch_scale": 262144.0 / 131088.69, "write_scale": 1.0},
+    # one application of the learned network on the 100^3 run (--inner learned): the four k_pc_tile
+    # convolutions summed (first with the fused x, r update, two middle ones, last forming z)
+    ("pcnet", 1000000, 1, "f64"): {"fetch_kib": 11216.56 + 2390.75 + 2395.25 + 10607.00,
+                                   "write_kib": 12217.72 + 4074.50 + 4074.50 + 4080.47,
+                                   "fetch_scale": 262144.0 / 131088.69, "write_scale": 1.0},
     # k_apply<float, 4> on the 4000 x 4000 grid (bench.py --workload spmm --grid 4000)
     ("spmm", 16000000, 4, "f32"): {"fetch_kib": 132070.94, "write_kib": 257261.72,
                                    "fetch_scale": 262144.0 / 131088.69, "write_scale": 1.0},
@@ -770,7 +775,10 @@ def main_c3(args):
         tf = flops / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": "pcnet (four k_pc_tile convolutions, the flexible-CG update fused into the first)",
                 "achieved": round(tf, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic("pcnet", op.n, 1, "f64"),
+                "traffic_unit": "bytes per application (rocprofv3 FETCH_SIZE + WRITE_SIZE of the four kernels, "
+                                "copy-calibrated)",
                 "flops_per_launch": flops, "bytes_per_launch": agg[dom]["bytes_per_launch"],
                 "avg_launch_us": round(avg_ms * 1000.0, 2),
                 "note": "FP32 multiply-adds of the four convolutions of one network application (the x, r update "
