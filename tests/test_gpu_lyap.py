@@ -341,3 +341,28 @@ def test_c2_full_size_properties(lib):
     Rs = AZr @ Zr.T + Zr @ AZr.T + C[rows] @ C[rows].T
     scale = np.max(np.abs(C[rows] @ C[rows].T))
     assert np.max(np.abs(Rs)) <= 1e-5 * scale, np.max(np.abs(Rs)) / scale
+
+
+
+@pytest.mark.parametrize("s", [1, 2])
+@pytest.mark.parametrize("every", [0, 1])
+def test_exact_breakdown_at_first_step(lib, s, every):
+    """A = -2 I and C = s unit vectors: the first block spans an invariant
+    subspace and A V - V tau is exactly zero, so the block after it is rank
+    deficient at the first step (Section 2, the remark on rank-deficient
+    blocks); the check of the basis that the breakdown ends finds the exact
+    solution X = C C^T / 4 at m = 1.  every = 1 runs the fixed schedule's
+    checks several at a time (the breakdown is read from the first of them),
+    every = 0 the adaptive schedule, whose first check lies past it."""
+    import dataclasses
+    b = _b()
+    op = dataclasses.replace(laplace2d(30), cc=-2.0, co=0.0)
+    C = np.zeros((op.n, s))
+    for c, k in enumerate((17, 401)[:s]):
+        C[k, c] = 1.0
+    sol = b.lyap_solve(b.device_op(op), _dev_C(C), tol=1e-8, check_every=every)
+    assert sol.status == b.OK and sol.m == 1
+    assert sol.res <= 1e-12
+    Z = sol.Z.cpu().numpy()
+    X = C @ C.T / 4.0
+    assert np.linalg.norm(Z @ Z.T - X) <= 1e-12 * np.linalg.norm(X)
