@@ -217,3 +217,29 @@ def test_example5_against_oracle(lib, s):
     ex = Y.explicit_residual(op.to_scipy(), B, Z1, Z2, C1, C2) / (sol.beta1 * sol.beta2)
     print(f"  explicit residual {ex:.3e}, reported {sol.res:.3e}")
     assert ex <= 1.2e-6
+
+
+@pytest.mark.parametrize("s", [1, 2])
+@pytest.mark.parametrize("every", [0, 1])
+def test_exact_breakdown_at_first_step(lib, s, every):
+    """A = -2 I, B = -3 I (dense, 20 x 20) and C1, C2 unit vectors: the first
+    block of A's space spans an invariant subspace, the block after it is rank
+    deficient at the first step, and Algorithm 5 on the basis that the
+    breakdown ends finds X = C1 C2^T / 5 at m = 1 (every = 1: the fixed
+    schedule's checks several at a time)."""
+    import dataclasses
+    b = _b()
+    opA = dataclasses.replace(laplace2d(30), cc=-2.0, co=0.0)
+    n2 = 20
+    B = -3.0 * np.eye(n2)
+    C1 = np.zeros((opA.n, s))
+    C2 = np.zeros((n2, s))
+    for c in range(s):
+        C1[(17, 401)[c], c] = 1.0
+        C2[(5, 12)[c], c] = 1.0
+    sol = b.sylv_solve_small_b(b.device_op(opA), _dev(B), _dev(C1), _dev(C2), tol=1e-8, check_every=every)
+    assert sol.status == b.OK and sol.m == 1
+    assert sol.res <= 1e-12
+    X = C1 @ C2.T / 5.0
+    Z1, Z2 = sol.Z1.cpu().numpy(), sol.Z2.cpu().numpy()
+    assert np.linalg.norm(Z1 @ Z2.T - X) <= 1e-12 * np.linalg.norm(X)

@@ -245,3 +245,27 @@ def test_example4_against_oracle(lib, s):
     ex = Y.explicit_residual(opA.to_scipy(), opB.to_scipy(), Z1, Z2, C1, C2) / (sol.beta1 * sol.beta2)
     print(f"  explicit residual {ex:.3e}, reported {sol.res:.3e}")
     assert ex <= 1.2e-6
+
+
+@pytest.mark.parametrize("s", [1, 2])
+@pytest.mark.parametrize("every", [0, 1])
+def test_exact_breakdown_at_first_step(lib, s, every):
+    """A = B = -2 I and C1, C2 unit vectors: both first blocks span invariant
+    subspaces, the blocks after them are rank deficient at the first step, and
+    the check of the bases that the breakdown ends finds X = C1 C2^T / 4 at
+    m = 1 (every = 1: the fixed schedule's checks several at a time)."""
+    import dataclasses
+    b = _b()
+    opA = dataclasses.replace(laplace2d(30), cc=-2.0, co=0.0)
+    opB = dataclasses.replace(laplace2d(20), cc=-2.0, co=0.0)
+    C1 = np.zeros((opA.n, s))
+    C2 = np.zeros((opB.n, s))
+    for c in range(s):
+        C1[(17, 401)[c], c] = 1.0
+        C2[(5, 222)[c], c] = 1.0
+    sol = b.sylv_solve(b.device_op(opA), b.device_op(opB), _dev(C1), _dev(C2), tol=1e-8, check_every=every)
+    assert sol.status == b.OK and sol.m == 1
+    assert sol.res <= 1e-12
+    X = C1 @ C2.T / 4.0
+    Z1, Z2 = sol.Z1.cpu().numpy(), sol.Z2.cpu().numpy()
+    assert np.linalg.norm(Z1 @ Z2.T - X) <= 1e-12 * np.linalg.norm(X)
