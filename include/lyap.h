@@ -293,7 +293,8 @@ lyap_status sylv_solve(const lyap_op* A, const lyap_op* B, const double* C1, int
  *        keeps every block.  tol applies to the transformed residual
  *        ||L^{-1} R L^{-T}||_F / ||L^{-1} C||_F^2, R = A X E + E X A + C C^T
  *        (out->beta = ||L^{-1} C||_F, out->hist_res the same ratio).
- *  out   as lyap_solve, with inner_iters / n_inner counting the E solves.
+ *  out   as lyap_solve, with inner_iters / n_inner counting the E solves
+ *        of the accepted steps (not those of steps run beside the last check).
  * Errors: E_ARG, E_INNER (an E solve missed inner_tol), E_INDEFINITE (a Ritz
  * value >= 0 or a diagonal entry of E <= 0), E_BREAKDOWN, E_NUMERIC.
  */

@@ -394,7 +394,26 @@ lyap_status gen_impl(const lyap_op* A, const lyap_op* E, const double* C, int S,
   out->beta = std::sqrt(beta2);
   const double* gamma_dev = glog.as<double>() + 6 * S * S;
 
-  Checker ck(S, S, st);
+  // The residual check runs on a stream of its own while the next steps
+  // proceed: a check at mm reads only the band's first mm S columns, gamma and
+  // the log entry of step mm - 1, which later steps never write.  It always
+  // runs at the scheduled m, so the results do not depend on timing; a step
+  // that fails while a check is pending first lets that check decide (the
+  // steps past the converging check are not used).
+  struct CheckStream {
+    hipStream_t s = nullptr;
+    hipEvent_t ev_step = nullptr, ev_chk = nullptr;
+    ~CheckStream() {
+      if (s) (void)hipStreamSynchronize(s);
+      if (ev_step) (void)hipEventDestroy(ev_step);
+      if (ev_chk) (void)hipEventDestroy(ev_chk);
+      if (s) (void)hipStreamDestroy(s);
+    }
+  } cstr;
+  LYAP_HIP(hipStreamCreateWithFlags(&cstr.s, hipStreamNonBlocking));
+  LYAP_HIP(hipEventCreateWithFlags(&cstr.ev_step, hipEventDisableTiming));
+  LYAP_HIP(hipEventCreateWithFlags(&cstr.ev_chk, hipEventDisableTiming));
+  Checker ck(S, S, cstr.s);
   DevBuf chk(sizeof(CheckOut));
   HostBuf hchk(sizeof(CheckOut) + 2 * sizeof(int) + 2 * sizeof(double));
   CheckSchedule sched{o.check_every, maxit};
@@ -412,23 +431,35 @@ lyap_status gen_impl(const lyap_op* A, const lyap_op* E, const double* C, int S,
     run.step(Wp, wslot(j), Pp, Pb[j % 3].as<double>(), wslot(j + 1), Pb[(j + 1) % 3].as<double>(),
              logb.as<double>() + (size_t)j * LS, band.as<double>(), j, flags.as<int>());
   };
-  const auto t_pass1 = Clock::now();
-  for (int j = 0; j < maxit; ++j) {
-    step_at(j);
-    const int mm = j + 1;
-    if (mm < next_check && mm < maxit) continue;
-    const auto t0 = Clock::now();
+  bool pending = false;
+  int pending_mm = 0, last_launched = 0;
+  auto launch_check = [&](int mm) {
     const int k = mm * S;
-    ck.run(band.as<double>(), k, gamma_dev, logb.as<double>() + (size_t)j * LS + 6 * S * S, chk.as<CheckOut>());
-    LYAP_HIP(hipMemcpyAsync(hc, chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, st));
-    LYAP_HIP(hipMemcpyAsync(hf, flags.p, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    LYAP_HIP(hipMemcpyAsync(&hl[0], ck.lam(), sizeof(double), hipMemcpyDeviceToHost, st));
-    LYAP_HIP(hipMemcpyAsync(&hl[1], ck.lam() + k - 1, sizeof(double), hipMemcpyDeviceToHost, st));
-    LYAP_HIP(hipStreamSynchronize(st));
+    LYAP_HIP(hipEventRecord(cstr.ev_step, st));
+    LYAP_HIP(hipStreamWaitEvent(cstr.s, cstr.ev_step, 0));
+    ck.run(band.as<double>(), k, gamma_dev, logb.as<double>() + (size_t)(mm - 1) * LS + 6 * S * S, chk.as<CheckOut>());
+    LYAP_HIP(hipMemcpyAsync(hc, chk.p, sizeof(CheckOut), hipMemcpyDeviceToHost, cstr.s));
+    LYAP_HIP(hipMemcpyAsync(hf, flags.p, 2 * sizeof(int), hipMemcpyDeviceToHost, cstr.s));
+    LYAP_HIP(hipMemcpyAsync(&hl[0], ck.lam(), sizeof(double), hipMemcpyDeviceToHost, cstr.s));
+    LYAP_HIP(hipMemcpyAsync(&hl[1], ck.lam() + k - 1, sizeof(double), hipMemcpyDeviceToHost, cstr.s));
+    LYAP_HIP(hipEventRecord(cstr.ev_chk, cstr.s));
+    pending = true;
+    pending_mm = mm;
+    last_launched = mm;
+  };
+  // waits for the pending check and reads it; returns true when the iteration stops
+  auto finish_check = [&]() -> bool {
+    const auto t0 = Clock::now();
+    LYAP_HIP(hipEventSynchronize(cstr.ev_chk));
     check_ms += ms_since(t0);
+    pending = false;
+    const int mm = pending_mm;
+    const int k = mm * S;
     out->n_checks++;
-    LYAP_REQUIRE(!(hf[1] > 0 && (hf[0] == 0 || hf[1] <= hf[0])), LYAP_E_NUMERIC,
-                 "non-finite values in the Lanczos recurrence at step %d", hf[1]);
+    // flags of steps after mm (run beside the check) do not concern this check
+    const int fb = hf[0] > 0 && hf[0] <= mm ? hf[0] : 0, fn = hf[1] > 0 && hf[1] <= mm ? hf[1] : 0;
+    LYAP_REQUIRE(!(fn > 0 && (fb == 0 || fn <= fb)), LYAP_E_NUMERIC,
+                 "non-finite values in the Lanczos recurrence at step %d", fn);
     LYAP_REQUIRE(std::isfinite(hc->res), LYAP_E_NUMERIC, "residual is not finite at m=%d", mm);
     const double rel = hc->res / beta2;
     hm.push_back(mm);
@@ -442,16 +473,51 @@ lyap_status gen_impl(const lyap_op* A, const lyap_op* E, const double* C, int S,
     if (rel <= o.tol) {
       status = LYAP_OK;
       t_to_tol = ms_since(t_entry);
-      break;
+      return true;
     }
-    if (hf[0] > 0) {
+    if (fb > 0) {
       status = LYAP_E_BREAKDOWN;
-      set_error("block Lanczos breakdown at m=%d with residual %.3e above tol", hf[0], rel);
-      break;
+      set_error("block Lanczos breakdown at m=%d with residual %.3e above tol", fb, rel);
+      return true;
     }
+    if (mm >= maxit) return true;
     next_check = sched.next(mm, rel, o.tol);
+    return false;
+  };
+  const auto t_pass1 = Clock::now();
+  int steps = 0;  // steps enqueued
+  bool stop = false;
+  // inner-solve counts after each step: the steps run beside the converging
+  // check are not counted, so that the reported counts do not depend on timing
+  std::vector<std::pair<int64_t, int>> cg_at{{run.cg->stats().iters, run.cg->stats().solves}};
+  while (!stop) {
+    if (pending && (steps >= maxit || hipEventQuery(cstr.ev_chk) == hipSuccess)) {
+      stop = finish_check();
+      continue;
+    }
+    if (!pending && next_check > last_launched && steps >= std::min(next_check, maxit)) {
+      launch_check(std::min(next_check, maxit));
+      continue;
+    }
+    if (steps >= maxit) break;  // (not reached: the check at maxit ends the iteration)
+    if (!pending) {
+      step_at(steps++);
+      cg_at.emplace_back(run.cg->stats().iters, run.cg->stats().solves);
+      continue;
+    }
+    try {
+      step_at(steps);
+      ++steps;
+      cg_at.emplace_back(run.cg->stats().iters, run.cg->stats().solves);
+    } catch (const Error&) {
+      // the pending check decides first; the step's error stands only if it does not stop
+      if (finish_check()) break;
+      throw;
+    }
   }
   const double pass1_ms = ms_since(t_pass1) - check_ms;
+  const std::pair<int64_t, int> past_m{run.cg->stats().iters - cg_at[std::min<size_t>(m, cg_at.size() - 1)].first,
+                                      run.cg->stats().solves - cg_at[std::min<size_t>(m, cg_at.size() - 1)].second};
   store_history(out, hm, hr);
   out->m = m;
   out->res = last_res;
@@ -530,8 +596,8 @@ lyap_status gen_impl(const lyap_op* A, const lyap_op* E, const double* C, int S,
     rowmajor_to_colmajor(tau_h.data(), S, S, out->tau);
   }
   const CgStats& cs = run.cg->stats();
-  out->inner_iters = cs.iters;
-  out->n_inner = cs.solves;
+  out->inner_iters = cs.iters - past_m.first;
+  out->n_inner = cs.solves - past_m.second;
   out->times_ms[LYAP_T_PASS1] = pass1_ms;
   out->times_ms[LYAP_T_CHECKS] = check_ms;
   out->times_ms[LYAP_T_FINAL] = fin_ms;
